@@ -1,0 +1,361 @@
+"""CPU oracle for the RBSOG force evaluation (TEST INFRASTRUCTURE).
+
+A plain FP64 implementation of what the paper computes, written in C
+(`rbsog_oracle.c`, built by `oracle.build`) and driven through ctypes.  It is
+the reference the GPU library is checked against: only the tests, the smoke
+check and the CPU-baseline leg of the benchmark may import it.  It shares no
+code with the GPU library, and the library never imports it.
+
+Functions that the paper fixes but the C file does not need (the SOG in its
+integral form, the brute-force Yukawa image sum used as a pin) are written
+here in numpy.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+ADAPTIVE, FLAT, K2, DH4PI = 0, 1, 2, 3
+
+_d = C.c_double
+_i = C.c_int
+_i64 = C.c_int64
+_u64 = C.c_uint64
+_u32 = C.c_uint32
+_p = C.c_void_p
+
+
+def build(force: bool = True) -> str:
+    from . import build_oracle as _b
+    return _b.build(force=force)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        sig = {
+            "orc_yukawa": (_d, [_d, _d]),
+            "orc_yukawa_dr": (_d, [_d, _d]),
+            "orc_f": (_d, [_d, _d, _d]),
+            "orc_h_star": (_d, [_d, _d]),
+            "orc_sog_w": (_d, [_d, _d, _d, _d, _i, _i]),
+            "orc_sog_far": (_d, [_d, _d, _d, _d, _i, _i, _d]),
+            "orc_sog_c1_residual": (_d, [_d, _d, _d, _d, _i, _i]),
+            "orc_sog_c1_root": (_i, [_d, _d, _d, _i, _i, _p, _p]),
+            "orc_sog_maxerr": (_d, [_d, _d, _d, _d, _d, _i, _i]),
+            "orc_sog_auto": (_i, [_d, _d, _d, _p, _p, _p, _p, _p, _p]),
+            "orc_sog_expand": (None, [_d, _d, _d, _d, _i, _i, _p, _p, _p, _p]),
+            "orc_F": (_d, [_i, _p, _p, _d]),
+            "orc_Fhat": (_d, [_i, _p, _p, _d]),
+            "orc_density": (_d, [_i, _d, _d, _d, _d, _d]),
+            "orc_mmax_default": (_i, [_i, _p, _p, _d]),
+            "orc_lattice_count": (_i64, [_i]),
+            "orc_lattice_build": (None, [_i, _p, _p]),
+            "orc_shell_table": (_i, [_i, _p, _i, _p, _p, _d, _i, _d, _d, _d, _i, _p, _p, _p]),
+            "orc_philox4x64_10": (None, [_p, _p, _p]),
+            "orc_cells": (_i, [_i64, _p, _d, _d, _p, _p]),
+            "orc_near": (None, [_i64, _p, _p, _d, _d, _d, _i, _p, _p, _p, _p]),
+            "orc_rho": (None, [_i64, _p, _p, _d, _i, _p, _p]),
+            "orc_far_rb": (None, [_i64, _p, _p, _d, _i, _p, _p, _p, _p]),
+            "orc_far_rb_energy": (_d, [_i, _p, _p]),
+            "orc_far_full": (_d, [_i64, _p, _p, _d, _i, _p, _p, _i, _p]),
+            "orc_sys_create": (_p, [_i64, _d, _d, _d, _d, _i, _i, _u64, _u32, _i, _i, _i, _p, _p, _p, _p, _p, _p]),
+            "orc_sys_destroy": (None, [_p]),
+            "orc_sys_mmax": (_i, [_p]),
+            "orc_sys_nshell": (_i, [_p]),
+            "orc_sys_nlat": (_i64, [_p]),
+            "orc_sys_tables": (None, [_p, _p, _p, _p]),
+            "orc_sys_lattice": (None, [_p, _p, _p]),
+            "orc_sys_draw": (None, [_p, _u64, _p, _p]),
+            "orc_sys_force": (None, [_p, _u64, _p, _p, _p, _p]),
+            "orc_sys_run": (_i, [_p, _p, _p, _p, _u64, _i, _d, _p]),
+            "orc_num_threads": (_i, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# SOG decomposition (Section 3, Algorithm 1)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SOG:
+    lam: float
+    rc: float
+    h: float
+    t0: float
+    w: float
+    M1: int
+    M2: int
+    c: np.ndarray = None
+    s: np.ndarray = None
+    A: np.ndarray = None
+    B: np.ndarray = None
+    err: float = float("nan")
+
+    @property
+    def n(self) -> int:
+        return self.M1 + self.M2 + 1
+
+    @property
+    def F0(self) -> float:
+        return float(sum(self.c))
+
+    @property
+    def Fhat0(self) -> float:
+        return float(sum(self.A))
+
+    def expand(self) -> "SOG":
+        n = self.n
+        self.c, self.s, self.A, self.B = (np.zeros(n) for _ in range(4))
+        lib().orc_sog_expand(self.lam, self.h, self.t0, self.w, self.M1, self.M2, _ptr(self.c), _ptr(self.s),
+                             _ptr(self.A), _ptr(self.B))
+        return self
+
+    def F(self, r) -> np.ndarray:
+        r = np.asarray(r, dtype=np.float64)
+        return np.array([lib().orc_F(self.n, _ptr(self.c), _ptr(self.s), float(x)) for x in r.ravel()]).reshape(r.shape)
+
+    def Fhat(self, k2) -> np.ndarray:
+        k2 = np.asarray(k2, dtype=np.float64)
+        return np.array([lib().orc_Fhat(self.n, _ptr(self.A), _ptr(self.B), float(x)) for x in k2.ravel()]).reshape(k2.shape)
+
+
+def h_star(eps: float, delta: float) -> float:
+    return lib().orc_h_star(eps, delta)
+
+
+def sog_c1(lam: float, rc: float, h: float, M1: int, M2: int) -> SOG:
+    t0, w = C.c_double(), C.c_double()
+    rc_ = lib().orc_sog_c1_root(lam, rc, h, M1, M2, C.byref(t0), C.byref(w))
+    if rc_ != 0:
+        raise ValueError("no C1 root with positive weight")
+    return SOG(lam, rc, h, t0.value, w.value, M1, M2).expand()
+
+
+def sog_auto(lam: float, rc: float, eps: float) -> SOG:
+    M1, M2 = C.c_int(), C.c_int()
+    h, t0, w, err = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    r = lib().orc_sog_auto(lam, rc, eps, C.byref(M1), C.byref(M2), C.byref(h), C.byref(t0), C.byref(w), C.byref(err))
+    if r != 0:
+        raise ValueError("no SOG found")
+    s = SOG(lam, rc, h.value, t0.value, w.value, M1.value, M2.value).expand()
+    s.err = err.value
+    return s
+
+
+def sog_w(lam, rc, h, t0, M1, M2) -> float:
+    return lib().orc_sog_w(lam, rc, h, t0, M1, M2)
+
+
+def sog_far(lam, h, t0, w, M1, M2, r) -> float:
+    return lib().orc_sog_far(lam, h, t0, w, M1, M2, r)
+
+
+def sog_c1_residual(lam, rc, h, t0, M1, M2) -> float:
+    return lib().orc_sog_c1_residual(lam, rc, h, t0, M1, M2)
+
+
+def sog_maxerr(s: SOG) -> float:
+    return lib().orc_sog_maxerr(s.lam, s.rc, s.h, s.t0, s.w, s.M1, s.M2)
+
+
+# ---------------------------------------------------------------------------
+# Random numbers, lattice, sampling tables (Section 4.3)
+# ---------------------------------------------------------------------------
+
+def philox(counter, key) -> np.ndarray:
+    ctr = np.ascontiguousarray(counter, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(_ptr(ctr), _ptr(k), _ptr(out))
+    return out
+
+
+def lattice(mmax: int):
+    cnt = lib().orc_lattice_count(mmax)
+    n3 = np.zeros((cnt, 3), dtype=np.int32)
+    start = np.zeros(mmax + 2, dtype=np.int64)
+    lib().orc_lattice_build(mmax, _ptr(n3), _ptr(start))
+    return n3, start
+
+
+def mmax_default(s: SOG, L: float) -> int:
+    return lib().orc_mmax_default(s.n, _ptr(s.A), _ptr(s.B), L)
+
+
+def density(kind: int, kT: float, V: float, Q2: float, lam: float, k2: float) -> float:
+    return lib().orc_density(kind, kT, V, Q2, lam, k2)
+
+
+# ---------------------------------------------------------------------------
+# Cells, near field, far field
+# ---------------------------------------------------------------------------
+
+def cells(x: np.ndarray, L: float, rc: float):
+    x = _f64(x)
+    N = x.shape[1]
+    nc = int(math.floor(L / rc))
+    cs = np.zeros(nc ** 3 + 1, dtype=np.int32)
+    order = np.zeros(N, dtype=np.int32)
+    lib().orc_cells(N, _ptr(x), L, rc, _ptr(cs), _ptr(order))
+    return cs, order
+
+
+def near(x, q, L, s: SOG):
+    x, q = _f64(x), _f64(q)
+    N = x.shape[1]
+    f = np.zeros((3, N))
+    U = C.c_double()
+    lib().orc_near(N, _ptr(x), _ptr(q), L, s.lam, s.rc, s.n, _ptr(s.c), _ptr(s.s), _ptr(f), C.byref(U))
+    return f, U.value
+
+
+def rho(x, q, L, n3) -> np.ndarray:
+    x, q = _f64(x), _f64(q)
+    n3 = np.ascontiguousarray(n3, dtype=np.int32)
+    P = n3.shape[0]
+    out = np.zeros((P, 2))
+    lib().orc_rho(x.shape[1], _ptr(x), _ptr(q), L, P, _ptr(n3), _ptr(out))
+    return out
+
+
+def far_rb(x, q, L, n3, coef, rho_):
+    x, q = _f64(x), _f64(q)
+    n3 = np.ascontiguousarray(n3, dtype=np.int32)
+    coef, rho_ = _f64(coef), _f64(rho_)
+    f = np.zeros_like(x)
+    lib().orc_far_rb(x.shape[1], _ptr(x), _ptr(q), L, n3.shape[0], _ptr(n3), _ptr(coef), _ptr(rho_), _ptr(f))
+    return f
+
+
+def far_full(x, q, L, s: SOG, mmax: int):
+    x, q = _f64(x), _f64(q)
+    f = np.zeros_like(x)
+    U = lib().orc_far_full(x.shape[1], _ptr(x), _ptr(q), L, s.n, _ptr(s.A), _ptr(s.B), mmax, _ptr(f))
+    return f, U
+
+
+# ---------------------------------------------------------------------------
+# A whole system (Algorithm 2)
+# ---------------------------------------------------------------------------
+
+class System:
+    """Sampling tables plus force evaluation and velocity-Verlet stepping."""
+
+    def __init__(self, q, m, L: float, s: SOG, kT: float, P: int, seed: int, replica: int = 0, mmax: int = 0,
+                 density: int = ADAPTIVE, full_k: bool = False):
+        self.q = _f64(q)
+        self.m = _f64(m)
+        self.N = self.q.shape[0]
+        self.L, self.sog, self.kT, self.P = L, s, kT, P
+        self.V = L ** 3
+        self._h = lib().orc_sys_create(self.N, L, s.lam, s.rc, kT, P, mmax, seed, replica, density, int(full_k),
+                                       s.n, _ptr(s.c), _ptr(s.s), _ptr(s.A), _ptr(s.B), _ptr(self.q),
+                                       _ptr(self.m))
+        if not self._h:
+            raise ValueError("oracle system creation failed")
+        self.mmax = lib().orc_sys_mmax(self._h)
+        self.nshell = lib().orc_sys_nshell(self._h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_sys_destroy(h)
+            self._h = None
+
+    def tables(self):
+        ns = self.nshell
+        m = np.zeros(ns, dtype=np.int32)
+        cdf = np.zeros(ns)
+        coef = np.zeros(ns)
+        lib().orc_sys_tables(self._h, _ptr(m), _ptr(cdf), _ptr(coef))
+        return m, cdf, coef
+
+    def lattice(self):
+        cnt = lib().orc_sys_nlat(self._h)
+        n3 = np.zeros((cnt, 3), dtype=np.int32)
+        start = np.zeros(self.mmax + 2, dtype=np.int64)
+        lib().orc_sys_lattice(self._h, _ptr(n3), _ptr(start))
+        return n3, start
+
+    def draw(self, step: int):
+        n = np.zeros((self.P, 3), dtype=np.int32)
+        coef = np.zeros(self.P)
+        lib().orc_sys_draw(self._h, step, _ptr(n), _ptr(coef))
+        return n, coef
+
+    def force(self, x, step: int):
+        """Returns (f, f_near, energy[6])."""
+        x = _f64(x)
+        f = np.zeros_like(x)
+        fn = np.zeros_like(x)
+        e = np.zeros(6)
+        lib().orc_sys_force(self._h, step, _ptr(x), _ptr(f), _ptr(fn), _ptr(e))
+        return f, fn, e
+
+    def run(self, x, v, f, step0: int, nsteps: int, dt: float):
+        """Advances (x, v, f) in place; returns the [nsteps, 6] energy history."""
+        eh = np.zeros((nsteps, 6))
+        r = lib().orc_sys_run(self._h, _ptr(x), _ptr(v), _ptr(f), step0, nsteps, dt, _ptr(eh))
+        if r != 0:
+            raise RuntimeError("a particle moved a full box length in one step")
+        return eh
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+# ---------------------------------------------------------------------------
+# Plain definitions used as pins
+# ---------------------------------------------------------------------------
+
+def yukawa_image_sum(x, q, L, lam, r_max: float):
+    """Energy and forces of the periodic Yukawa system by direct summation over
+    every image with |r_ij + n L| < r_max (the plain definition the method
+    approximates; Section 2).  Pure numpy, for a handful of particles."""
+    x = _f64(x)
+    q = _f64(q)
+    N = x.shape[1]
+    nimg = int(math.ceil(r_max / L)) + 1
+    rng = np.arange(-nimg, nimg + 1)
+    sh = np.stack(np.meshgrid(rng, rng, rng, indexing="ij"), -1).reshape(-1, 3) * L
+    U = 0.0
+    f = np.zeros((3, N))
+    pos = x.T
+    for i in range(N):
+        d = pos[i][None, None, :] - pos[:, None, :] - sh[None, :, :]   # (N, nsh, 3), d = r_i - r_j - nL
+        r = np.sqrt((d * d).sum(-1))
+        mask = (r < r_max) & (r > 0)
+        rr = np.where(mask, r, 1.0)
+        y = np.where(mask, np.exp(-rr / lam) / rr, 0.0)
+        U += 0.5 * q[i] * float((q[:, None] * y).sum())
+        fac = np.where(mask, np.exp(-rr / lam) * (1.0 + rr / lam) / rr ** 3, 0.0)
+        f[:, i] = q[i] * ((q[:, None, None] * fac[:, :, None] * d).sum(axis=(0, 1)))
+    return U, f

@@ -1,0 +1,904 @@
+/*
+ * rbsog_oracle.c -- plain FP64 CPU oracle for the random batch sum-of-Gaussians
+ * (RBSOG) force evaluation and velocity-Verlet step for 3-D periodic Yukawa
+ * systems (Chen, Liang & Xu, "Random batch sum-of-Gaussians algorithm for
+ * molecular dynamics simulations of Yukawa systems in three dimensions").
+ *
+ * TEST INFRASTRUCTURE.  This file is the slow, obviously-correct reference that
+ * the GPU library is checked against.  Only the test-suite, the smoke check and
+ * the CPU-baseline leg of the benchmark load it.  It shares no code, header,
+ * table or constant generator with the GPU library.
+ *
+ * Conventions (all FP64, IEEE round-to-nearest, compiled without fast-math and
+ * with -ffp-contract=off):
+ *   positions are SoA x[3*N] = {x_0..x_{N-1}, y_0.., z_0..}, cubic box [0,L)^3;
+ *   the SOG far field is F(r) = sum_j c_j exp(-s_j r^2), j ascending in m;
+ *   its 3-D Fourier transform is Fhat(k) = sum_j A_j exp(-B_j k^2).
+ *
+ * Every function names the part of the paper it follows.  Where the paper is
+ * silent or ambiguous, the reading taken is stated at the function.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <float.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.141592653589793
+
+/* ------------------------------------------------------------------------- */
+/* Section 1 and 3.1: the kernel and its integral representation             */
+/* ------------------------------------------------------------------------- */
+
+/* Yukawa kernel Y(r) = exp(-r/lambda)/r (Section 1). */
+double orc_yukawa(double r, double lambda) { return exp(-r / lambda) / r; }
+
+/* dY/dr = -exp(-r/lambda) (1/(lambda r) + 1/r^2). */
+double orc_yukawa_dr(double r, double lambda)
+{
+    return -exp(-r / lambda) * (1.0 / (lambda * r) + 1.0 / (r * r));
+}
+
+/* Integrand of the integral representation Y(r) = int f(t,r) dt (eq. ftr):
+ * f(t,r) = pi^{-1/2} exp(-r^2 e^t - e^{-t}/(4 lambda^2) + t/2). */
+double orc_f(double t, double r, double lambda)
+{
+    return exp(-r * r * exp(t) - exp(-t) / (4.0 * lambda * lambda) + 0.5 * t) / sqrt(ORC_PI);
+}
+
+/* d f(t,r)/dr = -2 r e^t f(t,r). */
+static double orc_f_dr(double t, double r, double lambda)
+{
+    return -2.0 * r * exp(t) * orc_f(t, r, lambda);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Section 3.1-3.2, Algorithm 1: the C1-continuous SOG decomposition          */
+/* ------------------------------------------------------------------------- */
+
+/* Step size from the aliasing bound, eq. (2.30), taken with equality:
+ * h = pi^2 / ( log(eps + 6 sqrt(2 pi) e^{1/6} / delta) + log(1/eps) ). */
+double orc_h_star(double eps, double delta)
+{
+    return ORC_PI * ORC_PI /
+           (log(eps + 6.0 * sqrt(2.0 * ORC_PI) * exp(1.0 / 6.0) / delta) + log(1.0 / eps));
+}
+
+/* Weight of the narrowest Gaussian from the C0 condition, eq. (2.42):
+ * w = [ Y(rc) - h sum_{m=-M1}^{M2-1} f(t_m, rc) ] / ( h f(t_{M2}, rc) ). */
+double orc_sog_w(double lambda, double rc, double h, double t0, int M1, int M2)
+{
+    double acc = 0.0;
+    for (int m = -M1; m <= M2 - 1; ++m) acc += orc_f(t0 + m * h, rc, lambda);
+    double den = h * orc_f(t0 + M2 * h, rc, lambda);
+    /* The narrowest Gaussian must be representable at r_c with full FP64
+     * precision, otherwise w is not determined (it would be a quotient by an
+     * underflowed number). */
+    if (!(den >= DBL_MIN / DBL_EPSILON)) return NAN;
+    return (orc_yukawa(rc, lambda) - h * acc) / den;
+}
+
+/* The far-field SOG in the paper's own form, eq. (2.41):
+ * F(r) = h [ w f(t_{M2}, r) + sum_{m=-M1}^{M2-1} f(t_m, r) ]. */
+double orc_sog_far(double lambda, double h, double t0, double w, int M1, int M2, double r)
+{
+    double acc = 0.0;
+    for (int m = -M1; m <= M2 - 1; ++m) acc += orc_f(t0 + m * h, r, lambda);
+    return h * (w * orc_f(t0 + M2 * h, r, lambda) + acc);
+}
+
+static double orc_sog_far_dr(double lambda, double h, double t0, double w, int M1, int M2, double r)
+{
+    double acc = 0.0;
+    for (int m = -M1; m <= M2 - 1; ++m) acc += orc_f_dr(t0 + m * h, r, lambda);
+    return h * (w * orc_f_dr(t0 + M2 * h, r, lambda) + acc);
+}
+
+typedef struct { double lambda, rc, h; int M1, M2; } c1_ctx;
+
+/* Residual of the force-continuity (C1) condition, eq. (1.25), with w_{M2}
+ * eliminated through eq. (2.42): R(t0) = Y'(rc) - F'(rc; t0, w(t0)). */
+static double c1_residual(double t0, void *vctx)
+{
+    const c1_ctx *c = (const c1_ctx *)vctx;
+    double w = orc_sog_w(c->lambda, c->rc, c->h, t0, c->M1, c->M2);
+    return orc_yukawa_dr(c->rc, c->lambda) - orc_sog_far_dr(c->lambda, c->h, t0, w, c->M1, c->M2, c->rc);
+}
+
+double orc_sog_c1_residual(double lambda, double rc, double h, double t0, int M1, int M2)
+{
+    c1_ctx c = {lambda, rc, h, M1, M2};
+    return c1_residual(t0, &c);
+}
+
+/* Brent's root finder (bisection safeguarded by secant and inverse quadratic
+ * interpolation; R. P. Brent, "Algorithms for Minimization without
+ * Derivatives", 1973).  Requires fa*fb < 0. */
+static double brent(double (*fn)(double, void *), void *ctx, double a, double b, double fa, double fb,
+                    double xtol)
+{
+    double c = a, fc = fa, d = b - a, e = d;
+    for (int it = 0; it < 300; ++it) {
+        if ((fb > 0.0 && fc > 0.0) || (fb < 0.0 && fc < 0.0)) {
+            c = a; fc = fa; d = b - a; e = d;
+        }
+        if (fabs(fc) < fabs(fb)) {
+            a = b; b = c; c = a;
+            fa = fb; fb = fc; fc = fa;
+        }
+        double tol = 2.0 * DBL_EPSILON * fabs(b) + 0.5 * xtol;
+        double mid = 0.5 * (c - b);
+        if (fabs(mid) <= tol || fb == 0.0) return b;
+        if (fabs(e) >= tol && fabs(fa) > fabs(fb)) {
+            double s = fb / fa, p, q;
+            if (a == c) {
+                p = 2.0 * mid * s;
+                q = 1.0 - s;
+            } else {
+                double qq = fa / fc, r = fb / fc;
+                p = s * (2.0 * mid * qq * (qq - r) - (b - a) * (r - 1.0));
+                q = (qq - 1.0) * (r - 1.0) * (s - 1.0);
+            }
+            if (p > 0.0) q = -q; else p = -p;
+            double lim1 = 3.0 * mid * q - fabs(tol * q), lim2 = fabs(e * q);
+            if (2.0 * p < (lim1 < lim2 ? lim1 : lim2)) { e = d; d = p / q; }
+            else { d = mid; e = mid; }
+        } else {
+            d = mid; e = mid;
+        }
+        a = b; fa = fb;
+        b += (fabs(d) > tol) ? d : (mid > 0.0 ? tol : -tol);
+        fb = fn(b, ctx);
+    }
+    return b;
+}
+
+/* Algorithm 1 step 6 for fixed (h, M1, M2): the starting point t0 in [0,h)
+ * that satisfies C1 (eq. 1.25) with w from C0 (eq. 2.42).  The paper allows
+ * several roots; the reading taken is the smallest root in [0,h) whose weight
+ * w is positive (this is the root printed in Table 1 for every row).
+ * Roots are bracketed by a scan of [0,h) in 400 equal subintervals and refined
+ * with Brent's method.  Returns 0 and sets *t0,*w on success, -1 if no root. */
+int orc_sog_c1_root(double lambda, double rc, double h, int M1, int M2, double *t0_out, double *w_out)
+{
+    c1_ctx c = {lambda, rc, h, M1, M2};
+    const int nscan = 400;
+    double a = 0.0, fa = c1_residual(a, &c);
+    for (int k = 0; k < nscan; ++k) {
+        double b = (double)(k + 1) * h / (double)nscan;
+        double fb = c1_residual(b, &c);
+        double root = NAN;
+        if (fa == 0.0) root = a;
+        else if ((fa < 0.0 && fb > 0.0) || (fa > 0.0 && fb < 0.0)) root = brent(c1_residual, &c, a, b, fa, fb, 1e-15);
+        /* accept only a genuine zero of the residual (a sign change across a
+         * jump of an undetermined w is not a root) */
+        if (!isnan(root) && !(fabs(c1_residual(root, &c)) <= 1e-8 * fabs(orc_yukawa_dr(rc, lambda)))) root = NAN;
+        if (!isnan(root) && root < h) {
+            double w = orc_sog_w(lambda, rc, h, root, M1, M2);
+            if (w > 0.0 && isfinite(w)) {
+                *t0_out = root;
+                *w_out = w;
+                return 0;
+            }
+        }
+        a = b; fa = fb;
+    }
+    return -1;
+}
+
+/* max_{r in G} |Y(r) - F(r)| on the grid G = { rc + (33 lambda - rc) u^2 : u = j/1600,
+ * j = 0..1600 }, the approximation range [delta, R] = [rc, 33 lambda] of
+ * Section 3.2 sampled densely near rc. */
+double orc_sog_maxerr(double lambda, double rc, double h, double t0, double w, int M1, int M2)
+{
+    double R = 33.0 * lambda, emax = 0.0;
+    for (int j = 0; j <= 1600; ++j) {
+        double u = (double)j / 1600.0;
+        double r = rc + (R - rc) * u * u;
+        double e = fabs(orc_yukawa(r, lambda) - orc_sog_far(lambda, h, t0, w, M1, M2, r));
+        if (e > emax) emax = e;
+    }
+    return emax;
+}
+
+/* Algorithm 1 with the numbers of Gaussians chosen automatically.  The
+ * paper's truncation criteria (eqs. 2.33-2.34) need t0, which in turn needs
+ * M1, M2; the reading taken is the smallest total M_tot = M1 + M2 + 1 for which
+ * a C1 root with w > 0 exists and the pointwise error on [rc, 33 lambda] is at
+ * most eps.  For each M_tot the candidates are M2 = -12 .. M_tot-1 in that
+ * order (M1 = M_tot - 1 - M2 >= 0); the first one accepted is returned. */
+int orc_sog_auto(double lambda, double rc, double eps, int *M1_out, int *M2_out, double *h_out,
+                 double *t0_out, double *w_out, double *err_out)
+{
+    double h = orc_h_star(eps, rc);
+    for (int Mtot = 1; Mtot <= 48; ++Mtot) {
+        for (int M2 = -12; M2 <= Mtot - 1; ++M2) {
+            int M1 = Mtot - 1 - M2;
+            if (M1 < 0) continue;
+            double t0, w;
+            if (orc_sog_c1_root(lambda, rc, h, M1, M2, &t0, &w) != 0) continue;
+            double err = orc_sog_maxerr(lambda, rc, h, t0, w, M1, M2);
+            if (err <= eps) {
+                *M1_out = M1; *M2_out = M2; *h_out = h; *t0_out = t0; *w_out = w; *err_out = err;
+                return 0;
+            }
+        }
+    }
+    return -1;
+}
+
+/* Expansion of the SOG (eq. 2.41) into Gaussian coefficients, index
+ * j = m + M1 for m = -M1..M2 (ascending m), and of its 3-D Fourier transform
+ * (Section 4.1, the transform of F):
+ *   t_m = t0 + m h,  s_j = e^{t_m},
+ *   c_j = (h / sqrt(pi)) exp(t_m/2 - e^{-t_m}/(4 lambda^2))   (times w at m = M2),
+ *   A_j = pi^{3/2} c_j / (s_j sqrt(s_j)),  B_j = 1 / (4 s_j),
+ * so that F(r) = sum_j c_j exp(-s_j r^2) and Fhat(k) = sum_j A_j exp(-B_j k^2).
+ * The evaluation order of every expression is part of the contract with the
+ * sampler (the shell weights must be reproducible bit for bit). */
+void orc_sog_expand(double lambda, double h, double t0, double w, int M1, int M2, double *c, double *s,
+                    double *A, double *B)
+{
+    const double pi = ORC_PI;
+    const double pi32 = pi * sqrt(pi);
+    const double inv4l2 = 1.0 / (4.0 * lambda * lambda);
+    for (int m = -M1; m <= M2; ++m) {
+        int j = m + M1;
+        double t = t0 + (double)m * h;
+        double sj = exp(t);
+        double cj = (h / sqrt(pi)) * exp(0.5 * t - exp(-t) * inv4l2);
+        if (m == M2) cj = cj * w;
+        c[j] = cj;
+        s[j] = sj;
+        A[j] = pi32 * cj / (sj * sqrt(sj));
+        B[j] = 1.0 / (4.0 * sj);
+    }
+}
+
+/* F(r) and Fhat(k^2) from the expanded coefficients, summed in ascending j. */
+double orc_F(int nG, const double *c, const double *s, double r)
+{
+    double acc = 0.0;
+    for (int j = 0; j < nG; ++j) acc += c[j] * exp(-s[j] * r * r);
+    return acc;
+}
+
+double orc_Fhat(int nG, const double *A, const double *B, double k2)
+{
+    double acc = 0.0;
+    for (int j = 0; j < nG; ++j) acc += A[j] * exp(-B[j] * k2);
+    return acc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Section 4.3: the adaptive importance-sampling density                      */
+/* ------------------------------------------------------------------------- */
+
+enum { ORC_ADAPTIVE = 0, ORC_FLAT = 1, ORC_K2 = 2, ORC_DH4PI = 3 };
+
+/* Correction factor F(k) of the sampling measure P(k) = F(k) Fhat(k) / S
+ * (eq. 3.124).  ADAPTIVE is the leading Debye-Hueckel term of eq. (3.22),
+ * kTV / (kTV/sum q^2 + eps(k)^{-1}/k^2) with eps(k) = 1 + (lambda k)^{-2}
+ * (eq. epsilon), so eps^{-1}/k^2 = lambda^2/(1 + lambda^2 k^2), taken literally
+ * as printed.  FLAT (F = 1) and K2 (F = k^2) are the two earlier densities the
+ * paper compares against in Section 4.2; DH4PI keeps the 4 pi that the
+ * potential's own Fourier transform carries (4 pi lambda^2/(1 + lambda^2 k^2)). */
+double orc_density(int kind, double kT, double V, double Q2, double lambda, double k2)
+{
+    double l2 = lambda * lambda;
+    switch (kind) {
+    case ORC_FLAT: return 1.0;
+    case ORC_K2: return k2;
+    case ORC_DH4PI: return (kT * V) / ((kT * V) / Q2 + (4.0 * ORC_PI * l2) / (1.0 + l2 * k2));
+    default: return (kT * V) / ((kT * V) / Q2 + l2 / (1.0 + l2 * k2));
+    }
+}
+
+/* Default lattice truncation: the largest m >= 1 with Fhat(tk2 m) >= 1e-16 Fhat(0),
+ * tk2 = (2 pi / L)^2.  Fhat decreases monotonically in k^2, so the sum over
+ * |n|^2 <= m_max holds every term above that level. */
+int orc_mmax_default(int nG, const double *A, const double *B, double L)
+{
+    double t = (2.0 * ORC_PI) / L;
+    double tk2 = t * t;
+    double thr = 1e-16 * orc_Fhat(nG, A, B, 0.0);
+    int m = 1;
+    while (orc_Fhat(nG, A, B, tk2 * (double)(m + 1)) >= thr) ++m;
+    return m;
+}
+
+/* The integer lattice {n in Z^3 : 1 <= |n|^2 <= mmax}, sorted by
+ * (|n|^2, nx, ny, nz) ascending.  n3 holds [count][3]; start[m] is the first
+ * index with |n|^2 = m, for m = 0..mmax+1 (start[mmax+1] = count).
+ * A plain enumeration followed by a counting placement per shell. */
+int64_t orc_lattice_count(int mmax)
+{
+    int R = (int)floor(sqrt((double)mmax)) + 1;
+    int64_t cnt = 0;
+    for (int a = -R; a <= R; ++a)
+        for (int b = -R; b <= R; ++b)
+            for (int c = -R; c <= R; ++c) {
+                int64_t m = (int64_t)a * a + (int64_t)b * b + (int64_t)c * c;
+                if (m >= 1 && m <= mmax) ++cnt;
+            }
+    return cnt;
+}
+
+void orc_lattice_build(int mmax, int32_t *n3, int64_t *start)
+{
+    int R = (int)floor(sqrt((double)mmax)) + 1;
+    int64_t *fill = (int64_t *)calloc((size_t)mmax + 2, sizeof(int64_t));
+    for (int m = 0; m <= mmax + 1; ++m) start[m] = 0;
+    /* counts per shell */
+    for (int a = -R; a <= R; ++a)
+        for (int b = -R; b <= R; ++b)
+            for (int c = -R; c <= R; ++c) {
+                int64_t m = (int64_t)a * a + (int64_t)b * b + (int64_t)c * c;
+                if (m >= 1 && m <= mmax) fill[m]++;
+            }
+    int64_t run = 0;
+    for (int m = 0; m <= mmax; ++m) {
+        start[m] = run;
+        run += fill[m];
+        fill[m] = 0;
+    }
+    start[mmax + 1] = run;
+    /* enumeration in (nx, ny, nz) ascending order keeps each shell sorted */
+    for (int a = -R; a <= R; ++a)
+        for (int b = -R; b <= R; ++b)
+            for (int c = -R; c <= R; ++c) {
+                int64_t m = (int64_t)a * a + (int64_t)b * b + (int64_t)c * c;
+                if (m >= 1 && m <= mmax) {
+                    int64_t p = start[m] + fill[m]++;
+                    n3[3 * p + 0] = a;
+                    n3[3 * p + 1] = b;
+                    n3[3 * p + 2] = c;
+                }
+            }
+    free(fill);
+}
+
+/* Cumulative shell weights of P(k) = F(k) Fhat(k) / S restricted to the
+ * lattice {1 <= |n|^2 <= mmax}, k = (2 pi / L) n.  In a cubic box both F and
+ * Fhat depend on |n|^2 only, so the measure is a per-shell weight
+ * W(m) = F(k^2) Fhat(k^2) times the shell size r3(m).  For the shells m with
+ * r3(m) > 0 in ascending m: cdf_i = cdf_{i-1} + r3(m_i) W(m_i), S = cdf_last.
+ * Also returns per shell the coefficient coef = S / (P V F(k^2)) of the
+ * estimators of eq. (UF).  Returns the number of shells. */
+int orc_shell_table(int mmax, const int64_t *start, int nG, const double *A, const double *B, double L,
+                    int kind, double kT, double Q2, double lambda, int P, int32_t *shell_m, double *cdf,
+                    double *coef)
+{
+    double t = (2.0 * ORC_PI) / L;
+    double tk2 = t * t;
+    double V = L * L * L;
+    int ns = 0;
+    double run = 0.0;
+    for (int m = 1; m <= mmax; ++m) {
+        int64_t r3 = start[m + 1] - start[m];
+        if (r3 <= 0) continue;
+        double k2 = tk2 * (double)m;
+        double Fk = orc_density(kind, kT, V, Q2, lambda, k2);
+        double W = Fk * orc_Fhat(nG, A, B, k2);
+        run = run + (double)r3 * W;
+        shell_m[ns] = m;
+        cdf[ns] = run;
+        ns++;
+    }
+    double S = run;
+    for (int i = 0; i < ns; ++i) {
+        double k2 = tk2 * (double)shell_m[i];
+        double Fk = orc_density(kind, kT, V, Q2, lambda, k2);
+        coef[i] = S / ((double)P * V * Fk);
+    }
+    return ns;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Counter-based random numbers: Philox4x64-10 (Salmon, Moraes, Dror & Shaw,  */
+/* "Parallel random numbers: as easy as 1, 2, 3", SC'11).                     */
+/* ------------------------------------------------------------------------- */
+
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+{
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        uint64_t hi0, lo0, hi1, lo1;
+        mulhilo64(M0, x0, &hi0, &lo0);
+        mulhilo64(M1, x2, &hi1, &lo1);
+        uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Algorithm 2, first step of each time step: draw P i.i.d. Fourier modes from
+ * P(k).  The paper draws them with a Metropolis-Hastings chain whose details it
+ * does not give; the reading taken here is exact inverse-CDF sampling of the
+ * same measure, which is what the unbiasedness lemma assumes.
+ * Sample l at force-evaluation index `step`:
+ *   (w0,w1,w2,w3) = Philox4x64-10(counter = (l, step, 0, 0), key = (seed, replica));
+ *   u = (w0 >> 11) 2^-53;  target = u S;
+ *   i = first shell with cdf_i > target (the last shell if none);
+ *   j = floor(w1 r3(m_i) / 2^64)  (high word of the 64x64 product);
+ *   n_l = lattice[start[m_i] + j],  coef_l = coef of shell i. */
+void orc_draw(int P, uint64_t step, uint64_t seed, uint32_t replica, int nshell, const int32_t *shell_m,
+              const double *cdf, const double *shell_coef, const int64_t *start, const int32_t *n3,
+              int32_t *n_out, double *coef_out)
+{
+    double S = cdf[nshell - 1];
+    for (int l = 0; l < P; ++l) {
+        uint64_t ctr[4] = {(uint64_t)l, step, 0, 0}, key[2] = {seed, (uint64_t)replica}, w[4];
+        orc_philox4x64_10(ctr, key, w);
+        double u = (double)(w[0] >> 11) * (1.0 / 9007199254740992.0);
+        double target = u * S;
+        int lo = 0, hi = nshell; /* first index with cdf > target */
+        while (lo < hi) {
+            int mid = lo + (hi - lo) / 2;
+            if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        int i = lo < nshell ? lo : nshell - 1;
+        int m = shell_m[i];
+        uint64_t r3 = (uint64_t)(start[m + 1] - start[m]);
+        uint64_t jhi, jlo;
+        mulhilo64(w[1], r3, &jhi, &jlo);
+        int64_t p = start[m] + (int64_t)jhi;
+        n_out[3 * l + 0] = n3[3 * p + 0];
+        n_out[3 * l + 1] = n3[3 * p + 1];
+        n_out[3 * l + 2] = n3[3 * p + 2];
+        coef_out[l] = shell_coef[i];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cell list (the neighbour set of eq. 3.8, built as cells of width >= rc)    */
+/* ------------------------------------------------------------------------- */
+
+/* nc = floor(L/rc) cells per axis, inv = nc/L, c_d = clamp(floor(x_d inv), 0, nc-1),
+ * id = (c_z nc + c_y) nc + c_x.  cell_start[nc^3+1] and order[N] list the
+ * particles sorted by id, ties in ascending particle index (a stable sort of
+ * the original order).  Returns nc. */
+int orc_cells(int64_t N, const double *x, double L, double rc, int32_t *cell_start, int32_t *order)
+{
+    int nc = (int)floor(L / rc);
+    double inv = (double)nc / L;
+    int64_t ncell = (int64_t)nc * nc * nc;
+    int32_t *id = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));
+    int64_t *cnt = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < N; ++i) {
+        int cd[3];
+        for (int d = 0; d < 3; ++d) {
+            double f = floor(x[d * N + i] * inv);
+            int c = (int)f;
+            if (f < 0.0) c = 0;
+            if (c > nc - 1) c = nc - 1;
+            cd[d] = c;
+        }
+        id[i] = (cd[2] * nc + cd[1]) * nc + cd[0];
+        cnt[id[i]]++;
+    }
+    int64_t run = 0;
+    for (int64_t c = 0; c < ncell; ++c) {
+        cell_start[c] = (int32_t)run;
+        run += cnt[c];
+        cnt[c] = 0;
+    }
+    cell_start[ncell] = (int32_t)run;
+    for (int64_t i = 0; i < N; ++i) {
+        int c = id[i];
+        order[cell_start[c] + cnt[c]++] = (int32_t)i;
+    }
+    free(cnt);
+    free(id);
+    return nc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Section 4.1, eq. (3.8): near field                                         */
+/* ------------------------------------------------------------------------- */
+
+/* Pair force factor and energy of the near part N(r) = Y(r) - F(r), r < rc
+ * (eq. short):  F_N1(r) = e^{-r/lambda}(1 + r/lambda)/r^3,
+ * F_N2(r) = -2 sum_j c_j s_j e^{-s_j r^2};  the force on i from j is
+ * q_i q_j (F_N1 + F_N2) d with d = r_i - r_j (minimum image; eq. 3.8 is
+ * written with r_ij, whose sign is read so that like charges repel). */
+static void near_pair(double r2, double lambda, int nG, const double *c, const double *s, double *fac,
+                      double *en)
+{
+    double r = sqrt(r2);
+    double ey = exp(-r / lambda);
+    double f1 = ey * (1.0 + r / lambda) / (r2 * r);
+    double f2 = 0.0, fr = 0.0;
+    for (int j = 0; j < nG; ++j) {
+        double g = exp(-s[j] * r2);
+        f2 += c[j] * s[j] * g;
+        fr += c[j] * g;
+    }
+    *fac = f1 - 2.0 * f2;
+    *en = ey / r - fr;
+}
+
+/* Near-field forces (written to f, SoA) and energy U_N = 1/2 sum over ordered
+ * pairs and images of q_i q_j N(|d|) with 0 < |d| < rc.  With L >= 3 rc and
+ * N > 2000 the pairs are found through the cell list; otherwise every image
+ * shift that can reach within rc is looped over directly (tiny boxes). */
+void orc_near(int64_t N, const double *x, const double *q, double L, double lambda, double rc, int nG,
+              const double *c, const double *s, double *f, double *U_out)
+{
+    double rc2 = rc * rc;
+    double *ei = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
+    int nc = (int)floor(L / rc);
+    if (nc >= 3 && N > 2000) {
+        int32_t *cs = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nc * nc * nc + 1));
+        int32_t *ord = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+        orc_cells(N, x, L, rc, cs, ord);
+        double inv = (double)nc / L;
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t i = 0; i < N; ++i) {
+            double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
+            int ci[3];
+            for (int d = 0; d < 3; ++d) {
+                double fl = floor(x[d * N + i] * inv);
+                int cc = (int)fl;
+                if (fl < 0.0) cc = 0;
+                if (cc > nc - 1) cc = nc - 1;
+                ci[d] = cc;
+            }
+            double fx = 0, fy = 0, fz = 0, e = 0;
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int cx = ci[0] + dx, cy = ci[1] + dy, cz = ci[2] + dz;
+                        double sx = 0, sy = 0, sz = 0; /* image shift of the neighbour cell */
+                        if (cx < 0) { cx += nc; sx = -L; } else if (cx >= nc) { cx -= nc; sx = L; }
+                        if (cy < 0) { cy += nc; sy = -L; } else if (cy >= nc) { cy -= nc; sy = L; }
+                        if (cz < 0) { cz += nc; sz = -L; } else if (cz >= nc) { cz -= nc; sz = L; }
+                        int cell = (cz * nc + cy) * nc + cx;
+                        for (int32_t p = cs[cell]; p < cs[cell + 1]; ++p) {
+                            int64_t j = ord[p];
+                            if (j == i) continue;
+                            double dx_ = xi - (x[j] + sx), dy_ = yi - (x[N + j] + sy), dz_ = zi - (x[2 * N + j] + sz);
+                            double r2 = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
+                            if (r2 >= rc2) continue;
+                            double fac, en;
+                            near_pair(r2, lambda, nG, c, s, &fac, &en);
+                            double qq = q[i] * q[j];
+                            fx += qq * fac * dx_; fy += qq * fac * dy_; fz += qq * fac * dz_;
+                            e += 0.5 * qq * en;
+                        }
+                    }
+            f[i] = fx; f[N + i] = fy; f[2 * N + i] = fz;
+            ei[i] = e;
+        }
+        free(cs);
+        free(ord);
+    } else {
+        int nimg = (int)ceil(rc / L);
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t i = 0; i < N; ++i) {
+            double fx = 0, fy = 0, fz = 0, e = 0;
+            for (int64_t j = 0; j < N; ++j) {
+                for (int a = -nimg; a <= nimg; ++a)
+                    for (int b = -nimg; b <= nimg; ++b)
+                        for (int cc = -nimg; cc <= nimg; ++cc) {
+                            if (j == i && a == 0 && b == 0 && cc == 0) continue;
+                            double dx_ = x[i] - x[j] - a * L;
+                            double dy_ = x[N + i] - x[N + j] - b * L;
+                            double dz_ = x[2 * N + i] - x[2 * N + j] - cc * L;
+                            double r2 = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
+                            if (r2 >= rc2 || r2 == 0.0) continue;
+                            double fac, en;
+                            near_pair(r2, lambda, nG, c, s, &fac, &en);
+                            double qq = q[i] * q[j];
+                            fx += qq * fac * dx_; fy += qq * fac * dy_; fz += qq * fac * dz_;
+                            e += 0.5 * qq * en;
+                        }
+            }
+            f[i] = fx; f[N + i] = fy; f[2 * N + i] = fz;
+            ei[i] = e;
+        }
+    }
+    double U = 0.0;
+    for (int64_t i = 0; i < N; ++i) U += ei[i];
+    *U_out = U;
+    free(ei);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Section 2 and 4.1: structure factors and the far field                     */
+/* ------------------------------------------------------------------------- */
+
+/* rho(k_l) = sum_j q_j e^{i k_l . r_j} with k_l = (2 pi/L) n_l (Section 2).
+ * rho is [P][2] = (re, im).  The phase is formed literally as k . r. */
+void orc_rho(int64_t N, const double *x, const double *q, double L, int P, const int32_t *n3, double *rho)
+{
+    double t = (2.0 * ORC_PI) / L;
+#pragma omp parallel for schedule(static)
+    for (int l = 0; l < P; ++l) {
+        double kx = t * n3[3 * l], ky = t * n3[3 * l + 1], kz = t * n3[3 * l + 2];
+        double re = 0.0, im = 0.0;
+        for (int64_t j = 0; j < N; ++j) {
+            double th = kx * x[j] + ky * x[N + j] + kz * x[2 * N + j];
+            re += q[j] * cos(th);
+            im += q[j] * sin(th);
+        }
+        rho[2 * l] = re;
+        rho[2 * l + 1] = im;
+    }
+}
+
+/* Random-batch far force, eq. (UF):  F*_i = -(S/(2PV)) sum_l grad_i |rho_l|^2 / F(k_l)
+ * with grad_i |rho|^2 = 2 q_i k Im(e^{-i k.r_i} rho), i.e.
+ * F*_i = -q_i sum_l coef_l k_l (rho_im cos th - rho_re sin th),  coef = S/(P V F(k)).
+ * Adds into f (SoA). */
+void orc_far_rb(int64_t N, const double *x, const double *q, double L, int P, const int32_t *n3,
+                const double *coef, const double *rho, double *f)
+{
+    double t = (2.0 * ORC_PI) / L;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double fx = 0, fy = 0, fz = 0;
+        for (int l = 0; l < P; ++l) {
+            double kx = t * n3[3 * l], ky = t * n3[3 * l + 1], kz = t * n3[3 * l + 2];
+            double th = kx * x[i] + ky * x[N + i] + kz * x[2 * N + i];
+            double im = rho[2 * l + 1] * cos(th) - rho[2 * l] * sin(th);
+            double g = coef[l] * im;
+            fx += g * kx; fy += g * ky; fz += g * kz;
+        }
+        f[i] -= q[i] * fx;
+        f[N + i] -= q[i] * fy;
+        f[2 * N + i] -= q[i] * fz;
+    }
+}
+
+/* Estimator of the far energy, eq. (UF): U*_F = S/(2PV) sum_l |rho_l|^2 / F(k_l)
+ * = 1/2 sum_l coef_l |rho_l|^2. */
+double orc_far_rb_energy(int P, const double *coef, const double *rho)
+{
+    double U = 0.0;
+    for (int l = 0; l < P; ++l) U += coef[l] * (rho[2 * l] * rho[2 * l] + rho[2 * l + 1] * rho[2 * l + 1]);
+    return 0.5 * U;
+}
+
+/* Deterministic far field summed over every lattice mode 1 <= |n|^2 <= mmax
+ * (eqs. 3.5 and 3.8, k = 0 excluded; its energy is added separately):
+ *   U_F = (1/2V) sum_k Fhat(k) |rho(k)|^2,
+ *   F_i += -(q_i/V) sum_k k Fhat(k) Im(e^{-ik.r_i} rho(k)).
+ * Adds into f; returns U_F. */
+double orc_far_full(int64_t N, const double *x, const double *q, double L, int nG, const double *A,
+                    const double *B, int mmax, double *f)
+{
+    int64_t cnt = orc_lattice_count(mmax);
+    int32_t *n3 = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)cnt);
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * ((size_t)mmax + 2));
+    orc_lattice_build(mmax, n3, start);
+    double t = (2.0 * ORC_PI) / L, V = L * L * L;
+    double *rho = (double *)malloc(sizeof(double) * 2 * (size_t)cnt);
+    double *fh = (double *)malloc(sizeof(double) * (size_t)cnt);
+    for (int64_t p = 0; p < cnt; ++p) {
+        double m = (double)n3[3 * p] * n3[3 * p] + (double)n3[3 * p + 1] * n3[3 * p + 1] +
+                   (double)n3[3 * p + 2] * n3[3 * p + 2];
+        fh[p] = orc_Fhat(nG, A, B, t * t * m);
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < cnt; ++p) {
+        double kx = t * n3[3 * p], ky = t * n3[3 * p + 1], kz = t * n3[3 * p + 2];
+        double re = 0.0, im = 0.0;
+        for (int64_t j = 0; j < N; ++j) {
+            double th = kx * x[j] + ky * x[N + j] + kz * x[2 * N + j];
+            re += q[j] * cos(th);
+            im += q[j] * sin(th);
+        }
+        rho[2 * p] = re;
+        rho[2 * p + 1] = im;
+    }
+    double U = 0.0;
+    for (int64_t p = 0; p < cnt; ++p) U += fh[p] * (rho[2 * p] * rho[2 * p] + rho[2 * p + 1] * rho[2 * p + 1]);
+    U = U / (2.0 * V);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < N; ++i) {
+        double fx = 0, fy = 0, fz = 0;
+        for (int64_t p = 0; p < cnt; ++p) {
+            double kx = t * n3[3 * p], ky = t * n3[3 * p + 1], kz = t * n3[3 * p + 2];
+            double th = kx * x[i] + ky * x[N + i] + kz * x[2 * N + i];
+            double im = rho[2 * p + 1] * cos(th) - rho[2 * p] * sin(th);
+            double g = fh[p] * im;
+            fx += g * kx; fy += g * ky; fz += g * kz;
+        }
+        f[i] -= q[i] * fx / V;
+        f[N + i] -= q[i] * fy / V;
+        f[2 * N + i] -= q[i] * fz / V;
+    }
+    free(n3); free(start); free(rho); free(fh);
+    return U;
+}
+
+/* ------------------------------------------------------------------------- */
+/* A whole system: tables, one force evaluation, Algorithm 2's time loop      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int64_t N;
+    double L, V, lambda, rc, kT, Q1, Q2;
+    int P, mmax, density, full_k, nG;
+    uint64_t seed;
+    uint32_t replica;
+    double c[64], s[64], A[64], B[64];
+    double F0, Fhat0;
+    const double *q, *m; /* caller-owned, length N */
+    /* sampling tables */
+    int64_t nlat;
+    int32_t *n3;
+    int64_t *start;
+    int nshell;
+    int32_t *shell_m;
+    double *cdf, *shell_coef;
+} orc_sys;
+
+/* Builds the sampling tables of a system.  q and m must outlive the system. */
+orc_sys *orc_sys_create(int64_t N, double L, double lambda, double rc, double kT, int P, int mmax,
+                        uint64_t seed, uint32_t replica, int density, int full_k, int nG, const double *c,
+                        const double *s, const double *A, const double *B, const double *q, const double *m)
+{
+    if (nG < 1 || nG > 64) return NULL;
+    orc_sys *S = (orc_sys *)calloc(1, sizeof(orc_sys));
+    S->N = N; S->L = L; S->V = L * L * L; S->lambda = lambda; S->rc = rc; S->kT = kT;
+    S->P = P; S->density = density; S->full_k = full_k; S->nG = nG;
+    S->seed = seed; S->replica = replica; S->q = q; S->m = m;
+    memcpy(S->c, c, sizeof(double) * nG); memcpy(S->s, s, sizeof(double) * nG);
+    memcpy(S->A, A, sizeof(double) * nG); memcpy(S->B, B, sizeof(double) * nG);
+    double q1 = 0.0, q2 = 0.0;
+    for (int64_t i = 0; i < N; ++i) { q1 += q[i]; q2 += q[i] * q[i]; }
+    S->Q1 = q1; S->Q2 = q2;
+    S->F0 = 0.0; for (int j = 0; j < nG; ++j) S->F0 += c[j];
+    S->Fhat0 = orc_Fhat(nG, A, B, 0.0);
+    S->mmax = mmax > 0 ? mmax : orc_mmax_default(nG, A, B, L);
+    S->nlat = orc_lattice_count(S->mmax);
+    S->n3 = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)S->nlat);
+    S->start = (int64_t *)malloc(sizeof(int64_t) * ((size_t)S->mmax + 2));
+    orc_lattice_build(S->mmax, S->n3, S->start);
+    S->shell_m = (int32_t *)malloc(sizeof(int32_t) * ((size_t)S->mmax + 1));
+    S->cdf = (double *)malloc(sizeof(double) * ((size_t)S->mmax + 1));
+    S->shell_coef = (double *)malloc(sizeof(double) * ((size_t)S->mmax + 1));
+    S->nshell = orc_shell_table(S->mmax, S->start, nG, A, B, L, density, kT, q2, lambda, P, S->shell_m,
+                                S->cdf, S->shell_coef);
+    return S;
+}
+
+void orc_sys_destroy(orc_sys *S)
+{
+    if (!S) return;
+    free(S->n3); free(S->start); free(S->shell_m); free(S->cdf); free(S->shell_coef);
+    free(S);
+}
+
+int orc_sys_mmax(const orc_sys *S) { return S->mmax; }
+int orc_sys_nshell(const orc_sys *S) { return S->nshell; }
+int64_t orc_sys_nlat(const orc_sys *S) { return S->nlat; }
+void orc_sys_tables(const orc_sys *S, int32_t *shell_m, double *cdf, double *coef)
+{
+    memcpy(shell_m, S->shell_m, sizeof(int32_t) * S->nshell);
+    memcpy(cdf, S->cdf, sizeof(double) * S->nshell);
+    memcpy(coef, S->shell_coef, sizeof(double) * S->nshell);
+}
+void orc_sys_lattice(const orc_sys *S, int32_t *n3, int64_t *start)
+{
+    memcpy(n3, S->n3, sizeof(int32_t) * 3 * (size_t)S->nlat);
+    memcpy(start, S->start, sizeof(int64_t) * ((size_t)S->mmax + 2));
+}
+
+void orc_sys_draw(const orc_sys *S, uint64_t step, int32_t *n_out, double *coef_out)
+{
+    orc_draw(S->P, step, S->seed, S->replica, S->nshell, S->shell_m, S->cdf, S->shell_coef, S->start, S->n3,
+             n_out, coef_out);
+}
+
+/* One force evaluation at force-evaluation index `step` (Algorithm 2, lines
+ * 3-5).  f (SoA) receives near + far forces; f_near (nullable) the near part
+ * alone.  energy[6] (nullable) = { U_N, U_F (estimator, or the full sum in
+ * full-k mode), U_k0, U_self, U_bg, 0 }, where
+ *   U_k0   = Fhat(0) (sum q)^2 / (2V)  -- the k = 0 mode of eq. (3.5), excluded
+ *            from sampling and added deterministically;
+ *   U_self = -1/2 sum q_i^2 F(0)       -- Section 4.1;
+ *   U_bg   = -(sum q)^2 4 pi lambda^2 / (2V) -- the uniform neutralising
+ *            background's interaction energy (constant, no force). */
+void orc_sys_force(const orc_sys *S, uint64_t step, const double *x, double *f, double *f_near, double *energy)
+{
+    int64_t N = S->N;
+    double UN = 0.0, UF = 0.0;
+    orc_near(N, x, S->q, S->L, S->lambda, S->rc, S->nG, S->c, S->s, f, &UN);
+    if (f_near) memcpy(f_near, f, sizeof(double) * 3 * (size_t)N);
+    if (S->full_k) {
+        UF = orc_far_full(N, x, S->q, S->L, S->nG, S->A, S->B, S->mmax, f);
+    } else {
+        int32_t *n = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)S->P);
+        double *coef = (double *)malloc(sizeof(double) * (size_t)S->P);
+        double *rho = (double *)malloc(sizeof(double) * 2 * (size_t)S->P);
+        orc_sys_draw(S, step, n, coef);
+        orc_rho(N, x, S->q, S->L, S->P, n, rho);
+        orc_far_rb(N, x, S->q, S->L, S->P, n, coef, rho, f);
+        UF = orc_far_rb_energy(S->P, coef, rho);
+        free(n); free(coef); free(rho);
+    }
+    if (energy) {
+        energy[0] = UN;
+        energy[1] = UF;
+        energy[2] = S->Fhat0 * S->Q1 * S->Q1 / (2.0 * S->V);
+        energy[3] = -0.5 * S->Q2 * S->F0;
+        energy[4] = -(S->Q1 * S->Q1) * (4.0 * ORC_PI * S->lambda * S->lambda) / (2.0 * S->V);
+        energy[5] = 0.0;
+    }
+}
+
+static double kinetic(const orc_sys *S, const double *v)
+{
+    int64_t N = S->N;
+    double ke = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+        ke += 0.5 * S->m[i] * (v[i] * v[i] + v[N + i] * v[N + i] + v[2 * N + i] * v[2 * N + i]);
+    return ke;
+}
+
+/* Velocity-Verlet (Algorithm 2, last line; Section 5.1), with f = F(x, step0)
+ * on entry.  For each of nsteps steps n = 0..nsteps-1:
+ *   v += (dt/2) f / m;   x += dt v;   wrap x into [0, L);
+ *   f = F(x, step0 + n + 1);   v += (dt/2) f / m.
+ * ehist (nullable) receives [nsteps][6] energies of the new state, with
+ * KE in slot 5.  Returns 0, or -1 if a particle moved a full box length. */
+int orc_sys_run(const orc_sys *S, double *x, double *v, double *f, uint64_t step0, int nsteps, double dt,
+                double *ehist)
+{
+    int64_t N = S->N;
+    double L = S->L;
+    int bad = 0;
+    for (int n = 0; n < nsteps; ++n) {
+        for (int64_t i = 0; i < N; ++i) {
+            double hm = (0.5 * dt) / S->m[i];
+            for (int d = 0; d < 3; ++d) {
+                double vv = v[d * N + i] + hm * f[d * N + i];
+                double dx = dt * vv;
+                if (fabs(dx) >= L) bad = 1;
+                double xx = x[d * N + i] + dx;
+                if (xx >= L) xx -= L;
+                if (xx < 0.0) xx += L;
+                if (xx >= L) xx = 0.0;
+                v[d * N + i] = vv;
+                x[d * N + i] = xx;
+            }
+        }
+        double e[6];
+        orc_sys_force(S, step0 + (uint64_t)n + 1, x, f, NULL, e);
+        for (int64_t i = 0; i < N; ++i) {
+            double hm = (0.5 * dt) / S->m[i];
+            for (int d = 0; d < 3; ++d) v[d * N + i] = v[d * N + i] + hm * f[d * N + i];
+        }
+        if (ehist) {
+            e[5] = kinetic(S, v);
+            memcpy(ehist + 6 * (size_t)n, e, sizeof(e));
+        }
+    }
+    return bad ? -1 : 0;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
