@@ -1,0 +1,238 @@
+/*
+ * rbsog.h -- C-ABI of the MI355X (gfx950) library for the random batch
+ * sum-of-Gaussians (RBSOG) force evaluation and velocity-Verlet step of 3-D
+ * periodic Yukawa systems (Chen, Liang & Xu, "Random batch sum-of-Gaussians
+ * algorithm for molecular dynamics simulations of Yukawa systems in three
+ * dimensions").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an int status: RBSOG_OK (0) or a negative code;
+ *    rbsog_last_error() returns a thread-local message for the last failure.
+ *    Nothing throws across this interface.
+ *  - Pointers named *_dev are device pointers (HIP global memory on the GPU the
+ *    handle was created on); pointers named *_host, and struct pointers, are
+ *    host pointers.  The caller owns every buffer it passes.
+ *  - Particle arrays are FP64 structure-of-arrays in the caller's particle
+ *    order: x[3*N] = {x_0..x_{N-1}, y_0..y_{N-1}, z_0..z_{N-1}}, likewise v and
+ *    f; q[N] charges, m[N] masses.  Positions lie in the cubic box [0, L)^3.
+ *  - All device work is enqueued on the HIP stream given at creation (passed
+ *    as void* so this header needs no HIP include) and is asynchronous with
+ *    respect to the host unless a function says otherwise.
+ *  - The single-system path allocates no device memory after rbsog_create:
+ *    every scratch buffer lives in the caller's workspace, sized by
+ *    rbsog_workspace_size.
+ *  - Force-evaluation index: the random Fourier modes of an evaluation are a
+ *    pure function of (seed, replica, step), so any evaluation can be repeated
+ *    or resumed.  rbsog_step uses step0 for the force given on entry and
+ *    step0 + n + 1 for the force after the (n+1)-th drift.
+ */
+#ifndef RBSOG_H
+#define RBSOG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define RBSOG_OK 0
+#define RBSOG_EINVAL (-1)      /* invalid argument or parameter combination */
+#define RBSOG_ENOROOT (-2)     /* no C1 starting point with positive weight / no SOG meets eps */
+#define RBSOG_EWORKSPACE (-3)  /* workspace missing, misaligned or too small */
+#define RBSOG_EAGAIN (-4)      /* served ensemble: no slot or memory free now */
+#define RBSOG_ENONFINITE (-5)  /* a non-finite force or position was produced */
+#define RBSOG_EHIP (-6)        /* a HIP runtime call failed */
+#define RBSOG_ENOMEM (-7)      /* host memory allocation failed */
+
+/* precision of the force arithmetic */
+#define RBSOG_FP64 0   /* everything in FP64 */
+#define RBSOG_MIXED 1  /* pair-kernel and per-particle phase arithmetic in FP32;
+                          positions, k.r argument reduction, rho(k) and force
+                          accumulation, integration and energies in FP64 */
+
+/* correction F(k) of the importance-sampling measure P(k) = F(k) Fhat(k) / S
+ * (Section 4.3, eq. 3.124) */
+#define RBSOG_ADAPTIVE 0  /* Debye-Hueckel leading term of eq. (3.22), as printed:
+                             kTV / (kTV / sum q^2 + lambda^2 / (1 + lambda^2 k^2)) */
+#define RBSOG_FLAT 1      /* F = 1 (the density of the random batch Ewald method) */
+#define RBSOG_K2 2        /* F = k^2 (the density of the earlier Coulomb RBSOG) */
+#define RBSOG_DH4PI 3     /* as ADAPTIVE with 4 pi lambda^2 in place of lambda^2 */
+
+#define RBSOG_AUTO (-999)   /* M1 = M2 = RBSOG_AUTO: choose the numbers of Gaussians */
+#define RBSOG_MAX_GAUSS 32
+
+/*
+ * SOG decomposition Y(r) = N(r) + F(r) of the Yukawa kernel
+ * Y(r) = exp(-r/lambda)/r (Section 3, Algorithm 1, C1-continuous form):
+ *   F(r)    = h [ w f(t_{M2}, r) + sum_{m=-M1}^{M2-1} f(t_m, r) ]  (eq. 2.41)
+ *           = sum_j c[j] exp(-s[j] r^2),     j = m + M1, m = -M1..M2,
+ *   Fhat(k) = sum_j A[j] exp(-B[j] k^2)      (its 3-D Fourier transform, Section 4.1),
+ * with f(t,r) = pi^{-1/2} exp(-r^2 e^t - e^{-t}/(4 lambda^2) + t/2) (eq. ftr),
+ * t_m = t0 + m h, and N(r) = Y(r) - F(r) for r < r_c, 0 beyond (eq. short).
+ */
+typedef struct rbsog_sog {
+    double lambda, r_c, eps; /* inputs: screening length, near cutoff, tolerance   */
+    double h, t0, w;         /* step (eq. 2.30), starting point, weight of m = M2  */
+    int M1, M2, n;           /* n = M1 + M2 + 1 Gaussians (1..RBSOG_MAX_GAUSS)     */
+    double c[RBSOG_MAX_GAUSS], s[RBSOG_MAX_GAUSS];
+    double A[RBSOG_MAX_GAUSS], B[RBSOG_MAX_GAUSS];
+    double F0;               /* F(0) = sum c                                         */
+    double Fhat0;            /* Fhat(0) = sum A                                      */
+    double max_err;          /* max |Y - F| on [r_c, 33 lambda] (sampled densely)    */
+} rbsog_sog;
+
+/*
+ * Algorithm 1 (Section 3.2): h from eq. (2.30) with delta = r_c, then the
+ * smallest starting point t0 in [0, h) that makes the decomposition C1 at r_c
+ * (eq. 1.25) with w from the C0 condition (eq. 2.42) and w > 0.  With
+ * M1 = M2 = RBSOG_AUTO the smallest total M1 + M2 + 1 whose error on
+ * [r_c, 33 lambda] is <= eps is chosen (for each total, M2 = -12 upward);
+ * otherwise the given M1 >= 0, M2 are used.  Host only, no GPU needed.
+ * Errors: RBSOG_EINVAL (lambda, r_c or eps not positive and finite,
+ * r_c >= 33 lambda, eps >= 1, bad M1/M2), RBSOG_ENOROOT.
+ */
+int rbsog_sog_init(double lambda, double r_c, double eps, int M1, int M2, rbsog_sog *out);
+
+/*
+ * Recomputes c, s, A, B, F0, Fhat0 and max_err of *sog from its lambda, r_c,
+ * h, t0, w, M1, M2 (for a decomposition given by its parameters, e.g. a row of
+ * the paper's Table 1).  The expansion is evaluated in a fixed IEEE FP64
+ * expression order (t = t0 + m h; s = exp(t);
+ * c = (h/sqrt(pi)) exp(t/2 - exp(-t)/(4 lambda^2)) [* w at m = M2];
+ * A = pi sqrt(pi) c / (s sqrt(s)); B = 1/(4 s)), so identical parameters give
+ * identical coefficients on any conforming host.  Host only.
+ * Errors: RBSOG_EINVAL.
+ */
+int rbsog_sog_expand(rbsog_sog *sog);
+
+/* One periodic system. */
+typedef struct rbsog_params {
+    int64_t N;          /* particles, >= 1                                         */
+    double L;           /* cubic box edge; requires floor(L / r_c) >= 3            */
+    double kT;          /* k_B T entering the adaptive density (eq. 3.22), > 0     */
+    int P;              /* random-batch size, 1..4096                              */
+    int mmax;           /* Fourier lattice 1 <= |n|^2 <= mmax, k = 2 pi n / L;
+                           0 = the largest m with Fhat(k^2) >= 1e-16 Fhat(0)       */
+    uint64_t seed;      /* Philox key word 0                                       */
+    uint32_t replica;   /* Philox key word 1                                       */
+    int precision;      /* RBSOG_FP64 or RBSOG_MIXED                               */
+    int density;        /* RBSOG_ADAPTIVE, RBSOG_FLAT, RBSOG_K2 or RBSOG_DH4PI     */
+} rbsog_params;
+
+typedef struct rbsog_handle rbsog_handle;
+
+/* Derived sizes of a created system (host copy). */
+typedef struct rbsog_info {
+    int64_t N;
+    int nc;             /* cells per axis, floor(L / r_c)                          */
+    int mmax;           /* lattice truncation in use                               */
+    int nshell;         /* non-empty shells |n|^2 = m in the lattice               */
+    int64_t nlat;       /* lattice points                                          */
+    double S;           /* normalisation of P(k) (eq. 3.124)                       */
+    double Q1, Q2;      /* sum q, sum q^2                                          */
+    size_t ws_bytes;    /* workspace bytes the system needs                        */
+} rbsog_info;
+
+/*
+ * Bytes of device workspace a system with these parameters needs (the Fourier
+ * lattice, sampling tables, cell list, cell-ordered particle copy, sample and
+ * structure-factor buffers, reduction partials).  Host only.
+ * Errors: RBSOG_EINVAL.
+ */
+int rbsog_workspace_size(const rbsog_params *p, const rbsog_sog *sog, size_t *bytes);
+
+/*
+ * Creates a system.  Builds the Fourier lattice and the shell CDF of P(k) on
+ * the host (eq. 3.124 restricted to the lattice; the measure depends on |n|^2
+ * only in a cubic box), reads q_dev (to form sum q and sum q^2) and uploads the
+ * tables into the caller's workspace, synchronising the stream once.  q_dev and
+ * m_dev (N doubles each, device) are referenced, not copied, and must stay
+ * valid and unchanged for the handle's lifetime; ws_dev must be 256-byte
+ * aligned and at least rbsog_workspace_size bytes, and is owned by the caller.
+ * Errors: RBSOG_EINVAL, RBSOG_EWORKSPACE, RBSOG_EHIP, RBSOG_ENOMEM.
+ */
+int rbsog_create(const rbsog_params *p, const rbsog_sog *sog, const double *q_dev, const double *m_dev,
+                 void *ws_dev, size_t ws_bytes, void *hip_stream, rbsog_handle **out);
+
+/* Copies the derived sizes of a system into *out (host).  Errors: RBSOG_EINVAL. */
+int rbsog_get_info(const rbsog_handle *h, rbsog_info *out);
+
+/*
+ * Cell list of positions x_dev (the neighbour set of eq. 3.8): nc = floor(L/r_c)
+ * cells per axis, cell of x is c_d = clamp(floor(x_d nc/L), 0, nc-1),
+ * id = (c_z nc + c_y) nc + c_x; particles sorted by id with ties in ascending
+ * particle index (a stable sort).  Writes cell_start_dev[nc^3 + 1] and
+ * order_dev[N] (int32, device) when non-null; the list is also kept in the
+ * workspace.  Errors: RBSOG_EINVAL, RBSOG_EHIP.
+ */
+int rbsog_build_cells(rbsog_handle *h, const double *x_dev, int32_t *cell_start_dev, int32_t *order_dev);
+
+/*
+ * Draws the P Fourier modes of force evaluation `step` from P(k) (Algorithm 2,
+ * first step of a time step; eq. 3.124), i.i.d. by inverse CDF:
+ *   (w0..w3) = Philox4x64-10(counter = (l, step, 0, 0), key = (seed, replica));
+ *   target = ((w0 >> 11) 2^-53) S;  shell = first with cdf > target;
+ *   point  = high word of w1 * r3(shell) within the shell, shells sorted by
+ *            (|n|^2, nx, ny, nz).
+ * Writes n_dev[P][3] (int32 lattice vectors, k = 2 pi n / L) and
+ * coef_dev[P] = S / (P V F(k)) (the estimator weight of eq. UF).
+ * Errors: RBSOG_EINVAL, RBSOG_EHIP.
+ */
+int rbsog_sample_k(rbsog_handle *h, uint64_t step, int32_t *n_dev, double *coef_dev);
+
+/*
+ * Structure factors rho(k_l) = sum_j q_j exp(i k_l . r_j) (Section 2) of the
+ * modes of evaluation `step`, rho_dev[P][2] = (re, im), FP64 accumulation in a
+ * fixed order (bitwise reproducible run to run).  Errors: RBSOG_EINVAL, RBSOG_EHIP.
+ */
+int rbsog_compute_rho(rbsog_handle *h, uint64_t step, const double *x_dev, double *rho_dev);
+
+/*
+ * One force evaluation (Algorithm 2, lines 3-5; eq. 3.8 with the random-batch
+ * far field of eq. UF):
+ *   f_i = sum_{j: |d| < r_c} q_i q_j [F_N1 + F_N2](|d|) d            (near, d = r_i - r_j, minimum image)
+ *       - q_i sum_l coef_l k_l Im(exp(-i k_l . r_i) rho(k_l))          (far, random batch)
+ * writes f_dev[3*N] (original particle order), f_near_dev[3*N] (nullable) the
+ * near part alone, and energy_dev[6] (nullable, device) =
+ *   { U_N, U*_F, U_k0 = Fhat(0)(sum q)^2/(2V), U_self = -F(0) sum q^2 / 2,
+ *     U_bg = -(sum q)^2 4 pi lambda^2/(2V), 0 }.
+ * Errors: RBSOG_EINVAL, RBSOG_EHIP.
+ */
+int rbsog_compute_forces(rbsog_handle *h, uint64_t step, const double *x_dev, double *f_dev,
+                         double *f_near_dev, double *energy_dev);
+
+/*
+ * nsteps velocity-Verlet steps (Algorithm 2 time loop), in place:
+ *   v += (dt/2) f / m;  x += dt v;  wrap into [0, L);  f = F(x, step0 + n + 1);
+ *   v += (dt/2) f / m.
+ * f_dev must hold F(x, step0) on entry (e.g. from rbsog_compute_forces).
+ * energy_hist_dev (nullable, device) receives [nsteps][6] energies of the new
+ * state, as in rbsog_compute_forces with KE = sum m v^2 / 2 in slot 5.
+ * A particle moving a box length or more in one step, or a non-finite force,
+ * raises a device flag reported by rbsog_check.
+ * Errors: RBSOG_EINVAL, RBSOG_EHIP.
+ */
+int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double *f_dev, uint64_t step0, int nsteps,
+               double dt, double *energy_hist_dev);
+
+/*
+ * Synchronises the stream and reports the device flag: RBSOG_OK, or
+ * RBSOG_ENONFINITE if any evaluation since the last check produced a
+ * non-finite force or an over-long step (the flag is then cleared).
+ */
+int rbsog_check(rbsog_handle *h);
+
+/* Releases the host-side handle (the caller still owns the workspace). */
+void rbsog_destroy(rbsog_handle *h);
+
+/* Thread-local message describing the last failing call. */
+const char *rbsog_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBSOG_H */

@@ -618,6 +618,59 @@ void orc_near(int64_t N, const double *x, const double *q, double L, double lamb
     free(ei);
 }
 
+/* Near-field force on a subset of particles idx[0..nsub) (for checks at sizes
+ * where the whole near field is too slow on the CPU): the same pair sum over
+ * every j != i and every image with |d| < rc, found by a cell list when
+ * L >= 3 rc.  f_out is [3][nsub]. */
+void orc_near_subset(int64_t N, const double *x, const double *q, double L, double lambda, double rc, int nG,
+                     const double *c, const double *s, int64_t nsub, const int64_t *idx, double *f_out)
+{
+    double rc2 = rc * rc;
+    int nc = (int)floor(L / rc);
+    if (nc < 3) return;
+    int32_t *cs = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nc * nc * nc + 1));
+    int32_t *ord = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    orc_cells(N, x, L, rc, cs, ord);
+    double inv = (double)nc / L;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < nsub; ++k) {
+        int64_t i = idx[k];
+        int ci[3];
+        for (int d = 0; d < 3; ++d) {
+            double fl = floor(x[d * N + i] * inv);
+            int cc = (int)fl;
+            if (fl < 0.0) cc = 0;
+            if (cc > nc - 1) cc = nc - 1;
+            ci[d] = cc;
+        }
+        double fx = 0, fy = 0, fz = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int cx = ci[0] + dx, cy = ci[1] + dy, cz = ci[2] + dz;
+                    double sx = 0, sy = 0, sz = 0;
+                    if (cx < 0) { cx += nc; sx = -L; } else if (cx >= nc) { cx -= nc; sx = L; }
+                    if (cy < 0) { cy += nc; sy = -L; } else if (cy >= nc) { cy -= nc; sy = L; }
+                    if (cz < 0) { cz += nc; sz = -L; } else if (cz >= nc) { cz -= nc; sz = L; }
+                    int cell = (cz * nc + cy) * nc + cx;
+                    for (int32_t p = cs[cell]; p < cs[cell + 1]; ++p) {
+                        int64_t j = ord[p];
+                        if (j == i) continue;
+                        double ddx = x[i] - (x[j] + sx), ddy = x[N + i] - (x[N + j] + sy), ddz = x[2 * N + i] - (x[2 * N + j] + sz);
+                        double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                        if (r2 >= rc2) continue;
+                        double fac, en;
+                        near_pair(r2, lambda, nG, c, s, &fac, &en);
+                        double qq = q[i] * q[j];
+                        fx += qq * fac * ddx; fy += qq * fac * ddy; fz += qq * fac * ddz;
+                    }
+                }
+        f_out[k] = fx; f_out[nsub + k] = fy; f_out[2 * nsub + k] = fz;
+    }
+    free(cs);
+    free(ord);
+}
+
 /* ------------------------------------------------------------------------- */
 /* Section 2 and 4.1: structure factors and the far field                     */
 /* ------------------------------------------------------------------------- */

@@ -1,0 +1,236 @@
+"""MI355X (gfx950) library for the random batch sum-of-Gaussians (RBSOG)
+force evaluation and velocity-Verlet step of 3-D periodic Yukawa systems.
+
+This module is the Python binding of the C-ABI in ``include/rbsog.h``: each
+function has the C name and only marshals arguments (torch tensors become
+device pointers, the current torch stream becomes the HIP stream).  Every step
+of the computation runs in the HIP kernels of ``librbsog.so``; there is no
+Python or CPU fallback.  Loading fails loudly if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbsog.so")
+
+RBSOG_OK = 0
+RBSOG_EINVAL, RBSOG_ENOROOT, RBSOG_EWORKSPACE, RBSOG_EAGAIN, RBSOG_ENONFINITE, RBSOG_EHIP, RBSOG_ENOMEM = range(-1, -8, -1)
+RBSOG_FP64, RBSOG_MIXED = 0, 1
+RBSOG_ADAPTIVE, RBSOG_FLAT, RBSOG_K2, RBSOG_DH4PI = 0, 1, 2, 3
+RBSOG_AUTO = -999
+RBSOG_MAX_GAUSS = 32
+
+
+class RbsogError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"rbsog error {code}: {msg}")
+        self.code = code
+
+
+class rbsog_sog(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("r_c", C.c_double), ("eps", C.c_double),
+                ("h", C.c_double), ("t0", C.c_double), ("w", C.c_double),
+                ("M1", C.c_int), ("M2", C.c_int), ("n", C.c_int),
+                ("c", C.c_double * RBSOG_MAX_GAUSS), ("s", C.c_double * RBSOG_MAX_GAUSS),
+                ("A", C.c_double * RBSOG_MAX_GAUSS), ("B", C.c_double * RBSOG_MAX_GAUSS),
+                ("F0", C.c_double), ("Fhat0", C.c_double), ("max_err", C.c_double)]
+
+
+class rbsog_params(C.Structure):
+    _fields_ = [("N", C.c_int64), ("L", C.c_double), ("kT", C.c_double), ("P", C.c_int), ("mmax", C.c_int),
+                ("seed", C.c_uint64), ("replica", C.c_uint32), ("precision", C.c_int), ("density", C.c_int)]
+
+
+class rbsog_info(C.Structure):
+    _fields_ = [("N", C.c_int64), ("nc", C.c_int), ("mmax", C.c_int), ("nshell", C.c_int), ("nlat", C.c_int64),
+                ("S", C.c_double), ("Q1", C.c_double), ("Q2", C.c_double), ("ws_bytes", C.c_size_t)]
+
+
+_lib = None
+_p = C.c_void_p
+_sizes = {}  # handle address -> (N, P, ncell) for argument-size checks
+
+
+def lib() -> C.CDLL:
+    """The loaded librbsog.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "rbsog_sog_init": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.POINTER(rbsog_sog)]),
+            "rbsog_sog_expand": (C.c_int, [C.POINTER(rbsog_sog)]),
+            "rbsog_workspace_size": (C.c_int, [C.POINTER(rbsog_params), C.POINTER(rbsog_sog), C.POINTER(C.c_size_t)]),
+            "rbsog_create": (C.c_int, [C.POINTER(rbsog_params), C.POINTER(rbsog_sog), _p, _p, _p, C.c_size_t, _p,
+                                       C.POINTER(_p)]),
+            "rbsog_get_info": (C.c_int, [_p, C.POINTER(rbsog_info)]),
+            "rbsog_build_cells": (C.c_int, [_p, _p, _p, _p]),
+            "rbsog_sample_k": (C.c_int, [_p, C.c_uint64, _p, _p]),
+            "rbsog_compute_rho": (C.c_int, [_p, C.c_uint64, _p, _p]),
+            "rbsog_compute_forces": (C.c_int, [_p, C.c_uint64, _p, _p, _p, _p]),
+            "rbsog_step": (C.c_int, [_p, _p, _p, _p, C.c_uint64, C.c_int, C.c_double, _p]),
+            "rbsog_check": (C.c_int, [_p]),
+            "rbsog_destroy": (None, [_p]),
+            "rbsog_last_error": (C.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int) -> int:
+    if code != RBSOG_OK:
+        raise RbsogError(code, lib().rbsog_last_error().decode())
+    return code
+
+
+def _dptr(t, dtype=None, numel: Optional[int] = None):
+    """Device pointer of a contiguous torch tensor (None passes through)."""
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"expected at least {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(device=None) -> C.c_void_p:
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+# --- host functions ---------------------------------------------------------------
+
+def rbsog_sog_init(lambda_: float, r_c: float, eps: float, M1: int = RBSOG_AUTO, M2: int = RBSOG_AUTO) -> rbsog_sog:
+    out = rbsog_sog()
+    _check(lib().rbsog_sog_init(lambda_, r_c, eps, M1, M2, C.byref(out)))
+    return out
+
+
+def rbsog_sog_expand(sog: rbsog_sog) -> rbsog_sog:
+    _check(lib().rbsog_sog_expand(C.byref(sog)))
+    return sog
+
+
+def sog_from_parameters(lambda_: float, r_c: float, h: float, t0: float, w: float, M1: int, M2: int,
+                        eps: float = 0.0) -> rbsog_sog:
+    """A decomposition given by its parameters (h, t0, w, M1, M2), expanded by the library."""
+    s = rbsog_sog()
+    s.lambda_, s.r_c, s.eps, s.h, s.t0, s.w, s.M1, s.M2 = lambda_, r_c, eps, h, t0, w, M1, M2
+    s.n = M1 + M2 + 1
+    return rbsog_sog_expand(s)
+
+
+def make_params(N: int, L: float, kT: float, P: int, seed: int, replica: int = 0, mmax: int = 0,
+                precision: int = RBSOG_FP64, density: int = RBSOG_ADAPTIVE) -> rbsog_params:
+    return rbsog_params(N=N, L=L, kT=kT, P=P, mmax=mmax, seed=seed, replica=replica, precision=precision,
+                        density=density)
+
+
+def rbsog_workspace_size(params: rbsog_params, sog: rbsog_sog) -> int:
+    n = C.c_size_t()
+    _check(lib().rbsog_workspace_size(C.byref(params), C.byref(sog), C.byref(n)))
+    return n.value
+
+
+# --- device functions -------------------------------------------------------------
+
+def rbsog_create(params: rbsog_params, sog: rbsog_sog, q, m, ws, stream=None) -> C.c_void_p:
+    import torch
+    N = params.N
+    h = C.c_void_p()
+    _check(lib().rbsog_create(C.byref(params), C.byref(sog), _dptr(q, torch.float64, N), _dptr(m, torch.float64, N),
+                              _dptr(ws), ws.numel() * ws.element_size(), stream or _stream(q.device), C.byref(h)))
+    info = rbsog_get_info(h)
+    _sizes[h.value] = (info.N, params.P, info.nc ** 3)
+    return h
+
+
+def _n(h):
+    return _sizes.get(h.value if isinstance(h, C.c_void_p) else h, (None, None, None))
+
+
+def rbsog_get_info(h) -> rbsog_info:
+    out = rbsog_info()
+    _check(lib().rbsog_get_info(h, C.byref(out)))
+    return out
+
+
+def rbsog_build_cells(h, x, cell_start=None, order=None):
+    import torch
+    N, P, nce = _n(h)
+    _check(lib().rbsog_build_cells(h, _dptr(x, torch.float64, 3 * N), _dptr(cell_start, torch.int32, nce + 1),
+                                   _dptr(order, torch.int32, N)))
+
+
+def rbsog_sample_k(h, step: int, n=None, coef=None):
+    import torch
+    N, P, _ = _n(h)
+    _check(lib().rbsog_sample_k(h, step, _dptr(n, torch.int32, 3 * P), _dptr(coef, torch.float64, P)))
+
+
+def rbsog_compute_rho(h, step: int, x, rho):
+    import torch
+    N, P, _ = _n(h)
+    _check(lib().rbsog_compute_rho(h, step, _dptr(x, torch.float64, 3 * N), _dptr(rho, torch.float64, 2 * P)))
+
+
+def rbsog_compute_forces(h, step: int, x, f, f_near=None, energy=None):
+    import torch
+    N, P, _ = _n(h)
+    _check(lib().rbsog_compute_forces(h, step, _dptr(x, torch.float64, 3 * N), _dptr(f, torch.float64, 3 * N),
+                                      _dptr(f_near, torch.float64, 3 * N), _dptr(energy, torch.float64, 6)))
+
+
+def rbsog_step(h, x, v, f, step0: int, nsteps: int, dt: float, energy_hist=None):
+    import torch
+    N, P, _ = _n(h)
+    _check(lib().rbsog_step(h, _dptr(x, torch.float64, 3 * N), _dptr(v, torch.float64, 3 * N),
+                            _dptr(f, torch.float64, 3 * N), step0, nsteps, dt,
+                            _dptr(energy_hist, torch.float64, 6 * nsteps)))
+
+
+def rbsog_check(h) -> None:
+    _check(lib().rbsog_check(h))
+
+
+def rbsog_destroy(h) -> None:
+    _sizes.pop(h.value if isinstance(h, C.c_void_p) else h, None)
+    lib().rbsog_destroy(h)
+
+
+class System:
+    """Holds one system's device buffers (charges, masses, workspace) and
+    handle; all work goes through the C-ABI on the current torch stream."""
+
+    def __init__(self, q, m, L: float, sog: rbsog_sog, kT: float, P: int, seed: int, replica: int = 0,
+                 mmax: int = 0, precision: int = RBSOG_FP64, density: int = RBSOG_ADAPTIVE, device="cuda"):
+        import torch
+        self.q = torch.as_tensor(q, dtype=torch.float64, device=device).contiguous()
+        self.m = torch.as_tensor(m, dtype=torch.float64, device=device).contiguous()
+        self.N = self.q.numel()
+        self.sog = sog
+        self.params = make_params(self.N, L, kT, P, seed, replica, mmax, precision, density)
+        nbytes = rbsog_workspace_size(self.params, sog)
+        self.ws = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device=device)
+        self.h = rbsog_create(self.params, sog, self.q, self.m, self.ws)
+        self.info = rbsog_get_info(self.h)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            rbsog_destroy(h)
+            self.h = None

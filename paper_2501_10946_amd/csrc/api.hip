@@ -1,0 +1,459 @@
+// C-ABI of librbsog (declared in include/rbsog.h): parameter checks, workspace
+// layout, table upload and the per-evaluation launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "launch.h"
+
+namespace rbsog {
+
+namespace {
+thread_local std::string g_error;
+constexpr double kPi = 3.141592653589793;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Offsets of every buffer inside the workspace.
+struct Layout {
+    size_t lattice, cdf, coef, first, size;
+    size_t cell_id, count, cell_start, fill, tmp, order, xs;
+    size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy;
+    size_t total;
+};
+
+int nchunks(int64_t N) { return (int)((N + kRhoChunk - 1) / kRhoChunk); }
+int nblocks(int64_t N) { return (int)((N + kBlock - 1) / kBlock); }
+
+Layout make_layout(int64_t N, int ncell, int64_t nlat, int nshell_max, int P)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.lattice = take(sizeof(int32_t) * (size_t)nlat);
+    L.cdf = take(sizeof(double) * (size_t)nshell_max);
+    L.coef = take(sizeof(double) * (size_t)nshell_max);
+    L.first = take(sizeof(int32_t) * (size_t)nshell_max);
+    L.size = take(sizeof(int32_t) * (size_t)nshell_max);
+    L.cell_id = take(sizeof(int32_t) * (size_t)N);
+    L.count = take(sizeof(int32_t) * (size_t)ncell);
+    L.cell_start = take(sizeof(int32_t) * ((size_t)ncell + 1));
+    L.fill = take(sizeof(int32_t) * (size_t)ncell);
+    L.tmp = take(sizeof(int32_t) * (size_t)N);
+    L.order = take(sizeof(int32_t) * (size_t)N);
+    L.xs = take(sizeof(double) * 4 * (size_t)N);
+    L.samp = take(sizeof(double) * 4 * (size_t)P);
+    L.part = take(sizeof(double) * 2 * (size_t)nchunks(N) * (size_t)P);
+    L.rho = take(sizeof(double) * 2 * (size_t)P);
+    L.gk = take(sizeof(double) * 2 * (size_t)P);
+    L.eF = take(sizeof(double) * (size_t)P);
+    L.fnear = take(sizeof(double) * 3 * (size_t)N);
+    L.epart = take(sizeof(double) * (size_t)nblocks(N));
+    L.kepart = take(sizeof(double) * (size_t)nblocks(N));
+    L.flag = take(sizeof(int32_t) * 4);
+    L.energy = take(sizeof(double) * 8);
+    L.total = off;
+    return L;
+}
+
+int check_params(const rbsog_params *p, const rbsog_sog *s)
+{
+    if (!p || !s) return fail(RBSOG_EINVAL, "null params or sog");
+    if (p->N < 1 || p->N > (int64_t)1 << 30) return fail(RBSOG_EINVAL, "N must lie in [1, 2^30]");
+    if (!(p->L > 0.0) || !std::isfinite(p->L)) return fail(RBSOG_EINVAL, "L must be positive and finite");
+    if (!(p->kT > 0.0) || !std::isfinite(p->kT)) return fail(RBSOG_EINVAL, "kT must be positive and finite");
+    if (p->P < 1 || p->P > 4096) return fail(RBSOG_EINVAL, "P must lie in [1, 4096]");
+    if (p->precision != RBSOG_FP64 && p->precision != RBSOG_MIXED) return fail(RBSOG_EINVAL, "unknown precision");
+    if (p->density < RBSOG_ADAPTIVE || p->density > RBSOG_DH4PI) return fail(RBSOG_EINVAL, "unknown density");
+    if (p->mmax < 0 || p->mmax > kMaxLatticeM) return fail(RBSOG_EINVAL, "mmax must lie in [0, %d]", kMaxLatticeM);
+    if (s->n < 1 || s->n > RBSOG_MAX_GAUSS || s->n != s->M1 + s->M2 + 1)
+        return fail(RBSOG_EINVAL, "sog: inconsistent number of Gaussians");
+    if (!(s->r_c > 0.0) || !(s->lambda > 0.0)) return fail(RBSOG_EINVAL, "sog: lambda and r_c must be positive");
+    double nc = std::floor(p->L / s->r_c);
+    if (nc < 3.0) return fail(RBSOG_EINVAL, "box too small: floor(L / r_c) = %g < 3", nc);
+    if (nc * nc * nc > (double)(1 << 26)) return fail(RBSOG_EINVAL, "too many cells");
+    return RBSOG_OK;
+}
+
+#define HIPCHECK(call)                                                                      \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) return fail(RBSOG_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+}  // namespace rbsog
+
+using namespace rbsog;
+
+struct rbsog_handle {
+    rbsog_params p;
+    rbsog_sog sog;
+    const double *q, *m;
+    hipStream_t st;
+    CellGeom g;
+    Tables t;  // host copy (sizes; the vectors are released after upload)
+    double V, Q1, Q2, Uk0, Uself, Ubg;
+    Layout lay;
+    char *ws;
+    size_t ws_bytes;
+    SogDev sd;
+    int32_t *lattice, *first, *size, *cell_id, *count, *cell_start, *fill, *tmp, *order, *flag;
+    double *cdf, *coef, *eF, *fnear, *epart, *kepart, *energy;
+    double4 *xs, *samp;
+    double2 *part, *rho, *gk;
+};
+
+namespace {
+
+CellArgs cell_args(rbsog_handle *h, const double *x)
+{
+    CellArgs a{};
+    a.N = (int)h->p.N;
+    a.g = h->g;
+    a.x = x;
+    a.q = h->q;
+    a.cell_id = h->cell_id;
+    a.count = h->count;
+    a.cell_start = h->cell_start;
+    a.fill = h->fill;
+    a.tmp = h->tmp;
+    a.order = h->order;
+    a.xs = h->xs;
+    return a;
+}
+
+SampleArgs sample_args(rbsog_handle *h, uint64_t step)
+{
+    SampleArgs a{};
+    a.P = h->p.P;
+    a.step = step;
+    a.seed = h->p.seed;
+    a.replica = h->p.replica;
+    a.nshell = h->t.nshell;
+    a.S = h->t.S;
+    a.cdf = h->cdf;
+    a.coef = h->coef;
+    a.first = h->first;
+    a.size = h->size;
+    a.lattice = h->lattice;
+    a.samp = h->samp;
+    return a;
+}
+
+RhoArgs rho_args(rbsog_handle *h)
+{
+    RhoArgs a{};
+    a.N = (int)h->p.N;
+    a.P = h->p.P;
+    a.nchunk = nchunks(h->p.N);
+    a.inv_L = 1.0 / h->p.L;
+    a.xs = h->xs;
+    a.samp = h->samp;
+    a.part = h->part;
+    a.rho = h->rho;
+    a.gk = h->gk;
+    a.eF = h->eF;
+    a.mixed = h->p.precision == RBSOG_MIXED;
+    return a;
+}
+
+// Sampling, structure factors, near field, far field (+ optional kick) and the
+// energy sums of one evaluation whose cell list is already built.
+int evaluate(rbsog_handle *h, uint64_t step, double *f, double *f_near, double *v, double dt, double *energy)
+{
+    HIPCHECK(launch_sample(sample_args(h, step), h->st));
+    HIPCHECK(launch_rho(rho_args(h), h->st));
+    NearArgs na{};
+    na.N = (int)h->p.N;
+    na.g = h->g;
+    na.rc2 = h->sog.r_c * h->sog.r_c;
+    na.sog = h->sd;
+    na.xs = h->xs;
+    na.cell_start = h->cell_start;
+    na.fnear = h->fnear;
+    na.epart = h->epart;
+    na.mixed = h->p.precision == RBSOG_MIXED;
+    HIPCHECK(launch_near(na, h->st));
+    FarArgs fa{};
+    fa.N = (int)h->p.N;
+    fa.P = h->p.P;
+    fa.two_pi_over_L = (2.0 * kPi) / h->p.L;
+    fa.inv_L = 1.0 / h->p.L;
+    fa.xs = h->xs;
+    fa.order = h->order;
+    fa.samp = h->samp;
+    fa.gk = h->gk;
+    fa.fnear = h->fnear;
+    fa.f = f;
+    fa.f_near_out = f_near;
+    fa.v = v;
+    fa.m = h->m;
+    fa.half_dt = 0.5 * dt;
+    fa.kepart = v ? h->kepart : nullptr;
+    fa.flag = h->flag;
+    fa.mixed = h->p.precision == RBSOG_MIXED;
+    HIPCHECK(launch_far(fa, h->st));
+    if (energy) {
+        EnergyArgs ea{};
+        ea.nnear = nblocks(h->p.N);
+        ea.nfar = nblocks(h->p.N);
+        ea.P = h->p.P;
+        ea.epart = h->epart;
+        ea.kepart = v ? h->kepart : nullptr;
+        ea.eF = h->eF;
+        ea.Uk0 = h->Uk0;
+        ea.Uself = h->Uself;
+        ea.Ubg = h->Ubg;
+        ea.out = energy;
+        HIPCHECK(launch_energy(ea, h->st));
+    }
+    return RBSOG_OK;
+}
+
+}  // namespace
+
+extern "C" const char *rbsog_last_error(void) { return g_error.c_str(); }
+
+extern "C" int rbsog_workspace_size(const rbsog_params *p, const rbsog_sog *s, size_t *bytes)
+{
+    int rc = check_params(p, s);
+    if (rc) return rc;
+    if (!bytes) return fail(RBSOG_EINVAL, "bytes is null");
+    int mmax = p->mmax > 0 ? p->mmax : default_mmax(*s, p->L);
+    int nc = (int)std::floor(p->L / s->r_c);
+    *bytes = make_layout(p->N, nc * nc * nc, lattice_points(mmax), mmax, p->P).total;
+    return RBSOG_OK;
+}
+
+extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const double *q_dev, const double *m_dev,
+                            void *ws_dev, size_t ws_bytes, void *hip_stream, rbsog_handle **out)
+{
+    int rc = check_params(p, s);
+    if (rc) return rc;
+    if (!q_dev || !m_dev || !out) return fail(RBSOG_EINVAL, "null q, m or out");
+    if (!ws_dev || ((uintptr_t)ws_dev % kAlign)) return fail(RBSOG_EWORKSPACE, "workspace must be 256-byte aligned");
+    rbsog_handle *h = new (std::nothrow) rbsog_handle{};
+    if (!h) return fail(RBSOG_ENOMEM, "handle allocation");
+    h->p = *p;
+    h->sog = *s;
+    h->q = q_dev;
+    h->m = m_dev;
+    h->st = (hipStream_t)hip_stream;
+    int nc = (int)std::floor(p->L / s->r_c);
+    h->g.nc = nc;
+    h->g.ncell = nc * nc * nc;
+    h->g.L = p->L;
+    h->g.inv_cell = (double)nc / p->L;
+    h->V = p->L * p->L * p->L;
+    // sum q and sum q^2 in particle order (they enter the measure, eq. 3.22)
+    std::vector<double> qh((size_t)p->N);
+    hipError_t e = hipMemcpyAsync(qh.data(), q_dev, sizeof(double) * (size_t)p->N, hipMemcpyDeviceToHost, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(RBSOG_EHIP, "reading q: %s", hipGetErrorString(e));
+    }
+    double q1 = 0.0, q2 = 0.0;
+    charge_sums(qh.data(), p->N, &q1, &q2);
+    h->Q1 = q1;
+    h->Q2 = q2;
+    if (!(q2 > 0.0)) {
+        delete h;
+        return fail(RBSOG_EINVAL, "all charges are zero");
+    }
+    int mmax = p->mmax > 0 ? p->mmax : default_mmax(*s, p->L);
+    build_tables(*s, *p, q2, mmax, &h->t);
+    h->lay = make_layout(p->N, h->g.ncell, h->t.nlat, mmax, p->P);
+    if (ws_bytes < h->lay.total) {
+        size_t need = h->lay.total;
+        delete h;
+        return fail(RBSOG_EWORKSPACE, "workspace of %zu bytes is below the %zu needed", ws_bytes, need);
+    }
+    h->ws = (char *)ws_dev;
+    h->ws_bytes = ws_bytes;
+    char *w = h->ws;
+    const Layout &L = h->lay;
+    h->lattice = (int32_t *)(w + L.lattice);
+    h->cdf = (double *)(w + L.cdf);
+    h->coef = (double *)(w + L.coef);
+    h->first = (int32_t *)(w + L.first);
+    h->size = (int32_t *)(w + L.size);
+    h->cell_id = (int32_t *)(w + L.cell_id);
+    h->count = (int32_t *)(w + L.count);
+    h->cell_start = (int32_t *)(w + L.cell_start);
+    h->fill = (int32_t *)(w + L.fill);
+    h->tmp = (int32_t *)(w + L.tmp);
+    h->order = (int32_t *)(w + L.order);
+    h->xs = (double4 *)(w + L.xs);
+    h->samp = (double4 *)(w + L.samp);
+    h->part = (double2 *)(w + L.part);
+    h->rho = (double2 *)(w + L.rho);
+    h->gk = (double2 *)(w + L.gk);
+    h->eF = (double *)(w + L.eF);
+    h->fnear = (double *)(w + L.fnear);
+    h->epart = (double *)(w + L.epart);
+    h->kepart = (double *)(w + L.kepart);
+    h->flag = (int32_t *)(w + L.flag);
+    h->energy = (double *)(w + L.energy);
+    const Tables &t = h->t;
+    e = hipMemcpyAsync(h->lattice, t.packed.data(), sizeof(int32_t) * t.packed.size(), hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->cdf, t.cdf.data(), sizeof(double) * t.nshell, hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->coef, t.coef.data(), sizeof(double) * t.nshell, hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->first, t.shell_first.data(), sizeof(int32_t) * t.nshell, hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->size, t.shell_size.data(), sizeof(int32_t) * t.nshell, hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess) e = hipMemsetAsync(h->flag, 0, sizeof(int32_t) * 4, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(RBSOG_EHIP, "uploading tables: %s", hipGetErrorString(e));
+    }
+    // the host copies of the tables are no longer needed
+    h->t.packed = std::vector<int32_t>();
+    h->t.cdf = std::vector<double>();
+    h->t.shell_first = std::vector<int32_t>();
+    h->t.shell_size = std::vector<int32_t>();
+    // kernel-side SOG and the constant energies (Section 4.1)
+    h->sd.n = s->n;
+    h->sd.inv_lambda = 1.0 / s->lambda;
+    for (int j = 0; j < s->n; ++j) {
+        h->sd.c[j] = s->c[j];
+        h->sd.s[j] = s->s[j];
+        h->sd.cs2[j] = 2.0 * s->c[j] * s->s[j];
+    }
+    h->Uk0 = s->Fhat0 * q1 * q1 / (2.0 * h->V);
+    h->Uself = -0.5 * q2 * s->F0;
+    h->Ubg = -(q1 * q1) * (4.0 * kPi * s->lambda * s->lambda) / (2.0 * h->V);
+    *out = h;
+    return RBSOG_OK;
+}
+
+extern "C" int rbsog_get_info(const rbsog_handle *h, rbsog_info *out)
+{
+    if (!h || !out) return fail(RBSOG_EINVAL, "null handle or out");
+    out->N = h->p.N;
+    out->nc = h->g.nc;
+    out->mmax = h->t.mmax;
+    out->nshell = h->t.nshell;
+    out->nlat = h->t.nlat;
+    out->S = h->t.S;
+    out->Q1 = h->Q1;
+    out->Q2 = h->Q2;
+    out->ws_bytes = h->lay.total;
+    return RBSOG_OK;
+}
+
+extern "C" int rbsog_build_cells(rbsog_handle *h, const double *x_dev, int32_t *cell_start_dev, int32_t *order_dev)
+{
+    if (!h || !x_dev) return fail(RBSOG_EINVAL, "null handle or x");
+    CellArgs a = cell_args(h, x_dev);
+    HIPCHECK(launch_cell_ids(a, h->st));
+    HIPCHECK(launch_cells_finish(a, h->st));
+    if (cell_start_dev)
+        HIPCHECK(hipMemcpyAsync(cell_start_dev, h->cell_start, sizeof(int32_t) * ((size_t)h->g.ncell + 1),
+                                hipMemcpyDeviceToDevice, h->st));
+    if (order_dev)
+        HIPCHECK(hipMemcpyAsync(order_dev, h->order, sizeof(int32_t) * (size_t)h->p.N, hipMemcpyDeviceToDevice, h->st));
+    return RBSOG_OK;
+}
+
+extern "C" int rbsog_sample_k(rbsog_handle *h, uint64_t step, int32_t *n_dev, double *coef_dev)
+{
+    if (!h) return fail(RBSOG_EINVAL, "null handle");
+    SampleArgs a = sample_args(h, step);
+    a.n_out = n_dev;
+    a.coef_out = coef_dev;
+    HIPCHECK(launch_sample(a, h->st));
+    return RBSOG_OK;
+}
+
+extern "C" int rbsog_compute_rho(rbsog_handle *h, uint64_t step, const double *x_dev, double *rho_dev)
+{
+    if (!h || !x_dev || !rho_dev) return fail(RBSOG_EINVAL, "null handle, x or rho");
+    HIPCHECK(launch_sample(sample_args(h, step), h->st));
+    RhoArgs a = rho_args(h);
+    a.xs = nullptr;
+    a.x = x_dev;
+    a.q = h->q;
+    a.rho_out = rho_dev;
+    HIPCHECK(launch_rho(a, h->st));
+    return RBSOG_OK;
+}
+
+extern "C" int rbsog_compute_forces(rbsog_handle *h, uint64_t step, const double *x_dev, double *f_dev,
+                                    double *f_near_dev, double *energy_dev)
+{
+    if (!h || !x_dev || !f_dev) return fail(RBSOG_EINVAL, "null handle, x or f");
+    CellArgs a = cell_args(h, x_dev);
+    HIPCHECK(launch_cell_ids(a, h->st));
+    HIPCHECK(launch_cells_finish(a, h->st));
+    return evaluate(h, step, f_dev, f_near_dev, nullptr, 0.0, energy_dev);
+}
+
+extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double *f_dev, uint64_t step0, int nsteps,
+                          double dt, double *energy_hist_dev)
+{
+    if (!h || !x_dev || !v_dev || !f_dev) return fail(RBSOG_EINVAL, "null handle, x, v or f");
+    if (nsteps < 0) return fail(RBSOG_EINVAL, "nsteps must be >= 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RBSOG_EINVAL, "dt must be positive and finite");
+    for (int n = 0; n < nsteps; ++n) {
+        KickDriftArgs k{};
+        k.N = (int)h->p.N;
+        k.g = h->g;
+        k.dt = dt;
+        k.x = x_dev;
+        k.v = v_dev;
+        k.f = f_dev;
+        k.m = h->m;
+        k.cell_id = h->cell_id;
+        k.count = h->count;
+        k.flag = h->flag;
+        HIPCHECK(launch_kick_drift(k, h->st));
+        CellArgs a = cell_args(h, x_dev);
+        HIPCHECK(launch_cells_finish(a, h->st));
+        double *e = energy_hist_dev ? energy_hist_dev + 6 * (size_t)n : nullptr;
+        int rc = evaluate(h, step0 + (uint64_t)n + 1, f_dev, nullptr, v_dev, dt, e);
+        if (rc) return rc;
+    }
+    return RBSOG_OK;
+}
+
+extern "C" int rbsog_check(rbsog_handle *h)
+{
+    if (!h) return fail(RBSOG_EINVAL, "null handle");
+    int32_t flag = 0;
+    HIPCHECK(hipMemcpyAsync(&flag, h->flag, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+    HIPCHECK(hipStreamSynchronize(h->st));
+    if (flag) {
+        HIPCHECK(hipMemsetAsync(h->flag, 0, sizeof(int32_t), h->st));
+        HIPCHECK(hipStreamSynchronize(h->st));
+        return fail(RBSOG_ENONFINITE, "non-finite force or over-long step detected");
+    }
+    return RBSOG_OK;
+}
+
+extern "C" void rbsog_destroy(rbsog_handle *h) { delete h; }

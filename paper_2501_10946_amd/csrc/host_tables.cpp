@@ -1,0 +1,132 @@
+// Host side of the importance-sampling measure (Section 4.3, eq. 3.124):
+// the Fourier lattice and the per-shell cumulative weights of
+// P(k) = F(k) Fhat(k) / S.  Built with -ffp-contract=off: the cumulative
+// weights are a fixed sequence of IEEE FP64 operations, so two conforming
+// implementations produce the same bits and therefore the same samples.
+#include <cmath>
+
+#include "internal.h"
+
+namespace rbsog {
+namespace {
+
+constexpr double kPi = 3.141592653589793;
+
+// Fhat(k^2) = sum_j A_j exp(-B_j k^2), ascending j.
+double fhat(const rbsog_sog &s, double k2)
+{
+    double acc = 0.0;
+    for (int j = 0; j < s.n; ++j) acc += s.A[j] * std::exp(-s.B[j] * k2);
+    return acc;
+}
+
+}  // namespace
+
+// Correction factor of the measure.  ADAPTIVE is the leading Debye-Hueckel
+// term of eq. (3.22) as printed, with eps(k)^{-1}/k^2 = lambda^2/(1 + lambda^2 k^2)
+// for the Yukawa dielectric eps(k) = 1 + (lambda k)^{-2}.
+double density(int kind, double kT, double V, double Q2, double lambda, double k2)
+{
+    double l2 = lambda * lambda;
+    if (kind == RBSOG_FLAT) return 1.0;
+    if (kind == RBSOG_K2) return k2;
+    if (kind == RBSOG_DH4PI) return (kT * V) / ((kT * V) / Q2 + (4.0 * kPi * l2) / (1.0 + l2 * k2));
+    return (kT * V) / ((kT * V) / Q2 + l2 / (1.0 + l2 * k2));
+}
+
+// Largest m >= 1 with Fhat((2 pi/L)^2 m) >= 1e-16 Fhat(0).
+int default_mmax(const rbsog_sog &s, double L)
+{
+    double t = (2.0 * kPi) / L;
+    double tk2 = t * t;
+    double floor_val = 1e-16 * fhat(s, 0.0);
+    int m = 1;
+    while (m < kMaxLatticeM && fhat(s, tk2 * (double)(m + 1)) >= floor_val) ++m;
+    return m;
+}
+
+int64_t lattice_points(int mmax)
+{
+    int64_t total = 0;
+    int R = (int)std::sqrt((double)mmax) + 1;
+    for (int a = -R; a <= R; ++a)
+        for (int b = -R; b <= R; ++b) {
+            int64_t ab = (int64_t)a * a + (int64_t)b * b;
+            if (ab > mmax) continue;
+            for (int c = -R; c <= R; ++c) {
+                int64_t m = ab + (int64_t)c * c;
+                total += (m >= 1 && m <= mmax);
+            }
+        }
+    return total;
+}
+
+void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax, Tables *t)
+{
+    t->mmax = mmax;
+    int R = (int)std::sqrt((double)mmax) + 1;
+    // shell sizes r3(m)
+    std::vector<int64_t> size(mmax + 1, 0);
+    for (int a = -R; a <= R; ++a)
+        for (int b = -R; b <= R; ++b)
+            for (int c = -R; c <= R; ++c) {
+                int64_t m = (int64_t)a * a + (int64_t)b * b + (int64_t)c * c;
+                if (m >= 1 && m <= mmax) ++size[m];
+            }
+    std::vector<int64_t> first(mmax + 1, 0);
+    int64_t run = 0;
+    for (int m = 1; m <= mmax; ++m) {
+        first[m] = run;
+        run += size[m];
+    }
+    t->nlat = run;
+    t->packed.assign((size_t)run, 0);
+    // lexicographic (nx, ny, nz) enumeration fills each shell in sorted order
+    std::vector<int64_t> fill(first);
+    for (int a = -R; a <= R; ++a)
+        for (int b = -R; b <= R; ++b)
+            for (int c = -R; c <= R; ++c) {
+                int64_t m = (int64_t)a * a + (int64_t)b * b + (int64_t)c * c;
+                if (m < 1 || m > mmax) continue;
+                t->packed[(size_t)fill[m]++] = (int32_t)((uint32_t)(a + kLatticeBias) |
+                                                         ((uint32_t)(b + kLatticeBias) << 10) |
+                                                         ((uint32_t)(c + kLatticeBias) << 20));
+            }
+    // cumulative shell weights
+    double tt = (2.0 * kPi) / p.L;
+    double tk2 = tt * tt;
+    double V = p.L * p.L * p.L;
+    t->cdf.clear();
+    t->coef.clear();
+    t->shell_first.clear();
+    t->shell_size.clear();
+    std::vector<double> Fk_of;
+    double acc = 0.0;
+    for (int m = 1; m <= mmax; ++m) {
+        if (size[m] == 0) continue;
+        double k2 = tk2 * (double)m;
+        double Fk = density(p.density, p.kT, V, Q2, s.lambda, k2);
+        double W = Fk * fhat(s, k2);
+        acc = acc + (double)size[m] * W;
+        t->cdf.push_back(acc);
+        t->shell_first.push_back((int32_t)first[m]);
+        t->shell_size.push_back((int32_t)size[m]);
+        Fk_of.push_back(Fk);
+    }
+    t->nshell = (int)t->cdf.size();
+    t->S = acc;
+    for (int i = 0; i < t->nshell; ++i) t->coef.push_back(t->S / ((double)p.P * V * Fk_of[i]));
+}
+
+void charge_sums(const double *q, int64_t N, double *q1, double *q2)
+{
+    double a = 0.0, b = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        a += q[i];
+        b += q[i] * q[i];
+    }
+    *q1 = a;
+    *q2 = b;
+}
+
+}  // namespace rbsog

@@ -1,0 +1,47 @@
+// Internal declarations shared by the host code and the kernel launchers of
+// librbsog.  Nothing here is part of the C-ABI.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rbsog.h"
+
+namespace rbsog {
+
+// thread-local error message behind rbsog_last_error()
+int fail(int code, const char *fmt, ...);
+
+// ---- host: Algorithm 1 (host_sog.cpp) --------------------------------------
+double step_size(double eps, double delta);
+int c1_start(double lambda, double rc, double h, int M1, int M2, double *t0, double *w);
+void expand(rbsog_sog *s);
+double sog_max_error(const rbsog_sog &s);
+
+// ---- host: Fourier lattice and sampling tables (host_tables.cpp) -----------
+// Lattice vectors are packed into one int32: (nx+512) | (ny+512)<<10 | (nz+512)<<20.
+constexpr int kLatticeBias = 512;
+constexpr int kMaxLatticeM = 511 * 511;
+
+struct Tables {
+    int mmax = 0;
+    int64_t nlat = 0;
+    int nshell = 0;
+    double S = 0.0;
+    std::vector<int32_t> packed;       // [nlat], sorted by (|n|^2, nx, ny, nz)
+    std::vector<double> cdf;           // [nshell] running sum of shell weights
+    std::vector<double> coef;          // [nshell] S / (P V F(k^2))
+    std::vector<int32_t> shell_first;  // [nshell] index of the shell's first point
+    std::vector<int32_t> shell_size;   // [nshell] points in the shell, r3(m)
+};
+
+int default_mmax(const rbsog_sog &s, double L);
+int64_t lattice_points(int mmax);
+double density(int kind, double kT, double V, double Q2, double lambda, double k2);
+void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax, Tables *t);
+// sum q and sum q^2 in particle order (plain FP64 additions, no contraction)
+void charge_sums(const double *q, int64_t N, double *q1, double *q2);
+
+}  // namespace rbsog

@@ -1,0 +1,143 @@
+// Kernel argument blocks and launcher declarations of librbsog.  Every device
+// pointer here points into the caller's workspace or the caller's particle
+// arrays; launchers enqueue on the given stream and return the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace rbsog {
+
+constexpr int kBlock = 256;        // threads per workgroup of the streaming and pair kernels
+constexpr int kRhoChunk = 256;     // particles per structure-factor partial
+constexpr int kMaxGauss = 32;
+
+// SOG coefficients as the kernels need them.
+struct SogDev {
+    int n;                 // Gaussians
+    double inv_lambda;     // 1/lambda
+    double c[kMaxGauss];   // F(r) = sum c exp(-s r^2)
+    double s[kMaxGauss];
+    double cs2[kMaxGauss]; // 2 c s (force factor of the Gaussians)
+};
+
+// Geometry of the cell list.
+struct CellGeom {
+    int nc;                // cells per axis
+    int ncell;             // nc^3
+    double L, inv_cell;    // box edge, nc / L
+};
+
+// --- cells -----------------------------------------------------------------
+struct CellArgs {
+    int N;
+    CellGeom g;
+    const double *x;       // SoA [3][N], original order
+    const double *q;       // [N]
+    int32_t *cell_id;      // [N]
+    int32_t *count;        // [ncell]
+    int32_t *cell_start;   // [ncell + 1]
+    int32_t *fill;         // [ncell]
+    int32_t *tmp;          // [N] unordered members per cell
+    int32_t *order;        // [N] cell order -> original index
+    double4 *xs;           // [N] (x, y, z, q) in cell order
+};
+hipError_t launch_cell_ids(const CellArgs &a, hipStream_t st);      // zero counts, ids, counts
+hipError_t launch_cells_finish(const CellArgs &a, hipStream_t st);  // scan, scatter, stable rank + gather
+
+// --- integration ------------------------------------------------------------
+struct KickDriftArgs {
+    int N;
+    CellGeom g;
+    double dt;
+    double *x, *v;         // SoA [3][N], original order, updated in place
+    const double *f;       // SoA [3][N]
+    const double *m;       // [N]
+    int32_t *cell_id, *count;
+    int *flag;             // set to 1 on a step of a box length or more
+};
+hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t st);
+
+// --- sampling ----------------------------------------------------------------
+struct SampleArgs {
+    int P;
+    uint64_t step, seed;
+    uint32_t replica;
+    int nshell;
+    double S;
+    const double *cdf;         // [nshell]
+    const double *coef;        // [nshell]
+    const int32_t *first;      // [nshell]
+    const int32_t *size;       // [nshell]
+    const int32_t *lattice;    // packed lattice vectors
+    double4 *samp;             // [P] (nx, ny, nz, coef)
+    int32_t *n_out;            // [P][3] or null
+    double *coef_out;          // [P] or null
+};
+hipError_t launch_sample(const SampleArgs &a, hipStream_t st);
+
+// --- structure factors -----------------------------------------------------------
+struct RhoArgs {
+    int N, P, nchunk;
+    double inv_L;
+    const double4 *xs;         // cell-ordered (x, y, z, q), or null to read x/q
+    const double *x, *q;       // original-order SoA positions and charges
+    const double4 *samp;       // [P]
+    double2 *part;             // [nchunk][P]
+    double2 *rho;              // [P]
+    double2 *gk;               // [P] coef * rho
+    double *eF;                // [P] coef |rho|^2 / 2
+    double *rho_out;           // [P][2] or null
+    int mixed;
+};
+hipError_t launch_rho(const RhoArgs &a, hipStream_t st);
+
+// --- near field ------------------------------------------------------------
+struct NearArgs {
+    int N;
+    CellGeom g;
+    double rc2;
+    SogDev sog;
+    const double4 *xs;         // cell order
+    const int32_t *cell_start;
+    double *fnear;             // SoA [3][N] in cell order
+    double *epart;             // [blocks] energy partials
+    int mixed;
+};
+hipError_t launch_near(const NearArgs &a, hipStream_t st);
+
+// --- far field + assembly + second half-kick ---------------------------------------
+struct FarArgs {
+    int N, P;
+    double two_pi_over_L, inv_L;
+    const double4 *xs;         // cell order
+    const int32_t *order;
+    const double4 *samp;       // [P] (nx, ny, nz, coef)
+    const double2 *gk;         // [P] coef * rho
+    const double *fnear;       // SoA [3][N] cell order
+    double *f;                 // SoA [3][N] original order
+    double *f_near_out;        // SoA [3][N] original order, or null
+    double *v;                 // null, or velocities to kick (original order)
+    const double *m;
+    double half_dt;
+    double *kepart;            // [blocks] kinetic-energy partials (when v)
+    int *flag;                 // set to 1 on a non-finite force
+    int mixed;
+};
+hipError_t launch_far(const FarArgs &a, hipStream_t st);
+
+// --- energies ---------------------------------------------------------------
+struct EnergyArgs {
+    int nnear, nfar, P;
+    const double *epart;       // [nnear]
+    const double *kepart;      // [nfar] or null
+    const double *eF;          // [P]
+    double Uk0, Uself, Ubg;
+    double *out;               // [6]
+};
+hipError_t launch_energy(const EnergyArgs &a, hipStream_t st);
+
+hipError_t launch_zero_int(int32_t *p, int n, hipStream_t st);
+
+}  // namespace rbsog

@@ -1,0 +1,236 @@
+"""Parity of the gfx950 library (through its C-ABI) with the FP64 CPU oracle on
+identical seeded inputs: sampled modes and cell lists bit-exact, structure
+factors and forces within 1e-12 relative RMS in FP64 and 1e-5 in mixed
+precision, energies, and the velocity-Verlet trajectory."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_2501_10946_amd")
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-5
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    R.lib()
+    return torch.device("cuda:0")
+
+
+class Case:
+    """One system on both sides: the oracle's SOG parameters expanded by the
+    library (so both use the same coefficients bit for bit)."""
+
+    def __init__(self, dev, w: workloads.Workload, precision=0, density=0, state=None, mmax=0):
+        print(f"\n[case] {w.name} N={w.N} P={w.P} prec={precision} dens={density}", flush=True)
+        self.w = w
+        self.st = state or workloads.make_state(w)
+        self.o = oracle.sog_auto(w.lam, w.r_c, w.eps)
+        self.sog = R.sog_from_parameters(self.o.lam, self.o.rc, self.o.h, self.o.t0, self.o.w, self.o.M1, self.o.M2)
+        self.sys = R.System(self.st.q, self.st.m, w.L, self.sog, w.kT, w.P, seed=w.seed, precision=precision,
+                            density=density, mmax=mmax, device=dev)
+        self.ref = oracle.System(self.st.q, self.st.m, w.L, self.o, w.kT, w.P, seed=w.seed, density=density,
+                                 mmax=mmax)
+        self.dev = dev
+        self.x = torch.tensor(self.st.x, device=dev)
+
+    def forces(self, step, x=None):
+        x = self.x if x is None else x
+        f = torch.empty_like(x)
+        fn = torch.empty_like(x)
+        e = torch.zeros(6, dtype=torch.float64, device=self.dev)
+        R.rbsog_compute_forces(self.sys.h, step, x, f, fn, e)
+        torch.cuda.synchronize()
+        return f.cpu().numpy(), fn.cpu().numpy(), e.cpu().numpy()
+
+
+SMALL = [
+    workloads.OCP_1K,
+    workloads.Workload("ragged_n777_p300", N=777, kappa=1.0, gamma=1.0, r_c=3.0, P=300, seed=5),
+    workloads.Workload("n1_single", N=1, kappa=1.0, gamma=1.0, r_c=0.5, P=7, seed=3),
+    workloads.Workload("nc3_exact_k2", N=150, kappa=2.0, gamma=3.0, r_c=2.5, P=1, seed=8),
+    workloads.Workload("mix_n5000", N=5000, kappa=0.5, gamma=5.0, r_c=4.0, P=64, seed=12, frac_b=0.1, q_b=5.0,
+                       m_b=20.0),
+]
+
+
+@pytest.mark.parametrize("w", SMALL, ids=lambda w: w.name)
+@pytest.mark.parametrize("density", [0, 1, 2, 3])
+def test_samples_bit_exact(dev, w, density):
+    c = Case(dev, w, density=density)
+    info = R.rbsog_get_info(c.sys.h)
+    assert info.mmax == c.ref.mmax and info.nshell == c.ref.nshell
+    n = torch.zeros((w.P, 3), dtype=torch.int32, device=dev)
+    coef = torch.zeros(w.P, dtype=torch.float64, device=dev)
+    for step in (0, 1, 17, 2 ** 40 + 3):
+        R.rbsog_sample_k(c.sys.h, step, n, coef)
+        torch.cuda.synchronize()
+        no, co = c.ref.draw(step)
+        assert np.array_equal(n.cpu().numpy(), no)
+        assert np.array_equal(coef.cpu().numpy().view(np.uint64), co.view(np.uint64))
+
+
+@pytest.mark.parametrize("w", SMALL + [workloads.OCP_100K], ids=lambda w: w.name)
+def test_cells_bit_exact(dev, w):
+    c = Case(dev, w)
+    nc = int(math.floor(w.L / w.r_c))
+    cs = torch.zeros(nc ** 3 + 1, dtype=torch.int32, device=dev)
+    order = torch.zeros(w.N, dtype=torch.int32, device=dev)
+    x = c.st.x.copy()
+    x[0, : min(3, w.N)] = 0.0                       # edges: x = 0 and the largest x < L
+    x[1, : min(3, w.N)] = np.nextafter(w.L, 0)
+    xt = torch.tensor(x, device=dev)
+    for _ in range(2):                               # rebuilding gives the same list
+        R.rbsog_build_cells(c.sys.h, xt, cs, order)
+        torch.cuda.synchronize()
+        cso, oo = oracle.cells(x, w.L, w.r_c)
+        assert np.array_equal(cs.cpu().numpy(), cso)
+        assert np.array_equal(order.cpu().numpy(), oo)
+
+
+@pytest.mark.parametrize("w", SMALL, ids=lambda w: w.name)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_rho(dev, w, precision):
+    c = Case(dev, w, precision=precision)
+    rho = torch.zeros((w.P, 2), dtype=torch.float64, device=dev)
+    for step in (0, 5):
+        R.rbsog_compute_rho(c.sys.h, step, c.x, rho)
+        torch.cuda.synchronize()
+        n3, coef = c.ref.draw(step)
+        ro = oracle.rho(c.st.x, c.st.q, w.L, n3)
+        tol = FP64_TOL if precision == 0 else MIXED_TOL
+        assert rel(rho.cpu().numpy(), ro) <= tol
+
+
+@pytest.mark.parametrize("w", SMALL, ids=lambda w: w.name)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_forces_and_energy(dev, w, precision):
+    c = Case(dev, w, precision=precision)
+    tol = FP64_TOL if precision == 0 else MIXED_TOL
+    for step in (0, 3):
+        f, fn, e = c.forces(step)
+        fo, fno, eo = c.ref.force(c.st.x, step)
+        if w.N > 1:
+            assert rel(f, fo) <= tol
+            if np.linalg.norm(fno) > 0:
+                assert rel(fn, fno) <= tol
+            assert rel(f - fn, fo - fno) <= tol
+        else:
+            assert np.abs(f - fo).max() <= 1e-12 and np.abs(fn).max() == 0.0
+        for k in (0, 1):
+            assert abs(e[k] - eo[k]) <= tol * max(abs(eo[k]), 1e-300) + (1e-300 if eo[k] == 0 else 0)
+        assert np.allclose(e[2:5], eo[2:5], rtol=1e-13, atol=0)
+
+
+def test_forces_repeatable(dev):
+    """Two evaluations of the same input give the same bits (fixed-order reductions)."""
+    c = Case(dev, workloads.OCP_1K)
+    a = c.forces(9)
+    b = c.forces(9)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_trajectory_small_ocp(dev, precision):
+    """The small one-component plasma for 100 velocity-Verlet steps: positions
+    agree with the oracle's trajectory to 1e-10 in FP64 (1e-4 mixed), and so do
+    the per-step energies."""
+    w = workloads.OCP_1K
+    c = Case(dev, w, precision=precision)
+    x = c.x.clone()
+    v = torch.tensor(c.st.v, device=dev)
+    f, _, _ = c.forces(0)
+    ft = torch.tensor(f, device=dev)
+    eh = torch.zeros((w.steps, 6), dtype=torch.float64, device=dev)
+    R.rbsog_step(c.sys.h, x, v, ft, 0, w.steps, w.dt, eh)
+    R.rbsog_check(c.sys.h)
+    xo, vo = c.st.x.copy(), c.st.v.copy()
+    fo, _, _ = c.ref.force(xo, 0)
+    eho = c.ref.run(xo, vo, fo, 0, w.steps, w.dt)
+    d = x.cpu().numpy() - xo
+    d -= w.L * np.round(d / w.L)
+    tol = 1e-10 if precision == 0 else 1e-4
+    assert np.abs(d).max() <= tol
+    E, Eo = eh.cpu().numpy().sum(1), eho.sum(1)
+    assert np.abs(E - Eo).max() <= (1e-9 if precision == 0 else 1e-3) * np.abs(Eo).max()
+
+
+def _sampled_reference(c, step, idx):
+    """Oracle forces on the particles idx only: near field by the subset pair sum,
+    far field from the full structure factors of the same sampled modes."""
+    w, st = c.w, c.st
+    n3, coef = c.ref.draw(step)
+    rho = oracle.rho(st.x, st.q, w.L, n3)
+    fn = oracle.near_subset(st.x, st.q, w.L, c.o, idx)
+    ff = oracle.far_rb(st.x[:, idx], st.q[idx], w.L, n3, coef, rho)
+    return fn + ff, fn, rho
+
+
+@pytest.mark.parametrize("w", [workloads.OCP_100K, workloads.MIXTURE_200K, workloads.OCP_1M_STRONG],
+                         ids=lambda w: w.name)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_sampled(dev, w, precision):
+    """At the full workload sizes, in the launch configuration the benchmark
+    times: forces on 256 sampled particles (and all structure factors) against
+    the oracle computed for those particles alone."""
+    c = Case(dev, w, precision=precision)
+    step = 11
+    f, fn, e = c.forces(step)
+    rng = np.random.default_rng(w.seed)
+    idx = np.sort(rng.choice(w.N, 256, replace=False))
+    fo, fno, rho_o = _sampled_reference(c, step, idx)
+    tol = FP64_TOL if precision == 0 else MIXED_TOL
+    assert rel(f[:, idx], fo) <= tol
+    assert rel(fn[:, idx], fno) <= tol
+    assert rel(f[:, idx] - fn[:, idx], fo - fno) <= tol
+    rho = torch.zeros((w.P, 2), dtype=torch.float64, device=dev)
+    R.rbsog_compute_rho(c.sys.h, step, c.x, rho)
+    torch.cuda.synchronize()
+    assert rel(rho.cpu().numpy(), rho_o) <= tol
+
+
+def test_invalid_arguments(dev):
+    """Errors are reported, not crashed on: a box below 3 cells, a null pointer,
+    a workspace that is too small."""
+    w = workloads.OCP_1K
+    st = workloads.make_state(w)
+    sog = R.rbsog_sog_init(w.lam, w.r_c, 1e-4)
+    q = torch.tensor(st.q, device=dev)
+    m = torch.tensor(st.m, device=dev)
+    bad = R.make_params(w.N, 2.5 * w.r_c, w.kT, w.P, 1)
+    with pytest.raises(R.RbsogError) as ei:
+        R.rbsog_workspace_size(bad, sog)
+    assert ei.value.code == R.RBSOG_EINVAL
+    p = R.make_params(w.N, w.L, w.kT, w.P, 1)
+    need = R.rbsog_workspace_size(p, sog)
+    small = torch.empty(need // 16, dtype=torch.float64, device=dev)
+    with pytest.raises(R.RbsogError) as ei:
+        R.rbsog_create(p, sog, q, m, small)
+    assert ei.value.code == R.RBSOG_EWORKSPACE
+
+
+def test_nonfinite_flag(dev):
+    """A NaN position yields a non-finite force, reported by rbsog_check."""
+    c = Case(dev, workloads.OCP_1K)
+    x = c.x.clone()
+    x[0, 5] = float("nan")
+    f = torch.empty_like(x)
+    R.rbsog_compute_forces(c.sys.h, 0, x, f)
+    with pytest.raises(R.RbsogError) as ei:
+        R.rbsog_check(c.sys.h)
+    assert ei.value.code == R.RBSOG_ENONFINITE
+    R.rbsog_check(c.sys.h)  # the flag was cleared
