@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Throughput of the RBSOG time step on one MI355X.
+
+Workload: the Yukawa one-component plasma with N = 1e5 unit charges at number
+density 3/(4 pi) (Wigner-Seitz radius 1), kappa = 0.5, Gamma = 10, r_c = 4,
+P = 200 sampled Fourier modes, SOG tolerance 1e-4, dt = 0.01; seeded uniform
+positions and Maxwell velocities, pre-equilibrated for 200 steps with the
+velocities rescaled to k_B T after each step (untimed).  A timed step is one
+velocity-Verlet step: half-kick + drift, cell list, mode sampling, structure
+factors, near field, far field + second half-kick.
+
+Prints one JSON line: particle-steps/s of the FP64 path (`value`), the same for
+the mixed-precision path, the force error against the FP64 CPU oracle at the
+final state, the roofline position of the dominant kernel (per-kernel HIP
+events recorded on the stream the kernels run on), and the oracle's own
+throughput on this machine's host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s at stated force RMS error; served-ensemble p50/p99 step latency"
+PEAK_FP64_TFLOPS = 78.6      # 256 CU x 2.4 GHz x 64 FP64 FMA lanes x 2
+PEAK_FP32_TFLOPS = 157.3     # published FP32 vector peak (packed FP32)
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic FP64 flops per unit of work (FMA = 2); derivations in the design doc.
+FLOPS_SINCOS = 40            # revolution reduction + sin and cos polynomials on [-1/8, 1/8] rev
+FLOPS_EXP = 28               # ln2 reduction + degree-11 polynomial + scale
+FLOPS_FAR_PER_IK = 6 + FLOPS_SINCOS + 3 + 6          # phase, sincos, Im(e^{-ikr} rho) coef, 3 FMA
+FLOPS_RHO_PER_IK = 6 + FLOPS_SINCOS + 4              # phase, sincos, 2 FMA
+
+
+def flops_near_per_pair(n_gauss: int) -> int:
+    # sqrt + reciprocal (16), exp(-r/lambda) (1 + 28), F_N1 (6),
+    # per Gaussian exp + 2 FMA (29 + 4), force 3 FMA (6), energy (4)
+    return 16 + 29 + 6 + n_gauss * 33 + 6 + 4
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def count_pairs(x, L, rc) -> int:
+    """Ordered pairs within r_c (periodic), the near field's algorithmic work."""
+    from scipy.spatial import cKDTree
+    t = cKDTree(x.T.copy() % L, boxsize=L)
+    return 2 * len(t.query_pairs(rc, output_type="ndarray"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--preeq", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget for the oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the library has no multi-GPU path (see the design notes on sharding); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2501_10946_amd as R
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = workloads.OCP_100K
+    st = workloads.make_state(w)
+    sog = R.rbsog_sog_init(w.lam, w.r_c, w.eps)
+    log(f"[bench] {w.name}: N={w.N} L={w.L:.4f} P={w.P} SOG M1={sog.M1} M2={sog.M2} err={sog.max_err:.2e}")
+
+    # ---- pre-equilibration (FP64, velocity rescaling to kT each step) ----
+    sys64 = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, precision=R.RBSOG_FP64, device=dev)
+    x = torch.tensor(st.x, device=dev)
+    v = torch.tensor(st.v, device=dev)
+    f = torch.empty_like(x)
+    R.rbsog_compute_forces(sys64.h, 0, x, f)
+    eh = torch.zeros((1, 6), dtype=torch.float64, device=dev)
+    ke_target = 0.5 * (3 * w.N - 3) * w.kT
+    step = 0
+    t0 = time.perf_counter()
+    for _ in range(args.preeq):
+        R.rbsog_step(sys64.h, x, v, f, step, 1, w.dt, eh)
+        step += 1
+        v.mul_(torch.sqrt(ke_target / eh[0, 5]))
+    R.rbsog_check(sys64.h)
+    torch.cuda.synchronize()
+    log(f"[bench] pre-equilibration {args.preeq} steps: {time.perf_counter() - t0:.2f} s")
+    x_eq, v_eq, f_eq, step_eq = x.clone(), v.clone(), f.clone(), step
+
+    results = {}
+    for name, prec in (("fp64", R.RBSOG_FP64), ("mixed", R.RBSOG_MIXED)):
+        s = sys64 if prec == R.RBSOG_FP64 else R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed,
+                                                         precision=prec, device=dev)
+        x, v, f = x_eq.clone(), v_eq.clone(), f_eq.clone()
+        step = step_eq
+        R.rbsog_compute_forces(s.h, step, x, f)
+        R.rbsog_step(s.h, x, v, f, step, args.warmup, w.dt)
+        step += args.warmup
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R.rbsog_step(s.h, x, v, f, step, args.steps, w.dt)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        step += args.steps
+        R.rbsog_check(s.h)
+        res = {"value": w.N * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps}
+        # per-kernel HIP events over a second pass of the same number of steps
+        if not args.no_roofline:
+            R.rbsog_timing_enable(s.h, True)
+            R.rbsog_step(s.h, x, v, f, step, args.steps, w.dt)
+            step += args.steps
+            res["kernels"] = {k: {"ms_per_launch": (t / n if n else 0.0), "launches": n}
+                              for k, (t, n) in R.rbsog_timing_read(s.h).items()}
+            R.rbsog_timing_enable(s.h, False)
+        res["x"], res["step"] = x, step
+        results[name] = res
+        log(f"[bench] {name}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.3f} ms/step")
+
+    # ---- force error at the final FP64 state, against the FP64 oracle ----
+    import oracle
+    o = oracle.sog_auto(w.lam, w.r_c, w.eps)
+    xf = results["fp64"]["x"]
+    xh = xf.cpu().numpy()
+    ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(w.N, 512, replace=False))
+    estep = results["fp64"]["step"] + 1
+    n3, coef = ref.draw(estep)
+    rho = oracle.rho(xh, st.q, w.L, n3)
+    fno = oracle.near_subset(xh, st.q, w.L, o, idx)
+    ffo = oracle.far_rb(xh[:, idx], st.q[idx], w.L, n3, coef, rho)
+    sog_o = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+    errs = {}
+    for name, prec in (("fp64", R.RBSOG_FP64), ("mixed", R.RBSOG_MIXED)):
+        s = R.System(st.q, st.m, w.L, sog_o, w.kT, w.P, seed=w.seed, precision=prec, device=dev)
+        fg = torch.empty_like(xf)
+        fng = torch.empty_like(xf)
+        R.rbsog_compute_forces(s.h, estep, xf, fg, fng)
+        torch.cuda.synchronize()
+        fg, fng = fg.cpu().numpy()[:, idx], fng.cpu().numpy()[:, idx]
+        rr = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        errs[name] = {"total": rr(fg, fno + ffo), "near": rr(fng, fno), "far": rr(fg - fng, ffo)}
+        log(f"[bench] {name} force rel RMS vs oracle: {errs[name]}")
+
+    # ---- roofline of the dominant kernel (FP64 path) ----
+    roofline = None
+    if not args.no_roofline:
+        kern = results["fp64"]["kernels"]
+        dom = max(kern, key=lambda k: kern[k]["ms_per_launch"] * kern[k]["launches"])
+        ms = kern[dom]["ms_per_launch"]
+        npairs = count_pairs(xh, w.L, w.r_c)
+        work = {
+            "far": w.N * w.P * FLOPS_FAR_PER_IK,
+            "rho_partial": w.N * w.P * FLOPS_RHO_PER_IK,
+            "near": npairs * flops_near_per_pair(sog.n),
+        }
+        if dom in work:
+            achieved = work[dom] / (ms * 1e-3) / 1e12
+            roofline = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                        "ms_per_launch": ms, "flops_per_launch": work[dom]}
+        log(f"[bench] kernels (fp64): " + ", ".join(f"{k} {v['ms_per_launch']:.4f} ms" for k, v in kern.items()))
+        log(f"[bench] near pairs {npairs} ({npairs / w.N:.1f} per particle)")
+        results["fp64"]["algorithmic_tflops"] = {k: work[k] / (kern[k]["ms_per_launch"] * 1e-3) / 1e12
+                                                 for k in work if kern[k]["ms_per_launch"] > 0}
+
+    # ---- the oracle on this machine's host cores (bounded sample) ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        xo = x_eq.cpu().numpy().copy()
+        vo = v_eq.cpu().numpy().copy()
+        fo, _, _ = ref.force(xo, step_eq)
+        t0 = time.perf_counter()
+        ref.run(xo, vo, fo, step_eq, 1, w.dt)
+        t1 = time.perf_counter() - t0
+        k = max(1, min(100, int(args.cpu_seconds / max(t1, 1e-6)) - 1))
+        t0 = time.perf_counter()
+        ref.run(xo, vo, fo, step_eq + 1, k, w.dt)
+        tk = time.perf_counter() - t0 + t1
+        cpu = {"value": w.N * (k + 1) / tk, "unit": "particle-steps/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": f"{k + 1} velocity-Verlet steps of the same workload (FP64, OpenMP)"}
+        log(f"[bench] oracle: {cpu['value']:.4g} particle-steps/s on {cpu['cores']} threads ({tk:.1f} s)")
+
+    r64 = results["fp64"]
+    out = {
+        "metric": METRIC,
+        "value": r64["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "N": w.N, "kappa": w.kappa, "gamma": w.gamma, "r_c": w.r_c, "P": w.P,
+                   "eps": w.eps, "dt": w.dt, "n_gauss": sog.n, "preequilibration_steps": args.preeq,
+                   "force_rel_rms": errs["fp64"]},
+        "mixed": {"value": results["mixed"]["value"], "ms_per_step": results["mixed"]["ms_per_step"],
+                  "dtype": "f32 pair/phase arithmetic, f64 accumulation", "force_rel_rms": errs["mixed"]},
+        "kernels_ms": {k: v["ms_per_launch"] for k, v in r64.get("kernels", {}).items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if "kernels" in results["mixed"]:
+        out["mixed"]["kernels_ms"] = {k: v["ms_per_launch"] for k, v in results["mixed"]["kernels"].items()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

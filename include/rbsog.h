@@ -225,6 +225,28 @@ int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double *f_dev, uin
  */
 int rbsog_check(rbsog_handle *h);
 
+/*
+ * Per-kernel timing with HIP events recorded on the handle's stream around each
+ * kernel launch (off by default; costs a few microseconds per launch when on).
+ * Kernel classes, in slot order: 0 cell list (ids, scan, scatter, stable
+ * rank + gather), 1 half-kick + drift, 2 mode sampling, 3 structure-factor
+ * partials, 4 structure-factor reduction, 5 near field, 6 far field + force
+ * assembly + half-kick, 7 energy sums.
+ */
+#define RBSOG_NUM_KERNEL_CLASSES 8
+typedef struct rbsog_timing {
+    double ms[RBSOG_NUM_KERNEL_CLASSES];       /* summed event-to-event milliseconds */
+    int64_t launches[RBSOG_NUM_KERNEL_CLASSES];
+} rbsog_timing;
+
+/* Turns timing on (enable != 0) or off and clears the accumulators.
+ * Errors: RBSOG_EINVAL, RBSOG_EHIP. */
+int rbsog_timing_enable(rbsog_handle *h, int enable);
+
+/* Synchronises the stream, writes the accumulated times since the last
+ * enable/read into *out and clears them.  Errors: RBSOG_EINVAL, RBSOG_EHIP. */
+int rbsog_timing_read(rbsog_handle *h, rbsog_timing *out);
+
 /* Releases the host-side handle (the caller still owns the workspace). */
 void rbsog_destroy(rbsog_handle *h);
 

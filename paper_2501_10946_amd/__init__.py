@@ -44,6 +44,14 @@ class rbsog_params(C.Structure):
                 ("seed", C.c_uint64), ("replica", C.c_uint32), ("precision", C.c_int), ("density", C.c_int)]
 
 
+RBSOG_NUM_KERNEL_CLASSES = 8
+KERNEL_CLASSES = ("cells", "kick_drift", "sample", "rho_partial", "rho_reduce", "near", "far", "energy")
+
+
+class rbsog_timing(C.Structure):
+    _fields_ = [("ms", C.c_double * RBSOG_NUM_KERNEL_CLASSES), ("launches", C.c_int64 * RBSOG_NUM_KERNEL_CLASSES)]
+
+
 class rbsog_info(C.Structure):
     _fields_ = [("N", C.c_int64), ("nc", C.c_int), ("mmax", C.c_int), ("nshell", C.c_int), ("nlat", C.c_int64),
                 ("S", C.c_double), ("Q1", C.c_double), ("Q2", C.c_double), ("ws_bytes", C.c_size_t)]
@@ -74,6 +82,8 @@ def lib() -> C.CDLL:
             "rbsog_compute_forces": (C.c_int, [_p, C.c_uint64, _p, _p, _p, _p]),
             "rbsog_step": (C.c_int, [_p, _p, _p, _p, C.c_uint64, C.c_int, C.c_double, _p]),
             "rbsog_check": (C.c_int, [_p]),
+            "rbsog_timing_enable": (C.c_int, [_p, C.c_int]),
+            "rbsog_timing_read": (C.c_int, [_p, C.POINTER(rbsog_timing)]),
             "rbsog_destroy": (None, [_p]),
             "rbsog_last_error": (C.c_char_p, []),
         }
@@ -205,6 +215,17 @@ def rbsog_step(h, x, v, f, step0: int, nsteps: int, dt: float, energy_hist=None)
 
 def rbsog_check(h) -> None:
     _check(lib().rbsog_check(h))
+
+
+def rbsog_timing_enable(h, enable: bool = True) -> None:
+    _check(lib().rbsog_timing_enable(h, int(enable)))
+
+
+def rbsog_timing_read(h) -> dict:
+    """{kernel class: (total ms, launches)} accumulated since the last enable/read."""
+    t = rbsog_timing()
+    _check(lib().rbsog_timing_read(h, C.byref(t)))
+    return {name: (t.ms[i], t.launches[i]) for i, name in enumerate(KERNEL_CLASSES)}
 
 
 def rbsog_destroy(h) -> None:

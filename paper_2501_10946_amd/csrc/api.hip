@@ -126,9 +126,58 @@ struct rbsog_handle {
     double *cdf, *coef, *eF, *fnear, *epart, *kepart, *energy;
     double4 *xs, *samp;
     double2 *part, *rho, *gk;
+    // per-kernel event timing (rbsog_timing_enable)
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    std::vector<std::pair<int, int>> records;  // (kernel class, index of the start event)
+    int used = 0;
+    double ms[RBSOG_NUM_KERNEL_CLASSES] = {};
+    int64_t launches[RBSOG_NUM_KERNEL_CLASSES] = {};
 };
 
 namespace {
+
+enum KernelClass { kCells = 0, kKickDrift, kSample, kRhoPartial, kRhoReduce, kNear, kFar, kEnergy };
+constexpr int kTimingEvents = 4096;
+
+// Turns recorded event pairs into accumulated milliseconds (synchronises).
+hipError_t harvest(rbsog_handle *h)
+{
+    if (h->records.empty()) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) return e;
+    for (auto &r : h->records) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, h->events[r.second], h->events[r.second + 1]);
+        if (e != hipSuccess) return e;
+        h->ms[r.first] += ms;
+        h->launches[r.first] += 1;
+    }
+    h->records.clear();
+    h->used = 0;
+    return hipSuccess;
+}
+
+// Runs one launcher; when timing is on, brackets it with events on the stream.
+template <class F>
+hipError_t timed(rbsog_handle *h, int cls, F &&launch)
+{
+    if (!h->timing) return launch();
+    if (h->used + 2 > (int)h->events.size()) {
+        hipError_t e = harvest(h);
+        if (e != hipSuccess) return e;
+    }
+    int s = h->used;
+    hipError_t e = hipEventRecord(h->events[s], h->st);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(h->events[s + 1], h->st);
+    if (e != hipSuccess) return e;
+    h->records.emplace_back(cls, s);
+    h->used += 2;
+    return hipSuccess;
+}
 
 CellArgs cell_args(rbsog_handle *h, const double *x)
 {
@@ -186,8 +235,11 @@ RhoArgs rho_args(rbsog_handle *h)
 // energy sums of one evaluation whose cell list is already built.
 int evaluate(rbsog_handle *h, uint64_t step, double *f, double *f_near, double *v, double dt, double *energy)
 {
-    HIPCHECK(launch_sample(sample_args(h, step), h->st));
-    HIPCHECK(launch_rho(rho_args(h), h->st));
+    SampleArgs sa = sample_args(h, step);
+    HIPCHECK(timed(h, kSample, [&] { return launch_sample(sa, h->st); }));
+    RhoArgs ra = rho_args(h);
+    HIPCHECK(timed(h, kRhoPartial, [&] { return launch_rho_partial(ra, h->st); }));
+    HIPCHECK(timed(h, kRhoReduce, [&] { return launch_rho_reduce(ra, h->st); }));
     NearArgs na{};
     na.N = (int)h->p.N;
     na.g = h->g;
@@ -198,7 +250,7 @@ int evaluate(rbsog_handle *h, uint64_t step, double *f, double *f_near, double *
     na.fnear = h->fnear;
     na.epart = h->epart;
     na.mixed = h->p.precision == RBSOG_MIXED;
-    HIPCHECK(launch_near(na, h->st));
+    HIPCHECK(timed(h, kNear, [&] { return launch_near(na, h->st); }));
     FarArgs fa{};
     fa.N = (int)h->p.N;
     fa.P = h->p.P;
@@ -217,7 +269,7 @@ int evaluate(rbsog_handle *h, uint64_t step, double *f, double *f_near, double *
     fa.kepart = v ? h->kepart : nullptr;
     fa.flag = h->flag;
     fa.mixed = h->p.precision == RBSOG_MIXED;
-    HIPCHECK(launch_far(fa, h->st));
+    HIPCHECK(timed(h, kFar, [&] { return launch_far(fa, h->st); }));
     if (energy) {
         EnergyArgs ea{};
         ea.nnear = nblocks(h->p.N);
@@ -230,7 +282,7 @@ int evaluate(rbsog_handle *h, uint64_t step, double *f, double *f_near, double *
         ea.Uself = h->Uself;
         ea.Ubg = h->Ubg;
         ea.out = energy;
-        HIPCHECK(launch_energy(ea, h->st));
+        HIPCHECK(timed(h, kEnergy, [&] { return launch_energy(ea, h->st); }));
     }
     return RBSOG_OK;
 }
@@ -371,8 +423,10 @@ extern "C" int rbsog_build_cells(rbsog_handle *h, const double *x_dev, int32_t *
 {
     if (!h || !x_dev) return fail(RBSOG_EINVAL, "null handle or x");
     CellArgs a = cell_args(h, x_dev);
-    HIPCHECK(launch_cell_ids(a, h->st));
-    HIPCHECK(launch_cells_finish(a, h->st));
+    HIPCHECK(timed(h, kCells, [&] {
+        hipError_t e = launch_cell_ids(a, h->st);
+        return e == hipSuccess ? launch_cells_finish(a, h->st) : e;
+    }));
     if (cell_start_dev)
         HIPCHECK(hipMemcpyAsync(cell_start_dev, h->cell_start, sizeof(int32_t) * ((size_t)h->g.ncell + 1),
                                 hipMemcpyDeviceToDevice, h->st));
@@ -394,13 +448,15 @@ extern "C" int rbsog_sample_k(rbsog_handle *h, uint64_t step, int32_t *n_dev, do
 extern "C" int rbsog_compute_rho(rbsog_handle *h, uint64_t step, const double *x_dev, double *rho_dev)
 {
     if (!h || !x_dev || !rho_dev) return fail(RBSOG_EINVAL, "null handle, x or rho");
-    HIPCHECK(launch_sample(sample_args(h, step), h->st));
+    SampleArgs sa = sample_args(h, step);
+    HIPCHECK(timed(h, kSample, [&] { return launch_sample(sa, h->st); }));
     RhoArgs a = rho_args(h);
     a.xs = nullptr;
     a.x = x_dev;
     a.q = h->q;
     a.rho_out = rho_dev;
-    HIPCHECK(launch_rho(a, h->st));
+    HIPCHECK(timed(h, kRhoPartial, [&] { return launch_rho_partial(a, h->st); }));
+    HIPCHECK(timed(h, kRhoReduce, [&] { return launch_rho_reduce(a, h->st); }));
     return RBSOG_OK;
 }
 
@@ -409,8 +465,10 @@ extern "C" int rbsog_compute_forces(rbsog_handle *h, uint64_t step, const double
 {
     if (!h || !x_dev || !f_dev) return fail(RBSOG_EINVAL, "null handle, x or f");
     CellArgs a = cell_args(h, x_dev);
-    HIPCHECK(launch_cell_ids(a, h->st));
-    HIPCHECK(launch_cells_finish(a, h->st));
+    HIPCHECK(timed(h, kCells, [&] {
+        hipError_t e = launch_cell_ids(a, h->st);
+        return e == hipSuccess ? launch_cells_finish(a, h->st) : e;
+    }));
     return evaluate(h, step, f_dev, f_near_dev, nullptr, 0.0, energy_dev);
 }
 
@@ -432,9 +490,9 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         k.cell_id = h->cell_id;
         k.count = h->count;
         k.flag = h->flag;
-        HIPCHECK(launch_kick_drift(k, h->st));
+        HIPCHECK(timed(h, kKickDrift, [&] { return launch_kick_drift(k, h->st); }));
         CellArgs a = cell_args(h, x_dev);
-        HIPCHECK(launch_cells_finish(a, h->st));
+        HIPCHECK(timed(h, kCells, [&] { return launch_cells_finish(a, h->st); }));
         double *e = energy_hist_dev ? energy_hist_dev + 6 * (size_t)n : nullptr;
         int rc = evaluate(h, step0 + (uint64_t)n + 1, f_dev, nullptr, v_dev, dt, e);
         if (rc) return rc;
@@ -456,4 +514,39 @@ extern "C" int rbsog_check(rbsog_handle *h)
     return RBSOG_OK;
 }
 
-extern "C" void rbsog_destroy(rbsog_handle *h) { delete h; }
+extern "C" int rbsog_timing_enable(rbsog_handle *h, int enable)
+{
+    if (!h) return fail(RBSOG_EINVAL, "null handle");
+    HIPCHECK(harvest(h));
+    if (enable && h->events.empty()) {
+        h->events.resize(kTimingEvents);
+        for (auto &e : h->events) HIPCHECK(hipEventCreate(&e));
+    }
+    h->timing = enable != 0;
+    for (int k = 0; k < RBSOG_NUM_KERNEL_CLASSES; ++k) {
+        h->ms[k] = 0.0;
+        h->launches[k] = 0;
+    }
+    return RBSOG_OK;
+}
+
+extern "C" int rbsog_timing_read(rbsog_handle *h, rbsog_timing *out)
+{
+    if (!h || !out) return fail(RBSOG_EINVAL, "null handle or out");
+    HIPCHECK(harvest(h));
+    for (int k = 0; k < RBSOG_NUM_KERNEL_CLASSES; ++k) {
+        out->ms[k] = h->ms[k];
+        out->launches[k] = h->launches[k];
+        h->ms[k] = 0.0;
+        h->launches[k] = 0;
+    }
+    return RBSOG_OK;
+}
+
+extern "C" void rbsog_destroy(rbsog_handle *h)
+{
+    if (!h) return;
+    if (!h->records.empty()) (void)hipStreamSynchronize(h->st);
+    for (auto &e : h->events) (void)hipEventDestroy(e);
+    delete h;
+}

@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_rho_reduce(RhoArgs a)
     }
 }
 
-hipError_t launch_rho(const RhoArgs &a, hipStream_t st)
+hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st)
 {
     dim3 grid(a.nchunk, (a.P + kBlock - 1) / kBlock);
     if (a.xs) {
@@ -292,6 +292,11 @@ hipError_t launch_rho(const RhoArgs &a, hipStream_t st)
         if (a.mixed) hipLaunchKernelGGL((k_rho_partial<false, true>), grid, dim3(kBlock), 0, st, a);
         else hipLaunchKernelGGL((k_rho_partial<false, false>), grid, dim3(kBlock), 0, st, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st)
+{
     hipLaunchKernelGGL(k_rho_reduce, dim3(a.P), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }

@@ -91,7 +91,8 @@ struct RhoArgs {
     double *rho_out;           // [P][2] or null
     int mixed;
 };
-hipError_t launch_rho(const RhoArgs &a, hipStream_t st);
+hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st);
+hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st);
 
 // --- near field ------------------------------------------------------------
 struct NearArgs {

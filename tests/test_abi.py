@@ -1,0 +1,81 @@
+"""The C-ABI library loads without a GPU, exports every function the public
+headers declare, and its host-only functions (Algorithm 1, workspace sizing)
+agree with the oracle."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for hdr in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(hdr).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(rbsog_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_2501_10946_amd as R
+    R.lib()
+    return R
+
+
+def test_exports_every_declared_symbol(R):
+    names = declared_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(R.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("lam,rc,eps", [(1.0, 3.0, 1e-4), (2.0, 4.0, 1e-4), (10.0, 5.0, 1e-4), (0.5, 4.0, 1e-4),
+                                        (0.5773, 2.8865, 1e-7)])
+def test_sog_init_matches_oracle(R, lam, rc, eps):
+    """The library's Algorithm 1 (its own root finder) picks the same numbers of
+    Gaussians as the oracle, the same step size bit for bit, and a starting
+    point within 1e-13 h at eps = 1e-4 (the C1 root is well conditioned
+    there; at tighter eps the residual flattens and only the error bound is
+    compared)."""
+    s = R.rbsog_sog_init(lam, rc, eps)
+    o = oracle.sog_auto(lam, rc, eps)
+    assert (s.M1, s.M2) == (o.M1, o.M2)
+    assert s.h == o.h
+    if eps >= 1e-4:
+        assert abs(s.t0 - o.t0) <= 1e-13 * o.h      # t0 ranges over [0, h)
+    assert s.max_err <= eps
+    assert abs(s.max_err - o.err) <= 1e-3 * eps
+
+
+def test_expansion_is_bitwise(R):
+    """Given the same parameters, library and oracle expand to the same bits."""
+    o = oracle.sog_auto(2.0, 4.0, 1e-4)
+    s = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+    for a, b in ((s.c, o.c), (s.s, o.s), (s.A, o.A), (s.B, o.B)):
+        assert np.array_equal(np.array(a[: o.n]).view(np.uint64), np.asarray(b).view(np.uint64))
+
+
+def test_host_errors(R):
+    with pytest.raises(R.RbsogError) as e:
+        R.rbsog_sog_init(-1.0, 3.0, 1e-4)
+    assert e.value.code == R.RBSOG_EINVAL
+    with pytest.raises(R.RbsogError) as e:
+        R.rbsog_sog_init(1.0, 40.0, 1e-4)
+    assert e.value.code == R.RBSOG_EINVAL
+    sog = R.rbsog_sog_init(1.0, 3.0, 1e-4)
+    with pytest.raises(R.RbsogError) as e:
+        R.rbsog_workspace_size(R.make_params(1000, 8.0, 1.0, 100, 1), sog)   # floor(8/3) = 2 cells
+    assert e.value.code == R.RBSOG_EINVAL
+    with pytest.raises(R.RbsogError) as e:
+        R.rbsog_workspace_size(R.make_params(1000, 16.0, 1.0, 0, 1), sog)    # P = 0
+    assert e.value.code == R.RBSOG_EINVAL
+    assert R.rbsog_workspace_size(R.make_params(1000, 16.1199, 1.0, 100, 1), sog) > 0
