@@ -110,7 +110,7 @@ int rbsog_sog_expand(rbsog_sog *sog);
 
 /* One periodic system. */
 typedef struct rbsog_params {
-    int64_t N;          /* particles, >= 1                                         */
+    int64_t N;          /* particles, 1 .. 2^27 - 1                                */
     double L;           /* cubic box edge; requires floor(L / r_c) >= 3            */
     double kT;          /* k_B T entering the adaptive density (eq. 3.22), > 0     */
     int P;              /* random-batch size, 1..4096                              */
@@ -230,10 +230,11 @@ int rbsog_check(rbsog_handle *h);
  * kernel launch (off by default; costs a few microseconds per launch when on).
  * Kernel classes, in slot order: 0 cell list (ids, scan, scatter, stable
  * rank + gather), 1 half-kick + drift, 2 mode sampling, 3 structure-factor
- * partials, 4 structure-factor reduction, 5 near field, 6 far field + force
- * assembly + half-kick, 7 energy sums.
+ * partials, 4 structure-factor reduction, 5 near-field pair evaluation,
+ * 6 far field + force assembly + half-kick, 7 energy sums, 8 near-field
+ * neighbour lists.
  */
-#define RBSOG_NUM_KERNEL_CLASSES 8
+#define RBSOG_NUM_KERNEL_CLASSES 9
 typedef struct rbsog_timing {
     double ms[RBSOG_NUM_KERNEL_CLASSES];       /* summed event-to-event milliseconds */
     int64_t launches[RBSOG_NUM_KERNEL_CLASSES];

@@ -44,8 +44,8 @@ class rbsog_params(C.Structure):
                 ("seed", C.c_uint64), ("replica", C.c_uint32), ("precision", C.c_int), ("density", C.c_int)]
 
 
-RBSOG_NUM_KERNEL_CLASSES = 8
-KERNEL_CLASSES = ("cells", "kick_drift", "sample", "rho_partial", "rho_reduce", "near", "far", "energy")
+RBSOG_NUM_KERNEL_CLASSES = 9
+KERNEL_CLASSES = ("cells", "kick_drift", "sample", "rho_partial", "rho_reduce", "near", "far", "energy", "nlist")
 
 
 class rbsog_timing(C.Structure):

@@ -4,6 +4,8 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -25,15 +27,45 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Offsets of every buffer inside the workspace.
 struct Layout {
     size_t lattice, cdf, coef, first, size;
-    size_t cell_id, count, cell_start, fill, tmp, order, xs;
-    size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy;
+    size_t cell_id, count, cell_start, fill, tmp, order, xs, tile_sum;
+    size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_cnt;
     size_t total;
 };
 
-int nchunks(int64_t N) { return (int)((N + kRhoChunk - 1) / kRhoChunk); }
-int nblocks(int64_t N) { return (int)((N + kBlock - 1) / kBlock); }
+int nchunks(int64_t N, int P) { return (int)((N + rho_chunk((int)N, P) - 1) / rho_chunk((int)N, P)); }
 
-Layout make_layout(int64_t N, int ncell, int64_t nlat, int nshell_max, int P)
+// Cell grids: the coarse one (cells >= r_c, the cell list of rbsog_build_cells)
+// and the fine one the force evaluation uses (cells >= r_c / 2).
+CellGeom make_geom(double L, int nc)
+{
+    CellGeom g{};
+    g.nc = nc;
+    g.ncell = nc * nc * nc;
+    g.L = L;
+    g.inv_cell = (double)nc / L;
+    return g;
+}
+int coarse_cells(double L, double rc) { return (int)std::floor(L / rc); }
+int fine_cells(double L, double rc) { return (int)std::floor(2.0 * L / rc); }
+
+// Capacity of each (particle, plane) neighbour list: 1.5x the expected count
+// of the fullest plane (a slab of width w through the particle's sphere) plus
+// 24; a lane that overflows is finished by a second walk, so this only sizes
+// the fast path.  RBSOG_NEAR_CAPACITY overrides it (a tuning knob).
+int near_capacity(int64_t N, double L, double rc)
+{
+    if (const char *e = std::getenv("RBSOG_NEAR_CAPACITY")) {
+        int v = std::atoi(e);
+        if (v >= 1 && v <= 4096) return v;
+    }
+    double n = (double)N / (L * L * L);
+    double w = L / std::floor(2.0 * L / rc);
+    double expected = n * kPi * rc * rc * w;
+    return std::min(4096, std::max(8, (int)std::ceil(1.5 * expected + 24.0)));
+}
+
+// ncell: cells of the fine grid (the larger one); kp: neighbour-list capacity
+Layout make_layout(int64_t N, int ncell, int64_t nlat, int nshell_max, int P, int kp)
 {
     Layout L{};
     size_t off = 0;
@@ -54,16 +86,19 @@ Layout make_layout(int64_t N, int ncell, int64_t nlat, int nshell_max, int P)
     L.tmp = take(sizeof(int32_t) * (size_t)N);
     L.order = take(sizeof(int32_t) * (size_t)N);
     L.xs = take(sizeof(double) * 4 * (size_t)N);
+    L.tile_sum = take(sizeof(int32_t) * (size_t)scan_tiles(ncell));
     L.samp = take(sizeof(double) * 4 * (size_t)P);
-    L.part = take(sizeof(double) * 2 * (size_t)nchunks(N) * (size_t)P);
+    L.part = take(sizeof(double) * 2 * (size_t)nchunks(N, P) * (size_t)P);
     L.rho = take(sizeof(double) * 2 * (size_t)P);
     L.gk = take(sizeof(double) * 2 * (size_t)P);
     L.eF = take(sizeof(double) * (size_t)P);
     L.fnear = take(sizeof(double) * 3 * (size_t)N);
-    L.epart = take(sizeof(double) * (size_t)nblocks(N));
-    L.kepart = take(sizeof(double) * (size_t)nblocks(N));
+    L.epart = take(sizeof(double) * (size_t)near_blocks((int)N));
+    L.kepart = take(sizeof(double) * (size_t)far_blocks((int)N));
     L.flag = take(sizeof(int32_t) * 4);
     L.energy = take(sizeof(double) * 8);
+    L.nbr = take(sizeof(int32_t) * (size_t)kp * 5 * (size_t)N);
+    L.nbr_cnt = take(sizeof(int32_t) * 5 * (size_t)N);
     L.total = off;
     return L;
 }
@@ -71,7 +106,7 @@ Layout make_layout(int64_t N, int ncell, int64_t nlat, int nshell_max, int P)
 int check_params(const rbsog_params *p, const rbsog_sog *s)
 {
     if (!p || !s) return fail(RBSOG_EINVAL, "null params or sog");
-    if (p->N < 1 || p->N > (int64_t)1 << 30) return fail(RBSOG_EINVAL, "N must lie in [1, 2^30]");
+    if (p->N < 1 || p->N > ((int64_t)1 << 27) - 1) return fail(RBSOG_EINVAL, "N must lie in [1, 2^27 - 1]");
     if (!(p->L > 0.0) || !std::isfinite(p->L)) return fail(RBSOG_EINVAL, "L must be positive and finite");
     if (!(p->kT > 0.0) || !std::isfinite(p->kT)) return fail(RBSOG_EINVAL, "kT must be positive and finite");
     if (p->P < 1 || p->P > 4096) return fail(RBSOG_EINVAL, "P must lie in [1, 4096]");
@@ -83,7 +118,8 @@ int check_params(const rbsog_params *p, const rbsog_sog *s)
     if (!(s->r_c > 0.0) || !(s->lambda > 0.0)) return fail(RBSOG_EINVAL, "sog: lambda and r_c must be positive");
     double nc = std::floor(p->L / s->r_c);
     if (nc < 3.0) return fail(RBSOG_EINVAL, "box too small: floor(L / r_c) = %g < 3", nc);
-    if (nc * nc * nc > (double)(1 << 26)) return fail(RBSOG_EINVAL, "too many cells");
+    double nf = std::floor(2.0 * p->L / s->r_c);
+    if (nf * nf * nf > (double)(1 << 26)) return fail(RBSOG_EINVAL, "too many cells (L / r_c too large)");
     return RBSOG_OK;
 }
 
@@ -115,15 +151,18 @@ struct rbsog_handle {
     rbsog_sog sog;
     const double *q, *m;
     hipStream_t st;
-    CellGeom g;
+    CellGeom g;   // coarse grid (rbsog_build_cells)
+    CellGeom gf;  // fine grid (force evaluation)
     Tables t;  // host copy (sizes; the vectors are released after upload)
     double V, Q1, Q2, Uk0, Uself, Ubg;
     Layout lay;
     char *ws;
     size_t ws_bytes;
     SogDev sd;
-    int32_t *lattice, *first, *size, *cell_id, *count, *cell_start, *fill, *tmp, *order, *flag;
+    int32_t *lattice, *first, *size, *cell_id, *count, *cell_start, *fill, *tmp, *order, *flag, *tile_sum;
     double *cdf, *coef, *eF, *fnear, *epart, *kepart, *energy;
+    int32_t *nbr, *nbr_cnt;
+    int kp;
     double4 *xs, *samp;
     double2 *part, *rho, *gk;
     // per-kernel event timing (rbsog_timing_enable)
@@ -137,7 +176,7 @@ struct rbsog_handle {
 
 namespace {
 
-enum KernelClass { kCells = 0, kKickDrift, kSample, kRhoPartial, kRhoReduce, kNear, kFar, kEnergy };
+enum KernelClass { kCells = 0, kKickDrift, kSample, kRhoPartial, kRhoReduce, kNear, kFar, kEnergy, kNlist };
 constexpr int kTimingEvents = 4096;
 
 // Turns recorded event pairs into accumulated milliseconds (synchronises).
@@ -179,11 +218,11 @@ hipError_t timed(rbsog_handle *h, int cls, F &&launch)
     return hipSuccess;
 }
 
-CellArgs cell_args(rbsog_handle *h, const double *x)
+CellArgs cell_args(rbsog_handle *h, const double *x, const CellGeom &g)
 {
     CellArgs a{};
     a.N = (int)h->p.N;
-    a.g = h->g;
+    a.g = g;
     a.x = x;
     a.q = h->q;
     a.cell_id = h->cell_id;
@@ -193,6 +232,7 @@ CellArgs cell_args(rbsog_handle *h, const double *x)
     a.tmp = h->tmp;
     a.order = h->order;
     a.xs = h->xs;
+    a.tile_sum = h->tile_sum;
     return a;
 }
 
@@ -219,7 +259,8 @@ RhoArgs rho_args(rbsog_handle *h)
     RhoArgs a{};
     a.N = (int)h->p.N;
     a.P = h->p.P;
-    a.nchunk = nchunks(h->p.N);
+    a.chunk = rho_chunk((int)h->p.N, h->p.P);
+    a.nchunk = nchunks(h->p.N, h->p.P);
     a.inv_L = 1.0 / h->p.L;
     a.xs = h->xs;
     a.samp = h->samp;
@@ -228,6 +269,7 @@ RhoArgs rho_args(rbsog_handle *h)
     a.gk = h->gk;
     a.eF = h->eF;
     a.mixed = h->p.precision == RBSOG_MIXED;
+    a.sc = make_sincos_poly();
     return a;
 }
 
@@ -242,7 +284,14 @@ int evaluate(rbsog_handle *h, uint64_t step, double *f, double *f_near, double *
     HIPCHECK(timed(h, kRhoReduce, [&] { return launch_rho_reduce(ra, h->st); }));
     NearArgs na{};
     na.N = (int)h->p.N;
-    na.g = h->g;
+    na.g = h->gf;
+    na.w = h->p.L / (double)h->gf.nc;
+    na.margin = 1e-9 * h->p.L;
+    na.inv_L = 1.0 / h->p.L;
+    na.e2 = make_exp2_poly();
+    na.nbr = h->nbr;
+    na.nbr_cnt = h->nbr_cnt;
+    na.kp = h->kp;
     na.rc2 = h->sog.r_c * h->sog.r_c;
     na.sog = h->sd;
     na.xs = h->xs;
@@ -250,6 +299,8 @@ int evaluate(rbsog_handle *h, uint64_t step, double *f, double *f_near, double *
     na.fnear = h->fnear;
     na.epart = h->epart;
     na.mixed = h->p.precision == RBSOG_MIXED;
+    na.energy = energy != nullptr;
+    HIPCHECK(timed(h, kNlist, [&] { return launch_nlist(na, h->st); }));
     HIPCHECK(timed(h, kNear, [&] { return launch_near(na, h->st); }));
     FarArgs fa{};
     fa.N = (int)h->p.N;
@@ -269,11 +320,12 @@ int evaluate(rbsog_handle *h, uint64_t step, double *f, double *f_near, double *
     fa.kepart = v ? h->kepart : nullptr;
     fa.flag = h->flag;
     fa.mixed = h->p.precision == RBSOG_MIXED;
+    fa.sc = make_sincos_poly();
     HIPCHECK(timed(h, kFar, [&] { return launch_far(fa, h->st); }));
     if (energy) {
         EnergyArgs ea{};
-        ea.nnear = nblocks(h->p.N);
-        ea.nfar = nblocks(h->p.N);
+        ea.nnear = near_blocks((int)h->p.N);
+        ea.nfar = far_blocks((int)h->p.N);
         ea.P = h->p.P;
         ea.epart = h->epart;
         ea.kepart = v ? h->kepart : nullptr;
@@ -297,8 +349,8 @@ extern "C" int rbsog_workspace_size(const rbsog_params *p, const rbsog_sog *s, s
     if (rc) return rc;
     if (!bytes) return fail(RBSOG_EINVAL, "bytes is null");
     int mmax = p->mmax > 0 ? p->mmax : default_mmax(*s, p->L);
-    int nc = (int)std::floor(p->L / s->r_c);
-    *bytes = make_layout(p->N, nc * nc * nc, lattice_points(mmax), mmax, p->P).total;
+    int nf = fine_cells(p->L, s->r_c);
+    *bytes = make_layout(p->N, nf * nf * nf, lattice_points(mmax), mmax, p->P, near_capacity(p->N, p->L, s->r_c)).total;
     return RBSOG_OK;
 }
 
@@ -316,11 +368,8 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     h->q = q_dev;
     h->m = m_dev;
     h->st = (hipStream_t)hip_stream;
-    int nc = (int)std::floor(p->L / s->r_c);
-    h->g.nc = nc;
-    h->g.ncell = nc * nc * nc;
-    h->g.L = p->L;
-    h->g.inv_cell = (double)nc / p->L;
+    h->g = make_geom(p->L, coarse_cells(p->L, s->r_c));
+    h->gf = make_geom(p->L, fine_cells(p->L, s->r_c));
     h->V = p->L * p->L * p->L;
     // sum q and sum q^2 in particle order (they enter the measure, eq. 3.22)
     std::vector<double> qh((size_t)p->N);
@@ -340,7 +389,8 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     }
     int mmax = p->mmax > 0 ? p->mmax : default_mmax(*s, p->L);
     build_tables(*s, *p, q2, mmax, &h->t);
-    h->lay = make_layout(p->N, h->g.ncell, h->t.nlat, mmax, p->P);
+    h->kp = near_capacity(p->N, p->L, s->r_c);
+    h->lay = make_layout(p->N, h->gf.ncell, h->t.nlat, mmax, p->P, h->kp);
     if (ws_bytes < h->lay.total) {
         size_t need = h->lay.total;
         delete h;
@@ -362,6 +412,7 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     h->tmp = (int32_t *)(w + L.tmp);
     h->order = (int32_t *)(w + L.order);
     h->xs = (double4 *)(w + L.xs);
+    h->tile_sum = (int32_t *)(w + L.tile_sum);
     h->samp = (double4 *)(w + L.samp);
     h->part = (double2 *)(w + L.part);
     h->rho = (double2 *)(w + L.rho);
@@ -372,6 +423,8 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     h->kepart = (double *)(w + L.kepart);
     h->flag = (int32_t *)(w + L.flag);
     h->energy = (double *)(w + L.energy);
+    h->nbr = (int32_t *)(w + L.nbr);
+    h->nbr_cnt = (int32_t *)(w + L.nbr_cnt);
     const Tables &t = h->t;
     e = hipMemcpyAsync(h->lattice, t.packed.data(), sizeof(int32_t) * t.packed.size(), hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess) e = hipMemcpyAsync(h->cdf, t.cdf.data(), sizeof(double) * t.nshell, hipMemcpyHostToDevice, h->st);
@@ -390,11 +443,13 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     h->t.shell_first = std::vector<int32_t>();
     h->t.shell_size = std::vector<int32_t>();
     // kernel-side SOG and the constant energies (Section 4.1)
+    const double log2e = 1.4426950408889634;
     h->sd.n = s->n;
     h->sd.inv_lambda = 1.0 / s->lambda;
+    h->sd.inv_lambda_log2e = log2e / s->lambda;
     for (int j = 0; j < s->n; ++j) {
         h->sd.c[j] = s->c[j];
-        h->sd.s[j] = s->s[j];
+        h->sd.s_log2e[j] = s->s[j] * log2e;
         h->sd.cs2[j] = 2.0 * s->c[j] * s->s[j];
     }
     h->Uk0 = s->Fhat0 * q1 * q1 / (2.0 * h->V);
@@ -422,7 +477,7 @@ extern "C" int rbsog_get_info(const rbsog_handle *h, rbsog_info *out)
 extern "C" int rbsog_build_cells(rbsog_handle *h, const double *x_dev, int32_t *cell_start_dev, int32_t *order_dev)
 {
     if (!h || !x_dev) return fail(RBSOG_EINVAL, "null handle or x");
-    CellArgs a = cell_args(h, x_dev);
+    CellArgs a = cell_args(h, x_dev, h->g);
     HIPCHECK(timed(h, kCells, [&] {
         hipError_t e = launch_cell_ids(a, h->st);
         return e == hipSuccess ? launch_cells_finish(a, h->st) : e;
@@ -464,7 +519,7 @@ extern "C" int rbsog_compute_forces(rbsog_handle *h, uint64_t step, const double
                                     double *f_near_dev, double *energy_dev)
 {
     if (!h || !x_dev || !f_dev) return fail(RBSOG_EINVAL, "null handle, x or f");
-    CellArgs a = cell_args(h, x_dev);
+    CellArgs a = cell_args(h, x_dev, h->gf);
     HIPCHECK(timed(h, kCells, [&] {
         hipError_t e = launch_cell_ids(a, h->st);
         return e == hipSuccess ? launch_cells_finish(a, h->st) : e;
@@ -481,7 +536,7 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
     for (int n = 0; n < nsteps; ++n) {
         KickDriftArgs k{};
         k.N = (int)h->p.N;
-        k.g = h->g;
+        k.g = h->gf;
         k.dt = dt;
         k.x = x_dev;
         k.v = v_dev;
@@ -491,7 +546,7 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         k.count = h->count;
         k.flag = h->flag;
         HIPCHECK(timed(h, kKickDrift, [&] { return launch_kick_drift(k, h->st); }));
-        CellArgs a = cell_args(h, x_dev);
+        CellArgs a = cell_args(h, x_dev, h->gf);
         HIPCHECK(timed(h, kCells, [&] { return launch_cells_finish(a, h->st); }));
         double *e = energy_hist_dev ? energy_hist_dev + 6 * (size_t)n : nullptr;
         int rc = evaluate(h, step0 + (uint64_t)n + 1, f_dev, nullptr, v_dev, dt, e);

@@ -1,5 +1,12 @@
-// Device helpers of librbsog: the counter-based generator and the phase
-// functions, written for gfx950.
+// Device helpers of librbsog: the counter-based generator and the elementary
+// functions of the force kernels, written for gfx950.
+//
+// The functions here are specialised to the arguments the kernels produce:
+// exponentials of non-positive arguments (Gaussians and the screened factor)
+// and sines/cosines of phases given in revolutions.  Both use Taylor series
+// on a reduced range, with enough terms that the truncation error is below
+// half an ulp, and no special-case branches (no overflow is possible; a very
+// negative argument underflows to zero through ldexp).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,20 +41,108 @@ __device__ inline void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint
     out[3] = c3;
 }
 
-// sin and cos of 2 pi u for a phase u given in revolutions (FP64).  The
-// integer part is removed exactly first (u - rint(u) is exact in FP64), so the
-// accuracy does not depend on |u|.
-__device__ inline void sincos_rev(double u, double *s, double *c)
+// ---------------------------------------------------------------------------
+// Taylor coefficients.  They are built at compile time on the host and handed
+// to the kernels in their argument blocks, so they sit in scalar registers and
+// each Horner step is a single FMA with a scalar operand.
+// ---------------------------------------------------------------------------
+
+constexpr double kLn2 = 0.6931471805599453;     // ln 2 rounded to FP64
+constexpr double kTwoPi = 6.283185307179586;    // 2 pi rounded to FP64
+constexpr double kLog2e = 1.4426950408889634;   // 1 / ln 2 rounded to FP64
+
+// a^k / k!
+constexpr double taylor_coef(double a, int k)
 {
-    double r = u - rint(u);
-    sincospi(2.0 * r, s, c);
+    double c = 1.0;
+    for (int i = 1; i <= k; ++i) c = c * a / (double)i;
+    return c;
 }
 
-// The same in FP32 after the FP64 reduction to [-1/2, 1/2] revolutions.
+// 2^f = sum_k (f ln2)^k / k!, k = 0..13: c[k] = ln2^k / k!.  For |f| <= 1/2 the
+// first omitted term is below 4.4e-18.
+struct Exp2Poly {
+    double c[14];
+};
+constexpr Exp2Poly make_exp2_poly()
+{
+    Exp2Poly p{};
+    for (int k = 0; k < 14; ++k) p.c[k] = taylor_coef(kLn2, k);
+    return p;
+}
+
+// sin(2 pi f) = f sum_k s[k] f^(2k), s[k] = (-1)^k (2 pi)^(2k+1)/(2k+1)!, k = 0..8
+// cos(2 pi f) = sum_k c[k] f^(2k),    c[k] = (-1)^k (2 pi)^(2k)/(2k)!,     k = 0..8
+// For |f| <= 1/8 (|2 pi f| <= pi/4) the first omitted terms are below 2.1e-18.
+struct SinCosPoly {
+    double s[9];
+    double c[9];
+};
+constexpr SinCosPoly make_sincos_poly()
+{
+    SinCosPoly p{};
+    for (int k = 0; k < 9; ++k) {
+        double sg = (k % 2) ? -1.0 : 1.0;
+        p.s[k] = sg * taylor_coef(kTwoPi, 2 * k + 1);
+        p.c[k] = sg * taylor_coef(kTwoPi, 2 * k);
+    }
+    return p;
+}
+
+// 2^y for finite y <= 0 (FP64): 2^y = 2^n 2^f with n = rint(y), f = y - n exact.
+__device__ inline double exp2_nonpos(double y, const Exp2Poly &P)
+{
+    double n = rint(y);
+    double f = y - n;
+    double p = P.c[13];
+#pragma unroll
+    for (int k = 12; k >= 0; --k) p = fma(p, f, P.c[k]);
+    return ldexp(p, (int)n);
+}
+
+// sin(2 pi u), cos(2 pi u) for a phase u in revolutions (FP64).  The integer
+// and quarter-turn parts are removed exactly (u - rint(u) and r - q/4 are
+// exact in FP64), leaving f in [-1/8, 1/8]; the quarter turn q rotates the
+// result.
+__device__ inline void sincos_rev(double u, const SinCosPoly &P, double *s, double *c)
+{
+    double r = u - rint(u);
+    double q = rint(4.0 * r);
+    double f = fma(-0.25, q, r);
+    double f2 = f * f;
+    double sp = P.s[8], cp = P.c[8];
+#pragma unroll
+    for (int k = 7; k >= 0; --k) {
+        sp = fma(sp, f2, P.s[k]);
+        cp = fma(cp, f2, P.c[k]);
+    }
+    double sn = sp * f;
+    // rotate by q quarter turns, q in {-2, -1, 0, 1, 2}
+    int qi = (int)q & 3;
+    double s1 = (qi & 1) ? cp : sn;
+    double c1 = (qi & 1) ? sn : cp;
+    *s = (qi & 2) ? -s1 : s1;
+    *c = ((qi + 1) & 2) ? -c1 : c1;
+}
+
+// The same in FP32 after the exact FP64 reduction to [-1/2, 1/2] revolutions:
+// the hardware sine and cosine take their argument in revolutions.
 __device__ inline void sincos_rev_f32(double u, float *s, float *c)
 {
     float r = (float)(u - rint(u));
-    sincospif(2.0f * r, s, c);
+    *s = __builtin_amdgcn_sinf(r);
+    *c = __builtin_amdgcn_cosf(r);
+}
+
+// Workgroup index remapped so that consecutive logical indices run on the same
+// XCD (the hardware deals workgroups to the 8 XCDs round-robin; each XCD has
+// its own L2, so spatially adjacent work should share one).
+__device__ inline int xcd_block(int b, int nb)
+{
+    const int nx = 8;
+    int x = b % nx, k = b / nx;
+    int q = nb / nx, r = nb % nx;
+    return x * q + min(x, r) + k;
 }
 
 }  // namespace rbsog

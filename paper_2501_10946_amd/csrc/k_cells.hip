@@ -1,0 +1,225 @@
+// gfx950 kernels of librbsog: cell list (counting sort with a stable rank) and the
+// first velocity-Verlet half step.
+//
+// Data layout in HBM: the caller's particle arrays stay FP64 SoA in the
+// caller's order; each evaluation builds a cell-ordered copy xs[N] of
+// (x, y, z, q) as double4 (32-byte rows) that the pair and far-field kernels
+// stream.
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+
+namespace rbsog {
+
+__global__ void k_zero_int(int32_t *p, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+hipError_t launch_zero_int(int32_t *p, int n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_int, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, p, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// cell list: ids + counts, scan, scatter, stable rank + gather
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_cell_ids(CellArgs a)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.N) return;
+    int nc = a.g.nc;
+    int cx = cell_coord(a.x[i], a.g.inv_cell, nc);
+    int cy = cell_coord(a.x[a.N + i], a.g.inv_cell, nc);
+    int cz = cell_coord(a.x[2 * a.N + i], a.g.inv_cell, nc);
+    int id = (cz * nc + cy) * nc + cx;
+    a.cell_id[i] = id;
+    atomicAdd(&a.count[id], 1);
+}
+
+// Exclusive scan of the cell counts in three passes: per-tile sums, a scan of
+// the (few) tile sums, then each tile scanned with its offset.  The last pass
+// also clears the fill counters of the scatter.
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kBlock * kScanPer;
+
+__device__ inline int32_t block_exclusive_scan_256(int32_t v, int32_t *sh, int32_t *total)
+{
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        int32_t u = (t >= off) ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += u;
+        __syncthreads();
+    }
+    int32_t incl = sh[t];
+    *total = sh[kBlock - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(CellArgs a)
+{
+    __shared__ int32_t sh[kBlock];
+    int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+        if (base + k < a.g.ncell) s += a.count[base + k];
+    int32_t total;
+    block_exclusive_scan_256(s, sh, &total);
+    if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_top(CellArgs a, int ntiles)
+{
+    __shared__ int32_t sums[1024];
+    int t = threadIdx.x;
+    int per = (ntiles + 1023) / 1024;
+    int b = t * per, e = min(ntiles, b + per);
+    int32_t s = 0;
+    for (int k = b; k < e; ++k) s += a.tile_sum[k];
+    sums[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int32_t v = (t >= off) ? sums[t - off] : 0;
+        __syncthreads();
+        sums[t] += v;
+        __syncthreads();
+    }
+    int32_t run = (t == 0) ? 0 : sums[t - 1];
+    for (int k = b; k < e; ++k) {
+        int32_t c = a.tile_sum[k];
+        a.tile_sum[k] = run;
+        run += c;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_apply(CellArgs a)
+{
+    __shared__ int32_t sh[kBlock];
+    int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    int32_t c[kScanPer];
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        c[k] = (base + k < a.g.ncell) ? a.count[base + k] : 0;
+        s += c[k];
+    }
+    int32_t total;
+    int32_t run = block_exclusive_scan_256(s, sh, &total) + a.tile_sum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < a.g.ncell) {
+            a.cell_start[base + k] = run;
+            a.fill[base + k] = 0;
+        }
+        run += c[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.cell_start[a.g.ncell] = a.N;
+}
+
+int scan_tiles(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
+
+// Unordered placement into each cell's segment.
+__global__ __launch_bounds__(kBlock) void k_scatter(CellArgs a)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.N) return;
+    int c = a.cell_id[i];
+    int slot = atomicAdd(&a.fill[c], 1);
+    a.tmp[a.cell_start[c] + slot] = i;
+}
+
+// Stable position: a particle's rank within its cell is the number of cell
+// members with a smaller index, so ties keep ascending particle index whatever
+// order the scatter produced.  Gathers (x, y, z, q) into cell order.
+__global__ __launch_bounds__(kBlock) void k_rank(CellArgs a)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.N) return;
+    int c = a.cell_id[i];
+    int b = a.cell_start[c], e = a.cell_start[c + 1];
+    int r = 0;
+    for (int k = b; k < e; ++k) r += (a.tmp[k] < i);
+    int p = b + r;
+    a.order[p] = i;
+    a.xs[p] = make_double4(a.x[i], a.x[a.N + i], a.x[2 * a.N + i], a.q[i]);
+}
+
+static bool cell_args_ok(const CellArgs &a)
+{
+    return a.N >= 1 && a.g.nc >= 1 && a.x && a.q && a.cell_id && a.count && a.cell_start && a.fill && a.tmp &&
+           a.order && a.xs && a.tile_sum;
+}
+
+hipError_t launch_cell_ids(const CellArgs &a, hipStream_t st)
+{
+    if (!cell_args_ok(a)) return hipErrorInvalidValue;
+    hipError_t e = launch_zero_int(a.count, a.g.ncell, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cell_ids, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cells_finish(const CellArgs &a, hipStream_t st)
+{
+    if (!cell_args_ok(a)) return hipErrorInvalidValue;
+    int grid = (a.N + kBlock - 1) / kBlock;
+    int nt = scan_tiles(a.g.ncell);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, a, nt);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_rank, dim3(grid), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// first half-kick + drift + wrap, fused with the cell ids of the new positions
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_kick_drift(KickDriftArgs a)
+{
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.N) return;
+    double L = a.g.L;
+    double hm = (0.5 * a.dt) / a.m[i];
+    int cc[3];
+    bool bad = false;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double vv = a.v[d * a.N + i] + hm * a.f[d * a.N + i];
+        double dx = a.dt * vv;
+        bad |= !(fabs(dx) < L);
+        double xx = a.x[d * a.N + i] + dx;
+        if (xx >= L) xx -= L;
+        if (xx < 0.0) xx += L;
+        if (xx >= L) xx = 0.0;
+        a.v[d * a.N + i] = vv;
+        a.x[d * a.N + i] = xx;
+        cc[d] = cell_coord(xx, a.g.inv_cell, a.g.nc);
+    }
+    if (bad) atomicOr(a.flag, 1);
+    int id = (cc[2] * a.g.nc + cc[1]) * a.g.nc + cc[0];
+    a.cell_id[i] = id;
+    atomicAdd(&a.count[id], 1);
+}
+
+hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t st)
+{
+    if (a.N < 1 || !a.x || !a.v || !a.f || !a.m || !a.cell_id || !a.count || !a.flag) return hipErrorInvalidValue;
+    hipError_t e = launch_zero_int(a.count, a.g.ncell, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_kick_drift, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+
+}  // namespace rbsog

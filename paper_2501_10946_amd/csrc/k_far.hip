@@ -1,0 +1,159 @@
+// gfx950 kernels of librbsog: far field, force assembly, second half-kick, energies.
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+
+namespace rbsog {
+
+// ---------------------------------------------------------------------------
+// far field of the random batch (eq. UF):
+//   f_i += -q_i (2 pi / L) sum_l coef_l n_l Im(exp(-i k_l . r_i) rho_l).
+// A workgroup owns 64 consecutive particles (cell order) and has 4 waves; wave
+// g takes the samples l = g mod 4 of each LDS tile of 256 samples, so every
+// particle's sum is spread over 4 lanes (4x the waves of one lane per particle,
+// which the latency of the dependent FP64 chains needs).  The 4 partial sums are
+// added in a fixed order, then near + far is written in the caller's particle
+// order and the second half-kick applied.
+// ---------------------------------------------------------------------------
+
+constexpr int kFarGroups = 4;
+constexpr int kFarThreads = 64 * kFarGroups;
+constexpr int kFarTile = 256;
+
+template <bool MIXED>
+__global__ __launch_bounds__(kFarThreads) void k_far(FarArgs a)
+{
+    __shared__ double4 sk[kFarTile];
+    __shared__ double2 sg[kFarTile];
+    __shared__ double part[3][kFarThreads];
+    __shared__ double red[64];
+    const int t = threadIdx.x;
+    const int g = t >> 6, lane = t & 63;
+    const int p = blockIdx.x * 64 + lane;
+    const bool live = p < a.N;
+    double4 pi = live ? a.xs[p] : make_double4(0.0, 0.0, 0.0, 0.0);
+    double sx = pi.x * a.inv_L, sy = pi.y * a.inv_L, sz = pi.z * a.inv_L;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int l0 = 0; l0 < a.P; l0 += kFarTile) {
+        __syncthreads();
+        if (l0 + t < a.P) {
+            sk[t] = a.samp[l0 + t];
+            sg[t] = a.gk[l0 + t];
+        }
+        __syncthreads();
+        int nl = min(kFarTile, a.P - l0);
+        for (int k = g; k < nl; k += kFarGroups) {
+            double4 kv = sk[k];
+            double2 gv = sg[k];
+            double u = kv.x * sx + kv.y * sy + kv.z * sz;
+            double im;
+            if (MIXED) {
+                float sn, cs;
+                sincos_rev_f32(u, &sn, &cs);
+                im = gv.y * (double)cs - gv.x * (double)sn;
+            } else {
+                double sn, cs;
+                sincos_rev(u, a.sc, &sn, &cs);
+                im = gv.y * cs - gv.x * sn;
+            }
+            ax += im * kv.x;
+            ay += im * kv.y;
+            az += im * kv.z;
+        }
+    }
+    part[0][t] = ax;
+    part[1][t] = ay;
+    part[2][t] = az;
+    __syncthreads();
+    double ke = 0.0;
+    if (t < 64 && live) {
+        double bx = 0.0, by = 0.0, bz = 0.0;
+#pragma unroll
+        for (int k = 0; k < kFarGroups; ++k) {
+            bx += part[0][k * 64 + t];
+            by += part[1][k * 64 + t];
+            bz += part[2][k * 64 + t];
+        }
+        double sc = -pi.w * a.two_pi_over_L;
+        double fnx = a.fnear[p], fny = a.fnear[a.N + p], fnz = a.fnear[2 * a.N + p];
+        double fx = fnx + sc * bx, fy = fny + sc * by, fz = fnz + sc * bz;
+        int i = a.order[p];
+        a.f[i] = fx;
+        a.f[a.N + i] = fy;
+        a.f[2 * a.N + i] = fz;
+        if (a.f_near_out) {
+            a.f_near_out[i] = fnx;
+            a.f_near_out[a.N + i] = fny;
+            a.f_near_out[2 * a.N + i] = fnz;
+        }
+        if (!isfinite(fx + fy + fz)) atomicOr(a.flag, 1);
+        if (a.v) {
+            double mi = a.m[i];
+            double hm = a.half_dt / mi;
+            double vx = a.v[i] + hm * fx, vy = a.v[a.N + i] + hm * fy, vz = a.v[2 * a.N + i] + hm * fz;
+            a.v[i] = vx;
+            a.v[a.N + i] = vy;
+            a.v[2 * a.N + i] = vz;
+            ke = 0.5 * mi * (vx * vx + vy * vy + vz * vz);
+        }
+    }
+    if (a.kepart) {
+        if (t < 64) red[t] = ke;
+        __syncthreads();
+        for (int off = 32; off > 0; off >>= 1) {
+            if (t < off) red[t] += red[t + off];
+            __syncthreads();
+        }
+        if (t == 0) a.kepart[blockIdx.x] = red[0];
+    }
+}
+
+int far_blocks(int N) { return (N + 63) / 64; }
+
+hipError_t launch_far(const FarArgs &a, hipStream_t st)
+{
+    if (a.N < 1 || a.P < 1 || !a.xs || !a.order || !a.samp || !a.gk || !a.fnear || !a.f || !a.flag ||
+        (a.v && (!a.m || !a.kepart)))
+        return hipErrorInvalidValue;
+    dim3 grid(far_blocks(a.N));
+    if (a.mixed) hipLaunchKernelGGL(k_far<true>, grid, dim3(kFarThreads), 0, st, a);
+    else hipLaunchKernelGGL(k_far<false>, grid, dim3(kFarThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// energies: fixed-order sums of the block partials
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a)
+{
+    __shared__ double red[kBlock];
+    double un = 0.0, ke = 0.0, uf = 0.0;
+    for (int b = threadIdx.x; b < a.nnear; b += kBlock) un += a.epart[b];
+    for (int l = threadIdx.x; l < a.P; l += kBlock) uf += a.eF[l];
+    if (a.kepart)
+        for (int b = threadIdx.x; b < a.nfar; b += kBlock) ke += a.kepart[b];
+    un = block_sum_256(un, red);
+    __syncthreads();
+    uf = block_sum_256(uf, red);
+    __syncthreads();
+    ke = block_sum_256(ke, red);
+    if (threadIdx.x == 0) {
+        a.out[0] = un;
+        a.out[1] = uf;
+        a.out[2] = a.Uk0;
+        a.out[3] = a.Uself;
+        a.out[4] = a.Ubg;
+        a.out[5] = ke;
+    }
+}
+
+hipError_t launch_energy(const EnergyArgs &a, hipStream_t st)
+{
+    if (!a.epart || !a.eF || !a.out) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_energy, dim3(1), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+
+}  // namespace rbsog

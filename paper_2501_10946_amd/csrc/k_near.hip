@@ -1,0 +1,359 @@
+// gfx950 kernel of librbsog: the near field of eq. (3.8),
+//   f_i = sum_{j : |d| < r_c} q_i q_j [F_N1(r) + F_N2(r)] d,   d = r_i - r_j (minimum image),
+//   F_N1 = exp(-r/lambda)(1 + r/lambda)/r^3,  F_N2 = -2 sum_g c_g s_g exp(-s_g r^2),
+// and the near energy U_N = 1/2 sum q_i q_j (Y(r) - F(r)).
+//
+// Two kernels.  The cell grid is the fine one, cells of width
+// w = L / floor(2L / r_c) >= r_c / 2, so the neighbour stencil is 5 x 5 x 5
+// cells; cell order makes each x-row of 5 cells one contiguous index range (two
+// where it wraps around the box).  Work is split into (particle, plane) lanes:
+// a workgroup owns 64 consecutive particles (cell order) and has 5 waves, wave
+// dz (= -2..2) handling the z-plane dz of each particle.  Rows and x-cells whose
+// distance from the particle already exceeds r_c are skipped per particle.
+//
+//   k_nlist  walks the candidates (four loads in flight per lane) and stores the
+//            accepted j of each lane, in candidate order, into a column-major
+//            list of capacity kp per lane, plus the lane's total count;
+//   k_near   evaluates the pair function on the lists (every lane busy on
+//            accepted pairs only).  A lane whose count exceeds kp walks its
+//            candidates again and evaluates the ones beyond the first kp.
+//
+// Each lane sums its (particle, plane) force in candidate order and the five
+// planes are added in a fixed order: the result is deterministic.
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+
+namespace rbsog {
+
+constexpr int kNearPlanes = 5;                 // waves per workgroup, one per dz
+constexpr int kNearThreads = 64 * kNearPlanes;
+constexpr int kStage = 8;                      // accepted entries staged per lane before storing
+constexpr int kShiftBits = 5;                  // image-shift code 0..26 in the top bits of a range start
+constexpr uint32_t kIndexMask = (1u << (32 - kShiftBits)) - 1u;
+constexpr int kMaxRanges = 10;                 // 5 rows, each at most two pieces
+
+__device__ inline double shift_of(int code, double L) { return (double)(code - 1) * L; }
+
+// Distance from coordinate y to the slab [c w - m, (c + 1) w + m] (0 inside).
+__device__ inline double slab_gap(double y, int c, double w, double m)
+{
+    double lo = (double)c * w - m, hi = (double)(c + 1) * w + m;
+    return fmax(0.0, fmax(lo - y, y - hi));
+}
+
+// One candidate range: particles [start, end) of the cell-ordered copy, all
+// under one image shift (code = xc + 3 yc + 9 zc, each 0/1/2 for -L/0/+L).
+struct Range {
+    int32_t start_code;     // start | code << 27
+    int32_t end;
+};
+
+// The (particle, plane) a lane works on, with its home cell.
+struct Lane {
+    int p, plane;
+    double4 pi;
+    int cx, cy, cz, zc;     // home x, y; wrapped z cell of the plane and its shift code
+    double gz;              // z-gap from the particle to the plane
+};
+
+__device__ inline Lane make_lane(const NearArgs &a, int p, int plane)
+{
+    Lane l;
+    l.p = p;
+    l.plane = plane;
+    l.pi = make_double4(0.0, 0.0, 0.0, 0.0);
+    l.cx = l.cy = l.cz = 0;
+    l.zc = 1;
+    l.gz = 1e300;
+    if (p < a.N) {
+        const int nf = a.g.nc;
+        l.pi = a.xs[p];
+        l.cx = cell_coord(l.pi.x, a.g.inv_cell, nf);
+        l.cy = cell_coord(l.pi.y, a.g.inv_cell, nf);
+        int czu = cell_coord(l.pi.z, a.g.inv_cell, nf) + plane - 2;
+        l.gz = slab_gap(l.pi.z, czu, a.w, a.margin);
+        l.cz = czu;
+        if (czu < 0) { l.cz += nf; l.zc = 0; } else if (czu >= nf) { l.cz -= nf; l.zc = 2; }
+    }
+    return l;
+}
+
+// The candidate ranges of row `row` (dy = row - 2) for a lane: 0, 1 or 2.
+__device__ inline int row_ranges(const NearArgs &a, const Lane &l, int row, Range out[2])
+{
+    const int nf = a.g.nc;
+    const double w = a.w, m = a.margin;
+    int cyu = l.cy + row - 2;
+    double gy = slab_gap(l.pi.y, cyu, w, m);
+    double rem = a.rc2 - gy * gy - l.gz * l.gz;
+    if (!(rem > 0.0)) return 0;
+    int dxlo = -2, dxhi = 2;
+    for (int k = 0; k < 2; ++k) {   // at most two x-cells per side can be culled
+        double gl = slab_gap(l.pi.x, l.cx + dxlo, w, m);
+        if (dxlo < 0 && !(gl * gl < rem)) ++dxlo;
+        double gh = slab_gap(l.pi.x, l.cx + dxhi, w, m);
+        if (dxhi > 0 && !(gh * gh < rem)) --dxhi;
+    }
+    int xa = l.cx + dxlo, xb = l.cx + dxhi;   // unwrapped; xb - xa <= 4 < nf
+    int cyw = cyu, yc = 1;
+    if (cyw < 0) { cyw += nf; yc = 0; } else if (cyw >= nf) { cyw -= nf; yc = 2; }
+    int base = (l.cz * nf + cyw) * nf;
+    int code = 3 * yc + 9 * l.zc;
+    int n = 0;
+    // piece left of the wrap (or the whole row), then the piece past it
+    int lo0 = xa < 0 ? xa + nf : xa, hi0 = xa < 0 ? nf - 1 : min(xb, nf - 1);
+    int xc0 = xa < 0 ? 0 : 1;
+    int s0 = a.cell_start[base + lo0], e0 = a.cell_start[base + hi0 + 1];
+    if (s0 < e0) out[n++] = Range{(int32_t)((uint32_t)s0 | ((uint32_t)(code + xc0) << 27)), e0};
+    if (xa < 0 || xb > nf - 1) {
+        int hi1 = xa < 0 ? xb : xb - nf;
+        int xc1 = xa < 0 ? 1 : 2;
+        int s1 = a.cell_start[base], e1 = a.cell_start[base + hi1 + 1];
+        if (s1 < e1) out[n++] = Range{(int32_t)((uint32_t)s1 | ((uint32_t)(code + xc1) << 27)), e1};
+    }
+    return n;
+}
+
+// Walk position within one range.
+struct Cursor {
+    int j, jend;
+    double bx, by, bz;      // particle position minus the image shift of the range
+};
+
+__device__ inline Cursor open_range(const Range &g, const double4 &pi, double L)
+{
+    Cursor c;
+    c.j = g.start_code & (int32_t)kIndexMask;
+    c.jend = g.end;
+    uint32_t code = (uint32_t)g.start_code >> 27;
+    c.bx = pi.x - shift_of((int)(code % 3u), L);
+    c.by = pi.y - shift_of((int)((code / 3u) % 3u), L);
+    c.bz = pi.z - shift_of((int)(code / 9u), L);
+    return c;
+}
+
+// The acceptance test shared by the list build and the overflow walk.
+__device__ inline bool accept(const NearArgs &a, const Cursor &c, const double4 &q, int j, int p)
+{
+    double dx = c.bx - q.x, dy = c.by - q.y, dz = c.bz - q.z;
+    double r2 = dx * dx + dy * dy + dz * dz;
+    return r2 < a.rc2 && j != p;
+}
+
+// FP64 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps.
+__device__ inline double rsqrt_f64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double hx = 0.5 * x;
+    double e = fma(-hx * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-hx * y, y, 0.5);
+    return fma(y, e, y);
+}
+
+template <bool MIXED, bool ENERGY>
+__device__ inline void pair_force(const NearArgs &a, const double4 &pi, int j, double &fx, double &fy, double &fz,
+                                  double &en)
+{
+    const double L = a.g.L;
+    double4 pj = a.xs[j];
+    // d by the minimum image (|d| < r_c <= L/3)
+    double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+    dx = fma(-L, rint(dx * a.inv_L), dx);
+    dy = fma(-L, rint(dy * a.inv_L), dy);
+    dz = fma(-L, rint(dz * a.inv_L), dz);
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double qq = pi.w * pj.w;
+    if (MIXED) {
+        float r2f = (float)r2;
+        float irf = __builtin_amdgcn_rsqf(r2f);
+        float rf = r2f * irf;
+        float ey = __builtin_amdgcn_exp2f(-rf * (float)a.sog.inv_lambda_log2e);
+        float f1 = ey * (1.0f + rf * (float)a.sog.inv_lambda) * (irf * irf * irf);
+        float gs = 0.0f, fs = 0.0f;
+        for (int g = 0; g < a.sog.n; ++g) {
+            float eg = __builtin_amdgcn_exp2f(-(float)a.sog.s_log2e[g] * r2f);
+            gs = fmaf((float)a.sog.cs2[g], eg, gs);
+            if (ENERGY) fs = fmaf((float)a.sog.c[g], eg, fs);
+        }
+        double fac = qq * (double)(f1 - gs);
+        fx = fma(fac, dx, fx);
+        fy = fma(fac, dy, fy);
+        fz = fma(fac, dz, fz);
+        if (ENERGY) en = fma(qq, (double)(ey * irf - fs), en);
+    } else {
+        double ir = rsqrt_f64(r2);
+        double r = r2 * ir;
+        double ey = exp2_nonpos(-r * a.sog.inv_lambda_log2e, a.e2);
+        double f1 = ey * fma(r, a.sog.inv_lambda, 1.0) * (ir * ir * ir);
+        double gs = 0.0, fs = 0.0;
+        for (int g = 0; g < a.sog.n; ++g) {
+            double eg = exp2_nonpos(-a.sog.s_log2e[g] * r2, a.e2);
+            gs = fma(a.sog.cs2[g], eg, gs);
+            if (ENERGY) fs = fma(a.sog.c[g], eg, fs);
+        }
+        double fac = qq * (f1 - gs);
+        fx = fma(fac, dx, fx);
+        fy = fma(fac, dy, fy);
+        fz = fma(fac, dz, fz);
+        if (ENERGY) en = fma(qq, ey * ir - fs, en);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// neighbour lists
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kNearThreads) void k_nlist(NearArgs a)
+{
+    __shared__ Range rng[kMaxRanges][kNearThreads];
+    __shared__ int32_t stage[kStage][kNearThreads];
+    const int t = threadIdx.x;
+    const int plane = t >> 6;
+    const int p = xcd_block(blockIdx.x, gridDim.x) * 64 + (t & 63);
+    const Lane l = make_lane(a, p, plane);
+    int nr = 0;
+    if (p < a.N && l.gz * l.gz < a.rc2) {
+        for (int row = 0; row < 5; ++row) {
+            Range g[2];
+            int n = row_ranges(a, l, row, g);
+            for (int k = 0; k < n; ++k) rng[nr++][t] = g[k];
+        }
+    }
+    const size_t stride = (size_t)kNearPlanes * (size_t)a.N;
+    int32_t *out = a.nbr + (size_t)plane * a.N + p;
+    int r = 0, total = 0;
+    Cursor c{0, 0, 0.0, 0.0, 0.0};
+    if (nr > 0) c = open_range(rng[0][t], l.pi, a.g.L);
+    do {
+        int cnt = 0;
+        while (cnt <= kStage - 4 && r < nr) {
+            if (c.j >= c.jend) {
+                if (++r < nr) c = open_range(rng[r][t], l.pi, a.g.L);
+                continue;
+            }
+            int last = c.jend - 1;
+            int n = min(4, c.jend - c.j);
+            double4 q0 = a.xs[c.j];
+            double4 q1 = a.xs[min(c.j + 1, last)];
+            double4 q2 = a.xs[min(c.j + 2, last)];
+            double4 q3 = a.xs[min(c.j + 3, last)];
+            if (accept(a, c, q0, c.j, p)) stage[cnt++][t] = c.j;
+            if (n > 1 && accept(a, c, q1, c.j + 1, p)) stage[cnt++][t] = c.j + 1;
+            if (n > 2 && accept(a, c, q2, c.j + 2, p)) stage[cnt++][t] = c.j + 2;
+            if (n > 3 && accept(a, c, q3, c.j + 3, p)) stage[cnt++][t] = c.j + 3;
+            c.j += n;
+        }
+        for (int k = 0; k < cnt; ++k)
+            if (total + k < a.kp) out[(size_t)(total + k) * stride] = stage[k][t];
+        total += cnt;
+    } while (__any(r < nr));
+    if (p < a.N) a.nbr_cnt[(size_t)plane * a.N + p] = total;
+}
+
+// ---------------------------------------------------------------------------
+// evaluation
+// ---------------------------------------------------------------------------
+
+template <bool MIXED, bool ENERGY>
+__global__ __launch_bounds__(kNearThreads) void k_near(NearArgs a)
+{
+    __shared__ double part[4][kNearThreads];
+    const int t = threadIdx.x;
+    const int plane = t >> 6;
+    const int p = xcd_block(blockIdx.x, gridDim.x) * 64 + (t & 63);
+    const size_t stride = (size_t)kNearPlanes * (size_t)a.N;
+    double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
+    int cnt = 0;
+    if (p < a.N) {
+        pi = a.xs[p];
+        cnt = a.nbr_cnt[(size_t)plane * a.N + p];
+    }
+    const int32_t *in = a.nbr + (size_t)plane * a.N + p;
+    const int m = min(cnt, a.kp);
+    double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0;
+    for (int k = 0; k < m; ++k) pair_force<MIXED, ENERGY>(a, pi, in[(size_t)k * stride], fx, fy, fz, en);
+    if (cnt > a.kp) {
+        // overflow: walk the candidates again, evaluate the accepted beyond kp
+        const Lane l = make_lane(a, p, plane);
+        int seen = 0;
+        for (int row = 0; row < 5; ++row) {
+            Range g[2];
+            int n = row_ranges(a, l, row, g);
+            for (int k = 0; k < n; ++k) {
+                Cursor c = open_range(g[k], pi, a.g.L);
+                for (; c.j < c.jend; ++c.j) {
+                    if (!accept(a, c, a.xs[c.j], c.j, p)) continue;
+                    if (seen++ >= a.kp) pair_force<MIXED, ENERGY>(a, pi, c.j, fx, fy, fz, en);
+                }
+            }
+        }
+    }
+    // the five planes of each particle, added in plane order
+    part[0][t] = fx;
+    part[1][t] = fy;
+    part[2][t] = fz;
+    part[3][t] = ENERGY ? 0.5 * en : 0.0;
+    __syncthreads();
+    if (t < 64 && p < a.N) {
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+        for (int k = 0; k < kNearPlanes; ++k) {
+            sx += part[0][k * 64 + t];
+            sy += part[1][k * 64 + t];
+            sz += part[2][k * 64 + t];
+        }
+        a.fnear[p] = sx;
+        a.fnear[a.N + p] = sy;
+        a.fnear[2 * a.N + p] = sz;
+    }
+    if (ENERGY) {
+        double e = 0.0;
+        if (t < 64) {
+#pragma unroll
+            for (int k = 0; k < kNearPlanes; ++k) e += part[3][k * 64 + t];
+        }
+        __syncthreads();
+        if (t < 64) part[0][t] = e;
+        __syncthreads();
+        for (int off = 32; off > 0; off >>= 1) {
+            if (t < off) part[0][t] += part[0][t + off];
+            __syncthreads();
+        }
+        if (t == 0) a.epart[blockIdx.x] = part[0][0];
+    }
+}
+
+int near_blocks(int N) { return (N + 63) / 64; }
+
+// A launch with a missing buffer is refused on the host.
+static bool near_args_ok(const NearArgs &a)
+{
+    return a.N >= 1 && a.xs && a.cell_start && a.nbr && a.nbr_cnt && a.fnear && a.kp >= 1 && a.g.nc >= 6 &&
+           a.rc2 > 0.0 && a.w > 0.0 && (!a.energy || a.epart);
+}
+
+hipError_t launch_nlist(const NearArgs &a, hipStream_t st)
+{
+    if (!near_args_ok(a)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_nlist, dim3(near_blocks(a.N)), dim3(kNearThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_near(const NearArgs &a, hipStream_t st)
+{
+    if (!near_args_ok(a)) return hipErrorInvalidValue;
+    dim3 grid(near_blocks(a.N));
+    dim3 block(kNearThreads);
+    if (a.mixed) {
+        if (a.energy) hipLaunchKernelGGL((k_near<true, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_near<true, false>), grid, block, 0, st, a);
+    } else {
+        if (a.energy) hipLaunchKernelGGL((k_near<false, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_near<false, false>), grid, block, 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace rbsog

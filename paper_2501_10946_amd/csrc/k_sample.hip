@@ -1,0 +1,48 @@
+// gfx950 kernel of librbsog: i.i.d. draws of the Fourier modes.
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+
+namespace rbsog {
+
+// ---------------------------------------------------------------------------
+// sampling: P i.i.d. modes from the shell CDF (bit-exact integer/IEEE steps)
+// ---------------------------------------------------------------------------
+
+__global__ void k_sample(SampleArgs a)
+{
+    int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= a.P) return;
+    uint64_t w[4];
+    philox4x64_10((uint64_t)l, a.step, 0, 0, a.seed, (uint64_t)a.replica, w);
+    double u = (double)(w[0] >> 11) * 0x1p-53;
+    double target = u * a.S;
+    int lo = 0, hi = a.nshell;
+    while (lo < hi) {
+        int mid = lo + ((hi - lo) >> 1);
+        if (a.cdf[mid] > target) hi = mid; else lo = mid + 1;
+    }
+    int i = lo < a.nshell ? lo : a.nshell - 1;
+    uint64_t j = __umul64hi(w[1], (uint64_t)a.size[i]);
+    uint32_t pk = (uint32_t)a.lattice[a.first[i] + (int64_t)j];
+    int nx = (int)(pk & 1023u) - 512, ny = (int)((pk >> 10) & 1023u) - 512, nz = (int)((pk >> 20) & 1023u) - 512;
+    double cf = a.coef[i];
+    a.samp[l] = make_double4((double)nx, (double)ny, (double)nz, cf);
+    if (a.n_out) {
+        a.n_out[3 * l + 0] = nx;
+        a.n_out[3 * l + 1] = ny;
+        a.n_out[3 * l + 2] = nz;
+    }
+    if (a.coef_out) a.coef_out[l] = cf;
+}
+
+hipError_t launch_sample(const SampleArgs &a, hipStream_t st)
+{
+    if (a.P < 1 || a.nshell < 1 || !a.cdf || !a.coef || !a.first || !a.size || !a.lattice || !a.samp)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sample, dim3((a.P + 63) / 64), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+
+}  // namespace rbsog

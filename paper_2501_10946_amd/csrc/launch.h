@@ -7,19 +7,22 @@
 
 #include <cstdint>
 
+#include "dev_math.h"
+
 namespace rbsog {
 
 constexpr int kBlock = 256;        // threads per workgroup of the streaming and pair kernels
-constexpr int kRhoChunk = 256;     // particles per structure-factor partial
+constexpr int kRhoChunkMax = 256;  // particles per structure-factor partial (at most)
 constexpr int kMaxGauss = 32;
 
 // SOG coefficients as the kernels need them.
 struct SogDev {
-    int n;                 // Gaussians
-    double inv_lambda;     // 1/lambda
-    double c[kMaxGauss];   // F(r) = sum c exp(-s r^2)
-    double s[kMaxGauss];
-    double cs2[kMaxGauss]; // 2 c s (force factor of the Gaussians)
+    int n;                      // Gaussians
+    double inv_lambda;          // 1/lambda
+    double inv_lambda_log2e;    // log2(e)/lambda: exp(-r/lambda) = 2^(-r log2(e)/lambda)
+    double c[kMaxGauss];        // F(r) = sum c exp(-s r^2)
+    double s_log2e[kMaxGauss];  // s log2(e): exp(-s r^2) = 2^(-s log2(e) r^2)
+    double cs2[kMaxGauss];      // 2 c s (force factor of the Gaussians)
 };
 
 // Geometry of the cell list.
@@ -42,7 +45,9 @@ struct CellArgs {
     int32_t *tmp;          // [N] unordered members per cell
     int32_t *order;        // [N] cell order -> original index
     double4 *xs;           // [N] (x, y, z, q) in cell order
+    int32_t *tile_sum;     // [scan_tiles(ncell)] scan workspace
 };
+int scan_tiles(int ncell);
 hipError_t launch_cell_ids(const CellArgs &a, hipStream_t st);      // zero counts, ids, counts
 hipError_t launch_cells_finish(const CellArgs &a, hipStream_t st);  // scan, scatter, stable rank + gather
 
@@ -79,7 +84,7 @@ hipError_t launch_sample(const SampleArgs &a, hipStream_t st);
 
 // --- structure factors -----------------------------------------------------------
 struct RhoArgs {
-    int N, P, nchunk;
+    int N, P, nchunk, chunk;   // chunk = particles per partial (64, 128 or 256)
     double inv_L;
     const double4 *xs;         // cell-ordered (x, y, z, q), or null to read x/q
     const double *x, *q;       // original-order SoA positions and charges
@@ -90,6 +95,7 @@ struct RhoArgs {
     double *eF;                // [P] coef |rho|^2 / 2
     double *rho_out;           // [P][2] or null
     int mixed;
+    SinCosPoly sc;
 };
 hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st);
 hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st);
@@ -103,9 +109,22 @@ struct NearArgs {
     const double4 *xs;         // cell order
     const int32_t *cell_start;
     double *fnear;             // SoA [3][N] in cell order
-    double *epart;             // [blocks] energy partials
+    double *epart;             // [near_blocks(N)] energy partials (when energy)
     int mixed;
+    int energy;
+    double w;                  // cell width L / nc (g is the fine grid, nc = floor(2L / r_c))
+    double margin;             // slack of the per-particle cell culling
+    double inv_L;
+    Exp2Poly e2;
+    int32_t *nbr;              // [kp][5][N] accepted j per (particle, plane), column-major
+    int32_t *nbr_cnt;          // [5][N] accepted count per (particle, plane)
+    int kp;                    // list capacity per (particle, plane)
 };
+hipError_t launch_nlist(const NearArgs &a, hipStream_t st);
+int near_blocks(int N);
+int far_blocks(int N);
+// Particles per structure-factor partial for a system of N particles and P samples.
+int rho_chunk(int N, int P);
 hipError_t launch_near(const NearArgs &a, hipStream_t st);
 
 // --- far field + assembly + second half-kick ---------------------------------------
@@ -122,9 +141,10 @@ struct FarArgs {
     double *v;                 // null, or velocities to kick (original order)
     const double *m;
     double half_dt;
-    double *kepart;            // [blocks] kinetic-energy partials (when v)
+    double *kepart;            // [far_blocks(N)] kinetic-energy partials (when v)
     int *flag;                 // set to 1 on a non-finite force
     int mixed;
+    SinCosPoly sc;
 };
 hipError_t launch_far(const FarArgs &a, hipStream_t st);
 

@@ -234,3 +234,17 @@ def test_nonfinite_flag(dev):
         R.rbsog_check(c.sys.h)
     assert ei.value.code == R.RBSOG_ENONFINITE
     R.rbsog_check(c.sys.h)  # the flag was cleared
+
+
+@pytest.mark.parametrize("cap", [1, 3])
+def test_neighbour_list_overflow(dev, cap, monkeypatch):
+    """With the neighbour-list capacity forced tiny, every lane overflows and
+    finishes its pairs by the second walk: forces and energies unchanged."""
+    monkeypatch.setenv("RBSOG_NEAR_CAPACITY", str(cap))
+    w = workloads.Workload("ragged_n2000_cap", N=2000, kappa=0.5, gamma=2.0, r_c=4.0, P=50, seed=21)
+    c = Case(dev, w)
+    for prec in (0,):
+        f, fn, e = c.forces(4)
+        fo, fno, eo = c.ref.force(c.st.x, 4)
+        assert rel(fn, fno) <= FP64_TOL and rel(f, fo) <= FP64_TOL
+        assert abs(e[0] - eo[0]) <= FP64_TOL * abs(eo[0])
