@@ -120,6 +120,11 @@ typedef struct rbsog_params {
     uint32_t replica;   /* Philox key word 1                                       */
     int precision;      /* RBSOG_FP64 or RBSOG_MIXED                               */
     int density;        /* RBSOG_ADAPTIVE, RBSOG_FLAT, RBSOG_K2 or RBSOG_DH4PI     */
+    double skin;        /* neighbour-list skin: lists hold pairs within r_c + skin
+                           and rbsog_step rebuilds them only when some particle
+                           has moved more than skin/2 since the last build; < 0 =
+                           default 0.1 r_c; capped so that L >= 3 (r_c + skin);
+                           0 = rebuild every step.  Results do not depend on it. */
 } rbsog_params;
 
 typedef struct rbsog_handle rbsog_handle;
@@ -134,6 +139,9 @@ typedef struct rbsog_info {
     double S;           /* normalisation of P(k) (eq. 3.124)                       */
     double Q1, Q2;      /* sum q, sum q^2                                          */
     size_t ws_bytes;    /* workspace bytes the system needs                        */
+    double skin;        /* neighbour-list skin in use                              */
+    int nf;             /* cells per axis of the force evaluation's fine grid      */
+    int near_capacity;  /* neighbour-list capacity per (particle, z-plane)         */
 } rbsog_info;
 
 /*

@@ -41,7 +41,8 @@ class rbsog_sog(C.Structure):
 
 class rbsog_params(C.Structure):
     _fields_ = [("N", C.c_int64), ("L", C.c_double), ("kT", C.c_double), ("P", C.c_int), ("mmax", C.c_int),
-                ("seed", C.c_uint64), ("replica", C.c_uint32), ("precision", C.c_int), ("density", C.c_int)]
+                ("seed", C.c_uint64), ("replica", C.c_uint32), ("precision", C.c_int), ("density", C.c_int),
+                ("skin", C.c_double)]
 
 
 RBSOG_NUM_KERNEL_CLASSES = 9
@@ -54,7 +55,8 @@ class rbsog_timing(C.Structure):
 
 class rbsog_info(C.Structure):
     _fields_ = [("N", C.c_int64), ("nc", C.c_int), ("mmax", C.c_int), ("nshell", C.c_int), ("nlat", C.c_int64),
-                ("S", C.c_double), ("Q1", C.c_double), ("Q2", C.c_double), ("ws_bytes", C.c_size_t)]
+                ("S", C.c_double), ("Q1", C.c_double), ("Q2", C.c_double), ("ws_bytes", C.c_size_t),
+                ("skin", C.c_double), ("nf", C.c_int), ("near_capacity", C.c_int)]
 
 
 _lib = None
@@ -145,9 +147,9 @@ def sog_from_parameters(lambda_: float, r_c: float, h: float, t0: float, w: floa
 
 
 def make_params(N: int, L: float, kT: float, P: int, seed: int, replica: int = 0, mmax: int = 0,
-                precision: int = RBSOG_FP64, density: int = RBSOG_ADAPTIVE) -> rbsog_params:
+                precision: int = RBSOG_FP64, density: int = RBSOG_ADAPTIVE, skin: float = -1.0) -> rbsog_params:
     return rbsog_params(N=N, L=L, kT=kT, P=P, mmax=mmax, seed=seed, replica=replica, precision=precision,
-                        density=density)
+                        density=density, skin=skin)
 
 
 def rbsog_workspace_size(params: rbsog_params, sog: rbsog_sog) -> int:
@@ -238,13 +240,14 @@ class System:
     handle; all work goes through the C-ABI on the current torch stream."""
 
     def __init__(self, q, m, L: float, sog: rbsog_sog, kT: float, P: int, seed: int, replica: int = 0,
-                 mmax: int = 0, precision: int = RBSOG_FP64, density: int = RBSOG_ADAPTIVE, device="cuda"):
+                 mmax: int = 0, precision: int = RBSOG_FP64, density: int = RBSOG_ADAPTIVE, skin: float = -1.0,
+                 device="cuda"):
         import torch
         self.q = torch.as_tensor(q, dtype=torch.float64, device=device).contiguous()
         self.m = torch.as_tensor(m, dtype=torch.float64, device=device).contiguous()
         self.N = self.q.numel()
         self.sog = sog
-        self.params = make_params(self.N, L, kT, P, seed, replica, mmax, precision, density)
+        self.params = make_params(self.N, L, kT, P, seed, replica, mmax, precision, density, skin)
         nbytes = rbsog_workspace_size(self.params, sog)
         self.ws = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device=device)
         self.h = rbsog_create(self.params, sog, self.q, self.m, self.ws)

@@ -2,11 +2,11 @@
 // layout, table upload and the per-evaluation launch sequence.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
-#include <cstdlib>
-#include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -27,15 +27,13 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Offsets of every buffer inside the workspace.
 struct Layout {
     size_t lattice, cdf, coef, first, size;
-    size_t cell_id, count, cell_start, fill, tmp, order, xs, tile_sum;
+    size_t cell_id, count, cell_start, fill, tmp, order, xs, tile_sum, xb;
     size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_cnt;
     size_t total;
 };
 
 int nchunks(int64_t N, int P) { return (int)((N + rho_chunk((int)N, P) - 1) / rho_chunk((int)N, P)); }
 
-// Cell grids: the coarse one (cells >= r_c, the cell list of rbsog_build_cells)
-// and the fine one the force evaluation uses (cells >= r_c / 2).
 CellGeom make_geom(double L, int nc)
 {
     CellGeom g{};
@@ -45,28 +43,55 @@ CellGeom make_geom(double L, int nc)
     g.inv_cell = (double)nc / L;
     return g;
 }
-int coarse_cells(double L, double rc) { return (int)std::floor(L / rc); }
-int fine_cells(double L, double rc) { return (int)std::floor(2.0 * L / rc); }
+
+// Sizes derived from the parameters, shared by rbsog_workspace_size and
+// rbsog_create.  Two cell grids: the coarse one (cells >= r_c), which is the
+// cell list of rbsog_build_cells, and the fine one of the force evaluation
+// (cells >= (r_c + skin)/2, a 5 x 5 x 5 stencil).
+struct Derived {
+    double skin, rl;   // neighbour-list skin and radius r_c + skin
+    int nc, nf;        // coarse and fine cells per axis
+    int mmax;
+    int64_t nlat;
+    int kp;            // neighbour-list capacity per (particle, plane)
+};
 
 // Capacity of each (particle, plane) neighbour list: 1.5x the expected count
-// of the fullest plane (a slab of width w through the particle's sphere) plus
-// 24; a lane that overflows is finished by a second walk, so this only sizes
+// of the fullest plane (a slab of width w through the list sphere) plus 24;
+// a lane that overflows walks its cells directly instead, so this only sizes
 // the fast path.  RBSOG_NEAR_CAPACITY overrides it (a tuning knob).
-int near_capacity(int64_t N, double L, double rc)
+int near_capacity(int64_t N, double L, double rl, int nf)
 {
     if (const char *e = std::getenv("RBSOG_NEAR_CAPACITY")) {
         int v = std::atoi(e);
         if (v >= 1 && v <= 4096) return v;
     }
     double n = (double)N / (L * L * L);
-    double w = L / std::floor(2.0 * L / rc);
-    double expected = n * kPi * rc * rc * w;
+    double w = L / (double)nf;
+    double expected = n * kPi * rl * rl * w;
     return std::min(4096, std::max(8, (int)std::ceil(1.5 * expected + 24.0)));
 }
 
-// ncell: cells of the fine grid (the larger one); kp: neighbour-list capacity
-Layout make_layout(int64_t N, int ncell, int64_t nlat, int nshell_max, int P, int kp)
+Derived derive(const rbsog_params *p, const rbsog_sog *s)
 {
+    Derived d{};
+    // default skin 0.1 r_c; never so large that the fine grid drops below 6 cells
+    double skin = p->skin < 0.0 ? 0.1 * s->r_c : p->skin;
+    skin = std::max(0.0, std::min(skin, p->L / 3.0 - s->r_c));
+    d.nc = (int)std::floor(p->L / s->r_c);
+    d.nf = std::max(6, (int)std::floor(2.0 * p->L / (s->r_c + skin)));
+    // the 5-cell stencil reaches 2 w = 2 L / nf: keep the list radius within it
+    d.rl = std::min(s->r_c + skin, 2.0 * p->L / (double)d.nf);
+    d.skin = std::max(0.0, d.rl - s->r_c);
+    d.mmax = p->mmax > 0 ? p->mmax : default_mmax(*s, p->L);
+    d.nlat = lattice_points(d.mmax);
+    d.kp = near_capacity(p->N, p->L, d.rl, d.nf);
+    return d;
+}
+
+Layout make_layout(int64_t N, const Derived &d, int P)
+{
+    int ncell = d.nf * d.nf * d.nf;  // the fine grid is the larger one
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -74,11 +99,11 @@ Layout make_layout(int64_t N, int ncell, int64_t nlat, int nshell_max, int P, in
         off = align_up(off + bytes);
         return o;
     };
-    L.lattice = take(sizeof(int32_t) * (size_t)nlat);
-    L.cdf = take(sizeof(double) * (size_t)nshell_max);
-    L.coef = take(sizeof(double) * (size_t)nshell_max);
-    L.first = take(sizeof(int32_t) * (size_t)nshell_max);
-    L.size = take(sizeof(int32_t) * (size_t)nshell_max);
+    L.lattice = take(sizeof(int32_t) * (size_t)d.nlat);
+    L.cdf = take(sizeof(double) * (size_t)d.mmax);
+    L.coef = take(sizeof(double) * (size_t)d.mmax);
+    L.first = take(sizeof(int32_t) * (size_t)d.mmax);
+    L.size = take(sizeof(int32_t) * (size_t)d.mmax);
     L.cell_id = take(sizeof(int32_t) * (size_t)N);
     L.count = take(sizeof(int32_t) * (size_t)ncell);
     L.cell_start = take(sizeof(int32_t) * ((size_t)ncell + 1));
@@ -87,6 +112,7 @@ Layout make_layout(int64_t N, int ncell, int64_t nlat, int nshell_max, int P, in
     L.order = take(sizeof(int32_t) * (size_t)N);
     L.xs = take(sizeof(double) * 4 * (size_t)N);
     L.tile_sum = take(sizeof(int32_t) * (size_t)scan_tiles(ncell));
+    L.xb = take(sizeof(double) * 3 * (size_t)N);
     L.samp = take(sizeof(double) * 4 * (size_t)P);
     L.part = take(sizeof(double) * 2 * (size_t)nchunks(N, P) * (size_t)P);
     L.rho = take(sizeof(double) * 2 * (size_t)P);
@@ -97,7 +123,7 @@ Layout make_layout(int64_t N, int ncell, int64_t nlat, int nshell_max, int P, in
     L.kepart = take(sizeof(double) * (size_t)far_blocks((int)N));
     L.flag = take(sizeof(int32_t) * 4);
     L.energy = take(sizeof(double) * 8);
-    L.nbr = take(sizeof(int32_t) * (size_t)kp * 5 * (size_t)N);
+    L.nbr = take(sizeof(int32_t) * (size_t)d.kp * 5 * (size_t)N);
     L.nbr_cnt = take(sizeof(int32_t) * 5 * (size_t)N);
     L.total = off;
     return L;
@@ -113,6 +139,7 @@ int check_params(const rbsog_params *p, const rbsog_sog *s)
     if (p->precision != RBSOG_FP64 && p->precision != RBSOG_MIXED) return fail(RBSOG_EINVAL, "unknown precision");
     if (p->density < RBSOG_ADAPTIVE || p->density > RBSOG_DH4PI) return fail(RBSOG_EINVAL, "unknown density");
     if (p->mmax < 0 || p->mmax > kMaxLatticeM) return fail(RBSOG_EINVAL, "mmax must lie in [0, %d]", kMaxLatticeM);
+    if (!std::isfinite(p->skin)) return fail(RBSOG_EINVAL, "skin must be finite");
     if (s->n < 1 || s->n > RBSOG_MAX_GAUSS || s->n != s->M1 + s->M2 + 1)
         return fail(RBSOG_EINVAL, "sog: inconsistent number of Gaussians");
     if (!(s->r_c > 0.0) || !(s->lambda > 0.0)) return fail(RBSOG_EINVAL, "sog: lambda and r_c must be positive");
@@ -123,9 +150,9 @@ int check_params(const rbsog_params *p, const rbsog_sog *s)
     return RBSOG_OK;
 }
 
-#define HIPCHECK(call)                                                                      \
-    do {                                                                                    \
-        hipError_t e_ = (call);                                                             \
+#define HIPCHECK(call)                                                                          \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
         if (e_ != hipSuccess) return fail(RBSOG_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
@@ -151,20 +178,22 @@ struct rbsog_handle {
     rbsog_sog sog;
     const double *q, *m;
     hipStream_t st;
+    Derived d;
     CellGeom g;   // coarse grid (rbsog_build_cells)
     CellGeom gf;  // fine grid (force evaluation)
-    Tables t;  // host copy (sizes; the vectors are released after upload)
-    double V, Q1, Q2, Uk0, Uself, Ubg;
+    int nshell;
+    double S, V, Q1, Q2, Uk0, Uself, Ubg;
     Layout lay;
     char *ws;
-    size_t ws_bytes;
     SogDev sd;
+    // views into the workspace
     int32_t *lattice, *first, *size, *cell_id, *count, *cell_start, *fill, *tmp, *order, *flag, *tile_sum;
-    double *cdf, *coef, *eF, *fnear, *epart, *kepart, *energy;
-    int32_t *nbr, *nbr_cnt;
-    int kp;
+    double *cdf, *coef, *eF, *fnear, *epart, *kepart, *energy, *xb;
     double4 *xs, *samp;
     double2 *part, *rho, *gk;
+    int32_t *nbr, *nbr_cnt;
+    int32_t *gate;       // device: rebuild the cell order and lists in this step
+    bool lists_valid;    // cell order and lists in the workspace belong to the fine grid
     // per-kernel event timing (rbsog_timing_enable)
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -218,7 +247,7 @@ hipError_t timed(rbsog_handle *h, int cls, F &&launch)
     return hipSuccess;
 }
 
-CellArgs cell_args(rbsog_handle *h, const double *x, const CellGeom &g)
+CellArgs cell_args(rbsog_handle *h, const double *x, const CellGeom &g, const int32_t *gate, double *xb)
 {
     CellArgs a{};
     a.N = (int)h->p.N;
@@ -233,7 +262,34 @@ CellArgs cell_args(rbsog_handle *h, const double *x, const CellGeom &g)
     a.order = h->order;
     a.xs = h->xs;
     a.tile_sum = h->tile_sum;
+    a.gate = gate;
+    a.xb = xb;
     return a;
+}
+
+NearArgs near_args(rbsog_handle *h, const int32_t *gate, bool energy)
+{
+    NearArgs na{};
+    na.N = (int)h->p.N;
+    na.g = h->gf;
+    na.w = h->p.L / (double)h->gf.nc;
+    na.margin = 1e-9 * h->p.L;
+    na.inv_L = 1.0 / h->p.L;
+    na.e2 = make_exp2_poly();
+    na.nbr = h->nbr;
+    na.nbr_cnt = h->nbr_cnt;
+    na.kp = h->d.kp;
+    na.rc2 = h->sog.r_c * h->sog.r_c;
+    na.rl2 = h->d.rl * h->d.rl;
+    na.gate = gate;
+    na.sog = h->sd;
+    na.xs = h->xs;
+    na.cell_start = h->cell_start;
+    na.fnear = h->fnear;
+    na.epart = h->epart;
+    na.mixed = h->p.precision == RBSOG_MIXED;
+    na.energy = energy;
+    return na;
 }
 
 SampleArgs sample_args(rbsog_handle *h, uint64_t step)
@@ -243,8 +299,8 @@ SampleArgs sample_args(rbsog_handle *h, uint64_t step)
     a.step = step;
     a.seed = h->p.seed;
     a.replica = h->p.replica;
-    a.nshell = h->t.nshell;
-    a.S = h->t.S;
+    a.nshell = h->nshell;
+    a.S = h->S;
     a.cdf = h->cdf;
     a.coef = h->coef;
     a.first = h->first;
@@ -273,8 +329,26 @@ RhoArgs rho_args(rbsog_handle *h)
     return a;
 }
 
+// Cell order + neighbour lists of the fine grid for positions x: always
+// (gate == null, a single evaluation) or only when the device gate is raised
+// (the step path, which then gathers xs from x in the current order and
+// clears the gate).
+int prepare(rbsog_handle *h, const double *x, const int32_t *gate)
+{
+    CellArgs ca = cell_args(h, x, h->gf, gate, h->xb);
+    HIPCHECK(timed(h, kCells, [&] { return launch_cell_build(ca, h->st); }));
+    NearArgs na = near_args(h, gate, false);
+    HIPCHECK(timed(h, kNlist, [&] { return launch_nlist(na, h->st); }));
+    if (gate) {
+        GatherArgs ga{(int)h->p.N, h->order, x, h->q, h->xs, h->gate};
+        HIPCHECK(timed(h, kCells, [&] { return launch_gather(ga, h->st); }));
+    }
+    h->lists_valid = true;
+    return RBSOG_OK;
+}
+
 // Sampling, structure factors, near field, far field (+ optional kick) and the
-// energy sums of one evaluation whose cell list is already built.
+// energy sums of one evaluation whose cell order and lists are prepared.
 int evaluate(rbsog_handle *h, uint64_t step, double *f, double *f_near, double *v, double dt, double *energy)
 {
     SampleArgs sa = sample_args(h, step);
@@ -282,25 +356,7 @@ int evaluate(rbsog_handle *h, uint64_t step, double *f, double *f_near, double *
     RhoArgs ra = rho_args(h);
     HIPCHECK(timed(h, kRhoPartial, [&] { return launch_rho_partial(ra, h->st); }));
     HIPCHECK(timed(h, kRhoReduce, [&] { return launch_rho_reduce(ra, h->st); }));
-    NearArgs na{};
-    na.N = (int)h->p.N;
-    na.g = h->gf;
-    na.w = h->p.L / (double)h->gf.nc;
-    na.margin = 1e-9 * h->p.L;
-    na.inv_L = 1.0 / h->p.L;
-    na.e2 = make_exp2_poly();
-    na.nbr = h->nbr;
-    na.nbr_cnt = h->nbr_cnt;
-    na.kp = h->kp;
-    na.rc2 = h->sog.r_c * h->sog.r_c;
-    na.sog = h->sd;
-    na.xs = h->xs;
-    na.cell_start = h->cell_start;
-    na.fnear = h->fnear;
-    na.epart = h->epart;
-    na.mixed = h->p.precision == RBSOG_MIXED;
-    na.energy = energy != nullptr;
-    HIPCHECK(timed(h, kNlist, [&] { return launch_nlist(na, h->st); }));
+    NearArgs na = near_args(h, nullptr, energy != nullptr);
     HIPCHECK(timed(h, kNear, [&] { return launch_near(na, h->st); }));
     FarArgs fa{};
     fa.N = (int)h->p.N;
@@ -348,9 +404,7 @@ extern "C" int rbsog_workspace_size(const rbsog_params *p, const rbsog_sog *s, s
     int rc = check_params(p, s);
     if (rc) return rc;
     if (!bytes) return fail(RBSOG_EINVAL, "bytes is null");
-    int mmax = p->mmax > 0 ? p->mmax : default_mmax(*s, p->L);
-    int nf = fine_cells(p->L, s->r_c);
-    *bytes = make_layout(p->N, nf * nf * nf, lattice_points(mmax), mmax, p->P, near_capacity(p->N, p->L, s->r_c)).total;
+    *bytes = make_layout(p->N, derive(p, s), p->P).total;
     return RBSOG_OK;
 }
 
@@ -368,9 +422,16 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     h->q = q_dev;
     h->m = m_dev;
     h->st = (hipStream_t)hip_stream;
-    h->g = make_geom(p->L, coarse_cells(p->L, s->r_c));
-    h->gf = make_geom(p->L, fine_cells(p->L, s->r_c));
+    h->d = derive(p, s);
+    h->g = make_geom(p->L, h->d.nc);
+    h->gf = make_geom(p->L, h->d.nf);
     h->V = p->L * p->L * p->L;
+    h->lay = make_layout(p->N, h->d, p->P);
+    if (ws_bytes < h->lay.total) {
+        size_t need = h->lay.total;
+        delete h;
+        return fail(RBSOG_EWORKSPACE, "workspace of %zu bytes is below the %zu needed", ws_bytes, need);
+    }
     // sum q and sum q^2 in particle order (they enter the measure, eq. 3.22)
     std::vector<double> qh((size_t)p->N);
     hipError_t e = hipMemcpyAsync(qh.data(), q_dev, sizeof(double) * (size_t)p->N, hipMemcpyDeviceToHost, h->st);
@@ -387,17 +448,11 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
         delete h;
         return fail(RBSOG_EINVAL, "all charges are zero");
     }
-    int mmax = p->mmax > 0 ? p->mmax : default_mmax(*s, p->L);
-    build_tables(*s, *p, q2, mmax, &h->t);
-    h->kp = near_capacity(p->N, p->L, s->r_c);
-    h->lay = make_layout(p->N, h->gf.ncell, h->t.nlat, mmax, p->P, h->kp);
-    if (ws_bytes < h->lay.total) {
-        size_t need = h->lay.total;
-        delete h;
-        return fail(RBSOG_EWORKSPACE, "workspace of %zu bytes is below the %zu needed", ws_bytes, need);
-    }
+    Tables t;
+    build_tables(*s, *p, q2, h->d.mmax, &t);
+    h->nshell = t.nshell;
+    h->S = t.S;
     h->ws = (char *)ws_dev;
-    h->ws_bytes = ws_bytes;
     char *w = h->ws;
     const Layout &L = h->lay;
     h->lattice = (int32_t *)(w + L.lattice);
@@ -413,6 +468,7 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     h->order = (int32_t *)(w + L.order);
     h->xs = (double4 *)(w + L.xs);
     h->tile_sum = (int32_t *)(w + L.tile_sum);
+    h->xb = (double *)(w + L.xb);
     h->samp = (double4 *)(w + L.samp);
     h->part = (double2 *)(w + L.part);
     h->rho = (double2 *)(w + L.rho);
@@ -422,26 +478,24 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     h->epart = (double *)(w + L.epart);
     h->kepart = (double *)(w + L.kepart);
     h->flag = (int32_t *)(w + L.flag);
+    h->gate = h->flag + 1;
     h->energy = (double *)(w + L.energy);
     h->nbr = (int32_t *)(w + L.nbr);
     h->nbr_cnt = (int32_t *)(w + L.nbr_cnt);
-    const Tables &t = h->t;
+    h->lists_valid = false;
     e = hipMemcpyAsync(h->lattice, t.packed.data(), sizeof(int32_t) * t.packed.size(), hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess) e = hipMemcpyAsync(h->cdf, t.cdf.data(), sizeof(double) * t.nshell, hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess) e = hipMemcpyAsync(h->coef, t.coef.data(), sizeof(double) * t.nshell, hipMemcpyHostToDevice, h->st);
-    if (e == hipSuccess) e = hipMemcpyAsync(h->first, t.shell_first.data(), sizeof(int32_t) * t.nshell, hipMemcpyHostToDevice, h->st);
-    if (e == hipSuccess) e = hipMemcpyAsync(h->size, t.shell_size.data(), sizeof(int32_t) * t.nshell, hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->first, t.shell_first.data(), sizeof(int32_t) * t.nshell, hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->size, t.shell_size.data(), sizeof(int32_t) * t.nshell, hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess) e = hipMemsetAsync(h->flag, 0, sizeof(int32_t) * 4, h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (e != hipSuccess) {
         delete h;
         return fail(RBSOG_EHIP, "uploading tables: %s", hipGetErrorString(e));
     }
-    // the host copies of the tables are no longer needed
-    h->t.packed = std::vector<int32_t>();
-    h->t.cdf = std::vector<double>();
-    h->t.shell_first = std::vector<int32_t>();
-    h->t.shell_size = std::vector<int32_t>();
     // kernel-side SOG and the constant energies (Section 4.1)
     const double log2e = 1.4426950408889634;
     h->sd.n = s->n;
@@ -464,24 +518,25 @@ extern "C" int rbsog_get_info(const rbsog_handle *h, rbsog_info *out)
     if (!h || !out) return fail(RBSOG_EINVAL, "null handle or out");
     out->N = h->p.N;
     out->nc = h->g.nc;
-    out->mmax = h->t.mmax;
-    out->nshell = h->t.nshell;
-    out->nlat = h->t.nlat;
-    out->S = h->t.S;
+    out->mmax = h->d.mmax;
+    out->nshell = h->nshell;
+    out->nlat = h->d.nlat;
+    out->S = h->S;
     out->Q1 = h->Q1;
     out->Q2 = h->Q2;
     out->ws_bytes = h->lay.total;
+    out->skin = h->d.skin;
+    out->nf = h->gf.nc;
+    out->near_capacity = h->d.kp;
     return RBSOG_OK;
 }
 
 extern "C" int rbsog_build_cells(rbsog_handle *h, const double *x_dev, int32_t *cell_start_dev, int32_t *order_dev)
 {
     if (!h || !x_dev) return fail(RBSOG_EINVAL, "null handle or x");
-    CellArgs a = cell_args(h, x_dev, h->g);
-    HIPCHECK(timed(h, kCells, [&] {
-        hipError_t e = launch_cell_ids(a, h->st);
-        return e == hipSuccess ? launch_cells_finish(a, h->st) : e;
-    }));
+    CellArgs a = cell_args(h, x_dev, h->g, nullptr, nullptr);
+    HIPCHECK(timed(h, kCells, [&] { return launch_cell_build(a, h->st); }));
+    h->lists_valid = false;  // the workspace now holds the coarse list
     if (cell_start_dev)
         HIPCHECK(hipMemcpyAsync(cell_start_dev, h->cell_start, sizeof(int32_t) * ((size_t)h->g.ncell + 1),
                                 hipMemcpyDeviceToDevice, h->st));
@@ -496,7 +551,7 @@ extern "C" int rbsog_sample_k(rbsog_handle *h, uint64_t step, int32_t *n_dev, do
     SampleArgs a = sample_args(h, step);
     a.n_out = n_dev;
     a.coef_out = coef_dev;
-    HIPCHECK(launch_sample(a, h->st));
+    HIPCHECK(timed(h, kSample, [&] { return launch_sample(a, h->st); }));
     return RBSOG_OK;
 }
 
@@ -519,11 +574,8 @@ extern "C" int rbsog_compute_forces(rbsog_handle *h, uint64_t step, const double
                                     double *f_near_dev, double *energy_dev)
 {
     if (!h || !x_dev || !f_dev) return fail(RBSOG_EINVAL, "null handle, x or f");
-    CellArgs a = cell_args(h, x_dev, h->gf);
-    HIPCHECK(timed(h, kCells, [&] {
-        hipError_t e = launch_cell_ids(a, h->st);
-        return e == hipSuccess ? launch_cells_finish(a, h->st) : e;
-    }));
+    int rc = prepare(h, x_dev, nullptr);
+    if (rc) return rc;
     return evaluate(h, step, f_dev, f_near_dev, nullptr, 0.0, energy_dev);
 }
 
@@ -534,22 +586,26 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
     if (nsteps < 0) return fail(RBSOG_EINVAL, "nsteps must be >= 0");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RBSOG_EINVAL, "dt must be positive and finite");
     for (int n = 0; n < nsteps; ++n) {
+        // force a rebuild when the workspace holds no lists of the fine grid
+        if (!h->lists_valid) HIPCHECK(launch_set_int(h->gate, 1, h->st));
         KickDriftArgs k{};
         k.N = (int)h->p.N;
-        k.g = h->gf;
+        k.L = h->p.L;
+        k.inv_L = 1.0 / h->p.L;
         k.dt = dt;
         k.x = x_dev;
         k.v = v_dev;
         k.f = f_dev;
         k.m = h->m;
-        k.cell_id = h->cell_id;
-        k.count = h->count;
+        k.xb = h->xb;
+        k.half_skin2 = 0.25 * h->d.skin * h->d.skin;
+        k.gate = h->gate;
         k.flag = h->flag;
         HIPCHECK(timed(h, kKickDrift, [&] { return launch_kick_drift(k, h->st); }));
-        CellArgs a = cell_args(h, x_dev, h->gf);
-        HIPCHECK(timed(h, kCells, [&] { return launch_cells_finish(a, h->st); }));
+        int rc = prepare(h, x_dev, h->gate);
+        if (rc) return rc;
         double *e = energy_hist_dev ? energy_hist_dev + 6 * (size_t)n : nullptr;
-        int rc = evaluate(h, step0 + (uint64_t)n + 1, f_dev, nullptr, v_dev, dt, e);
+        rc = evaluate(h, step0 + (uint64_t)n + 1, f_dev, nullptr, v_dev, dt, e);
         if (rc) return rc;
     }
     return RBSOG_OK;
@@ -562,7 +618,7 @@ extern "C" int rbsog_check(rbsog_handle *h)
     HIPCHECK(hipMemcpyAsync(&flag, h->flag, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
     HIPCHECK(hipStreamSynchronize(h->st));
     if (flag) {
-        HIPCHECK(hipMemsetAsync(h->flag, 0, sizeof(int32_t), h->st));
+        HIPCHECK(launch_set_int(h->flag, 0, h->st));
         HIPCHECK(hipStreamSynchronize(h->st));
         return fail(RBSOG_ENONFINITE, "non-finite force or over-long step detected");
     }

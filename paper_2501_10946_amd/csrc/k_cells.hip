@@ -1,18 +1,28 @@
-// gfx950 kernels of librbsog: cell list (counting sort with a stable rank) and the
-// first velocity-Verlet half step.
+// gfx950 kernels of librbsog: the cell list (a counting sort with a stable
+// rank), the gather of positions into list order, and the first
+// velocity-Verlet half step.
 //
 // Data layout in HBM: the caller's particle arrays stay FP64 SoA in the
-// caller's order; each evaluation builds a cell-ordered copy xs[N] of
-// (x, y, z, q) as double4 (32-byte rows) that the pair and far-field kernels
-// stream.
+// caller's order.  A build sorts the particles by cell into `order` and writes
+// a cell-ordered copy xs[N] of (x, y, z, q) as double4 (32-byte rows) that the
+// pair and far-field kernels stream; between builds the same order is reused
+// and only the positions are gathered again.
+//
+// Builds can be gated: every build kernel takes a device flag and returns at
+// once when it is zero, so the decision to rebuild (some particle moved more
+// than half the list skin) is taken on the device with no host round-trip.
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
 
 namespace rbsog {
 
-__global__ void k_zero_int(int32_t *p, int n)
+// A build kernel proceeds when it has no gate or its gate is raised.
+__device__ inline bool gate_open(const int32_t *gate) { return gate == nullptr || *gate != 0; }
+
+__global__ void k_zero_int(int32_t *p, int n, const int32_t *gate)
 {
+    if (!gate_open(gate)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
 }
@@ -20,7 +30,8 @@ __global__ void k_zero_int(int32_t *p, int n)
 hipError_t launch_zero_int(int32_t *p, int n, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_int, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, p, n);
+    hipLaunchKernelGGL(k_zero_int, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, p, n,
+                       (const int32_t *)nullptr);
     return hipGetLastError();
 }
 
@@ -30,6 +41,7 @@ hipError_t launch_zero_int(int32_t *p, int n, hipStream_t st)
 
 __global__ __launch_bounds__(kBlock) void k_cell_ids(CellArgs a)
 {
+    if (!gate_open(a.gate)) return;
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.N) return;
     int nc = a.g.nc;
@@ -66,6 +78,7 @@ __device__ inline int32_t block_exclusive_scan_256(int32_t v, int32_t *sh, int32
 
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(CellArgs a)
 {
+    if (!gate_open(a.gate)) return;
     __shared__ int32_t sh[kBlock];
     int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
     int32_t s = 0;
@@ -79,6 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(CellArgs a)
 
 __global__ __launch_bounds__(1024) void k_scan_top(CellArgs a, int ntiles)
 {
+    if (!gate_open(a.gate)) return;
     __shared__ int32_t sums[1024];
     int t = threadIdx.x;
     int per = (ntiles + 1023) / 1024;
@@ -103,6 +117,7 @@ __global__ __launch_bounds__(1024) void k_scan_top(CellArgs a, int ntiles)
 
 __global__ __launch_bounds__(kBlock) void k_scan_apply(CellArgs a)
 {
+    if (!gate_open(a.gate)) return;
     __shared__ int32_t sh[kBlock];
     int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
     int32_t c[kScanPer];
@@ -130,6 +145,7 @@ int scan_tiles(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
 // Unordered placement into each cell's segment.
 __global__ __launch_bounds__(kBlock) void k_scatter(CellArgs a)
 {
+    if (!gate_open(a.gate)) return;
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.N) return;
     int c = a.cell_id[i];
@@ -139,9 +155,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter(CellArgs a)
 
 // Stable position: a particle's rank within its cell is the number of cell
 // members with a smaller index, so ties keep ascending particle index whatever
-// order the scatter produced.  Gathers (x, y, z, q) into cell order.
+// order the scatter produced.  Gathers (x, y, z, q) into cell order and, when
+// asked, records the positions of the build.
 __global__ __launch_bounds__(kBlock) void k_rank(CellArgs a)
 {
+    if (!gate_open(a.gate)) return;
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.N) return;
     int c = a.cell_id[i];
@@ -149,8 +167,14 @@ __global__ __launch_bounds__(kBlock) void k_rank(CellArgs a)
     int r = 0;
     for (int k = b; k < e; ++k) r += (a.tmp[k] < i);
     int p = b + r;
+    double x = a.x[i], y = a.x[a.N + i], z = a.x[2 * a.N + i];
     a.order[p] = i;
-    a.xs[p] = make_double4(a.x[i], a.x[a.N + i], a.x[2 * a.N + i], a.q[i]);
+    a.xs[p] = make_double4(x, y, z, a.q[i]);
+    if (a.xb) {
+        a.xb[i] = x;
+        a.xb[a.N + i] = y;
+        a.xb[2 * a.N + i] = z;
+    }
 }
 
 static bool cell_args_ok(const CellArgs &a)
@@ -159,20 +183,14 @@ static bool cell_args_ok(const CellArgs &a)
            a.order && a.xs && a.tile_sum;
 }
 
-hipError_t launch_cell_ids(const CellArgs &a, hipStream_t st)
-{
-    if (!cell_args_ok(a)) return hipErrorInvalidValue;
-    hipError_t e = launch_zero_int(a.count, a.g.ncell, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cell_ids, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_cells_finish(const CellArgs &a, hipStream_t st)
+hipError_t launch_cell_build(const CellArgs &a, hipStream_t st)
 {
     if (!cell_args_ok(a)) return hipErrorInvalidValue;
     int grid = (a.N + kBlock - 1) / kBlock;
     int nt = scan_tiles(a.g.ncell);
+    hipLaunchKernelGGL(k_zero_int, dim3((a.g.ncell + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a.count, a.g.ncell,
+                       a.gate);
+    hipLaunchKernelGGL(k_cell_ids, dim3(grid), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, a, nt);
     hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kBlock), 0, st, a);
@@ -182,16 +200,39 @@ hipError_t launch_cells_finish(const CellArgs &a, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-// first half-kick + drift + wrap, fused with the cell ids of the new positions
+// gather of the current positions into the order of the last build; clears
+// the rebuild gate once everything that reads it has run
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
+{
+    int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < a.N) {
+        int i = a.order[p];
+        a.xs[p] = make_double4(a.x[i], a.x[a.N + i], a.x[2 * a.N + i], a.q[i]);
+    }
+    if (a.gate && p == 0) *a.gate = 0;
+}
+
+hipError_t launch_gather(const GatherArgs &a, hipStream_t st)
+{
+    if (a.N < 1 || !a.order || !a.x || !a.q || !a.xs) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gather, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// first half-kick + drift + wrap; raises the rebuild gate when a particle has
+// moved more than half the skin since the last build
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_kick_drift(KickDriftArgs a)
 {
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.N) return;
-    double L = a.g.L;
+    const double L = a.L;
     double hm = (0.5 * a.dt) / a.m[i];
-    int cc[3];
+    double d2 = 0.0;
     bool bad = false;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -204,22 +245,28 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(KickDriftArgs a)
         if (xx >= L) xx = 0.0;
         a.v[d * a.N + i] = vv;
         a.x[d * a.N + i] = xx;
-        cc[d] = cell_coord(xx, a.g.inv_cell, a.g.nc);
+        double s = xx - a.xb[d * a.N + i];
+        s = fma(-L, rint(s * a.inv_L), s);
+        d2 = fma(s, s, d2);
     }
     if (bad) atomicOr(a.flag, 1);
-    int id = (cc[2] * a.g.nc + cc[1]) * a.g.nc + cc[0];
-    a.cell_id[i] = id;
-    atomicAdd(&a.count[id], 1);
+    if (!(d2 <= a.half_skin2)) atomicOr(a.gate, 1);
 }
 
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t st)
 {
-    if (a.N < 1 || !a.x || !a.v || !a.f || !a.m || !a.cell_id || !a.count || !a.flag) return hipErrorInvalidValue;
-    hipError_t e = launch_zero_int(a.count, a.g.ncell, st);
-    if (e != hipSuccess) return e;
+    if (a.N < 1 || !a.x || !a.v || !a.f || !a.m || !a.xb || !a.gate || !a.flag) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_kick_drift, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 
+__global__ void k_set_int(int32_t *p, int32_t v) { *p = v; }
+
+hipError_t launch_set_int(int32_t *p, int32_t v, hipStream_t st)
+{
+    if (!p) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, p, v);
+    return hipGetLastError();
+}
 
 }  // namespace rbsog

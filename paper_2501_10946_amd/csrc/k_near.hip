@@ -14,9 +14,14 @@
 //   k_nlist  walks the candidates (four loads in flight per lane) and stores the
 //            accepted j of each lane, in candidate order, into a column-major
 //            list of capacity kp per lane, plus the lane's total count;
-//   k_near   evaluates the pair function on the lists (every lane busy on
-//            accepted pairs only).  A lane whose count exceeds kp walks its
-//            candidates again and evaluates the ones beyond the first kp.
+//   k_near   evaluates the pair function on the lists.  A lane whose count
+//            exceeded kp at the build walks the candidates of the current
+//            positions instead.
+//
+// Lists hold every j within r_c + skin at the build.  The step path rebuilds
+// them (and the cell order) only when some particle has moved more than
+// skin / 2 since the last build, so every pair within r_c is listed; pairs
+// listed but now beyond r_c are skipped in the evaluation.
 //
 // Each lane sums its (particle, plane) force in candidate order and the five
 // planes are added in a fixed order: the result is deterministic.
@@ -79,14 +84,16 @@ __device__ inline Lane make_lane(const NearArgs &a, int p, int plane)
     return l;
 }
 
-// The candidate ranges of row `row` (dy = row - 2) for a lane: 0, 1 or 2.
-__device__ inline int row_ranges(const NearArgs &a, const Lane &l, int row, Range out[2])
+// The candidate ranges of row `row` (dy = row - 2) for a lane within radius
+// sqrt(R2) (R2 <= the list radius squared, which the fine grid is built for):
+// 0, 1 or 2 ranges.
+__device__ inline int row_ranges(const NearArgs &a, const Lane &l, int row, double R2, Range out[2])
 {
     const int nf = a.g.nc;
     const double w = a.w, m = a.margin;
     int cyu = l.cy + row - 2;
     double gy = slab_gap(l.pi.y, cyu, w, m);
-    double rem = a.rc2 - gy * gy - l.gz * l.gz;
+    double rem = R2 - gy * gy - l.gz * l.gz;
     if (!(rem > 0.0)) return 0;
     int dxlo = -2, dxhi = 2;
     for (int k = 0; k < 2; ++k) {   // at most two x-cells per side can be culled
@@ -133,12 +140,12 @@ __device__ inline Cursor open_range(const Range &g, const double4 &pi, double L)
     return c;
 }
 
-// The acceptance test shared by the list build and the overflow walk.
-__device__ inline bool accept(const NearArgs &a, const Cursor &c, const double4 &q, int j, int p)
+// The acceptance test of a candidate within radius sqrt(R2).
+__device__ inline bool accept(const Cursor &c, const double4 &q, int j, int p, double R2)
 {
     double dx = c.bx - q.x, dy = c.by - q.y, dz = c.bz - q.z;
     double r2 = dx * dx + dy * dy + dz * dz;
-    return r2 < a.rc2 && j != p;
+    return r2 < R2 && j != p;
 }
 
 // FP64 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps.
@@ -164,6 +171,7 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, int j, d
     dy = fma(-L, rint(dy * a.inv_L), dy);
     dz = fma(-L, rint(dz * a.inv_L), dz);
     double r2 = dx * dx + dy * dy + dz * dz;
+    if (!(r2 < a.rc2)) return;   // listed within r_c + skin, beyond r_c now
     double qq = pi.w * pj.w;
     if (MIXED) {
         float r2f = (float)r2;
@@ -207,6 +215,7 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, int j, d
 
 __global__ __launch_bounds__(kNearThreads) void k_nlist(NearArgs a)
 {
+    if (a.gate && *a.gate == 0) return;
     __shared__ Range rng[kMaxRanges][kNearThreads];
     __shared__ int32_t stage[kStage][kNearThreads];
     const int t = threadIdx.x;
@@ -214,10 +223,10 @@ __global__ __launch_bounds__(kNearThreads) void k_nlist(NearArgs a)
     const int p = xcd_block(blockIdx.x, gridDim.x) * 64 + (t & 63);
     const Lane l = make_lane(a, p, plane);
     int nr = 0;
-    if (p < a.N && l.gz * l.gz < a.rc2) {
+    if (p < a.N && l.gz * l.gz < a.rl2) {
         for (int row = 0; row < 5; ++row) {
             Range g[2];
-            int n = row_ranges(a, l, row, g);
+            int n = row_ranges(a, l, row, a.rl2, g);
             for (int k = 0; k < n; ++k) rng[nr++][t] = g[k];
         }
     }
@@ -239,10 +248,10 @@ __global__ __launch_bounds__(kNearThreads) void k_nlist(NearArgs a)
             double4 q1 = a.xs[min(c.j + 1, last)];
             double4 q2 = a.xs[min(c.j + 2, last)];
             double4 q3 = a.xs[min(c.j + 3, last)];
-            if (accept(a, c, q0, c.j, p)) stage[cnt++][t] = c.j;
-            if (n > 1 && accept(a, c, q1, c.j + 1, p)) stage[cnt++][t] = c.j + 1;
-            if (n > 2 && accept(a, c, q2, c.j + 2, p)) stage[cnt++][t] = c.j + 2;
-            if (n > 3 && accept(a, c, q3, c.j + 3, p)) stage[cnt++][t] = c.j + 3;
+            if (accept(c, q0, c.j, p, a.rl2)) stage[cnt++][t] = c.j;
+            if (n > 1 && accept(c, q1, c.j + 1, p, a.rl2)) stage[cnt++][t] = c.j + 1;
+            if (n > 2 && accept(c, q2, c.j + 2, p, a.rl2)) stage[cnt++][t] = c.j + 2;
+            if (n > 3 && accept(c, q3, c.j + 3, p, a.rl2)) stage[cnt++][t] = c.j + 3;
             c.j += n;
         }
         for (int k = 0; k < cnt; ++k)
@@ -271,21 +280,24 @@ __global__ __launch_bounds__(kNearThreads) void k_near(NearArgs a)
         cnt = a.nbr_cnt[(size_t)plane * a.N + p];
     }
     const int32_t *in = a.nbr + (size_t)plane * a.N + p;
-    const int m = min(cnt, a.kp);
     double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0;
-    for (int k = 0; k < m; ++k) pair_force<MIXED, ENERGY>(a, pi, in[(size_t)k * stride], fx, fy, fz, en);
-    if (cnt > a.kp) {
-        // overflow: walk the candidates again, evaluate the accepted beyond kp
+    if (cnt <= a.kp) {
+        for (int k = 0; k < cnt; ++k) pair_force<MIXED, ENERGY>(a, pi, in[(size_t)k * stride], fx, fy, fz, en);
+    } else {
+        // the list of this lane overflowed at the build: walk the cells around
+        // the current position directly.  Particles may have moved up to
+        // skin/2 out of the cells they were sorted into (and wrapped around the
+        // box), so the cells are culled with the list radius and the pair
+        // function itself (minimum image, r < r_c) decides.
         const Lane l = make_lane(a, p, plane);
-        int seen = 0;
-        for (int row = 0; row < 5; ++row) {
-            Range g[2];
-            int n = row_ranges(a, l, row, g);
-            for (int k = 0; k < n; ++k) {
-                Cursor c = open_range(g[k], pi, a.g.L);
-                for (; c.j < c.jend; ++c.j) {
-                    if (!accept(a, c, a.xs[c.j], c.j, p)) continue;
-                    if (seen++ >= a.kp) pair_force<MIXED, ENERGY>(a, pi, c.j, fx, fy, fz, en);
+        if (l.gz * l.gz < a.rl2) {
+            for (int row = 0; row < 5; ++row) {
+                Range g[2];
+                int n = row_ranges(a, l, row, a.rl2, g);
+                for (int k = 0; k < n; ++k) {
+                    int j0 = g[k].start_code & (int32_t)kIndexMask;
+                    for (int j = j0; j < g[k].end; ++j)
+                        if (j != p) pair_force<MIXED, ENERGY>(a, pi, j, fx, fy, fz, en);
                 }
             }
         }
@@ -331,7 +343,7 @@ int near_blocks(int N) { return (N + 63) / 64; }
 static bool near_args_ok(const NearArgs &a)
 {
     return a.N >= 1 && a.xs && a.cell_start && a.nbr && a.nbr_cnt && a.fnear && a.kp >= 1 && a.g.nc >= 6 &&
-           a.rc2 > 0.0 && a.w > 0.0 && (!a.energy || a.epart);
+           a.rc2 > 0.0 && a.rl2 >= a.rc2 && a.w > 0.0 && (!a.energy || a.epart);
 }
 
 hipError_t launch_nlist(const NearArgs &a, hipStream_t st)

@@ -46,20 +46,33 @@ struct CellArgs {
     int32_t *order;        // [N] cell order -> original index
     double4 *xs;           // [N] (x, y, z, q) in cell order
     int32_t *tile_sum;     // [scan_tiles(ncell)] scan workspace
+    const int32_t *gate;   // null: always build; else build only when *gate != 0
+    double *xb;            // null, or SoA [3][N] positions recorded at the build
 };
 int scan_tiles(int ncell);
-hipError_t launch_cell_ids(const CellArgs &a, hipStream_t st);      // zero counts, ids, counts
-hipError_t launch_cells_finish(const CellArgs &a, hipStream_t st);  // scan, scatter, stable rank + gather
+// zero counts, ids + counts, scan, scatter, stable rank + gather
+hipError_t launch_cell_build(const CellArgs &a, hipStream_t st);
+
+struct GatherArgs {
+    int N;
+    const int32_t *order;
+    const double *x, *q;
+    double4 *xs;
+    int32_t *gate;         // cleared (if not null) after the gather
+};
+hipError_t launch_gather(const GatherArgs &a, hipStream_t st);
+hipError_t launch_set_int(int32_t *p, int32_t v, hipStream_t st);
 
 // --- integration ------------------------------------------------------------
 struct KickDriftArgs {
     int N;
-    CellGeom g;
-    double dt;
+    double L, inv_L, dt;
     double *x, *v;         // SoA [3][N], original order, updated in place
     const double *f;       // SoA [3][N]
     const double *m;       // [N]
-    int32_t *cell_id, *count;
+    const double *xb;      // SoA [3][N] positions at the last list build
+    double half_skin2;     // (skin / 2)^2
+    int32_t *gate;         // raised when a particle moved more than skin / 2 since the build
     int *flag;             // set to 1 on a step of a box length or more
 };
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t st);
@@ -116,9 +129,11 @@ struct NearArgs {
     double margin;             // slack of the per-particle cell culling
     double inv_L;
     Exp2Poly e2;
-    int32_t *nbr;              // [kp][5][N] accepted j per (particle, plane), column-major
-    int32_t *nbr_cnt;          // [5][N] accepted count per (particle, plane)
+    int32_t *nbr;              // [kp][5][N] listed j per (particle, plane), column-major
+    int32_t *nbr_cnt;          // [5][N] listed count per (particle, plane)
     int kp;                    // list capacity per (particle, plane)
+    double rl2;                // squared list radius (r_c + skin)^2; the fine grid has cells >= (r_c + skin)/2
+    const int32_t *gate;       // list build: null = always, else only when *gate != 0
 };
 hipError_t launch_nlist(const NearArgs &a, hipStream_t st);
 int near_blocks(int N);

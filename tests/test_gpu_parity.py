@@ -248,3 +248,29 @@ def test_neighbour_list_overflow(dev, cap, monkeypatch):
         fo, fno, eo = c.ref.force(c.st.x, 4)
         assert rel(fn, fno) <= FP64_TOL and rel(f, fo) <= FP64_TOL
         assert abs(e[0] - eo[0]) <= FP64_TOL * abs(eo[0])
+
+
+@pytest.mark.parametrize("skin", [0.0, 0.3, 1.5])
+def test_trajectory_independent_of_skin(dev, skin):
+    """The neighbour-list skin changes only when lists are rebuilt: 60 steps of
+    the small plasma give the oracle's trajectory (1e-10) for any skin,
+    including rebuilding every step (0) and rarely (1.5)."""
+    w = workloads.OCP_1K
+    st = workloads.make_state(w)
+    o = oracle.sog_auto(w.lam, w.r_c, w.eps)
+    sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+    s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, skin=skin, device=dev)
+    assert abs(s.info.skin - skin) <= 1e-12
+    x = torch.tensor(st.x, device=dev)
+    v = torch.tensor(st.v, device=dev)
+    f = torch.empty_like(x)
+    R.rbsog_compute_forces(s.h, 0, x, f)
+    R.rbsog_step(s.h, x, v, f, 0, 60, w.dt)
+    R.rbsog_check(s.h)
+    ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
+    xo, vo = st.x.copy(), st.v.copy()
+    fo, _, _ = ref.force(xo, 0)
+    ref.run(xo, vo, fo, 0, 60, w.dt)
+    d = x.cpu().numpy() - xo
+    d -= w.L * np.round(d / w.L)
+    assert np.abs(d).max() <= 1e-10
