@@ -32,17 +32,48 @@ PEAK_FP64_TFLOPS = 78.6      # 256 CU x 2.4 GHz x 64 FP64 FMA lanes x 2
 PEAK_FP32_TFLOPS = 157.3     # published FP32 vector peak (packed FP32)
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FP64 flops per unit of work (FMA = 2); derivations in the design doc.
-FLOPS_SINCOS = 40            # revolution reduction + sin and cos polynomials on [-1/8, 1/8] rev
-FLOPS_EXP = 28               # ln2 reduction + degree-11 polynomial + scale
-FLOPS_FAR_PER_IK = 6 + FLOPS_SINCOS + 3 + 6          # phase, sincos, Im(e^{-ikr} rho) coef, 3 FMA
-FLOPS_RHO_PER_IK = 6 + FLOPS_SINCOS + 4              # phase, sincos, 2 FMA
+# Algorithmic FP64 flops per unit of work (FMA = 2; the elementary functions count
+# their own operations: exp2 29, revolution sincos 40); derivations in the design notes.
+FLOPS_SINCOS = 40
+FLOPS_EXP2 = 29
+FLOPS_FAR_PER_IK = 5 + FLOPS_SINCOS + 3 + 6          # phase, sincos, Im(e^{-ikr} rho) coef, 3 FMA
+FLOPS_RHO_PER_IK = 5 + FLOPS_SINCOS + 4              # phase, sincos, 2 FMA
 
 
 def flops_near_per_pair(n_gauss: int) -> int:
-    # sqrt + reciprocal (16), exp(-r/lambda) (1 + 28), F_N1 (6),
-    # per Gaussian exp + 2 FMA (29 + 4), force 3 FMA (6), energy (4)
-    return 16 + 29 + 6 + n_gauss * 33 + 6 + 4
+    # minimum image 15, r^2 5, cutoff test 1, qq 1, rsqrt 12, r 1, exp(-r/lambda) 1 + 29,
+    # F_N1 6, per Gaussian (1 + 29 + 2), factor 2, force 3 FMA 6
+    return 15 + 5 + 1 + 1 + 12 + 1 + (1 + FLOPS_EXP2) + 6 + n_gauss * (1 + FLOPS_EXP2 + 2) + 2 + 6
+
+
+# HBM bytes per launch of a kernel, from one FETCH_SIZE and one WRITE_SIZE counter
+# run (KiB per dispatch), each scaled by what the same counter reads for an FP64
+# copy of known size.  A figure holds only for the kernel sources it was taken
+# on: it is reported when the SHA-256 over the library sources still matches.
+MEASURED_TRAFFIC = {
+    # kernel: (sources sha256, FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale)
+    "near": ("d6f7651eb403ffcb4ad790f29809178290b09f89aa0eda4d197c07fc71e65e34",
+             31350.0875, 2343.75, 262144 / 131086.6458, 262144 / 262146.9167),
+}
+
+
+def sources_sha256() -> str:
+    import hashlib
+    d = os.path.join(ROOT, "paper_2501_10946_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    t = MEASURED_TRAFFIC.get(kernel)
+    if t is None or t[0] != sources_sha256():
+        return None
+    return (t[1] * t[3] + t[2] * t[4]) * 1024.0
 
 
 def log(*a):
@@ -65,6 +96,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget for the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--copy-calibration", type=float, default=0.0,
+                    help="MiB of an elementwise FP64 copy (y = 2x) to run first, as a known-traffic reference "
+                         "for hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (see the design notes on sharding); "
@@ -79,6 +113,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * 2 ** 20 / 8)
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            b = a * 2.0
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {n * 8} bytes read and written per launch")
+        del a, b
     w = workloads.OCP_100K
     st = workloads.make_state(w)
     sog = R.rbsog_sog_init(w.lam, w.r_c, w.eps)
@@ -173,7 +215,7 @@ def main():
         if dom in work:
             achieved = work[dom] / (ms * 1e-3) / 1e12
             roofline = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(dom),
                         "ms_per_launch": ms, "flops_per_launch": work[dom]}
         log(f"[bench] kernels (fp64): " + ", ".join(f"{k} {v['ms_per_launch']:.4f} ms" for k, v in kern.items()))
         log(f"[bench] near pairs {npairs} ({npairs / w.N:.1f} per particle)")
@@ -189,7 +231,7 @@ def main():
         t0 = time.perf_counter()
         ref.run(xo, vo, fo, step_eq, 1, w.dt)
         t1 = time.perf_counter() - t0
-        k = max(1, min(100, int(args.cpu_seconds / max(t1, 1e-6)) - 1))
+        k = max(1, min(1000, int(args.cpu_seconds / max(t1, 1e-6)) - 1))
         t0 = time.perf_counter()
         ref.run(xo, vo, fo, step_eq + 1, k, w.dt)
         tk = time.perf_counter() - t0 + t1
