@@ -118,13 +118,13 @@ Layout make_layout(int64_t N, const Derived &d, int P)
     L.rho = take(sizeof(double) * 2 * (size_t)P);
     L.gk = take(sizeof(double) * 2 * (size_t)P);
     L.eF = take(sizeof(double) * (size_t)P);
-    L.fnear = take(sizeof(double) * 3 * (size_t)N);
+    L.fnear = take(sizeof(double) * 15 * (size_t)N);
     L.epart = take(sizeof(double) * (size_t)near_blocks((int)N));
     L.kepart = take(sizeof(double) * (size_t)far_blocks((int)N));
     L.flag = take(sizeof(int32_t) * 4);
     L.energy = take(sizeof(double) * 8);
     L.nbr = take(sizeof(int32_t) * (size_t)d.kp * 5 * (size_t)N);
-    L.nbr_cnt = take(sizeof(int32_t) * 5 * (size_t)N);
+    L.nbr_cnt = take(sizeof(int32_t) * (size_t)N);
     L.total = off;
     return L;
 }

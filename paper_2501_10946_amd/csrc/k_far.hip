@@ -75,7 +75,15 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs a)
             bz += part[2][k * 64 + t];
         }
         double sc = -pi.w * a.two_pi_over_L;
-        double fnx = a.fnear[p], fny = a.fnear[a.N + p], fnz = a.fnear[2 * a.N + p];
+        // near field: the five lane partials, added in lane order
+        double fnx = 0.0, fny = 0.0, fnz = 0.0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const double *pl = a.fnear + (size_t)k * 3 * a.N + p;
+            fnx += pl[0];
+            fny += pl[a.N];
+            fnz += pl[2 * (size_t)a.N];
+        }
         double fx = fnx + sc * bx, fy = fny + sc * by, fz = fnz + sc * bz;
         int i = a.order[p];
         a.f[i] = fx;

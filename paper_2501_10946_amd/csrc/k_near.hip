@@ -3,36 +3,48 @@
 //   F_N1 = exp(-r/lambda)(1 + r/lambda)/r^3,  F_N2 = -2 sum_g c_g s_g exp(-s_g r^2),
 // and the near energy U_N = 1/2 sum q_i q_j (Y(r) - F(r)).
 //
-// Two kernels.  The cell grid is the fine one, cells of width
-// w = L / floor(2L / r_c) >= r_c / 2, so the neighbour stencil is 5 x 5 x 5
-// cells; cell order makes each x-row of 5 cells one contiguous index range (two
-// where it wraps around the box).  Work is split into (particle, plane) lanes:
-// a workgroup owns 64 consecutive particles (cell order) and has 5 waves, wave
-// dz (= -2..2) handling the z-plane dz of each particle.  Rows and x-cells whose
-// distance from the particle already exceeds r_c are skipped per particle.
+// The cell grid is the fine one, cells of width w = L / floor(2L / (r_c + skin))
+// >= (r_c + skin) / 2, so the neighbour stencil is 5 x 5 x 5 cells; cell order
+// makes each x-row of 5 cells one contiguous index range (two where it wraps
+// around the box).  Work is split into (particle, plane) lanes, plane dz =
+// -2..2 of the stencil; rows and x-cells whose distance from the particle
+// already exceeds the list radius are skipped per particle.
 //
-//   k_nlist  walks the candidates (four loads in flight per lane) and stores the
-//            accepted j of each lane, in candidate order, into a column-major
-//            list of capacity kp per lane, plus the lane's total count;
-//   k_near   evaluates the pair function on the lists.  A lane whose count
-//            exceeded kp at the build walks the candidates of the current
-//            positions instead.
+//   k_nlist  a workgroup owns 64 consecutive particles (cell order) and has 5
+//            waves, one per plane; each lane walks its candidates (four loads
+//            in flight) and stores the accepted j, in candidate order, in rows
+//            of its plane (capacity kp per plane); the five planes of each
+//            particle are then moved together into one column-major list of
+//            the particle's neighbours, plus its count;
+//   k_near   a workgroup owns 256 consecutive particles and one of five lanes
+//            per particle (4 waves); lane s evaluates entries s, s + 5, ... of
+//            the particle's list, so the five lanes get equal shares (a split
+//            by plane would not: the outer planes hold 0 to ~17 entries
+//            depending on where the particle sits in its cell).  Each lane
+//            runs down its entries with the next index and the next neighbour
+//            position already in flight, and stores its partial force; the
+//            far-field kernel adds the five partials in lane order.  The
+//            number of Gaussians is a template parameter for the common
+//            counts, so their coefficients stay in scalar registers.  When a
+//            plane of a particle overflowed kp at the build, its lanes walk
+//            the candidates of the current positions, one plane each.
 //
 // Lists hold every j within r_c + skin at the build.  The step path rebuilds
 // them (and the cell order) only when some particle has moved more than
 // skin / 2 since the last build, so every pair within r_c is listed; pairs
 // listed but now beyond r_c are skipped in the evaluation.
 //
-// Each lane sums its (particle, plane) force in candidate order and the five
-// planes are added in a fixed order: the result is deterministic.
+// Each lane sums its share of a particle's force in list order and the five
+// shares are added in a fixed order: the result is deterministic.
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
 
 namespace rbsog {
 
-constexpr int kNearPlanes = 5;                 // waves per workgroup, one per dz
-constexpr int kNearThreads = 64 * kNearPlanes;
+constexpr int kNearPlanes = 5;                 // stencil planes dz = -2..2
+constexpr int kNearThreads = 64 * kNearPlanes; // list build: 64 particles x 5 planes
+constexpr int kEvalThreads = 256;              // evaluation: 256 particles x 1 plane
 constexpr int kStage = 8;                      // accepted entries staged per lane before storing
 constexpr int kShiftBits = 5;                  // image-shift code 0..26 in the top bits of a range start
 constexpr uint32_t kIndexMask = (1u << (32 - kShiftBits)) - 1u;
@@ -159,12 +171,16 @@ __device__ inline double rsqrt_f64(double x)
     return fma(y, e, y);
 }
 
-template <bool MIXED, bool ENERGY>
-__device__ inline void pair_force(const NearArgs &a, const double4 &pi, int j, double &fx, double &fy, double &fz,
-                                  double &en)
+// Gaussians of the pair function: NG > 0 is a compile-time count, 0 the
+// run-time count of the argument block.
+template <int NG>
+__device__ inline int gauss_count(const NearArgs &a) { return NG > 0 ? NG : a.sog.n; }
+
+template <bool MIXED, bool ENERGY, int NG>
+__device__ inline void pair_force(const NearArgs &a, const double4 &pi, const double4 &pj, double &fx, double &fy,
+                                  double &fz, double &en)
 {
     const double L = a.g.L;
-    double4 pj = a.xs[j];
     // d by the minimum image (|d| < r_c <= L/3)
     double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
     dx = fma(-L, rint(dx * a.inv_L), dx);
@@ -180,7 +196,8 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, int j, d
         float ey = __builtin_amdgcn_exp2f(-rf * (float)a.sog.inv_lambda_log2e);
         float f1 = ey * (1.0f + rf * (float)a.sog.inv_lambda) * (irf * irf * irf);
         float gs = 0.0f, fs = 0.0f;
-        for (int g = 0; g < a.sog.n; ++g) {
+#pragma unroll
+        for (int g = 0; g < gauss_count<NG>(a); ++g) {
             float eg = __builtin_amdgcn_exp2f(-(float)a.sog.s_log2e[g] * r2f);
             gs = fmaf((float)a.sog.cs2[g], eg, gs);
             if (ENERGY) fs = fmaf((float)a.sog.c[g], eg, fs);
@@ -196,7 +213,8 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, int j, d
         double ey = exp2_nonpos(-r * a.sog.inv_lambda_log2e, a.e2);
         double f1 = ey * fma(r, a.sog.inv_lambda, 1.0) * (ir * ir * ir);
         double gs = 0.0, fs = 0.0;
-        for (int g = 0; g < a.sog.n; ++g) {
+#pragma unroll
+        for (int g = 0; g < gauss_count<NG>(a); ++g) {
             double eg = exp2_nonpos(-a.sog.s_log2e[g] * r2, a.e2);
             gs = fma(a.sog.cs2[g], eg, gs);
             if (ENERGY) fs = fma(a.sog.c[g], eg, fs);
@@ -230,8 +248,9 @@ __global__ __launch_bounds__(kNearThreads) void k_nlist(NearArgs a)
             for (int k = 0; k < n; ++k) rng[nr++][t] = g[k];
         }
     }
-    const size_t stride = (size_t)kNearPlanes * (size_t)a.N;
-    int32_t *out = a.nbr + (size_t)plane * a.N + p;
+    // plane `plane` of particle p is stored first in rows plane*kp .. plane*kp + kp - 1
+    const size_t N = (size_t)a.N;
+    int32_t *out = a.nbr + (size_t)plane * a.kp * N + p;
     int r = 0, total = 0;
     Cursor c{0, 0, 0.0, 0.0, 0.0};
     if (nr > 0) c = open_range(rng[0][t], l.pi, a.g.L);
@@ -255,37 +274,91 @@ __global__ __launch_bounds__(kNearThreads) void k_nlist(NearArgs a)
             c.j += n;
         }
         for (int k = 0; k < cnt; ++k)
-            if (total + k < a.kp) out[(size_t)(total + k) * stride] = stage[k][t];
+            if (total + k < a.kp) out[(size_t)(total + k) * N] = stage[k][t];
         total += cnt;
     } while (__any(r < nr));
-    if (p < a.N) a.nbr_cnt[(size_t)plane * a.N + p] = total;
+
+    // Concatenate the five planes of each particle in plane order: plane r
+    // moves down to row off_r = sum of the counts of the planes before it.
+    // off_r <= r*kp, so a forward copy is safe, and the rounds run in plane
+    // order because plane r's destination may cover plane r-1's source rows.
+    __shared__ int32_t cnts[kNearPlanes][64];
+    const int lane = t & 63;
+    cnts[plane][lane] = total;
+    __syncthreads();
+    int off = 0, all = 0;
+    bool over = false;
+#pragma unroll
+    for (int q = 0; q < kNearPlanes; ++q) {
+        int c = cnts[q][lane];
+        over |= c > a.kp;
+        off += q < plane ? c : 0;
+        all += c;
+    }
+    for (int r = 1; r < kNearPlanes; ++r) {
+        if (plane == r && p < a.N && !over && off < r * a.kp) {
+            int32_t *dst = a.nbr + (size_t)off * N + p;
+            const int32_t *src = a.nbr + (size_t)r * a.kp * N + p;
+            int k = 0;
+            for (; k + 4 <= total; k += 4) {
+                int32_t e0 = src[(size_t)k * N], e1 = src[(size_t)(k + 1) * N];
+                int32_t e2 = src[(size_t)(k + 2) * N], e3 = src[(size_t)(k + 3) * N];
+                dst[(size_t)k * N] = e0;
+                dst[(size_t)(k + 1) * N] = e1;
+                dst[(size_t)(k + 2) * N] = e2;
+                dst[(size_t)(k + 3) * N] = e3;
+            }
+            for (; k < total; ++k) dst[(size_t)k * N] = src[(size_t)k * N];
+        }
+        __syncthreads();
+    }
+    if (plane == 0 && p < a.N) a.nbr_cnt[p] = over ? kNearPlanes * a.kp + 1 : all;
 }
 
 // ---------------------------------------------------------------------------
 // evaluation
 // ---------------------------------------------------------------------------
 
-template <bool MIXED, bool ENERGY>
-__global__ __launch_bounds__(kNearThreads) void k_near(NearArgs a)
+template <bool MIXED, bool ENERGY, int NG>
+__global__ __launch_bounds__(kEvalThreads) void k_near(NearArgs a)
 {
-    __shared__ double part[4][kNearThreads];
+    __shared__ double red[kEvalThreads];
     const int t = threadIdx.x;
-    const int plane = t >> 6;
-    const int p = xcd_block(blockIdx.x, gridDim.x) * 64 + (t & 63);
+    const int lb = xcd_block(blockIdx.x, gridDim.x);   // the five planes of a group share an XCD
+    const int grp = lb / kNearPlanes;
+    const int plane = lb - grp * kNearPlanes;
+    const int p = grp * kEvalThreads + t;
     const size_t stride = (size_t)kNearPlanes * (size_t)a.N;
     double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
-    int cnt = 0;
+    int total = 0;
     if (p < a.N) {
         pi = a.xs[p];
-        cnt = a.nbr_cnt[(size_t)plane * a.N + p];
+        total = a.nbr_cnt[p];
     }
-    const int32_t *in = a.nbr + (size_t)plane * a.N + p;
     double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0;
-    if (cnt <= a.kp) {
-        for (int k = 0; k < cnt; ++k) pair_force<MIXED, ENERGY>(a, pi, in[(size_t)k * stride], fx, fy, fz, en);
+    if (total <= kNearPlanes * a.kp) {
+        // lane `plane` takes entries plane, plane + 5, ... of the particle's
+        // list; entry k is evaluated while the position of entry k + 1 and the
+        // index of entry k + 2 are loading (the index clamped to the list)
+        const int cnt = total > plane ? (total - plane + kNearPlanes - 1) / kNearPlanes : 0;
+        const int32_t *in = a.nbr + (size_t)plane * a.N + p;
+        int jn = p;
+        double4 qn = pi;
+        if (cnt > 0) {
+            qn = a.xs[in[0]];
+            if (cnt > 1) in += stride;
+            jn = *in;
+        }
+        for (int k = 0; k < cnt; ++k) {
+            const double4 q = qn;
+            qn = a.xs[jn];
+            if (k + 2 < cnt) in += stride;
+            jn = *in;
+            pair_force<MIXED, ENERGY, NG>(a, pi, q, fx, fy, fz, en);
+        }
     } else {
-        // the list of this lane overflowed at the build: walk the cells around
-        // the current position directly.  Particles may have moved up to
+        // a plane of this particle overflowed at the build: each of its five
+        // lanes walks the cells of its plane around the current position.  Particles may have moved up to
         // skin/2 out of the cells they were sorted into (and wrapped around the
         // box), so the cells are culled with the list radius and the pair
         // function itself (minimum image, r < r_c) decides.
@@ -297,47 +370,30 @@ __global__ __launch_bounds__(kNearThreads) void k_near(NearArgs a)
                 for (int k = 0; k < n; ++k) {
                     int j0 = g[k].start_code & (int32_t)kIndexMask;
                     for (int j = j0; j < g[k].end; ++j)
-                        if (j != p) pair_force<MIXED, ENERGY>(a, pi, j, fx, fy, fz, en);
+                        if (j != p) pair_force<MIXED, ENERGY, NG>(a, pi, a.xs[j], fx, fy, fz, en);
                 }
             }
         }
     }
-    // the five planes of each particle, added in plane order
-    part[0][t] = fx;
-    part[1][t] = fy;
-    part[2][t] = fz;
-    part[3][t] = ENERGY ? 0.5 * en : 0.0;
-    __syncthreads();
-    if (t < 64 && p < a.N) {
-        double sx = 0.0, sy = 0.0, sz = 0.0;
-#pragma unroll
-        for (int k = 0; k < kNearPlanes; ++k) {
-            sx += part[0][k * 64 + t];
-            sy += part[1][k * 64 + t];
-            sz += part[2][k * 64 + t];
-        }
-        a.fnear[p] = sx;
-        a.fnear[a.N + p] = sy;
-        a.fnear[2 * a.N + p] = sz;
+    if (p < a.N) {
+        double *o = a.fnear + (size_t)plane * 3 * a.N + p;
+        o[0] = fx;
+        o[a.N] = fy;
+        o[2 * (size_t)a.N] = fz;
     }
     if (ENERGY) {
-        double e = 0.0;
-        if (t < 64) {
-#pragma unroll
-            for (int k = 0; k < kNearPlanes; ++k) e += part[3][k * 64 + t];
-        }
+        red[t] = 0.5 * en;
         __syncthreads();
-        if (t < 64) part[0][t] = e;
-        __syncthreads();
-        for (int off = 32; off > 0; off >>= 1) {
-            if (t < off) part[0][t] += part[0][t + off];
+        for (int off = kEvalThreads / 2; off > 0; off >>= 1) {
+            if (t < off) red[t] += red[t + off];
             __syncthreads();
         }
-        if (t == 0) a.epart[blockIdx.x] = part[0][0];
+        if (t == 0) a.epart[lb] = red[0];
     }
 }
 
-int near_blocks(int N) { return (N + 63) / 64; }
+int nlist_blocks(int N) { return (N + 63) / 64; }
+int near_blocks(int N) { return kNearPlanes * ((N + kEvalThreads - 1) / kEvalThreads); }
 
 // A launch with a missing buffer is refused on the host.
 static bool near_args_ok(const NearArgs &a)
@@ -349,21 +405,40 @@ static bool near_args_ok(const NearArgs &a)
 hipError_t launch_nlist(const NearArgs &a, hipStream_t st)
 {
     if (!near_args_ok(a)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_nlist, dim3(near_blocks(a.N)), dim3(kNearThreads), 0, st, a);
+    hipLaunchKernelGGL(k_nlist, dim3(nlist_blocks(a.N)), dim3(kNearThreads), 0, st, a);
     return hipGetLastError();
+}
+
+template <bool MIXED, bool ENERGY>
+static void launch_near_ng(const NearArgs &a, dim3 grid, hipStream_t st)
+{
+    dim3 block(kEvalThreads);
+    switch (a.sog.n) {
+#define RBSOG_NEAR_NG(n) \
+    case n: hipLaunchKernelGGL((k_near<MIXED, ENERGY, n>), grid, block, 0, st, a); return;
+        RBSOG_NEAR_NG(1)
+        RBSOG_NEAR_NG(2)
+        RBSOG_NEAR_NG(3)
+        RBSOG_NEAR_NG(4)
+        RBSOG_NEAR_NG(5)
+        RBSOG_NEAR_NG(6)
+        RBSOG_NEAR_NG(7)
+        RBSOG_NEAR_NG(8)
+#undef RBSOG_NEAR_NG
+    default: hipLaunchKernelGGL((k_near<MIXED, ENERGY, 0>), grid, block, 0, st, a); return;
+    }
 }
 
 hipError_t launch_near(const NearArgs &a, hipStream_t st)
 {
-    if (!near_args_ok(a)) return hipErrorInvalidValue;
+    if (!near_args_ok(a) || a.sog.n < 1 || a.sog.n > kMaxGauss) return hipErrorInvalidValue;
     dim3 grid(near_blocks(a.N));
-    dim3 block(kNearThreads);
     if (a.mixed) {
-        if (a.energy) hipLaunchKernelGGL((k_near<true, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_near<true, false>), grid, block, 0, st, a);
+        if (a.energy) launch_near_ng<true, true>(a, grid, st);
+        else launch_near_ng<true, false>(a, grid, st);
     } else {
-        if (a.energy) hipLaunchKernelGGL((k_near<false, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_near<false, false>), grid, block, 0, st, a);
+        if (a.energy) launch_near_ng<false, true>(a, grid, st);
+        else launch_near_ng<false, false>(a, grid, st);
     }
     return hipGetLastError();
 }

@@ -121,7 +121,7 @@ struct NearArgs {
     SogDev sog;
     const double4 *xs;         // cell order
     const int32_t *cell_start;
-    double *fnear;             // SoA [3][N] in cell order
+    double *fnear;             // [5][3][N] partial forces of the five lanes per particle, cell order
     double *epart;             // [near_blocks(N)] energy partials (when energy)
     int mixed;
     int energy;
@@ -129,13 +129,14 @@ struct NearArgs {
     double margin;             // slack of the per-particle cell culling
     double inv_L;
     Exp2Poly e2;
-    int32_t *nbr;              // [kp][5][N] listed j per (particle, plane), column-major
-    int32_t *nbr_cnt;          // [5][N] listed count per (particle, plane)
+    int32_t *nbr;              // [5 kp][N] listed j per particle (planes concatenated), column-major
+    int32_t *nbr_cnt;          // [N] listed count per particle; 5 kp + 1 when a plane overflowed
     int kp;                    // list capacity per (particle, plane)
     double rl2;                // squared list radius (r_c + skin)^2; the fine grid has cells >= (r_c + skin)/2
     const int32_t *gate;       // list build: null = always, else only when *gate != 0
 };
 hipError_t launch_nlist(const NearArgs &a, hipStream_t st);
+int nlist_blocks(int N);
 int near_blocks(int N);
 int far_blocks(int N);
 // Particles per structure-factor partial for a system of N particles and P samples.
@@ -150,7 +151,7 @@ struct FarArgs {
     const int32_t *order;
     const double4 *samp;       // [P] (nx, ny, nz, coef)
     const double2 *gk;         // [P] coef * rho
-    const double *fnear;       // SoA [3][N] cell order
+    const double *fnear;       // [5][3][N] partial near forces of the five lanes, cell order
     double *f;                 // SoA [3][N] original order
     double *f_near_out;        // SoA [3][N] original order, or null
     double *v;                 // null, or velocities to kick (original order)
