@@ -27,7 +27,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Offsets of every buffer inside the workspace.
 struct Layout {
     size_t lattice, cdf, coef, first, size;
-    size_t cell_id, count, cell_start, fill, tmp, order, xs, tile_sum, xb;
+    size_t cell_id, count, cell_start, fill, tmp, order, pos, xs, tile_sum, xb;
     size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_cnt;
     size_t total;
 };
@@ -54,6 +54,7 @@ struct Derived {
     int mmax;
     int64_t nlat;
     int kp;            // neighbour-list capacity per (particle, plane)
+    int sbatch;        // steps whose modes one sampling launch draws
 };
 
 // Capacity of each (particle, plane) neighbour list: 1.5x the expected count
@@ -86,12 +87,13 @@ Derived derive(const rbsog_params *p, const rbsog_sog *s)
     d.mmax = p->mmax > 0 ? p->mmax : default_mmax(*s, p->L);
     d.nlat = lattice_points(d.mmax);
     d.kp = near_capacity(p->N, p->L, d.rl, d.nf);
+    d.sbatch = std::max(1, std::min(64, 16384 / std::max(1, p->P)));
     return d;
 }
 
 Layout make_layout(int64_t N, const Derived &d, int P)
 {
-    int ncell = d.nf * d.nf * d.nf;  // the fine grid is the larger one
+    int ncell = std::max(d.nf * d.nf * d.nf, d.nc * d.nc * d.nc);  // either grid
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -110,10 +112,11 @@ Layout make_layout(int64_t N, const Derived &d, int P)
     L.fill = take(sizeof(int32_t) * (size_t)ncell);
     L.tmp = take(sizeof(int32_t) * (size_t)N);
     L.order = take(sizeof(int32_t) * (size_t)N);
+    L.pos = take(sizeof(int32_t) * (size_t)N);
     L.xs = take(sizeof(double) * 4 * (size_t)N);
     L.tile_sum = take(sizeof(int32_t) * (size_t)scan_tiles(ncell));
     L.xb = take(sizeof(double) * 3 * (size_t)N);
-    L.samp = take(sizeof(double) * 4 * (size_t)P);
+    L.samp = take(sizeof(double) * 4 * (size_t)P * (size_t)d.sbatch);
     L.part = take(sizeof(double) * 2 * (size_t)nchunks(N, P) * (size_t)P);
     L.rho = take(sizeof(double) * 2 * (size_t)P);
     L.gk = take(sizeof(double) * 2 * (size_t)P);
@@ -187,13 +190,18 @@ struct rbsog_handle {
     char *ws;
     SogDev sd;
     // views into the workspace
-    int32_t *lattice, *first, *size, *cell_id, *count, *cell_start, *fill, *tmp, *order, *flag, *tile_sum;
+    int32_t *lattice, *first, *size, *cell_id, *count, *cell_start, *fill, *tmp, *order, *pos, *flag, *tile_sum;
     double *cdf, *coef, *eF, *fnear, *epart, *kepart, *energy, *xb;
     double4 *xs, *samp;
     double2 *part, *rho, *gk;
     int32_t *nbr, *nbr_cnt;
-    int32_t *gate;       // device: rebuild the cell order and lists in this step
+    int32_t *gate;       // device, two words: rebuild the cell order and lists in this step
+                         // (steps alternate between them; each step clears the other)
+    int32_t *ticket;     // device: the scan's finished-tile counter
+    int phase;           // which gate word the next step uses
     bool lists_valid;    // cell order and lists in the workspace belong to the fine grid
+    uint64_t samp_step;  // first step of the modes in samp, with samp_n steps drawn
+    int samp_n;
     // per-kernel event timing (rbsog_timing_enable)
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -260,8 +268,10 @@ CellArgs cell_args(rbsog_handle *h, const double *x, const CellGeom &g, const in
     a.fill = h->fill;
     a.tmp = h->tmp;
     a.order = h->order;
+    a.pos = h->pos;
     a.xs = h->xs;
     a.tile_sum = h->tile_sum;
+    a.ticket = h->ticket;
     a.gate = gate;
     a.xb = xb;
     return a;
@@ -292,10 +302,11 @@ NearArgs near_args(rbsog_handle *h, const int32_t *gate, bool energy)
     return na;
 }
 
-SampleArgs sample_args(rbsog_handle *h, uint64_t step)
+SampleArgs sample_args(rbsog_handle *h, uint64_t step, int nstep)
 {
     SampleArgs a{};
     a.P = h->p.P;
+    a.nstep = nstep;
     a.step = step;
     a.seed = h->p.seed;
     a.replica = h->p.replica;
@@ -310,7 +321,7 @@ SampleArgs sample_args(rbsog_handle *h, uint64_t step)
     return a;
 }
 
-RhoArgs rho_args(rbsog_handle *h)
+RhoArgs rho_args(rbsog_handle *h, const double4 *samp)
 {
     RhoArgs a{};
     a.N = (int)h->p.N;
@@ -319,7 +330,7 @@ RhoArgs rho_args(rbsog_handle *h)
     a.nchunk = nchunks(h->p.N, h->p.P);
     a.inv_L = 1.0 / h->p.L;
     a.xs = h->xs;
-    a.samp = h->samp;
+    a.samp = samp;
     a.part = h->part;
     a.rho = h->rho;
     a.gk = h->gk;
@@ -331,29 +342,37 @@ RhoArgs rho_args(rbsog_handle *h)
 
 // Cell order + neighbour lists of the fine grid for positions x: always
 // (gate == null, a single evaluation) or only when the device gate is raised
-// (the step path, which then gathers xs from x in the current order and
-// clears the gate).
+// (the step path, where the drift has already written the positions into xs).
 int prepare(rbsog_handle *h, const double *x, const int32_t *gate)
 {
     CellArgs ca = cell_args(h, x, h->gf, gate, h->xb);
     HIPCHECK(timed(h, kCells, [&] { return launch_cell_build(ca, h->st); }));
     NearArgs na = near_args(h, gate, false);
     HIPCHECK(timed(h, kNlist, [&] { return launch_nlist(na, h->st); }));
-    if (gate) {
-        GatherArgs ga{(int)h->p.N, h->order, x, h->q, h->xs, h->gate};
-        HIPCHECK(timed(h, kCells, [&] { return launch_gather(ga, h->st); }));
-    }
     h->lists_valid = true;
     return RBSOG_OK;
 }
 
-// Sampling, structure factors, near field, far field (+ optional kick) and the
-// energy sums of one evaluation whose cell order and lists are prepared.
-int evaluate(rbsog_handle *h, uint64_t step, double *f, double *f_near, double *v, double dt, double *energy)
+// The modes of `step` in samp: drawn for `ahead` steps from it unless an
+// earlier draw already holds them.
+int modes(rbsog_handle *h, uint64_t step, int ahead, const double4 **samp)
 {
-    SampleArgs sa = sample_args(h, step);
-    HIPCHECK(timed(h, kSample, [&] { return launch_sample(sa, h->st); }));
-    RhoArgs ra = rho_args(h);
+    if (!(h->samp_n > 0 && step >= h->samp_step && step - h->samp_step < (uint64_t)h->samp_n)) {
+        int n = std::max(1, std::min(ahead, h->d.sbatch));
+        SampleArgs sa = sample_args(h, step, n);
+        HIPCHECK(timed(h, kSample, [&] { return launch_sample(sa, h->st); }));
+        h->samp_step = step;
+        h->samp_n = n;
+    }
+    *samp = h->samp + (size_t)(step - h->samp_step) * (size_t)h->p.P;
+    return RBSOG_OK;
+}
+
+// Structure factors, near field, far field (+ optional kick) and the energy
+// sums of one evaluation whose cell order, lists and modes are prepared.
+int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, double *v, double dt, double *energy)
+{
+    RhoArgs ra = rho_args(h, samp);
     HIPCHECK(timed(h, kRhoPartial, [&] { return launch_rho_partial(ra, h->st); }));
     HIPCHECK(timed(h, kRhoReduce, [&] { return launch_rho_reduce(ra, h->st); }));
     NearArgs na = near_args(h, nullptr, energy != nullptr);
@@ -365,7 +384,7 @@ int evaluate(rbsog_handle *h, uint64_t step, double *f, double *f_near, double *
     fa.inv_L = 1.0 / h->p.L;
     fa.xs = h->xs;
     fa.order = h->order;
-    fa.samp = h->samp;
+    fa.samp = samp;
     fa.gk = h->gk;
     fa.fnear = h->fnear;
     fa.f = f;
@@ -466,6 +485,7 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     h->fill = (int32_t *)(w + L.fill);
     h->tmp = (int32_t *)(w + L.tmp);
     h->order = (int32_t *)(w + L.order);
+    h->pos = (int32_t *)(w + L.pos);
     h->xs = (double4 *)(w + L.xs);
     h->tile_sum = (int32_t *)(w + L.tile_sum);
     h->xb = (double *)(w + L.xb);
@@ -479,6 +499,9 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     h->kepart = (double *)(w + L.kepart);
     h->flag = (int32_t *)(w + L.flag);
     h->gate = h->flag + 1;
+    h->ticket = h->flag + 3;
+    h->phase = 0;
+    h->samp_n = 0;
     h->energy = (double *)(w + L.energy);
     h->nbr = (int32_t *)(w + L.nbr);
     h->nbr_cnt = (int32_t *)(w + L.nbr_cnt);
@@ -491,6 +514,7 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->size, t.shell_size.data(), sizeof(int32_t) * t.nshell, hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess) e = hipMemsetAsync(h->flag, 0, sizeof(int32_t) * 4, h->st);
+    if (e == hipSuccess) e = hipMemsetAsync(h->count, 0, L.cell_start - L.count, h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (e != hipSuccess) {
         delete h;
@@ -548,19 +572,22 @@ extern "C" int rbsog_build_cells(rbsog_handle *h, const double *x_dev, int32_t *
 extern "C" int rbsog_sample_k(rbsog_handle *h, uint64_t step, int32_t *n_dev, double *coef_dev)
 {
     if (!h) return fail(RBSOG_EINVAL, "null handle");
-    SampleArgs a = sample_args(h, step);
+    SampleArgs a = sample_args(h, step, 1);
     a.n_out = n_dev;
     a.coef_out = coef_dev;
     HIPCHECK(timed(h, kSample, [&] { return launch_sample(a, h->st); }));
+    h->samp_step = step;
+    h->samp_n = 1;
     return RBSOG_OK;
 }
 
 extern "C" int rbsog_compute_rho(rbsog_handle *h, uint64_t step, const double *x_dev, double *rho_dev)
 {
     if (!h || !x_dev || !rho_dev) return fail(RBSOG_EINVAL, "null handle, x or rho");
-    SampleArgs sa = sample_args(h, step);
-    HIPCHECK(timed(h, kSample, [&] { return launch_sample(sa, h->st); }));
-    RhoArgs a = rho_args(h);
+    const double4 *samp = nullptr;
+    int rc = modes(h, step, 1, &samp);
+    if (rc) return rc;
+    RhoArgs a = rho_args(h, samp);
     a.xs = nullptr;
     a.x = x_dev;
     a.q = h->q;
@@ -576,7 +603,10 @@ extern "C" int rbsog_compute_forces(rbsog_handle *h, uint64_t step, const double
     if (!h || !x_dev || !f_dev) return fail(RBSOG_EINVAL, "null handle, x or f");
     int rc = prepare(h, x_dev, nullptr);
     if (rc) return rc;
-    return evaluate(h, step, f_dev, f_near_dev, nullptr, 0.0, energy_dev);
+    const double4 *samp = nullptr;
+    rc = modes(h, step, 1, &samp);
+    if (rc) return rc;
+    return evaluate(h, samp, f_dev, f_near_dev, nullptr, 0.0, energy_dev);
 }
 
 extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double *f_dev, uint64_t step0, int nsteps,
@@ -586,8 +616,9 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
     if (nsteps < 0) return fail(RBSOG_EINVAL, "nsteps must be >= 0");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RBSOG_EINVAL, "dt must be positive and finite");
     for (int n = 0; n < nsteps; ++n) {
+        int32_t *gate = h->gate + h->phase, *gate_next = h->gate + (1 - h->phase);
         // force a rebuild when the workspace holds no lists of the fine grid
-        if (!h->lists_valid) HIPCHECK(launch_set_int(h->gate, 1, h->st));
+        if (!h->lists_valid) HIPCHECK(launch_set_int(gate, 1, h->st));
         KickDriftArgs k{};
         k.N = (int)h->p.N;
         k.L = h->p.L;
@@ -599,13 +630,24 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         k.m = h->m;
         k.xb = h->xb;
         k.half_skin2 = 0.25 * h->d.skin * h->d.skin;
-        k.gate = h->gate;
+        k.gate = gate;
+        k.gate_next = gate_next;
         k.flag = h->flag;
+        if (h->lists_valid) {   // pos and xs hold the fine grid's order
+            k.xs = h->xs;
+            k.pos = h->pos;
+            k.q = h->q;
+        }
         HIPCHECK(timed(h, kKickDrift, [&] { return launch_kick_drift(k, h->st); }));
-        int rc = prepare(h, x_dev, h->gate);
+        h->phase = 1 - h->phase;
+        int rc = prepare(h, x_dev, gate);
+        if (rc) return rc;
+        const double4 *samp = nullptr;
+        uint64_t step = step0 + (uint64_t)n + 1;
+        rc = modes(h, step, nsteps - n, &samp);
         if (rc) return rc;
         double *e = energy_hist_dev ? energy_hist_dev + 6 * (size_t)n : nullptr;
-        rc = evaluate(h, step0 + (uint64_t)n + 1, f_dev, nullptr, v_dev, dt, e);
+        rc = evaluate(h, samp, f_dev, nullptr, v_dev, dt, e);
         if (rc) return rc;
     }
     return RBSOG_OK;

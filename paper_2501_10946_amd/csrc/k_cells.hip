@@ -1,12 +1,12 @@
 // gfx950 kernels of librbsog: the cell list (a counting sort with a stable
-// rank), the gather of positions into list order, and the first
-// velocity-Verlet half step.
+// rank) and the first velocity-Verlet half step.
 //
 // Data layout in HBM: the caller's particle arrays stay FP64 SoA in the
-// caller's order.  A build sorts the particles by cell into `order` and writes
-// a cell-ordered copy xs[N] of (x, y, z, q) as double4 (32-byte rows) that the
-// pair and far-field kernels stream; between builds the same order is reused
-// and only the positions are gathered again.
+// caller's order.  A build sorts the particles by cell into `order` (and its
+// inverse `pos`) and writes a cell-ordered copy xs[N] of (x, y, z, q) as
+// double4 (32-byte rows) that the pair and far-field kernels stream; between
+// builds the same order is reused and the drift writes the new positions
+// straight into their rows of xs.
 //
 // Builds can be gated: every build kernel takes a device flag and returns at
 // once when it is zero, so the decision to rebuild (some particle moved more
@@ -19,21 +19,6 @@ namespace rbsog {
 
 // A build kernel proceeds when it has no gate or its gate is raised.
 __device__ inline bool gate_open(const int32_t *gate) { return gate == nullptr || *gate != 0; }
-
-__global__ void k_zero_int(int32_t *p, int n, const int32_t *gate)
-{
-    if (!gate_open(gate)) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
-hipError_t launch_zero_int(int32_t *p, int n, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_int, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, p, n,
-                       (const int32_t *)nullptr);
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // cell list: ids + counts, scan, scatter, stable rank + gather
@@ -53,9 +38,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids(CellArgs a)
     atomicAdd(&a.count[id], 1);
 }
 
-// Exclusive scan of the cell counts in three passes: per-tile sums, a scan of
-// the (few) tile sums, then each tile scanned with its offset.  The last pass
-// also clears the fill counters of the scatter.
+// Exclusive scan of the cell counts in two passes.
 constexpr int kScanPer = 8;
 constexpr int kScanTile = kBlock * kScanPer;
 
@@ -76,45 +59,43 @@ __device__ inline int32_t block_exclusive_scan_256(int32_t v, int32_t *sh, int32
     return incl - v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(CellArgs a)
+// Pass 1: per-tile sums; the last tile to finish (a ticket counter) turns them
+// into exclusive tile offsets and resets the ticket.
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(CellArgs a, int ntiles)
 {
     if (!gate_open(a.gate)) return;
     __shared__ int32_t sh[kBlock];
-    int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    __shared__ int last;
+    const int t = threadIdx.x;
+    int base = blockIdx.x * kScanTile + t * kScanPer;
     int32_t s = 0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k)
         if (base + k < a.g.ncell) s += a.count[base + k];
     int32_t total;
     block_exclusive_scan_256(s, sh, &total);
-    if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(1024) void k_scan_top(CellArgs a, int ntiles)
-{
-    if (!gate_open(a.gate)) return;
-    __shared__ int32_t sums[1024];
-    int t = threadIdx.x;
-    int per = (ntiles + 1023) / 1024;
-    int b = t * per, e = min(ntiles, b + per);
-    int32_t s = 0;
-    for (int k = b; k < e; ++k) s += a.tile_sum[k];
-    sums[t] = s;
+    if (t == 0) {
+        a.tile_sum[blockIdx.x] = total;
+        __threadfence();
+        last = atomicAdd(a.ticket, 1) == ntiles - 1;
+    }
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int32_t v = (t >= off) ? sums[t - off] : 0;
-        __syncthreads();
-        sums[t] += v;
-        __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // exclusive scan of the tile sums, kBlock at a time
+    int32_t run = 0;
+    for (int b0 = 0; b0 < ntiles; b0 += kBlock) {
+        int32_t v = b0 + t < ntiles ? __atomic_load_n(&a.tile_sum[b0 + t], __ATOMIC_RELAXED) : 0;
+        int32_t chunk;
+        int32_t ex = block_exclusive_scan_256(v, sh, &chunk);
+        if (b0 + t < ntiles) a.tile_sum[b0 + t] = run + ex;
+        run += chunk;
     }
-    int32_t run = (t == 0) ? 0 : sums[t - 1];
-    for (int k = b; k < e; ++k) {
-        int32_t c = a.tile_sum[k];
-        a.tile_sum[k] = run;
-        run += c;
-    }
+    if (t == 0) *a.ticket = 0;
 }
 
+// Pass 2: each tile scanned with its offset; also clears the scatter's fill
+// counters and the cell counts (ready for the next build).
 __global__ __launch_bounds__(kBlock) void k_scan_apply(CellArgs a)
 {
     if (!gate_open(a.gate)) return;
@@ -134,6 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(CellArgs a)
         if (base + k < a.g.ncell) {
             a.cell_start[base + k] = run;
             a.fill[base + k] = 0;
+            a.count[base + k] = 0;
         }
         run += c[k];
     }
@@ -169,6 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_rank(CellArgs a)
     int p = b + r;
     double x = a.x[i], y = a.x[a.N + i], z = a.x[2 * a.N + i];
     a.order[p] = i;
+    a.pos[i] = p;
     a.xs[p] = make_double4(x, y, z, a.q[i]);
     if (a.xb) {
         a.xb[i] = x;
@@ -180,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_rank(CellArgs a)
 static bool cell_args_ok(const CellArgs &a)
 {
     return a.N >= 1 && a.g.nc >= 1 && a.x && a.q && a.cell_id && a.count && a.cell_start && a.fill && a.tmp &&
-           a.order && a.xs && a.tile_sum;
+           a.order && a.pos && a.xs && a.tile_sum && a.ticket;
 }
 
 hipError_t launch_cell_build(const CellArgs &a, hipStream_t st)
@@ -188,11 +171,8 @@ hipError_t launch_cell_build(const CellArgs &a, hipStream_t st)
     if (!cell_args_ok(a)) return hipErrorInvalidValue;
     int grid = (a.N + kBlock - 1) / kBlock;
     int nt = scan_tiles(a.g.ncell);
-    hipLaunchKernelGGL(k_zero_int, dim3((a.g.ncell + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a.count, a.g.ncell,
-                       a.gate);
     hipLaunchKernelGGL(k_cell_ids, dim3(grid), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, a, nt);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kBlock), 0, st, a, nt);
     hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_rank, dim3(grid), dim3(kBlock), 0, st, a);
@@ -200,39 +180,21 @@ hipError_t launch_cell_build(const CellArgs &a, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-// gather of the current positions into the order of the last build; clears
-// the rebuild gate once everything that reads it has run
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a)
-{
-    int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p < a.N) {
-        int i = a.order[p];
-        a.xs[p] = make_double4(a.x[i], a.x[a.N + i], a.x[2 * a.N + i], a.q[i]);
-    }
-    if (a.gate && p == 0) *a.gate = 0;
-}
-
-hipError_t launch_gather(const GatherArgs &a, hipStream_t st)
-{
-    if (a.N < 1 || !a.order || !a.x || !a.q || !a.xs) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gather, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// first half-kick + drift + wrap; raises the rebuild gate when a particle has
-// moved more than half the skin since the last build
+// first half-kick + drift + wrap; writes the new position into the particle's
+// row of the cell-ordered copy, raises the rebuild gate of this step when a
+// particle has moved more than half the skin since the last build, and clears
+// the gate of the next step
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_kick_drift(KickDriftArgs a)
 {
     int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) *a.gate_next = 0;
     if (i >= a.N) return;
     const double L = a.L;
     double hm = (0.5 * a.dt) / a.m[i];
     double d2 = 0.0;
+    double xn[3];
     bool bad = false;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -245,17 +207,21 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(KickDriftArgs a)
         if (xx >= L) xx = 0.0;
         a.v[d * a.N + i] = vv;
         a.x[d * a.N + i] = xx;
+        xn[d] = xx;
         double s = xx - a.xb[d * a.N + i];
         s = fma(-L, rint(s * a.inv_L), s);
         d2 = fma(s, s, d2);
     }
+    if (a.xs) a.xs[a.pos[i]] = make_double4(xn[0], xn[1], xn[2], a.q[i]);
     if (bad) atomicOr(a.flag, 1);
     if (!(d2 <= a.half_skin2)) atomicOr(a.gate, 1);
 }
 
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t st)
 {
-    if (a.N < 1 || !a.x || !a.v || !a.f || !a.m || !a.xb || !a.gate || !a.flag) return hipErrorInvalidValue;
+    if (a.N < 1 || !a.x || !a.v || !a.f || !a.m || !a.xb || !a.gate || !a.gate_next || !a.flag ||
+        (a.xs && (!a.pos || !a.q)))
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_kick_drift, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }

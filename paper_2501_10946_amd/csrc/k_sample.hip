@@ -6,15 +6,17 @@
 namespace rbsog {
 
 // ---------------------------------------------------------------------------
-// sampling: P i.i.d. modes from the shell CDF (bit-exact integer/IEEE steps)
+// sampling: P i.i.d. modes per step from the shell CDF (bit-exact integer/IEEE
+// steps), for a batch of consecutive steps in one launch
 // ---------------------------------------------------------------------------
 
 __global__ void k_sample(SampleArgs a)
 {
-    int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= a.P) return;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)a.P * a.nstep) return;
+    int s = (int)(idx / a.P), l = (int)(idx - (int64_t)s * a.P);
     uint64_t w[4];
-    philox4x64_10((uint64_t)l, a.step, 0, 0, a.seed, (uint64_t)a.replica, w);
+    philox4x64_10((uint64_t)l, a.step + (uint64_t)s, 0, 0, a.seed, (uint64_t)a.replica, w);
     double u = (double)(w[0] >> 11) * 0x1p-53;
     double target = u * a.S;
     int lo = 0, hi = a.nshell;
@@ -27,7 +29,7 @@ __global__ void k_sample(SampleArgs a)
     uint32_t pk = (uint32_t)a.lattice[a.first[i] + (int64_t)j];
     int nx = (int)(pk & 1023u) - 512, ny = (int)((pk >> 10) & 1023u) - 512, nz = (int)((pk >> 20) & 1023u) - 512;
     double cf = a.coef[i];
-    a.samp[l] = make_double4((double)nx, (double)ny, (double)nz, cf);
+    a.samp[idx] = make_double4((double)nx, (double)ny, (double)nz, cf);
     if (a.n_out) {
         a.n_out[3 * l + 0] = nx;
         a.n_out[3 * l + 1] = ny;
@@ -38,9 +40,11 @@ __global__ void k_sample(SampleArgs a)
 
 hipError_t launch_sample(const SampleArgs &a, hipStream_t st)
 {
-    if (a.P < 1 || a.nshell < 1 || !a.cdf || !a.coef || !a.first || !a.size || !a.lattice || !a.samp)
+    if (a.P < 1 || a.nstep < 1 || a.nshell < 1 || !a.cdf || !a.coef || !a.first || !a.size || !a.lattice ||
+        !a.samp || (a.nstep > 1 && (a.n_out || a.coef_out)))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_sample, dim3((a.P + 63) / 64), dim3(64), 0, st, a);
+    int64_t n = (int64_t)a.P * a.nstep;
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 

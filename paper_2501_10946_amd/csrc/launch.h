@@ -44,23 +44,17 @@ struct CellArgs {
     int32_t *fill;         // [ncell]
     int32_t *tmp;          // [N] unordered members per cell
     int32_t *order;        // [N] cell order -> original index
+    int32_t *pos;          // [N] original index -> cell order
     double4 *xs;           // [N] (x, y, z, q) in cell order
     int32_t *tile_sum;     // [scan_tiles(ncell)] scan workspace
+    int32_t *ticket;       // scan's finished-tile counter: zero between builds
     const int32_t *gate;   // null: always build; else build only when *gate != 0
     double *xb;            // null, or SoA [3][N] positions recorded at the build
 };
 int scan_tiles(int ncell);
-// zero counts, ids + counts, scan, scatter, stable rank + gather
+// ids + counts, scan (which leaves the counts zero again), scatter, stable rank
+// + gather; `count` must be zero on entry
 hipError_t launch_cell_build(const CellArgs &a, hipStream_t st);
-
-struct GatherArgs {
-    int N;
-    const int32_t *order;
-    const double *x, *q;
-    double4 *xs;
-    int32_t *gate;         // cleared (if not null) after the gather
-};
-hipError_t launch_gather(const GatherArgs &a, hipStream_t st);
 hipError_t launch_set_int(int32_t *p, int32_t v, hipStream_t st);
 
 // --- integration ------------------------------------------------------------
@@ -73,13 +67,18 @@ struct KickDriftArgs {
     const double *xb;      // SoA [3][N] positions at the last list build
     double half_skin2;     // (skin / 2)^2
     int32_t *gate;         // raised when a particle moved more than skin / 2 since the build
+    int32_t *gate_next;    // the next step's gate, cleared
     int *flag;             // set to 1 on a step of a box length or more
+    double4 *xs;           // null, or the cell-ordered copy to write the new positions into
+    const int32_t *pos;    // [N] original index -> cell order (when xs)
+    const double *q;       // [N] (when xs)
 };
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t st);
 
 // --- sampling ----------------------------------------------------------------
 struct SampleArgs {
     int P;
+    int nstep;                 // steps drawn: step .. step + nstep - 1
     uint64_t step, seed;
     uint32_t replica;
     int nshell;
@@ -89,9 +88,9 @@ struct SampleArgs {
     const int32_t *first;      // [nshell]
     const int32_t *size;       // [nshell]
     const int32_t *lattice;    // packed lattice vectors
-    double4 *samp;             // [P] (nx, ny, nz, coef)
-    int32_t *n_out;            // [P][3] or null
-    double *coef_out;          // [P] or null
+    double4 *samp;             // [nstep][P] (nx, ny, nz, coef)
+    int32_t *n_out;            // [P][3] or null (nstep == 1)
+    double *coef_out;          // [P] or null (nstep == 1)
 };
 hipError_t launch_sample(const SampleArgs &a, hipStream_t st);
 
@@ -175,6 +174,5 @@ struct EnergyArgs {
 };
 hipError_t launch_energy(const EnergyArgs &a, hipStream_t st);
 
-hipError_t launch_zero_int(int32_t *p, int n, hipStream_t st);
 
 }  // namespace rbsog
