@@ -17,6 +17,8 @@
 
 namespace rbsog {
 
+static_assert(kPhaseTable == kPhaseTab, "host and device rotation tables differ in size");
+
 namespace {
 thread_local std::string g_error;
 constexpr double kPi = 3.141592653589793;
@@ -28,7 +30,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t lattice, cdf, coef, first, size;
     size_t cell_id, count, cell_start, fill, tmp, order, pos, xs, tile_sum, xb;
-    size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_cnt;
+    size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_cnt, tab;
     size_t total;
 };
 
@@ -128,6 +130,7 @@ Layout make_layout(int64_t N, const Derived &d, int P)
     L.energy = take(sizeof(double) * 8);
     L.nbr = take(sizeof(int32_t) * (size_t)d.kp * 5 * (size_t)N);
     L.nbr_cnt = take(sizeof(int32_t) * (size_t)N);
+    L.tab = take(sizeof(double) * 2 * kPhaseTable);
     L.total = off;
     return L;
 }
@@ -193,7 +196,7 @@ struct rbsog_handle {
     int32_t *lattice, *first, *size, *cell_id, *count, *cell_start, *fill, *tmp, *order, *pos, *flag, *tile_sum;
     double *cdf, *coef, *eF, *fnear, *epart, *kepart, *energy, *xb;
     double4 *xs, *samp;
-    double2 *part, *rho, *gk;
+    double2 *part, *rho, *gk, *tab;
     int32_t *nbr, *nbr_cnt;
     int32_t *gate;       // device, two words: rebuild the cell order and lists in this step
                          // (steps alternate between them; each step clears the other)
@@ -336,7 +339,8 @@ RhoArgs rho_args(rbsog_handle *h, const double4 *samp)
     a.gk = h->gk;
     a.eF = h->eF;
     a.mixed = h->p.precision == RBSOG_MIXED;
-    a.sc = make_sincos_poly();
+    a.tab = h->tab;
+    a.ss = make_sincos_short();
     return a;
 }
 
@@ -395,7 +399,8 @@ int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, do
     fa.kepart = v ? h->kepart : nullptr;
     fa.flag = h->flag;
     fa.mixed = h->p.precision == RBSOG_MIXED;
-    fa.sc = make_sincos_poly();
+    fa.tab = h->tab;
+    fa.ss = make_sincos_short();
     HIPCHECK(timed(h, kFar, [&] { return launch_far(fa, h->st); }));
     if (energy) {
         EnergyArgs ea{};
@@ -505,6 +510,9 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     h->energy = (double *)(w + L.energy);
     h->nbr = (int32_t *)(w + L.nbr);
     h->nbr_cnt = (int32_t *)(w + L.nbr_cnt);
+    h->tab = (double2 *)(w + L.tab);
+    double tabh[2 * kPhaseTable];
+    phase_table(tabh);
     h->lists_valid = false;
     e = hipMemcpyAsync(h->lattice, t.packed.data(), sizeof(int32_t) * t.packed.size(), hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess) e = hipMemcpyAsync(h->cdf, t.cdf.data(), sizeof(double) * t.nshell, hipMemcpyHostToDevice, h->st);
@@ -513,6 +521,7 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
         e = hipMemcpyAsync(h->first, t.shell_first.data(), sizeof(int32_t) * t.nshell, hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->size, t.shell_size.data(), sizeof(int32_t) * t.nshell, hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h->tab, tabh, sizeof(tabh), hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess) e = hipMemsetAsync(h->flag, 0, sizeof(int32_t) * 4, h->st);
     if (e == hipSuccess) e = hipMemsetAsync(h->count, 0, L.cell_start - L.count, h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);

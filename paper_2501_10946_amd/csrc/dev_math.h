@@ -125,6 +125,42 @@ __device__ inline void sincos_rev(double u, const SinCosPoly &P, double *s, doub
     *c = ((qi + 1) & 2) ? -c1 : c1;
 }
 
+// sin(2 pi f), cos(2 pi f) for |f| <= 1/256 by their Taylor series to degree 7
+// and 6 (s[k], c[k] as in SinCosPoly, k = 0..3): the first omitted terms are
+// below 4e-19 relative to sin and 4e-18 absolute.
+struct SinCosShort {
+    double s[4];
+    double c[4];
+};
+constexpr SinCosShort make_sincos_short()
+{
+    SinCosShort p{};
+    for (int k = 0; k < 4; ++k) {
+        double sg = (k % 2) ? -1.0 : 1.0;
+        p.s[k] = sg * taylor_coef(kTwoPi, 2 * k + 1);
+        p.c[k] = sg * taylor_coef(kTwoPi, 2 * k);
+    }
+    return p;
+}
+
+constexpr int kPhaseTab = 128;   // entries of the rotation table
+
+// sin(2 pi u), cos(2 pi u) for a phase u in revolutions (FP64) with a table of
+// (sin, cos)(2 pi j / 128): u - rint(u) = j / 128 + f exactly (|f| <= 1/256),
+// the short series give the rotation by f, and the table entry the rest.
+__device__ inline void sincos_rev_tab(double u, const double2 *tab, const SinCosShort &P, double *s, double *c)
+{
+    double r = u - rint(u);
+    double jr = rint(r * (double)kPhaseTab);
+    double f = fma(jr, -1.0 / kPhaseTab, r);
+    double2 t = tab[(int)jr & (kPhaseTab - 1)];
+    double f2 = f * f;
+    double sp = fma(fma(fma(P.s[3], f2, P.s[2]), f2, P.s[1]), f2, P.s[0]) * f;
+    double cp = fma(fma(fma(P.c[3], f2, P.c[2]), f2, P.c[1]), f2, P.c[0]);
+    *s = fma(t.x, cp, t.y * sp);
+    *c = fma(t.y, cp, -(t.x * sp));
+}
+
 // The same in FP32 after the exact FP64 reduction to [-1/2, 1/2] revolutions:
 // the hardware sine and cosine take their argument in revolutions.
 __device__ inline void sincos_rev_f32(double u, float *s, float *c)

@@ -41,6 +41,10 @@ int default_mmax(const rbsog_sog &s, double L);
 int64_t lattice_points(int mmax);
 double density(int kind, double kT, double V, double Q2, double lambda, double k2);
 void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax, Tables *t);
+// (sin, cos)(2 pi j / kPhaseTable), j = 0 .. kPhaseTable - 1, interleaved, from
+// the host's libm: the rotation table of the FP64 phase kernels
+constexpr int kPhaseTable = 128;
+void phase_table(double out[2 * kPhaseTable]);
 // sum q and sum q^2 in particle order (plain FP64 additions, no contraction)
 void charge_sums(const double *q, int64_t N, double *q1, double *q2);
 

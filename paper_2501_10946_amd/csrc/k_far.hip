@@ -25,15 +25,18 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs a)
 {
     __shared__ double4 sk[kFarTile];
     __shared__ double2 sg[kFarTile];
+    __shared__ double2 tab[kPhaseTab];
     __shared__ double part[3][kFarThreads];
     __shared__ double red[64];
     const int t = threadIdx.x;
-    const int g = t >> 6, lane = t & 63;
+    const int g = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;   // g is uniform per wave
     const int p = blockIdx.x * 64 + lane;
     const bool live = p < a.N;
     double4 pi = live ? a.xs[p] : make_double4(0.0, 0.0, 0.0, 0.0);
     double sx = pi.x * a.inv_L, sy = pi.y * a.inv_L, sz = pi.z * a.inv_L;
     double ax = 0.0, ay = 0.0, az = 0.0;
+    if (!MIXED)
+        for (int k = t; k < kPhaseTab; k += kFarThreads) tab[k] = a.tab[k];
     for (int l0 = 0; l0 < a.P; l0 += kFarTile) {
         __syncthreads();
         if (l0 + t < a.P) {
@@ -53,7 +56,7 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs a)
                 im = gv.y * (double)cs - gv.x * (double)sn;
             } else {
                 double sn, cs;
-                sincos_rev(u, a.sc, &sn, &cs);
+                sincos_rev_tab(u, tab, a.ss, &sn, &cs);
                 im = gv.y * cs - gv.x * sn;
             }
             ax += im * kv.x;
@@ -121,7 +124,7 @@ int far_blocks(int N) { return (N + 63) / 64; }
 hipError_t launch_far(const FarArgs &a, hipStream_t st)
 {
     if (a.N < 1 || a.P < 1 || !a.xs || !a.order || !a.samp || !a.gk || !a.fnear || !a.f || !a.flag ||
-        (a.v && (!a.m || !a.kepart)))
+        (a.v && (!a.m || !a.kepart)) || (!a.mixed && !a.tab))
         return hipErrorInvalidValue;
     dim3 grid(far_blocks(a.N));
     if (a.mixed) hipLaunchKernelGGL(k_far<true>, grid, dim3(kFarThreads), 0, st, a);

@@ -6,48 +6,70 @@
 namespace rbsog {
 
 // ---------------------------------------------------------------------------
-// structure factors: lanes own samples, particles stream through LDS.
-// A workgroup takes a chunk of particles (64..256, chosen so that the grid has
-// enough waves to cover the chip) and up to 256 samples, and writes one
-// partial sum per (chunk, sample); a second kernel adds the partials of each
-// sample in a fixed order.
+// structure factors.  Particles are cut into groups of C (the "chunk") and the
+// lanes of the grid are laid out flat over (group s, sample l), lane s P + l,
+// so every lane of every wave has work whatever P is.  A workgroup stages the
+// particles of the groups its lanes touch in LDS; each lane sums its group in
+// two interleaved streams and writes one partial per (group, sample); a second
+// kernel adds the partials of each sample in a fixed order.
 // ---------------------------------------------------------------------------
+
+constexpr int kRhoStage = 1024;   // particles one workgroup stages at most
+
+template <bool CELL, bool MIXED>
+__device__ inline void rho_term(const RhoArgs &a, const double2 *tab, const double4 &k, const double4 &p,
+                                double &re, double &im)
+{
+    double u = k.x * p.x + k.y * p.y + k.z * p.z;
+    if (MIXED) {
+        float sn, cs;
+        sincos_rev_f32(u, &sn, &cs);
+        re = fma(p.w, (double)cs, re);
+        im = fma(p.w, (double)sn, im);
+    } else {
+        double sn, cs;
+        sincos_rev_tab(u, tab, a.ss, &sn, &cs);
+        re = fma(p.w, cs, re);
+        im = fma(p.w, sn, im);
+    }
+}
 
 template <bool CELL, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_rho_partial(RhoArgs a)
 {
-    __shared__ double4 sp[kRhoChunkMax];
-    int chunk = blockIdx.x;
-    int j0 = chunk * a.chunk;
-    int nj = min(a.chunk, a.N - j0);
-    for (int t = threadIdx.x; t < nj; t += kBlock) {
-        int j = j0 + t;
+    // dynamic LDS: the rotation table, then the staged particles
+    extern __shared__ double4 lds[];
+    double2 *tab = (double2 *)lds;
+    double4 *sp = lds + kPhaseTab / 2;
+    const int t = threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.x * kBlock;
+    const int s_lo = (int)(g0 / a.P);
+    const int s_hi = (int)min((int64_t)a.nchunk - 1, (g0 + kBlock - 1) / a.P);
+    const int j_lo = s_lo * a.chunk;
+    const int j_hi = min(a.N, (s_hi + 1) * a.chunk);
+    for (int k = t; k < j_hi - j_lo; k += kBlock) {
+        int j = j_lo + k;
         double4 v;
         if (CELL) v = a.xs[j];
         else v = make_double4(a.x[j], a.x[a.N + j], a.x[2 * a.N + j], a.q[j]);
-        sp[t] = make_double4(v.x * a.inv_L, v.y * a.inv_L, v.z * a.inv_L, v.w);
+        sp[k] = make_double4(v.x * a.inv_L, v.y * a.inv_L, v.z * a.inv_L, v.w);
     }
+    if (!MIXED)
+        for (int k = t; k < kPhaseTab; k += kBlock) tab[k] = a.tab[k];
     __syncthreads();
-    int l = blockIdx.y * kBlock + threadIdx.x;
-    if (l >= a.P) return;
-    double4 k = a.samp[l];
-    double re = 0.0, im = 0.0;
-    for (int t = 0; t < nj; ++t) {
-        double4 s = sp[t];
-        double u = k.x * s.x + k.y * s.y + k.z * s.z;
-        if (MIXED) {
-            float sn, cs;
-            sincos_rev_f32(u, &sn, &cs);
-            re += s.w * (double)cs;
-            im += s.w * (double)sn;
-        } else {
-            double sn, cs;
-            sincos_rev(u, a.sc, &sn, &cs);
-            re += s.w * cs;
-            im += s.w * sn;
-        }
+    const int64_t g = g0 + t;
+    if (g >= (int64_t)a.nchunk * a.P) return;
+    const int s = (int)(g / a.P), l = (int)(g - (int64_t)s * a.P);
+    const double4 k = a.samp[l];
+    const int b = s * a.chunk - j_lo, e = min(a.N, (s + 1) * a.chunk) - j_lo;
+    double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+    int i = b;
+    for (; i + 1 < e; i += 2) {
+        rho_term<CELL, MIXED>(a, tab, k, sp[i], re0, im0);
+        rho_term<CELL, MIXED>(a, tab, k, sp[i + 1], re1, im1);
     }
-    a.part[(size_t)chunk * a.P + l] = make_double2(re, im);
+    if (i < e) rho_term<CELL, MIXED>(a, tab, k, sp[i], re0, im0);
+    a.part[g] = make_double2(re0 + re1, im0 + im1);
 }
 
 // One workgroup per sample: fixed-order sum of the chunk partials.
@@ -78,25 +100,32 @@ __global__ __launch_bounds__(kBlock) void k_rho_reduce(RhoArgs a)
 
 int rho_chunk(int N, int P)
 {
-    // enough workgroups for ~8 waves per SIMD (4 waves per workgroup, 1024 SIMDs)
-    int groups = (P + kBlock - 1) / kBlock;
-    for (int c = kRhoChunkMax; c > 64; c >>= 1)
-        if ((int64_t)((N + c - 1) / c) * groups >= 2048) return c;
-    return 64;
+    // the staged groups of a workgroup fit in LDS: a workgroup's lanes touch at
+    // most 255 / P + 2 groups
+    int cap = kRhoStage / (255 / P + 2);
+    int c = 1;
+    while (2 * c <= cap && 2 * c <= kRhoChunkMax) c *= 2;
+    // at least ~4 waves per SIMD (4096 waves of 64 lanes) where N and P allow
+    while (c > 8 && (int64_t)((N + c - 1) / c) * P < 4096 * 64) c /= 2;
+    return c;
 }
 
 hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st)
 {
+    int64_t lanes = (int64_t)a.nchunk * a.P;
     if (a.N < 1 || a.P < 1 || a.chunk < 1 || a.chunk > kRhoChunkMax || !a.samp || !a.part ||
-        (!a.xs && (!a.x || !a.q)))
+        (!a.xs && (!a.x || !a.q)) || (!a.mixed && !a.tab) ||
+        (int64_t)(255 / a.P + 2) * a.chunk > kRhoStage || (int64_t)a.nchunk * a.chunk < a.N ||
+        (lanes + kBlock - 1) / kBlock > 0x7fffffff)
         return hipErrorInvalidValue;
-    dim3 grid(a.nchunk, (a.P + kBlock - 1) / kBlock);
+    dim3 grid((unsigned)((lanes + kBlock - 1) / kBlock));
+    size_t lds = sizeof(double4) * (kPhaseTab / 2 + (size_t)(255 / a.P + 2) * a.chunk);
     if (a.xs) {
-        if (a.mixed) hipLaunchKernelGGL((k_rho_partial<true, true>), grid, dim3(kBlock), 0, st, a);
-        else hipLaunchKernelGGL((k_rho_partial<true, false>), grid, dim3(kBlock), 0, st, a);
+        if (a.mixed) hipLaunchKernelGGL((k_rho_partial<true, true>), grid, dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((k_rho_partial<true, false>), grid, dim3(kBlock), lds, st, a);
     } else {
-        if (a.mixed) hipLaunchKernelGGL((k_rho_partial<false, true>), grid, dim3(kBlock), 0, st, a);
-        else hipLaunchKernelGGL((k_rho_partial<false, false>), grid, dim3(kBlock), 0, st, a);
+        if (a.mixed) hipLaunchKernelGGL((k_rho_partial<false, true>), grid, dim3(kBlock), lds, st, a);
+        else hipLaunchKernelGGL((k_rho_partial<false, false>), grid, dim3(kBlock), lds, st, a);
     }
     return hipGetLastError();
 }

@@ -12,7 +12,7 @@
 namespace rbsog {
 
 constexpr int kBlock = 256;        // threads per workgroup of the streaming and pair kernels
-constexpr int kRhoChunkMax = 256;  // particles per structure-factor partial (at most)
+constexpr int kRhoChunkMax = 256;  // particles per structure-factor group (at most)
 constexpr int kMaxGauss = 32;
 
 // SOG coefficients as the kernels need them.
@@ -96,18 +96,19 @@ hipError_t launch_sample(const SampleArgs &a, hipStream_t st);
 
 // --- structure factors -----------------------------------------------------------
 struct RhoArgs {
-    int N, P, nchunk, chunk;   // chunk = particles per partial (64, 128 or 256)
+    int N, P, nchunk, chunk;   // chunk = particles per group (a power of two, rho_chunk)
     double inv_L;
     const double4 *xs;         // cell-ordered (x, y, z, q), or null to read x/q
     const double *x, *q;       // original-order SoA positions and charges
     const double4 *samp;       // [P]
-    double2 *part;             // [nchunk][P]
+    double2 *part;             // [nchunk][P] partial sums per (group, sample)
     double2 *rho;              // [P]
     double2 *gk;               // [P] coef * rho
     double *eF;                // [P] coef |rho|^2 / 2
     double *rho_out;           // [P][2] or null
     int mixed;
-    SinCosPoly sc;
+    const double2 *tab;        // [kPhaseTab] (sin, cos)(2 pi j / kPhaseTab) (FP64 path)
+    SinCosShort ss;
 };
 hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st);
 hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st);
@@ -159,7 +160,8 @@ struct FarArgs {
     double *kepart;            // [far_blocks(N)] kinetic-energy partials (when v)
     int *flag;                 // set to 1 on a non-finite force
     int mixed;
-    SinCosPoly sc;
+    const double2 *tab;        // [kPhaseTab] (sin, cos)(2 pi j / kPhaseTab) (FP64 path)
+    SinCosShort ss;
 };
 hipError_t launch_far(const FarArgs &a, hipStream_t st);
 
