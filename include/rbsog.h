@@ -259,6 +259,65 @@ int rbsog_timing_read(rbsog_handle *h, rbsog_timing *out);
 /* Releases the host-side handle (the caller still owns the workspace). */
 void rbsog_destroy(rbsog_handle *h);
 
+/* ------------------------------------------------------------------------
+ * Served ensemble (Algorithm 2 for many independent systems at once)
+ * ------------------------------------------------------------------------
+ * Replicas -- independent systems of their own size, screening, temperature,
+ * precision and seed, each running Algorithm 2 for a given number of steps --
+ * are admitted into a device pool the ensemble owns, advanced together one
+ * step per rbsog_ens_step (every step kernel is launched once for all active
+ * replicas, over a (replica, workgroup) work list), and retired when done.
+ * A replica's step n (n = 1 .. nsteps) is exactly the step of one system
+ * (rbsog_step with step0 = 0): force-evaluation index 0 for the initial force,
+ * computed at admission, and n for the force after the n-th drift, with the
+ * replica's own seed and replica id keying the modes.  Not thread-safe: one
+ * host thread drives an ensemble.  All device work is on the given stream. */
+typedef struct rbsog_ens rbsog_ens;
+
+/* Allocates the pool (hbm_budget bytes, rounded down to 256) and room for
+ * max_slots resident replicas.  Errors: RBSOG_EINVAL, RBSOG_EHIP (the pool
+ * could not be allocated), RBSOG_ENOMEM. */
+int rbsog_ens_create(size_t hbm_budget, int max_slots, void *hip_stream, rbsog_ens **out);
+
+/* Admits one replica: copies x, v (SoA [3][N]), q, m ([N]) from host memory
+ * into the pool, computes its initial force and queues it for nsteps steps of
+ * length dt.  *slot_out receives its slot.  Synchronises the stream.
+ * Errors: RBSOG_EAGAIN (no free slot, or no contiguous pool range for its
+ * workspace + state + energy history: retry after a retirement),
+ * RBSOG_EINVAL, RBSOG_ENOROOT, RBSOG_EHIP. */
+int rbsog_ens_admit(rbsog_ens *e, const rbsog_params *p, const rbsog_sog *sog, const double *x_host,
+                    const double *v_host, const double *q_host, const double *m_host, int nsteps, double dt,
+                    int *slot_out);
+
+/* Enqueues one step of every active replica (nothing when none is active);
+ * asynchronous.  Errors: RBSOG_EINVAL, RBSOG_EHIP. */
+int rbsog_ens_step(rbsog_ens *e);
+
+/* Writes into done_slots (room for max_slots) the slots whose last step has
+ * completed on the device and were not reported before; *n_done their count.
+ * Does not wait.  Errors: RBSOG_EINVAL, RBSOG_EHIP. */
+int rbsog_ens_poll(rbsog_ens *e, int *done_slots, int *n_done);
+
+/* Copies a finished replica out (any of x_host, v_host [3][N] and
+ * energy_hist_host [nsteps][6], rows as rbsog_compute_forces' energy_out of
+ * steps 1..nsteps, may be null) and frees its slot and pool range.
+ * Synchronises.  Errors: RBSOG_EINVAL (no such slot, or steps left),
+ * RBSOG_ENONFINITE (the replica produced a non-finite force or an over-long
+ * step; its slot is freed all the same), RBSOG_EHIP. */
+int rbsog_ens_retire(rbsog_ens *e, int slot, double *x_host, double *v_host, double *energy_hist_host);
+
+/* Resident replicas (active or finished, not yet retired), active replicas,
+ * ensemble steps launched so far, free pool bytes (any may be null). */
+int rbsog_ens_status(const rbsog_ens *e, int *resident, int *active, uint64_t *ens_steps, size_t *pool_free);
+
+/* Milliseconds from rbsog_ens_create to the device completion of ensemble
+ * step ens_step (1-based, one of the last 8192 launched); waits for it.
+ * Errors: RBSOG_EINVAL, RBSOG_EHIP. */
+int rbsog_ens_step_time(rbsog_ens *e, uint64_t ens_step, double *ms);
+
+/* Waits for the stream and frees the pool and every resident replica. */
+void rbsog_ens_destroy(rbsog_ens *e);
+
 /* Thread-local message describing the last failing call. */
 const char *rbsog_last_error(void);
 

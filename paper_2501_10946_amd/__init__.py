@@ -87,6 +87,16 @@ def lib() -> C.CDLL:
             "rbsog_timing_enable": (C.c_int, [_p, C.c_int]),
             "rbsog_timing_read": (C.c_int, [_p, C.POINTER(rbsog_timing)]),
             "rbsog_destroy": (None, [_p]),
+            "rbsog_ens_create": (C.c_int, [C.c_size_t, C.c_int, _p, C.POINTER(_p)]),
+            "rbsog_ens_admit": (C.c_int, [_p, C.POINTER(rbsog_params), C.POINTER(rbsog_sog), _p, _p, _p, _p, C.c_int,
+                                          C.c_double, C.POINTER(C.c_int)]),
+            "rbsog_ens_step": (C.c_int, [_p]),
+            "rbsog_ens_poll": (C.c_int, [_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+            "rbsog_ens_retire": (C.c_int, [_p, C.c_int, _p, _p, _p]),
+            "rbsog_ens_status": (C.c_int, [_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_uint64),
+                                           C.POINTER(C.c_size_t)]),
+            "rbsog_ens_step_time": (C.c_int, [_p, C.c_uint64, C.POINTER(C.c_double)]),
+            "rbsog_ens_destroy": (None, [_p]),
             "rbsog_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -233,6 +243,65 @@ def rbsog_timing_read(h) -> dict:
 def rbsog_destroy(h) -> None:
     _sizes.pop(h.value if isinstance(h, C.c_void_p) else h, None)
     lib().rbsog_destroy(h)
+
+
+# --- served ensemble -----------------------------------------------------------
+
+def _hptr(a, numel: int):
+    """Host pointer of a contiguous float64 numpy array of at least numel elements."""
+    import numpy as np
+    if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous:
+        raise ValueError("expected a contiguous float64 numpy array")
+    if a.size < numel:
+        raise ValueError(f"expected at least {numel} elements, got {a.size}")
+    return C.c_void_p(a.ctypes.data)
+
+
+def rbsog_ens_create(hbm_budget: int, max_slots: int, stream=None) -> C.c_void_p:
+    e = _p()
+    _check(lib().rbsog_ens_create(hbm_budget, max_slots, stream if stream is not None else _stream(), C.byref(e)))
+    return e
+
+
+def rbsog_ens_admit(e, params: rbsog_params, sog: rbsog_sog, x, v, q, m, nsteps: int, dt: float) -> int:
+    """Slot of the admitted replica; raises RbsogError (code RBSOG_EAGAIN) when it does not fit now."""
+    N = int(params.N)
+    slot = C.c_int(-1)
+    _check(lib().rbsog_ens_admit(e, C.byref(params), C.byref(sog), _hptr(x, 3 * N), _hptr(v, 3 * N), _hptr(q, N),
+                                 _hptr(m, N), nsteps, dt, C.byref(slot)))
+    return slot.value
+
+
+def rbsog_ens_step(e) -> None:
+    _check(lib().rbsog_ens_step(e))
+
+
+def rbsog_ens_poll(e, max_slots: int) -> list:
+    buf = (C.c_int * max(1, max_slots))()
+    n = C.c_int(0)
+    _check(lib().rbsog_ens_poll(e, buf, C.byref(n)))
+    return [buf[i] for i in range(n.value)]
+
+
+def rbsog_ens_retire(e, slot: int, x=None, v=None, energy_hist=None) -> None:
+    ptr = lambda a: None if a is None else _hptr(a, 0)
+    _check(lib().rbsog_ens_retire(e, slot, ptr(x), ptr(v), ptr(energy_hist)))
+
+
+def rbsog_ens_status(e) -> dict:
+    r, a, n, f = C.c_int(0), C.c_int(0), C.c_uint64(0), C.c_size_t(0)
+    _check(lib().rbsog_ens_status(e, C.byref(r), C.byref(a), C.byref(n), C.byref(f)))
+    return {"resident": r.value, "active": a.value, "ens_steps": n.value, "pool_free": f.value}
+
+
+def rbsog_ens_step_time(e, ens_step: int) -> float:
+    ms = C.c_double(0.0)
+    _check(lib().rbsog_ens_step_time(e, ens_step, C.byref(ms)))
+    return ms.value
+
+
+def rbsog_ens_destroy(e) -> None:
+    lib().rbsog_ens_destroy(e)
 
 
 class System:

@@ -12,8 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "internal.h"
-#include "launch.h"
+#include "system.h"
 
 namespace rbsog {
 
@@ -21,18 +20,10 @@ static_assert(kPhaseTable == kPhaseTab, "host and device rotation tables differ 
 
 namespace {
 thread_local std::string g_error;
-constexpr double kPi = 3.141592653589793;
-constexpr size_t kAlign = 256;
+}  // namespace
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Offsets of every buffer inside the workspace.
-struct Layout {
-    size_t lattice, cdf, coef, first, size;
-    size_t cell_id, count, cell_start, fill, tmp, order, pos, xs, tile_sum, xb;
-    size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_cnt, tab;
-    size_t total;
-};
 
 int nchunks(int64_t N, int P) { return (int)((N + rho_chunk((int)N, P) - 1) / rho_chunk((int)N, P)); }
 
@@ -46,18 +37,6 @@ CellGeom make_geom(double L, int nc)
     return g;
 }
 
-// Sizes derived from the parameters, shared by rbsog_workspace_size and
-// rbsog_create.  Two cell grids: the coarse one (cells >= r_c), which is the
-// cell list of rbsog_build_cells, and the fine one of the force evaluation
-// (cells >= (r_c + skin)/2, a 5 x 5 x 5 stencil).
-struct Derived {
-    double skin, rl;   // neighbour-list skin and radius r_c + skin
-    int nc, nf;        // coarse and fine cells per axis
-    int mmax;
-    int64_t nlat;
-    int kp;            // neighbour-list capacity per (particle, plane)
-    int sbatch;        // steps whose modes one sampling launch draws
-};
 
 // Capacity of each (particle, plane) neighbour list: 1.5x the expected count
 // of the fullest plane (a slab of width w through the list sphere) plus 24;
@@ -156,13 +135,7 @@ int check_params(const rbsog_params *p, const rbsog_sog *s)
     return RBSOG_OK;
 }
 
-#define HIPCHECK(call)                                                                          \
-    do {                                                                                        \
-        hipError_t e_ = (call);                                                                 \
-        if (e_ != hipSuccess) return fail(RBSOG_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
 
-}  // namespace
 
 int fail(int code, const char *fmt, ...)
 {
@@ -179,42 +152,7 @@ int fail(int code, const char *fmt, ...)
 
 using namespace rbsog;
 
-struct rbsog_handle {
-    rbsog_params p;
-    rbsog_sog sog;
-    const double *q, *m;
-    hipStream_t st;
-    Derived d;
-    CellGeom g;   // coarse grid (rbsog_build_cells)
-    CellGeom gf;  // fine grid (force evaluation)
-    int nshell;
-    double S, V, Q1, Q2, Uk0, Uself, Ubg;
-    Layout lay;
-    char *ws;
-    SogDev sd;
-    // views into the workspace
-    int32_t *lattice, *first, *size, *cell_id, *count, *cell_start, *fill, *tmp, *order, *pos, *flag, *tile_sum;
-    double *cdf, *coef, *eF, *fnear, *epart, *kepart, *energy, *xb;
-    double4 *xs, *samp;
-    double2 *part, *rho, *gk, *tab;
-    int32_t *nbr, *nbr_cnt;
-    int32_t *gate;       // device, two words: rebuild the cell order and lists in this step
-                         // (steps alternate between them; each step clears the other)
-    int32_t *ticket;     // device: the scan's finished-tile counter
-    int phase;           // which gate word the next step uses
-    bool lists_valid;    // cell order and lists in the workspace belong to the fine grid
-    uint64_t samp_step;  // first step of the modes in samp, with samp_n steps drawn
-    int samp_n;
-    // per-kernel event timing (rbsog_timing_enable)
-    bool timing = false;
-    std::vector<hipEvent_t> events;
-    std::vector<std::pair<int, int>> records;  // (kernel class, index of the start event)
-    int used = 0;
-    double ms[RBSOG_NUM_KERNEL_CLASSES] = {};
-    int64_t launches[RBSOG_NUM_KERNEL_CLASSES] = {};
-};
-
-namespace {
+namespace rbsog {
 
 enum KernelClass { kCells = 0, kKickDrift, kSample, kRhoPartial, kRhoReduce, kNear, kFar, kEnergy, kNlist };
 constexpr int kTimingEvents = 4096;
@@ -237,26 +175,6 @@ hipError_t harvest(rbsog_handle *h)
     return hipSuccess;
 }
 
-// Runs one launcher; when timing is on, brackets it with events on the stream.
-template <class F>
-hipError_t timed(rbsog_handle *h, int cls, F &&launch)
-{
-    if (!h->timing) return launch();
-    if (h->used + 2 > (int)h->events.size()) {
-        hipError_t e = harvest(h);
-        if (e != hipSuccess) return e;
-    }
-    int s = h->used;
-    hipError_t e = hipEventRecord(h->events[s], h->st);
-    if (e != hipSuccess) return e;
-    e = launch();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(h->events[s + 1], h->st);
-    if (e != hipSuccess) return e;
-    h->records.emplace_back(cls, s);
-    h->used += 2;
-    return hipSuccess;
-}
 
 CellArgs cell_args(rbsog_handle *h, const double *x, const CellGeom &g, const int32_t *gate, double *xb)
 {
@@ -372,15 +290,8 @@ int modes(rbsog_handle *h, uint64_t step, int ahead, const double4 **samp)
     return RBSOG_OK;
 }
 
-// Structure factors, near field, far field (+ optional kick) and the energy
-// sums of one evaluation whose cell order, lists and modes are prepared.
-int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, double *v, double dt, double *energy)
+FarArgs far_args(rbsog_handle *h, const double4 *samp, double *f, double *f_near, double *v, double dt)
 {
-    RhoArgs ra = rho_args(h, samp);
-    HIPCHECK(timed(h, kRhoPartial, [&] { return launch_rho_partial(ra, h->st); }));
-    HIPCHECK(timed(h, kRhoReduce, [&] { return launch_rho_reduce(ra, h->st); }));
-    NearArgs na = near_args(h, nullptr, energy != nullptr);
-    HIPCHECK(timed(h, kNear, [&] { return launch_near(na, h->st); }));
     FarArgs fa{};
     fa.N = (int)h->p.N;
     fa.P = h->p.P;
@@ -401,25 +312,44 @@ int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, do
     fa.mixed = h->p.precision == RBSOG_MIXED;
     fa.tab = h->tab;
     fa.ss = make_sincos_short();
+    return fa;
+}
+
+EnergyArgs energy_args(rbsog_handle *h, double *out, bool kick)
+{
+    EnergyArgs ea{};
+    ea.nnear = near_blocks((int)h->p.N);
+    ea.nfar = far_blocks((int)h->p.N);
+    ea.P = h->p.P;
+    ea.epart = h->epart;
+    ea.kepart = kick ? h->kepart : nullptr;
+    ea.eF = h->eF;
+    ea.Uk0 = h->Uk0;
+    ea.Uself = h->Uself;
+    ea.Ubg = h->Ubg;
+    ea.out = out;
+    return ea;
+}
+
+// Structure factors, near field, far field (+ optional kick) and the energy
+// sums of one evaluation whose cell order, lists and modes are prepared.
+int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, double *v, double dt, double *energy)
+{
+    RhoArgs ra = rho_args(h, samp);
+    HIPCHECK(timed(h, kRhoPartial, [&] { return launch_rho_partial(ra, h->st); }));
+    HIPCHECK(timed(h, kRhoReduce, [&] { return launch_rho_reduce(ra, h->st); }));
+    NearArgs na = near_args(h, nullptr, energy != nullptr);
+    HIPCHECK(timed(h, kNear, [&] { return launch_near(na, h->st); }));
+    FarArgs fa = far_args(h, samp, f, f_near, v, dt);
     HIPCHECK(timed(h, kFar, [&] { return launch_far(fa, h->st); }));
     if (energy) {
-        EnergyArgs ea{};
-        ea.nnear = near_blocks((int)h->p.N);
-        ea.nfar = far_blocks((int)h->p.N);
-        ea.P = h->p.P;
-        ea.epart = h->epart;
-        ea.kepart = v ? h->kepart : nullptr;
-        ea.eF = h->eF;
-        ea.Uk0 = h->Uk0;
-        ea.Uself = h->Uself;
-        ea.Ubg = h->Ubg;
-        ea.out = energy;
+        EnergyArgs ea = energy_args(h, energy, v != nullptr);
         HIPCHECK(timed(h, kEnergy, [&] { return launch_energy(ea, h->st); }));
     }
     return RBSOG_OK;
 }
 
-}  // namespace
+}  // namespace rbsog
 
 extern "C" const char *rbsog_last_error(void) { return g_error.c_str(); }
 

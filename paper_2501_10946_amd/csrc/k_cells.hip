@@ -24,10 +24,14 @@ __device__ inline bool gate_open(const int32_t *gate) { return gate == nullptr |
 // cell list: ids + counts, scan, scatter, stable rank + gather
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_cell_ids(CellArgs a)
+// Every kernel body takes its argument block and its workgroup index b within
+// the system's grid; the single-system kernels pass blockIdx.x, the ensemble
+// kernels the (replica, block) item of a work list.
+
+__device__ inline void cell_ids_body(const CellArgs &a, int b)
 {
     if (!gate_open(a.gate)) return;
-    int i = blockIdx.x * kBlock + threadIdx.x;
+    int i = b * kBlock + threadIdx.x;
     if (i >= a.N) return;
     int nc = a.g.nc;
     int cx = cell_coord(a.x[i], a.g.inv_cell, nc);
@@ -39,8 +43,6 @@ __global__ __launch_bounds__(kBlock) void k_cell_ids(CellArgs a)
 }
 
 // Exclusive scan of the cell counts in two passes.
-constexpr int kScanPer = 8;
-constexpr int kScanTile = kBlock * kScanPer;
 
 __device__ inline int32_t block_exclusive_scan_256(int32_t v, int32_t *sh, int32_t *total)
 {
@@ -61,13 +63,14 @@ __device__ inline int32_t block_exclusive_scan_256(int32_t v, int32_t *sh, int32
 
 // Pass 1: per-tile sums; the last tile to finish (a ticket counter) turns them
 // into exclusive tile offsets and resets the ticket.
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(CellArgs a, int ntiles)
+__device__ inline void scan_tiles_body(const CellArgs &a, int b)
 {
     if (!gate_open(a.gate)) return;
     __shared__ int32_t sh[kBlock];
     __shared__ int last;
     const int t = threadIdx.x;
-    int base = blockIdx.x * kScanTile + t * kScanPer;
+    const int ntiles = scan_tiles(a.g.ncell);
+    int base = b * kScanTile + t * kScanPer;
     int32_t s = 0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k)
@@ -75,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(CellArgs a, int ntiles)
     int32_t total;
     block_exclusive_scan_256(s, sh, &total);
     if (t == 0) {
-        a.tile_sum[blockIdx.x] = total;
+        a.tile_sum[b] = total;
         __threadfence();
         last = atomicAdd(a.ticket, 1) == ntiles - 1;
     }
@@ -96,11 +99,11 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(CellArgs a, int ntiles)
 
 // Pass 2: each tile scanned with its offset; also clears the scatter's fill
 // counters and the cell counts (ready for the next build).
-__global__ __launch_bounds__(kBlock) void k_scan_apply(CellArgs a)
+__device__ inline void scan_apply_body(const CellArgs &a, int b)
 {
     if (!gate_open(a.gate)) return;
     __shared__ int32_t sh[kBlock];
-    int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    int base = b * kScanTile + threadIdx.x * kScanPer;
     int32_t c[kScanPer];
     int32_t s = 0;
 #pragma unroll
@@ -109,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(CellArgs a)
         s += c[k];
     }
     int32_t total;
-    int32_t run = block_exclusive_scan_256(s, sh, &total) + a.tile_sum[blockIdx.x];
+    int32_t run = block_exclusive_scan_256(s, sh, &total) + a.tile_sum[b];
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
         if (base + k < a.g.ncell) {
@@ -119,16 +122,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(CellArgs a)
         }
         run += c[k];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.cell_start[a.g.ncell] = a.N;
+    if (b == 0 && threadIdx.x == 0) a.cell_start[a.g.ncell] = a.N;
 }
 
-int scan_tiles(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
-
 // Unordered placement into each cell's segment.
-__global__ __launch_bounds__(kBlock) void k_scatter(CellArgs a)
+__device__ inline void scatter_body(const CellArgs &a, int b)
 {
     if (!gate_open(a.gate)) return;
-    int i = blockIdx.x * kBlock + threadIdx.x;
+    int i = b * kBlock + threadIdx.x;
     if (i >= a.N) return;
     int c = a.cell_id[i];
     int slot = atomicAdd(&a.fill[c], 1);
@@ -139,16 +140,16 @@ __global__ __launch_bounds__(kBlock) void k_scatter(CellArgs a)
 // members with a smaller index, so ties keep ascending particle index whatever
 // order the scatter produced.  Gathers (x, y, z, q) into cell order and, when
 // asked, records the positions of the build.
-__global__ __launch_bounds__(kBlock) void k_rank(CellArgs a)
+__device__ inline void rank_body(const CellArgs &a, int b)
 {
     if (!gate_open(a.gate)) return;
-    int i = blockIdx.x * kBlock + threadIdx.x;
+    int i = b * kBlock + threadIdx.x;
     if (i >= a.N) return;
     int c = a.cell_id[i];
-    int b = a.cell_start[c], e = a.cell_start[c + 1];
+    int cb = a.cell_start[c], ce = a.cell_start[c + 1];
     int r = 0;
-    for (int k = b; k < e; ++k) r += (a.tmp[k] < i);
-    int p = b + r;
+    for (int k = cb; k < ce; ++k) r += (a.tmp[k] < i);
+    int p = cb + r;
     double x = a.x[i], y = a.x[a.N + i], z = a.x[2 * a.N + i];
     a.order[p] = i;
     a.pos[i] = p;
@@ -159,6 +160,12 @@ __global__ __launch_bounds__(kBlock) void k_rank(CellArgs a)
         a.xb[2 * a.N + i] = z;
     }
 }
+
+RBSOG_KERNELS(cell_ids, CellArgs, kBlock)
+RBSOG_KERNELS(scan_tiles, CellArgs, kBlock)
+RBSOG_KERNELS(scan_apply, CellArgs, kBlock)
+RBSOG_KERNELS(scatter, CellArgs, kBlock)
+RBSOG_KERNELS(rank, CellArgs, kBlock)
 
 static bool cell_args_ok(const CellArgs &a)
 {
@@ -172,10 +179,22 @@ hipError_t launch_cell_build(const CellArgs &a, hipStream_t st)
     int grid = (a.N + kBlock - 1) / kBlock;
     int nt = scan_tiles(a.g.ncell);
     hipLaunchKernelGGL(k_cell_ids, dim3(grid), dim3(kBlock), 0, st, a);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kBlock), 0, st, a, nt);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_rank, dim3(grid), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_build_batch(const CellArgs *tab, const EnsItem *per256, int n256, const EnsItem *pertile,
+                                   int ntile, hipStream_t st)
+{
+    if (!tab || (n256 > 0 && !per256) || (ntile > 0 && !pertile)) return hipErrorInvalidValue;
+    if (n256 > 0) hipLaunchKernelGGL(k_cell_ids_batch, dim3(n256), dim3(kBlock), 0, st, tab, per256);
+    if (ntile > 0) hipLaunchKernelGGL(k_scan_tiles_batch, dim3(ntile), dim3(kBlock), 0, st, tab, pertile);
+    if (ntile > 0) hipLaunchKernelGGL(k_scan_apply_batch, dim3(ntile), dim3(kBlock), 0, st, tab, pertile);
+    if (n256 > 0) hipLaunchKernelGGL(k_scatter_batch, dim3(n256), dim3(kBlock), 0, st, tab, per256);
+    if (n256 > 0) hipLaunchKernelGGL(k_rank_batch, dim3(n256), dim3(kBlock), 0, st, tab, per256);
     return hipGetLastError();
 }
 
@@ -183,13 +202,13 @@ hipError_t launch_cell_build(const CellArgs &a, hipStream_t st)
 // first half-kick + drift + wrap; writes the new position into the particle's
 // row of the cell-ordered copy, raises the rebuild gate of this step when a
 // particle has moved more than half the skin since the last build, and clears
-// the gate of the next step
+// the gate of the next step (when the caller alternates two gates)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_kick_drift(KickDriftArgs a)
+__device__ inline void kick_drift_body(const KickDriftArgs &a, int b)
 {
-    int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i == 0) *a.gate_next = 0;
+    int i = b * kBlock + threadIdx.x;
+    if (i == 0 && a.gate_next) *a.gate_next = 0;
     if (i >= a.N) return;
     const double L = a.L;
     double hm = (0.5 * a.dt) / a.m[i];
@@ -217,12 +236,20 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(KickDriftArgs a)
     if (!(d2 <= a.half_skin2)) atomicOr(a.gate, 1);
 }
 
+RBSOG_KERNELS(kick_drift, KickDriftArgs, kBlock)
+
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t st)
 {
-    if (a.N < 1 || !a.x || !a.v || !a.f || !a.m || !a.xb || !a.gate || !a.gate_next || !a.flag ||
-        (a.xs && (!a.pos || !a.q)))
+    if (a.N < 1 || !a.x || !a.v || !a.f || !a.m || !a.xb || !a.gate || !a.flag || (a.xs && (!a.pos || !a.q)))
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_kick_drift, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_drift_batch(const KickDriftArgs *tab, const EnsItem *per256, int n, hipStream_t st)
+{
+    if (!tab || !per256 || n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_kick_drift_batch, dim3(n), dim3(kBlock), 0, st, tab, per256);
     return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ constexpr int kFarThreads = 64 * kFarGroups;
 constexpr int kFarTile = 256;
 
 template <bool MIXED>
-__global__ __launch_bounds__(kFarThreads) void k_far(FarArgs a)
+__device__ inline void far_body(const FarArgs &a, int b)
 {
     __shared__ double4 sk[kFarTile];
     __shared__ double2 sg[kFarTile];
@@ -30,7 +30,8 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs a)
     __shared__ double red[64];
     const int t = threadIdx.x;
     const int g = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;   // g is uniform per wave
-    const int p = blockIdx.x * 64 + lane;
+    const int p = b * 64 + lane;
+    if (a.gate_clear && b == 0 && t == 0) *a.gate_clear = 0;
     const bool live = p < a.N;
     double4 pi = live ? a.xs[p] : make_double4(0.0, 0.0, 0.0, 0.0);
     double sx = pi.x * a.inv_L, sy = pi.y * a.inv_L, sz = pi.z * a.inv_L;
@@ -115,11 +116,31 @@ __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs a)
             if (t < off) red[t] += red[t + off];
             __syncthreads();
         }
-        if (t == 0) a.kepart[blockIdx.x] = red[0];
+        if (t == 0) a.kepart[b] = red[0];
     }
 }
 
-int far_blocks(int N) { return (N + 63) / 64; }
+template <bool MIXED>
+__global__ __launch_bounds__(kFarThreads) void k_far(FarArgs a)
+{
+    far_body<MIXED>(a, (int)blockIdx.x);
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(kFarThreads) void k_far_batch(const FarArgs *__restrict__ tab,
+                                                           const EnsItem *__restrict__ items)
+{
+    const EnsItem e = items[blockIdx.x];
+    far_body<MIXED>(tab[e.r], e.b);
+}
+
+hipError_t launch_far_batch(const FarArgs *tab, const EnsItem *items, int n, bool mixed, hipStream_t st)
+{
+    if (!tab || !items || n < 1) return hipErrorInvalidValue;
+    if (mixed) hipLaunchKernelGGL(k_far_batch<true>, dim3(n), dim3(kFarThreads), 0, st, tab, items);
+    else hipLaunchKernelGGL(k_far_batch<false>, dim3(n), dim3(kFarThreads), 0, st, tab, items);
+    return hipGetLastError();
+}
 
 hipError_t launch_far(const FarArgs &a, hipStream_t st)
 {
@@ -136,7 +157,8 @@ hipError_t launch_far(const FarArgs &a, hipStream_t st)
 // energies: fixed-order sums of the block partials
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a)
+// shift: rows of `out` to skip (the ensemble writes row shift + row0)
+__device__ inline void energy_body(const EnergyArgs &a, uint64_t shift)
 {
     __shared__ double red[kBlock];
     double un = 0.0, ke = 0.0, uf = 0.0;
@@ -150,13 +172,29 @@ __global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a)
     __syncthreads();
     ke = block_sum_256(ke, red);
     if (threadIdx.x == 0) {
-        a.out[0] = un;
-        a.out[1] = uf;
-        a.out[2] = a.Uk0;
-        a.out[3] = a.Uself;
-        a.out[4] = a.Ubg;
-        a.out[5] = ke;
+        double *o = a.out + 6 * (shift + a.row0);
+        o[0] = un;
+        o[1] = uf;
+        o[2] = a.Uk0;
+        o[3] = a.Uself;
+        o[4] = a.Ubg;
+        o[5] = ke;
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a) { energy_body(a, 0); }
+
+__global__ __launch_bounds__(kBlock) void k_energy_batch(const EnergyArgs *__restrict__ tab,
+                                                         const EnsItem *__restrict__ items, uint64_t shift)
+{
+    energy_body(tab[items[blockIdx.x].r], shift);
+}
+
+hipError_t launch_energy_batch(const EnergyArgs *tab, const EnsItem *items, int n, uint64_t shift, hipStream_t st)
+{
+    if (!tab || !items || n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_energy_batch, dim3(n), dim3(kBlock), 0, st, tab, items, shift);
+    return hipGetLastError();
 }
 
 hipError_t launch_energy(const EnergyArgs &a, hipStream_t st)

@@ -231,14 +231,15 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
 // neighbour lists
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kNearThreads) void k_nlist(NearArgs a)
+// lb: the logical workgroup (64 particles, five planes)
+__device__ inline void nlist_body(const NearArgs &a, int lb)
 {
     if (a.gate && *a.gate == 0) return;
     __shared__ Range rng[kMaxRanges][kNearThreads];
     __shared__ int32_t stage[kStage][kNearThreads];
     const int t = threadIdx.x;
     const int plane = t >> 6;
-    const int p = xcd_block(blockIdx.x, gridDim.x) * 64 + (t & 63);
+    const int p = lb * 64 + (t & 63);
     const Lane l = make_lane(a, p, plane);
     int nr = 0;
     if (p < a.N && l.gz * l.gz < a.rl2) {
@@ -319,12 +320,12 @@ __global__ __launch_bounds__(kNearThreads) void k_nlist(NearArgs a)
 // evaluation
 // ---------------------------------------------------------------------------
 
+// lb: the logical workgroup (256 particles, one of five lanes each)
 template <bool MIXED, bool ENERGY, int NG>
-__global__ __launch_bounds__(kEvalThreads) void k_near(NearArgs a)
+__device__ inline void near_body(const NearArgs &a, int lb)
 {
     __shared__ double red[kEvalThreads];
     const int t = threadIdx.x;
-    const int lb = xcd_block(blockIdx.x, gridDim.x);   // the five planes of a group share an XCD
     const int grp = lb / kNearPlanes;
     const int plane = lb - grp * kNearPlanes;
     const int p = grp * kEvalThreads + t;
@@ -392,8 +393,32 @@ __global__ __launch_bounds__(kEvalThreads) void k_near(NearArgs a)
     }
 }
 
-int nlist_blocks(int N) { return (N + 63) / 64; }
-int near_blocks(int N) { return kNearPlanes * ((N + kEvalThreads - 1) / kEvalThreads); }
+// Single system: workgroups remapped so that neighbouring groups share an XCD.
+__global__ __launch_bounds__(kNearThreads) void k_nlist(NearArgs a)
+{
+    nlist_body(a, xcd_block((int)blockIdx.x, (int)gridDim.x));
+}
+
+template <bool MIXED, bool ENERGY, int NG>
+__global__ __launch_bounds__(kEvalThreads) void k_near(NearArgs a)
+{
+    near_body<MIXED, ENERGY, NG>(a, xcd_block((int)blockIdx.x, (int)gridDim.x));
+}
+
+__global__ __launch_bounds__(kNearThreads) void k_nlist_batch(const NearArgs *__restrict__ tab,
+                                                              const EnsItem *__restrict__ items)
+{
+    const EnsItem e = items[blockIdx.x];
+    nlist_body(tab[e.r], e.b);
+}
+
+template <bool MIXED, bool ENERGY, int NG>
+__global__ __launch_bounds__(kEvalThreads) void k_near_batch(const NearArgs *__restrict__ tab,
+                                                             const EnsItem *__restrict__ items)
+{
+    const EnsItem e = items[blockIdx.x];
+    near_body<MIXED, ENERGY, NG>(tab[e.r], e.b);
+}
 
 // A launch with a missing buffer is refused on the host.
 static bool near_args_ok(const NearArgs &a)
@@ -427,6 +452,32 @@ static void launch_near_ng(const NearArgs &a, dim3 grid, hipStream_t st)
 #undef RBSOG_NEAR_NG
     default: hipLaunchKernelGGL((k_near<MIXED, ENERGY, 0>), grid, block, 0, st, a); return;
     }
+}
+
+hipError_t launch_nlist_batch(const NearArgs *tab, const EnsItem *items, int n, hipStream_t st)
+{
+    if (!tab || !items || n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_nlist_batch, dim3(n), dim3(kNearThreads), 0, st, tab, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_near_batch(const NearArgs *tab, const EnsItem *items, int n, int ng, bool mixed, bool energy,
+                             hipStream_t st)
+{
+    if (!tab || !items || n < 1 || ng < 0 || ng > 8) return hipErrorInvalidValue;
+    dim3 grid(n), block(kEvalThreads);
+#define RBSOG_NEAR_B(M, E, G) \
+    if (mixed == M && energy == E && ng == G) { \
+        hipLaunchKernelGGL((k_near_batch<M, E, G>), grid, block, 0, st, tab, items); \
+        return hipGetLastError(); \
+    }
+#define RBSOG_NEAR_BG(G) RBSOG_NEAR_B(true, true, G) RBSOG_NEAR_B(true, false, G) \
+    RBSOG_NEAR_B(false, true, G) RBSOG_NEAR_B(false, false, G)
+    RBSOG_NEAR_BG(0) RBSOG_NEAR_BG(1) RBSOG_NEAR_BG(2) RBSOG_NEAR_BG(3) RBSOG_NEAR_BG(4)
+    RBSOG_NEAR_BG(5) RBSOG_NEAR_BG(6) RBSOG_NEAR_BG(7) RBSOG_NEAR_BG(8)
+#undef RBSOG_NEAR_BG
+#undef RBSOG_NEAR_B
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_near(const NearArgs &a, hipStream_t st)

@@ -35,14 +35,14 @@ __device__ inline void rho_term(const RhoArgs &a, const double2 *tab, const doub
 }
 
 template <bool CELL, bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_rho_partial(RhoArgs a)
+__device__ inline void rho_partial_body(const RhoArgs &a, int b)
 {
     // dynamic LDS: the rotation table, then the staged particles
     extern __shared__ double4 lds[];
     double2 *tab = (double2 *)lds;
     double4 *sp = lds + kPhaseTab / 2;
     const int t = threadIdx.x;
-    const int64_t g0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t g0 = (int64_t)b * kBlock;
     const int s_lo = (int)(g0 / a.P);
     const int s_hi = (int)min((int64_t)a.nchunk - 1, (g0 + kBlock - 1) / a.P);
     const int j_lo = s_lo * a.chunk;
@@ -61,9 +61,9 @@ __global__ __launch_bounds__(kBlock) void k_rho_partial(RhoArgs a)
     if (g >= (int64_t)a.nchunk * a.P) return;
     const int s = (int)(g / a.P), l = (int)(g - (int64_t)s * a.P);
     const double4 k = a.samp[l];
-    const int b = s * a.chunk - j_lo, e = min(a.N, (s + 1) * a.chunk) - j_lo;
+    const int ib = s * a.chunk - j_lo, e = min(a.N, (s + 1) * a.chunk) - j_lo;
     double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
-    int i = b;
+    int i = ib;
     for (; i + 1 < e; i += 2) {
         rho_term<CELL, MIXED>(a, tab, k, sp[i], re0, im0);
         rho_term<CELL, MIXED>(a, tab, k, sp[i + 1], re1, im1);
@@ -72,11 +72,25 @@ __global__ __launch_bounds__(kBlock) void k_rho_partial(RhoArgs a)
     a.part[g] = make_double2(re0 + re1, im0 + im1);
 }
 
+template <bool CELL, bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_rho_partial(RhoArgs a)
+{
+    rho_partial_body<CELL, MIXED>(a, (int)blockIdx.x);
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_rho_partial_batch(const RhoArgs *__restrict__ tab,
+                                                              const EnsItem *__restrict__ items)
+{
+    const EnsItem e = items[blockIdx.x];
+    rho_partial_body<true, MIXED>(tab[e.r], e.b);
+}
+
 // One workgroup per sample: fixed-order sum of the chunk partials.
-__global__ __launch_bounds__(kBlock) void k_rho_reduce(RhoArgs a)
+__device__ inline void rho_reduce_body(const RhoArgs &a, int b)
 {
     __shared__ double red[kBlock];
-    int l = blockIdx.x;
+    int l = b;
     double re = 0.0, im = 0.0;
     for (int c = threadIdx.x; c < a.nchunk; c += kBlock) {
         double2 v = a.part[(size_t)c * a.P + l];
@@ -97,6 +111,8 @@ __global__ __launch_bounds__(kBlock) void k_rho_reduce(RhoArgs a)
         }
     }
 }
+
+RBSOG_KERNELS(rho_reduce, RhoArgs, kBlock)
 
 int rho_chunk(int N, int P)
 {
@@ -119,7 +135,7 @@ hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st)
         (lanes + kBlock - 1) / kBlock > 0x7fffffff)
         return hipErrorInvalidValue;
     dim3 grid((unsigned)((lanes + kBlock - 1) / kBlock));
-    size_t lds = sizeof(double4) * (kPhaseTab / 2 + (size_t)(255 / a.P + 2) * a.chunk);
+    size_t lds = rho_lds_bytes(a.P, a.chunk);
     if (a.xs) {
         if (a.mixed) hipLaunchKernelGGL((k_rho_partial<true, true>), grid, dim3(kBlock), lds, st, a);
         else hipLaunchKernelGGL((k_rho_partial<true, false>), grid, dim3(kBlock), lds, st, a);
@@ -137,5 +153,23 @@ hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
+
+// Ensemble: one launch over every replica's groups (items: rho_blocks per
+// replica) with the largest staging any of them needs, then the reduction
+// (items: P per replica).
+size_t rho_lds_bytes(int P, int chunk)
+{
+    return sizeof(double4) * (kPhaseTab / 2 + (size_t)(255 / P + 2) * chunk);
+}
+
+hipError_t launch_rho_batch(const RhoArgs *tab, const EnsItem *part_items, int npart, size_t lds, bool mixed,
+                            const EnsItem *red_items, int nred, hipStream_t st)
+{
+    if (!tab || !part_items || !red_items || npart < 1 || nred < 1 || lds > 65536) return hipErrorInvalidValue;
+    if (mixed) hipLaunchKernelGGL((k_rho_partial_batch<true>), dim3(npart), dim3(kBlock), lds, st, tab, part_items);
+    else hipLaunchKernelGGL((k_rho_partial_batch<false>), dim3(npart), dim3(kBlock), lds, st, tab, part_items);
+    hipLaunchKernelGGL(k_rho_reduce_batch, dim3(nred), dim3(kBlock), 0, st, tab, red_items);
+    return hipGetLastError();
+}
 
 }  // namespace rbsog

@@ -10,13 +10,16 @@ namespace rbsog {
 // steps), for a batch of consecutive steps in one launch
 // ---------------------------------------------------------------------------
 
-__global__ void k_sample(SampleArgs a)
+constexpr int kSampleThreads = 64;
+
+// Draw idx of the launch: mode l of step a.step + shift + s, idx = s P + l.
+__device__ inline void sample_body(const SampleArgs &a, int b, uint64_t shift)
 {
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t idx = (int64_t)b * kSampleThreads + threadIdx.x;
     if (idx >= (int64_t)a.P * a.nstep) return;
     int s = (int)(idx / a.P), l = (int)(idx - (int64_t)s * a.P);
     uint64_t w[4];
-    philox4x64_10((uint64_t)l, a.step + (uint64_t)s, 0, 0, a.seed, (uint64_t)a.replica, w);
+    philox4x64_10((uint64_t)l, a.step + shift + (uint64_t)s, 0, 0, a.seed, (uint64_t)a.replica, w);
     double u = (double)(w[0] >> 11) * 0x1p-53;
     double target = u * a.S;
     int lo = 0, hi = a.nshell;
@@ -38,13 +41,32 @@ __global__ void k_sample(SampleArgs a)
     if (a.coef_out) a.coef_out[l] = cf;
 }
 
+__global__ __launch_bounds__(kSampleThreads) void k_sample(SampleArgs a) { sample_body(a, (int)blockIdx.x, 0); }
+
+// Ensemble: one step per replica, the replica's step being its table entry's
+// step plus the launch's shift (the ensemble step counter).
+__global__ __launch_bounds__(kSampleThreads) void k_sample_batch(const SampleArgs *__restrict__ tab,
+                                                                 const EnsItem *__restrict__ items, uint64_t shift)
+{
+    const EnsItem e = items[blockIdx.x];
+    sample_body(tab[e.r], e.b, shift);
+}
+
+hipError_t launch_sample_batch(const SampleArgs *tab, const EnsItem *items, int n, uint64_t shift, hipStream_t st)
+{
+    if (!tab || !items || n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sample_batch, dim3(n), dim3(kSampleThreads), 0, st, tab, items, shift);
+    return hipGetLastError();
+}
+
 hipError_t launch_sample(const SampleArgs &a, hipStream_t st)
 {
     if (a.P < 1 || a.nstep < 1 || a.nshell < 1 || !a.cdf || !a.coef || !a.first || !a.size || !a.lattice ||
         !a.samp || (a.nstep > 1 && (a.n_out || a.coef_out)))
         return hipErrorInvalidValue;
     int64_t n = (int64_t)a.P * a.nstep;
-    hipLaunchKernelGGL(k_sample, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)((n + kSampleThreads - 1) / kSampleThreads)), dim3(kSampleThreads),
+                       0, st, a);
     return hipGetLastError();
 }
 

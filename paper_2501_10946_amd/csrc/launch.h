@@ -12,8 +12,28 @@
 namespace rbsog {
 
 constexpr int kBlock = 256;        // threads per workgroup of the streaming and pair kernels
+constexpr int kScanPer = 8;        // cell counts per thread of the scan
+constexpr int kScanTile = kBlock * kScanPer;
 constexpr int kRhoChunkMax = 256;  // particles per structure-factor group (at most)
 constexpr int kMaxGauss = 32;
+
+// One workgroup of a batched (ensemble) launch: replica slot r, workgroup b of
+// that replica's own grid.
+struct EnsItem {
+    int32_t r, b;
+};
+
+// A kernel body `name##_body(const Args &, int b)` gives two kernels: k_name
+// for one system (b = blockIdx.x) and k_name_batch over the items of a work
+// list, each reading its replica's argument block from a device table.
+#define RBSOG_KERNELS(name, Args, threads)                                                               \
+    __global__ __launch_bounds__(threads) void k_##name(Args a) { name##_body(a, (int)blockIdx.x); }     \
+    __global__ __launch_bounds__(threads) void k_##name##_batch(const Args *__restrict__ tab,             \
+                                                               const EnsItem *__restrict__ items)      \
+    {                                                                                                    \
+        const EnsItem e = items[blockIdx.x];                                                             \
+        name##_body(tab[e.r], e.b);                                                                      \
+    }
 
 // SOG coefficients as the kernels need them.
 struct SogDev {
@@ -51,10 +71,14 @@ struct CellArgs {
     const int32_t *gate;   // null: always build; else build only when *gate != 0
     double *xb;            // null, or SoA [3][N] positions recorded at the build
 };
-int scan_tiles(int ncell);
+__host__ __device__ inline int scan_tiles(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
 // ids + counts, scan (which leaves the counts zero again), scatter, stable rank
 // + gather; `count` must be zero on entry
 hipError_t launch_cell_build(const CellArgs &a, hipStream_t st);
+// the same for every replica of a work list: per256 has ceil(N/256) items per
+// replica, pertile scan_tiles(ncell)
+hipError_t launch_cell_build_batch(const CellArgs *tab, const EnsItem *per256, int n256, const EnsItem *pertile,
+                                   int ntile, hipStream_t st);
 hipError_t launch_set_int(int32_t *p, int32_t v, hipStream_t st);
 
 // --- integration ------------------------------------------------------------
@@ -67,13 +91,14 @@ struct KickDriftArgs {
     const double *xb;      // SoA [3][N] positions at the last list build
     double half_skin2;     // (skin / 2)^2
     int32_t *gate;         // raised when a particle moved more than skin / 2 since the build
-    int32_t *gate_next;    // the next step's gate, cleared
+    int32_t *gate_next;    // null, or the next step's gate, cleared
     int *flag;             // set to 1 on a step of a box length or more
     double4 *xs;           // null, or the cell-ordered copy to write the new positions into
     const int32_t *pos;    // [N] original index -> cell order (when xs)
     const double *q;       // [N] (when xs)
 };
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t st);
+hipError_t launch_kick_drift_batch(const KickDriftArgs *tab, const EnsItem *per256, int n, hipStream_t st);
 
 // --- sampling ----------------------------------------------------------------
 struct SampleArgs {
@@ -93,6 +118,8 @@ struct SampleArgs {
     double *coef_out;          // [P] or null (nstep == 1)
 };
 hipError_t launch_sample(const SampleArgs &a, hipStream_t st);
+// ensemble: items of 64 draws, ceil(P/64) per replica, nstep = 1
+hipError_t launch_sample_batch(const SampleArgs *tab, const EnsItem *items, int n, uint64_t shift, hipStream_t st);
 
 // --- structure factors -----------------------------------------------------------
 struct RhoArgs {
@@ -112,6 +139,13 @@ struct RhoArgs {
 };
 hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st);
 hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st);
+// workgroups of the partial kernel and its dynamic LDS bytes
+__host__ __device__ inline int64_t rho_blocks(int nchunk, int P) { return ((int64_t)nchunk * P + kBlock - 1) / kBlock; }
+size_t rho_lds_bytes(int P, int chunk);
+// ensemble: partials (rho_blocks items per replica, lds = the largest
+// rho_lds_bytes), then the reduction (P items per replica)
+hipError_t launch_rho_batch(const RhoArgs *tab, const EnsItem *part_items, int npart, size_t lds, bool mixed,
+                            const EnsItem *red_items, int nred, hipStream_t st);
 
 // --- near field ------------------------------------------------------------
 struct NearArgs {
@@ -136,9 +170,16 @@ struct NearArgs {
     const int32_t *gate;       // list build: null = always, else only when *gate != 0
 };
 hipError_t launch_nlist(const NearArgs &a, hipStream_t st);
-int nlist_blocks(int N);
-int near_blocks(int N);
-int far_blocks(int N);
+// workgroups per system: list build (64 particles x 5 planes), evaluation
+// (256 particles x one of 5 lanes), far field (64 particles)
+__host__ __device__ inline int nlist_blocks(int N) { return (N + 63) / 64; }
+__host__ __device__ inline int near_blocks(int N) { return 5 * ((N + 255) / 256); }
+__host__ __device__ inline int far_blocks(int N) { return (N + 63) / 64; }
+// ensemble: list builds (nlist_blocks items per replica); evaluations of the
+// replicas with `ng` Gaussians (0: any count, read at run time)
+hipError_t launch_nlist_batch(const NearArgs *tab, const EnsItem *items, int n, hipStream_t st);
+hipError_t launch_near_batch(const NearArgs *tab, const EnsItem *items, int n, int ng, bool mixed, bool energy,
+                             hipStream_t st);
 // Particles per structure-factor partial for a system of N particles and P samples.
 int rho_chunk(int N, int P);
 hipError_t launch_near(const NearArgs &a, hipStream_t st);
@@ -162,8 +203,11 @@ struct FarArgs {
     int mixed;
     const double2 *tab;        // [kPhaseTab] (sin, cos)(2 pi j / kPhaseTab) (FP64 path)
     SinCosShort ss;
+    int32_t *gate_clear;       // null, or a rebuild gate to clear (nothing later in the step reads it)
 };
 hipError_t launch_far(const FarArgs &a, hipStream_t st);
+// ensemble: far_blocks items per replica
+hipError_t launch_far_batch(const FarArgs *tab, const EnsItem *items, int n, bool mixed, hipStream_t st);
 
 // --- energies ---------------------------------------------------------------
 struct EnergyArgs {
@@ -172,9 +216,12 @@ struct EnergyArgs {
     const double *kepart;      // [nfar] or null
     const double *eF;          // [P]
     double Uk0, Uself, Ubg;
-    double *out;               // [6]
+    double *out;               // [rows][6]; one system writes row row0
+    uint64_t row0;
 };
 hipError_t launch_energy(const EnergyArgs &a, hipStream_t st);
+// ensemble: one item per replica; each writes row shift + row0 of its out
+hipError_t launch_energy_batch(const EnergyArgs *tab, const EnsItem *items, int n, uint64_t shift, hipStream_t st);
 
 
 }  // namespace rbsog

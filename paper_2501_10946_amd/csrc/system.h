@@ -1,0 +1,130 @@
+// The single-system state of librbsog behind the opaque rbsog_handle, and the
+// host helpers that size, describe and launch it.  Shared by the C-ABI of one
+// system and the served ensemble; nothing here is part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+#include "launch.h"
+
+namespace rbsog {
+
+constexpr double kPi = 3.141592653589793;
+constexpr size_t kAlign = 256;
+
+#define HIPCHECK(call)                                                                          \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) return fail(RBSOG_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Offsets of every buffer inside the workspace.
+struct Layout {
+    size_t lattice, cdf, coef, first, size;
+    size_t cell_id, count, cell_start, fill, tmp, order, pos, xs, tile_sum, xb;
+    size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_cnt, tab;
+    size_t total;
+};
+
+// Sizes derived from the parameters, shared by rbsog_workspace_size and
+// rbsog_create.  Two cell grids: the coarse one (cells >= r_c), which is the
+// cell list of rbsog_build_cells, and the fine one of the force evaluation
+// (cells >= (r_c + skin)/2, a 5 x 5 x 5 stencil).
+struct Derived {
+    double skin, rl;   // neighbour-list skin and radius r_c + skin
+    int nc, nf;        // coarse and fine cells per axis
+    int mmax;
+    int64_t nlat;
+    int kp;            // neighbour-list capacity per (particle, plane)
+    int sbatch;        // steps whose modes one sampling launch draws
+};
+
+size_t align_up(size_t v);
+int nchunks(int64_t N, int P);
+CellGeom make_geom(double L, int nc);
+Derived derive(const rbsog_params *p, const rbsog_sog *s);
+Layout make_layout(int64_t N, const Derived &d, int P);
+int check_params(const rbsog_params *p, const rbsog_sog *s);
+
+}  // namespace rbsog
+
+struct rbsog_handle {
+    using Derived = rbsog::Derived;
+    using CellGeom = rbsog::CellGeom;
+    using Layout = rbsog::Layout;
+    using SogDev = rbsog::SogDev;
+    rbsog_params p;
+    rbsog_sog sog;
+    const double *q, *m;
+    hipStream_t st;
+    Derived d;
+    CellGeom g;   // coarse grid (rbsog_build_cells)
+    CellGeom gf;  // fine grid (force evaluation)
+    int nshell;
+    double S, V, Q1, Q2, Uk0, Uself, Ubg;
+    Layout lay;
+    char *ws;
+    SogDev sd;
+    // views into the workspace
+    int32_t *lattice, *first, *size, *cell_id, *count, *cell_start, *fill, *tmp, *order, *pos, *flag, *tile_sum;
+    double *cdf, *coef, *eF, *fnear, *epart, *kepart, *energy, *xb;
+    double4 *xs, *samp;
+    double2 *part, *rho, *gk, *tab;
+    int32_t *nbr, *nbr_cnt;
+    int32_t *gate;       // device, two words: rebuild the cell order and lists in this step
+                         // (steps alternate between them; each step clears the other)
+    int32_t *ticket;     // device: the scan's finished-tile counter
+    int phase;           // which gate word the next step uses
+    bool lists_valid;    // cell order and lists in the workspace belong to the fine grid
+    uint64_t samp_step;  // first step of the modes in samp, with samp_n steps drawn
+    int samp_n;
+    // per-kernel event timing (rbsog_timing_enable)
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    std::vector<std::pair<int, int>> records;  // (kernel class, index of the start event)
+    int used = 0;
+    double ms[RBSOG_NUM_KERNEL_CLASSES] = {};
+    int64_t launches[RBSOG_NUM_KERNEL_CLASSES] = {};
+};
+
+namespace rbsog {
+
+
+hipError_t harvest(rbsog_handle *h);
+
+// Runs one launcher; when timing is on, brackets it with events on the stream.
+template <class F>
+hipError_t timed(rbsog_handle *h, int cls, F &&launch)
+{
+    if (!h->timing) return launch();
+    if (h->used + 2 > (int)h->events.size()) {
+        hipError_t e = harvest(h);
+        if (e != hipSuccess) return e;
+    }
+    int s = h->used;
+    hipError_t e = hipEventRecord(h->events[s], h->st);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(h->events[s + 1], h->st);
+    if (e != hipSuccess) return e;
+    h->records.emplace_back(cls, s);
+    h->used += 2;
+    return hipSuccess;
+}
+
+CellArgs cell_args(rbsog_handle *h, const double *x, const CellGeom &g, const int32_t *gate, double *xb);
+NearArgs near_args(rbsog_handle *h, const int32_t *gate, bool energy);
+SampleArgs sample_args(rbsog_handle *h, uint64_t step, int nstep);
+RhoArgs rho_args(rbsog_handle *h, const double4 *samp);
+FarArgs far_args(rbsog_handle *h, const double4 *samp, double *f, double *f_near, double *v, double dt);
+EnergyArgs energy_args(rbsog_handle *h, double *out, bool kick);
+int prepare(rbsog_handle *h, const double *x, const int32_t *gate);
+int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, double *v, double dt, double *energy);
+
+}  // namespace rbsog
