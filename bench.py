@@ -80,6 +80,120 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def energy_drift(E, dt: float, scale: float) -> dict:
+    """Least-squares slope of the per-step total energy (in units of `scale`,
+    N k_B T) per unit time, with its standard error, and the spread."""
+    import numpy as np
+    t = dt * np.arange(1, len(E) + 1)
+    y = np.asarray(E) / scale
+    A = np.vstack([t, np.ones_like(t)]).T
+    coef, res, _, _ = np.linalg.lstsq(A, y, rcond=None)
+    n = len(y)
+    resid = y - A @ coef
+    s2 = float(resid @ resid) / max(1, n - 2)
+    se = (s2 / float(((t - t.mean()) ** 2).sum())) ** 0.5
+    return {"steps": n, "slope_NkT_per_time": float(coef[0]), "stderr": se, "std_NkT": float(np.std(y))}
+
+
+def serve(args, dev, log):
+    """The served ensemble: seeded requests (N log-uniform in [500, 5e4], Gamma
+    log-uniform in [0.1, 100], kappa uniform in [0.1, 2], r_c 4, P 200, 100
+    steps, mixed precision) admitted into one ensemble.  First all at t = 0
+    (saturated capacity), then Poisson arrivals at fractions of that capacity,
+    then a small pool that forces queueing."""
+    import numpy as np
+    import torch
+
+    import paper_2501_10946_amd as R
+    import workloads
+
+    reqs = workloads.served_requests(args.serve_requests)
+    prep = []
+    for i, (_, w) in enumerate(reqs):
+        st = workloads.make_state(w)
+        sog = R.rbsog_sog_init(w.lam, w.r_c, w.eps)
+        params = R.make_params(w.N, w.L, w.kT, w.P, 104, i, 0, R.RBSOG_MIXED)
+        prep.append((w, st, sog, params))
+    total_ps = sum(w.N * w.steps for w, _, _, _ in prep)
+    need = [R.rbsog_ens_bytes(p, sg, w.steps) for w, _, sg, p in prep]
+    free, _ = torch.cuda.mem_get_info(dev)
+    log(f"[serve] {len(prep)} requests, {sum(w.N for w, *_ in prep)} particles, "
+        f"{sum(need) / 2**30:.2f} GiB of replica state, {free / 2**30:.1f} GiB free")
+
+    def run(arrivals, budget, max_slots):
+        ens = R.rbsog_ens_create(budget, max_slots)
+        try:
+            pending = list(range(len(prep)))
+            slot_req, t_adm, t_done, active_at = {}, {}, {}, []
+            done = 0
+            t0 = time.perf_counter()
+            while done < len(prep):
+                now = time.perf_counter() - t0
+                while pending and arrivals[pending[0]] <= now:
+                    i = pending[0]
+                    w, st, sg, p = prep[i]
+                    try:
+                        slot = R.rbsog_ens_admit(ens, p, sg, np.ascontiguousarray(st.x), np.ascontiguousarray(st.v),
+                                                 np.ascontiguousarray(st.q), np.ascontiguousarray(st.m), w.steps,
+                                                 w.dt)
+                    except R.RbsogError as e:
+                        if e.code != R.RBSOG_EAGAIN:
+                            raise
+                        break
+                    slot_req[slot] = i
+                    t_adm[i] = time.perf_counter() - t0
+                    pending.pop(0)
+                stat = R.rbsog_ens_status(ens)
+                if stat["active"] > 0:
+                    active_at.append(stat["active"])
+                    R.rbsog_ens_step(ens)
+                    # stay at most two ensemble steps ahead of the device
+                    if stat["ens_steps"] >= 1:
+                        R.rbsog_ens_step_time(ens, stat["ens_steps"])
+                elif pending and arrivals[pending[0]] > now:
+                    time.sleep(min(1e-3, arrivals[pending[0]] - now))
+                else:
+                    torch.cuda.synchronize()
+                for slot in R.rbsog_ens_poll(ens, max_slots):
+                    R.rbsog_ens_retire(ens, slot)
+                    t_done[slot_req.pop(slot)] = time.perf_counter() - t0
+                    done += 1
+            wall = time.perf_counter() - t0
+            nst = R.rbsog_ens_status(ens)["ens_steps"]
+            times = np.array([R.rbsog_ens_step_time(ens, k) for k in range(1, nst + 1)])
+        finally:
+            R.rbsog_ens_destroy(ens)
+        # per (replica, step) latency: the gap between consecutive ensemble-step
+        # completions, counted once per replica active in the later step
+        gaps = np.diff(times)
+        w_gaps = np.repeat(gaps, active_at[1:len(times)]) if len(gaps) else np.zeros(1)
+        lat = np.array([t_done[i] - arrivals[i] for i in range(len(prep))])
+        return {"wall_s": wall, "ens_steps": int(nst), "particle_steps_per_s": total_ps / wall,
+                "requests_per_s": len(prep) / wall,
+                "step_ms_p50": float(np.percentile(w_gaps, 50)), "step_ms_p99": float(np.percentile(w_gaps, 99)),
+                "request_ms_p50": 1e3 * float(np.percentile(lat, 50)),
+                "request_ms_p99": 1e3 * float(np.percentile(lat, 99)),
+                "mean_active": float(np.mean(active_at)) if active_at else 0.0}
+
+    budget = int(free * 0.8)
+    zero = np.zeros(len(prep))
+    sat = run(zero, budget, len(prep))
+    log(f"[serve] saturated: {sat}")
+    out = {"workload": f"served_{len(prep)}req_mixed", "requests": len(prep), "steps_each": 100,
+           "particle_steps": total_ps, "budget_bytes": budget, "saturated": sat, "poisson": {}}
+    cap = sat["requests_per_s"]
+    for frac in [float(v) for v in args.serve_rates.split(",") if v]:
+        arr = np.array([t for t, _ in workloads.served_requests(args.serve_requests, rate=frac * cap)])
+        r = run(arr, budget, len(prep))
+        out["poisson"][f"{frac:g}"] = r
+        log(f"[serve] poisson {frac:g}x capacity ({frac * cap:.1f} req/s): {r}")
+    small = max(need) + sum(sorted(need)[: len(need) // 8])
+    r = run(zero, small, len(prep))
+    out["small_budget"] = dict(r, budget_bytes=small)
+    log(f"[serve] small pool {small / 2**20:.0f} MiB: {r}")
+    return out
+
+
 def count_pairs(x, L, rc) -> int:
     """Ordered pairs within r_c (periodic), the near field's algorithmic work."""
     from scipy.spatial import cKDTree
@@ -96,6 +210,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget for the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--drift-steps", type=int, default=500, help="NVE steps of the energy-drift runs (0: none)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-ensemble measurement")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-rates", default="0.5,0.8,1.2",
+                    help="Poisson arrival rates as fractions of the measured saturated capacity")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="MiB of an elementwise FP64 copy (y = 2x) to run first, as a known-traffic reference "
                          "for hardware byte counters")
@@ -171,8 +290,28 @@ def main():
                               for k, (t, n) in R.rbsog_timing_read(s.h).items()}
             R.rbsog_timing_enable(s.h, False)
         res["x"], res["step"] = x, step
+        # force-only rate: one evaluation (cell order and lists rebuilt, modes,
+        # structure factors, near and far field) per call at the final state
+        fo = torch.empty_like(x)
+        R.rbsog_compute_forces(s.h, step, x, fo)
+        torch.cuda.synchronize()
+        nf = max(10, args.steps // 4)
+        t0 = time.perf_counter()
+        for k in range(nf):
+            R.rbsog_compute_forces(s.h, step + k, x, fo)
+        torch.cuda.synchronize()
+        res["force_only"] = w.N * nf / (time.perf_counter() - t0)
+        # energy drift over NVE steps from the equilibrated state (untimed)
+        if args.drift_steps > 0:
+            xd, vd, fd = x_eq.clone(), v_eq.clone(), torch.empty_like(x_eq)
+            R.rbsog_compute_forces(s.h, step_eq, xd, fd)
+            ehd = torch.zeros((args.drift_steps, 6), dtype=torch.float64, device=dev)
+            R.rbsog_step(s.h, xd, vd, fd, step_eq, args.drift_steps, w.dt, ehd)
+            R.rbsog_check(s.h)
+            res["drift"] = energy_drift(ehd.sum(dim=1).cpu().numpy(), w.dt, w.N * w.kT)
         results[name] = res
-        log(f"[bench] {name}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.3f} ms/step")
+        log(f"[bench] {name}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.3f} ms/step, "
+            f"force-only {res['force_only']:.4g}/s, drift {res.get('drift')}")
 
     # ---- force error at the final FP64 state, against the FP64 oracle ----
     import oracle
@@ -262,6 +401,13 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    out["force_only"] = {"fp64": results["fp64"]["force_only"], "mixed": results["mixed"]["force_only"],
+                         "unit": "particle-evaluations/s"}
+    if "drift" in results["fp64"]:
+        out["energy_drift"] = {"fp64": results["fp64"]["drift"], "mixed": results["mixed"]["drift"],
+                               "unit": "N k_B T per unit time"}
+    if not args.no_serve:
+        out["served"] = serve(args, dev, log)
     if "kernels" in results["mixed"]:
         out["mixed"]["kernels_ms"] = {k: v["ms_per_launch"] for k, v in results["mixed"]["kernels"].items()}
     print(json.dumps(out), flush=True)

@@ -275,9 +275,16 @@ void rbsog_destroy(rbsog_handle *h);
 typedef struct rbsog_ens rbsog_ens;
 
 /* Allocates the pool (hbm_budget bytes, rounded down to 256) and room for
- * max_slots resident replicas.  Errors: RBSOG_EINVAL, RBSOG_EHIP (the pool
- * could not be allocated), RBSOG_ENOMEM. */
+ * max_slots resident replicas; the ensemble's own tables, work lists and the
+ * shared Fourier lattice are allocated beside it.  Errors: RBSOG_EINVAL,
+ * RBSOG_EHIP (the pool could not be allocated), RBSOG_ENOMEM. */
 int rbsog_ens_create(size_t hbm_budget, int max_slots, void *hip_stream, rbsog_ens **out);
+
+/* Pool bytes one replica with these parameters and step count occupies (its
+ * workspace without the Fourier lattice, which the ensemble keeps once for
+ * all replicas outside the pool, plus x, v, f, q, m and the energy history).
+ * Errors: RBSOG_EINVAL. */
+int rbsog_ens_bytes(const rbsog_params *p, const rbsog_sog *sog, int nsteps, size_t *bytes);
 
 /* Admits one replica: copies x, v (SoA [3][N]), q, m ([N]) from host memory
  * into the pool, computes its initial force and queues it for nsteps steps of

@@ -88,6 +88,8 @@ def lib() -> C.CDLL:
             "rbsog_timing_read": (C.c_int, [_p, C.POINTER(rbsog_timing)]),
             "rbsog_destroy": (None, [_p]),
             "rbsog_ens_create": (C.c_int, [C.c_size_t, C.c_int, _p, C.POINTER(_p)]),
+            "rbsog_ens_bytes": (C.c_int, [C.POINTER(rbsog_params), C.POINTER(rbsog_sog), C.c_int,
+                                          C.POINTER(C.c_size_t)]),
             "rbsog_ens_admit": (C.c_int, [_p, C.POINTER(rbsog_params), C.POINTER(rbsog_sog), _p, _p, _p, _p, C.c_int,
                                           C.c_double, C.POINTER(C.c_int)]),
             "rbsog_ens_step": (C.c_int, [_p]),
@@ -261,6 +263,12 @@ def rbsog_ens_create(hbm_budget: int, max_slots: int, stream=None) -> C.c_void_p
     e = _p()
     _check(lib().rbsog_ens_create(hbm_budget, max_slots, stream if stream is not None else _stream(), C.byref(e)))
     return e
+
+
+def rbsog_ens_bytes(params: rbsog_params, sog: rbsog_sog, nsteps: int) -> int:
+    b = C.c_size_t(0)
+    _check(lib().rbsog_ens_bytes(C.byref(params), C.byref(sog), nsteps, C.byref(b)))
+    return b.value
 
 
 def rbsog_ens_admit(e, params: rbsog_params, sog: rbsog_sog, x, v, q, m, nsteps: int, dt: float) -> int:

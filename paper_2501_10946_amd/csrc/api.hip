@@ -72,7 +72,7 @@ Derived derive(const rbsog_params *p, const rbsog_sog *s)
     return d;
 }
 
-Layout make_layout(int64_t N, const Derived &d, int P)
+Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
 {
     int ncell = std::max(d.nf * d.nf * d.nf, d.nc * d.nc * d.nc);  // either grid
     Layout L{};
@@ -82,7 +82,7 @@ Layout make_layout(int64_t N, const Derived &d, int P)
         off = align_up(off + bytes);
         return o;
     };
-    L.lattice = take(sizeof(int32_t) * (size_t)d.nlat);
+    L.lattice = take(shared_lattice ? 0 : sizeof(int32_t) * (size_t)d.nlat);
     L.cdf = take(sizeof(double) * (size_t)d.mmax);
     L.coef = take(sizeof(double) * (size_t)d.mmax);
     L.first = take(sizeof(int32_t) * (size_t)d.mmax);
@@ -358,12 +358,20 @@ extern "C" int rbsog_workspace_size(const rbsog_params *p, const rbsog_sog *s, s
     int rc = check_params(p, s);
     if (rc) return rc;
     if (!bytes) return fail(RBSOG_EINVAL, "bytes is null");
-    *bytes = make_layout(p->N, derive(p, s), p->P).total;
+    *bytes = make_layout(p->N, derive(p, s), p->P, false).total;
     return RBSOG_OK;
 }
 
 extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const double *q_dev, const double *m_dev,
                             void *ws_dev, size_t ws_bytes, void *hip_stream, rbsog_handle **out)
+{
+    return create_system(p, s, q_dev, m_dev, ws_dev, ws_bytes, (hipStream_t)hip_stream, nullptr, out);
+}
+
+namespace rbsog {
+
+int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev, const double *m_dev, void *ws_dev,
+                  size_t ws_bytes, hipStream_t stream, const int32_t *lattice_dev, rbsog_handle **out)
 {
     int rc = check_params(p, s);
     if (rc) return rc;
@@ -375,12 +383,12 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     h->sog = *s;
     h->q = q_dev;
     h->m = m_dev;
-    h->st = (hipStream_t)hip_stream;
+    h->st = stream;
     h->d = derive(p, s);
     h->g = make_geom(p->L, h->d.nc);
     h->gf = make_geom(p->L, h->d.nf);
     h->V = p->L * p->L * p->L;
-    h->lay = make_layout(p->N, h->d, p->P);
+    h->lay = make_layout(p->N, h->d, p->P, lattice_dev != nullptr);
     if (ws_bytes < h->lay.total) {
         size_t need = h->lay.total;
         delete h;
@@ -403,13 +411,13 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
         return fail(RBSOG_EINVAL, "all charges are zero");
     }
     Tables t;
-    build_tables(*s, *p, q2, h->d.mmax, &t);
+    build_tables(*s, *p, q2, h->d.mmax, &t, lattice_dev == nullptr);
     h->nshell = t.nshell;
     h->S = t.S;
     h->ws = (char *)ws_dev;
     char *w = h->ws;
     const Layout &L = h->lay;
-    h->lattice = (int32_t *)(w + L.lattice);
+    h->lattice = lattice_dev ? (int32_t *)lattice_dev : (int32_t *)(w + L.lattice);
     h->cdf = (double *)(w + L.cdf);
     h->coef = (double *)(w + L.coef);
     h->first = (int32_t *)(w + L.first);
@@ -444,7 +452,10 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     double tabh[2 * kPhaseTable];
     phase_table(tabh);
     h->lists_valid = false;
-    e = hipMemcpyAsync(h->lattice, t.packed.data(), sizeof(int32_t) * t.packed.size(), hipMemcpyHostToDevice, h->st);
+    e = hipSuccess;
+    if (!lattice_dev)
+        e = hipMemcpyAsync(h->lattice, t.packed.data(), sizeof(int32_t) * t.packed.size(), hipMemcpyHostToDevice,
+                           h->st);
     if (e == hipSuccess) e = hipMemcpyAsync(h->cdf, t.cdf.data(), sizeof(double) * t.nshell, hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess) e = hipMemcpyAsync(h->coef, t.coef.data(), sizeof(double) * t.nshell, hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess)
@@ -475,6 +486,8 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
     *out = h;
     return RBSOG_OK;
 }
+
+}  // namespace rbsog
 
 extern "C" int rbsog_get_info(const rbsog_handle *h, rbsog_info *out)
 {

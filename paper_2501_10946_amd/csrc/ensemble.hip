@@ -152,6 +152,10 @@ struct rbsog_ens {
     int nactive = 0;
     bool dirty = false;
     uint64_t E = 0;  // ensemble steps launched
+    // the packed Fourier lattice shared by every replica (a prefix serves any
+    // smaller m_max), outside the pool
+    int32_t *lat = nullptr;
+    int lat_mmax = 0;
     hipEvent_t ev0 = nullptr;
     std::vector<hipEvent_t> ev;
 };
@@ -220,6 +224,16 @@ hipError_t put(T *table, int slot, const T &v, hipStream_t st)
     return e;
 }
 
+// Pool bytes of one replica: its workspace (without the lattice), x, v, f,
+// q, m and the energy history.
+size_t replica_bytes(const rbsog_params *p, const rbsog_sog *sog, int nsteps)
+{
+    const size_t N = (size_t)p->N;
+    const size_t ws = make_layout(p->N, derive(p, sog), p->P, true).total;
+    return align_up(ws) + align_up(sizeof(double) * 3 * N) * 3 + align_up(sizeof(double) * N) * 2 +
+           align_up(sizeof(double) * 6 * (size_t)nsteps);
+}
+
 // Argument blocks of slot r (the replica was admitted with e_adm steps launched).
 int write_tables(rbsog_ens *s, int r, double dt)
 {
@@ -262,6 +276,39 @@ int write_tables(rbsog_ens *s, int r, double dt)
     EnergyArgs ea = energy_args(h, R.ehist, true);
     ea.row0 = (uint64_t)0 - R.e_adm;
     if ((e = put(s->t_energy, r, ea, s->st)) != hipSuccess) return ens_fail_hip(e, "energy table");
+    return RBSOG_OK;
+}
+
+// Makes the shared lattice cover m_max, re-pointing the resident replicas'
+// sampling tables when it moves.
+int ensure_lattice(rbsog_ens *s, int mmax)
+{
+    if (mmax <= s->lat_mmax) return RBSOG_OK;
+    int64_t n = lattice_points(mmax);
+    std::vector<int32_t> host((size_t)n);
+    lattice_copy(mmax, host.data());
+    int32_t *dev = nullptr;
+    hipError_t e = hipStreamSynchronize(s->st);   // nothing may still read the old table
+    if (e == hipSuccess) e = hipMalloc((void **)&dev, sizeof(int32_t) * (size_t)n);
+    if (e == hipSuccess) e = hipMemcpyAsync(dev, host.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    if (e != hipSuccess) {
+        if (dev) (void)hipFree(dev);
+        return ens_fail_hip(e, "uploading the lattice");
+    }
+    for (int r = 0; r < s->max_slots; ++r) {
+        Replica &R = s->rep[r];
+        if (!R.used || !R.h) continue;
+        R.h->lattice = dev;
+        SampleArgs sa = sample_args(R.h, (uint64_t)1 - R.e_adm, 1);
+        if ((e = put(s->t_samp, r, sa, s->st)) != hipSuccess) {
+            (void)hipFree(dev);
+            return ens_fail_hip(e, "sample table");
+        }
+    }
+    if (s->lat) (void)hipFree(s->lat);
+    s->lat = dev;
+    s->lat_mmax = mmax;
     return RBSOG_OK;
 }
 
@@ -313,6 +360,16 @@ extern "C" int rbsog_ens_create(size_t hbm_budget, int max_slots, void *hip_stre
     return RBSOG_OK;
 }
 
+extern "C" int rbsog_ens_bytes(const rbsog_params *p, const rbsog_sog *sog, int nsteps, size_t *bytes)
+{
+    if (!bytes) return fail(RBSOG_EINVAL, "bytes is null");
+    if (nsteps < 1) return fail(RBSOG_EINVAL, "nsteps must be >= 1");
+    int rc = check_params(p, sog);
+    if (rc) return rc;
+    *bytes = replica_bytes(p, sog, nsteps);
+    return RBSOG_OK;
+}
+
 extern "C" int rbsog_ens_admit(rbsog_ens *s, const rbsog_params *p, const rbsog_sog *sog, const double *x_host,
                                const double *v_host, const double *q_host, const double *m_host, int nsteps, double dt,
                                int *slot_out)
@@ -329,13 +386,12 @@ extern "C" int rbsog_ens_admit(rbsog_ens *s, const rbsog_params *p, const rbsog_
             break;
         }
     if (slot < 0) return fail(RBSOG_EAGAIN, "no free slot (%d resident)", s->max_slots);
-    size_t ws = 0;
-    rc = rbsog_workspace_size(p, sog, &ws);
+    const Derived d = derive(p, sog);
+    rc = ensure_lattice(s, d.mmax);
     if (rc) return rc;
+    const size_t ws = make_layout(p->N, d, p->P, true).total;
     const size_t N = (size_t)p->N;
-    const size_t state = align_up(sizeof(double) * 3 * N) * 3 + align_up(sizeof(double) * N) * 2 +
-                         align_up(sizeof(double) * 6 * (size_t)nsteps);
-    size_t bytes = align_up(ws) + state, off = 0;
+    size_t bytes = replica_bytes(p, sog, nsteps), off = 0;
     if (!s->alloc.alloc(bytes, &off))
         return fail(RBSOG_EAGAIN, "pool has no %zu contiguous bytes (%zu free)", bytes, s->alloc.free_bytes());
     Replica &R = s->rep[slot];
@@ -370,7 +426,7 @@ extern "C" int rbsog_ens_admit(rbsog_ens *s, const rbsog_params *p, const rbsog_
         drop_replica(s, slot);
         return ens_fail_hip(e, "uploading the replica");
     }
-    rc = rbsog_create(p, sog, R.q, R.m, wsp, align_up(ws), s->st, &R.h);
+    rc = create_system(p, sog, R.q, R.m, wsp, align_up(ws), s->st, s->lat, &R.h);
     if (rc) {
         drop_replica(s, slot);
         return rc;
@@ -514,6 +570,7 @@ extern "C" void rbsog_ens_destroy(rbsog_ens *s)
     for (int r = 0; r < s->max_slots; ++r)
         if (s->rep[r].h) rbsog_destroy(s->rep[r].h);
     s->items.release();
+    if (s->lat) (void)hipFree(s->lat);
     for (void *p : {(void *)s->t_kick, (void *)s->t_cell, (void *)s->t_nlist, (void *)s->t_near, (void *)s->t_samp,
                     (void *)s->t_rho, (void *)s->t_far, (void *)s->t_energy, (void *)s->pool})
         if (p) (void)hipFree(p);

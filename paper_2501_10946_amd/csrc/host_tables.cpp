@@ -3,7 +3,9 @@
 // P(k) = F(k) Fhat(k) / S.  Built with -ffp-contract=off: the cumulative
 // weights are a fixed sequence of IEEE FP64 operations, so two conforming
 // implementations produce the same bits and therefore the same samples.
+#include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 
@@ -45,32 +47,30 @@ int default_mmax(const rbsog_sog &s, double L)
     return m;
 }
 
-int64_t lattice_points(int mmax)
-{
-    int64_t total = 0;
-    int R = (int)std::sqrt((double)mmax) + 1;
-    for (int a = -R; a <= R; ++a)
-        for (int b = -R; b <= R; ++b) {
-            int64_t ab = (int64_t)a * a + (int64_t)b * b;
-            if (ab > mmax) continue;
-            for (int c = -R; c <= R; ++c) {
-                int64_t m = ab + (int64_t)c * c;
-                total += (m >= 1 && m <= mmax);
-            }
-        }
-    return total;
-}
+namespace {
 
-void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax, Tables *t)
+// Process-wide cache of the packed lattice for the largest m_max built so far:
+// all n with 1 <= |n|^2 <= m_max sorted by (|n|^2, nx, ny, nz), and the shell
+// sizes r3(m).  The list of a smaller m_max is a prefix of this one, so every
+// system (and every replica of an ensemble) reads the same table.
+struct LatticeCache {
+    std::mutex mu;
+    int mmax = 0;
+    std::vector<int32_t> packed;
+    std::vector<int64_t> size;    // [mmax + 1]
+    std::vector<int64_t> first;   // [mmax + 1] index of the shell's first point
+};
+LatticeCache g_lat;
+
+void grow_cache(int mmax)
 {
-    t->mmax = mmax;
+    LatticeCache &c = g_lat;
     int R = (int)std::sqrt((double)mmax) + 1;
-    // shell sizes r3(m)
     std::vector<int64_t> size(mmax + 1, 0);
     for (int a = -R; a <= R; ++a)
         for (int b = -R; b <= R; ++b)
-            for (int c = -R; c <= R; ++c) {
-                int64_t m = (int64_t)a * a + (int64_t)b * b + (int64_t)c * c;
+            for (int cc = -R; cc <= R; ++cc) {
+                int64_t m = (int64_t)a * a + (int64_t)b * b + (int64_t)cc * cc;
                 if (m >= 1 && m <= mmax) ++size[m];
             }
     std::vector<int64_t> first(mmax + 1, 0);
@@ -79,19 +79,54 @@ void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax
         first[m] = run;
         run += size[m];
     }
-    t->nlat = run;
-    t->packed.assign((size_t)run, 0);
+    std::vector<int32_t> packed((size_t)run, 0);
     // lexicographic (nx, ny, nz) enumeration fills each shell in sorted order
     std::vector<int64_t> fill(first);
     for (int a = -R; a <= R; ++a)
         for (int b = -R; b <= R; ++b)
-            for (int c = -R; c <= R; ++c) {
-                int64_t m = (int64_t)a * a + (int64_t)b * b + (int64_t)c * c;
+            for (int cc = -R; cc <= R; ++cc) {
+                int64_t m = (int64_t)a * a + (int64_t)b * b + (int64_t)cc * cc;
                 if (m < 1 || m > mmax) continue;
-                t->packed[(size_t)fill[m]++] = (int32_t)((uint32_t)(a + kLatticeBias) |
-                                                         ((uint32_t)(b + kLatticeBias) << 10) |
-                                                         ((uint32_t)(c + kLatticeBias) << 20));
+                packed[(size_t)fill[m]++] = (int32_t)((uint32_t)(a + kLatticeBias) |
+                                                      ((uint32_t)(b + kLatticeBias) << 10) |
+                                                      ((uint32_t)(cc + kLatticeBias) << 20));
             }
+    c.mmax = mmax;
+    c.packed.swap(packed);
+    c.size.swap(size);
+    c.first.swap(first);
+}
+
+}  // namespace
+
+int64_t lattice_points(int mmax)
+{
+    std::lock_guard<std::mutex> lock(g_lat.mu);
+    if (g_lat.mmax < mmax) grow_cache(mmax);
+    return g_lat.first[mmax] + g_lat.size[mmax];
+}
+
+void lattice_copy(int mmax, int32_t *out)
+{
+    std::lock_guard<std::mutex> lock(g_lat.mu);
+    if (g_lat.mmax < mmax) grow_cache(mmax);
+    int64_t n = g_lat.first[mmax] + g_lat.size[mmax];
+    std::copy(g_lat.packed.begin(), g_lat.packed.begin() + n, out);
+}
+
+void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax, Tables *t, bool with_lattice)
+{
+    t->mmax = mmax;
+    std::vector<int64_t> size, first;
+    {
+        std::lock_guard<std::mutex> lock(g_lat.mu);
+        if (g_lat.mmax < mmax) grow_cache(mmax);
+        size.assign(g_lat.size.begin(), g_lat.size.begin() + mmax + 1);
+        first.assign(g_lat.first.begin(), g_lat.first.begin() + mmax + 1);
+        t->nlat = first[mmax] + size[mmax];
+        if (with_lattice) t->packed.assign(g_lat.packed.begin(), g_lat.packed.begin() + t->nlat);
+        else t->packed.clear();
+    }
     // cumulative shell weights
     double tt = (2.0 * kPi) / p.L;
     double tk2 = tt * tt;

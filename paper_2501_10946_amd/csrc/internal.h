@@ -38,9 +38,13 @@ struct Tables {
 };
 
 int default_mmax(const rbsog_sog &s, double L);
+// points of the lattice up to m_max, and a copy of its packed list (both from
+// a process-wide cache that grows to the largest m_max asked for)
 int64_t lattice_points(int mmax);
+void lattice_copy(int mmax, int32_t *out);
 double density(int kind, double kT, double V, double Q2, double lambda, double k2);
-void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax, Tables *t);
+// shell CDF, coefficients and shell ranges; the packed lattice too when asked
+void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax, Tables *t, bool with_lattice);
 // (sin, cos)(2 pi j / kPhaseTable), j = 0 .. kPhaseTable - 1, interleaved, from
 // the host's libm: the rotation table of the FP64 phase kernels
 constexpr int kPhaseTable = 128;

@@ -48,7 +48,8 @@ size_t align_up(size_t v);
 int nchunks(int64_t N, int P);
 CellGeom make_geom(double L, int nc);
 Derived derive(const rbsog_params *p, const rbsog_sog *s);
-Layout make_layout(int64_t N, const Derived &d, int P);
+// shared_lattice: the packed lattice lives outside the workspace
+Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice);
 int check_params(const rbsog_params *p, const rbsog_sog *s);
 
 }  // namespace rbsog
@@ -125,6 +126,10 @@ RhoArgs rho_args(rbsog_handle *h, const double4 *samp);
 FarArgs far_args(rbsog_handle *h, const double4 *samp, double *f, double *f_near, double *v, double dt);
 EnergyArgs energy_args(rbsog_handle *h, double *out, bool kick);
 int prepare(rbsog_handle *h, const double *x, const int32_t *gate);
+// rbsog_create; with lattice_dev (the packed lattice up to at least the
+// system's m_max, owned by the caller) the workspace holds no lattice copy
+int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev, const double *m_dev, void *ws_dev,
+                  size_t ws_bytes, hipStream_t stream, const int32_t *lattice_dev, rbsog_handle **out);
 int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, double *v, double dt, double *energy);
 
 }  // namespace rbsog

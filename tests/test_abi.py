@@ -79,3 +79,23 @@ def test_host_errors(R):
         R.rbsog_workspace_size(R.make_params(1000, 16.0, 1.0, 0, 1), sog)    # P = 0
     assert e.value.code == R.RBSOG_EINVAL
     assert R.rbsog_workspace_size(R.make_params(1000, 16.1199, 1.0, 100, 1), sog) > 0
+
+
+def test_ensemble_sizing(R):
+    """A replica's pool share (host-only): its workspace without the shared
+    lattice plus state and energy history; it grows with N and steps, and bad
+    parameters are refused."""
+    sog = R.rbsog_sog_init(1.0, 3.0, 1e-4)
+    p = R.make_params(1000, 16.1199, 1.0, 100, 1)
+    b100 = R.rbsog_ens_bytes(p, sog, 100)
+    b200 = R.rbsog_ens_bytes(p, sog, 200)
+    assert b100 % 256 == 0 and b200 >= b100 + 100 * 6 * 8
+    assert b100 >= 11 * 8 * 1000
+    big = R.make_params(8000, 2 * 16.1199, 1.0, 100, 1)
+    assert R.rbsog_ens_bytes(big, sog, 100) > b100
+    with pytest.raises(R.RbsogError) as e:
+        R.rbsog_ens_bytes(p, sog, 0)
+    assert e.value.code == R.RBSOG_EINVAL
+    with pytest.raises(R.RbsogError) as e:
+        R.rbsog_ens_bytes(R.make_params(1000, 8.0, 1.0, 100, 1), sog, 10)
+    assert e.value.code == R.RBSOG_EINVAL

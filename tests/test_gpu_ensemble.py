@@ -138,7 +138,8 @@ def test_ensemble_admission_and_timeline(dev):
     W = workloads.Workload
     big = Req(W("e_big", N=3000, kappa=0.5, gamma=10.0, r_c=4.0, P=200, seed=51), 0, R.RBSOG_MIXED, 4)
     small = Req(W("e_small", N=800, kappa=1.0, gamma=1.0, r_c=3.0, P=50, seed=52), 1, R.RBSOG_FP64, 3)
-    need = R.rbsog_workspace_size(big.params, big.sog) + 11 * 8 * 3000 + 6 * 8 * 4 + 4096
+    need = R.rbsog_ens_bytes(big.params, big.sog, big.nsteps)
+    assert need < R.rbsog_workspace_size(big.params, big.sog) + 11 * 8 * 3000 + 6 * 8 * 4 + 4096
     ens = R.rbsog_ens_create(need, 4)
     try:
         slot = big.admit(ens)
