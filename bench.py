@@ -210,6 +210,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget for the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--skin", type=float, default=-1.0, help="neighbour-list skin (negative: the library default)")
     ap.add_argument("--drift-steps", type=int, default=500, help="NVE steps of the energy-drift runs (0: none)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-ensemble measurement")
     ap.add_argument("--serve-requests", type=int, default=256)
@@ -246,7 +247,8 @@ def main():
     log(f"[bench] {w.name}: N={w.N} L={w.L:.4f} P={w.P} SOG M1={sog.M1} M2={sog.M2} err={sog.max_err:.2e}")
 
     # ---- pre-equilibration (FP64, velocity rescaling to kT each step) ----
-    sys64 = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, precision=R.RBSOG_FP64, device=dev)
+    sys64 = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, precision=R.RBSOG_FP64, skin=args.skin,
+                     device=dev)
     x = torch.tensor(st.x, device=dev)
     v = torch.tensor(st.v, device=dev)
     f = torch.empty_like(x)
@@ -267,7 +269,7 @@ def main():
     results = {}
     for name, prec in (("fp64", R.RBSOG_FP64), ("mixed", R.RBSOG_MIXED)):
         s = sys64 if prec == R.RBSOG_FP64 else R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed,
-                                                         precision=prec, device=dev)
+                                                         precision=prec, skin=args.skin, device=dev)
         x, v, f = x_eq.clone(), v_eq.clone(), f_eq.clone()
         step = step_eq
         R.rbsog_compute_forces(s.h, step, x, f)

@@ -12,10 +12,10 @@
 //
 //   k_nlist  a workgroup owns 64 consecutive particles (cell order) and has 5
 //            waves, one per plane; each lane walks its candidates (four loads
-//            in flight) and stores the accepted j, in candidate order, in rows
-//            of its plane (capacity kp per plane); the five planes of each
-//            particle are then moved together into one column-major list of
-//            the particle's neighbours, plus its count;
+//            in flight) and stores the accepted j, in candidate order, in
+//            staging rows of its plane (capacity kp per plane); the five
+//            planes of each particle are then copied, all at once, into one
+//            column-major list of the particle's neighbours, plus its count;
 //   k_near   a workgroup owns 256 consecutive particles and one of five lanes
 //            per particle (4 waves); lane s evaluates entries s, s + 5, ... of
 //            the particle's list, so the five lanes get equal shares (a split
@@ -249,9 +249,9 @@ __device__ inline void nlist_body(const NearArgs &a, int lb)
             for (int k = 0; k < n; ++k) rng[nr++][t] = g[k];
         }
     }
-    // plane `plane` of particle p is stored first in rows plane*kp .. plane*kp + kp - 1
+    // plane `plane` of particle p is staged in rows plane*kp .. plane*kp + kp - 1
     const size_t N = (size_t)a.N;
-    int32_t *out = a.nbr + (size_t)plane * a.kp * N + p;
+    int32_t *out = a.nbr_stage + (size_t)plane * a.kp * N + p;
     int r = 0, total = 0;
     Cursor c{0, 0, 0.0, 0.0, 0.0};
     if (nr > 0) c = open_range(rng[0][t], l.pi, a.g.L);
@@ -280,9 +280,8 @@ __device__ inline void nlist_body(const NearArgs &a, int lb)
     } while (__any(r < nr));
 
     // Concatenate the five planes of each particle in plane order: plane r
-    // moves down to row off_r = sum of the counts of the planes before it.
-    // off_r <= r*kp, so a forward copy is safe, and the rounds run in plane
-    // order because plane r's destination may cover plane r-1's source rows.
+    // goes to rows off_r = (sum of the counts of the planes before it) onward
+    // of the final list, every plane at once (staging and list are disjoint).
     __shared__ int32_t cnts[kNearPlanes][64];
     const int lane = t & 63;
     cnts[plane][lane] = total;
@@ -296,22 +295,19 @@ __device__ inline void nlist_body(const NearArgs &a, int lb)
         off += q < plane ? c : 0;
         all += c;
     }
-    for (int r = 1; r < kNearPlanes; ++r) {
-        if (plane == r && p < a.N && !over && off < r * a.kp) {
-            int32_t *dst = a.nbr + (size_t)off * N + p;
-            const int32_t *src = a.nbr + (size_t)r * a.kp * N + p;
-            int k = 0;
-            for (; k + 4 <= total; k += 4) {
-                int32_t e0 = src[(size_t)k * N], e1 = src[(size_t)(k + 1) * N];
-                int32_t e2 = src[(size_t)(k + 2) * N], e3 = src[(size_t)(k + 3) * N];
-                dst[(size_t)k * N] = e0;
-                dst[(size_t)(k + 1) * N] = e1;
-                dst[(size_t)(k + 2) * N] = e2;
-                dst[(size_t)(k + 3) * N] = e3;
-            }
-            for (; k < total; ++k) dst[(size_t)k * N] = src[(size_t)k * N];
+    if (p < a.N && !over) {
+        int32_t *dst = a.nbr + (size_t)off * N + p;
+        const int32_t *src = out;   // this lane's own staged rows
+        int k = 0;
+        for (; k + 4 <= total; k += 4) {
+            int32_t e0 = src[(size_t)k * N], e1 = src[(size_t)(k + 1) * N];
+            int32_t e2 = src[(size_t)(k + 2) * N], e3 = src[(size_t)(k + 3) * N];
+            dst[(size_t)k * N] = e0;
+            dst[(size_t)(k + 1) * N] = e1;
+            dst[(size_t)(k + 2) * N] = e2;
+            dst[(size_t)(k + 3) * N] = e3;
         }
-        __syncthreads();
+        for (; k < total; ++k) dst[(size_t)k * N] = src[(size_t)k * N];
     }
     if (plane == 0 && p < a.N) a.nbr_cnt[p] = over ? kNearPlanes * a.kp + 1 : all;
 }
@@ -423,7 +419,8 @@ __global__ __launch_bounds__(kEvalThreads) void k_near_batch(const NearArgs *__r
 // A launch with a missing buffer is refused on the host.
 static bool near_args_ok(const NearArgs &a)
 {
-    return a.N >= 1 && a.xs && a.cell_start && a.nbr && a.nbr_cnt && a.fnear && a.kp >= 1 && a.g.nc >= 6 &&
+    return a.N >= 1 && a.xs && a.cell_start && a.nbr && a.nbr_stage && a.nbr_cnt && a.fnear && a.kp >= 1 &&
+           a.g.nc >= 6 &&
            a.rc2 > 0.0 && a.rl2 >= a.rc2 && a.w > 0.0 && (!a.energy || a.epart);
 }
 

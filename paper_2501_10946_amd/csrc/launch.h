@@ -164,6 +164,7 @@ struct NearArgs {
     double inv_L;
     Exp2Poly e2;
     int32_t *nbr;              // [5 kp][N] listed j per particle (planes concatenated), column-major
+    int32_t *nbr_stage;        // [5 kp][N] list build: rows plane*kp.. of each plane
     int32_t *nbr_cnt;          // [N] listed count per particle; 5 kp + 1 when a plane overflowed
     int kp;                    // list capacity per (particle, plane)
     double rl2;                // squared list radius (r_c + skin)^2; the fine grid has cells >= (r_c + skin)/2

@@ -27,7 +27,7 @@ constexpr size_t kAlign = 256;
 struct Layout {
     size_t lattice, cdf, coef, first, size;
     size_t cell_id, count, cell_start, fill, tmp, order, pos, xs, tile_sum, xb;
-    size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_cnt, tab;
+    size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_stage, nbr_cnt, tab;
     size_t total;
 };
 
@@ -76,7 +76,7 @@ struct rbsog_handle {
     double *cdf, *coef, *eF, *fnear, *epart, *kepart, *energy, *xb;
     double4 *xs, *samp;
     double2 *part, *rho, *gk, *tab;
-    int32_t *nbr, *nbr_cnt;
+    int32_t *nbr, *nbr_stage, *nbr_cnt;
     int32_t *gate;       // device, two words: rebuild the cell order and lists in this step
                          // (steps alternate between them; each step clears the other)
     int32_t *ticket;     // device: the scan's finished-tile counter
