@@ -108,6 +108,21 @@ int rbsog_sog_init(double lambda, double r_c, double eps, int M1, int M2, rbsog_
  */
 int rbsog_sog_expand(rbsog_sog *sog);
 
+/*
+ * The near-field pair function, eq. (3.8), as the FP64 kernels evaluate it:
+ * H(r) = r^3 [F_N1(r) + F_N2(r)] = exp(-r/lambda)(1 + r/lambda) - r^3 G(r^2)
+ * with G(r^2) = sum_m 2 c_m s_m exp(-s_m r^2) (the pair force is
+ * q_i q_j H(r)/r^3 d), and K(r) = r (Y(r) - F(r)) (the pair energy is
+ * q_i q_j K(r)/r), on 0 <= r <= r_c as polynomials of degree 28 in
+ * y = 2 r / r_c - 1, ascending powers written to h[29] and k[29] (Chebyshev
+ * interpolation in extended precision, converted to powers of y).  Returns 1
+ * when both are within 1e-15 (absolute; H(0) = K(0) = 1) over the whole
+ * interval, with FP64 Horner evaluation (then the FP64 pair kernel uses them),
+ * 0 when not (then it evaluates the exponentials one by one).  Host only.
+ * Errors: RBSOG_EINVAL.
+ */
+int rbsog_sog_near_poly(const rbsog_sog *sog, double *h, double *k);
+
 /* One periodic system. */
 typedef struct rbsog_params {
     int64_t N;          /* particles, 1 .. 2^27 - 1                                */
@@ -142,6 +157,7 @@ typedef struct rbsog_info {
     double skin;        /* neighbour-list skin in use                              */
     int nf;             /* cells per axis of the force evaluation's fine grid      */
     int near_capacity;  /* neighbour-list capacity per (particle, z-plane)         */
+    int near_poly;      /* 1: the FP64 pair kernel uses the polynomial H, K        */
 } rbsog_info;
 
 /*

@@ -56,7 +56,7 @@ class rbsog_timing(C.Structure):
 class rbsog_info(C.Structure):
     _fields_ = [("N", C.c_int64), ("nc", C.c_int), ("mmax", C.c_int), ("nshell", C.c_int), ("nlat", C.c_int64),
                 ("S", C.c_double), ("Q1", C.c_double), ("Q2", C.c_double), ("ws_bytes", C.c_size_t),
-                ("skin", C.c_double), ("nf", C.c_int), ("near_capacity", C.c_int)]
+                ("skin", C.c_double), ("nf", C.c_int), ("near_capacity", C.c_int), ("near_poly", C.c_int)]
 
 
 _lib = None
@@ -74,6 +74,7 @@ def lib() -> C.CDLL:
         sig = {
             "rbsog_sog_init": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.POINTER(rbsog_sog)]),
             "rbsog_sog_expand": (C.c_int, [C.POINTER(rbsog_sog)]),
+            "rbsog_sog_near_poly": (C.c_int, [C.POINTER(rbsog_sog), _p, _p]),
             "rbsog_workspace_size": (C.c_int, [C.POINTER(rbsog_params), C.POINTER(rbsog_sog), C.POINTER(C.c_size_t)]),
             "rbsog_create": (C.c_int, [C.POINTER(rbsog_params), C.POINTER(rbsog_sog), _p, _p, _p, C.c_size_t, _p,
                                        C.POINTER(_p)]),
@@ -147,6 +148,18 @@ def rbsog_sog_init(lambda_: float, r_c: float, eps: float, M1: int = RBSOG_AUTO,
 def rbsog_sog_expand(sog: rbsog_sog) -> rbsog_sog:
     _check(lib().rbsog_sog_expand(C.byref(sog)))
     return sog
+
+
+def rbsog_sog_near_poly(sog: rbsog_sog):
+    """(accepted, h[29], k[29]): the FP64 pair kernel's polynomials H(r) = r^3 (F_N1 + F_N2)
+    and K(r) = r (Y - F) in y = 2 r / r_c - 1."""
+    import numpy as np
+    h = np.zeros(29)
+    k = np.zeros(29)
+    r = lib().rbsog_sog_near_poly(C.byref(sog), C.c_void_p(h.ctypes.data), C.c_void_p(k.ctypes.data))
+    if r < 0:
+        _check(r)
+    return bool(r), h, k
 
 
 def sog_from_parameters(lambda_: float, r_c: float, h: float, t0: float, w: float, M1: int, M2: int,

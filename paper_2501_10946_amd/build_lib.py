@@ -14,7 +14,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "librbsog.so")
 BUILD = os.path.join(HERE, "_build")
 
-HOST_SRCS = ["host_sog.cpp", "host_tables.cpp"]
+HOST_SRCS = ["host_sog.cpp", "host_tables.cpp", "host_near.cpp"]
 HIP_SRCS = ["k_cells.hip", "k_sample.hip", "k_rho.hip", "k_near.hip", "k_far.hip", "api.hip", "ensemble.hip"]
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall", f"-I{INCLUDE}"]

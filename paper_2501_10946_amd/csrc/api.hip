@@ -484,6 +484,11 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
         h->sd.s_log2e[j] = s->s[j] * log2e;
         h->sd.cs2[j] = 2.0 * s->c[j] * s->s[j];
     }
+    static_assert(kNearPolyDeg + 1 == sizeof(h->sd.hpoly) / sizeof(double), "near polynomial size");
+    h->sd.poly = near_poly(*s, s->r_c, h->sd.hpoly, h->sd.kpoly) ? 1 : 0;
+    h->sd.y_scale = 2.0 / s->r_c;
+    if (const char *e = std::getenv("RBSOG_NEAR_POLY"))   // 0: evaluate the Gaussians one by one
+        if (std::atoi(e) == 0) h->sd.poly = 0;
     h->Uk0 = s->Fhat0 * q1 * q1 / (2.0 * h->V);
     h->Uself = -0.5 * q2 * s->F0;
     h->Ubg = -(q1 * q1) * (4.0 * kPi * s->lambda * s->lambda) / (2.0 * h->V);
@@ -508,6 +513,7 @@ extern "C" int rbsog_get_info(const rbsog_handle *h, rbsog_info *out)
     out->skin = h->d.skin;
     out->nf = h->gf.nc;
     out->near_capacity = h->d.kp;
+    out->near_poly = h->sd.poly;
     return RBSOG_OK;
 }
 

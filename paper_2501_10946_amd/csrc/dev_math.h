@@ -3,10 +3,10 @@
 //
 // The functions here are specialised to the arguments the kernels produce:
 // exponentials of non-positive arguments (Gaussians and the screened factor)
-// and sines/cosines of phases given in revolutions.  Both use Taylor series
-// on a reduced range, with enough terms that the truncation error is below
-// half an ulp, and no special-case branches (no overflow is possible; a very
-// negative argument underflows to zero through ldexp).
+// and sines/cosines of phases given in revolutions.  Both use polynomials on
+// a reduced range whose truncation error is well below half an ulp, and no
+// special-case branches (no overflow is possible; a very negative argument
+// underflows to zero through ldexp).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -59,16 +59,18 @@ constexpr double taylor_coef(double a, int k)
     return c;
 }
 
-// 2^f = sum_k (f ln2)^k / k!, k = 0..13: c[k] = ln2^k / k!.  For |f| <= 1/2 the
-// first omitted term is below 4.4e-18.
+// 2^f for |f| <= 1/2: the degree-11 Chebyshev economization of its Taylor
+// series (gen_exp2_poly.py beside this file derives the coefficients in exact
+// arithmetic; the dropped terms are below 3.2e-18 and the coefficients as
+// rounded to FP64 are within 0.17 ulp of 2^f over the interval).
 struct Exp2Poly {
-    double c[14];
+    double c[12];
 };
 constexpr Exp2Poly make_exp2_poly()
 {
-    Exp2Poly p{};
-    for (int k = 0; k < 14; ++k) p.c[k] = taylor_coef(kLn2, k);
-    return p;
+    return Exp2Poly{{0x1.0000000000000p+0, 0x1.62e42fefa39efp-1, 0x1.ebfbdff82c5aep-3, 0x1.c6b08d704a0d1p-5,
+                     0x1.3b2ab6fb9f1a3p-7, 0x1.5d87fe78a2292p-10, 0x1.430913112cb56p-13, 0x1.ffcbfc75f302dp-17,
+                     0x1.62bfc2c7ae40ep-20, 0x1.b524db38fd1f9p-24, 0x1.e6228bff026d1p-28, 0x1.ea044321bc0aap-32}};
 }
 
 // sin(2 pi f) = f sum_k s[k] f^(2k), s[k] = (-1)^k (2 pi)^(2k+1)/(2k+1)!, k = 0..8
@@ -94,9 +96,9 @@ __device__ inline double exp2_nonpos(double y, const Exp2Poly &P)
 {
     double n = rint(y);
     double f = y - n;
-    double p = P.c[13];
+    double p = P.c[11];
 #pragma unroll
-    for (int k = 12; k >= 0; --k) p = fma(p, f, P.c[k]);
+    for (int k = 10; k >= 0; --k) p = fma(p, f, P.c[k]);
     return ldexp(p, (int)n);
 }
 

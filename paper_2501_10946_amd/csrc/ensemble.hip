@@ -95,7 +95,7 @@ struct Replica {
 };
 
 constexpr int kEnsEvents = 8192;  // completion events kept (ring)
-constexpr int kGroups = 9;        // near-field groups by Gaussian count (0: run-time count)
+constexpr int kGroups = 10;       // near-field groups: Gaussian count (0: run-time count), 9: polynomial sums
 
 // A device array grown on demand (the ensemble's own bookkeeping, outside the pool).
 template <class T>
@@ -438,6 +438,7 @@ extern "C" int rbsog_ens_admit(rbsog_ens *s, const rbsog_params *p, const rbsog_
         return rc;
     }
     R.h->samp_n = 0;
+    if (!R.mixed && R.h->sd.poly) R.ng = 9;
     R.e_adm = s->E;
     rc = write_tables(s, slot, dt);
     if (rc) {

@@ -1,0 +1,101 @@
+// The near-field pair function as one polynomial.
+//
+// Inside the cutoff, eq. (3.8), the pair force is q_i q_j [F_N1 + F_N2](r) d with
+// F_N1 = exp(-r/lambda)(1 + r/lambda)/r^3 and F_N2 = -G(r^2), G(r^2) =
+// sum_g 2 c_g s_g exp(-s_g r^2), and the pair energy q_i q_j (Y(r) - F(r)) with
+// F(r) = sum_g c_g exp(-s_g r^2).  Multiplying out the singular factors leaves
+//   H(r) = r^3 [F_N1 + F_N2] = exp(-r/lambda)(1 + r/lambda) - r^3 G(r^2),
+//   K(r) = r (Y - F)         = exp(-r/lambda) - r F(r^2),
+// both entire in r with H(0) = K(0) = 1 and derivatives governed by
+// r_c/lambda and s_max r_c^2 (a few units for the SOG of Algorithm 1 at eps =
+// 1e-4).  On [0, r_c] each is matched by a single polynomial of degree
+// kNearPolyDeg in y = 2 r / r_c - 1: Chebyshev interpolation at 64 nodes in long
+// double, truncated, converted to powers of y.  A fit is accepted only if its
+// error, measured against a long-double evaluation on a fine grid with the
+// kernel's FP64 Horner, is below kNearPolyTol; otherwise the kernels evaluate
+// the exponentials one by one.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace rbsog {
+
+namespace {
+
+constexpr int kNodes = 64;
+
+// H(r) (force) or K(r) (energy) in extended precision.
+long double hk(const rbsog_sog &s, long double r, bool force)
+{
+    const long double r2 = r * r, rl = r / (long double)s.lambda;
+    long double acc = 0.0L;
+    for (int g = 0; g < s.n; ++g) {
+        long double e = std::exp(-(long double)s.s[g] * r2);
+        acc += force ? 2.0L * (long double)s.c[g] * (long double)s.s[g] * e : (long double)s.c[g] * e;
+    }
+    long double ey = std::exp(-rl);
+    return force ? ey * (1.0L + rl) - r2 * r * acc : ey - r * acc;
+}
+
+// Chebyshev interpolant of degree < kNodes of H or K over r = (y + 1) r_c / 2,
+// y in [-1, 1], truncated to degree kNearPolyDeg and written in powers of y.
+bool fit(const rbsog_sog &s, double rc, bool force, double out[kNearPolyDeg + 1])
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<long double> fx(kNodes), b(kNodes);
+    for (int j = 0; j < kNodes; ++j) {
+        long double y = std::cos(pi * (j + 0.5L) / kNodes);
+        fx[j] = hk(s, 0.5L * (y + 1.0L) * (long double)rc, force);
+    }
+    for (int k = 0; k < kNodes; ++k) {
+        long double acc = 0.0L;
+        for (int j = 0; j < kNodes; ++j) acc += fx[j] * std::cos(pi * k * (j + 0.5L) / kNodes);
+        b[k] = acc * (k == 0 ? 1.0L : 2.0L) / kNodes;
+    }
+    // sum_k b_k T_k(x) -> sum_k a_k x^k (k <= deg), with T_{k+1} = 2x T_k - T_{k-1}
+    std::vector<long double> a(kNearPolyDeg + 1, 0.0L), t0(kNearPolyDeg + 1, 0.0L), t1(kNearPolyDeg + 1, 0.0L);
+    t0[0] = 1.0L;
+    t1[1] = 1.0L;
+    a[0] += b[0];
+    for (int i = 0; i <= kNearPolyDeg; ++i) a[i] += b[1] * t1[i];
+    for (int k = 2; k <= kNearPolyDeg; ++k) {
+        std::vector<long double> t2(kNearPolyDeg + 1, 0.0L);
+        for (int i = 0; i < kNearPolyDeg; ++i) t2[i + 1] = 2.0L * t1[i];
+        for (int i = 0; i <= kNearPolyDeg; ++i) t2[i] -= t0[i];
+        for (int i = 0; i <= kNearPolyDeg; ++i) a[i] += b[k] * t2[i];
+        t0.swap(t1);
+        t1.swap(t2);
+    }
+    for (int i = 0; i <= kNearPolyDeg; ++i) out[i] = (double)a[i];
+    // accept only a fit within tolerance (FP64 Horner as the kernel runs it;
+    // H(0) = K(0) = 1 sets the scale)
+    long double worst = 0.0L;
+    for (int j = 0; j <= 4096; ++j) {
+        double y = -1.0 + 2.0 * j / 4096.0;
+        double p = out[kNearPolyDeg];
+        for (int i = kNearPolyDeg - 1; i >= 0; --i) p = std::fma(p, y, out[i]);
+        long double ref = hk(s, 0.5L * ((long double)y + 1.0L) * (long double)rc, force);
+        worst = std::max(worst, std::fabs((long double)p - ref));
+    }
+    return worst <= (long double)kNearPolyTol;
+}
+
+}  // namespace
+
+bool near_poly(const rbsog_sog &s, double rc, double h_out[kNearPolyDeg + 1], double k_out[kNearPolyDeg + 1])
+{
+    if (s.n < 1 || !(s.lambda > 0.0)) return false;
+    return fit(s, rc, true, h_out) && fit(s, rc, false, k_out);
+}
+
+}  // namespace rbsog
+
+extern "C" int rbsog_sog_near_poly(const rbsog_sog *sog, double *h, double *k)
+{
+    if (!sog || !h || !k) return rbsog::fail(RBSOG_EINVAL, "null argument");
+    if (sog->n < 1 || sog->n > RBSOG_MAX_GAUSS || !(sog->r_c > 0.0) || !(sog->lambda > 0.0))
+        return rbsog::fail(RBSOG_EINVAL, "not an expanded decomposition");
+    return rbsog::near_poly(*sog, sog->r_c, h, k) ? 1 : 0;
+}

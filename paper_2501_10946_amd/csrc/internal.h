@@ -20,6 +20,14 @@ int c1_start(double lambda, double rc, double h, int M1, int M2, double *t0, dou
 void expand(rbsog_sog *s);
 double sog_max_error(const rbsog_sog &s);
 
+// ---- host: the near-field pair function as a polynomial (host_near.cpp) ----
+// H(r) = r^3 [F_N1 + F_N2](r) and K(r) = r (Y(r) - F(r)) on [0, r_c] as
+// polynomials of degree kNearPolyDeg in y = 2 r / r_c - 1 (ascending powers);
+// false when either misses kNearPolyTol (absolute; H(0) = K(0) = 1).
+constexpr int kNearPolyDeg = 28;
+constexpr double kNearPolyTol = 1e-15;
+bool near_poly(const rbsog_sog &s, double rc, double h_out[kNearPolyDeg + 1], double k_out[kNearPolyDeg + 1]);
+
 // ---- host: Fourier lattice and sampling tables (host_tables.cpp) -----------
 // Lattice vectors are packed into one int32: (nx+512) | (ny+512)<<10 | (nz+512)<<20.
 constexpr int kLatticeBias = 512;

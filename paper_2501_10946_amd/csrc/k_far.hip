@@ -20,6 +20,23 @@ constexpr int kFarGroups = 4;
 constexpr int kFarThreads = 64 * kFarGroups;
 constexpr int kFarTile = 256;
 
+// Im(exp(-i k.r) coef rho) of one mode (kv: n, gv: coef rho), r/L = (sx, sy, sz).
+template <bool MIXED>
+__device__ inline double far_term(const FarArgs &a, const double2 *tab, const double4 &kv, const double2 &gv,
+                                  double sx, double sy, double sz)
+{
+    double u = kv.x * sx + kv.y * sy + kv.z * sz;
+    if (MIXED) {
+        float sn, cs;
+        sincos_rev_f32(u, &sn, &cs);
+        return gv.y * (double)cs - gv.x * (double)sn;
+    } else {
+        double sn, cs;
+        sincos_rev_tab(u, tab, a.ss, &sn, &cs);
+        return gv.y * cs - gv.x * sn;
+    }
+}
+
 template <bool MIXED>
 __device__ inline void far_body(const FarArgs &a, int b)
 {
@@ -46,23 +63,25 @@ __device__ inline void far_body(const FarArgs &a, int b)
         }
         __syncthreads();
         int nl = min(kFarTile, a.P - l0);
-        for (int k = g; k < nl; k += kFarGroups) {
-            double4 kv = sk[k];
-            double2 gv = sg[k];
-            double u = kv.x * sx + kv.y * sy + kv.z * sz;
-            double im;
-            if (MIXED) {
-                float sn, cs;
-                sincos_rev_f32(u, &sn, &cs);
-                im = gv.y * (double)cs - gv.x * (double)sn;
-            } else {
-                double sn, cs;
-                sincos_rev_tab(u, tab, a.ss, &sn, &cs);
-                im = gv.y * cs - gv.x * sn;
-            }
-            ax += im * kv.x;
-            ay += im * kv.y;
-            az += im * kv.z;
+        // two modes per pass (independent chains), added in mode order
+        int k = g;
+        for (; k + kFarGroups < nl; k += 2 * kFarGroups) {
+            const double4 k0 = sk[k], k1 = sk[k + kFarGroups];
+            const double im0 = far_term<MIXED>(a, tab, k0, sg[k], sx, sy, sz);
+            const double im1 = far_term<MIXED>(a, tab, k1, sg[k + kFarGroups], sx, sy, sz);
+            ax += im0 * k0.x;
+            ay += im0 * k0.y;
+            az += im0 * k0.z;
+            ax += im1 * k1.x;
+            ay += im1 * k1.y;
+            az += im1 * k1.z;
+        }
+        if (k < nl) {
+            const double4 k0 = sk[k];
+            const double im0 = far_term<MIXED>(a, tab, k0, sg[k], sx, sy, sz);
+            ax += im0 * k0.x;
+            ay += im0 * k0.y;
+            az += im0 * k0.z;
         }
     }
     part[0][t] = ax;

@@ -23,9 +23,11 @@
 //            depending on where the particle sits in its cell).  Each lane
 //            runs down its entries with the next index and the next neighbour
 //            position already in flight, and stores its partial force; the
-//            far-field kernel adds the five partials in lane order.  The
-//            number of Gaussians is a template parameter for the common
-//            counts, so their coefficients stay in scalar registers.  When a
+//            far-field kernel adds the five partials in lane order.  In FP64
+//            the pair function is, when its fit is accurate, one polynomial
+//            in r (r^3 times the force factor, 28 FMAs, no exponential),
+//            otherwise the number of Gaussians is a template parameter for
+//            the common counts; coefficients stay in scalar registers.  When a
 //            plane of a particle overflowed kp at the build, its lanes walk
 //            the candidates of the current positions, one plane each.
 //
@@ -172,9 +174,20 @@ __device__ inline double rsqrt_f64(double x)
 }
 
 // Gaussians of the pair function: NG > 0 is a compile-time count, 0 the
-// run-time count of the argument block.
+// run-time count of the argument block; kPolyNG: the whole pair function from
+// the polynomials of the argument block (FP64).
+constexpr int kPolyNG = -1;
 template <int NG>
 __device__ inline int gauss_count(const NearArgs &a) { return NG > 0 ? NG : a.sog.n; }
+
+// Horner in y of the degree-28 polynomial c (ascending powers).
+__device__ inline double near_poly_eval(const double *c, double y)
+{
+    double p = c[28];
+#pragma unroll
+    for (int k = 27; k >= 0; --k) p = fma(p, y, c[k]);
+    return p;
+}
 
 template <bool MIXED, bool ENERGY, int NG>
 __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const double4 &pj, double &fx, double &fy,
@@ -197,7 +210,7 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
         float f1 = ey * (1.0f + rf * (float)a.sog.inv_lambda) * (irf * irf * irf);
         float gs = 0.0f, fs = 0.0f;
 #pragma unroll
-        for (int g = 0; g < gauss_count<NG>(a); ++g) {
+        for (int g = 0; g < (NG == kPolyNG ? 0 : gauss_count<NG>(a)); ++g) {
             float eg = __builtin_amdgcn_exp2f(-(float)a.sog.s_log2e[g] * r2f);
             gs = fmaf((float)a.sog.cs2[g], eg, gs);
             if (ENERGY) fs = fmaf((float)a.sog.c[g], eg, fs);
@@ -207,17 +220,29 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
         fy = fma(fac, dy, fy);
         fz = fma(fac, dz, fz);
         if (ENERGY) en = fma(qq, (double)(ey * irf - fs), en);
+    } else if constexpr (NG == kPolyNG) {
+        // H(r) / r^3 and K(r) / r with H, K the polynomials in y = 2 r / r_c - 1
+        double ir = rsqrt_f64(r2);
+        double r = r2 * ir;
+        const double y = fma(r, a.sog.y_scale, -1.0);
+        double fac = qq * (near_poly_eval(a.sog.hpoly, y) * (ir * ir * ir));
+        fx = fma(fac, dx, fx);
+        fy = fma(fac, dy, fy);
+        fz = fma(fac, dz, fz);
+        if (ENERGY) en = fma(qq, near_poly_eval(a.sog.kpoly, y) * ir, en);
     } else {
         double ir = rsqrt_f64(r2);
         double r = r2 * ir;
         double ey = exp2_nonpos(-r * a.sog.inv_lambda_log2e, a.e2);
         double f1 = ey * fma(r, a.sog.inv_lambda, 1.0) * (ir * ir * ir);
         double gs = 0.0, fs = 0.0;
+        {
 #pragma unroll
-        for (int g = 0; g < gauss_count<NG>(a); ++g) {
-            double eg = exp2_nonpos(-a.sog.s_log2e[g] * r2, a.e2);
-            gs = fma(a.sog.cs2[g], eg, gs);
-            if (ENERGY) fs = fma(a.sog.c[g], eg, fs);
+            for (int g = 0; g < gauss_count<NG>(a); ++g) {
+                double eg = exp2_nonpos(-a.sog.s_log2e[g] * r2, a.e2);
+                gs = fma(a.sog.cs2[g], eg, gs);
+                if (ENERGY) fs = fma(a.sog.c[g], eg, fs);
+            }
         }
         double fac = qq * (f1 - gs);
         fx = fma(fac, dx, fx);
@@ -335,30 +360,35 @@ __device__ inline void near_body(const NearArgs &a, int lb)
     double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0;
     if (total <= kNearPlanes * a.kp) {
         // lane `plane` takes entries plane, plane + 5, ... of the particle's
-        // list; entry k is evaluated while the position of entry k + 1 and the
-        // index of entry k + 2 are loading (the index clamped to the list)
+        // list, two per pass: entries k, k + 1 are evaluated while the
+        // positions of k + 2, k + 3 and the indices of k + 4, k + 5 are loading
+        // (an index past the lane's count is not read: the particle itself
+        // stands in for it and is never evaluated)
         const int cnt = total > plane ? (total - plane + kNearPlanes - 1) / kNearPlanes : 0;
         const int32_t *in = a.nbr + (size_t)plane * a.N + p;
-        int jn = p;
-        double4 qn = pi;
-        if (cnt > 0) {
-            qn = a.xs[in[0]];
-            if (cnt > 1) in += stride;
-            jn = *in;
-        }
-        for (int k = 0; k < cnt; ++k) {
-            const double4 q = qn;
-            qn = a.xs[jn];
-            if (k + 2 < cnt) in += stride;
-            jn = *in;
-            pair_force<MIXED, ENERGY, NG>(a, pi, q, fx, fy, fz, en);
+        int ja = cnt > 0 ? in[0] : p;
+        int jb = cnt > 1 ? in[stride] : p;
+        double4 qa = a.xs[ja], qb = a.xs[jb];
+        in += 2 * stride;
+        int jc = cnt > 2 ? in[0] : p;
+        int jd = cnt > 3 ? in[stride] : p;
+        for (int k = 0; k < cnt; k += 2) {
+            const double4 ca = qa, cb = qb;
+            qa = a.xs[jc];
+            qb = a.xs[jd];
+            in += 2 * stride;
+            jc = k + 4 < cnt ? in[0] : p;
+            jd = k + 5 < cnt ? in[stride] : p;
+            pair_force<MIXED, ENERGY, NG>(a, pi, ca, fx, fy, fz, en);
+            if (k + 1 < cnt) pair_force<MIXED, ENERGY, NG>(a, pi, cb, fx, fy, fz, en);
         }
     } else {
         // a plane of this particle overflowed at the build: each of its five
-        // lanes walks the cells of its plane around the current position.  Particles may have moved up to
-        // skin/2 out of the cells they were sorted into (and wrapped around the
-        // box), so the cells are culled with the list radius and the pair
-        // function itself (minimum image, r < r_c) decides.
+        // lanes walks the cells of its plane around the current position.
+        // Particles may have moved up to skin/2 out of the cells they were
+        // sorted into (and wrapped around the box), so the cells are culled
+        // with the list radius and the pair function itself (minimum image,
+        // r < r_c) decides.
         const Lane l = make_lane(a, p, plane);
         if (l.gz * l.gz < a.rl2) {
             for (int row = 0; row < 5; ++row) {
@@ -413,7 +443,13 @@ __global__ __launch_bounds__(kEvalThreads) void k_near_batch(const NearArgs *__r
                                                              const EnsItem *__restrict__ items)
 {
     const EnsItem e = items[blockIdx.x];
-    near_body<MIXED, ENERGY, NG>(tab[e.r], e.b);
+    if constexpr (NG == 0) {
+        near_body<MIXED, ENERGY, NG>(tab[e.r], e.b);
+    } else {
+        // read before any store, the copy's fields become scalar loads
+        const NearArgs a = tab[e.r];
+        near_body<MIXED, ENERGY, NG>(a, e.b);
+    }
 }
 
 // A launch with a missing buffer is refused on the host.
@@ -435,6 +471,10 @@ template <bool MIXED, bool ENERGY>
 static void launch_near_ng(const NearArgs &a, dim3 grid, hipStream_t st)
 {
     dim3 block(kEvalThreads);
+    if (!MIXED && a.sog.poly) {
+        hipLaunchKernelGGL((k_near<false, ENERGY, kPolyNG>), grid, block, 0, st, a);
+        return;
+    }
     switch (a.sog.n) {
 #define RBSOG_NEAR_NG(n) \
     case n: hipLaunchKernelGGL((k_near<MIXED, ENERGY, n>), grid, block, 0, st, a); return;
@@ -461,7 +501,14 @@ hipError_t launch_nlist_batch(const NearArgs *tab, const EnsItem *items, int n, 
 hipError_t launch_near_batch(const NearArgs *tab, const EnsItem *items, int n, int ng, bool mixed, bool energy,
                              hipStream_t st)
 {
-    if (!tab || !items || n < 1 || ng < 0 || ng > 8) return hipErrorInvalidValue;
+    if (!tab || !items || n < 1 || ng < 0 || ng > 9 || (ng == 9 && mixed)) return hipErrorInvalidValue;
+    if (ng == 9) {   // FP64 replicas whose Gaussian sums are polynomials
+        if (energy) hipLaunchKernelGGL((k_near_batch<false, true, kPolyNG>), dim3(n), dim3(kEvalThreads), 0, st, tab,
+                                       items);
+        else hipLaunchKernelGGL((k_near_batch<false, false, kPolyNG>), dim3(n), dim3(kEvalThreads), 0, st, tab,
+                                items);
+        return hipGetLastError();
+    }
     dim3 grid(n), block(kEvalThreads);
 #define RBSOG_NEAR_B(M, E, G) \
     if (mixed == M && energy == E && ng == G) { \

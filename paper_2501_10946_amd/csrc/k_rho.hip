@@ -1,6 +1,8 @@
 // gfx950 kernels of librbsog: structure factors rho(k).
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "dev_common.h"
 
 namespace rbsog {
@@ -87,20 +89,49 @@ __global__ __launch_bounds__(kBlock) void k_rho_partial_batch(const RhoArgs *__r
 }
 
 // One workgroup per sample: fixed-order sum of the chunk partials.
+// Mode b: thread t adds the partials of groups t, t + 256, ... in order (four
+// loads in flight), the 64 lanes of each wave are added by a fixed butterfly,
+// and thread 0 adds the four wave sums in order.
 __device__ inline void rho_reduce_body(const RhoArgs &a, int b)
 {
-    __shared__ double red[kBlock];
-    int l = b;
+    __shared__ double2 red[kBlock / 64];
+    const int l = b, t = threadIdx.x;
+    const double2 *col = a.part + l;
+    const size_t P = (size_t)a.P;
     double re = 0.0, im = 0.0;
-    for (int c = threadIdx.x; c < a.nchunk; c += kBlock) {
-        double2 v = a.part[(size_t)c * a.P + l];
+    int c = t;
+    for (; c + 3 * kBlock < a.nchunk; c += 4 * kBlock) {
+        double2 v0 = col[(size_t)c * P], v1 = col[(size_t)(c + kBlock) * P];
+        double2 v2 = col[(size_t)(c + 2 * kBlock) * P], v3 = col[(size_t)(c + 3 * kBlock) * P];
+        re += v0.x;
+        im += v0.y;
+        re += v1.x;
+        im += v1.y;
+        re += v2.x;
+        im += v2.y;
+        re += v3.x;
+        im += v3.y;
+    }
+    for (; c < a.nchunk; c += kBlock) {
+        double2 v = col[(size_t)c * P];
         re += v.x;
         im += v.y;
     }
-    re = block_sum_256(re, red);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_xor(re, off);
+        im += __shfl_xor(im, off);
+    }
+    if ((t & 63) == 0) red[t >> 6] = make_double2(re, im);
     __syncthreads();
-    im = block_sum_256(im, red);
-    if (threadIdx.x == 0) {
+    if (t == 0) {
+        re = 0.0;
+        im = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            re += red[w].x;
+            im += red[w].y;
+        }
         double cf = a.samp[l].w;
         a.rho[l] = make_double2(re, im);
         a.gk[l] = make_double2(cf * re, cf * im);
@@ -121,6 +152,11 @@ int rho_chunk(int N, int P)
     int cap = kRhoStage / (255 / P + 2);
     int c = 1;
     while (2 * c <= cap && 2 * c <= kRhoChunkMax) c *= 2;
+    // RBSOG_RHO_CHUNK (a power of two within the cap) overrides the choice: a tuning knob
+    if (const char *e = std::getenv("RBSOG_RHO_CHUNK")) {
+        int v = std::atoi(e);
+        if (v >= 1 && v <= c && (v & (v - 1)) == 0) return v;
+    }
     // at least ~4 waves per SIMD (4096 waves of 64 lanes) where N and P allow
     while (c > 8 && (int64_t)((N + c - 1) / c) * P < 4096 * 64) c /= 2;
     return c;

@@ -43,6 +43,11 @@ struct SogDev {
     double c[kMaxGauss];        // F(r) = sum c exp(-s r^2)
     double s_log2e[kMaxGauss];  // s log2(e): exp(-s r^2) = 2^(-s log2(e) r^2)
     double cs2[kMaxGauss];      // 2 c s (force factor of the Gaussians)
+    // the pair function as polynomials of y = r y_scale - 1 (when poly != 0)
+    int poly;
+    double y_scale;             // 2 / r_c
+    double hpoly[29];           // r^3 (F_N1 + F_N2), ascending powers of y
+    double kpoly[29];           // r (Y - F)
 };
 
 // Geometry of the cell list.
@@ -177,7 +182,8 @@ __host__ __device__ inline int nlist_blocks(int N) { return (N + 63) / 64; }
 __host__ __device__ inline int near_blocks(int N) { return 5 * ((N + 255) / 256); }
 __host__ __device__ inline int far_blocks(int N) { return (N + 63) / 64; }
 // ensemble: list builds (nlist_blocks items per replica); evaluations of the
-// replicas with `ng` Gaussians (0: any count, read at run time)
+// replicas with `ng` Gaussians (0: any count, read at run time; 9: FP64 with
+// the polynomial Gaussian sums)
 hipError_t launch_nlist_batch(const NearArgs *tab, const EnsItem *items, int n, hipStream_t st);
 hipError_t launch_near_batch(const NearArgs *tab, const EnsItem *items, int n, int ng, bool mixed, bool energy,
                              hipStream_t st);

@@ -99,3 +99,36 @@ def test_ensemble_sizing(R):
     with pytest.raises(R.RbsogError) as e:
         R.rbsog_ens_bytes(R.make_params(1000, 8.0, 1.0, 100, 1), sog, 10)
     assert e.value.code == R.RBSOG_EINVAL
+
+
+@pytest.mark.parametrize("lam,rc", [(2.0, 4.0), (1.0, 3.0), (10.0, 5.0), (0.5, 4.0), (1.0 / 0.1, 4.0), (1.0 / 1.9, 4.0)])
+def test_near_poly_matches_pair_function(R, lam, rc):
+    """The FP64 pair kernel's polynomials H(r) = r^3 (F_N1 + F_N2) and
+    K(r) = r (Y - F) (eq. 3.8) agree with the pair function built term by term
+    from the oracle's SOG on a grid of r in [0, r_c] to 2e-15 absolute
+    (H(0) = K(0) = 1), and K(r)/r with the oracle's F(r)."""
+    o = oracle.sog_auto(lam, rc, 1e-4)
+    s = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+    ok, h, k = R.rbsog_sog_near_poly(s)
+    assert ok
+    r = np.linspace(0.0, rc, 2001)
+    y = 2.0 * r / rc - 1.0
+    ph = np.polynomial.polynomial.polyval(y, h)
+    pk = np.polynomial.polynomial.polyval(y, k)
+    c, sg = np.asarray(o.c), np.asarray(o.s)
+    G = (2.0 * c * sg * np.exp(-np.outer(r * r, sg))).sum(axis=1)
+    F = (c * np.exp(-np.outer(r * r, sg))).sum(axis=1)
+    ey = np.exp(-r / lam)
+    assert np.max(np.abs(ph - (ey * (1.0 + r / lam) - r ** 3 * G))) < 2e-15
+    assert np.max(np.abs(pk - (ey - r * F))) < 2e-15
+    rr = r[1:]
+    assert np.allclose(pk[1:] / rr, np.exp(-rr / lam) / rr - o.F(rr), rtol=0, atol=2e-15 / rr.min())
+
+
+def test_near_poly_declines_when_inaccurate(R):
+    """A decomposition whose pair function a degree-28 polynomial cannot follow
+    to 1e-15 (eps = 1e-10: narrow Gaussians) is declined."""
+    o = oracle.sog_auto(1.0, 3.0, 1e-10)
+    s = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+    ok, _, _ = R.rbsog_sog_near_poly(s)
+    assert not ok
