@@ -148,13 +148,14 @@ constexpr SinCosShort make_sincos_short()
 constexpr int kPhaseTab = 128;   // entries of the rotation table
 
 // sin(2 pi u), cos(2 pi u) for a phase u in revolutions (FP64) with a table of
-// (sin, cos)(2 pi j / 128): u - rint(u) = j / 128 + f exactly (|f| <= 1/256),
-// the short series give the rotation by f, and the table entry the rest.
+// (sin, cos)(2 pi j / 128): u = m / 128 + f exactly with m = rint(128 u) and
+// |f| <= 1/256 (u 128 and m / 128 are exact; for |u| < 2^24 the difference is
+// exact too), the short series give the rotation by f, and the table entry of
+// m mod 128 the rest.
 __device__ inline void sincos_rev_tab(double u, const double2 *tab, const SinCosShort &P, double *s, double *c)
 {
-    double r = u - rint(u);
-    double jr = rint(r * (double)kPhaseTab);
-    double f = fma(jr, -1.0 / kPhaseTab, r);
+    double jr = rint(u * (double)kPhaseTab);
+    double f = fma(jr, -1.0 / kPhaseTab, u);
     double2 t = tab[(int)jr & (kPhaseTab - 1)];
     double f2 = f * f;
     double sp = fma(fma(fma(P.s[3], f2, P.s[2]), f2, P.s[1]), f2, P.s[0]) * f;

@@ -11,11 +11,14 @@
 // already exceeds the list radius are skipped per particle.
 //
 //   k_nlist  a workgroup owns 64 consecutive particles (cell order) and has 5
-//            waves, one per plane; each lane walks its candidates (four loads
-//            in flight) and stores the accepted j, in candidate order, in
-//            staging rows of its plane (capacity kp per plane); the five
-//            planes of each particle are then copied, all at once, into one
-//            column-major list of the particle's neighbours, plus its count;
+//            waves.  Wave w first finds the candidate ranges of plane w of
+//            each particle; then wave w walks the w-th fifth of each
+//            particle's candidates (all planes in order, four loads in
+//            flight), so every lane has the same share however the planes are
+//            filled, and stores the accepted j in staging rows of its chunk
+//            (capacity kp per chunk); the five chunks of each particle are
+//            then copied, all at once, into one column-major list of the
+//            particle's neighbours in candidate order, plus its count;
 //   k_near   a workgroup owns 256 consecutive particles and one of five lanes
 //            per particle (4 waves); lane s evaluates entries s, s + 5, ... of
 //            the particle's list, so the five lanes get equal shares (a split
@@ -261,34 +264,77 @@ __device__ inline void nlist_body(const NearArgs &a, int lb)
 {
     if (a.gate && *a.gate == 0) return;
     __shared__ Range rng[kMaxRanges][kNearThreads];
+    __shared__ int32_t nrng[kNearThreads], tot[kNearThreads];
     __shared__ int32_t stage[kStage][kNearThreads];
     const int t = threadIdx.x;
-    const int plane = t >> 6;
-    const int p = lb * 64 + (t & 63);
-    const Lane l = make_lane(a, p, plane);
-    int nr = 0;
-    if (p < a.N && l.gz * l.gz < a.rl2) {
-        for (int row = 0; row < 5; ++row) {
-            Range g[2];
-            int n = row_ranges(a, l, row, a.rl2, g);
-            for (int k = 0; k < n; ++k) rng[nr++][t] = g[k];
+    const int w = t >> 6, lane = t & 63;
+    const int p = lb * 64 + lane;
+    // 1. thread (plane w, particle p): the candidate ranges of that plane
+    {
+        const Lane l = make_lane(a, p, w);
+        int nr = 0, nc = 0;
+        if (p < a.N && l.gz * l.gz < a.rl2) {
+            for (int row = 0; row < 5; ++row) {
+                Range g[2];
+                int n = row_ranges(a, l, row, a.rl2, g);
+                for (int k = 0; k < n; ++k) {
+                    rng[nr++][t] = g[k];
+                    nc += g[k].end - (g[k].start_code & (int32_t)kIndexMask);
+                }
+            }
         }
+        nrng[t] = nr;
+        tot[t] = nc;
     }
-    // plane `plane` of particle p is staged in rows plane*kp .. plane*kp + kp - 1
-    const size_t N = (size_t)a.N;
-    int32_t *out = a.nbr_stage + (size_t)plane * a.kp * N + p;
-    int r = 0, total = 0;
+    __syncthreads();
+    // 2. thread (chunk w, particle p): the w-th fifth of the particle's
+    // candidates, planes and ranges in order, so that every thread walks the
+    // same number of candidates whatever the planes hold
+    int T = 0;
+#pragma unroll
+    for (int k = 0; k < kNearPlanes; ++k) T += tot[k * 64 + lane];
+    const int b0 = (int)(((int64_t)w * T) / kNearPlanes), e0 = (int)(((int64_t)(w + 1) * T) / kNearPlanes);
+    int left = e0 - b0;
+    // locate candidate b0: plane, range, offset
+    int q = 0, r = 0, skip = b0;
+    while (q < kNearPlanes && skip >= tot[q * 64 + lane]) {
+        skip -= tot[q * 64 + lane];
+        ++q;
+    }
+    const double4 pi = p < a.N ? a.xs[p] : make_double4(0.0, 0.0, 0.0, 0.0);
     Cursor c{0, 0, 0.0, 0.0, 0.0};
-    if (nr > 0) c = open_range(rng[0][t], l.pi, a.g.L);
+    if (left > 0) {
+        for (;;) {
+            Range g = rng[r][q * 64 + lane];
+            int len = g.end - (g.start_code & (int32_t)kIndexMask);
+            if (skip < len) break;
+            skip -= len;
+            ++r;
+        }
+        c = open_range(rng[r][q * 64 + lane], pi, a.g.L);
+        c.j += skip;
+    }
+    // this chunk is staged in rows w*kp .. w*kp + kp - 1
+    const size_t N = (size_t)a.N;
+    int32_t *out = a.nbr_stage + (size_t)w * a.kp * N + p;
+    int total = 0;
     do {
         int cnt = 0;
-        while (cnt <= kStage - 4 && r < nr) {
-            if (c.j >= c.jend) {
-                if (++r < nr) c = open_range(rng[r][t], l.pi, a.g.L);
+        while (cnt <= kStage - 4 && left > 0) {
+            if (c.j >= c.jend) {   // next range, of this plane or the next non-empty one
+                if (++r >= nrng[q * 64 + lane]) {
+                    r = 0;
+                    do ++q; while (q < kNearPlanes && nrng[q * 64 + lane] == 0);
+                    if (q >= kNearPlanes) {   // cannot happen: the counts add up
+                        left = 0;
+                        break;
+                    }
+                }
+                c = open_range(rng[r][q * 64 + lane], pi, a.g.L);
                 continue;
             }
             int last = c.jend - 1;
-            int n = min(4, c.jend - c.j);
+            int n = min(min(4, c.jend - c.j), left);
             double4 q0 = a.xs[c.j];
             double4 q1 = a.xs[min(c.j + 1, last)];
             double4 q2 = a.xs[min(c.j + 2, last)];
@@ -298,27 +344,28 @@ __device__ inline void nlist_body(const NearArgs &a, int lb)
             if (n > 2 && accept(c, q2, c.j + 2, p, a.rl2)) stage[cnt++][t] = c.j + 2;
             if (n > 3 && accept(c, q3, c.j + 3, p, a.rl2)) stage[cnt++][t] = c.j + 3;
             c.j += n;
+            left -= n;
         }
         for (int k = 0; k < cnt; ++k)
             if (total + k < a.kp) out[(size_t)(total + k) * N] = stage[k][t];
         total += cnt;
-    } while (__any(r < nr));
+    } while (__any(left > 0));
 
-    // Concatenate the five planes of each particle in plane order: plane r
-    // goes to rows off_r = (sum of the counts of the planes before it) onward
-    // of the final list, every plane at once (staging and list are disjoint).
+    // Concatenate the five chunks of each particle in order: chunk w goes to
+    // rows off_w = (sum of the counts of the chunks before it) onward of the
+    // final list, every chunk at once (staging and list are disjoint).  The
+    // list holds the accepted candidates in candidate order.
     __shared__ int32_t cnts[kNearPlanes][64];
-    const int lane = t & 63;
-    cnts[plane][lane] = total;
+    cnts[w][lane] = total;
     __syncthreads();
     int off = 0, all = 0;
     bool over = false;
 #pragma unroll
-    for (int q = 0; q < kNearPlanes; ++q) {
-        int c = cnts[q][lane];
-        over |= c > a.kp;
-        off += q < plane ? c : 0;
-        all += c;
+    for (int k = 0; k < kNearPlanes; ++k) {
+        int cc = cnts[k][lane];
+        over |= cc > a.kp;
+        off += k < w ? cc : 0;
+        all += cc;
     }
     if (p < a.N && !over) {
         int32_t *dst = a.nbr + (size_t)off * N + p;
@@ -334,7 +381,7 @@ __device__ inline void nlist_body(const NearArgs &a, int lb)
         }
         for (; k < total; ++k) dst[(size_t)k * N] = src[(size_t)k * N];
     }
-    if (plane == 0 && p < a.N) a.nbr_cnt[p] = over ? kNearPlanes * a.kp + 1 : all;
+    if (w == 0 && p < a.N) a.nbr_cnt[p] = over ? kNearPlanes * a.kp + 1 : all;
 }
 
 // ---------------------------------------------------------------------------
