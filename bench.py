@@ -124,7 +124,7 @@ def serve(args, dev, log):
         ens = R.rbsog_ens_create(budget, max_slots)
         try:
             pending = list(range(len(prep)))
-            slot_req, t_adm, t_done, active_at = {}, {}, {}, []
+            slot_req, t_adm, t_done, active_at, times = {}, {}, {}, [], []
             done = 0
             t0 = time.perf_counter()
             while done < len(prep):
@@ -147,9 +147,10 @@ def serve(args, dev, log):
                 if stat["active"] > 0:
                     active_at.append(stat["active"])
                     R.rbsog_ens_step(ens)
-                    # stay at most two ensemble steps ahead of the device
-                    if stat["ens_steps"] >= 1:
-                        R.rbsog_ens_step_time(ens, stat["ens_steps"])
+                    # keep one step queued behind the one running, no more; the
+                    # completion times are read as the steps are waited for
+                    while len(times) < stat["ens_steps"]:
+                        times.append(R.rbsog_ens_step_time(ens, len(times) + 1))
                 elif pending and arrivals[pending[0]] > now:
                     time.sleep(min(1e-3, arrivals[pending[0]] - now))
                 else:
@@ -160,7 +161,9 @@ def serve(args, dev, log):
                     done += 1
             wall = time.perf_counter() - t0
             nst = R.rbsog_ens_status(ens)["ens_steps"]
-            times = np.array([R.rbsog_ens_step_time(ens, k) for k in range(1, nst + 1)])
+            while len(times) < nst:
+                times.append(R.rbsog_ens_step_time(ens, len(times) + 1))
+            times = np.array(times)
         finally:
             R.rbsog_ens_destroy(ens)
         # per (replica, step) latency: the gap between consecutive ensemble-step
@@ -213,6 +216,8 @@ def main():
     ap.add_argument("--skin", type=float, default=-1.0, help="neighbour-list skin (negative: the library default)")
     ap.add_argument("--drift-steps", type=int, default=500, help="NVE steps of the energy-drift runs (0: none)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-ensemble measurement")
+    ap.add_argument("--no-fullk-energy", action="store_true",
+                    help="skip the deterministic full-lattice energy along the first 100 FP64 NVE steps")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rates", default="0.5,0.8,1.2",
                     help="Poisson arrival rates as fractions of the measured saturated capacity")
@@ -311,6 +316,29 @@ def main():
             R.rbsog_step(s.h, xd, vd, fd, step_eq, args.drift_steps, w.dt, ehd)
             R.rbsog_check(s.h)
             res["drift"] = energy_drift(ehd.sum(dim=1).cpu().numpy(), w.dt, w.N * w.kT)
+            if prec == R.RBSOG_FP64 and not args.no_fullk_energy:
+                # the same trajectory's energy with the whole lattice (no sampling
+                # noise) at steps 0, 25, 50, 75, 100
+                sfk = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, precision=R.RBSOG_FP64, full_k=True,
+                               device=dev)
+                mt = torch.tensor(st.m, device=dev)
+                xd, vd, fd = x_eq.clone(), v_eq.clone(), torch.empty_like(x_eq)
+                R.rbsog_compute_forces(s.h, step_eq, xd, fd)
+                ftmp = torch.empty_like(xd)
+                e6 = torch.zeros(6, dtype=torch.float64, device=dev)
+                efull, sd = [], step_eq
+                for c in range(5):
+                    R.rbsog_compute_forces(sfk.h, 0, xd, ftmp, None, e6)
+                    ke = 0.5 * float((mt * (vd * vd).sum(dim=0)).sum())
+                    efull.append((float(e6[:5].sum()) + ke) / (w.N * w.kT))
+                    if c < 4:
+                        R.rbsog_step(s.h, xd, vd, fd, sd, 25, w.dt)
+                        sd += 25
+                tt = w.dt * 25 * np.arange(5)
+                slope = float(np.polyfit(tt, np.array(efull), 1)[0])
+                res["drift"]["full_k"] = {"steps": [0, 25, 50, 75, 100], "E_NkT": efull,
+                                          "slope_NkT_per_time": slope, "lattice_points": R.rbsog_get_info(sfk.h).nlat}
+                del sfk
         results[name] = res
         log(f"[bench] {name}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.3f} ms/step, "
             f"force-only {res['force_only']:.4g}/s, drift {res.get('drift')}")

@@ -140,6 +140,11 @@ typedef struct rbsog_params {
                            has moved more than skin/2 since the last build; < 0 =
                            default 0.15 r_c; capped so that L >= 3 (r_c + skin);
                            0 = rebuild every step.  Results do not depend on it. */
+    int full_k;         /* 0: random batch of P sampled modes (the method);
+                           1: deterministic far field over the whole lattice,
+                           coefficient Fhat(k)/V per mode (eqs. 3.5, UF without
+                           sampling) -- a test reference, N x nlat work per force;
+                           P is then unused and rbsog_compute_rho is refused   */
 } rbsog_params;
 
 typedef struct rbsog_handle rbsog_handle;
@@ -156,7 +161,7 @@ typedef struct rbsog_info {
     size_t ws_bytes;    /* workspace bytes the system needs                        */
     double skin;        /* neighbour-list skin in use                              */
     int nf;             /* cells per axis of the force evaluation's fine grid      */
-    int near_capacity;  /* neighbour-list capacity per (particle, z-plane)         */
+    int near_capacity;  /* neighbour-list capacity per (particle, fifth of its list) */
     int near_poly;      /* 1: the FP64 pair kernel uses the polynomial H, K        */
 } rbsog_info;
 

@@ -42,7 +42,7 @@ class rbsog_sog(C.Structure):
 class rbsog_params(C.Structure):
     _fields_ = [("N", C.c_int64), ("L", C.c_double), ("kT", C.c_double), ("P", C.c_int), ("mmax", C.c_int),
                 ("seed", C.c_uint64), ("replica", C.c_uint32), ("precision", C.c_int), ("density", C.c_int),
-                ("skin", C.c_double)]
+                ("skin", C.c_double), ("full_k", C.c_int)]
 
 
 RBSOG_NUM_KERNEL_CLASSES = 9
@@ -172,9 +172,10 @@ def sog_from_parameters(lambda_: float, r_c: float, h: float, t0: float, w: floa
 
 
 def make_params(N: int, L: float, kT: float, P: int, seed: int, replica: int = 0, mmax: int = 0,
-                precision: int = RBSOG_FP64, density: int = RBSOG_ADAPTIVE, skin: float = -1.0) -> rbsog_params:
+                precision: int = RBSOG_FP64, density: int = RBSOG_ADAPTIVE, skin: float = -1.0,
+                full_k: bool = False) -> rbsog_params:
     return rbsog_params(N=N, L=L, kT=kT, P=P, mmax=mmax, seed=seed, replica=replica, precision=precision,
-                        density=density, skin=skin)
+                        density=density, skin=skin, full_k=1 if full_k else 0)
 
 
 def rbsog_workspace_size(params: rbsog_params, sog: rbsog_sog) -> int:
@@ -331,13 +332,13 @@ class System:
 
     def __init__(self, q, m, L: float, sog: rbsog_sog, kT: float, P: int, seed: int, replica: int = 0,
                  mmax: int = 0, precision: int = RBSOG_FP64, density: int = RBSOG_ADAPTIVE, skin: float = -1.0,
-                 device="cuda"):
+                 full_k: bool = False, device="cuda"):
         import torch
         self.q = torch.as_tensor(q, dtype=torch.float64, device=device).contiguous()
         self.m = torch.as_tensor(m, dtype=torch.float64, device=device).contiguous()
         self.N = self.q.numel()
         self.sog = sog
-        self.params = make_params(self.N, L, kT, P, seed, replica, mmax, precision, density, skin)
+        self.params = make_params(self.N, L, kT, P, seed, replica, mmax, precision, density, skin, full_k)
         nbytes = rbsog_workspace_size(self.params, sog)
         self.ws = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device=device)
         self.h = rbsog_create(self.params, sog, self.q, self.m, self.ws)

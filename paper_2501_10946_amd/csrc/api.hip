@@ -38,20 +38,21 @@ CellGeom make_geom(double L, int nc)
 }
 
 
-// Capacity of each (particle, plane) neighbour list: 1.5x the expected count
-// of the fullest plane (a slab of width w through the list sphere) plus 24;
-// a lane that overflows walks its cells directly instead, so this only sizes
-// the fast path.  RBSOG_NEAR_CAPACITY overrides it (a tuning knob).
+// Capacity of each of a particle's five list chunks (a fifth of its
+// candidates each): 1.5x the expected number of neighbours within the list
+// radius divided by five, plus 16; a particle with a fuller chunk walks its
+// cells directly instead, so this only sizes the fast path.  RBSOG_NEAR_CAPACITY
+// overrides it (a tuning knob).
 int near_capacity(int64_t N, double L, double rl, int nf)
 {
+    (void)nf;
     if (const char *e = std::getenv("RBSOG_NEAR_CAPACITY")) {
         int v = std::atoi(e);
         if (v >= 1 && v <= 4096) return v;
     }
     double n = (double)N / (L * L * L);
-    double w = L / (double)nf;
-    double expected = n * kPi * rl * rl * w;
-    return std::min(4096, std::max(8, (int)std::ceil(1.5 * expected + 24.0)));
+    double expected = n * (4.0 / 3.0) * kPi * rl * rl * rl / 5.0;
+    return std::min(4096, std::max(8, (int)std::ceil(1.5 * expected + 16.0)));
 }
 
 Derived derive(const rbsog_params *p, const rbsog_sog *s)
@@ -70,6 +71,9 @@ Derived derive(const rbsog_params *p, const rbsog_sog *s)
     d.nlat = lattice_points(d.mmax);
     d.kp = near_capacity(p->N, p->L, d.rl, d.nf);
     d.sbatch = std::max(1, std::min(64, 16384 / std::max(1, p->P)));
+    d.full_k = p->full_k ? 1 : 0;
+    d.nmodes = d.full_k ? d.nlat : (int64_t)p->P;
+    if (d.full_k) d.sbatch = 1;
     return d;
 }
 
@@ -98,11 +102,12 @@ Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
     L.xs = take(sizeof(double) * 4 * (size_t)N);
     L.tile_sum = take(sizeof(int32_t) * (size_t)scan_tiles(ncell));
     L.xb = take(sizeof(double) * 3 * (size_t)N);
-    L.samp = take(sizeof(double) * 4 * (size_t)P * (size_t)d.sbatch);
-    L.part = take(sizeof(double) * 2 * (size_t)nchunks(N, P) * (size_t)P);
-    L.rho = take(sizeof(double) * 2 * (size_t)P);
-    L.gk = take(sizeof(double) * 2 * (size_t)P);
-    L.eF = take(sizeof(double) * (size_t)P);
+    const size_t nm = (size_t)d.nmodes;
+    L.samp = take(sizeof(double) * 4 * (d.full_k ? nm : (size_t)P * (size_t)d.sbatch));
+    L.part = take(d.full_k ? 0 : sizeof(double) * 2 * (size_t)nchunks(N, P) * (size_t)P);
+    L.rho = take(sizeof(double) * 2 * nm);
+    L.gk = take(sizeof(double) * 2 * nm);
+    L.eF = take(sizeof(double) * nm);
     L.fnear = take(sizeof(double) * 15 * (size_t)N);
     L.epart = take(sizeof(double) * (size_t)near_blocks((int)N));
     L.kepart = take(sizeof(double) * (size_t)far_blocks((int)N));
@@ -123,6 +128,7 @@ int check_params(const rbsog_params *p, const rbsog_sog *s)
     if (!(p->L > 0.0) || !std::isfinite(p->L)) return fail(RBSOG_EINVAL, "L must be positive and finite");
     if (!(p->kT > 0.0) || !std::isfinite(p->kT)) return fail(RBSOG_EINVAL, "kT must be positive and finite");
     if (p->P < 1 || p->P > 4096) return fail(RBSOG_EINVAL, "P must lie in [1, 4096]");
+    if (p->full_k != 0 && p->full_k != 1) return fail(RBSOG_EINVAL, "full_k must be 0 or 1");
     if (p->precision != RBSOG_FP64 && p->precision != RBSOG_MIXED) return fail(RBSOG_EINVAL, "unknown precision");
     if (p->density < RBSOG_ADAPTIVE || p->density > RBSOG_DH4PI) return fail(RBSOG_EINVAL, "unknown density");
     if (p->mmax < 0 || p->mmax > kMaxLatticeM) return fail(RBSOG_EINVAL, "mmax must lie in [0, %d]", kMaxLatticeM);
@@ -249,7 +255,7 @@ RhoArgs rho_args(rbsog_handle *h, const double4 *samp)
 {
     RhoArgs a{};
     a.N = (int)h->p.N;
-    a.P = h->p.P;
+    a.P = (int)h->d.nmodes;
     a.chunk = rho_chunk((int)h->p.N, h->p.P);
     a.nchunk = nchunks(h->p.N, h->p.P);
     a.inv_L = 1.0 / h->p.L;
@@ -282,6 +288,10 @@ int prepare(rbsog_handle *h, const double *x, const int32_t *gate)
 // earlier draw already holds them.
 int modes(rbsog_handle *h, uint64_t step, int ahead, const double4 **samp)
 {
+    if (h->d.full_k) {   // every lattice mode, uploaded at creation
+        *samp = h->samp;
+        return RBSOG_OK;
+    }
     if (!(h->samp_n > 0 && step >= h->samp_step && step - h->samp_step < (uint64_t)h->samp_n)) {
         int n = std::max(1, std::min(ahead, h->d.sbatch));
         SampleArgs sa = sample_args(h, step, n);
@@ -297,7 +307,7 @@ FarArgs far_args(rbsog_handle *h, const double4 *samp, double *f, double *f_near
 {
     FarArgs fa{};
     fa.N = (int)h->p.N;
-    fa.P = h->p.P;
+    fa.P = (int)h->d.nmodes;
     fa.two_pi_over_L = (2.0 * kPi) / h->p.L;
     fa.inv_L = 1.0 / h->p.L;
     fa.xs = h->xs;
@@ -323,7 +333,7 @@ EnergyArgs energy_args(rbsog_handle *h, double *out, bool kick)
     EnergyArgs ea{};
     ea.nnear = near_blocks((int)h->p.N);
     ea.nfar = far_blocks((int)h->p.N);
-    ea.P = h->p.P;
+    ea.P = (int)h->d.nmodes;
     ea.epart = h->epart;
     ea.kepart = kick ? h->kepart : nullptr;
     ea.eF = h->eF;
@@ -339,8 +349,12 @@ EnergyArgs energy_args(rbsog_handle *h, double *out, bool kick)
 int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, double *v, double dt, double *energy)
 {
     RhoArgs ra = rho_args(h, samp);
-    HIPCHECK(timed(h, kRhoPartial, [&] { return launch_rho_partial(ra, h->st); }));
-    HIPCHECK(timed(h, kRhoReduce, [&] { return launch_rho_reduce(ra, h->st); }));
+    if (h->d.full_k) {
+        HIPCHECK(timed(h, kRhoPartial, [&] { return launch_rho_full(ra, h->st); }));
+    } else {
+        HIPCHECK(timed(h, kRhoPartial, [&] { return launch_rho_partial(ra, h->st); }));
+        HIPCHECK(timed(h, kRhoReduce, [&] { return launch_rho_reduce(ra, h->st); }));
+    }
     NearArgs na = near_args(h, nullptr, energy != nullptr);
     HIPCHECK(timed(h, kNear, [&] { return launch_near(na, h->st); }));
     FarArgs fa = far_args(h, samp, f, f_near, v, dt);
@@ -391,6 +405,10 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     h->g = make_geom(p->L, h->d.nc);
     h->gf = make_geom(p->L, h->d.nf);
     h->V = p->L * p->L * p->L;
+    if (h->d.full_k && (lattice_dev || h->d.nlat > 0x7fffffff)) {
+        delete h;
+        return fail(RBSOG_EINVAL, "full_k needs a lattice of fewer than 2^31 points in the system's own workspace");
+    }
     h->lay = make_layout(p->N, h->d, p->P, lattice_dev != nullptr);
     if (ws_bytes < h->lay.total) {
         size_t need = h->lay.total;
@@ -467,6 +485,23 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->size, t.shell_size.data(), sizeof(int32_t) * t.nshell, hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess) e = hipMemcpyAsync(h->tab, tabh, sizeof(tabh), hipMemcpyHostToDevice, h->st);
+    // full lattice: every n with its coefficient Fhat(k^2)/V, k = 2 pi n / L
+    std::vector<double> full;
+    if (e == hipSuccess && h->d.full_k) {
+        const double tt = (2.0 * kPi) / p->L, V = p->L * p->L * p->L;
+        full.resize(4 * (size_t)t.nlat);
+        for (int64_t i = 0; i < t.nlat; ++i) {
+            uint32_t pk = (uint32_t)t.packed[(size_t)i];
+            int nx = (int)(pk & 1023u) - kLatticeBias, ny = (int)((pk >> 10) & 1023u) - kLatticeBias;
+            int nz = (int)((pk >> 20) & 1023u) - kLatticeBias;
+            double m = (double)nx * nx + (double)ny * ny + (double)nz * nz;
+            full[4 * i] = nx;
+            full[4 * i + 1] = ny;
+            full[4 * i + 2] = nz;
+            full[4 * i + 3] = fhat(*s, tt * tt * m) / V;
+        }
+        e = hipMemcpyAsync(h->samp, full.data(), sizeof(double) * full.size(), hipMemcpyHostToDevice, h->st);
+    }
     if (e == hipSuccess) e = hipMemsetAsync(h->flag, 0, sizeof(int32_t) * 4, h->st);
     if (e == hipSuccess) e = hipMemsetAsync(h->count, 0, L.cell_start - L.count, h->st);
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
@@ -534,6 +569,7 @@ extern "C" int rbsog_build_cells(rbsog_handle *h, const double *x_dev, int32_t *
 extern "C" int rbsog_sample_k(rbsog_handle *h, uint64_t step, int32_t *n_dev, double *coef_dev)
 {
     if (!h) return fail(RBSOG_EINVAL, "null handle");
+    if (h->d.full_k) return fail(RBSOG_EINVAL, "a full_k system samples no modes");
     SampleArgs a = sample_args(h, step, 1);
     a.n_out = n_dev;
     a.coef_out = coef_dev;
@@ -546,6 +582,7 @@ extern "C" int rbsog_sample_k(rbsog_handle *h, uint64_t step, int32_t *n_dev, do
 extern "C" int rbsog_compute_rho(rbsog_handle *h, uint64_t step, const double *x_dev, double *rho_dev)
 {
     if (!h || !x_dev || !rho_dev) return fail(RBSOG_EINVAL, "null handle, x or rho");
+    if (h->d.full_k) return fail(RBSOG_EINVAL, "rbsog_compute_rho samples modes; not for a full_k system");
     const double4 *samp = nullptr;
     int rc = modes(h, step, 1, &samp);
     if (rc) return rc;

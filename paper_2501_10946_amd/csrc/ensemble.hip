@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -152,6 +153,12 @@ struct rbsog_ens {
     int nactive = 0;
     bool dirty = false;
     uint64_t E = 0;  // ensemble steps launched
+    uint64_t *E_dev = nullptr;  // the same counter on the device, advanced by the step itself
+    // the step as a HIP graph, captured once per resident set and replayed
+    bool use_graph = true;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
     // the packed Fourier lattice shared by every replica (a prefix serves any
     // smaller m_max), outside the pool
     int32_t *lat = nullptr;
@@ -163,6 +170,20 @@ struct rbsog_ens {
 namespace {
 
 int ens_fail_hip(hipError_t e, const char *what) { return fail(RBSOG_EHIP, "%s: %s", what, hipGetErrorString(e)); }
+
+// The last node of a step: the device's ensemble step counter moves on.
+__global__ void k_ens_advance(uint64_t *E)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) E[0] = E[0] + 1;
+}
+
+void drop_graph(rbsog_ens *s)
+{
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->exec = nullptr;
+    s->graph = nullptr;
+}
 
 // Rebuilds and uploads the work lists of the active replicas (largest first,
 // so the longest workgroups start early).
@@ -205,6 +226,7 @@ int rebuild_lists(rbsog_ens *s)
     s->rho_lds[0] = lds[0];
     s->rho_lds[1] = lds[1];
     s->dirty = false;
+    drop_graph(s);
     if (total == 0) return RBSOG_OK;
     // the previous lists may still be read by launched kernels: let them finish
     hipError_t e = hipStreamSynchronize(s->st);
@@ -343,6 +365,9 @@ extern "C" int rbsog_ens_create(size_t hbm_budget, int max_slots, void *hip_stre
     if (e == hipSuccess) e = hipMalloc((void **)&s->t_rho, sizeof(RhoArgs) * n);
     if (e == hipSuccess) e = hipMalloc((void **)&s->t_far, sizeof(FarArgs) * n);
     if (e == hipSuccess) e = hipMalloc((void **)&s->t_energy, sizeof(EnergyArgs) * n);
+    if (e == hipSuccess) e = hipMalloc((void **)&s->E_dev, sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMemsetAsync(s->E_dev, 0, sizeof(uint64_t), s->st);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&s->ev0);
     if (e == hipSuccess) {
         s->ev.resize(kEnsEvents, nullptr);
@@ -356,6 +381,8 @@ extern "C" int rbsog_ens_create(size_t hbm_budget, int max_slots, void *hip_stre
         return ens_fail_hip(e, "creating the ensemble");
     }
     s->alloc.init(s->budget);
+    if (const char *g = std::getenv("RBSOG_ENS_GRAPH"))   // 0: launch the kernels one by one each step
+        s->use_graph = std::atoi(g) != 0;
     *out = s;
     return RBSOG_OK;
 }
@@ -379,6 +406,7 @@ extern "C" int rbsog_ens_admit(rbsog_ens *s, const rbsog_params *p, const rbsog_
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RBSOG_EINVAL, "dt must be positive and finite");
     int rc = check_params(p, sog);
     if (rc) return rc;
+    if (p->full_k) return fail(RBSOG_EINVAL, "the ensemble serves random-batch replicas only (full_k = 0)");
     int slot = -1;
     for (int r = 0; r < s->max_slots; ++r)
         if (!s->rep[r].used) {
@@ -452,6 +480,62 @@ extern "C" int rbsog_ens_admit(rbsog_ens *s, const rbsog_params *p, const rbsog_
     return RBSOG_OK;
 }
 
+namespace {
+
+// One ensemble step of every active replica, enqueued on st.
+hipError_t enqueue_step(rbsog_ens *s, hipStream_t st)
+{
+    const EnsItem *it = s->items.p;
+    auto list = [&](int k) { return it + s->off[k]; };
+    hipError_t e = launch_kick_drift_batch(s->t_kick, list(rbsog_ens::L256), s->cnt[rbsog_ens::L256], st);
+    if (e == hipSuccess)
+        e = launch_cell_build_batch(s->t_cell, list(rbsog_ens::L256), s->cnt[rbsog_ens::L256], list(rbsog_ens::LTILE),
+                                    s->cnt[rbsog_ens::LTILE], st);
+    if (e == hipSuccess) e = launch_nlist_batch(s->t_nlist, list(rbsog_ens::LNLIST), s->cnt[rbsog_ens::LNLIST], st);
+    if (e == hipSuccess)
+        e = launch_sample_batch(s->t_samp, list(rbsog_ens::LSAMP), s->cnt[rbsog_ens::LSAMP], s->E_dev, st);
+    for (int pr = 0; pr < 2 && e == hipSuccess; ++pr)
+        if (s->cnt[rbsog_ens::LRHO0 + pr] > 0)
+            e = launch_rho_batch(s->t_rho, list(rbsog_ens::LRHO0 + pr), s->cnt[rbsog_ens::LRHO0 + pr], s->rho_lds[pr],
+                                 pr == 1, list(rbsog_ens::LRED0 + pr), s->cnt[rbsog_ens::LRED0 + pr], st);
+    for (int pr = 0; pr < 2 && e == hipSuccess; ++pr)
+        for (int g = 0; g < kGroups && e == hipSuccess; ++g) {
+            int k = (pr ? rbsog_ens::LNEAR1 : rbsog_ens::LNEAR0) + g;
+            if (s->cnt[k] > 0) e = launch_near_batch(s->t_near, list(k), s->cnt[k], g, pr == 1, true, st);
+        }
+    for (int pr = 0; pr < 2 && e == hipSuccess; ++pr)
+        if (s->cnt[rbsog_ens::LFAR0 + pr] > 0)
+            e = launch_far_batch(s->t_far, list(rbsog_ens::LFAR0 + pr), s->cnt[rbsog_ens::LFAR0 + pr], pr == 1, st);
+    if (e == hipSuccess)
+        e = launch_energy_batch(s->t_energy, list(rbsog_ens::LENERGY), s->cnt[rbsog_ens::LENERGY], s->E_dev, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_ens_advance, dim3(1), dim3(64), 0, st, s->E_dev);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+// Captures the step into a graph (the launch sequence only: kernel nodes, no
+// memory operations) on the ensemble's own capture stream.
+hipError_t capture_step(rbsog_ens *s)
+{
+    hipError_t e = hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = enqueue_step(s, s->cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s->cap, &g);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return le != hipSuccess ? le : e;
+    }
+    s->graph = g;
+    e = hipGraphInstantiate(&s->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) drop_graph(s);
+    return e;
+}
+
+}  // namespace
+
 extern "C" int rbsog_ens_step(rbsog_ens *s)
 {
     if (!s) return fail(RBSOG_EINVAL, "null ensemble");
@@ -460,31 +544,14 @@ extern "C" int rbsog_ens_step(rbsog_ens *s)
         if (rc) return rc;
     }
     if (s->nactive == 0) return RBSOG_OK;
-    const EnsItem *it = s->items.p;
-    auto list = [&](int k) { return it + s->off[k]; };
-    hipStream_t st = s->st;
-    HIPCHECK(launch_kick_drift_batch(s->t_kick, list(rbsog_ens::L256), s->cnt[rbsog_ens::L256], st));
-    HIPCHECK(launch_cell_build_batch(s->t_cell, list(rbsog_ens::L256), s->cnt[rbsog_ens::L256],
-                                     list(rbsog_ens::LTILE), s->cnt[rbsog_ens::LTILE], st));
-    HIPCHECK(launch_nlist_batch(s->t_nlist, list(rbsog_ens::LNLIST), s->cnt[rbsog_ens::LNLIST], st));
-    HIPCHECK(launch_sample_batch(s->t_samp, list(rbsog_ens::LSAMP), s->cnt[rbsog_ens::LSAMP], s->E, st));
-    for (int pr = 0; pr < 2; ++pr)
-        if (s->cnt[rbsog_ens::LRHO0 + pr] > 0)
-            HIPCHECK(launch_rho_batch(s->t_rho, list(rbsog_ens::LRHO0 + pr), s->cnt[rbsog_ens::LRHO0 + pr],
-                                      s->rho_lds[pr], pr == 1, list(rbsog_ens::LRED0 + pr),
-                                      s->cnt[rbsog_ens::LRED0 + pr], st));
-    for (int pr = 0; pr < 2; ++pr)
-        for (int g = 0; g < kGroups; ++g) {
-            int k = (pr ? rbsog_ens::LNEAR1 : rbsog_ens::LNEAR0) + g;
-            if (s->cnt[k] > 0) HIPCHECK(launch_near_batch(s->t_near, list(k), s->cnt[k], g, pr == 1, true, st));
-        }
-    for (int pr = 0; pr < 2; ++pr)
-        if (s->cnt[rbsog_ens::LFAR0 + pr] > 0)
-            HIPCHECK(launch_far_batch(s->t_far, list(rbsog_ens::LFAR0 + pr), s->cnt[rbsog_ens::LFAR0 + pr], pr == 1,
-                                      st));
-    HIPCHECK(launch_energy_batch(s->t_energy, list(rbsog_ens::LENERGY), s->cnt[rbsog_ens::LENERGY], s->E, st));
+    if (s->use_graph) {
+        if (!s->exec) HIPCHECK(capture_step(s));
+        HIPCHECK(hipGraphLaunch(s->exec, s->st));
+    } else {
+        HIPCHECK(enqueue_step(s, s->st));
+    }
     s->E += 1;
-    HIPCHECK(hipEventRecord(s->ev[s->E % kEnsEvents], st));
+    HIPCHECK(hipEventRecord(s->ev[s->E % kEnsEvents], s->st));
     for (int r = 0; r < s->max_slots; ++r) {
         Replica &R = s->rep[r];
         if (R.active && s->E - R.e_adm >= (uint64_t)R.nsteps) {
@@ -570,8 +637,11 @@ extern "C" void rbsog_ens_destroy(rbsog_ens *s)
     (void)hipStreamSynchronize(s->st);
     for (int r = 0; r < s->max_slots; ++r)
         if (s->rep[r].h) rbsog_destroy(s->rep[r].h);
+    drop_graph(s);
+    if (s->cap) (void)hipStreamDestroy(s->cap);
     s->items.release();
     if (s->lat) (void)hipFree(s->lat);
+    if (s->E_dev) (void)hipFree(s->E_dev);
     for (void *p : {(void *)s->t_kick, (void *)s->t_cell, (void *)s->t_nlist, (void *)s->t_near, (void *)s->t_samp,
                     (void *)s->t_rho, (void *)s->t_far, (void *)s->t_energy, (void *)s->pool})
         if (p) (void)hipFree(p);

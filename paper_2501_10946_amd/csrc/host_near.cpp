@@ -25,6 +25,23 @@ namespace rbsog {
 namespace {
 
 constexpr int kNodes = 64;
+constexpr int kCheck = 512;   // validation intervals on [-1, 1]
+
+// cos(pi k (j + 1/2) / kNodes), shared by every fit
+struct CosTable {
+    long double c[kNodes][kNodes];
+    CosTable()
+    {
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int k = 0; k < kNodes; ++k)
+            for (int j = 0; j < kNodes; ++j) c[k][j] = std::cos(pi * k * (j + 0.5L) / kNodes);
+    }
+};
+const CosTable &cos_table()
+{
+    static const CosTable t;
+    return t;
+}
 
 // H(r) (force) or K(r) (energy) in extended precision.
 long double hk(const rbsog_sog &s, long double r, bool force)
@@ -43,15 +60,12 @@ long double hk(const rbsog_sog &s, long double r, bool force)
 // y in [-1, 1], truncated to degree kNearPolyDeg and written in powers of y.
 bool fit(const rbsog_sog &s, double rc, bool force, double out[kNearPolyDeg + 1])
 {
-    const long double pi = 3.141592653589793238462643383279502884L;
+    const CosTable &ct = cos_table();
     std::vector<long double> fx(kNodes), b(kNodes);
-    for (int j = 0; j < kNodes; ++j) {
-        long double y = std::cos(pi * (j + 0.5L) / kNodes);
-        fx[j] = hk(s, 0.5L * (y + 1.0L) * (long double)rc, force);
-    }
+    for (int j = 0; j < kNodes; ++j) fx[j] = hk(s, 0.5L * (ct.c[1][j] + 1.0L) * (long double)rc, force);
     for (int k = 0; k < kNodes; ++k) {
         long double acc = 0.0L;
-        for (int j = 0; j < kNodes; ++j) acc += fx[j] * std::cos(pi * k * (j + 0.5L) / kNodes);
+        for (int j = 0; j < kNodes; ++j) acc += fx[j] * ct.c[k][j];
         b[k] = acc * (k == 0 ? 1.0L : 2.0L) / kNodes;
     }
     // sum_k b_k T_k(x) -> sum_k a_k x^k (k <= deg), with T_{k+1} = 2x T_k - T_{k-1}
@@ -72,8 +86,8 @@ bool fit(const rbsog_sog &s, double rc, bool force, double out[kNearPolyDeg + 1]
     // accept only a fit within tolerance (FP64 Horner as the kernel runs it;
     // H(0) = K(0) = 1 sets the scale)
     long double worst = 0.0L;
-    for (int j = 0; j <= 4096; ++j) {
-        double y = -1.0 + 2.0 * j / 4096.0;
+    for (int j = 0; j <= kCheck; ++j) {
+        double y = -1.0 + 2.0 * j / (double)kCheck;
         double p = out[kNearPolyDeg];
         for (int i = kNearPolyDeg - 1; i >= 0; --i) p = std::fma(p, y, out[i]);
         long double ref = hk(s, 0.5L * ((long double)y + 1.0L) * (long double)rc, force);

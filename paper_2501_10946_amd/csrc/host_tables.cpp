@@ -14,6 +14,8 @@ namespace {
 
 constexpr double kPi = 3.141592653589793;
 
+}  // namespace
+
 // Fhat(k^2) = sum_j A_j exp(-B_j k^2), ascending j.
 double fhat(const rbsog_sog &s, double k2)
 {
@@ -21,8 +23,6 @@ double fhat(const rbsog_sog &s, double k2)
     for (int j = 0; j < s.n; ++j) acc += s.A[j] * std::exp(-s.B[j] * k2);
     return acc;
 }
-
-}  // namespace
 
 // Correction factor of the measure.  ADAPTIVE is the leading Debye-Hueckel
 // term of eq. (3.22) as printed, with eps(k)^{-1}/k^2 = lambda^2/(1 + lambda^2 k^2)

@@ -51,6 +51,8 @@ int default_mmax(const rbsog_sog &s, double L);
 int64_t lattice_points(int mmax);
 void lattice_copy(int mmax, int32_t *out);
 double density(int kind, double kT, double V, double Q2, double lambda, double k2);
+// Fhat(k^2) = sum_m A_m exp(-B_m k^2) in ascending m
+double fhat(const rbsog_sog &s, double k2);
 // shell CDF, coefficients and shell ranges; the packed lattice too when asked
 void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax, Tables *t, bool with_lattice);
 // (sin, cos)(2 pi j / kPhaseTable), j = 0 .. kPhaseTable - 1, interleaved, from

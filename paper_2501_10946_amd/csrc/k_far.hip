@@ -204,14 +204,15 @@ __device__ inline void energy_body(const EnergyArgs &a, uint64_t shift)
 __global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a) { energy_body(a, 0); }
 
 __global__ __launch_bounds__(kBlock) void k_energy_batch(const EnergyArgs *__restrict__ tab,
-                                                         const EnsItem *__restrict__ items, uint64_t shift)
+                                                         const EnsItem *__restrict__ items, const uint64_t *shift)
 {
-    energy_body(tab[items[blockIdx.x].r], shift);
+    energy_body(tab[items[blockIdx.x].r], *shift);
 }
 
-hipError_t launch_energy_batch(const EnergyArgs *tab, const EnsItem *items, int n, uint64_t shift, hipStream_t st)
+hipError_t launch_energy_batch(const EnergyArgs *tab, const EnsItem *items, int n, const uint64_t *shift,
+                               hipStream_t st)
 {
-    if (!tab || !items || n < 1) return hipErrorInvalidValue;
+    if (!tab || !items || n < 1 || !shift) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_energy_batch, dim3(n), dim3(kBlock), 0, st, tab, items, shift);
     return hipGetLastError();
 }

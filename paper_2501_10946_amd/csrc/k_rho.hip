@@ -190,6 +190,62 @@ hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st)
 }
 
 
+// ---------------------------------------------------------------------------
+// structure factors over the whole lattice (the deterministic reference):
+// one lane per mode, the particles streamed through LDS in tiles of 256, each
+// lane summing them in two interleaved chains; writes rho, coef rho and the
+// energy term of every mode directly
+// ---------------------------------------------------------------------------
+
+template <bool MIXED>
+__global__ __launch_bounds__(kBlock) void k_rho_full(RhoArgs a)
+{
+    __shared__ double4 sp[kBlock];
+    __shared__ double2 tab[kPhaseTab];
+    const int t = threadIdx.x;
+    if (!MIXED)
+        for (int k = t; k < kPhaseTab; k += kBlock) tab[k] = a.tab[k];
+    const int l = blockIdx.x * kBlock + t;
+    const bool live = l < a.P;
+    const double4 k = live ? a.samp[l] : make_double4(0.0, 0.0, 0.0, 0.0);
+    double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+    for (int j0 = 0; j0 < a.N; j0 += kBlock) {
+        __syncthreads();
+        if (j0 + t < a.N) {
+            double4 v = a.xs[j0 + t];
+            sp[t] = make_double4(v.x * a.inv_L, v.y * a.inv_L, v.z * a.inv_L, v.w);
+        }
+        __syncthreads();
+        const int nj = min(kBlock, a.N - j0);
+        int i = 0;
+        for (; i + 1 < nj; i += 2) {
+            rho_term<true, MIXED>(a, tab, k, sp[i], re0, im0);
+            rho_term<true, MIXED>(a, tab, k, sp[i + 1], re1, im1);
+        }
+        if (i < nj) rho_term<true, MIXED>(a, tab, k, sp[i], re0, im0);
+    }
+    if (live) {
+        const double re = re0 + re1, im = im0 + im1, cf = k.w;
+        a.rho[l] = make_double2(re, im);
+        a.gk[l] = make_double2(cf * re, cf * im);
+        a.eF[l] = 0.5 * cf * (re * re + im * im);
+        if (a.rho_out) {
+            a.rho_out[2 * l] = re;
+            a.rho_out[2 * l + 1] = im;
+        }
+    }
+}
+
+hipError_t launch_rho_full(const RhoArgs &a, hipStream_t st)
+{
+    if (a.N < 1 || a.P < 1 || !a.xs || !a.samp || !a.rho || !a.gk || !a.eF || (!a.mixed && !a.tab))
+        return hipErrorInvalidValue;
+    dim3 grid((unsigned)((a.P + kBlock - 1) / kBlock));
+    if (a.mixed) hipLaunchKernelGGL(k_rho_full<true>, grid, dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL(k_rho_full<false>, grid, dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
 // Ensemble: one launch over every replica's groups (items: rho_blocks per
 // replica) with the largest staging any of them needs, then the reduction
 // (items: P per replica).

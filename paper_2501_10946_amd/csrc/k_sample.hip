@@ -44,17 +44,20 @@ __device__ inline void sample_body(const SampleArgs &a, int b, uint64_t shift)
 __global__ __launch_bounds__(kSampleThreads) void k_sample(SampleArgs a) { sample_body(a, (int)blockIdx.x, 0); }
 
 // Ensemble: one step per replica, the replica's step being its table entry's
-// step plus the launch's shift (the ensemble step counter).
+// step plus the ensemble step counter (read from device memory, so that a
+// captured launch sequence can be replayed step after step).
 __global__ __launch_bounds__(kSampleThreads) void k_sample_batch(const SampleArgs *__restrict__ tab,
-                                                                 const EnsItem *__restrict__ items, uint64_t shift)
+                                                                 const EnsItem *__restrict__ items,
+                                                                 const uint64_t *shift)
 {
     const EnsItem e = items[blockIdx.x];
-    sample_body(tab[e.r], e.b, shift);
+    sample_body(tab[e.r], e.b, *shift);
 }
 
-hipError_t launch_sample_batch(const SampleArgs *tab, const EnsItem *items, int n, uint64_t shift, hipStream_t st)
+hipError_t launch_sample_batch(const SampleArgs *tab, const EnsItem *items, int n, const uint64_t *shift,
+                               hipStream_t st)
 {
-    if (!tab || !items || n < 1) return hipErrorInvalidValue;
+    if (!tab || !items || n < 1 || !shift) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sample_batch, dim3(n), dim3(kSampleThreads), 0, st, tab, items, shift);
     return hipGetLastError();
 }

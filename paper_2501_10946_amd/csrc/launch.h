@@ -124,7 +124,9 @@ struct SampleArgs {
 };
 hipError_t launch_sample(const SampleArgs &a, hipStream_t st);
 // ensemble: items of 64 draws, ceil(P/64) per replica, nstep = 1
-hipError_t launch_sample_batch(const SampleArgs *tab, const EnsItem *items, int n, uint64_t shift, hipStream_t st);
+// (shift: device word holding the ensemble step counter)
+hipError_t launch_sample_batch(const SampleArgs *tab, const EnsItem *items, int n, const uint64_t *shift,
+                               hipStream_t st);
 
 // --- structure factors -----------------------------------------------------------
 struct RhoArgs {
@@ -144,6 +146,8 @@ struct RhoArgs {
 };
 hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st);
 hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st);
+// every mode of samp[P] over all particles of xs, rho/gk/eF written directly
+hipError_t launch_rho_full(const RhoArgs &a, hipStream_t st);
 // workgroups of the partial kernel and its dynamic LDS bytes
 __host__ __device__ inline int64_t rho_blocks(int nchunk, int P) { return ((int64_t)nchunk * P + kBlock - 1) / kBlock; }
 size_t rho_lds_bytes(int P, int chunk);
@@ -171,7 +175,7 @@ struct NearArgs {
     int32_t *nbr;              // [5 kp][N] listed j per particle (planes concatenated), column-major
     int32_t *nbr_stage;        // [5 kp][N] list build: rows plane*kp.. of each plane
     int32_t *nbr_cnt;          // [N] listed count per particle; 5 kp + 1 when a plane overflowed
-    int kp;                    // list capacity per (particle, plane)
+    int kp;                    // list capacity per (particle, chunk); 5 kp per particle
     double rl2;                // squared list radius (r_c + skin)^2; the fine grid has cells >= (r_c + skin)/2
     const int32_t *gate;       // list build: null = always, else only when *gate != 0
 };
@@ -227,8 +231,9 @@ struct EnergyArgs {
     uint64_t row0;
 };
 hipError_t launch_energy(const EnergyArgs &a, hipStream_t st);
-// ensemble: one item per replica; each writes row shift + row0 of its out
-hipError_t launch_energy_batch(const EnergyArgs *tab, const EnsItem *items, int n, uint64_t shift, hipStream_t st);
+// ensemble: one item per replica; each writes row *shift + row0 of its out
+hipError_t launch_energy_batch(const EnergyArgs *tab, const EnsItem *items, int n, const uint64_t *shift,
+                               hipStream_t st);
 
 
 }  // namespace rbsog

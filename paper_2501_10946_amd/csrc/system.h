@@ -40,8 +40,10 @@ struct Derived {
     int nc, nf;        // coarse and fine cells per axis
     int mmax;
     int64_t nlat;
-    int kp;            // neighbour-list capacity per (particle, plane)
+    int kp;            // neighbour-list capacity per (particle, chunk)
     int sbatch;        // steps whose modes one sampling launch draws
+    int full_k;        // deterministic far field over the whole lattice
+    int64_t nmodes;    // modes of one evaluation: P, or nlat with full_k
 };
 
 size_t align_up(size_t v);

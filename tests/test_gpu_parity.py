@@ -274,3 +274,59 @@ def test_trajectory_independent_of_skin(dev, skin):
     d = x.cpu().numpy() - xo
     d -= w.L * np.round(d / w.L)
     assert np.abs(d).max() <= 1e-10
+
+
+FULLK = [
+    workloads.OCP_1K,
+    workloads.Workload("fullk_ragged_n777", N=777, kappa=1.0, gamma=1.0, r_c=3.0, P=300, seed=5),
+    workloads.Workload("fullk_mix_n2000", N=2000, kappa=0.5, gamma=5.0, r_c=4.0, P=64, seed=12, frac_b=0.1, q_b=5.0,
+                       m_b=20.0),
+]
+
+
+@pytest.mark.parametrize("w", FULLK, ids=lambda w: w.name)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_k_forces_and_energy(dev, w, precision):
+    """The deterministic full-lattice far field (full_k = 1) against the
+    oracle's full-lattice sum (eqs. 3.5 and UF without sampling): forces,
+    their far part, and the far energy; the result is the same at any
+    evaluation index (nothing is sampled)."""
+    st = workloads.make_state(w)
+    o = oracle.sog_auto(w.lam, w.r_c, w.eps)
+    sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+    print(f"\n[case] full_k {w.name} N={w.N} prec={precision}", flush=True)
+    s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, precision=precision, full_k=True, device=dev)
+    ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed, full_k=True)
+    x = torch.tensor(st.x, device=dev)
+    outs = []
+    for step in (3, 11):
+        f = torch.empty_like(x)
+        fn = torch.empty_like(x)
+        e = torch.zeros(6, dtype=torch.float64, device=dev)
+        R.rbsog_compute_forces(s.h, step, x, f, fn, e)
+        torch.cuda.synchronize()
+        outs.append((f.cpu().numpy(), fn.cpu().numpy(), e.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][2], outs[1][2])
+    f, fn, e = outs[0]
+    fo, fno, eo = ref.force(st.x, 3)
+    tol = FP64_TOL if precision == 0 else MIXED_TOL
+    assert rel(f, fo) < tol
+    assert rel(f - fn, fo - fno) < tol
+    assert abs(e[1] - eo[1]) <= tol * abs(eo[1])
+    assert np.allclose(e[[0, 2, 3, 4]], eo[[0, 2, 3, 4]], rtol=tol, atol=0)
+
+
+def test_full_k_refuses_sampling_calls(dev):
+    w = workloads.OCP_1K
+    st = workloads.make_state(w)
+    sog = R.rbsog_sog_init(w.lam, w.r_c, 1e-4)
+    s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=1, full_k=True, device=dev)
+    n = torch.zeros((w.P, 3), dtype=torch.int32, device=dev)
+    coef = torch.zeros(w.P, dtype=torch.float64, device=dev)
+    with pytest.raises(R.RbsogError) as ei:
+        R.rbsog_sample_k(s.h, 0, n, coef)
+    assert ei.value.code == R.RBSOG_EINVAL
+    rho = torch.zeros((w.P, 2), dtype=torch.float64, device=dev)
+    with pytest.raises(R.RbsogError) as ei:
+        R.rbsog_compute_rho(s.h, 0, torch.tensor(st.x, device=dev), rho)
+    assert ei.value.code == R.RBSOG_EINVAL
