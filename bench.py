@@ -95,6 +95,36 @@ def energy_drift(E, dt: float, scale: float) -> dict:
     return {"steps": n, "slope_NkT_per_time": float(coef[0]), "stderr": se, "std_NkT": float(np.std(y))}
 
 
+def force_noise(R, h, h_full, x, m, w, evals: int) -> dict:
+    """Random-batch force noise at one state: forces of `evals` independent
+    draws (force indices 10^6 + k) against the full-lattice force of the same
+    positions.  Velocity-Verlet applies each step's force noise xi over one
+    whole time step, so the kinetic energy grows by dt^2 |xi|^2 / (2 m) per
+    step and particle: the expected energy drift is dt <|xi|^2 / m> / (2 kT) in
+    N kT per unit time.  The mean of the draws estimates the bias, whose RMS
+    over particles should be that of the noise over sqrt(evals)."""
+    import torch
+    ff = torch.empty_like(x)
+    R.rbsog_compute_forces(h_full, 0, x, ff)
+    fr = torch.empty_like(x)
+    s1 = torch.zeros_like(x)
+    s2 = torch.zeros(x.shape[1], dtype=torch.float64, device=x.device)
+    for k in range(evals):
+        R.rbsog_compute_forces(h, 1_000_000 + k, x, fr)
+        d = fr - ff
+        s1 += d
+        s2 += (d * d).sum(dim=0)
+    torch.cuda.synchronize()
+    R.rbsog_check(h)
+    xi2 = s2 / evals
+    bias = s1 / evals
+    bias_rms = float((bias * bias).sum(dim=0).mean()) ** 0.5
+    noise_rms = float(xi2.mean()) ** 0.5
+    return {"evals": evals, "xi_rms": noise_rms, "f_full_rms": float((ff * ff).sum(dim=0).mean()) ** 0.5,
+            "bias_rms": bias_rms, "bias_rms_expected": noise_rms / evals ** 0.5,
+            "predicted_slope_NkT_per_time": w.dt * float((xi2 / m).mean()) / (2.0 * w.kT)}
+
+
 def serve(args, dev, log):
     """The served ensemble: seeded requests (N log-uniform in [500, 5e4], Gamma
     log-uniform in [0.1, 100], kappa uniform in [0.1, 2], r_c 4, P 200, 100
@@ -218,6 +248,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-ensemble measurement")
     ap.add_argument("--no-fullk-energy", action="store_true",
                     help="skip the deterministic full-lattice energy along the first 100 FP64 NVE steps")
+    ap.add_argument("--noise-evals", type=int, default=200,
+                    help="random-batch draws for the force-noise estimate of the drift (0: none)")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rates", default="0.5,0.8,1.2",
                     help="Poisson arrival rates as fractions of the measured saturated capacity")
@@ -338,6 +370,8 @@ def main():
                 slope = float(np.polyfit(tt, np.array(efull), 1)[0])
                 res["drift"]["full_k"] = {"steps": [0, 25, 50, 75, 100], "E_NkT": efull,
                                           "slope_NkT_per_time": slope, "lattice_points": R.rbsog_get_info(sfk.h).nlat}
+                if args.noise_evals > 0:
+                    res["drift"]["noise"] = force_noise(R, s.h, sfk.h, x_eq, mt, w, args.noise_evals)
                 del sfk
         results[name] = res
         log(f"[bench] {name}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.3f} ms/step, "

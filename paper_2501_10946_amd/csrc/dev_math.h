@@ -127,9 +127,12 @@ __device__ inline void sincos_rev(double u, const SinCosPoly &P, double *s, doub
     *c = ((qi + 1) & 2) ? -c1 : c1;
 }
 
-// sin(2 pi f), cos(2 pi f) for |f| <= 1/256 by their Taylor series to degree 7
-// and 6 (s[k], c[k] as in SinCosPoly, k = 0..3): the first omitted terms are
-// below 4e-19 relative to sin and 4e-18 absolute.
+constexpr int kPhaseTab = 128;   // entries of the rotation table
+
+// sin(2 pi f / 128), cos(2 pi f / 128) for |f| <= 1/2 (f in 1/128 revolutions)
+// by their Taylor series to degree 7 and 6 (s[k] = (-1)^k a^(2k+1)/(2k+1)!,
+// c[k] = (-1)^k a^(2k)/(2k)!, a = 2 pi / 128): the first omitted terms are below
+// 4e-19 relative to sin and 4e-18 absolute.
 struct SinCosShort {
     double s[4];
     double c[4];
@@ -139,23 +142,22 @@ constexpr SinCosShort make_sincos_short()
     SinCosShort p{};
     for (int k = 0; k < 4; ++k) {
         double sg = (k % 2) ? -1.0 : 1.0;
-        p.s[k] = sg * taylor_coef(kTwoPi, 2 * k + 1);
-        p.c[k] = sg * taylor_coef(kTwoPi, 2 * k);
+        p.s[k] = sg * taylor_coef(kTwoPi / kPhaseTab, 2 * k + 1);
+        p.c[k] = sg * taylor_coef(kTwoPi / kPhaseTab, 2 * k);
     }
     return p;
 }
 
-constexpr int kPhaseTab = 128;   // entries of the rotation table
 
-// sin(2 pi u), cos(2 pi u) for a phase u in revolutions (FP64) with a table of
-// (sin, cos)(2 pi j / 128): u = m / 128 + f exactly with m = rint(128 u) and
-// |f| <= 1/256 (u 128 and m / 128 are exact; for |u| < 2^24 the difference is
-// exact too), the short series give the rotation by f, and the table entry of
-// m mod 128 the rest.
-__device__ inline void sincos_rev_tab(double u, const double2 *tab, const SinCosShort &P, double *s, double *c)
+// sin(2 pi w / 128), cos(2 pi w / 128) for a phase w in 1/128 revolutions
+// (FP64; the callers scale positions by 128 / L, exactly) with a table of
+// (sin, cos)(2 pi j / 128): w = m + f exactly with m = rint(w) and |f| <= 1/2
+// (for |w| < 2^52 the difference is exact), the short series give the rotation
+// by f and the table entry of m mod 128 (in LDS) the rest.
+__device__ inline void sincos_rev_tab(double w, const double2 *tab, const SinCosShort &P, double *s, double *c)
 {
-    double jr = rint(u * (double)kPhaseTab);
-    double f = fma(jr, -1.0 / kPhaseTab, u);
+    double jr = rint(w);
+    double f = w - jr;
     double2 t = tab[(int)jr & (kPhaseTab - 1)];
     double f2 = f * f;
     double sp = fma(fma(fma(P.s[3], f2, P.s[2]), f2, P.s[1]), f2, P.s[0]) * f;

@@ -20,7 +20,9 @@ constexpr int kFarGroups = 4;
 constexpr int kFarThreads = 64 * kFarGroups;
 constexpr int kFarTile = 256;
 
-// Im(exp(-i k.r) coef rho) of one mode (kv: n, gv: coef rho), r/L = (sx, sy, sz).
+// Im(exp(-i k.r) coef rho) of one mode (kv: n, gv: coef rho); (sx, sy, sz) is
+// r/L (mixed) or 128 r/L (FP64), so that n.s is the phase in the unit that the
+// precision's sine and cosine take.
 template <bool MIXED>
 __device__ inline double far_term(const FarArgs &a, const double2 *tab, const double4 &kv, const double2 &gv,
                                   double sx, double sy, double sz)
@@ -43,15 +45,18 @@ __device__ inline void far_body(const FarArgs &a, int b)
     __shared__ double4 sk[kFarTile];
     __shared__ double2 sg[kFarTile];
     __shared__ double2 tab[kPhaseTab];
-    __shared__ double part[3][kFarThreads];
     __shared__ double red[64];
+    static_assert(sizeof(sk) >= 3 * kFarThreads * sizeof(double), "partials reuse the sample tile");
+    double(*part)[kFarThreads] = (double(*)[kFarThreads])sk;
     const int t = threadIdx.x;
     const int g = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;   // g is uniform per wave
     const int p = b * 64 + lane;
     if (a.gate_clear && b == 0 && t == 0) *a.gate_clear = 0;
     const bool live = p < a.N;
     double4 pi = live ? a.xs[p] : make_double4(0.0, 0.0, 0.0, 0.0);
-    double sx = pi.x * a.inv_L, sy = pi.y * a.inv_L, sz = pi.z * a.inv_L;
+    // phases in revolutions (mixed) or 1/128 revolutions (FP64 table path)
+    const double ph = MIXED ? a.inv_L : a.inv_L * kPhaseTab;
+    double sx = pi.x * ph, sy = pi.y * ph, sz = pi.z * ph;
     double ax = 0.0, ay = 0.0, az = 0.0;
     if (!MIXED)
         for (int k = t; k < kPhaseTab; k += kFarThreads) tab[k] = a.tab[k];
@@ -84,6 +89,7 @@ __device__ inline void far_body(const FarArgs &a, int b)
             az += im0 * k0.z;
         }
     }
+    __syncthreads();   // the sample tile is done with: it holds the partials next
     part[0][t] = ax;
     part[1][t] = ay;
     part[2][t] = az;

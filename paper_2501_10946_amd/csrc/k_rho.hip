@@ -18,6 +18,9 @@ namespace rbsog {
 
 constexpr int kRhoStage = 1024;   // particles one workgroup stages at most
 
+// One particle's term q exp(i k.r) of a mode; p holds (r/L, q) (mixed) or
+// (128 r/L, q) (FP64), so that k.p is the phase in the unit that the
+// precision's sine and cosine take.
 template <bool CELL, bool MIXED>
 __device__ inline void rho_term(const RhoArgs &a, const double2 *tab, const double4 &k, const double4 &p,
                                 double &re, double &im)
@@ -39,22 +42,23 @@ __device__ inline void rho_term(const RhoArgs &a, const double2 *tab, const doub
 template <bool CELL, bool MIXED>
 __device__ inline void rho_partial_body(const RhoArgs &a, int b)
 {
-    // dynamic LDS: the rotation table, then the staged particles
+    // dynamic LDS: the rotation table (FP64), then the staged particles
     extern __shared__ double4 lds[];
     double2 *tab = (double2 *)lds;
-    double4 *sp = lds + kPhaseTab / 2;
+    double4 *sp = lds + (MIXED ? 0 : kPhaseTab / 2);
     const int t = threadIdx.x;
     const int64_t g0 = (int64_t)b * kBlock;
     const int s_lo = (int)(g0 / a.P);
     const int s_hi = (int)min((int64_t)a.nchunk - 1, (g0 + kBlock - 1) / a.P);
     const int j_lo = s_lo * a.chunk;
     const int j_hi = min(a.N, (s_hi + 1) * a.chunk);
+    const double ph = MIXED ? a.inv_L : a.inv_L * kPhaseTab;   // phase unit of the precision
     for (int k = t; k < j_hi - j_lo; k += kBlock) {
         int j = j_lo + k;
         double4 v;
         if (CELL) v = a.xs[j];
         else v = make_double4(a.x[j], a.x[a.N + j], a.x[2 * a.N + j], a.q[j]);
-        sp[k] = make_double4(v.x * a.inv_L, v.y * a.inv_L, v.z * a.inv_L, v.w);
+        sp[k] = make_double4(v.x * ph, v.y * ph, v.z * ph, v.w);
     }
     if (!MIXED)
         for (int k = t; k < kPhaseTab; k += kBlock) tab[k] = a.tab[k];
@@ -88,21 +92,27 @@ __global__ __launch_bounds__(kBlock) void k_rho_partial_batch(const RhoArgs *__r
     rho_partial_body<true, MIXED>(tab[e.r], e.b);
 }
 
-// One workgroup per sample: fixed-order sum of the chunk partials.
-// Mode b: thread t adds the partials of groups t, t + 256, ... in order (four
-// loads in flight), the 64 lanes of each wave are added by a fixed butterfly,
-// and thread 0 adds the four wave sums in order.
+// Fixed-order sum of the chunk partials, one workgroup per kRedModes adjacent
+// samples so that each partial row is read as one contiguous segment.  Thread
+// t takes sample l = kRedModes b + (t mod kRedModes) and adds the partials of
+// groups c, c + 64, c + 128, ... (c = t / kRedModes, four loads in flight); the
+// 16 threads of a wave that share a sample are added by a fixed butterfly and
+// the four waves in order.
 __device__ inline void rho_reduce_body(const RhoArgs &a, int b)
 {
-    __shared__ double2 red[kBlock / 64];
-    const int l = b, t = threadIdx.x;
-    const double2 *col = a.part + l;
+    constexpr int kLanes = kBlock / kRedModes;   // group streams per sample
+    __shared__ double2 red[kBlock / 64][kRedModes];
+    const int t = threadIdx.x, m = t % kRedModes, c0 = t / kRedModes;
+    const int l = b * kRedModes + m;
+    const bool live = l < a.P;
+    const double2 *col = a.part + (live ? l : 0);
     const size_t P = (size_t)a.P;
+    const int nch = live ? a.nchunk : 0;
     double re = 0.0, im = 0.0;
-    int c = t;
-    for (; c + 3 * kBlock < a.nchunk; c += 4 * kBlock) {
-        double2 v0 = col[(size_t)c * P], v1 = col[(size_t)(c + kBlock) * P];
-        double2 v2 = col[(size_t)(c + 2 * kBlock) * P], v3 = col[(size_t)(c + 3 * kBlock) * P];
+    int c = c0;
+    for (; c + 3 * kLanes < nch; c += 4 * kLanes) {
+        double2 v0 = col[(size_t)c * P], v1 = col[(size_t)(c + kLanes) * P];
+        double2 v2 = col[(size_t)(c + 2 * kLanes) * P], v3 = col[(size_t)(c + 3 * kLanes) * P];
         re += v0.x;
         im += v0.y;
         re += v1.x;
@@ -112,25 +122,25 @@ __device__ inline void rho_reduce_body(const RhoArgs &a, int b)
         re += v3.x;
         im += v3.y;
     }
-    for (; c < a.nchunk; c += kBlock) {
+    for (; c < nch; c += kLanes) {
         double2 v = col[(size_t)c * P];
         re += v.x;
         im += v.y;
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
+    for (int off = 32; off >= kRedModes; off >>= 1) {
         re += __shfl_xor(re, off);
         im += __shfl_xor(im, off);
     }
-    if ((t & 63) == 0) red[t >> 6] = make_double2(re, im);
+    if ((t & 63) < kRedModes) red[t >> 6][m] = make_double2(re, im);
     __syncthreads();
-    if (t == 0) {
+    if (t < kRedModes && live) {
         re = 0.0;
         im = 0.0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) {
-            re += red[w].x;
-            im += red[w].y;
+            re += red[w][t].x;
+            im += red[w][t].y;
         }
         double cf = a.samp[l].w;
         a.rho[l] = make_double2(re, im);
@@ -171,7 +181,7 @@ hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st)
         (lanes + kBlock - 1) / kBlock > 0x7fffffff)
         return hipErrorInvalidValue;
     dim3 grid((unsigned)((lanes + kBlock - 1) / kBlock));
-    size_t lds = rho_lds_bytes(a.P, a.chunk);
+    size_t lds = rho_lds_bytes(a.P, a.chunk, a.mixed);
     if (a.xs) {
         if (a.mixed) hipLaunchKernelGGL((k_rho_partial<true, true>), grid, dim3(kBlock), lds, st, a);
         else hipLaunchKernelGGL((k_rho_partial<true, false>), grid, dim3(kBlock), lds, st, a);
@@ -185,7 +195,7 @@ hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st)
 hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st)
 {
     if (!a.part || !a.rho || !a.gk || !a.eF || !a.samp) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_rho_reduce, dim3(a.P), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_rho_reduce, dim3(rho_reduce_blocks(a.P)), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 
@@ -207,13 +217,14 @@ __global__ __launch_bounds__(kBlock) void k_rho_full(RhoArgs a)
         for (int k = t; k < kPhaseTab; k += kBlock) tab[k] = a.tab[k];
     const int l = blockIdx.x * kBlock + t;
     const bool live = l < a.P;
+    const double ph = MIXED ? a.inv_L : a.inv_L * kPhaseTab;   // phase unit of the precision
     const double4 k = live ? a.samp[l] : make_double4(0.0, 0.0, 0.0, 0.0);
     double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
     for (int j0 = 0; j0 < a.N; j0 += kBlock) {
         __syncthreads();
         if (j0 + t < a.N) {
             double4 v = a.xs[j0 + t];
-            sp[t] = make_double4(v.x * a.inv_L, v.y * a.inv_L, v.z * a.inv_L, v.w);
+            sp[t] = make_double4(v.x * ph, v.y * ph, v.z * ph, v.w);
         }
         __syncthreads();
         const int nj = min(kBlock, a.N - j0);
@@ -249,9 +260,9 @@ hipError_t launch_rho_full(const RhoArgs &a, hipStream_t st)
 // Ensemble: one launch over every replica's groups (items: rho_blocks per
 // replica) with the largest staging any of them needs, then the reduction
 // (items: P per replica).
-size_t rho_lds_bytes(int P, int chunk)
+size_t rho_lds_bytes(int P, int chunk, bool mixed)
 {
-    return sizeof(double4) * (kPhaseTab / 2 + (size_t)(255 / P + 2) * chunk);
+    return sizeof(double4) * ((mixed ? 0 : kPhaseTab / 2) + (size_t)(255 / P + 2) * chunk);
 }
 
 hipError_t launch_rho_batch(const RhoArgs *tab, const EnsItem *part_items, int npart, size_t lds, bool mixed,

@@ -150,9 +150,12 @@ hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st);
 hipError_t launch_rho_full(const RhoArgs &a, hipStream_t st);
 // workgroups of the partial kernel and its dynamic LDS bytes
 __host__ __device__ inline int64_t rho_blocks(int nchunk, int P) { return ((int64_t)nchunk * P + kBlock - 1) / kBlock; }
-size_t rho_lds_bytes(int P, int chunk);
+size_t rho_lds_bytes(int P, int chunk, bool mixed);
+// the reduction: one workgroup per kRedModes adjacent samples
+constexpr int kRedModes = 4;
+__host__ __device__ inline int rho_reduce_blocks(int P) { return (P + kRedModes - 1) / kRedModes; }
 // ensemble: partials (rho_blocks items per replica, lds = the largest
-// rho_lds_bytes), then the reduction (P items per replica)
+// rho_lds_bytes), then the reduction (rho_reduce_blocks items per replica)
 hipError_t launch_rho_batch(const RhoArgs *tab, const EnsItem *part_items, int npart, size_t lds, bool mixed,
                             const EnsItem *red_items, int nred, hipStream_t st);
 
