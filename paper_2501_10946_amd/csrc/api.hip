@@ -98,10 +98,15 @@ Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
     L.fill = take(sizeof(int32_t) * (size_t)ncell);
     L.tmp = take(sizeof(int32_t) * (size_t)N);
     L.order = take(sizeof(int32_t) * (size_t)N);
-    L.pos = take(sizeof(int32_t) * (size_t)N);
+    L.order_old = take(sizeof(int32_t) * (size_t)N);
     L.xs = take(sizeof(double) * 4 * (size_t)N);
+    L.xs_old = take(sizeof(double) * 4 * (size_t)N);
     L.tile_sum = take(sizeof(int32_t) * (size_t)scan_tiles(ncell));
     L.xb = take(sizeof(double) * 3 * (size_t)N);
+    L.vs = take(sizeof(double) * 3 * (size_t)N);
+    L.vs_old = take(sizeof(double) * 3 * (size_t)N);
+    L.fs = take(sizeof(double) * 3 * (size_t)N);
+    L.ms = take(sizeof(double) * (size_t)N);
     const size_t nm = (size_t)d.nmodes;
     L.samp = take(sizeof(double) * 4 * (d.full_k ? nm : (size_t)P * (size_t)d.sbatch));
     L.part = take(d.full_k ? 0 : sizeof(double) * 2 * (size_t)nchunks(N, P) * (size_t)P);
@@ -175,7 +180,7 @@ hipError_t harvest(rbsog_handle *h)
         float ms = 0.0f;
         e = hipEventElapsedTime(&ms, h->events[r.second], h->events[r.second + 1]);
         if (e != hipSuccess) return e;
-        h->ms[r.first] += ms;
+        h->timing_ms[r.first] += ms;
         h->launches[r.first] += 1;
     }
     h->records.clear();
@@ -184,25 +189,45 @@ hipError_t harvest(rbsog_handle *h)
 }
 
 
-CellArgs cell_args(rbsog_handle *h, const double *x, const CellGeom &g, const int32_t *gate, double *xb)
+CellArgs cell_args(rbsog_handle *h, const CellGeom &g, const int32_t *gate, bool carry_v)
 {
     CellArgs a{};
     a.N = (int)h->p.N;
     a.g = g;
-    a.x = x;
-    a.q = h->q;
+    a.xs = h->xs;
+    a.order = h->order;
+    a.vs = carry_v ? h->vs : nullptr;
+    a.xs_old = h->xs_old;
+    a.order_old = h->order_old;
+    a.vs_old = h->vs_old;
+    a.m = h->m;
+    a.ms = h->ms;
+    a.xb = h->xb;
     a.cell_id = h->cell_id;
     a.count = h->count;
     a.cell_start = h->cell_start;
     a.fill = h->fill;
     a.tmp = h->tmp;
-    a.order = h->order;
-    a.pos = h->pos;
-    a.xs = h->xs;
     a.tile_sum = h->tile_sum;
     a.ticket = h->ticket;
     a.gate = gate;
-    a.xb = xb;
+    return a;
+}
+
+PermArgs perm_args(rbsog_handle *h, double *x, double *v, double *f)
+{
+    PermArgs a{};
+    a.N = (int)h->p.N;
+    a.order = h->order;
+    a.x = x;
+    a.v = v;
+    a.f = f;
+    a.q = h->q;
+    a.m = h->m;
+    a.xs = h->xs;
+    a.vs = h->vs;
+    a.fs = h->fs;
+    a.ms = h->ms;
     return a;
 }
 
@@ -271,12 +296,12 @@ RhoArgs rho_args(rbsog_handle *h, const double4 *samp)
     return a;
 }
 
-// Cell order + neighbour lists of the fine grid for positions x: always
+// Cell order + neighbour lists of the fine grid for the rows in xs: always
 // (gate == null, a single evaluation) or only when the device gate is raised
-// (the step path, where the drift has already written the positions into xs).
-int prepare(rbsog_handle *h, const double *x, const int32_t *gate)
+// (the step path, where the drift has already moved the rows).
+int prepare(rbsog_handle *h, const int32_t *gate, bool carry_v)
 {
-    CellArgs ca = cell_args(h, x, h->gf, gate, h->xb);
+    CellArgs ca = cell_args(h, h->gf, gate, carry_v);
     HIPCHECK(timed(h, kCells, [&] { return launch_cell_build(ca, h->st); }));
     NearArgs na = near_args(h, gate, false);
     HIPCHECK(timed(h, kNlist, [&] { return launch_nlist(na, h->st); }));
@@ -303,7 +328,7 @@ int modes(rbsog_handle *h, uint64_t step, int ahead, const double4 **samp)
     return RBSOG_OK;
 }
 
-FarArgs far_args(rbsog_handle *h, const double4 *samp, double *f, double *f_near, double *v, double dt)
+FarArgs far_args(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bool kick, double dt)
 {
     FarArgs fa{};
     fa.N = (int)h->p.N;
@@ -317,10 +342,11 @@ FarArgs far_args(rbsog_handle *h, const double4 *samp, double *f, double *f_near
     fa.fnear = h->fnear;
     fa.f = f;
     fa.f_near_out = f_near;
-    fa.v = v;
-    fa.m = h->m;
+    fa.fs = kick ? h->fs : nullptr;
+    fa.vs = kick ? h->vs : nullptr;
+    fa.ms = h->ms;
     fa.half_dt = 0.5 * dt;
-    fa.kepart = v ? h->kepart : nullptr;
+    fa.kepart = kick ? h->kepart : nullptr;
     fa.flag = h->flag;
     fa.mixed = h->p.precision == RBSOG_MIXED;
     fa.tab = h->tab;
@@ -346,7 +372,7 @@ EnergyArgs energy_args(rbsog_handle *h, double *out, bool kick)
 
 // Structure factors, near field, far field (+ optional kick) and the energy
 // sums of one evaluation whose cell order, lists and modes are prepared.
-int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, double *v, double dt, double *energy)
+int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bool kick, double dt, double *energy)
 {
     RhoArgs ra = rho_args(h, samp);
     if (h->d.full_k) {
@@ -357,10 +383,10 @@ int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, do
     }
     NearArgs na = near_args(h, nullptr, energy != nullptr);
     HIPCHECK(timed(h, kNear, [&] { return launch_near(na, h->st); }));
-    FarArgs fa = far_args(h, samp, f, f_near, v, dt);
+    FarArgs fa = far_args(h, samp, f, f_near, kick, dt);
     HIPCHECK(timed(h, kFar, [&] { return launch_far(fa, h->st); }));
     if (energy) {
-        EnergyArgs ea = energy_args(h, energy, v != nullptr);
+        EnergyArgs ea = energy_args(h, energy, kick);
         HIPCHECK(timed(h, kEnergy, [&] { return launch_energy(ea, h->st); }));
     }
     return RBSOG_OK;
@@ -449,10 +475,15 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     h->fill = (int32_t *)(w + L.fill);
     h->tmp = (int32_t *)(w + L.tmp);
     h->order = (int32_t *)(w + L.order);
-    h->pos = (int32_t *)(w + L.pos);
+    h->order_old = (int32_t *)(w + L.order_old);
     h->xs = (double4 *)(w + L.xs);
+    h->xs_old = (double4 *)(w + L.xs_old);
     h->tile_sum = (int32_t *)(w + L.tile_sum);
     h->xb = (double *)(w + L.xb);
+    h->vs = (double *)(w + L.vs);
+    h->vs_old = (double *)(w + L.vs_old);
+    h->fs = (double *)(w + L.fs);
+    h->ms = (double *)(w + L.ms);
     h->samp = (double4 *)(w + L.samp);
     h->part = (double2 *)(w + L.part);
     h->rho = (double2 *)(w + L.rho);
@@ -504,6 +535,7 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     }
     if (e == hipSuccess) e = hipMemsetAsync(h->flag, 0, sizeof(int32_t) * 4, h->st);
     if (e == hipSuccess) e = hipMemsetAsync(h->count, 0, L.cell_start - L.count, h->st);
+    if (e == hipSuccess) e = launch_iota(h->order, (int)p->N, h->st);   // a cell order before the first build
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (e != hipSuccess) {
         delete h;
@@ -555,7 +587,9 @@ extern "C" int rbsog_get_info(const rbsog_handle *h, rbsog_info *out)
 extern "C" int rbsog_build_cells(rbsog_handle *h, const double *x_dev, int32_t *cell_start_dev, int32_t *order_dev)
 {
     if (!h || !x_dev) return fail(RBSOG_EINVAL, "null handle or x");
-    CellArgs a = cell_args(h, x_dev, h->g, nullptr, nullptr);
+    PermArgs in = perm_args(h, (double *)x_dev, nullptr, nullptr);   // state_in reads x only
+    HIPCHECK(timed(h, kKickDrift, [&] { return launch_state_in(in, h->st); }));
+    CellArgs a = cell_args(h, h->g, nullptr, false);
     HIPCHECK(timed(h, kCells, [&] { return launch_cell_build(a, h->st); }));
     h->lists_valid = false;  // the workspace now holds the coarse list
     if (cell_start_dev)
@@ -600,12 +634,14 @@ extern "C" int rbsog_compute_forces(rbsog_handle *h, uint64_t step, const double
                                     double *f_near_dev, double *energy_dev)
 {
     if (!h || !x_dev || !f_dev) return fail(RBSOG_EINVAL, "null handle, x or f");
-    int rc = prepare(h, x_dev, nullptr);
+    PermArgs in = perm_args(h, (double *)x_dev, nullptr, nullptr);   // state_in reads x only
+    HIPCHECK(timed(h, kKickDrift, [&] { return launch_state_in(in, h->st); }));
+    int rc = prepare(h, nullptr, false);
     if (rc) return rc;
     const double4 *samp = nullptr;
     rc = modes(h, step, 1, &samp);
     if (rc) return rc;
-    return evaluate(h, samp, f_dev, f_near_dev, nullptr, 0.0, energy_dev);
+    return evaluate(h, samp, f_dev, f_near_dev, false, 0.0, energy_dev);
 }
 
 extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double *f_dev, uint64_t step0, int nsteps,
@@ -614,6 +650,11 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
     if (!h || !x_dev || !v_dev || !f_dev) return fail(RBSOG_EINVAL, "null handle, x, v or f");
     if (nsteps < 0) return fail(RBSOG_EINVAL, "nsteps must be >= 0");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RBSOG_EINVAL, "dt must be positive and finite");
+    if (nsteps == 0) return RBSOG_OK;
+    // the state moves into cell order (the order of the last build) for the
+    // steps and back into the caller's order at the end
+    PermArgs io = perm_args(h, x_dev, v_dev, f_dev);
+    HIPCHECK(timed(h, kKickDrift, [&] { return launch_state_in(io, h->st); }));
     for (int n = 0; n < nsteps; ++n) {
         int32_t *gate = h->gate + h->phase, *gate_next = h->gate + (1 - h->phase);
         // force a rebuild when the workspace holds no lists of the fine grid
@@ -623,32 +664,28 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         k.L = h->p.L;
         k.inv_L = 1.0 / h->p.L;
         k.dt = dt;
-        k.x = x_dev;
-        k.v = v_dev;
-        k.f = f_dev;
-        k.m = h->m;
+        k.xs = h->xs;
+        k.vs = h->vs;
+        k.fs = h->fs;
+        k.ms = h->ms;
         k.xb = h->xb;
         k.half_skin2 = 0.25 * h->d.skin * h->d.skin;
         k.gate = gate;
         k.gate_next = gate_next;
         k.flag = h->flag;
-        if (h->lists_valid) {   // pos and xs hold the fine grid's order
-            k.xs = h->xs;
-            k.pos = h->pos;
-            k.q = h->q;
-        }
         HIPCHECK(timed(h, kKickDrift, [&] { return launch_kick_drift(k, h->st); }));
         h->phase = 1 - h->phase;
-        int rc = prepare(h, x_dev, gate);
+        int rc = prepare(h, gate, true);
         if (rc) return rc;
         const double4 *samp = nullptr;
         uint64_t step = step0 + (uint64_t)n + 1;
         rc = modes(h, step, nsteps - n, &samp);
         if (rc) return rc;
         double *e = energy_hist_dev ? energy_hist_dev + 6 * (size_t)n : nullptr;
-        rc = evaluate(h, samp, f_dev, nullptr, v_dev, dt, e);
+        rc = evaluate(h, samp, nullptr, nullptr, true, dt, e);
         if (rc) return rc;
     }
+    HIPCHECK(timed(h, kKickDrift, [&] { return launch_state_out(io, h->st); }));
     return RBSOG_OK;
 }
 
@@ -676,7 +713,7 @@ extern "C" int rbsog_timing_enable(rbsog_handle *h, int enable)
     }
     h->timing = enable != 0;
     for (int k = 0; k < RBSOG_NUM_KERNEL_CLASSES; ++k) {
-        h->ms[k] = 0.0;
+        h->timing_ms[k] = 0.0;
         h->launches[k] = 0;
     }
     return RBSOG_OK;
@@ -687,9 +724,9 @@ extern "C" int rbsog_timing_read(rbsog_handle *h, rbsog_timing *out)
     if (!h || !out) return fail(RBSOG_EINVAL, "null handle or out");
     HIPCHECK(harvest(h));
     for (int k = 0; k < RBSOG_NUM_KERNEL_CLASSES; ++k) {
-        out->ms[k] = h->ms[k];
+        out->ms[k] = h->timing_ms[k];
         out->launches[k] = h->launches[k];
-        h->ms[k] = 0.0;
+        h->timing_ms[k] = 0.0;
         h->launches[k] = 0;
     }
     return RBSOG_OK;

@@ -267,20 +267,17 @@ int write_tables(rbsog_ens *s, int r, double dt)
     k.L = h->p.L;
     k.inv_L = 1.0 / h->p.L;
     k.dt = dt;
-    k.x = R.x;
-    k.v = R.v;
-    k.f = R.f;
-    k.m = R.m;
+    k.xs = h->xs;
+    k.vs = h->vs;
+    k.fs = h->fs;
+    k.ms = h->ms;
     k.xb = h->xb;
     k.half_skin2 = 0.25 * h->d.skin * h->d.skin;
     k.gate = h->gate;
     k.gate_next = nullptr;
     k.flag = h->flag;
-    k.xs = h->xs;
-    k.pos = h->pos;
-    k.q = R.q;
     if ((e = put(s->t_kick, r, k, s->st)) != hipSuccess) return ens_fail_hip(e, "kick table");
-    CellArgs c = cell_args(h, R.x, h->gf, h->gate, h->xb);
+    CellArgs c = cell_args(h, h->gf, h->gate, true);
     if ((e = put(s->t_cell, r, c, s->st)) != hipSuccess) return ens_fail_hip(e, "cell table");
     NearArgs nl = near_args(h, h->gate, false);
     if ((e = put(s->t_nlist, r, nl, s->st)) != hipSuccess) return ens_fail_hip(e, "list table");
@@ -291,7 +288,7 @@ int write_tables(rbsog_ens *s, int r, double dt)
     if ((e = put(s->t_rho, r, ra, s->st)) != hipSuccess) return ens_fail_hip(e, "rho table");
     NearArgs na = near_args(h, nullptr, true);
     if ((e = put(s->t_near, r, na, s->st)) != hipSuccess) return ens_fail_hip(e, "near table");
-    FarArgs fa = far_args(h, h->samp, R.f, nullptr, R.v, dt);
+    FarArgs fa = far_args(h, h->samp, nullptr, nullptr, true, dt);
     fa.gate_clear = h->gate;
     if ((e = put(s->t_far, r, fa, s->st)) != hipSuccess) return ens_fail_hip(e, "far table");
     // energies of step E - e_adm go to row E - e_adm
@@ -459,8 +456,14 @@ extern "C" int rbsog_ens_admit(rbsog_ens *s, const rbsog_params *p, const rbsog_
         drop_replica(s, slot);
         return rc;
     }
-    // the force of the initial state, evaluation index 0
+    // the force of the initial state, evaluation index 0, then the state in
+    // cell order, where the steps keep it until retirement
     rc = rbsog_compute_forces(R.h, 0, R.x, R.f, nullptr, nullptr);
+    if (rc == RBSOG_OK) {
+        PermArgs in = perm_args(R.h, R.x, R.v, R.f);
+        hipError_t le = launch_state_in(in, s->st);
+        if (le != hipSuccess) rc = ens_fail_hip(le, "moving the replica into cell order");
+    }
     if (rc) {
         drop_replica(s, slot);
         return rc;
@@ -587,8 +590,10 @@ extern "C" int rbsog_ens_retire(rbsog_ens *s, int slot, double *x_host, double *
     Replica &R = s->rep[slot];
     if (R.active) return fail(RBSOG_EINVAL, "slot %d has steps left", slot);
     const size_t N = (size_t)R.N;
-    hipError_t e = hipSuccess;
-    if (x_host) e = hipMemcpyAsync(x_host, R.x, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s->st);
+    // the final state back into the caller's order
+    PermArgs out = perm_args(R.h, R.x, R.v, nullptr);
+    hipError_t e = launch_state_out(out, s->st);
+    if (e == hipSuccess && x_host) e = hipMemcpyAsync(x_host, R.x, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s->st);
     if (e == hipSuccess && v_host)
         e = hipMemcpyAsync(v_host, R.v, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s->st);
     if (e == hipSuccess && energy_hist_host)

@@ -1,12 +1,14 @@
 // gfx950 kernels of librbsog: the cell list (a counting sort with a stable
-// rank) and the first velocity-Verlet half step.
+// rank), the first velocity-Verlet half step, and the moves between the
+// caller's particle order and cell order.
 //
-// Data layout in HBM: the caller's particle arrays stay FP64 SoA in the
-// caller's order.  A build sorts the particles by cell into `order` (and its
-// inverse `pos`) and writes a cell-ordered copy xs[N] of (x, y, z, q) as
-// double4 (32-byte rows) that the pair and far-field kernels stream; between
-// builds the same order is reused and the drift writes the new positions
-// straight into their rows of xs.
+// Data layout in HBM: the caller's particle arrays are FP64 SoA in the
+// caller's order; the library keeps the state it steps in cell order (xs[N]
+// = (x, y, z, q) as double4, 32-byte rows, velocities, forces and masses as
+// SoA), with order[p] the caller index of cell position p.  Every kernel of a
+// step streams these arrays contiguously; the caller's arrays are read once
+// when a call starts and written once when it ends.  A build sorts the rows
+// by (cell, caller index) and moves them into the new order.
 //
 // Builds can be gated: every build kernel takes a device flag and returns at
 // once when it is zero, so the decision to rebuild (some particle moved more
@@ -31,14 +33,21 @@ __device__ inline bool gate_open(const int32_t *gate) { return gate == nullptr |
 __device__ inline void cell_ids_body(const CellArgs &a, int b)
 {
     if (!gate_open(a.gate)) return;
-    int i = b * kBlock + threadIdx.x;
-    if (i >= a.N) return;
+    int p = b * kBlock + threadIdx.x;
+    if (p >= a.N) return;
+    const double4 r = a.xs[p];
+    // snapshot of the row: the rank pass reads the old order from here while
+    // it writes the new one in place
+    a.xs_old[p] = r;
+    a.order_old[p] = a.order[p];
+    if (a.vs)
+        for (int d = 0; d < 3; ++d) a.vs_old[d * a.N + p] = a.vs[d * a.N + p];
     int nc = a.g.nc;
-    int cx = cell_coord(a.x[i], a.g.inv_cell, nc);
-    int cy = cell_coord(a.x[a.N + i], a.g.inv_cell, nc);
-    int cz = cell_coord(a.x[2 * a.N + i], a.g.inv_cell, nc);
+    int cx = cell_coord(r.x, a.g.inv_cell, nc);
+    int cy = cell_coord(r.y, a.g.inv_cell, nc);
+    int cz = cell_coord(r.z, a.g.inv_cell, nc);
     int id = (cz * nc + cy) * nc + cx;
-    a.cell_id[i] = id;
+    a.cell_id[p] = id;
     atomicAdd(&a.count[id], 1);
 }
 
@@ -125,40 +134,42 @@ __device__ inline void scan_apply_body(const CellArgs &a, int b)
     if (b == 0 && threadIdx.x == 0) a.cell_start[a.g.ncell] = a.N;
 }
 
-// Unordered placement into each cell's segment.
+// Unordered placement of the caller indices into each cell's segment.
 __device__ inline void scatter_body(const CellArgs &a, int b)
 {
     if (!gate_open(a.gate)) return;
-    int i = b * kBlock + threadIdx.x;
-    if (i >= a.N) return;
-    int c = a.cell_id[i];
+    int p = b * kBlock + threadIdx.x;
+    if (p >= a.N) return;
+    int c = a.cell_id[p];
     int slot = atomicAdd(&a.fill[c], 1);
-    a.tmp[a.cell_start[c] + slot] = i;
+    a.tmp[a.cell_start[c] + slot] = a.order_old[p];
 }
 
 // Stable position: a particle's rank within its cell is the number of cell
-// members with a smaller index, so ties keep ascending particle index whatever
-// order the scatter produced.  Gathers (x, y, z, q) into cell order and, when
-// asked, records the positions of the build.
+// members with a smaller caller index, so the new order is that of (cell,
+// caller index) whatever order the scatter produced and whatever the old cell
+// order was.  Moves the row, its velocity and mass, and records the positions
+// of the build.
 __device__ inline void rank_body(const CellArgs &a, int b)
 {
     if (!gate_open(a.gate)) return;
-    int i = b * kBlock + threadIdx.x;
-    if (i >= a.N) return;
-    int c = a.cell_id[i];
+    int p = b * kBlock + threadIdx.x;
+    if (p >= a.N) return;
+    int c = a.cell_id[p];
+    const int key = a.order_old[p];
     int cb = a.cell_start[c], ce = a.cell_start[c + 1];
     int r = 0;
-    for (int k = cb; k < ce; ++k) r += (a.tmp[k] < i);
-    int p = cb + r;
-    double x = a.x[i], y = a.x[a.N + i], z = a.x[2 * a.N + i];
-    a.order[p] = i;
-    a.pos[i] = p;
-    a.xs[p] = make_double4(x, y, z, a.q[i]);
-    if (a.xb) {
-        a.xb[i] = x;
-        a.xb[a.N + i] = y;
-        a.xb[2 * a.N + i] = z;
-    }
+    for (int k = cb; k < ce; ++k) r += (a.tmp[k] < key);
+    const int pn = cb + r;
+    const double4 row = a.xs_old[p];
+    a.xs[pn] = row;
+    a.order[pn] = key;
+    a.ms[pn] = a.m[key];
+    a.xb[pn] = row.x;
+    a.xb[a.N + pn] = row.y;
+    a.xb[2 * a.N + pn] = row.z;
+    if (a.vs)
+        for (int d = 0; d < 3; ++d) a.vs[d * a.N + pn] = a.vs_old[d * a.N + p];
 }
 
 RBSOG_KERNELS(cell_ids, CellArgs, kBlock)
@@ -169,8 +180,8 @@ RBSOG_KERNELS(rank, CellArgs, kBlock)
 
 static bool cell_args_ok(const CellArgs &a)
 {
-    return a.N >= 1 && a.g.nc >= 1 && a.x && a.q && a.cell_id && a.count && a.cell_start && a.fill && a.tmp &&
-           a.order && a.pos && a.xs && a.tile_sum && a.ticket;
+    return a.N >= 1 && a.g.nc >= 1 && a.xs && a.order && a.xs_old && a.order_old && (!a.vs || a.vs_old) && a.m &&
+           a.ms && a.xb && a.cell_id && a.count && a.cell_start && a.fill && a.tmp && a.tile_sum && a.ticket;
 }
 
 hipError_t launch_cell_build(const CellArgs &a, hipStream_t st)
@@ -199,39 +210,40 @@ hipError_t launch_cell_build_batch(const CellArgs *tab, const EnsItem *per256, i
 }
 
 // ---------------------------------------------------------------------------
-// first half-kick + drift + wrap; writes the new position into the particle's
-// row of the cell-ordered copy, raises the rebuild gate of this step when a
-// particle has moved more than half the skin since the last build, and clears
-// the gate of the next step (when the caller alternates two gates)
+// first half-kick + drift + wrap in cell order; raises the rebuild gate of
+// this step when a particle has moved more than half the skin since the last
+// build, and clears the gate of the next step (when the caller alternates two
+// gates)
 // ---------------------------------------------------------------------------
 
 __device__ inline void kick_drift_body(const KickDriftArgs &a, int b)
 {
-    int i = b * kBlock + threadIdx.x;
-    if (i == 0 && a.gate_next) *a.gate_next = 0;
-    if (i >= a.N) return;
+    int p = b * kBlock + threadIdx.x;
+    if (p == 0 && a.gate_next) *a.gate_next = 0;
+    if (p >= a.N) return;
     const double L = a.L;
-    double hm = (0.5 * a.dt) / a.m[i];
+    const double hm = (0.5 * a.dt) / a.ms[p];
+    const double4 r = a.xs[p];
+    const double xo[3] = {r.x, r.y, r.z};
     double d2 = 0.0;
     double xn[3];
     bool bad = false;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        double vv = a.v[d * a.N + i] + hm * a.f[d * a.N + i];
+        double vv = a.vs[d * a.N + p] + hm * a.fs[d * a.N + p];
         double dx = a.dt * vv;
         bad |= !(fabs(dx) < L);
-        double xx = a.x[d * a.N + i] + dx;
+        double xx = xo[d] + dx;
         if (xx >= L) xx -= L;
         if (xx < 0.0) xx += L;
         if (xx >= L) xx = 0.0;
-        a.v[d * a.N + i] = vv;
-        a.x[d * a.N + i] = xx;
+        a.vs[d * a.N + p] = vv;
         xn[d] = xx;
-        double s = xx - a.xb[d * a.N + i];
+        double s = xx - a.xb[d * a.N + p];
         s = fma(-L, rint(s * a.inv_L), s);
         d2 = fma(s, s, d2);
     }
-    if (a.xs) a.xs[a.pos[i]] = make_double4(xn[0], xn[1], xn[2], a.q[i]);
+    a.xs[p] = make_double4(xn[0], xn[1], xn[2], r.w);
     if (bad) atomicOr(a.flag, 1);
     if (!(d2 <= a.half_skin2)) atomicOr(a.gate, 1);
 }
@@ -240,8 +252,7 @@ RBSOG_KERNELS(kick_drift, KickDriftArgs, kBlock)
 
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t st)
 {
-    if (a.N < 1 || !a.x || !a.v || !a.f || !a.m || !a.xb || !a.gate || !a.flag || (a.xs && (!a.pos || !a.q)))
-        return hipErrorInvalidValue;
+    if (a.N < 1 || !a.xs || !a.vs || !a.fs || !a.ms || !a.xb || !a.gate || !a.flag) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_kick_drift, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
@@ -250,6 +261,69 @@ hipError_t launch_kick_drift_batch(const KickDriftArgs *tab, const EnsItem *per2
 {
     if (!tab || !per256 || n < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_kick_drift_batch, dim3(n), dim3(kBlock), 0, st, tab, per256);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// caller order <-> cell order
+// ---------------------------------------------------------------------------
+
+__device__ inline void state_in_body(const PermArgs &a, int b)
+{
+    int p = b * kBlock + threadIdx.x;
+    if (p >= a.N) return;
+    const int i = a.order[p];
+    a.xs[p] = make_double4(a.x[i], a.x[a.N + i], a.x[2 * a.N + i], a.q[i]);
+    a.ms[p] = a.m[i];
+    for (int d = 0; d < 3; ++d) {
+        if (a.v) a.vs[d * a.N + p] = a.v[d * a.N + i];
+        if (a.f) a.fs[d * a.N + p] = a.f[d * a.N + i];
+    }
+}
+
+__device__ inline void state_out_body(const PermArgs &a, int b)
+{
+    int p = b * kBlock + threadIdx.x;
+    if (p >= a.N) return;
+    const int i = a.order[p];
+    const double4 r = a.xs[p];
+    a.x[i] = r.x;
+    a.x[a.N + i] = r.y;
+    a.x[2 * a.N + i] = r.z;
+    for (int d = 0; d < 3; ++d) {
+        if (a.v) a.v[d * a.N + i] = a.vs[d * a.N + p];
+        if (a.f) a.f[d * a.N + i] = a.fs[d * a.N + p];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_state_in(PermArgs a) { state_in_body(a, (int)blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_state_out(PermArgs a) { state_out_body(a, (int)blockIdx.x); }
+
+hipError_t launch_state_in(const PermArgs &a, hipStream_t st)
+{
+    if (a.N < 1 || !a.order || !a.x || !a.q || !a.m || !a.xs || !a.ms || (a.v && !a.vs) || (a.f && !a.fs))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_state_in, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_out(const PermArgs &a, hipStream_t st)
+{
+    if (a.N < 1 || !a.order || !a.x || !a.xs || (a.v && !a.vs) || (a.f && !a.fs)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_state_out, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_iota(int32_t *order, int N)
+{
+    int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < N) order[p] = p;
+}
+
+hipError_t launch_iota(int32_t *order, int N, hipStream_t st)
+{
+    if (!order || N < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_iota, dim3((N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, order, N);
     return hipGetLastError();
 }
 

@@ -12,8 +12,8 @@ namespace rbsog {
 // g takes the samples l = g mod 4 of each LDS tile of 256 samples, so every
 // particle's sum is spread over 4 lanes (4x the waves of one lane per particle,
 // which the latency of the dependent FP64 chains needs).  The 4 partial sums are
-// added in a fixed order, then near + far is written in the caller's particle
-// order and the second half-kick applied.
+// added in a fixed order, then near + far is written (in cell order, and/or
+// in the caller's order) and the second half-kick applied in cell order.
 // ---------------------------------------------------------------------------
 
 constexpr int kFarGroups = 4;
@@ -114,23 +114,32 @@ __device__ inline void far_body(const FarArgs &a, int b)
             fnz += pl[2 * (size_t)a.N];
         }
         double fx = fnx + sc * bx, fy = fny + sc * by, fz = fnz + sc * bz;
-        int i = a.order[p];
-        a.f[i] = fx;
-        a.f[a.N + i] = fy;
-        a.f[2 * a.N + i] = fz;
-        if (a.f_near_out) {
-            a.f_near_out[i] = fnx;
-            a.f_near_out[a.N + i] = fny;
-            a.f_near_out[2 * a.N + i] = fnz;
+        if (a.fs) {
+            a.fs[p] = fx;
+            a.fs[a.N + p] = fy;
+            a.fs[2 * a.N + p] = fz;
+        }
+        if (a.f || a.f_near_out) {
+            int i = a.order[p];
+            if (a.f) {
+                a.f[i] = fx;
+                a.f[a.N + i] = fy;
+                a.f[2 * a.N + i] = fz;
+            }
+            if (a.f_near_out) {
+                a.f_near_out[i] = fnx;
+                a.f_near_out[a.N + i] = fny;
+                a.f_near_out[2 * a.N + i] = fnz;
+            }
         }
         if (!isfinite(fx + fy + fz)) atomicOr(a.flag, 1);
-        if (a.v) {
-            double mi = a.m[i];
+        if (a.vs) {
+            double mi = a.ms[p];
             double hm = a.half_dt / mi;
-            double vx = a.v[i] + hm * fx, vy = a.v[a.N + i] + hm * fy, vz = a.v[2 * a.N + i] + hm * fz;
-            a.v[i] = vx;
-            a.v[a.N + i] = vy;
-            a.v[2 * a.N + i] = vz;
+            double vx = a.vs[p] + hm * fx, vy = a.vs[a.N + p] + hm * fy, vz = a.vs[2 * a.N + p] + hm * fz;
+            a.vs[p] = vx;
+            a.vs[a.N + p] = vy;
+            a.vs[2 * a.N + p] = vz;
             ke = 0.5 * mi * (vx * vx + vy * vy + vz * vz);
         }
     }
@@ -169,8 +178,8 @@ hipError_t launch_far_batch(const FarArgs *tab, const EnsItem *items, int n, boo
 
 hipError_t launch_far(const FarArgs &a, hipStream_t st)
 {
-    if (a.N < 1 || a.P < 1 || !a.xs || !a.order || !a.samp || !a.gk || !a.fnear || !a.f || !a.flag ||
-        (a.v && (!a.m || !a.kepart)) || (!a.mixed && !a.tab))
+    if (a.N < 1 || a.P < 1 || !a.xs || !a.order || !a.samp || !a.gk || !a.fnear || (!a.f && !a.fs) || !a.flag ||
+        (a.vs && (!a.ms || !a.kepart)) || (!a.mixed && !a.tab))
         return hipErrorInvalidValue;
     dim3 grid(far_blocks(a.N));
     if (a.mixed) hipLaunchKernelGGL(k_far<true>, grid, dim3(kFarThreads), 0, st, a);

@@ -58,49 +58,72 @@ struct CellGeom {
 };
 
 // --- cells -----------------------------------------------------------------
+// The particle state lives in cell order: xs[p] = (x, y, z, q) of the particle
+// in cell position p, order[p] its index in the caller's arrays.  A build sorts
+// the current rows by (cell, caller index) and moves each row (and, when
+// given, its velocity) to its new position; the id pass snapshots the rows so
+// that the rank pass can write the new order in place.
 struct CellArgs {
     int N;
     CellGeom g;
-    const double *x;       // SoA [3][N], original order
-    const double *q;       // [N]
-    int32_t *cell_id;      // [N]
+    double4 *xs;           // [N] (x, y, z, q) in cell order, rewritten in the new order
+    int32_t *order;        // [N] cell order -> caller index, rewritten
+    double *vs;            // null, or SoA [3][N] cell-order velocities carried into the new order
+    double4 *xs_old;       // [N] snapshot of xs (id pass -> rank pass)
+    int32_t *order_old;    // [N] snapshot of order
+    double *vs_old;        // SoA [3][N] snapshot of vs (when vs)
+    const double *m;       // [N] caller-order masses
+    double *ms;            // [N] masses in the new cell order
+    double *xb;            // SoA [3][N] positions at the build, new cell order
+    int32_t *cell_id;      // [N] by current cell position
     int32_t *count;        // [ncell]
     int32_t *cell_start;   // [ncell + 1]
     int32_t *fill;         // [ncell]
-    int32_t *tmp;          // [N] unordered members per cell
-    int32_t *order;        // [N] cell order -> original index
-    int32_t *pos;          // [N] original index -> cell order
-    double4 *xs;           // [N] (x, y, z, q) in cell order
+    int32_t *tmp;          // [N] caller indices of each cell's members, unordered
     int32_t *tile_sum;     // [scan_tiles(ncell)] scan workspace
     int32_t *ticket;       // scan's finished-tile counter: zero between builds
     const int32_t *gate;   // null: always build; else build only when *gate != 0
-    double *xb;            // null, or SoA [3][N] positions recorded at the build
 };
 __host__ __device__ inline int scan_tiles(int ncell) { return (ncell + kScanTile - 1) / kScanTile; }
-// ids + counts, scan (which leaves the counts zero again), scatter, stable rank
-// + gather; `count` must be zero on entry
+// ids + counts + snapshot, scan (which leaves the counts zero again), scatter,
+// stable rank + move; `count` must be zero on entry
 hipError_t launch_cell_build(const CellArgs &a, hipStream_t st);
 // the same for every replica of a work list: per256 has ceil(N/256) items per
 // replica, pertile scan_tiles(ncell)
 hipError_t launch_cell_build_batch(const CellArgs *tab, const EnsItem *per256, int n256, const EnsItem *pertile,
                                    int ntile, hipStream_t st);
 hipError_t launch_set_int(int32_t *p, int32_t v, hipStream_t st);
+// order[p] = p (a valid cell order before the first build)
+hipError_t launch_iota(int32_t *order, int N, hipStream_t st);
+
+// Caller arrays <-> cell order through order[]: state_in writes xs (x and q),
+// ms, and vs / fs when given; state_out writes x, and v / f when given.
+struct PermArgs {
+    int N;
+    const int32_t *order;
+    double *x, *v, *f;     // SoA [3][N], caller order (v, f may be null; state_in only reads them)
+    const double *q, *m;   // [N], caller order (state_in)
+    double4 *xs;           // [N] cell order
+    double *vs, *fs;       // SoA [3][N], cell order
+    double *ms;            // [N], cell order
+};
+hipError_t launch_state_in(const PermArgs &a, hipStream_t st);
+hipError_t launch_state_out(const PermArgs &a, hipStream_t st);
 
 // --- integration ------------------------------------------------------------
+// First half-kick and drift in cell order.
 struct KickDriftArgs {
     int N;
     double L, inv_L, dt;
-    double *x, *v;         // SoA [3][N], original order, updated in place
-    const double *f;       // SoA [3][N]
-    const double *m;       // [N]
+    double4 *xs;           // [N] (x, y, z, q), positions updated in place
+    double *vs;            // SoA [3][N], updated in place
+    const double *fs;      // SoA [3][N]
+    const double *ms;      // [N]
     const double *xb;      // SoA [3][N] positions at the last list build
     double half_skin2;     // (skin / 2)^2
     int32_t *gate;         // raised when a particle moved more than skin / 2 since the build
     int32_t *gate_next;    // null, or the next step's gate, cleared
     int *flag;             // set to 1 on a step of a box length or more
-    double4 *xs;           // null, or the cell-ordered copy to write the new positions into
-    const int32_t *pos;    // [N] original index -> cell order (when xs)
-    const double *q;       // [N] (when xs)
 };
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t st);
 hipError_t launch_kick_drift_batch(const KickDriftArgs *tab, const EnsItem *per256, int n, hipStream_t st);
@@ -207,12 +230,13 @@ struct FarArgs {
     const double4 *samp;       // [P] (nx, ny, nz, coef)
     const double2 *gk;         // [P] coef * rho
     const double *fnear;       // [5][3][N] partial near forces of the five lanes, cell order
-    double *f;                 // SoA [3][N] original order
-    double *f_near_out;        // SoA [3][N] original order, or null
-    double *v;                 // null, or velocities to kick (original order)
-    const double *m;
+    double *f;                 // null, or SoA [3][N] forces in caller order (through order)
+    double *f_near_out;        // null, or SoA [3][N] near forces in caller order
+    double *fs;                // null, or SoA [3][N] forces in cell order
+    double *vs;                // null, or SoA [3][N] cell-order velocities to kick
+    const double *ms;          // [N] cell-order masses (when vs)
     double half_dt;
-    double *kepart;            // [far_blocks(N)] kinetic-energy partials (when v)
+    double *kepart;            // [far_blocks(N)] kinetic-energy partials (when vs)
     int *flag;                 // set to 1 on a non-finite force
     int mixed;
     const double2 *tab;        // [kPhaseTab] (sin, cos)(2 pi j / kPhaseTab) (FP64 path)

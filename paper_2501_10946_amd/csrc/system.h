@@ -26,7 +26,7 @@ constexpr size_t kAlign = 256;
 // Offsets of every buffer inside the workspace.
 struct Layout {
     size_t lattice, cdf, coef, first, size;
-    size_t cell_id, count, cell_start, fill, tmp, order, pos, xs, tile_sum, xb;
+    size_t cell_id, count, cell_start, fill, tmp, order, order_old, xs, xs_old, tile_sum, xb, vs, vs_old, fs, ms;
     size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_stage, nbr_cnt, tab;
     size_t total;
 };
@@ -74,9 +74,10 @@ struct rbsog_handle {
     char *ws;
     SogDev sd;
     // views into the workspace
-    int32_t *lattice, *first, *size, *cell_id, *count, *cell_start, *fill, *tmp, *order, *pos, *flag, *tile_sum;
+    int32_t *lattice, *first, *size, *cell_id, *count, *cell_start, *fill, *tmp, *order, *order_old, *flag, *tile_sum;
     double *cdf, *coef, *eF, *fnear, *epart, *kepart, *energy, *xb;
-    double4 *xs, *samp;
+    double *vs, *vs_old, *fs, *ms;   // the stepped state in cell order (with xs)
+    double4 *xs, *xs_old, *samp;
     double2 *part, *rho, *gk, *tab;
     int32_t *nbr, *nbr_stage, *nbr_cnt;
     int32_t *gate;       // device, two words: rebuild the cell order and lists in this step
@@ -91,7 +92,7 @@ struct rbsog_handle {
     std::vector<hipEvent_t> events;
     std::vector<std::pair<int, int>> records;  // (kernel class, index of the start event)
     int used = 0;
-    double ms[RBSOG_NUM_KERNEL_CLASSES] = {};
+    double timing_ms[RBSOG_NUM_KERNEL_CLASSES] = {};
     int64_t launches[RBSOG_NUM_KERNEL_CLASSES] = {};
 };
 
@@ -121,17 +122,23 @@ hipError_t timed(rbsog_handle *h, int cls, F &&launch)
     return hipSuccess;
 }
 
-CellArgs cell_args(rbsog_handle *h, const double *x, const CellGeom &g, const int32_t *gate, double *xb);
+// a build of grid g; carry_v: velocities are live and move with their rows
+CellArgs cell_args(rbsog_handle *h, const CellGeom &g, const int32_t *gate, bool carry_v);
+// caller arrays -> cell order (v, f may be null) and back
+PermArgs perm_args(rbsog_handle *h, double *x, double *v, double *f);
 NearArgs near_args(rbsog_handle *h, const int32_t *gate, bool energy);
 SampleArgs sample_args(rbsog_handle *h, uint64_t step, int nstep);
 RhoArgs rho_args(rbsog_handle *h, const double4 *samp);
-FarArgs far_args(rbsog_handle *h, const double4 *samp, double *f, double *f_near, double *v, double dt);
+// f, f_near: caller-order outputs (may be null); kick: write the cell-order
+// forces and apply the second half-kick to the cell-order velocities
+FarArgs far_args(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bool kick, double dt);
 EnergyArgs energy_args(rbsog_handle *h, double *out, bool kick);
-int prepare(rbsog_handle *h, const double *x, const int32_t *gate);
+// cell order + lists of the fine grid from the rows in xs (gated or not)
+int prepare(rbsog_handle *h, const int32_t *gate, bool carry_v);
 // rbsog_create; with lattice_dev (the packed lattice up to at least the
 // system's m_max, owned by the caller) the workspace holds no lattice copy
 int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev, const double *m_dev, void *ws_dev,
                   size_t ws_bytes, hipStream_t stream, const int32_t *lattice_dev, rbsog_handle **out);
-int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, double *v, double dt, double *energy);
+int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bool kick, double dt, double *energy);
 
 }  // namespace rbsog
