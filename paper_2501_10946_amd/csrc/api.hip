@@ -302,7 +302,10 @@ RhoArgs rho_args(rbsog_handle *h, const double4 *samp)
 int prepare(rbsog_handle *h, const int32_t *gate, bool carry_v)
 {
     CellArgs ca = cell_args(h, h->gf, gate, carry_v);
-    HIPCHECK(timed(h, kCells, [&] { return launch_cell_build(ca, h->st); }));
+    if (h->coop_grid > 0)
+        HIPCHECK(timed(h, kCells, [&] { return launch_cell_build_coop(ca, h->coop_grid, h->st); }));
+    else
+        HIPCHECK(timed(h, kCells, [&] { return launch_cell_build(ca, h->st); }));
     NearArgs na = near_args(h, gate, false);
     HIPCHECK(timed(h, kNlist, [&] { return launch_nlist(na, h->st); }));
     h->lists_valid = true;
@@ -372,18 +375,31 @@ EnergyArgs energy_args(rbsog_handle *h, double *out, bool kick)
 
 // Structure factors, near field, far field (+ optional kick) and the energy
 // sums of one evaluation whose cell order, lists and modes are prepared.
-int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bool kick, double dt, double *energy)
+int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bool kick, double dt, double *energy,
+             int32_t *gate_raise, int32_t *gate_clear)
 {
     RhoArgs ra = rho_args(h, samp);
+    NearArgs na = near_args(h, nullptr, energy != nullptr);
     if (h->d.full_k) {
         HIPCHECK(timed(h, kRhoPartial, [&] { return launch_rho_full(ra, h->st); }));
     } else {
         HIPCHECK(timed(h, kRhoPartial, [&] { return launch_rho_partial(ra, h->st); }));
-        HIPCHECK(timed(h, kRhoReduce, [&] { return launch_rho_reduce(ra, h->st); }));
+        // the reduction runs in the near kernel's first workgroups
+        na.red = ra;
+        na.nred = (rho_reduce_blocks(ra.P) + 7) / 8 * 8;
     }
-    NearArgs na = near_args(h, nullptr, energy != nullptr);
     HIPCHECK(timed(h, kNear, [&] { return launch_near(na, h->st); }));
     FarArgs fa = far_args(h, samp, f, f_near, kick, dt);
+    fa.gate_clear = gate_clear;
+    if (kick && gate_raise) {
+        fa.drift = 1;
+        fa.dt = dt;
+        fa.L = h->p.L;
+        fa.half_skin2 = 0.25 * h->d.skin * h->d.skin;
+        fa.xb = h->xb;
+        fa.xs_next = h->xs;
+        fa.gate_raise = gate_raise;
+    }
     HIPCHECK(timed(h, kFar, [&] { return launch_far(fa, h->st); }));
     if (energy) {
         EnergyArgs ea = energy_args(h, energy, kick);
@@ -536,6 +552,11 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     if (e == hipSuccess) e = hipMemsetAsync(h->flag, 0, sizeof(int32_t) * 4, h->st);
     if (e == hipSuccess) e = hipMemsetAsync(h->count, 0, L.cell_start - L.count, h->st);
     if (e == hipSuccess) e = launch_iota(h->order, (int)p->N, h->st);   // a cell order before the first build
+    // the cell build as one cooperative launch where the device allows it
+    // (RBSOG_COOP_BUILD=0: five launches)
+    h->coop_grid = cell_build_coop_grid((int)p->N, std::max(h->g.ncell, h->gf.ncell));
+    if (const char *cb = std::getenv("RBSOG_COOP_BUILD"))
+        if (std::atoi(cb) == 0) h->coop_grid = 0;
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (e != hipSuccess) {
         delete h;
@@ -590,7 +611,10 @@ extern "C" int rbsog_build_cells(rbsog_handle *h, const double *x_dev, int32_t *
     PermArgs in = perm_args(h, (double *)x_dev, nullptr, nullptr);   // state_in reads x only
     HIPCHECK(timed(h, kKickDrift, [&] { return launch_state_in(in, h->st); }));
     CellArgs a = cell_args(h, h->g, nullptr, false);
-    HIPCHECK(timed(h, kCells, [&] { return launch_cell_build(a, h->st); }));
+    if (h->coop_grid > 0)
+        HIPCHECK(timed(h, kCells, [&] { return launch_cell_build_coop(a, h->coop_grid, h->st); }));
+    else
+        HIPCHECK(timed(h, kCells, [&] { return launch_cell_build(a, h->st); }));
     h->lists_valid = false;  // the workspace now holds the coarse list
     if (cell_start_dev)
         HIPCHECK(hipMemcpyAsync(cell_start_dev, h->cell_start, sizeof(int32_t) * ((size_t)h->g.ncell + 1),
@@ -655,7 +679,11 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
     // steps and back into the caller's order at the end
     PermArgs io = perm_args(h, x_dev, v_dev, f_dev);
     HIPCHECK(timed(h, kKickDrift, [&] { return launch_state_in(io, h->st); }));
-    for (int n = 0; n < nsteps; ++n) {
+    // The first step's half-kick and drift run as their own kernel; those of
+    // the later steps are fused into the far kernel of the step before.  Steps
+    // alternate between two rebuild gates: the drift into step n raises gate n,
+    // step n's builds read it, and step n's far kernel clears it.
+    {
         int32_t *gate = h->gate + h->phase, *gate_next = h->gate + (1 - h->phase);
         // force a rebuild when the workspace holds no lists of the fine grid
         if (!h->lists_valid) HIPCHECK(launch_set_int(gate, 1, h->st));
@@ -674,7 +702,9 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         k.gate_next = gate_next;
         k.flag = h->flag;
         HIPCHECK(timed(h, kKickDrift, [&] { return launch_kick_drift(k, h->st); }));
-        h->phase = 1 - h->phase;
+    }
+    for (int n = 0; n < nsteps; ++n) {
+        int32_t *gate = h->gate + h->phase, *gate_next = h->gate + (1 - h->phase);
         int rc = prepare(h, gate, true);
         if (rc) return rc;
         const double4 *samp = nullptr;
@@ -682,8 +712,9 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         rc = modes(h, step, nsteps - n, &samp);
         if (rc) return rc;
         double *e = energy_hist_dev ? energy_hist_dev + 6 * (size_t)n : nullptr;
-        rc = evaluate(h, samp, nullptr, nullptr, true, dt, e);
+        rc = evaluate(h, samp, nullptr, nullptr, true, dt, e, n + 1 < nsteps ? gate_next : nullptr, gate);
         if (rc) return rc;
+        h->phase = 1 - h->phase;
     }
     HIPCHECK(timed(h, kKickDrift, [&] { return launch_state_out(io, h->st); }));
     return RBSOG_OK;

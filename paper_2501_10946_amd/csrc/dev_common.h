@@ -31,4 +31,92 @@ __device__ inline double block_sum_256(double v, double *red)
     return red[0];
 }
 
+// First half-kick and drift of one particle (cell position p): v += hm f,
+// x += dt v, wrapped into [0, L); returns the squared minimum-image distance
+// from the build position xb and sets *bad on a step of a box length or more.
+// The drift kernel and the far kernel's fused form both run this, so that
+// their trajectories agree bit for bit.
+__device__ inline double kick_drift_row(double x[3], double v[3], const double f[3], double hm, double dt, double L,
+                                        double inv_L, const double *xb, int N, int p, bool *bad)
+{
+    double d2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double vv = v[d] + hm * f[d];
+        double dx = dt * vv;
+        *bad |= !(fabs(dx) < L);
+        double xx = x[d] + dx;
+        if (xx >= L) xx -= L;
+        if (xx < 0.0) xx += L;
+        if (xx >= L) xx = 0.0;
+        v[d] = vv;
+        x[d] = xx;
+        double s = xx - xb[d * N + p];
+        s = fma(-L, rint(s * inv_L), s);
+        d2 = fma(s, s, d2);
+    }
+    return d2;
+}
+
+// Fixed-order sum of the chunk partials, one workgroup per kRedModes adjacent
+// samples so that each partial row is read as one contiguous segment.  Thread
+// t takes sample l = kRedModes b + (t mod kRedModes) and adds the partials of
+// groups c, c + 64, c + 128, ... (c = t / kRedModes, four loads in flight); the
+// 16 threads of a wave that share a sample are added by a fixed butterfly and
+// the four waves in order.
+__device__ inline void rho_reduce_body(const RhoArgs &a, int b)
+{
+    constexpr int kLanes = kBlock / kRedModes;   // group streams per sample
+    __shared__ double2 red[kBlock / 64][kRedModes];
+    const int t = threadIdx.x, m = t % kRedModes, c0 = t / kRedModes;
+    const int l = b * kRedModes + m;
+    const bool live = l < a.P;
+    const double2 *col = a.part + (live ? l : 0);
+    const size_t P = (size_t)a.P;
+    const int nch = live ? a.nchunk : 0;
+    double re = 0.0, im = 0.0;
+    int c = c0;
+    for (; c + 3 * kLanes < nch; c += 4 * kLanes) {
+        double2 v0 = col[(size_t)c * P], v1 = col[(size_t)(c + kLanes) * P];
+        double2 v2 = col[(size_t)(c + 2 * kLanes) * P], v3 = col[(size_t)(c + 3 * kLanes) * P];
+        re += v0.x;
+        im += v0.y;
+        re += v1.x;
+        im += v1.y;
+        re += v2.x;
+        im += v2.y;
+        re += v3.x;
+        im += v3.y;
+    }
+    for (; c < nch; c += kLanes) {
+        double2 v = col[(size_t)c * P];
+        re += v.x;
+        im += v.y;
+    }
+#pragma unroll
+    for (int off = 32; off >= kRedModes; off >>= 1) {
+        re += __shfl_xor(re, off);
+        im += __shfl_xor(im, off);
+    }
+    if ((t & 63) < kRedModes) red[t >> 6][m] = make_double2(re, im);
+    __syncthreads();
+    if (t < kRedModes && live) {
+        re = 0.0;
+        im = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            re += red[w][t].x;
+            im += red[w][t].y;
+        }
+        double cf = a.samp[l].w;
+        a.rho[l] = make_double2(re, im);
+        a.gk[l] = make_double2(cf * re, cf * im);
+        a.eF[l] = 0.5 * cf * (re * re + im * im);
+        if (a.rho_out) {
+            a.rho_out[2 * l] = re;
+            a.rho_out[2 * l + 1] = im;
+        }
+    }
+}
+
 }  // namespace rbsog

@@ -13,7 +13,10 @@
 // Builds can be gated: every build kernel takes a device flag and returns at
 // once when it is zero, so the decision to rebuild (some particle moved more
 // than half the list skin) is taken on the device with no host round-trip.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "dev_common.h"
 
@@ -197,6 +200,51 @@ hipError_t launch_cell_build(const CellArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
+// The five passes in one cooperative launch (every workgroup resident, a grid
+// barrier between passes): a closed gate costs one launch instead of five.
+// The gate is read once and is the same for every workgroup (nothing writes it
+// during the build), so either every workgroup returns at once or every one
+// reaches every barrier.
+__global__ __launch_bounds__(kBlock) void k_cell_build_coop(CellArgs a)
+{
+    if (!gate_open(a.gate)) return;
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    const int nb = (a.N + kBlock - 1) / kBlock, nt = scan_tiles(a.g.ncell);
+    const int g0 = (int)blockIdx.x, gs = (int)gridDim.x;
+    for (int b = g0; b < nb; b += gs) cell_ids_body(a, b);
+    grid.sync();
+    for (int b = g0; b < nt; b += gs) scan_tiles_body(a, b);
+    grid.sync();
+    for (int b = g0; b < nt; b += gs) scan_apply_body(a, b);
+    grid.sync();
+    for (int b = g0; b < nb; b += gs) scatter_body(a, b);
+    grid.sync();
+    for (int b = g0; b < nb; b += gs) rank_body(a, b);
+}
+
+int cell_build_coop_grid(int N, int ncell)
+{
+    int dev = 0, ncu = 0, coop = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cell_build_coop, kBlock, 0) != hipSuccess ||
+        per_cu < 1)
+        return 0;
+    // at most two workgroups per CU: the passes are short, more only adds barrier traffic
+    int need = std::max((N + kBlock - 1) / kBlock, scan_tiles(ncell));
+    return std::max(1, std::min(need, ncu * std::min(per_cu, 2)));
+}
+
+hipError_t launch_cell_build_coop(const CellArgs &a, int grid, hipStream_t st)
+{
+    if (!cell_args_ok(a) || grid < 1) return hipErrorInvalidValue;
+    CellArgs arg = a;
+    void *params[] = {&arg};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_cell_build_coop), dim3(grid), dim3(kBlock),
+                                      params, 0, st);
+}
+
 hipError_t launch_cell_build_batch(const CellArgs *tab, const EnsItem *per256, int n256, const EnsItem *pertile,
                                    int ntile, hipStream_t st)
 {
@@ -221,29 +269,15 @@ __device__ inline void kick_drift_body(const KickDriftArgs &a, int b)
     int p = b * kBlock + threadIdx.x;
     if (p == 0 && a.gate_next) *a.gate_next = 0;
     if (p >= a.N) return;
-    const double L = a.L;
     const double hm = (0.5 * a.dt) / a.ms[p];
     const double4 r = a.xs[p];
-    const double xo[3] = {r.x, r.y, r.z};
-    double d2 = 0.0;
-    double xn[3];
+    double x[3] = {r.x, r.y, r.z};
+    double v[3] = {a.vs[p], a.vs[a.N + p], a.vs[2 * a.N + p]};
+    const double f[3] = {a.fs[p], a.fs[a.N + p], a.fs[2 * a.N + p]};
     bool bad = false;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        double vv = a.vs[d * a.N + p] + hm * a.fs[d * a.N + p];
-        double dx = a.dt * vv;
-        bad |= !(fabs(dx) < L);
-        double xx = xo[d] + dx;
-        if (xx >= L) xx -= L;
-        if (xx < 0.0) xx += L;
-        if (xx >= L) xx = 0.0;
-        a.vs[d * a.N + p] = vv;
-        xn[d] = xx;
-        double s = xx - a.xb[d * a.N + p];
-        s = fma(-L, rint(s * a.inv_L), s);
-        d2 = fma(s, s, d2);
-    }
-    a.xs[p] = make_double4(xn[0], xn[1], xn[2], r.w);
+    double d2 = kick_drift_row(x, v, f, hm, a.dt, a.L, a.inv_L, a.xb, a.N, p, &bad);
+    for (int d = 0; d < 3; ++d) a.vs[d * a.N + p] = v[d];
+    a.xs[p] = make_double4(x[0], x[1], x[2], r.w);
     if (bad) atomicOr(a.flag, 1);
     if (!(d2 <= a.half_skin2)) atomicOr(a.gate, 1);
 }

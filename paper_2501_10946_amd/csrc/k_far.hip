@@ -13,7 +13,8 @@ namespace rbsog {
 // particle's sum is spread over 4 lanes (4x the waves of one lane per particle,
 // which the latency of the dependent FP64 chains needs).  The 4 partial sums are
 // added in a fixed order, then near + far is written (in cell order, and/or
-// in the caller's order) and the second half-kick applied in cell order.
+// in the caller's order) and the second half-kick applied in cell order; in a
+// run of steps the next step's first half-kick and drift follow at once.
 // ---------------------------------------------------------------------------
 
 constexpr int kFarGroups = 4;
@@ -39,7 +40,7 @@ __device__ inline double far_term(const FarArgs &a, const double2 *tab, const do
     }
 }
 
-template <bool MIXED>
+template <bool MIXED, bool DRIFT>
 __device__ inline void far_body(const FarArgs &a, int b)
 {
     __shared__ double4 sk[kFarTile];
@@ -137,10 +138,22 @@ __device__ inline void far_body(const FarArgs &a, int b)
             double mi = a.ms[p];
             double hm = a.half_dt / mi;
             double vx = a.vs[p] + hm * fx, vy = a.vs[a.N + p] + hm * fy, vz = a.vs[2 * a.N + p] + hm * fz;
+            ke = 0.5 * mi * (vx * vx + vy * vy + vz * vz);
+            if (DRIFT) {   // the next step's first half-kick and drift
+                double x[3] = {pi.x, pi.y, pi.z}, v[3] = {vx, vy, vz};
+                const double f[3] = {fx, fy, fz};
+                bool bad = false;
+                double d2 = kick_drift_row(x, v, f, hm, a.dt, a.L, a.inv_L, a.xb, a.N, p, &bad);
+                vx = v[0];
+                vy = v[1];
+                vz = v[2];
+                a.xs_next[p] = make_double4(x[0], x[1], x[2], pi.w);
+                if (bad) atomicOr(a.flag, 1);
+                if (!(d2 <= a.half_skin2)) atomicOr(a.gate_raise, 1);
+            }
             a.vs[p] = vx;
             a.vs[a.N + p] = vy;
             a.vs[2 * a.N + p] = vz;
-            ke = 0.5 * mi * (vx * vx + vy * vy + vz * vz);
         }
     }
     if (a.kepart) {
@@ -154,10 +167,10 @@ __device__ inline void far_body(const FarArgs &a, int b)
     }
 }
 
-template <bool MIXED>
+template <bool MIXED, bool DRIFT>
 __global__ __launch_bounds__(kFarThreads) void k_far(FarArgs a)
 {
-    far_body<MIXED>(a, (int)blockIdx.x);
+    far_body<MIXED, DRIFT>(a, (int)blockIdx.x);
 }
 
 template <bool MIXED>
@@ -165,7 +178,7 @@ __global__ __launch_bounds__(kFarThreads) void k_far_batch(const FarArgs *__rest
                                                            const EnsItem *__restrict__ items)
 {
     const EnsItem e = items[blockIdx.x];
-    far_body<MIXED>(tab[e.r], e.b);
+    far_body<MIXED, false>(tab[e.r], e.b);
 }
 
 hipError_t launch_far_batch(const FarArgs *tab, const EnsItem *items, int n, bool mixed, hipStream_t st)
@@ -179,11 +192,17 @@ hipError_t launch_far_batch(const FarArgs *tab, const EnsItem *items, int n, boo
 hipError_t launch_far(const FarArgs &a, hipStream_t st)
 {
     if (a.N < 1 || a.P < 1 || !a.xs || !a.order || !a.samp || !a.gk || !a.fnear || (!a.f && !a.fs) || !a.flag ||
-        (a.vs && (!a.ms || !a.kepart)) || (!a.mixed && !a.tab))
+        (a.vs && (!a.ms || !a.kepart)) || (!a.mixed && !a.tab) ||
+        (a.drift && (!a.vs || !a.xb || !a.xs_next || !a.gate_raise)))
         return hipErrorInvalidValue;
     dim3 grid(far_blocks(a.N));
-    if (a.mixed) hipLaunchKernelGGL(k_far<true>, grid, dim3(kFarThreads), 0, st, a);
-    else hipLaunchKernelGGL(k_far<false>, grid, dim3(kFarThreads), 0, st, a);
+    if (a.drift) {
+        if (a.mixed) hipLaunchKernelGGL((k_far<true, true>), grid, dim3(kFarThreads), 0, st, a);
+        else hipLaunchKernelGGL((k_far<false, true>), grid, dim3(kFarThreads), 0, st, a);
+    } else {
+        if (a.mixed) hipLaunchKernelGGL((k_far<true, false>), grid, dim3(kFarThreads), 0, st, a);
+        else hipLaunchKernelGGL((k_far<false, false>), grid, dim3(kFarThreads), 0, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -475,7 +475,13 @@ __global__ __launch_bounds__(kNearThreads) void k_nlist(NearArgs a)
 template <bool MIXED, bool ENERGY, int NG>
 __global__ __launch_bounds__(kEvalThreads) void k_near(NearArgs a)
 {
-    near_body<MIXED, ENERGY, NG>(a, xcd_block((int)blockIdx.x, (int)gridDim.x));
+    static_assert(kEvalThreads == kBlock, "the reduction workgroups have kBlock threads");
+    const int b = (int)blockIdx.x;
+    if (b < a.nred) {   // uniform per workgroup
+        rho_reduce_body(a.red, b);
+        return;
+    }
+    near_body<MIXED, ENERGY, NG>(a, xcd_block(b - a.nred, (int)gridDim.x - a.nred));
 }
 
 __global__ __launch_bounds__(kNearThreads) void k_nlist_batch(const NearArgs *__restrict__ tab,
@@ -504,7 +510,9 @@ static bool near_args_ok(const NearArgs &a)
 {
     return a.N >= 1 && a.xs && a.cell_start && a.nbr && a.nbr_stage && a.nbr_cnt && a.fnear && a.kp >= 1 &&
            a.g.nc >= 6 &&
-           a.rc2 > 0.0 && a.rl2 >= a.rc2 && a.w > 0.0 && (!a.energy || a.epart);
+           a.rc2 > 0.0 && a.rl2 >= a.rc2 && a.w > 0.0 && (!a.energy || a.epart) && a.nred >= 0 && a.nred % 8 == 0 &&
+           (a.nred == 0 || (a.red.part && a.red.rho && a.red.gk && a.red.eF && a.red.samp &&
+                            a.nred >= rho_reduce_blocks(a.red.P)));
 }
 
 hipError_t launch_nlist(const NearArgs &a, hipStream_t st)
@@ -574,7 +582,7 @@ hipError_t launch_near_batch(const NearArgs *tab, const EnsItem *items, int n, i
 hipError_t launch_near(const NearArgs &a, hipStream_t st)
 {
     if (!near_args_ok(a) || a.sog.n < 1 || a.sog.n > kMaxGauss) return hipErrorInvalidValue;
-    dim3 grid(near_blocks(a.N));
+    dim3 grid(near_blocks(a.N) + a.nred);
     if (a.mixed) {
         if (a.energy) launch_near_ng<true, true>(a, grid, st);
         else launch_near_ng<true, false>(a, grid, st);

@@ -88,6 +88,11 @@ __host__ __device__ inline int scan_tiles(int ncell) { return (ncell + kScanTile
 // ids + counts + snapshot, scan (which leaves the counts zero again), scatter,
 // stable rank + move; `count` must be zero on entry
 hipError_t launch_cell_build(const CellArgs &a, hipStream_t st);
+// The same passes as one cooperative launch of `grid` workgroups (all
+// resident); cell_build_coop_grid gives the grid for N particles and ncell
+// cells on the current device, 0 when cooperative launches are unavailable.
+int cell_build_coop_grid(int N, int ncell);
+hipError_t launch_cell_build_coop(const CellArgs &a, int grid, hipStream_t st);
 // the same for every replica of a work list: per256 has ceil(N/256) items per
 // replica, pertile scan_tiles(ncell)
 hipError_t launch_cell_build_batch(const CellArgs *tab, const EnsItem *per256, int n256, const EnsItem *pertile,
@@ -204,6 +209,12 @@ struct NearArgs {
     int kp;                    // list capacity per (particle, chunk); 5 kp per particle
     double rl2;                // squared list radius (r_c + skin)^2; the fine grid has cells >= (r_c + skin)/2
     const int32_t *gate;       // list build: null = always, else only when *gate != 0
+    // evaluation of one system: with nred > 0 the first nred workgroups (a
+    // multiple of 8, so the XCD mapping of the rest is unchanged) perform the
+    // structure-factor reduction of `red` instead (its partials are complete:
+    // the partial kernel ran before), saving a dependent launch
+    int nred;
+    RhoArgs red;
 };
 hipError_t launch_nlist(const NearArgs &a, hipStream_t st);
 // workgroups per system: list build (64 particles x 5 planes), evaluation
@@ -242,6 +253,16 @@ struct FarArgs {
     const double2 *tab;        // [kPhaseTab] (sin, cos)(2 pi j / kPhaseTab) (FP64 path)
     SinCosShort ss;
     int32_t *gate_clear;       // null, or a rebuild gate to clear (nothing later in the step reads it)
+    // With drift != 0 the kernel also applies the next step's first half-kick
+    // and drift to the cell-order rows (the drift kernel's arithmetic, fused;
+    // single systems only, the ensemble's far kernel ignores it):
+    // xs_next = xs (written back), gate_raise raised when a particle has moved
+    // more than half the skin since the build.
+    int drift;
+    double dt, L, half_skin2;
+    const double *xb;          // SoA [3][N] positions at the last build, cell order
+    double4 *xs_next;
+    int32_t *gate_raise;
 };
 hipError_t launch_far(const FarArgs &a, hipStream_t st);
 // ensemble: far_blocks items per replica

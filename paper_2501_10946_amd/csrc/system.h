@@ -85,6 +85,7 @@ struct rbsog_handle {
     int32_t *ticket;     // device: the scan's finished-tile counter
     int phase;           // which gate word the next step uses
     bool lists_valid;    // cell order and lists in the workspace belong to the fine grid
+    int coop_grid;       // workgroups of the cooperative cell build (0: five launches instead)
     uint64_t samp_step;  // first step of the modes in samp, with samp_n steps drawn
     int samp_n;
     // per-kernel event timing (rbsog_timing_enable)
@@ -139,6 +140,9 @@ int prepare(rbsog_handle *h, const int32_t *gate, bool carry_v);
 // system's m_max, owned by the caller) the workspace holds no lattice copy
 int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev, const double *m_dev, void *ws_dev,
                   size_t ws_bytes, hipStream_t stream, const int32_t *lattice_dev, rbsog_handle **out);
-int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bool kick, double dt, double *energy);
+// gate_raise non-null (with kick): the far kernel also applies the next
+// step's first half-kick and drift, raising gate_raise; gate_clear is cleared
+int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bool kick, double dt, double *energy,
+             int32_t *gate_raise = nullptr, int32_t *gate_clear = nullptr);
 
 }  // namespace rbsog

@@ -169,6 +169,33 @@ def test_trajectory_small_ocp(dev, precision):
     assert np.abs(E - Eo).max() <= (1e-9 if precision == 0 else 1e-3) * np.abs(Eo).max()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_split_calls_bit_exact(dev, precision):
+    """A run of 30 steps in one rbsog_step call and the same run in calls of
+    7, 1, 0 and 22 steps end in the same bits (x, v, f and the energy history):
+    moving the state into cell order and back at each call, and the first
+    step of a call drifting in its own kernel rather than in the far kernel
+    of the step before, change no arithmetic."""
+    w = workloads.OCP_1K
+    runs = []
+    for split in ([30], [7, 1, 0, 22]):
+        c = Case(dev, w, precision=precision)
+        x = c.x.clone()
+        v = torch.tensor(c.st.v, device=dev)
+        f, _, _ = c.forces(0)
+        ft = torch.tensor(f, device=dev)
+        eh = torch.zeros((30, 6), dtype=torch.float64, device=dev)
+        s0 = 0
+        for n in split:
+            R.rbsog_step(c.sys.h, x, v, ft, s0, n, w.dt, eh[s0:])
+            s0 += n
+        R.rbsog_check(c.sys.h)
+        torch.cuda.synchronize()
+        runs.append([t.cpu().numpy() for t in (x, v, ft, eh)])
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
 def _sampled_reference(c, step, idx):
     """Oracle forces on the particles idx only: near field by the subset pair sum,
     far field from the full structure factors of the same sampled modes."""
