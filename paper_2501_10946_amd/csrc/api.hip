@@ -118,8 +118,7 @@ Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
     L.kepart = take(sizeof(double) * (size_t)far_blocks((int)N));
     L.flag = take(sizeof(int32_t) * 4);
     L.energy = take(sizeof(double) * 8);
-    L.nbr = take(sizeof(int32_t) * (size_t)d.kp * 5 * (size_t)N);
-    L.nbr_stage = take(sizeof(int32_t) * (size_t)d.kp * 5 * (size_t)N);
+    L.nbr = take(sizeof(int32_t) * (size_t)d.kp * 5 * (size_t)list_padded(N));
     L.nbr_cnt = take(sizeof(int32_t) * (size_t)N);
     L.tab = take(sizeof(double) * 2 * kPhaseTable);
     L.total = off;
@@ -242,7 +241,6 @@ NearArgs near_args(rbsog_handle *h, const int32_t *gate, bool energy)
     na.e2 = make_exp2_poly();
     na.nbr = h->nbr;
     na.nbr_cnt = h->nbr_cnt;
-    na.nbr_stage = h->nbr_stage;
     na.kp = h->d.kp;
     na.rc2 = h->sog.r_c * h->sog.r_c;
     na.rl2 = h->d.rl * h->d.rl;
@@ -302,10 +300,7 @@ RhoArgs rho_args(rbsog_handle *h, const double4 *samp)
 int prepare(rbsog_handle *h, const int32_t *gate, bool carry_v)
 {
     CellArgs ca = cell_args(h, h->gf, gate, carry_v);
-    if (h->coop_grid > 0)
-        HIPCHECK(timed(h, kCells, [&] { return launch_cell_build_coop(ca, h->coop_grid, h->st); }));
-    else
-        HIPCHECK(timed(h, kCells, [&] { return launch_cell_build(ca, h->st); }));
+    HIPCHECK(timed(h, kCells, [&] { return launch_cell_build(ca, h->st); }));
     NearArgs na = near_args(h, gate, false);
     HIPCHECK(timed(h, kNlist, [&] { return launch_nlist(na, h->st); }));
     h->lists_valid = true;
@@ -516,7 +511,6 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     h->energy = (double *)(w + L.energy);
     h->nbr = (int32_t *)(w + L.nbr);
     h->nbr_cnt = (int32_t *)(w + L.nbr_cnt);
-    h->nbr_stage = (int32_t *)(w + L.nbr_stage);
     h->tab = (double2 *)(w + L.tab);
     double tabh[2 * kPhaseTable];
     phase_table(tabh);
@@ -552,11 +546,6 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     if (e == hipSuccess) e = hipMemsetAsync(h->flag, 0, sizeof(int32_t) * 4, h->st);
     if (e == hipSuccess) e = hipMemsetAsync(h->count, 0, L.cell_start - L.count, h->st);
     if (e == hipSuccess) e = launch_iota(h->order, (int)p->N, h->st);   // a cell order before the first build
-    // the cell build as one cooperative launch where the device allows it
-    // (RBSOG_COOP_BUILD=0: five launches)
-    h->coop_grid = cell_build_coop_grid((int)p->N, std::max(h->g.ncell, h->gf.ncell));
-    if (const char *cb = std::getenv("RBSOG_COOP_BUILD"))
-        if (std::atoi(cb) == 0) h->coop_grid = 0;
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
     if (e != hipSuccess) {
         delete h;
@@ -611,10 +600,7 @@ extern "C" int rbsog_build_cells(rbsog_handle *h, const double *x_dev, int32_t *
     PermArgs in = perm_args(h, (double *)x_dev, nullptr, nullptr);   // state_in reads x only
     HIPCHECK(timed(h, kKickDrift, [&] { return launch_state_in(in, h->st); }));
     CellArgs a = cell_args(h, h->g, nullptr, false);
-    if (h->coop_grid > 0)
-        HIPCHECK(timed(h, kCells, [&] { return launch_cell_build_coop(a, h->coop_grid, h->st); }));
-    else
-        HIPCHECK(timed(h, kCells, [&] { return launch_cell_build(a, h->st); }));
+    HIPCHECK(timed(h, kCells, [&] { return launch_cell_build(a, h->st); }));
     h->lists_valid = false;  // the workspace now holds the coarse list
     if (cell_start_dev)
         HIPCHECK(hipMemcpyAsync(cell_start_dev, h->cell_start, sizeof(int32_t) * ((size_t)h->g.ncell + 1),

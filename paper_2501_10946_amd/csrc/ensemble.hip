@@ -204,7 +204,7 @@ int rebuild_lists(rbsog_ens *s)
         };
         add(rbsog_ens::L256, (N + kBlock - 1) / kBlock);
         add(rbsog_ens::LTILE, scan_tiles(h->gf.ncell));
-        add(rbsog_ens::LNLIST, nlist_blocks(N));
+        add(rbsog_ens::LNLIST, nlist_blocks(h->gf.nc));
         add(rbsog_ens::LSAMP, (R.P + 63) / 64);
         add(rbsog_ens::LENERGY, 1);
         int chunk = rho_chunk(N, R.P), nch = nchunks(R.N, R.P);

@@ -13,10 +13,8 @@
 // Builds can be gated: every build kernel takes a device flag and returns at
 // once when it is zero, so the decision to rebuild (some particle moved more
 // than half the list skin) is taken on the device with no host round-trip.
-#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
 
 #include "dev_common.h"
 
@@ -198,51 +196,6 @@ hipError_t launch_cell_build(const CellArgs &a, hipStream_t st)
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, st, a);
     hipLaunchKernelGGL(k_rank, dim3(grid), dim3(kBlock), 0, st, a);
     return hipGetLastError();
-}
-
-// The five passes in one cooperative launch (every workgroup resident, a grid
-// barrier between passes): a closed gate costs one launch instead of five.
-// The gate is read once and is the same for every workgroup (nothing writes it
-// during the build), so either every workgroup returns at once or every one
-// reaches every barrier.
-__global__ __launch_bounds__(kBlock) void k_cell_build_coop(CellArgs a)
-{
-    if (!gate_open(a.gate)) return;
-    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
-    const int nb = (a.N + kBlock - 1) / kBlock, nt = scan_tiles(a.g.ncell);
-    const int g0 = (int)blockIdx.x, gs = (int)gridDim.x;
-    for (int b = g0; b < nb; b += gs) cell_ids_body(a, b);
-    grid.sync();
-    for (int b = g0; b < nt; b += gs) scan_tiles_body(a, b);
-    grid.sync();
-    for (int b = g0; b < nt; b += gs) scan_apply_body(a, b);
-    grid.sync();
-    for (int b = g0; b < nb; b += gs) scatter_body(a, b);
-    grid.sync();
-    for (int b = g0; b < nb; b += gs) rank_body(a, b);
-}
-
-int cell_build_coop_grid(int N, int ncell)
-{
-    int dev = 0, ncu = 0, coop = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_cell_build_coop, kBlock, 0) != hipSuccess ||
-        per_cu < 1)
-        return 0;
-    // at most two workgroups per CU: the passes are short, more only adds barrier traffic
-    int need = std::max((N + kBlock - 1) / kBlock, scan_tiles(ncell));
-    return std::max(1, std::min(need, ncu * std::min(per_cu, 2)));
-}
-
-hipError_t launch_cell_build_coop(const CellArgs &a, int grid, hipStream_t st)
-{
-    if (!cell_args_ok(a) || grid < 1) return hipErrorInvalidValue;
-    CellArgs arg = a;
-    void *params[] = {&arg};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_cell_build_coop), dim3(grid), dim3(kBlock),
-                                      params, 0, st);
 }
 
 hipError_t launch_cell_build_batch(const CellArgs *tab, const EnsItem *per256, int n256, const EnsItem *pertile,

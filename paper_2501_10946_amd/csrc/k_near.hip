@@ -10,15 +10,13 @@
 // -2..2 of the stencil; rows and x-cells whose distance from the particle
 // already exceeds the list radius are skipped per particle.
 //
-//   k_nlist  a workgroup owns 64 consecutive particles (cell order) and has 5
-//            waves.  Wave w first finds the candidate ranges of plane w of
-//            each particle; then wave w walks the w-th fifth of each
-//            particle's candidates (all planes in order, four loads in
-//            flight), so every lane has the same share however the planes are
-//            filled, and stores the accepted j in staging rows of its chunk
-//            (capacity kp per chunk); the five chunks of each particle are
-//            then copied, all at once, into one column-major list of the
-//            particle's neighbours in candidate order, plus its count;
+//   k_nlist  a wave lists the particles of two x-adjacent cells: lanes take
+//            the candidates of the pair's 5 x 5 x 6-cell window 64 at a time
+//            (loads coalesced along the rows) and test each against every
+//            home particle in turn; the accepted ones are appended in lane
+//            order straight into the particles' lists (tile-major: 64
+//            particles side by side per row, a tile's rows contiguous), in
+//            window order, with a count per particle;
 //   k_near   a workgroup owns 256 consecutive particles and one of five lanes
 //            per particle (4 waves); lane s evaluates entries s, s + 5, ... of
 //            the particle's list, so the five lanes get equal shares (a split
@@ -48,12 +46,10 @@
 namespace rbsog {
 
 constexpr int kNearPlanes = 5;                 // stencil planes dz = -2..2
-constexpr int kNearThreads = 64 * kNearPlanes; // list build: 64 particles x 5 planes
+constexpr int kListThreads = 64 * kListWaves;  // list build: one cell pair per wave
 constexpr int kEvalThreads = 256;              // evaluation: 256 particles x 1 plane
-constexpr int kStage = 8;                      // accepted entries staged per lane before storing
 constexpr int kShiftBits = 5;                  // image-shift code 0..26 in the top bits of a range start
 constexpr uint32_t kIndexMask = (1u << (32 - kShiftBits)) - 1u;
-constexpr int kMaxRanges = 10;                 // 5 rows, each at most two pieces
 
 __device__ inline double shift_of(int code, double L) { return (double)(code - 1) * L; }
 
@@ -260,128 +256,126 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
 // ---------------------------------------------------------------------------
 
 // lb: the logical workgroup (64 particles, five planes)
+// One wave lists the neighbours of the particles of two x-adjacent cells (the
+// "pair"; the last cell of a row of odd length alone).  Its candidates are the
+// particles of the pair's window: 25 rows (dz, dy = -2..2) of the cells x0 - 2
+// .. x1 + 2, each row one contiguous range of the cell order or two where it
+// wraps.  Lanes take 64 consecutive candidates at a time (a row piece found by
+// a binary search of the pieces' prefix sums, loads coalesced along the rows);
+// for each home particle in turn every lane tests its candidate, and the
+// accepted ones are appended in lane order (ballot / mbcnt) to that particle's
+// list.  So a particle's list holds the candidates within the list radius in
+// window order — planes, rows, wrap pieces, cell order — the same list, entry
+// for entry, as a walk of the particle's own 5 x 5 x 5 cells: the pair window's
+// extra cells lie at least 2 w >= r_c + skin away from the other cell's
+// particles.  A particle with more than 5 kp neighbours gets the count
+// 5 kp + 1 (its lanes then walk the cells in the evaluation).
+__device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
+{
+    __shared__ int32_t pstart[kListWaves][64], ppref[kListWaves][64], pcode[kListWaves][64];
+    const int lane = threadIdx.x & 63;
+    const int nf = a.g.nc, half = (nf + 1) >> 1;
+    if (q >= nf * nf * half) return;   // uniform per wave; no workgroup barrier below
+    const int row = q / half, ix = q - row * half;
+    const int cz = row / nf, cy = row - cz * nf;
+    const int x0 = 2 * ix, x1 = min(x0 + 1, nf - 1);
+    const int cbase = (cz * nf + cy) * nf;
+    const int h_beg = a.cell_start[cbase + x0], h_end = a.cell_start[cbase + x1 + 1];
+    if (h_beg >= h_end) return;
+    // piece `lane` (< 50) of the window: row r = lane / 2 (dz = r / 5 - 2,
+    // dy = r mod 5 - 2), piece lane mod 2 of its x-cells x0 - 2 .. x1 + 2 (the
+    // part left of the wrap first); image shift codes 0/1/2 for -L/0/+L
+    int ps = 0, plen = 0, pc = 0;
+    if (lane < 2 * 25) {
+        const int r = lane >> 1, k = lane & 1;
+        int czw = cz + r / 5 - 2, zc = 1;
+        if (czw < 0) { czw += nf; zc = 0; } else if (czw >= nf) { czw -= nf; zc = 2; }
+        int cyw = cy + r % 5 - 2, yc = 1;
+        if (cyw < 0) { cyw += nf; yc = 0; } else if (cyw >= nf) { cyw -= nf; yc = 2; }
+        const int rb = (czw * nf + cyw) * nf;
+        const int xa = x0 - 2, xb = x1 + 2;   // at most 6 cells <= nf: one side wraps at most
+        int lo = xa, hi = xb, xc = 1;
+        bool has = k == 0;
+        if (xa < 0) {
+            has = true;
+            if (k == 0) { lo = xa + nf; hi = nf - 1; xc = 0; } else { lo = 0; hi = xb; }
+        } else if (xb > nf - 1) {
+            has = true;
+            if (k == 0) { hi = nf - 1; } else { lo = 0; hi = xb - nf; xc = 2; }
+        }
+        if (has) {
+            ps = a.cell_start[rb + lo];
+            plen = a.cell_start[rb + hi + 1] - ps;
+            pc = xc | (yc << 2) | (zc << 4);
+        }
+    }
+    int incl = plen;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int u = __shfl_up(incl, off);
+        if (lane >= off) incl += u;
+    }
+    const int total = __shfl(incl, 63);
+    pstart[wv][lane] = ps;
+    ppref[wv][lane] = incl - plen;
+    pcode[wv][lane] = pc;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int rows = kNearPlanes * a.kp;
+    const double L = a.g.L;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));   // lanes under this one
+    // home particles 64 at a time; lane l keeps the count of home particle hb + l
+    for (int hb = h_beg; hb < h_end; hb += 64) {
+        const int he = min(h_end, hb + 64);
+        int cnt = 0;
+        for (int c0 = 0; c0 < total; c0 += 64) {
+            const int c = c0 + lane;
+            const bool live = c < total;
+            int j = 0;
+            double sx = 0.0, sy = 0.0, sz = 0.0;
+            double4 qj = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (live) {
+                // the last piece whose prefix is <= c (an empty piece shares the
+                // prefix of the next, so it is never the one found)
+                int lo = 0, n = 64;
+                while (n > 0) {
+                    int h2 = n >> 1;
+                    if (ppref[wv][lo + h2] <= c) { lo += h2 + 1; n -= h2 + 1; }
+                    else n = h2;
+                }
+                const int l = lo - 1;
+                j = pstart[wv][l] + (c - ppref[wv][l]);
+                const int code = pcode[wv][l];
+                sx = shift_of(code & 3, L);
+                sy = shift_of((code >> 2) & 3, L);
+                sz = shift_of(code >> 4, L);
+                qj = a.xs[j];
+            }
+            for (int h = hb; h < he; ++h) {
+                const double4 ph = a.xs[h];
+                const Cursor cu{0, 0, ph.x - sx, ph.y - sy, ph.z - sz};
+                const bool ok = live && accept(cu, qj, j, h, a.rl2);
+                const uint64_t m = __ballot(ok);
+                if (m) {
+                    const int base = __builtin_amdgcn_readlane(cnt, h - hb);
+                    if (ok) {
+                        const int k = base + __popcll(m & below);
+                        if (k < rows) a.nbr[list_at(h, k, rows)] = j;
+                    }
+                    if (lane == h - hb) cnt = base + __popcll(m);
+                }
+            }
+        }
+        if (lane < he - hb) a.nbr_cnt[hb + lane] = cnt > rows ? rows + 1 : cnt;
+    }
+}
+
 __device__ inline void nlist_body(const NearArgs &a, int lb)
 {
     if (a.gate && *a.gate == 0) return;
-    __shared__ Range rng[kMaxRanges][kNearThreads];
-    __shared__ int32_t nrng[kNearThreads], tot[kNearThreads];
-    __shared__ int32_t stage[kStage][kNearThreads];
-    const int t = threadIdx.x;
-    const int w = t >> 6, lane = t & 63;
-    const int p = lb * 64 + lane;
-    // 1. thread (plane w, particle p): the candidate ranges of that plane
-    {
-        const Lane l = make_lane(a, p, w);
-        int nr = 0, nc = 0;
-        if (p < a.N && l.gz * l.gz < a.rl2) {
-            for (int row = 0; row < 5; ++row) {
-                Range g[2];
-                int n = row_ranges(a, l, row, a.rl2, g);
-                for (int k = 0; k < n; ++k) {
-                    rng[nr++][t] = g[k];
-                    nc += g[k].end - (g[k].start_code & (int32_t)kIndexMask);
-                }
-            }
-        }
-        nrng[t] = nr;
-        tot[t] = nc;
-    }
-    __syncthreads();
-    // 2. thread (chunk w, particle p): the w-th fifth of the particle's
-    // candidates, planes and ranges in order, so that every thread walks the
-    // same number of candidates whatever the planes hold
-    int T = 0;
-#pragma unroll
-    for (int k = 0; k < kNearPlanes; ++k) T += tot[k * 64 + lane];
-    const int b0 = (int)(((int64_t)w * T) / kNearPlanes), e0 = (int)(((int64_t)(w + 1) * T) / kNearPlanes);
-    int left = e0 - b0;
-    // locate candidate b0: plane, range, offset
-    int q = 0, r = 0, skip = b0;
-    while (q < kNearPlanes && skip >= tot[q * 64 + lane]) {
-        skip -= tot[q * 64 + lane];
-        ++q;
-    }
-    const double4 pi = p < a.N ? a.xs[p] : make_double4(0.0, 0.0, 0.0, 0.0);
-    Cursor c{0, 0, 0.0, 0.0, 0.0};
-    if (left > 0) {
-        for (;;) {
-            Range g = rng[r][q * 64 + lane];
-            int len = g.end - (g.start_code & (int32_t)kIndexMask);
-            if (skip < len) break;
-            skip -= len;
-            ++r;
-        }
-        c = open_range(rng[r][q * 64 + lane], pi, a.g.L);
-        c.j += skip;
-    }
-    // this chunk is staged in rows w*kp .. w*kp + kp - 1
-    const size_t N = (size_t)a.N;
-    int32_t *out = a.nbr_stage + (size_t)w * a.kp * N + p;
-    int total = 0;
-    do {
-        int cnt = 0;
-        while (cnt <= kStage - 4 && left > 0) {
-            if (c.j >= c.jend) {   // next range, of this plane or the next non-empty one
-                if (++r >= nrng[q * 64 + lane]) {
-                    r = 0;
-                    do ++q; while (q < kNearPlanes && nrng[q * 64 + lane] == 0);
-                    if (q >= kNearPlanes) {   // cannot happen: the counts add up
-                        left = 0;
-                        break;
-                    }
-                }
-                c = open_range(rng[r][q * 64 + lane], pi, a.g.L);
-                continue;
-            }
-            int last = c.jend - 1;
-            int n = min(min(4, c.jend - c.j), left);
-            double4 q0 = a.xs[c.j];
-            double4 q1 = a.xs[min(c.j + 1, last)];
-            double4 q2 = a.xs[min(c.j + 2, last)];
-            double4 q3 = a.xs[min(c.j + 3, last)];
-            if (accept(c, q0, c.j, p, a.rl2)) stage[cnt++][t] = c.j;
-            if (n > 1 && accept(c, q1, c.j + 1, p, a.rl2)) stage[cnt++][t] = c.j + 1;
-            if (n > 2 && accept(c, q2, c.j + 2, p, a.rl2)) stage[cnt++][t] = c.j + 2;
-            if (n > 3 && accept(c, q3, c.j + 3, p, a.rl2)) stage[cnt++][t] = c.j + 3;
-            c.j += n;
-            left -= n;
-        }
-        for (int k = 0; k < cnt; ++k)
-            if (total + k < a.kp) out[(size_t)(total + k) * N] = stage[k][t];
-        total += cnt;
-    } while (__any(left > 0));
-
-    // Concatenate the five chunks of each particle in order: chunk w goes to
-    // rows off_w = (sum of the counts of the chunks before it) onward of the
-    // final list, every chunk at once (staging and list are disjoint).  The
-    // list holds the accepted candidates in candidate order.
-    __shared__ int32_t cnts[kNearPlanes][64];
-    cnts[w][lane] = total;
-    __syncthreads();
-    int off = 0, all = 0;
-    bool over = false;
-#pragma unroll
-    for (int k = 0; k < kNearPlanes; ++k) {
-        int cc = cnts[k][lane];
-        over |= cc > a.kp;
-        off += k < w ? cc : 0;
-        all += cc;
-    }
-    if (p < a.N && !over) {
-        int32_t *dst = a.nbr + (size_t)off * N + p;
-        const int32_t *src = out;   // this lane's own staged rows
-        int k = 0;
-        for (; k + 4 <= total; k += 4) {
-            int32_t e0 = src[(size_t)k * N], e1 = src[(size_t)(k + 1) * N];
-            int32_t e2 = src[(size_t)(k + 2) * N], e3 = src[(size_t)(k + 3) * N];
-            dst[(size_t)k * N] = e0;
-            dst[(size_t)(k + 1) * N] = e1;
-            dst[(size_t)(k + 2) * N] = e2;
-            dst[(size_t)(k + 3) * N] = e3;
-        }
-        for (; k < total; ++k) dst[(size_t)k * N] = src[(size_t)k * N];
-    }
-    if (w == 0 && p < a.N) a.nbr_cnt[p] = over ? kNearPlanes * a.kp + 1 : all;
+    const int wv = threadIdx.x >> 6;
+    nlist_pair(a, lb * kListWaves + wv, wv);
 }
 
 // ---------------------------------------------------------------------------
@@ -397,7 +391,7 @@ __device__ inline void near_body(const NearArgs &a, int lb)
     const int grp = lb / kNearPlanes;
     const int plane = lb - grp * kNearPlanes;
     const int p = grp * kEvalThreads + t;
-    const size_t stride = (size_t)kNearPlanes * (size_t)a.N;
+    const size_t stride = (size_t)kNearPlanes * 64;   // a lane's entries are five rows apart
     double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
     int total = 0;
     if (p < a.N) {
@@ -409,23 +403,25 @@ __device__ inline void near_body(const NearArgs &a, int lb)
         // lane `plane` takes entries plane, plane + 5, ... of the particle's
         // list, two per pass: entries k, k + 1 are evaluated while the
         // positions of k + 2, k + 3 and the indices of k + 4, k + 5 are loading
-        // (an index past the lane's count is not read: the particle itself
-        // stands in for it and is never evaluated)
+        // (an index past the lane's count is not read: the particle itself,
+        // or the last one for the lanes past N, stands in for it and is never
+        // evaluated)
         const int cnt = total > plane ? (total - plane + kNearPlanes - 1) / kNearPlanes : 0;
-        const int32_t *in = a.nbr + (size_t)plane * a.N + p;
-        int ja = cnt > 0 ? in[0] : p;
-        int jb = cnt > 1 ? in[stride] : p;
+        const int32_t *in = a.nbr + list_at(p, plane, kNearPlanes * a.kp);
+        const int self = p < a.N ? p : a.N - 1;   // stands in for entries not read
+        int ja = cnt > 0 ? in[0] : self;
+        int jb = cnt > 1 ? in[stride] : self;
         double4 qa = a.xs[ja], qb = a.xs[jb];
         in += 2 * stride;
-        int jc = cnt > 2 ? in[0] : p;
-        int jd = cnt > 3 ? in[stride] : p;
+        int jc = cnt > 2 ? in[0] : self;
+        int jd = cnt > 3 ? in[stride] : self;
         for (int k = 0; k < cnt; k += 2) {
             const double4 ca = qa, cb = qb;
             qa = a.xs[jc];
             qb = a.xs[jd];
             in += 2 * stride;
-            jc = k + 4 < cnt ? in[0] : p;
-            jd = k + 5 < cnt ? in[stride] : p;
+            jc = k + 4 < cnt ? in[0] : self;
+            jd = k + 5 < cnt ? in[stride] : self;
             pair_force<MIXED, ENERGY, NG>(a, pi, ca, fx, fy, fz, en);
             if (k + 1 < cnt) pair_force<MIXED, ENERGY, NG>(a, pi, cb, fx, fy, fz, en);
         }
@@ -467,7 +463,7 @@ __device__ inline void near_body(const NearArgs &a, int lb)
 }
 
 // Single system: workgroups remapped so that neighbouring groups share an XCD.
-__global__ __launch_bounds__(kNearThreads) void k_nlist(NearArgs a)
+__global__ __launch_bounds__(kListThreads) void k_nlist(NearArgs a)
 {
     nlist_body(a, xcd_block((int)blockIdx.x, (int)gridDim.x));
 }
@@ -484,7 +480,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_near(NearArgs a)
     near_body<MIXED, ENERGY, NG>(a, xcd_block(b - a.nred, (int)gridDim.x - a.nred));
 }
 
-__global__ __launch_bounds__(kNearThreads) void k_nlist_batch(const NearArgs *__restrict__ tab,
+__global__ __launch_bounds__(kListThreads) void k_nlist_batch(const NearArgs *__restrict__ tab,
                                                               const EnsItem *__restrict__ items)
 {
     const EnsItem e = items[blockIdx.x];
@@ -508,7 +504,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_near_batch(const NearArgs *__r
 // A launch with a missing buffer is refused on the host.
 static bool near_args_ok(const NearArgs &a)
 {
-    return a.N >= 1 && a.xs && a.cell_start && a.nbr && a.nbr_stage && a.nbr_cnt && a.fnear && a.kp >= 1 &&
+    return a.N >= 1 && a.xs && a.cell_start && a.nbr && a.nbr_cnt && a.fnear && a.kp >= 1 &&
            a.g.nc >= 6 &&
            a.rc2 > 0.0 && a.rl2 >= a.rc2 && a.w > 0.0 && (!a.energy || a.epart) && a.nred >= 0 && a.nred % 8 == 0 &&
            (a.nred == 0 || (a.red.part && a.red.rho && a.red.gk && a.red.eF && a.red.samp &&
@@ -518,7 +514,7 @@ static bool near_args_ok(const NearArgs &a)
 hipError_t launch_nlist(const NearArgs &a, hipStream_t st)
 {
     if (!near_args_ok(a)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_nlist, dim3(nlist_blocks(a.N)), dim3(kNearThreads), 0, st, a);
+    hipLaunchKernelGGL(k_nlist, dim3(nlist_blocks(a.g.nc)), dim3(kListThreads), 0, st, a);
     return hipGetLastError();
 }
 
@@ -549,7 +545,7 @@ static void launch_near_ng(const NearArgs &a, dim3 grid, hipStream_t st)
 hipError_t launch_nlist_batch(const NearArgs *tab, const EnsItem *items, int n, hipStream_t st)
 {
     if (!tab || !items || n < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_nlist_batch, dim3(n), dim3(kNearThreads), 0, st, tab, items);
+    hipLaunchKernelGGL(k_nlist_batch, dim3(n), dim3(kListThreads), 0, st, tab, items);
     return hipGetLastError();
 }
 

@@ -88,11 +88,6 @@ __host__ __device__ inline int scan_tiles(int ncell) { return (ncell + kScanTile
 // ids + counts + snapshot, scan (which leaves the counts zero again), scatter,
 // stable rank + move; `count` must be zero on entry
 hipError_t launch_cell_build(const CellArgs &a, hipStream_t st);
-// The same passes as one cooperative launch of `grid` workgroups (all
-// resident); cell_build_coop_grid gives the grid for N particles and ncell
-// cells on the current device, 0 when cooperative launches are unavailable.
-int cell_build_coop_grid(int N, int ncell);
-hipError_t launch_cell_build_coop(const CellArgs &a, int grid, hipStream_t st);
 // the same for every replica of a work list: per256 has ceil(N/256) items per
 // replica, pertile scan_tiles(ncell)
 hipError_t launch_cell_build_batch(const CellArgs *tab, const EnsItem *per256, int n256, const EnsItem *pertile,
@@ -203,8 +198,7 @@ struct NearArgs {
     double margin;             // slack of the per-particle cell culling
     double inv_L;
     Exp2Poly e2;
-    int32_t *nbr;              // [5 kp][N] listed j per particle (planes concatenated), column-major
-    int32_t *nbr_stage;        // [5 kp][N] list build: rows plane*kp.. of each plane
+    int32_t *nbr;              // 5 kp entries per particle (tile-major, list_at): listed j in candidate order
     int32_t *nbr_cnt;          // [N] listed count per particle; 5 kp + 1 when a plane overflowed
     int kp;                    // list capacity per (particle, chunk); 5 kp per particle
     double rl2;                // squared list radius (r_c + skin)^2; the fine grid has cells >= (r_c + skin)/2
@@ -217,9 +211,21 @@ struct NearArgs {
     RhoArgs red;
 };
 hipError_t launch_nlist(const NearArgs &a, hipStream_t st);
-// workgroups per system: list build (64 particles x 5 planes), evaluation
+// workgroups per system: list build (cell pairs of the fine grid of nf cells per axis), evaluation
 // (256 particles x one of 5 lanes), far field (64 particles)
-__host__ __device__ inline int nlist_blocks(int N) { return (N + 63) / 64; }
+// list build: one pair of x-adjacent cells per wave, kListWaves waves per workgroup
+constexpr int kListWaves = 4;
+__host__ __device__ inline int nlist_blocks(int nf) { return (nf * nf * ((nf + 1) / 2) + kListWaves - 1) / kListWaves; }
+// Neighbour lists are tile-major: entry k of particle p of an array with
+// `rows` entries per particle is at list_at(p, k, rows) — 64 consecutive
+// particles side by side in each row (a wave's row is one 256-byte segment)
+// and a tile's rows contiguous (a list build's stores stay within a few tens of
+// KB per tile).  Arrays hold list_padded(N) particles.
+__host__ __device__ inline size_t list_at(int p, int k, int rows)
+{
+    return ((size_t)(p >> 6) * (size_t)rows + (size_t)k) * 64 + (size_t)(p & 63);
+}
+__host__ __device__ inline int64_t list_padded(int64_t N) { return (N + 63) / 64 * 64; }
 __host__ __device__ inline int near_blocks(int N) { return 5 * ((N + 255) / 256); }
 __host__ __device__ inline int far_blocks(int N) { return (N + 63) / 64; }
 // ensemble: list builds (nlist_blocks items per replica); evaluations of the

@@ -27,7 +27,7 @@ constexpr size_t kAlign = 256;
 struct Layout {
     size_t lattice, cdf, coef, first, size;
     size_t cell_id, count, cell_start, fill, tmp, order, order_old, xs, xs_old, tile_sum, xb, vs, vs_old, fs, ms;
-    size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_stage, nbr_cnt, tab;
+    size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_cnt, tab;
     size_t total;
 };
 
@@ -79,13 +79,12 @@ struct rbsog_handle {
     double *vs, *vs_old, *fs, *ms;   // the stepped state in cell order (with xs)
     double4 *xs, *xs_old, *samp;
     double2 *part, *rho, *gk, *tab;
-    int32_t *nbr, *nbr_stage, *nbr_cnt;
+    int32_t *nbr, *nbr_cnt;
     int32_t *gate;       // device, two words: rebuild the cell order and lists in this step
                          // (steps alternate between them; each step clears the other)
     int32_t *ticket;     // device: the scan's finished-tile counter
     int phase;           // which gate word the next step uses
     bool lists_valid;    // cell order and lists in the workspace belong to the fine grid
-    int coop_grid;       // workgroups of the cooperative cell build (0: five launches instead)
     uint64_t samp_step;  // first step of the modes in samp, with samp_n steps drawn
     int samp_n;
     // per-kernel event timing (rbsog_timing_enable)
