@@ -51,9 +51,10 @@ def flops_near_per_pair(n_gauss: int) -> int:
 # copy of known size.  A figure holds only for the kernel sources it was taken
 # on: it is reported when the SHA-256 over the library sources still matches.
 MEASURED_TRAFFIC = {
-    # kernel: (sources sha256, FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale)
-    "near": ("d6f7651eb403ffcb4ad790f29809178290b09f89aa0eda4d197c07fc71e65e34",
-             31350.0875, 2343.75, 262144 / 131086.6458, 262144 / 262146.9167),
+    # kernel: (sources sha256, FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale); the scales are what
+    # the same counters read for an FP64 copy y = 2 x over 256 MiB (bench.py --copy-calibration 256)
+    "near": ("5fe7ff34136ce7b167b22c6f427e90ef30b85b199a1604f33cb1c5e5eeabadf5",
+             30432.0, 11726.5625, 262144 / 131087.0417, 262144 / 262147.9583),
 }
 
 
