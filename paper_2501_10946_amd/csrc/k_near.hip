@@ -256,6 +256,15 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
 // ---------------------------------------------------------------------------
 
 // lb: the logical workgroup (64 particles, five planes)
+// The value of v in lane l (l uniform), as a scalar.
+__device__ inline double readlane_f64(double v, int l)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // One wave lists the neighbours of the particles of two x-adjacent cells (the
 // "pair"; the last cell of a row of odd length alone).  Its candidates are the
 // particles of the pair's window: 25 rows (dz, dy = -2..2) of the cells x0 - 2
@@ -325,10 +334,12 @@ __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
     const int rows = kNearPlanes * a.kp;
     const double L = a.g.L;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));   // lanes under this one
-    // home particles 64 at a time; lane l keeps the count of home particle hb + l
+    // home particles 64 at a time; lane l keeps the position and the count of
+    // home particle hb + l (positions read once, then broadcast from lane h - hb)
     for (int hb = h_beg; hb < h_end; hb += 64) {
         const int he = min(h_end, hb + 64);
         int cnt = 0;
+        const double4 mine = hb + lane < he ? a.xs[hb + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
         for (int c0 = 0; c0 < total; c0 += 64) {
             const int c = c0 + lane;
             const bool live = c < total;
@@ -353,8 +364,10 @@ __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
                 qj = a.xs[j];
             }
             for (int h = hb; h < he; ++h) {
-                const double4 ph = a.xs[h];
-                const Cursor cu{0, 0, ph.x - sx, ph.y - sy, ph.z - sz};
+                const int src = h - hb;
+                const double hx = readlane_f64(mine.x, src), hy = readlane_f64(mine.y, src),
+                             hz = readlane_f64(mine.z, src);
+                const Cursor cu{0, 0, hx - sx, hy - sy, hz - sz};
                 const bool ok = live && accept(cu, qj, j, h, a.rl2);
                 const uint64_t m = __ballot(ok);
                 if (m) {
