@@ -161,7 +161,7 @@ typedef struct rbsog_info {
     size_t ws_bytes;    /* workspace bytes the system needs                        */
     double skin;        /* neighbour-list skin in use                              */
     int nf;             /* cells per axis of the force evaluation's fine grid      */
-    int near_capacity;  /* neighbour-list capacity per (particle, fifth of its list) */
+    int near_capacity;  /* kp: a particle's neighbour list holds up to 5 kp entries */
     int near_poly;      /* 1: the FP64 pair kernel uses the polynomial H, K        */
 } rbsog_info;
 
@@ -220,7 +220,7 @@ int rbsog_sample_k(rbsog_handle *h, uint64_t step, int32_t *n_dev, double *coef_
 int rbsog_compute_rho(rbsog_handle *h, uint64_t step, const double *x_dev, double *rho_dev);
 
 /*
- * One force evaluation (Algorithm 2, lines 3-5; eq. 3.8 with the random-batch
+ * One force evaluation (the force step of Algorithm 2; eq. 3.8 with the random-batch
  * far field of eq. UF):
  *   f_i = sum_{j: |d| < r_c} q_i q_j [F_N1 + F_N2](|d|) d            (near, d = r_i - r_j, minimum image)
  *       - q_i sum_l coef_l k_l Im(exp(-i k_l . r_i) rho(k_l))          (far, random batch)

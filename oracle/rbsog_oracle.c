@@ -860,8 +860,8 @@ void orc_sys_draw(const orc_sys *S, uint64_t step, int32_t *n_out, double *coef_
              n_out, coef_out);
 }
 
-/* One force evaluation at force-evaluation index `step` (Algorithm 2, lines
- * 3-5).  f (SoA) receives near + far forces; f_near (nullable) the near part
+/* One force evaluation at force-evaluation index `step` (the force step of
+ * Algorithm 2).  f (SoA) receives near + far forces; f_near (nullable) the near part
  * alone.  energy[6] (nullable) = { U_N, U_F (estimator, or the full sum in
  * full-k mode), U_k0, U_self, U_bg, 0 }, where
  *   U_k0   = Fhat(0) (sum q)^2 / (2V)  -- the k = 0 mode of eq. (3.5), excluded

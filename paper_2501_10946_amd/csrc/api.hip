@@ -38,11 +38,11 @@ CellGeom make_geom(double L, int nc)
 }
 
 
-// Capacity of each of a particle's five list chunks (a fifth of its
-// candidates each): 1.5x the expected number of neighbours within the list
-// radius divided by five, plus 16; a particle with a fuller chunk walks its
-// cells directly instead, so this only sizes the fast path.  RBSOG_NEAR_CAPACITY
-// overrides it (a tuning knob).
+// kp, a fifth of a particle's list capacity (the list holds 5 kp entries, the
+// five evaluation lanes taking every fifth): 1.5x the expected number of
+// neighbours within the list radius divided by five, plus 16; a particle with
+// more neighbours walks its cells directly instead, so this only sizes the
+// fast path.  RBSOG_NEAR_CAPACITY overrides it (a tuning knob).
 int near_capacity(int64_t N, double L, double rl, int nf)
 {
     (void)nf;
