@@ -170,6 +170,24 @@ def test_trajectory_small_ocp(dev, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_clustered_cells(dev, precision):
+    """A third of the particles packed into a cube of edge 2.5 around the box
+    corner: cells there hold ~100 particles (several 64-particle home chunks
+    per cell pair in the list build), the cluster wraps around every face, and
+    lists are long.  Forces and energies as for the uniform cases."""
+    w = workloads.Workload("cluster_n3000", N=3000, kappa=1.0, gamma=1.0, r_c=3.0, P=64, seed=77)
+    st = workloads.clustered_state(w, frac=1.0 / 3.0, side=2.5)
+    c = Case(dev, w, precision=precision, state=st)
+    f, fn, e = c.forces(3)
+    fo, fno, eo = c.ref.force(st.x, 3)
+    tol = FP64_TOL if precision == 0 else MIXED_TOL
+    assert rel(f, fo) <= tol
+    assert rel(fn, fno) <= tol
+    assert rel(f - fn, fo - fno) <= tol
+    assert abs(e[0] - eo[0]) <= tol * abs(eo[0])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_split_calls_bit_exact(dev, precision):
     """A run of 30 steps in one rbsog_step call and the same run in calls of
     7, 1, 0 and 22 steps end in the same bits (x, v, f and the energy history):

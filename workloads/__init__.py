@@ -129,6 +129,20 @@ def make_state(w: Workload, seed: Optional[int] = None) -> State:
     return State(x=positions(w.N, w.L, s), v=velocities(m, w.kT, s), q=q, m=m)
 
 
+def clustered_state(w: Workload, frac: float, side: float, seed: Optional[int] = None) -> State:
+    """The workload's state with a fraction `frac` of the particles moved into
+    a cube of edge `side` centred on the box corner (so the cluster wraps
+    around every face): cells there hold far more particles than the mean."""
+    st = make_state(w, seed)
+    g = rng(w.seed if seed is None else seed, 11)
+    n = int(round(frac * w.N))
+    idx = g.choice(w.N, size=n, replace=False)
+    x = st.x.copy()
+    x[:, idx] = np.mod(g.uniform(-0.5 * side, 0.5 * side, (3, n)), w.L)
+    x[x >= w.L] = 0.0
+    return State(x=np.ascontiguousarray(x), v=st.v, q=st.q, m=st.m)
+
+
 def small_system(N: int, L: float, seed: int, neutral: bool = False, qmax: float = 1.0) -> State:
     """A tiny test system in an arbitrary box: uniform positions, charges
     uniform in [-qmax, qmax] shifted to sum to zero when neutral, else all
