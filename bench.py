@@ -464,6 +464,10 @@ def main():
                   "dtype": "f32 pair/phase arithmetic, f64 accumulation", "force_rel_rms": errs["mixed"]},
         "kernels_ms": {k: v["ms_per_launch"] for k, v in r64.get("kernels", {}).items()},
         "roofline": roofline,
+        # every priced kernel against the FP64 vector peak (algorithmic flops per launch / its mean event time)
+        "kernel_rooflines": {k: {"achieved": v, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": v / PEAK_FP64_TFLOPS}
+                             for k, v in r64.get("algorithmic_tflops", {}).items()},
         "cpu_baseline": cpu,
     }
     out["force_only"] = {"fp64": results["fp64"]["force_only"], "mixed": results["mixed"]["force_only"],
