@@ -25,6 +25,7 @@ thread_local std::string g_error;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 
+// groups of the structure-factor partial buffer: an upper bound on those of any launch (rho_chunk <= rho_chunk_shared)
 int nchunks(int64_t N, int P) { return (int)((N + rho_chunk((int)N, P) - 1) / rho_chunk((int)N, P)); }
 
 CellGeom make_geom(double L, int nc)
@@ -279,8 +280,11 @@ RhoArgs rho_args(rbsog_handle *h, const double4 *samp)
     RhoArgs a{};
     a.N = (int)h->p.N;
     a.P = (int)h->d.nmodes;
-    a.chunk = rho_chunk((int)h->p.N, h->p.P);
-    a.nchunk = nchunks(h->p.N, h->p.P);
+    // the group size of the single-system step (partials in the near launch);
+    // the ensemble's partial launch uses the same, so that a replica sums in
+    // the same order as the system alone.  nchunks() (the buffer) bounds it.
+    a.chunk = rho_chunk_shared((int)h->p.N, h->p.P, h->p.precision == RBSOG_MIXED);
+    a.nchunk = (int)((h->p.N + a.chunk - 1) / a.chunk);
     a.inv_L = 1.0 / h->p.L;
     a.xs = h->xs;
     a.samp = samp;
@@ -378,12 +382,12 @@ int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bo
     if (h->d.full_k) {
         HIPCHECK(timed(h, kRhoPartial, [&] { return launch_rho_full(ra, h->st); }));
     } else {
-        HIPCHECK(timed(h, kRhoPartial, [&] { return launch_rho_partial(ra, h->st); }));
-        // the reduction runs in the near kernel's first workgroups
+        // the partial sums run in the near kernel's first workgroups
         na.red = ra;
-        na.nred = (rho_reduce_blocks(ra.P) + 7) / 8 * 8;
+        na.nrho = (int)((rho_blocks(ra.nchunk, ra.P) + 7) / 8 * 8);
     }
     HIPCHECK(timed(h, kNear, [&] { return launch_near(na, h->st); }));
+    if (!h->d.full_k) HIPCHECK(timed(h, kRhoReduce, [&] { return launch_rho_reduce(ra, h->st); }));
     FarArgs fa = far_args(h, samp, f, f_near, kick, dt);
     fa.gate_clear = gate_clear;
     if (kick && gate_raise) {

@@ -58,6 +58,75 @@ __device__ inline double kick_drift_row(double x[3], double v[3], const double f
     return d2;
 }
 
+// ---------------------------------------------------------------------------
+// structure factors.  Particles are cut into groups of C (the "chunk") and the
+// lanes of the grid are laid out flat over (group s, sample l), lane s P + l,
+// so every lane of every wave has work whatever P is.  A workgroup stages the
+// particles of the groups its lanes touch in LDS; each lane sums its group in
+// two interleaved streams and writes one partial per (group, sample); a second
+// kernel adds the partials of each sample in a fixed order.
+// ---------------------------------------------------------------------------
+
+// One particle's term q exp(i k.r) of a mode; p holds (r/L, q) (mixed) or
+// (128 r/L, q) (FP64), so that k.p is the phase in the unit that the
+// precision's sine and cosine take.
+template <bool CELL, bool MIXED>
+__device__ inline void rho_term(const RhoArgs &a, const double2 *tab, const double4 &k, const double4 &p,
+                                double &re, double &im)
+{
+    double u = k.x * p.x + k.y * p.y + k.z * p.z;
+    if (MIXED) {
+        float sn, cs;
+        sincos_rev_f32(u, &sn, &cs);
+        re = fma(p.w, (double)cs, re);
+        im = fma(p.w, (double)sn, im);
+    } else {
+        double sn, cs;
+        sincos_rev_tab(u, tab, a.ss, &sn, &cs);
+        re = fma(p.w, cs, re);
+        im = fma(p.w, sn, im);
+    }
+}
+
+template <bool CELL, bool MIXED>
+__device__ inline void rho_partial_body(const RhoArgs &a, int b)
+{
+    // dynamic LDS: the rotation table (FP64), then the staged particles
+    extern __shared__ double4 lds[];
+    double2 *tab = (double2 *)lds;
+    double4 *sp = lds + (MIXED ? 0 : kPhaseTab / 2);
+    const int t = threadIdx.x;
+    const int64_t g0 = (int64_t)b * kBlock;
+    const int s_lo = (int)(g0 / a.P);
+    const int s_hi = (int)min((int64_t)a.nchunk - 1, (g0 + kBlock - 1) / a.P);
+    const int j_lo = s_lo * a.chunk;
+    const int j_hi = min(a.N, (s_hi + 1) * a.chunk);
+    const double ph = MIXED ? a.inv_L : a.inv_L * kPhaseTab;   // phase unit of the precision
+    for (int k = t; k < j_hi - j_lo; k += kBlock) {
+        int j = j_lo + k;
+        double4 v;
+        if (CELL) v = a.xs[j];
+        else v = make_double4(a.x[j], a.x[a.N + j], a.x[2 * a.N + j], a.q[j]);
+        sp[k] = make_double4(v.x * ph, v.y * ph, v.z * ph, v.w);
+    }
+    if (!MIXED)
+        for (int k = t; k < kPhaseTab; k += kBlock) tab[k] = a.tab[k];
+    __syncthreads();
+    const int64_t g = g0 + t;
+    if (g >= (int64_t)a.nchunk * a.P) return;
+    const int s = (int)(g / a.P), l = (int)(g - (int64_t)s * a.P);
+    const double4 k = a.samp[l];
+    const int ib = s * a.chunk - j_lo, e = min(a.N, (s + 1) * a.chunk) - j_lo;
+    double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
+    int i = ib;
+    for (; i + 1 < e; i += 2) {
+        rho_term<CELL, MIXED>(a, tab, k, sp[i], re0, im0);
+        rho_term<CELL, MIXED>(a, tab, k, sp[i + 1], re1, im1);
+    }
+    if (i < e) rho_term<CELL, MIXED>(a, tab, k, sp[i], re0, im0);
+    a.part[g] = make_double2(re0 + re1, im0 + im1);
+}
+
 // Fixed-order sum of the chunk partials, one workgroup per kRedModes adjacent
 // samples so that each partial row is read as one contiguous segment.  Thread
 // t takes sample l = kRedModes b + (t mod kRedModes) and adds the partials of

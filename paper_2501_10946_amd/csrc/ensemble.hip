@@ -207,7 +207,7 @@ int rebuild_lists(rbsog_ens *s)
         add(rbsog_ens::LNLIST, nlist_blocks(h->gf.nc));
         add(rbsog_ens::LSAMP, (R.P + 63) / 64);
         add(rbsog_ens::LENERGY, 1);
-        int chunk = rho_chunk(N, R.P), nch = nchunks(R.N, R.P);
+        const int chunk = rho_chunk_shared(N, R.P, R.mixed), nch = (N + chunk - 1) / chunk;   // as rho_args
         add(rbsog_ens::LRHO0 + pr, rho_blocks(nch, R.P));
         add(rbsog_ens::LRED0 + pr, rho_reduce_blocks(R.P));
         add(rbsog_ens::LFAR0 + pr, far_blocks(N));

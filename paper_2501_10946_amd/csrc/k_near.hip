@@ -125,12 +125,21 @@ __device__ inline int row_ranges(const NearArgs &a, const Lane &l, int row, doub
     int lo0 = xa < 0 ? xa + nf : xa, hi0 = xa < 0 ? nf - 1 : min(xb, nf - 1);
     int xc0 = xa < 0 ? 0 : 1;
     int s0 = a.cell_start[base + lo0], e0 = a.cell_start[base + hi0 + 1];
-    if (s0 < e0) out[n++] = Range{(int32_t)((uint32_t)s0 | ((uint32_t)(code + xc0) << 27)), e0};
+    // (out[] written at fixed indices only, so that it stays in registers)
+    if (s0 < e0) {
+        out[0] = Range{(int32_t)((uint32_t)s0 | ((uint32_t)(code + xc0) << 27)), e0};
+        n = 1;
+    }
     if (xa < 0 || xb > nf - 1) {
         int hi1 = xa < 0 ? xb : xb - nf;
         int xc1 = xa < 0 ? 1 : 2;
         int s1 = a.cell_start[base], e1 = a.cell_start[base + hi1 + 1];
-        if (s1 < e1) out[n++] = Range{(int32_t)((uint32_t)s1 | ((uint32_t)(code + xc1) << 27)), e1};
+        if (s1 < e1) {
+            const Range r{(int32_t)((uint32_t)s1 | ((uint32_t)(code + xc1) << 27)), e1};
+            if (n == 0) out[0] = r;
+            else out[1] = r;
+            ++n;
+        }
     }
     return n;
 }
@@ -449,9 +458,11 @@ __device__ inline void near_body(const NearArgs &a, int lb)
         if (l.gz * l.gz < a.rl2) {
             for (int row = 0; row < 5; ++row) {
                 Range g[2];
-                int n = row_ranges(a, l, row, a.rl2, g);
-                for (int k = 0; k < n; ++k) {
-                    int j0 = g[k].start_code & (int32_t)kIndexMask;
+                const int n = row_ranges(a, l, row, a.rl2, g);
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {   // fixed indices: g stays in registers
+                    if (k >= n) break;
+                    const int j0 = g[k].start_code & (int32_t)kIndexMask;
                     for (int j = j0; j < g[k].end; ++j)
                         if (j != p) pair_force<MIXED, ENERGY, NG>(a, pi, a.xs[j], fx, fy, fz, en);
                 }
@@ -484,13 +495,13 @@ __global__ __launch_bounds__(kListThreads) void k_nlist(NearArgs a)
 template <bool MIXED, bool ENERGY, int NG>
 __global__ __launch_bounds__(kEvalThreads) void k_near(NearArgs a)
 {
-    static_assert(kEvalThreads == kBlock, "the reduction workgroups have kBlock threads");
+    static_assert(kEvalThreads == kBlock, "the structure-factor workgroups have kBlock threads");
     const int b = (int)blockIdx.x;
-    if (b < a.nred) {   // uniform per workgroup
-        rho_reduce_body(a.red, b);
+    if (b < a.nrho) {   // uniform per workgroup
+        if (b < rho_blocks(a.red.nchunk, a.red.P)) rho_partial_body<true, MIXED>(a.red, b);
         return;
     }
-    near_body<MIXED, ENERGY, NG>(a, xcd_block(b - a.nred, (int)gridDim.x - a.nred));
+    near_body<MIXED, ENERGY, NG>(a, xcd_block(b - a.nrho, (int)gridDim.x - a.nrho));
 }
 
 __global__ __launch_bounds__(kListThreads) void k_nlist_batch(const NearArgs *__restrict__ tab,
@@ -519,9 +530,9 @@ static bool near_args_ok(const NearArgs &a)
 {
     return a.N >= 1 && a.xs && a.cell_start && a.nbr && a.nbr_cnt && a.fnear && a.kp >= 1 &&
            a.g.nc >= 6 &&
-           a.rc2 > 0.0 && a.rl2 >= a.rc2 && a.w > 0.0 && (!a.energy || a.epart) && a.nred >= 0 && a.nred % 8 == 0 &&
-           (a.nred == 0 || (a.red.part && a.red.rho && a.red.gk && a.red.eF && a.red.samp &&
-                            a.nred >= rho_reduce_blocks(a.red.P)));
+           a.rc2 > 0.0 && a.rl2 >= a.rc2 && a.w > 0.0 && (!a.energy || a.epart) && a.nrho >= 0 && a.nrho % 8 == 0 &&
+           (a.nrho == 0 || (a.red.xs && rho_partial_ok(a.red) && a.red.mixed == a.mixed &&
+                            a.nrho >= rho_blocks(a.red.nchunk, a.red.P)));
 }
 
 hipError_t launch_nlist(const NearArgs &a, hipStream_t st)
@@ -535,13 +546,14 @@ template <bool MIXED, bool ENERGY>
 static void launch_near_ng(const NearArgs &a, dim3 grid, hipStream_t st)
 {
     dim3 block(kEvalThreads);
+    const size_t lds = a.nrho > 0 ? rho_lds_bytes(a.red.P, a.red.chunk, MIXED) : 0;
     if (!MIXED && a.sog.poly) {
-        hipLaunchKernelGGL((k_near<false, ENERGY, kPolyNG>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_near<false, ENERGY, kPolyNG>), grid, block, lds, st, a);
         return;
     }
     switch (a.sog.n) {
 #define RBSOG_NEAR_NG(n) \
-    case n: hipLaunchKernelGGL((k_near<MIXED, ENERGY, n>), grid, block, 0, st, a); return;
+    case n: hipLaunchKernelGGL((k_near<MIXED, ENERGY, n>), grid, block, lds, st, a); return;
         RBSOG_NEAR_NG(1)
         RBSOG_NEAR_NG(2)
         RBSOG_NEAR_NG(3)
@@ -551,7 +563,7 @@ static void launch_near_ng(const NearArgs &a, dim3 grid, hipStream_t st)
         RBSOG_NEAR_NG(7)
         RBSOG_NEAR_NG(8)
 #undef RBSOG_NEAR_NG
-    default: hipLaunchKernelGGL((k_near<MIXED, ENERGY, 0>), grid, block, 0, st, a); return;
+    default: hipLaunchKernelGGL((k_near<MIXED, ENERGY, 0>), grid, block, lds, st, a); return;
     }
 }
 
@@ -591,7 +603,7 @@ hipError_t launch_near_batch(const NearArgs *tab, const EnsItem *items, int n, i
 hipError_t launch_near(const NearArgs &a, hipStream_t st)
 {
     if (!near_args_ok(a) || a.sog.n < 1 || a.sog.n > kMaxGauss) return hipErrorInvalidValue;
-    dim3 grid(near_blocks(a.N) + a.nred);
+    dim3 grid(near_blocks(a.N) + a.nrho);
     if (a.mixed) {
         if (a.energy) launch_near_ng<true, true>(a, grid, st);
         else launch_near_ng<true, false>(a, grid, st);

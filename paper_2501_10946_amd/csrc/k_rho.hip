@@ -1,82 +1,15 @@
 // gfx950 kernels of librbsog: structure factors rho(k).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 
 #include "dev_common.h"
 
 namespace rbsog {
 
-// ---------------------------------------------------------------------------
-// structure factors.  Particles are cut into groups of C (the "chunk") and the
-// lanes of the grid are laid out flat over (group s, sample l), lane s P + l,
-// so every lane of every wave has work whatever P is.  A workgroup stages the
-// particles of the groups its lanes touch in LDS; each lane sums its group in
-// two interleaved streams and writes one partial per (group, sample); a second
-// kernel adds the partials of each sample in a fixed order.
-// ---------------------------------------------------------------------------
-
-constexpr int kRhoStage = 1024;   // particles one workgroup stages at most
-
-// One particle's term q exp(i k.r) of a mode; p holds (r/L, q) (mixed) or
-// (128 r/L, q) (FP64), so that k.p is the phase in the unit that the
-// precision's sine and cosine take.
-template <bool CELL, bool MIXED>
-__device__ inline void rho_term(const RhoArgs &a, const double2 *tab, const double4 &k, const double4 &p,
-                                double &re, double &im)
-{
-    double u = k.x * p.x + k.y * p.y + k.z * p.z;
-    if (MIXED) {
-        float sn, cs;
-        sincos_rev_f32(u, &sn, &cs);
-        re = fma(p.w, (double)cs, re);
-        im = fma(p.w, (double)sn, im);
-    } else {
-        double sn, cs;
-        sincos_rev_tab(u, tab, a.ss, &sn, &cs);
-        re = fma(p.w, cs, re);
-        im = fma(p.w, sn, im);
-    }
-}
-
-template <bool CELL, bool MIXED>
-__device__ inline void rho_partial_body(const RhoArgs &a, int b)
-{
-    // dynamic LDS: the rotation table (FP64), then the staged particles
-    extern __shared__ double4 lds[];
-    double2 *tab = (double2 *)lds;
-    double4 *sp = lds + (MIXED ? 0 : kPhaseTab / 2);
-    const int t = threadIdx.x;
-    const int64_t g0 = (int64_t)b * kBlock;
-    const int s_lo = (int)(g0 / a.P);
-    const int s_hi = (int)min((int64_t)a.nchunk - 1, (g0 + kBlock - 1) / a.P);
-    const int j_lo = s_lo * a.chunk;
-    const int j_hi = min(a.N, (s_hi + 1) * a.chunk);
-    const double ph = MIXED ? a.inv_L : a.inv_L * kPhaseTab;   // phase unit of the precision
-    for (int k = t; k < j_hi - j_lo; k += kBlock) {
-        int j = j_lo + k;
-        double4 v;
-        if (CELL) v = a.xs[j];
-        else v = make_double4(a.x[j], a.x[a.N + j], a.x[2 * a.N + j], a.q[j]);
-        sp[k] = make_double4(v.x * ph, v.y * ph, v.z * ph, v.w);
-    }
-    if (!MIXED)
-        for (int k = t; k < kPhaseTab; k += kBlock) tab[k] = a.tab[k];
-    __syncthreads();
-    const int64_t g = g0 + t;
-    if (g >= (int64_t)a.nchunk * a.P) return;
-    const int s = (int)(g / a.P), l = (int)(g - (int64_t)s * a.P);
-    const double4 k = a.samp[l];
-    const int ib = s * a.chunk - j_lo, e = min(a.N, (s + 1) * a.chunk) - j_lo;
-    double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
-    int i = ib;
-    for (; i + 1 < e; i += 2) {
-        rho_term<CELL, MIXED>(a, tab, k, sp[i], re0, im0);
-        rho_term<CELL, MIXED>(a, tab, k, sp[i + 1], re1, im1);
-    }
-    if (i < e) rho_term<CELL, MIXED>(a, tab, k, sp[i], re0, im0);
-    a.part[g] = make_double2(re0 + re1, im0 + im1);
-}
+// Partial sums per (group, sample): rho_partial_body (shared with the near
+// kernel, which can run it in its first workgroups) is in dev_common.h.
 
 template <bool CELL, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_rho_partial(RhoArgs a)
@@ -92,8 +25,7 @@ __global__ __launch_bounds__(kBlock) void k_rho_partial_batch(const RhoArgs *__r
     rho_partial_body<true, MIXED>(tab[e.r], e.b);
 }
 
-// rho_reduce_body (shared with the near kernel, which can run it in its
-// first workgroups) is in dev_common.h.
+// rho_reduce_body is in dev_common.h.
 RBSOG_KERNELS(rho_reduce, RhoArgs, kBlock)
 
 int rho_chunk(int N, int P)
@@ -113,14 +45,31 @@ int rho_chunk(int N, int P)
     return c;
 }
 
+bool rho_partial_ok(const RhoArgs &a)
+{
+    const int64_t lanes = (int64_t)a.nchunk * a.P;
+    return !(a.N < 1 || a.P < 1 || a.chunk < 1 || a.chunk > kRhoChunkMax || !a.samp || !a.part ||
+             (!a.xs && (!a.x || !a.q)) || (!a.mixed && !a.tab) ||
+             (int64_t)(255 / a.P + 2) * a.chunk > kRhoStage || (int64_t)a.nchunk * a.chunk < a.N ||
+             (lanes + kBlock - 1) / kBlock > 0x7fffffff);
+}
+
+int rho_chunk_shared(int N, int P, bool mixed)
+{
+    // the near workgroups supply the occupancy: groups as large as a staging
+    // area of at most 16 KB allows (every workgroup of the shared launch
+    // carries it), never smaller than the group of the launch of their own, so
+    // that the partials fit the same buffer
+    int c = 1;
+    while (2 * c <= kRhoChunkMax && rho_lds_bytes(P, 2 * c, mixed) <= 16384 && (255 / P + 2) * 2 * c <= kRhoStage)
+        c *= 2;
+    return std::max(c, rho_chunk(N, P));
+}
+
 hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st)
 {
-    int64_t lanes = (int64_t)a.nchunk * a.P;
-    if (a.N < 1 || a.P < 1 || a.chunk < 1 || a.chunk > kRhoChunkMax || !a.samp || !a.part ||
-        (!a.xs && (!a.x || !a.q)) || (!a.mixed && !a.tab) ||
-        (int64_t)(255 / a.P + 2) * a.chunk > kRhoStage || (int64_t)a.nchunk * a.chunk < a.N ||
-        (lanes + kBlock - 1) / kBlock > 0x7fffffff)
-        return hipErrorInvalidValue;
+    if (!rho_partial_ok(a)) return hipErrorInvalidValue;
+    const int64_t lanes = (int64_t)a.nchunk * a.P;
     dim3 grid((unsigned)((lanes + kBlock - 1) / kBlock));
     size_t lds = rho_lds_bytes(a.P, a.chunk, a.mixed);
     if (a.xs) {

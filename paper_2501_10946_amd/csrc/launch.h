@@ -15,6 +15,7 @@ constexpr int kBlock = 256;        // threads per workgroup of the streaming and
 constexpr int kScanPer = 8;        // cell counts per thread of the scan
 constexpr int kScanTile = kBlock * kScanPer;
 constexpr int kRhoChunkMax = 256;  // particles per structure-factor group (at most)
+constexpr int kRhoStage = 1024;    // particles one structure-factor workgroup stages at most
 constexpr int kMaxGauss = 32;
 
 // One workgroup of a batched (ensemble) launch: replica slot r, workgroup b of
@@ -168,6 +169,7 @@ struct RhoArgs {
     SinCosShort ss;
 };
 hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st);
+bool rho_partial_ok(const RhoArgs &a);   // the partial launch's argument checks
 hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st);
 // every mode of samp[P] over all particles of xs, rho/gk/eF written directly
 hipError_t launch_rho_full(const RhoArgs &a, hipStream_t st);
@@ -203,11 +205,12 @@ struct NearArgs {
     int kp;                    // list capacity per (particle, chunk); 5 kp per particle
     double rl2;                // squared list radius (r_c + skin)^2; the fine grid has cells >= (r_c + skin)/2
     const int32_t *gate;       // list build: null = always, else only when *gate != 0
-    // evaluation of one system: with nred > 0 the first nred workgroups (a
-    // multiple of 8, so the XCD mapping of the rest is unchanged) perform the
-    // structure-factor reduction of `red` instead (its partials are complete:
-    // the partial kernel ran before), saving a dependent launch
-    int nred;
+    // evaluation of one system: with nrho > 0 the first nrho workgroups (a
+    // multiple of 8, so the XCD mapping of the rest is unchanged) compute the
+    // structure-factor partial sums of `red` instead (the launch carries their
+    // dynamic LDS), so that they run alongside the near field, whose gathers
+    // leave the arithmetic units idle much of the time
+    int nrho;
     RhoArgs red;
 };
 hipError_t launch_nlist(const NearArgs &a, hipStream_t st);
@@ -236,6 +239,8 @@ hipError_t launch_near_batch(const NearArgs *tab, const EnsItem *items, int n, i
                              hipStream_t st);
 // Particles per structure-factor partial for a system of N particles and P samples.
 int rho_chunk(int N, int P);
+// The same when the partials run in the near launch's first workgroups (>= rho_chunk).
+int rho_chunk_shared(int N, int P, bool mixed);
 hipError_t launch_near(const NearArgs &a, hipStream_t st);
 
 // --- far field + assembly + second half-kick ---------------------------------------
