@@ -54,7 +54,7 @@ MEASURED_TRAFFIC = {
     # kernel: (sources sha256, FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale); the scales are what
     # the same counters read for an FP64 copy y = 2 x over 256 MiB (bench.py --copy-calibration 256)
     # (the near launch carries the structure-factor partial sums in its first workgroups)
-    "near": ("5664bf15aa4f49c14a4122737cdba4ec992cc76a6549880214511842f83ad3d4",
+    "near": ("416951cc2dead642657840c1aa4c78bdc957670a5209c842d227195270d88829",
              27793.2899, 14162.5, 262144 / 131086.9167, 262144 / 262146.2083),
 }
 

@@ -30,7 +30,11 @@
 //            otherwise the number of Gaussians is a template parameter for
 //            the common counts; coefficients stay in scalar registers.  When a
 //            plane of a particle overflowed kp at the build, its lanes walk
-//            the candidates of the current positions, one plane each.
+//            the candidates of the current positions, one plane each.  A
+//            single system's launch also computes the structure-factor
+//            partial sums in its first workgroups: the gathers above leave
+//            the arithmetic units idle much of the time, the partial sums
+//            keep them busy (the reduction follows as a launch of its own).
 //
 // Lists hold every j within r_c + skin at the build.  The step path rebuilds
 // them (and the cell order) only when some particle has moved more than
