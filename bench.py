@@ -54,7 +54,7 @@ MEASURED_TRAFFIC = {
     # kernel: (sources sha256, FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale); the scales are what
     # the same counters read for an FP64 copy y = 2 x over 256 MiB (bench.py --copy-calibration 256)
     # (the near launch carries the structure-factor partial sums in its first workgroups)
-    "near": ("416951cc2dead642657840c1aa4c78bdc957670a5209c842d227195270d88829",
+    "near": ("e2126f4486739a13b5f37ace456613befb35a97e325c338bb8ea18d50b306dd9",
              27793.2899, 14162.5, 262144 / 131086.9167, 262144 / 262146.2083),
 }
 
@@ -329,6 +329,13 @@ def main():
             step += args.steps
             res["kernels"] = {k: {"ms_per_launch": (t / n if n else 0.0), "launches": n}
                               for k, (t, n) in R.rbsog_timing_read(s.h).items()}
+            # the structure-factor partial sums as a launch of their own (the
+            # standalone entry point; in a step they share the near launch)
+            rho = torch.empty((w.P, 2), dtype=torch.float64, device=dev)
+            for k in range(args.steps):
+                R.rbsog_compute_rho(s.h, step + k, x, rho)
+            t_rho, n_rho = R.rbsog_timing_read(s.h)["rho_partial"]
+            res["rho_partial_standalone_ms"] = t_rho / n_rho if n_rho else 0.0
             R.rbsog_timing_enable(s.h, False)
         res["x"], res["step"] = x, step
         # force-only rate: one evaluation (cell order and lists rebuilt, modes,
@@ -433,6 +440,10 @@ def main():
         results["fp64"]["algorithmic_tflops"] = {("near+rho_partial" if fused and k == "near" else k):
                                                  work[k] / (kern[k]["ms_per_launch"] * 1e-3) / 1e12
                                                  for k in work if kern[k]["ms_per_launch"] > 0}
+        ms_rho = results["fp64"].get("rho_partial_standalone_ms", 0.0)
+        if ms_rho > 0:
+            results["fp64"]["algorithmic_tflops"]["rho_partial (standalone launch)"] = (
+                w.N * w.P * FLOPS_RHO_PER_IK / (ms_rho * 1e-3) / 1e12)
 
     # ---- the oracle on this machine's host cores (bounded sample) ----
     cpu = None

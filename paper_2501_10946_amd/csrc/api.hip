@@ -635,6 +635,9 @@ extern "C" int rbsog_compute_rho(rbsog_handle *h, uint64_t step, const double *x
     int rc = modes(h, step, 1, &samp);
     if (rc) return rc;
     RhoArgs a = rho_args(h, samp);
+    // a launch of its own: the group size that fills the GPU by itself
+    a.chunk = rho_chunk((int)h->p.N, h->p.P);
+    a.nchunk = nchunks(h->p.N, h->p.P);
     a.xs = nullptr;
     a.x = x_dev;
     a.q = h->q;
