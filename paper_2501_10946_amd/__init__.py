@@ -347,5 +347,8 @@ class System:
     def __del__(self):
         h = getattr(self, "h", None)
         if h:
-            rbsog_destroy(h)
+            try:
+                rbsog_destroy(h)
+            except (TypeError, AttributeError):   # interpreter shutdown: module globals already gone
+                pass
             self.h = None
