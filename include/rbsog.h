@@ -259,9 +259,11 @@ int rbsog_check(rbsog_handle *h);
  * kernel launch (off by default; costs a few microseconds per launch when on).
  * Kernel classes, in slot order: 0 cell list (ids, scan, scatter, stable
  * rank + gather), 1 half-kick + drift, 2 mode sampling, 3 structure-factor
- * partials, 4 structure-factor reduction, 5 near-field pair evaluation,
- * 6 far field + force assembly + half-kick, 7 energy sums, 8 near-field
- * neighbour lists.
+ * partials (a launch of their own: rbsog_compute_rho), 4 structure-factor
+ * reduction, 5 near-field pair evaluation (in a force evaluation or step this
+ * launch also computes the structure-factor partials, in its first
+ * workgroups), 6 far field + force assembly + half-kick, 7 energy sums,
+ * 8 near-field neighbour lists.
  */
 #define RBSOG_NUM_KERNEL_CLASSES 9
 typedef struct rbsog_timing {
