@@ -54,8 +54,8 @@ MEASURED_TRAFFIC = {
     # kernel: (sources sha256, FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale); the scales are what
     # the same counters read for an FP64 copy y = 2 x over 256 MiB (bench.py --copy-calibration 256)
     # (the near launch carries the structure-factor partial sums in its first workgroups)
-    "near": ("e2126f4486739a13b5f37ace456613befb35a97e325c338bb8ea18d50b306dd9",
-             27793.2899, 14162.5, 262144 / 131086.9167, 262144 / 262146.2083),
+    "near": ("1a2749fa542217772b4d6b4a2245d014e73a438852c5222130405e89b6e9a195",
+             27791.1806, 9475.0, 262144 / 131086.75, 262144 / 262147.0833),
 }
 
 

@@ -39,11 +39,11 @@ CellGeom make_geom(double L, int nc)
 }
 
 
-// kp, a fifth of a particle's list capacity (the list holds 5 kp entries, the
-// five evaluation lanes taking every fifth): 1.5x the expected number of
-// neighbours within the list radius divided by five, plus 16; a particle with
-// more neighbours walks its cells directly instead, so this only sizes the
-// fast path.  RBSOG_NEAR_CAPACITY overrides it (a tuning knob).
+// kp, a fifth of a particle's list capacity (the list holds 5 kp entries):
+// 1.5x the expected number of neighbours within the list radius divided by
+// five, plus 16; a particle with more neighbours walks its cells directly
+// instead, so this only sizes the fast path.  RBSOG_NEAR_CAPACITY overrides it
+// (a tuning knob).
 int near_capacity(int64_t N, double L, double rl, int nf)
 {
     (void)nf;
@@ -114,7 +114,7 @@ Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
     L.rho = take(sizeof(double) * 2 * nm);
     L.gk = take(sizeof(double) * 2 * nm);
     L.eF = take(sizeof(double) * nm);
-    L.fnear = take(sizeof(double) * 15 * (size_t)N);
+    L.fnear = take(sizeof(double) * 3 * kNearLanes * (size_t)N);
     L.epart = take(sizeof(double) * (size_t)near_blocks((int)N));
     L.kepart = take(sizeof(double) * (size_t)far_blocks((int)N));
     L.flag = take(sizeof(int32_t) * 4);

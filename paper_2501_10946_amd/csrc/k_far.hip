@@ -105,10 +105,10 @@ __device__ inline void far_body(const FarArgs &a, int b)
             bz += part[2][k * 64 + t];
         }
         double sc = -pi.w * a.two_pi_over_L;
-        // near field: the five lane partials, added in lane order
+        // near field: the lane partials, added in lane order
         double fnx = 0.0, fny = 0.0, fnz = 0.0;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < kNearLanes; ++k) {
             const double *pl = a.fnear + (size_t)k * 3 * a.N + p;
             fnx += pl[0];
             fny += pl[a.N];

@@ -17,20 +17,20 @@
 //            order straight into the particles' lists (tile-major: 64
 //            particles side by side per row, a tile's rows contiguous), in
 //            window order, with a count per particle;
-//   k_near   a workgroup owns 256 consecutive particles and one of five lanes
-//            per particle (4 waves); lane s evaluates entries s, s + 5, ... of
-//            the particle's list, so the five lanes get equal shares (a split
-//            by plane would not: the outer planes hold 0 to ~17 entries
-//            depending on where the particle sits in its cell).  Each lane
-//            runs down its entries with the next index and the next neighbour
-//            position already in flight, and stores its partial force; the
-//            far-field kernel adds the five partials in lane order.  In FP64
+//   k_near   a workgroup owns 256 consecutive particles and one of the
+//            kNearLanes lanes per particle (4 waves); lane s evaluates entries
+//            s, s + kNearLanes, ... of the particle's list, so the lanes get
+//            equal shares (a split by plane would not: the outer planes hold 0
+//            to ~17 entries depending on where the particle sits in its cell).
+//            Each lane runs down its entries with the next index and the next
+//            neighbour position already in flight, and stores its partial
+//            force; the far-field kernel adds the partials in lane order.  In FP64
 //            the pair function is, when its fit is accurate, one polynomial
 //            in r (r^3 times the force factor, 28 FMAs, no exponential),
 //            otherwise the number of Gaussians is a template parameter for
 //            the common counts; coefficients stay in scalar registers.  When a
-//            plane of a particle overflowed kp at the build, its lanes walk
-//            the candidates of the current positions, one plane each.  A
+//            particle's list overflowed at the build, its lanes walk the
+//            candidates of the current positions, plane by plane.  A
 //            single system's launch also computes the structure-factor
 //            partial sums in its first workgroups: the gathers above leave
 //            the arithmetic units idle much of the time, the partial sums
@@ -41,7 +41,7 @@
 // skin / 2 since the last build, so every pair within r_c is listed; pairs
 // listed but now beyond r_c are skipped in the evaluation.
 //
-// Each lane sums its share of a particle's force in list order and the five
+// Each lane sums its share of a particle's force in list order and the
 // shares are added in a fixed order: the result is deterministic.
 #include <hip/hip_runtime.h>
 
@@ -268,7 +268,6 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
 // neighbour lists
 // ---------------------------------------------------------------------------
 
-// lb: the logical workgroup (64 particles, five planes)
 // The value of v in lane l (l uniform), as a scalar.
 __device__ inline double readlane_f64(double v, int l)
 {
@@ -408,16 +407,16 @@ __device__ inline void nlist_body(const NearArgs &a, int lb)
 // evaluation
 // ---------------------------------------------------------------------------
 
-// lb: the logical workgroup (256 particles, one of five lanes each)
+// lb: the logical workgroup (256 particles, one of kNearLanes lanes each)
 template <bool MIXED, bool ENERGY, int NG>
 __device__ inline void near_body(const NearArgs &a, int lb)
 {
     __shared__ double red[kEvalThreads];
     const int t = threadIdx.x;
-    const int grp = lb / kNearPlanes;
-    const int plane = lb - grp * kNearPlanes;
+    const int grp = lb / kNearLanes;
+    const int s = lb - grp * kNearLanes;   // this lane of the particle
     const int p = grp * kEvalThreads + t;
-    const size_t stride = (size_t)kNearPlanes * 64;   // a lane's entries are five rows apart
+    const size_t stride = (size_t)kNearLanes * 64;   // a lane's entries are kNearLanes rows apart
     double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
     int total = 0;
     if (p < a.N) {
@@ -426,14 +425,13 @@ __device__ inline void near_body(const NearArgs &a, int lb)
     }
     double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0;
     if (total <= kNearPlanes * a.kp) {
-        // lane `plane` takes entries plane, plane + 5, ... of the particle's
-        // list, two per pass: entries k, k + 1 are evaluated while the
-        // positions of k + 2, k + 3 and the indices of k + 4, k + 5 are loading
-        // (an index past the lane's count is not read: the particle itself,
-        // or the last one for the lanes past N, stands in for it and is never
-        // evaluated)
-        const int cnt = total > plane ? (total - plane + kNearPlanes - 1) / kNearPlanes : 0;
-        const int32_t *in = a.nbr + list_at(p, plane, kNearPlanes * a.kp);
+        // lane s takes entries s, s + kNearLanes, ... of the particle's list,
+        // two per pass: entries k, k + 1 are evaluated while the positions of
+        // k + 2, k + 3 and the indices of k + 4, k + 5 are loading (an index
+        // past the lane's count is not read: the particle itself, or the last
+        // one for the lanes past N, stands in for it and is never evaluated)
+        const int cnt = total > s ? (total - s + kNearLanes - 1) / kNearLanes : 0;
+        const int32_t *in = a.nbr + list_at(p, s, kNearPlanes * a.kp);
         const int self = p < a.N ? p : a.N - 1;   // stands in for entries not read
         int ja = cnt > 0 ? in[0] : self;
         int jb = cnt > 1 ? in[stride] : self;
@@ -452,29 +450,32 @@ __device__ inline void near_body(const NearArgs &a, int lb)
             if (k + 1 < cnt) pair_force<MIXED, ENERGY, NG>(a, pi, cb, fx, fy, fz, en);
         }
     } else {
-        // a plane of this particle overflowed at the build: each of its five
-        // lanes walks the cells of its plane around the current position.
-        // Particles may have moved up to skin/2 out of the cells they were
-        // sorted into (and wrapped around the box), so the cells are culled
-        // with the list radius and the pair function itself (minimum image,
-        // r < r_c) decides.
-        const Lane l = make_lane(a, p, plane);
-        if (l.gz * l.gz < a.rl2) {
-            for (int row = 0; row < 5; ++row) {
-                Range g[2];
-                const int n = row_ranges(a, l, row, a.rl2, g);
+        // the particle's list overflowed at the build: its lanes walk the
+        // cells of the stencil planes dz = plane - 2 (lane s the planes s,
+        // s + kNearLanes, ...) around the current position.  Particles may
+        // have moved up to skin/2 out of the cells they were sorted into (and
+        // wrapped around the box), so the cells are culled with the list
+        // radius and the pair function itself (minimum image, r < r_c)
+        // decides.
+        for (int plane = s; plane < kNearPlanes; plane += kNearLanes) {
+            const Lane l = make_lane(a, p, plane);
+            if (l.gz * l.gz < a.rl2) {
+                for (int row = 0; row < 5; ++row) {
+                    Range g[2];
+                    const int n = row_ranges(a, l, row, a.rl2, g);
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {   // fixed indices: g stays in registers
-                    if (k >= n) break;
-                    const int j0 = g[k].start_code & (int32_t)kIndexMask;
-                    for (int j = j0; j < g[k].end; ++j)
-                        if (j != p) pair_force<MIXED, ENERGY, NG>(a, pi, a.xs[j], fx, fy, fz, en);
+                    for (int k = 0; k < 2; ++k) {   // fixed indices: g stays in registers
+                        if (k >= n) break;
+                        const int j0 = g[k].start_code & (int32_t)kIndexMask;
+                        for (int j = j0; j < g[k].end; ++j)
+                            if (j != p) pair_force<MIXED, ENERGY, NG>(a, pi, a.xs[j], fx, fy, fz, en);
+                    }
                 }
             }
         }
     }
     if (p < a.N) {
-        double *o = a.fnear + (size_t)plane * 3 * a.N + p;
+        double *o = a.fnear + (size_t)s * 3 * a.N + p;
         o[0] = fx;
         o[a.N] = fy;
         o[2 * (size_t)a.N] = fz;

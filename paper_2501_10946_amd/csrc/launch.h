@@ -192,7 +192,7 @@ struct NearArgs {
     SogDev sog;
     const double4 *xs;         // cell order
     const int32_t *cell_start;
-    double *fnear;             // [5][3][N] partial forces of the five lanes per particle, cell order
+    double *fnear;             // [kNearLanes][3][N] partial forces of the lanes of each particle, cell order
     double *epart;             // [near_blocks(N)] energy partials (when energy)
     int mixed;
     int energy;
@@ -229,7 +229,11 @@ __host__ __device__ inline size_t list_at(int p, int k, int rows)
     return ((size_t)(p >> 6) * (size_t)rows + (size_t)k) * 64 + (size_t)(p & 63);
 }
 __host__ __device__ inline int64_t list_padded(int64_t N) { return (N + 63) / 64 * 64; }
-__host__ __device__ inline int near_blocks(int N) { return 5 * ((N + 255) / 256); }
+// evaluation: a particle's list is dealt round-robin to kNearLanes lanes (3
+// measured fastest of 1..5 on the N = 1e5 plasma: longer runs per lane than 5,
+// enough waves to hide the gathers unlike 1 or 2)
+constexpr int kNearLanes = 3;
+__host__ __device__ inline int near_blocks(int N) { return kNearLanes * ((N + 255) / 256); }
 __host__ __device__ inline int far_blocks(int N) { return (N + 63) / 64; }
 // ensemble: list builds (nlist_blocks items per replica); evaluations of the
 // replicas with `ng` Gaussians (0: any count, read at run time; 9: FP64 with
@@ -251,7 +255,7 @@ struct FarArgs {
     const int32_t *order;
     const double4 *samp;       // [P] (nx, ny, nz, coef)
     const double2 *gk;         // [P] coef * rho
-    const double *fnear;       // [5][3][N] partial near forces of the five lanes, cell order
+    const double *fnear;       // [kNearLanes][3][N] partial near forces of the lanes, cell order
     double *f;                 // null, or SoA [3][N] forces in caller order (through order)
     double *f_near_out;        // null, or SoA [3][N] near forces in caller order
     double *fs;                // null, or SoA [3][N] forces in cell order
