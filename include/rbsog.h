@@ -138,7 +138,7 @@ typedef struct rbsog_params {
     double skin;        /* neighbour-list skin: lists hold pairs within r_c + skin
                            and rbsog_step rebuilds them only when some particle
                            has moved more than skin/2 since the last build; < 0 =
-                           default 0.15 r_c; capped so that L >= 3 (r_c + skin);
+                           default 0.125 r_c; capped so that L >= 3 (r_c + skin);
                            0 = rebuild every step.  Results do not depend on it. */
     int full_k;         /* 0: random batch of P sampled modes (the method);
                            1: deterministic far field over the whole lattice,

@@ -59,9 +59,9 @@ int near_capacity(int64_t N, double L, double rl, int nf)
 Derived derive(const rbsog_params *p, const rbsog_sog *s)
 {
     Derived d{};
-    // default skin 0.15 r_c (the fastest of 0.05..0.33 r_c on the N = 1e5 plasma);
+    // default skin 0.125 r_c (the fastest of 0.05..0.33 r_c on the N = 1e5 plasma);
     // never so large that the fine grid drops below 6 cells
-    double skin = p->skin < 0.0 ? 0.15 * s->r_c : p->skin;
+    double skin = p->skin < 0.0 ? 0.125 * s->r_c : p->skin;
     skin = std::max(0.0, std::min(skin, p->L / 3.0 - s->r_c));
     d.nc = (int)std::floor(p->L / s->r_c);
     d.nf = std::max(6, (int)std::floor(2.0 * p->L / (s->r_c + skin)));
