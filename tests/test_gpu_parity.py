@@ -64,6 +64,8 @@ SMALL = [
     workloads.Workload("nc3_exact_k2", N=150, kappa=2.0, gamma=3.0, r_c=2.5, P=1, seed=8),
     workloads.Workload("mix_n5000", N=5000, kappa=0.5, gamma=5.0, r_c=4.0, P=64, seed=12, frac_b=0.1, q_b=5.0,
                        m_b=20.0),
+    # many modes: six far-kernel sample tiles, partial-sum groups split over workgroups
+    workloads.Workload("manymodes_n3000_p1500", N=3000, kappa=0.8, gamma=2.0, r_c=3.5, P=1500, seed=31),
 ]
 
 
