@@ -32,8 +32,10 @@ PEAK_FP64_TFLOPS = 78.6      # 256 CU x 2.4 GHz x 64 FP64 FMA lanes x 2
 PEAK_FP32_TFLOPS = 157.3     # published FP32 vector peak (packed FP32)
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FP64 flops per unit of work (FMA = 2; the elementary functions count
-# their own operations: exp2 29, revolution sincos 40); derivations in the design notes.
+# Algorithmic FP64 flops per unit of work (FMA = 2, add/mul/rint/compare = 1).  An
+# elementary function is priced as a full-accuracy FP64 series: exp2 29 (rint,
+# subtract, 13-term Horner, ldexp), sincos in revolutions 40 (two rint, a
+# quarter-turn split, 8 + 8 Horner steps, one multiply), whatever the kernels spend.
 FLOPS_SINCOS = 40
 FLOPS_EXP2 = 29
 FLOPS_FAR_PER_IK = 5 + FLOPS_SINCOS + 3 + 6          # phase, sincos, Im(e^{-ikr} rho) coef, 3 FMA
@@ -260,8 +262,8 @@ def main():
                          "for hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path (see the design notes on sharding); "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library steps each system (or ensemble) on one GPU and has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
