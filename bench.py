@@ -56,8 +56,8 @@ MEASURED_TRAFFIC = {
     # kernel: (sources sha256, FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale); the scales are what
     # the same counters read for an FP64 copy y = 2 x over 256 MiB (bench.py --copy-calibration 256)
     # (the near launch carries the structure-factor partial sums in its first workgroups)
-    "near": ("a2b93e76d78ca638e7d0860438cc13f66a2e08fdfb16062b1f33681108e47260",
-             26487.6910, 9475.0, 262144 / 131086.9375, 262144 / 262150.875),
+    "near": ("55d8160675e4a3b15912bd5c7def180d41e0b5e59bf6d3a050bbf6c7a9aee5d3",
+             26486.9149, 9475.0, 262144 / 131086.7917, 262144 / 262147.125),
 }
 
 

@@ -141,7 +141,9 @@ typedef struct rbsog_params {
                            default 0.125 r_c; capped so that L >= 3 (r_c + skin);
                            0 = rebuild every step.  Results do not depend on it.
                            Hot systems, whose fastest particles cross skin/2 in a
-                           step or two, run fastest with 0 (lists of r_c only). */
+                           step or two, run fastest with 0 (lists of r_c only):
+                           the default drops to 0 at the first rbsog_step when
+                           sqrt(2 ln(3N + 1) kT / m_min) dt > skin/4. */
     int full_k;         /* 0: random batch of P sampled modes (the method);
                            1: deterministic far field over the whole lattice,
                            coefficient Fhat(k)/V per mode (eqs. 3.5, UF without

@@ -466,6 +466,14 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     }
     double q1 = 0.0, q2 = 0.0;
     charge_sums(qh.data(), p->N, &q1, &q2);
+    e = hipMemcpyAsync(qh.data(), m_dev, sizeof(double) * (size_t)p->N, hipMemcpyDeviceToHost, h->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(RBSOG_EHIP, "reading m: %s", hipGetErrorString(e));
+    }
+    h->m_min = *std::min_element(qh.begin(), qh.end());
+    h->skin_checked = p->skin >= 0.0;   // only the default skin adapts
     h->Q1 = q1;
     h->Q2 = q2;
     if (!(q2 > 0.0)) {
@@ -668,6 +676,20 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
     if (nsteps < 0) return fail(RBSOG_EINVAL, "nsteps must be >= 0");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RBSOG_EINVAL, "dt must be positive and finite");
     if (nsteps == 0) return RBSOG_OK;
+    // The default skin pays off only when lists outlive several steps.  At the
+    // first step (dt now known) the fastest of the 3N Maxwell velocity
+    // components, ~sqrt(2 ln 3N kT / m_min), is compared with the skin: when it
+    // would cross skin/2 within two steps, lists of r_c alone rebuilt every
+    // step are cheaper.  A smaller radius keeps the current lists valid (they
+    // cover more) and only tightens the rebuild test; results do not change.
+    if (!h->skin_checked) {
+        h->skin_checked = true;
+        const double vmax = std::sqrt(2.0 * std::log(3.0 * (double)h->p.N + 1.0) * h->p.kT / h->m_min);
+        if (h->m_min > 0.0 && 0.5 * h->d.skin < 2.0 * vmax * dt) {
+            h->d.skin = 0.0;
+            h->d.rl = h->sog.r_c;
+        }
+    }
     // the state moves into cell order (the order of the last build) for the
     // steps and back into the caller's order at the end
     PermArgs io = perm_args(h, x_dev, v_dev, f_dev);

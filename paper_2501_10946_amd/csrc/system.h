@@ -85,6 +85,8 @@ struct rbsog_handle {
     int32_t *ticket;     // device: the scan's finished-tile counter
     int phase;           // which gate word the next step uses
     bool lists_valid;    // cell order and lists in the workspace belong to the fine grid
+    double m_min;        // lightest mass (host copy, for the default skin's thermal check)
+    bool skin_checked;   // the default skin has been checked against the first step's dt
     uint64_t samp_step;  // first step of the modes in samp, with samp_n steps drawn
     int samp_n;
     // per-kernel event timing (rbsog_timing_enable)

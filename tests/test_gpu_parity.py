@@ -323,6 +323,37 @@ def test_trajectory_independent_of_skin(dev, skin):
     assert np.abs(d).max() <= 1e-10
 
 
+@pytest.mark.parametrize("gamma,hot", [(1.0, False), (0.01, True)])
+def test_default_skin_adapts(dev, gamma, hot):
+    """The default skin (0.125 r_c) stays for a cold plasma and drops to 0 at
+    the first step of a hot one, whose fastest thermal velocity component
+    would cross skin/2 within two steps; the trajectory is the oracle's either
+    way (1e-10)."""
+    w = workloads.Workload(f"skin_default_g{gamma}", N=1000, kappa=1.0, gamma=gamma, r_c=3.0, P=100, seed=41)
+    st = workloads.make_state(w)
+    o = oracle.sog_auto(w.lam, w.r_c, w.eps)
+    sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+    s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, device=dev)
+    skin0 = R.rbsog_get_info(s.h).skin
+    assert abs(skin0 - 0.125 * w.r_c) <= 1e-12
+    x = torch.tensor(st.x, device=dev)
+    v = torch.tensor(st.v, device=dev)
+    f = torch.empty_like(x)
+    R.rbsog_compute_forces(s.h, 0, x, f)
+    nsteps = 30
+    R.rbsog_step(s.h, x, v, f, 0, nsteps, w.dt)
+    R.rbsog_check(s.h)
+    skin1 = R.rbsog_get_info(s.h).skin
+    assert skin1 == (0.0 if hot else skin0)
+    ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
+    xo, vo = st.x.copy(), st.v.copy()
+    fo, _, _ = ref.force(xo, 0)
+    ref.run(xo, vo, fo, 0, nsteps, w.dt)
+    d = x.cpu().numpy() - xo
+    d -= w.L * np.round(d / w.L)
+    assert np.abs(d).max() <= 1e-10
+
+
 FULLK = [
     workloads.OCP_1K,
     workloads.Workload("fullk_ragged_n777", N=777, kappa=1.0, gamma=1.0, r_c=3.0, P=300, seed=5),
