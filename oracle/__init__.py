@@ -67,7 +67,7 @@ def lib():
             "orc_philox4x64_10": (None, [_p, _p, _p]),
             "orc_cells": (_i, [_i64, _p, _d, _d, _p, _p]),
             "orc_near": (None, [_i64, _p, _p, _d, _d, _d, _i, _p, _p, _p, _p]),
-            "orc_near_subset": (None, [_i64, _p, _p, _d, _d, _d, _i, _p, _p, _i64, _p, _p]),
+            "orc_near_subset": (_i, [_i64, _p, _p, _d, _d, _d, _i, _p, _p, _i64, _p, _p]),
             "orc_rho": (None, [_i64, _p, _p, _d, _i, _p, _p]),
             "orc_far_rb": (None, [_i64, _p, _p, _d, _i, _p, _p, _p, _p]),
             "orc_far_rb_energy": (_d, [_i, _p, _p]),
@@ -242,8 +242,10 @@ def near_subset(x, q, L, s: SOG, idx):
     x, q = _f64(x), _f64(q)
     idx = np.ascontiguousarray(idx, dtype=np.int64)
     f = np.zeros((3, len(idx)))
-    lib().orc_near_subset(x.shape[1], _ptr(x), _ptr(q), L, s.lam, s.rc, s.n, _ptr(s.c), _ptr(s.s), len(idx), _ptr(idx),
-                          _ptr(f))
+    rc = lib().orc_near_subset(x.shape[1], _ptr(x), _ptr(q), L, s.lam, s.rc, s.n, _ptr(s.c), _ptr(s.s), len(idx),
+                               _ptr(idx), _ptr(f))
+    if rc != 0:
+        raise ValueError("near_subset: particle index out of range")
     return f
 
 

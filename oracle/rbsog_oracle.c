@@ -619,15 +619,43 @@ void orc_near(int64_t N, const double *x, const double *q, double L, double lamb
 }
 
 /* Near-field force on a subset of particles idx[0..nsub) (for checks at sizes
- * where the whole near field is too slow on the CPU): the same pair sum over
- * every j != i and every image with |d| < rc, found by a cell list when
- * L >= 3 rc.  f_out is [3][nsub]. */
-void orc_near_subset(int64_t N, const double *x, const double *q, double L, double lambda, double rc, int nG,
-                     const double *c, const double *s, int64_t nsub, const int64_t *idx, double *f_out)
+ * where the whole near field is too slow on the CPU): the same pair sum of
+ * eq. (3.8) over every j != i and every image with |d| < rc, found by a cell
+ * list when L >= 3 rc and by looping over every image shift that can reach
+ * within rc otherwise (boxes smaller than three cutoffs).  f_out is
+ * [3][nsub].  Returns 0, or -1 for an index outside [0, N). */
+int orc_near_subset(int64_t N, const double *x, const double *q, double L, double lambda, double rc, int nG,
+                    const double *c, const double *s, int64_t nsub, const int64_t *idx, double *f_out)
 {
     double rc2 = rc * rc;
     int nc = (int)floor(L / rc);
-    if (nc < 3) return;
+    for (int64_t k = 0; k < nsub; ++k)
+        if (idx[k] < 0 || idx[k] >= N) return -1;
+    if (nc < 3) {
+        int nimg = (int)ceil(rc / L);
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t k = 0; k < nsub; ++k) {
+            int64_t i = idx[k];
+            double fx = 0, fy = 0, fz = 0;
+            for (int64_t j = 0; j < N; ++j)
+                for (int a = -nimg; a <= nimg; ++a)
+                    for (int b = -nimg; b <= nimg; ++b)
+                        for (int cc = -nimg; cc <= nimg; ++cc) {
+                            if (j == i && a == 0 && b == 0 && cc == 0) continue;
+                            double ddx = x[i] - x[j] - a * L;
+                            double ddy = x[N + i] - x[N + j] - b * L;
+                            double ddz = x[2 * N + i] - x[2 * N + j] - cc * L;
+                            double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                            if (r2 >= rc2 || r2 == 0.0) continue;
+                            double fac, en;
+                            near_pair(r2, lambda, nG, c, s, &fac, &en);
+                            double qq = q[i] * q[j];
+                            fx += qq * fac * ddx; fy += qq * fac * ddy; fz += qq * fac * ddz;
+                        }
+            f_out[k] = fx; f_out[nsub + k] = fy; f_out[2 * nsub + k] = fz;
+        }
+        return 0;
+    }
     int32_t *cs = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nc * nc * nc + 1));
     int32_t *ord = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
     orc_cells(N, x, L, rc, cs, ord);
@@ -669,6 +697,7 @@ void orc_near_subset(int64_t N, const double *x, const double *q, double L, doub
     }
     free(cs);
     free(ord);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------- */
