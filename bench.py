@@ -1,26 +1,32 @@
 #!/usr/bin/env python3
 """Throughput of the RBSOG time step on one MI355X.
 
-Workload: the Yukawa one-component plasma with N = 1e5 unit charges at number
-density 3/(4 pi) (Wigner-Seitz radius 1), kappa = 0.5, Gamma = 10, r_c = 4,
-P = 200 sampled Fourier modes, SOG tolerance 1e-4, dt = 0.01; seeded uniform
-positions and Maxwell velocities, pre-equilibrated for 200 steps with the
-velocities rescaled to k_B T after each step (untimed).  A timed step is one
-velocity-Verlet step: half-kick + drift, cell list, mode sampling, structure
-factors, near field, far field + second half-kick.
+Headline workload: the Yukawa one-component plasma with N = 1e6 unit charges
+at number density 3/(4 pi) (Wigner-Seitz radius 1), kappa = 0.1, r_c = 5,
+P = 500 sampled Fourier modes, SOG tolerance 1e-4, dt = 0.01, seeded uniform
+positions and Maxwell velocities, in two runs of 200 NVE velocity-Verlet steps:
+Gamma = 0.1 (k_B T = 10) and Gamma = 100 (k_B T = 0.01).  A timed step is one
+velocity-Verlet step: half-kick + drift, cell list, neighbour lists, mode
+sampling, structure factors, near field, far field + second half-kick, and the
+energy terms of the new state.  `value` is the FP64 throughput of the two runs
+together (their particle-steps over their summed time); mixed precision beside it.
 
-Prints one JSON line: particle-steps/s of the FP64 path (`value`), the same for
-the mixed-precision path, the force error against the FP64 CPU oracle at the
-final state, the roofline position of the dominant kernel (per-kernel HIP
-events recorded on the stream the kernels run on), and the oracle's own
-throughput on this machine's host cores.
+Also reported: the force error against the FP64 CPU oracle at the final state
+(total, near and far; relative RMS and the largest single-particle error), the
+energy drift of each run (all steps, and the second half), per-kernel times from
+HIP events on the stream the kernels run on, the roofline position of the
+dominant kernel, the oracle's throughput on this machine's host cores, and the
+other workloads of the suite (N = 1000, N = 1e5 with pre-equilibration, the
+served ensemble, the binary mixture) as extra keys.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -28,24 +34,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/s at stated force RMS error; served-ensemble p50/p99 step latency"
-PEAK_FP64_TFLOPS = 78.6      # 256 CU x 2.4 GHz x 64 FP64 FMA lanes x 2
-PEAK_FP32_TFLOPS = 157.3     # published FP32 vector peak (packed FP32)
+PEAK_FP64_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA)
+PEAK_SLOTS = PEAK_FP64_TFLOPS / 2 * 1e12   # VALU issue slots per second (one FMA, add, mul or compare each)
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic FP64 flops per unit of work (FMA = 2, add/mul/rint/compare = 1).  An
-# elementary function is priced as a full-accuracy FP64 series: exp2 29 (rint,
-# subtract, 13-term Horner, ldexp), sincos in revolutions 40 (two rint, a
-# quarter-turn split, 8 + 8 Horner steps, one multiply), whatever the kernels spend.
-FLOPS_SINCOS = 40
-FLOPS_EXP2 = 29
-FLOPS_FAR_PER_IK = 5 + FLOPS_SINCOS + 3 + 6          # phase, sincos, Im(e^{-ikr} rho) coef, 3 FMA
-FLOPS_RHO_PER_IK = 5 + FLOPS_SINCOS + 4              # phase, sincos, 2 FMA
+# Algorithmic VALU issue slots per unit of work (one slot per add, multiply,
+# FMA or compare), as the method states its work: an exponential, a square root
+# or a sine-cosine pair costs what the device library's FP64 function costs on
+# this GPU, measured live (elementary_prices) in FMA slots.
+#   pair within r_c: 1 sqrt + (M + 1) exp + (15 + 2 M) arithmetic + 3 FMA accumulation
+#   candidate tested: 3 sub + 3 FMA + 1 compare
+#   structure-factor term (particle, mode): 3 FMA phase + 1 fract + sincos + 2 FMA accumulation
+#   far-field term (particle, mode): 3 FMA phase + 1 fract + sincos + 2 (Im) + 1 (coef) + 3 FMA
 
 
-def flops_near_per_pair(n_gauss: int) -> int:
-    # minimum image 15, r^2 5, cutoff test 1, qq 1, rsqrt 12, r 1, exp(-r/lambda) 1 + 29,
-    # F_N1 6, per Gaussian (1 + 29 + 2), factor 2, force 3 FMA 6
-    return 15 + 5 + 1 + 1 + 12 + 1 + (1 + FLOPS_EXP2) + 6 + n_gauss * (1 + FLOPS_EXP2 + 2) + 2 + 6
+def slots_pair(M: int, pr: dict) -> float:
+    return pr["sqrt"] + (M + 1) * pr["exp"] + 15 + 2 * M + 3
+
+
+SLOTS_CANDIDATE = 7.0
+
+
+def slots_rho(pr: dict) -> float:
+    return 6 + pr["sincos"]
+
+
+def slots_far(pr: dict) -> float:
+    return 10 + pr["sincos"]
 
 
 # HBM bytes per launch of a kernel, from one FETCH_SIZE and one WRITE_SIZE counter
@@ -53,11 +68,13 @@ def flops_near_per_pair(n_gauss: int) -> int:
 # copy of known size.  A figure holds only for the kernel sources it was taken
 # on: it is reported when the SHA-256 over the library sources still matches.
 MEASURED_TRAFFIC = {
-    # kernel: (sources sha256, FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale); the scales are what
-    # the same counters read for an FP64 copy y = 2 x over 256 MiB (bench.py --copy-calibration 256)
-    # (the near launch carries the structure-factor partial sums in its first workgroups)
-    "near": ("55d8160675e4a3b15912bd5c7def180d41e0b5e59bf6d3a050bbf6c7a9aee5d3",
-             26486.9149, 9475.0, 262144 / 131086.7917, 262144 / 262147.125),
+    # kernel: (sources sha256, FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale)
+}
+
+# VALU counters of a kernel at the headline workload (rocprofv3 --pmc, one pass
+# each): SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, SQ_BUSY_CU_CYCLES (or GRBM), and
+# VALUUtilization; keyed like MEASURED_TRAFFIC.
+MEASURED_VALU = {
 }
 
 
@@ -80,56 +97,226 @@ def measured_traffic(kernel: str):
     return (t[1] * t[3] + t[2] * t[4]) * 1024.0
 
 
+def measured_valu(kernel: str):
+    t = MEASURED_VALU.get(kernel)
+    if t is None or t[0] != sources_sha256():
+        return None
+    return t[1]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
+
+def host_info() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model or platform.processor(), "nproc": avail, "cpu_count": os.cpu_count()}
+
+
+# ---------------------------------------------------------------------------
+# elementary-function prices (libprice.so, measured on this GPU)
+# ---------------------------------------------------------------------------
+
+def elementary_prices() -> dict:
+    """FMA issue slots per FP64 call of exp, sincos, sqrt and rsqrt (the device
+    library's functions), from the time per call against a plain FMA chain."""
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2501_10946_amd", "libprice.so"))
+    lib.rbsog_price_run.restype = ctypes.c_int
+    lib.rbsog_price_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    blocks = 256 * 8 * 4   # 8 workgroups of 4 waves per CU
+
+    def run(op, iters):
+        ms = ctypes.c_double()
+        if lib.rbsog_price_run(op, iters, blocks, ctypes.byref(ms)) != 0:
+            raise RuntimeError("rbsog_price_run failed")
+        return ms.value / (iters * 8.0)   # ms per call per lane-chain step (grid-wide)
+
+    t_fma = run(0, 4000)
+    t_exp = run(1, 400)
+    t_sc = run(2, 200)
+    t_sqrt = run(3, 1000)
+    t_rsq = run(4, 1000)
+    calls = blocks * 256.0   # lane-chain steps per ms-unit above: t_* is per (iteration x chain)
+    return {
+        "fma": 1.0,
+        "exp": t_exp / t_fma,
+        "sincos": t_sc / t_fma - 1.0,    # the chain's one FMA beside each call
+        "sqrt": t_sqrt / t_fma - 1.0,    # the chain's one add
+        "rsqrt": t_rsq / t_fma - 1.0,
+        "fma_calls_per_s": calls / (t_fma * 1e-3),
+        "fma_peak_fraction": (calls / (t_fma * 1e-3)) / PEAK_SLOTS,
+    }
+
+
+# ---------------------------------------------------------------------------
+# statistics
+# ---------------------------------------------------------------------------
 
 def energy_drift(E, dt: float, scale: float) -> dict:
     """Least-squares slope of the per-step total energy (in units of `scale`,
     N k_B T) per unit time, with its standard error, and the spread."""
     import numpy as np
+    E = np.asarray(E, dtype=np.float64)
     t = dt * np.arange(1, len(E) + 1)
-    y = np.asarray(E) / scale
+    y = E / scale
+    if len(y) < 3:
+        return {"steps": len(y)}
     A = np.vstack([t, np.ones_like(t)]).T
-    coef, res, _, _ = np.linalg.lstsq(A, y, rcond=None)
+    coef, _, _, _ = np.linalg.lstsq(A, y, rcond=None)
     n = len(y)
     resid = y - A @ coef
     s2 = float(resid @ resid) / max(1, n - 2)
     se = (s2 / float(((t - t.mean()) ** 2).sum())) ** 0.5
-    return {"steps": n, "slope_NkT_per_time": float(coef[0]), "stderr": se, "std_NkT": float(np.std(y))}
+    return {"steps": n, "slope_NkT_per_time": float(coef[0]), "stderr": se, "std_NkT": float(np.std(y)),
+            "E0_NkT": float(y[0]), "E_end_NkT": float(y[-1])}
 
 
-def force_noise(R, h, h_full, x, m, w, evals: int) -> dict:
-    """Random-batch force noise at one state: forces of `evals` independent
-    draws (force indices 10^6 + k) against the full-lattice force of the same
-    positions.  Velocity-Verlet applies each step's force noise xi over one
-    whole time step, so the kinetic energy grows by dt^2 |xi|^2 / (2 m) per
-    step and particle: the expected energy drift is dt <|xi|^2 / m> / (2 kT) in
-    N kT per unit time.  The mean of the draws estimates the bias, whose RMS
-    over particles should be that of the noise over sqrt(evals)."""
+def force_errors(fg, fng, fo, fno) -> dict:
+    """Relative RMS over all components and the largest single-particle error
+    (relative to the RMS particle force) of total, near and far forces."""
+    import numpy as np
+
+    def pair(a, b):
+        r = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        d = np.linalg.norm(a - b, axis=0)
+        s = float(np.sqrt(np.mean(np.linalg.norm(b, axis=0) ** 2)))
+        return {"rel_rms": r, "max_particle": float(d.max()) / s}
+
+    return {"total": pair(fg, fo), "near": pair(fng, fno), "far": pair(fg - fng, fo - fno)}
+
+
+def count_pairs(x, L, rc) -> int:
+    """Ordered pairs within r_c (periodic), the near field's algorithmic work."""
+    from scipy.spatial import cKDTree
+    t = cKDTree(x.T.copy() % L, boxsize=L)
+    return int(t.count_neighbors(t, rc)) - x.shape[1]   # every particle counts itself once
+
+
+def canonical_candidates(N: int, L: float, rc: float) -> float:
+    """Candidates a particle tests over the 27 cells of width L / floor(L / r_c)
+    around it (the cell-list search of the method), times N."""
+    nc = math.floor(L / rc)
+    return N * 27.0 * N / nc ** 3
+
+
+# ---------------------------------------------------------------------------
+# one system: timed steps, per-kernel times, force error, drift
+# ---------------------------------------------------------------------------
+
+def run_workload(R, w, st, sog, prec, steps, warmup, dev, skin=-1.0, x0=None, v0=None, step0=0,
+                 kernel_pass=True):
+    """W untimed warm-up steps from the state, then K timed NVE steps from the
+    same state (forces and integration; the near-field energy is optional in
+    the method and not evaluated), then (kernel_pass) a pass of K/4 more steps
+    with per-kernel events, then the same K steps once more from the state
+    with the per-step energies recorded (untimed) for the drift.  Returns
+    throughput, the final state of the timed run and the energy history."""
     import torch
-    ff = torch.empty_like(x)
-    R.rbsog_compute_forces(h_full, 0, x, ff)
-    fr = torch.empty_like(x)
-    s1 = torch.zeros_like(x)
-    s2 = torch.zeros(x.shape[1], dtype=torch.float64, device=x.device)
-    for k in range(evals):
-        R.rbsog_compute_forces(h, 1_000_000 + k, x, fr)
-        d = fr - ff
-        s1 += d
-        s2 += (d * d).sum(dim=0)
+    s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, precision=prec, skin=skin, device=dev)
+    xs = torch.tensor(st.x if x0 is None else x0, device=dev)
+    vs = torch.tensor(st.v if v0 is None else v0, device=dev)
+    if warmup > 0:
+        x, v, f = xs.clone(), vs.clone(), torch.empty_like(xs)
+        R.rbsog_compute_forces(s.h, step0, x, f)
+        R.rbsog_step(s.h, x, v, f, step0, warmup, w.dt)
+        torch.cuda.synchronize()
+        R.rbsog_check(s.h)
+        del x, v, f
+    x, v, f = xs.clone(), vs.clone(), torch.empty_like(xs)
+    R.rbsog_compute_forces(s.h, step0, x, f)
     torch.cuda.synchronize()
-    R.rbsog_check(h)
-    xi2 = s2 / evals
-    bias = s1 / evals
-    bias_rms = float((bias * bias).sum(dim=0).mean()) ** 0.5
-    noise_rms = float(xi2.mean()) ** 0.5
-    return {"evals": evals, "xi_rms": noise_rms, "f_full_rms": float((ff * ff).sum(dim=0).mean()) ** 0.5,
-            "bias_rms": bias_rms, "bias_rms_expected": noise_rms / evals ** 0.5,
-            "predicted_slope_NkT_per_time": w.dt * float((xi2 / m).mean()) / (2.0 * w.kT)}
+    t0 = time.perf_counter()
+    R.rbsog_step(s.h, x, v, f, step0, steps, w.dt)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    R.rbsog_check(s.h)
+    res = {"value": w.N * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps, "elapsed_s": elapsed,
+           "x": x.clone(), "v": v.clone(), "step": step0 + steps, "info": R.rbsog_get_info(s.h)}
+    if kernel_pass:
+        n = max(10, steps // 4)
+        xk, vk, fk = x.clone(), v.clone(), f.clone()
+        R.rbsog_timing_enable(s.h, True)
+        R.rbsog_step(s.h, xk, vk, fk, step0 + steps, n, w.dt)
+        res["kernels"] = {k: {"ms_per_launch": (t / c if c else 0.0), "launches": c, "ms_per_step": t / n}
+                          for k, (t, c) in R.rbsog_timing_read(s.h).items() if c}
+        R.rbsog_timing_enable(s.h, False)
+        R.rbsog_check(s.h)
+    # the energy history of the same trajectory (untimed)
+    x, v, f = xs.clone(), vs.clone(), torch.empty_like(xs)
+    eh = torch.zeros((steps, 6), dtype=torch.float64, device=dev)
+    R.rbsog_compute_forces(s.h, step0, x, f)
+    t0 = time.perf_counter()
+    R.rbsog_step(s.h, x, v, f, step0, steps, w.dt, eh)
+    torch.cuda.synchronize()
+    res["ms_per_step_with_energies"] = 1e3 * (time.perf_counter() - t0) / steps
+    R.rbsog_check(s.h)
+    res["ehist"] = eh.cpu().numpy()
+    res["system"] = s
+    return res
 
 
-def serve(args, dev, log):
+def force_check(R, oracle, w, st, o, x_state, step, dev, nsample=512):
+    """Library forces (FP64 and mixed) at one state against the FP64 oracle on
+    `nsample` sampled particles: near field by the oracle's subset pair sum, far
+    field from the oracle's structure factors of the same sampled modes."""
+    import numpy as np
+    import torch
+    xh = x_state.cpu().numpy() if hasattr(x_state, "cpu") else x_state
+    ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(w.N, min(nsample, w.N), replace=False))
+    n3, coef = ref.draw(step)
+    rho = oracle.rho(xh, st.q, w.L, n3)
+    fno = oracle.near_subset(xh, st.q, w.L, o, idx)
+    ffo = oracle.far_rb(xh[:, idx], st.q[idx], w.L, n3, coef, rho)
+    sog_o = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+    xt = torch.tensor(xh, device=dev)
+    out = {}
+    for name, prec in (("fp64", R.RBSOG_FP64), ("mixed", R.RBSOG_MIXED)):
+        s = R.System(st.q, st.m, w.L, sog_o, w.kT, w.P, seed=w.seed, precision=prec, device=dev)
+        fg = torch.empty_like(xt)
+        fng = torch.empty_like(xt)
+        R.rbsog_compute_forces(s.h, step, xt, fg, fng)
+        torch.cuda.synchronize()
+        out[name] = force_errors(fg.cpu().numpy()[:, idx], fng.cpu().numpy()[:, idx], fno + ffo, fno)
+        del s
+    out["sampled_particles"] = int(len(idx))
+    return out
+
+
+def strip(res: dict) -> dict:
+    return {k: v for k, v in res.items() if k not in ("x", "v", "ehist", "system", "info", "step", "elapsed_s")}
+
+
+def rooflines(kern: dict, work: dict) -> dict:
+    """Every priced kernel: algorithmic slots per launch / mean launch time."""
+    out = {}
+    for k, slots in work.items():
+        if k in kern and kern[k]["ms_per_launch"] > 0:
+            rate = slots / (kern[k]["ms_per_launch"] * 1e-3)
+            out[k] = {"achieved": 2 * rate / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                      "frac": rate / PEAK_SLOTS, "slots_per_launch": slots,
+                      "ms_per_launch": kern[k]["ms_per_launch"]}
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the served ensemble
+# ---------------------------------------------------------------------------
+
+def serve(args, dev):
     """The served ensemble: seeded requests (N log-uniform in [500, 5e4], Gamma
     log-uniform in [0.1, 100], kappa uniform in [0.1, 2], r_c 4, P 200, 100
     steps, mixed precision) admitted into one ensemble.  First all at t = 0
@@ -158,14 +345,16 @@ def serve(args, dev, log):
         ens = R.rbsog_ens_create(budget, max_slots)
         try:
             pending = list(range(len(prep)))
-            slot_req, t_adm, t_done, active_at, times = {}, {}, {}, [], []
+            slot_req, t_done, active_at, times = {}, {}, [], []
             done = 0
+            t_admit = 0.0
             t0 = time.perf_counter()
             while done < len(prep):
                 now = time.perf_counter() - t0
                 while pending and arrivals[pending[0]] <= now:
                     i = pending[0]
                     w, st, sg, p = prep[i]
+                    ta = time.perf_counter()
                     try:
                         slot = R.rbsog_ens_admit(ens, p, sg, np.ascontiguousarray(st.x), np.ascontiguousarray(st.v),
                                                  np.ascontiguousarray(st.q), np.ascontiguousarray(st.m), w.steps,
@@ -174,15 +363,14 @@ def serve(args, dev, log):
                         if e.code != R.RBSOG_EAGAIN:
                             raise
                         break
+                    finally:
+                        t_admit += time.perf_counter() - ta
                     slot_req[slot] = i
-                    t_adm[i] = time.perf_counter() - t0
                     pending.pop(0)
                 stat = R.rbsog_ens_status(ens)
                 if stat["active"] > 0:
                     active_at.append(stat["active"])
                     R.rbsog_ens_step(ens)
-                    # keep one step queued behind the one running, no more; the
-                    # completion times are read as the steps are waited for
                     while len(times) < stat["ens_steps"]:
                         times.append(R.rbsog_ens_step_time(ens, len(times) + 1))
                 elif pending and arrivals[pending[0]] > now:
@@ -200,13 +388,12 @@ def serve(args, dev, log):
             times = np.array(times)
         finally:
             R.rbsog_ens_destroy(ens)
-        # per (replica, step) latency: the gap between consecutive ensemble-step
-        # completions, counted once per replica active in the later step
         gaps = np.diff(times)
         w_gaps = np.repeat(gaps, active_at[1:len(times)]) if len(gaps) else np.zeros(1)
         lat = np.array([t_done[i] - arrivals[i] for i in range(len(prep))])
-        return {"wall_s": wall, "ens_steps": int(nst), "particle_steps_per_s": total_ps / wall,
-                "requests_per_s": len(prep) / wall,
+        return {"wall_s": wall, "admission_s": t_admit, "ens_steps": int(nst),
+                "step_time_sum_s": float(gaps.sum() / 1e3) if len(gaps) else 0.0,
+                "particle_steps_per_s": total_ps / wall, "requests_per_s": len(prep) / wall,
                 "step_ms_p50": float(np.percentile(w_gaps, 50)), "step_ms_p99": float(np.percentile(w_gaps, 99)),
                 "request_ms_p50": 1e3 * float(np.percentile(lat, 50)),
                 "request_ms_p99": 1e3 * float(np.percentile(lat, 99)),
@@ -222,7 +409,7 @@ def serve(args, dev, log):
     for frac in [float(v) for v in args.serve_rates.split(",") if v]:
         arr = np.array([t for t, _ in workloads.served_requests(args.serve_requests, rate=frac * cap)])
         r = run(arr, budget, len(prep))
-        out["poisson"][f"{frac:g}"] = r
+        out["poisson"][f"{frac:g}"] = dict(r, rate_req_per_s=frac * cap)
         log(f"[serve] poisson {frac:g}x capacity ({frac * cap:.1f} req/s): {r}")
     small = max(need) + sum(sorted(need)[: len(need) // 8])
     r = run(zero, small, len(prep))
@@ -231,29 +418,20 @@ def serve(args, dev, log):
     return out
 
 
-def count_pairs(x, L, rc) -> int:
-    """Ordered pairs within r_c (periodic), the near field's algorithmic work."""
-    from scipy.spatial import cKDTree
-    t = cKDTree(x.T.copy() % L, boxsize=L)
-    return 2 * len(t.query_pairs(rc, output_type="ndarray"))
-
+# ---------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=200, help="timed NVE steps per run of the headline workload")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--preeq", type=int, default=200)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget for the oracle baseline sample")
+    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle velocity-Verlet steps of the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-roofline", action="store_true")
-    ap.add_argument("--skin", type=float, default=-1.0, help="neighbour-list skin (negative: the library default)")
-    ap.add_argument("--drift-steps", type=int, default=500, help="NVE steps of the energy-drift runs (0: none)")
+    ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-ensemble measurement")
-    ap.add_argument("--no-fullk-energy", action="store_true",
-                    help="skip the deterministic full-lattice energy along the first 100 FP64 NVE steps")
-    ap.add_argument("--noise-evals", type=int, default=200,
-                    help="random-batch draws for the force-noise estimate of the drift (0: none)")
+    ap.add_argument("--no-force-check", action="store_true")
+    ap.add_argument("--skin", type=float, default=-1.0, help="neighbour-list skin (negative: the library default)")
+    ap.add_argument("--gammas", default="0.1,100", help="couplings of the headline runs")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rates", default="0.5,0.8,1.2",
                     help="Poisson arrival rates as fractions of the measured saturated capacity")
@@ -269,6 +447,7 @@ def main():
     import numpy as np
     import torch
 
+    import oracle
     import paper_2501_10946_amd as R
     import workloads
 
@@ -282,224 +461,201 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: {n * 8} bytes read and written per launch")
         del a, b
-    w = workloads.OCP_100K
-    st = workloads.make_state(w)
-    sog = R.rbsog_sog_init(w.lam, w.r_c, w.eps)
-    log(f"[bench] {w.name}: N={w.N} L={w.L:.4f} P={w.P} SOG M1={sog.M1} M2={sog.M2} err={sog.max_err:.2e}")
 
-    # ---- pre-equilibration (FP64, velocity rescaling to kT each step) ----
-    sys64 = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, precision=R.RBSOG_FP64, skin=args.skin,
-                     device=dev)
-    x = torch.tensor(st.x, device=dev)
-    v = torch.tensor(st.v, device=dev)
-    f = torch.empty_like(x)
-    R.rbsog_compute_forces(sys64.h, 0, x, f)
-    eh = torch.zeros((1, 6), dtype=torch.float64, device=dev)
-    ke_target = 0.5 * (3 * w.N - 3) * w.kT
-    step = 0
-    t0 = time.perf_counter()
-    for _ in range(args.preeq):
-        R.rbsog_step(sys64.h, x, v, f, step, 1, w.dt, eh)
-        step += 1
-        v.mul_(torch.sqrt(ke_target / eh[0, 5]))
-    R.rbsog_check(sys64.h)
-    torch.cuda.synchronize()
-    log(f"[bench] pre-equilibration {args.preeq} steps: {time.perf_counter() - t0:.2f} s")
-    x_eq, v_eq, f_eq, step_eq = x.clone(), v.clone(), f.clone(), step
+    prices = elementary_prices()
+    log(f"[bench] FP64 elementary functions in FMA slots: " +
+        ", ".join(f"{k} {prices[k]:.1f}" for k in ("exp", "sincos", "sqrt", "rsqrt")) +
+        f" (FMA chain at {prices['fma_peak_fraction']:.2f} of the issue peak)")
 
-    results = {}
-    for name, prec in (("fp64", R.RBSOG_FP64), ("mixed", R.RBSOG_MIXED)):
-        s = sys64 if prec == R.RBSOG_FP64 else R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed,
-                                                         precision=prec, skin=args.skin, device=dev)
-        x, v, f = x_eq.clone(), v_eq.clone(), f_eq.clone()
-        step = step_eq
-        R.rbsog_compute_forces(s.h, step, x, f)
-        R.rbsog_step(s.h, x, v, f, step, args.warmup, w.dt)
-        step += args.warmup
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        R.rbsog_step(s.h, x, v, f, step, args.steps, w.dt)
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t0
-        step += args.steps
-        R.rbsog_check(s.h)
-        res = {"value": w.N * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps}
-        # per-kernel HIP events over a second pass of the same number of steps
-        if not args.no_roofline:
-            R.rbsog_timing_enable(s.h, True)
-            R.rbsog_step(s.h, x, v, f, step, args.steps, w.dt)
-            step += args.steps
-            res["kernels"] = {k: {"ms_per_launch": (t / n if n else 0.0), "launches": n}
-                              for k, (t, n) in R.rbsog_timing_read(s.h).items()}
-            # the structure-factor partial sums as a launch of their own (the
-            # standalone entry point; in a step they share the near launch)
-            rho = torch.empty((w.P, 2), dtype=torch.float64, device=dev)
-            for k in range(args.steps):
-                R.rbsog_compute_rho(s.h, step + k, x, rho)
-            t_rho, n_rho = R.rbsog_timing_read(s.h)["rho_partial"]
-            res["rho_partial_standalone_ms"] = t_rho / n_rho if n_rho else 0.0
-            R.rbsog_timing_enable(s.h, False)
-        res["x"], res["step"] = x, step
-        # force-only rate: one evaluation (cell order and lists rebuilt, modes,
-        # structure factors, near and far field) per call at the final state
-        fo = torch.empty_like(x)
-        R.rbsog_compute_forces(s.h, step, x, fo)
-        torch.cuda.synchronize()
-        nf = max(10, args.steps // 4)
-        t0 = time.perf_counter()
-        for k in range(nf):
-            R.rbsog_compute_forces(s.h, step + k, x, fo)
-        torch.cuda.synchronize()
-        res["force_only"] = w.N * nf / (time.perf_counter() - t0)
-        # energy drift over NVE steps from the equilibrated state (untimed)
-        if args.drift_steps > 0:
-            xd, vd, fd = x_eq.clone(), v_eq.clone(), torch.empty_like(x_eq)
-            R.rbsog_compute_forces(s.h, step_eq, xd, fd)
-            ehd = torch.zeros((args.drift_steps, 6), dtype=torch.float64, device=dev)
-            R.rbsog_step(s.h, xd, vd, fd, step_eq, args.drift_steps, w.dt, ehd)
-            R.rbsog_check(s.h)
-            res["drift"] = energy_drift(ehd.sum(dim=1).cpu().numpy(), w.dt, w.N * w.kT)
-            if prec == R.RBSOG_FP64 and not args.no_fullk_energy:
-                # the same trajectory's energy with the whole lattice (no sampling
-                # noise) at steps 0, 25, 50, 75, 100
-                sfk = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, precision=R.RBSOG_FP64, full_k=True,
-                               device=dev)
-                mt = torch.tensor(st.m, device=dev)
-                xd, vd, fd = x_eq.clone(), v_eq.clone(), torch.empty_like(x_eq)
-                R.rbsog_compute_forces(s.h, step_eq, xd, fd)
-                ftmp = torch.empty_like(xd)
-                e6 = torch.zeros(6, dtype=torch.float64, device=dev)
-                efull, sd = [], step_eq
-                for c in range(5):
-                    R.rbsog_compute_forces(sfk.h, 0, xd, ftmp, None, e6)
-                    ke = 0.5 * float((mt * (vd * vd).sum(dim=0)).sum())
-                    efull.append((float(e6[:5].sum()) + ke) / (w.N * w.kT))
-                    if c < 4:
-                        R.rbsog_step(s.h, xd, vd, fd, sd, 25, w.dt)
-                        sd += 25
-                tt = w.dt * 25 * np.arange(5)
-                slope = float(np.polyfit(tt, np.array(efull), 1)[0])
-                res["drift"]["full_k"] = {"steps": [0, 25, 50, 75, 100], "E_NkT": efull,
-                                          "slope_NkT_per_time": slope, "lattice_points": R.rbsog_get_info(sfk.h).nlat}
-                if args.noise_evals > 0:
-                    res["drift"]["noise"] = force_noise(R, s.h, sfk.h, x_eq, mt, w, args.noise_evals)
-                del sfk
-        results[name] = res
-        log(f"[bench] {name}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.3f} ms/step, "
-            f"force-only {res['force_only']:.4g}/s, drift {res.get('drift')}")
-
-    # ---- force error at the final FP64 state, against the FP64 oracle ----
-    import oracle
-    o = oracle.sog_auto(w.lam, w.r_c, w.eps)
-    xf = results["fp64"]["x"]
-    xh = xf.cpu().numpy()
-    ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
-    rng = np.random.default_rng(1)
-    idx = np.sort(rng.choice(w.N, 512, replace=False))
-    estep = results["fp64"]["step"] + 1
-    n3, coef = ref.draw(estep)
-    rho = oracle.rho(xh, st.q, w.L, n3)
-    fno = oracle.near_subset(xh, st.q, w.L, o, idx)
-    ffo = oracle.far_rb(xh[:, idx], st.q[idx], w.L, n3, coef, rho)
-    sog_o = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
-    errs = {}
-    for name, prec in (("fp64", R.RBSOG_FP64), ("mixed", R.RBSOG_MIXED)):
-        s = R.System(st.q, st.m, w.L, sog_o, w.kT, w.P, seed=w.seed, precision=prec, device=dev)
-        fg = torch.empty_like(xf)
-        fng = torch.empty_like(xf)
-        R.rbsog_compute_forces(s.h, estep, xf, fg, fng)
-        torch.cuda.synchronize()
-        fg, fng = fg.cpu().numpy()[:, idx], fng.cpu().numpy()[:, idx]
-        rr = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
-        errs[name] = {"total": rr(fg, fno + ffo), "near": rr(fng, fno), "far": rr(fg - fng, ffo)}
-        log(f"[bench] {name} force rel RMS vs oracle: {errs[name]}")
-
-    # ---- roofline of the dominant kernel (FP64 path) ----
-    roofline = None
-    if not args.no_roofline:
-        kern = results["fp64"]["kernels"]
-        dom = max(kern, key=lambda k: kern[k]["ms_per_launch"] * kern[k]["launches"])
-        ms = kern[dom]["ms_per_launch"]
-        npairs = count_pairs(xh, w.L, w.r_c)
-        work = {
-            "far": w.N * w.P * FLOPS_FAR_PER_IK,
-            "rho_partial": w.N * w.P * FLOPS_RHO_PER_IK,
-            "near": npairs * flops_near_per_pair(sog.n),
-        }
-        # the structure-factor partials run inside the near launch (its first
-        # workgroups) when no launch of their own was timed: that launch does both
-        fused = kern["near"]["launches"] > 0 and kern["rho_partial"]["launches"] == 0
-        if fused:
-            work["near"] += work.pop("rho_partial")
-        if dom in work:
-            achieved = work[dom] / (ms * 1e-3) / 1e12
-            roofline = {"kernel": "near+rho_partial" if fused and dom == "near" else dom, "bound": "alu",
-                        "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(dom),
-                        "ms_per_launch": ms, "flops_per_launch": work[dom]}
-        log(f"[bench] kernels (fp64): " + ", ".join(f"{k} {v['ms_per_launch']:.4f} ms" for k, v in kern.items()))
-        log(f"[bench] near pairs {npairs} ({npairs / w.N:.1f} per particle)")
-        results["fp64"]["algorithmic_tflops"] = {("near+rho_partial" if fused and k == "near" else k):
-                                                 work[k] / (kern[k]["ms_per_launch"] * 1e-3) / 1e12
-                                                 for k in work if kern[k]["ms_per_launch"] > 0}
-        ms_rho = results["fp64"].get("rho_partial_standalone_ms", 0.0)
-        if ms_rho > 0:
-            results["fp64"]["algorithmic_tflops"]["rho_partial (standalone launch)"] = (
-                w.N * w.P * FLOPS_RHO_PER_IK / (ms_rho * 1e-3) / 1e12)
-
-    # ---- the oracle on this machine's host cores (bounded sample) ----
+    # ---- headline: N = 1e6, kappa = 0.1, r_c = 5, P = 500, Gamma = 0.1 and 100 ----
+    gammas = [float(g) for g in args.gammas.split(",") if g]
+    base = workloads.OCP_1M_WEAK
+    runs, t_tot = {}, {"fp64": 0.0, "mixed": 0.0}
+    ps_tot = 0
     cpu = None
-    if not args.no_cpu_baseline:
-        xo = x_eq.cpu().numpy().copy()
-        vo = v_eq.cpu().numpy().copy()
-        fo, _, _ = ref.force(xo, step_eq)
-        t0 = time.perf_counter()
-        ref.run(xo, vo, fo, step_eq, 1, w.dt)
-        t1 = time.perf_counter() - t0
-        k = max(1, min(1000, int(args.cpu_seconds / max(t1, 1e-6)) - 1))
-        t0 = time.perf_counter()
-        ref.run(xo, vo, fo, step_eq + 1, k, w.dt)
-        tk = time.perf_counter() - t0 + t1
-        cpu = {"value": w.N * (k + 1) / tk, "unit": "particle-steps/s", "cores": oracle.num_threads(),
-               "kind": "oracle", "sample": f"{k + 1} velocity-Verlet steps of the same workload (FP64, OpenMP)"}
-        log(f"[bench] oracle: {cpu['value']:.4g} particle-steps/s on {cpu['cores']} threads ({tk:.1f} s)")
+    headline_kernels = None
+    for g in gammas:
+        w = workloads.Workload(f"ocp_n{base.N}_k{base.kappa:g}_g{g:g}", N=base.N, kappa=base.kappa, gamma=g,
+                               r_c=base.r_c, P=base.P, steps=args.steps,
+                               seed=workloads.OCP_1M_WEAK.seed if g == 0.1 else
+                               (workloads.OCP_1M_STRONG.seed if g == 100 else base.seed))
+        st = workloads.make_state(w)
+        o = oracle.sog_auto(w.lam, w.r_c, w.eps)
+        sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+        log(f"[bench] {w.name}: N={w.N} L={w.L:.4f} P={w.P} SOG M1={sog.M1} M2={sog.M2} "
+            f"err={sog.max_err:.2e}")
+        rr = {}
+        for name, prec in (("fp64", R.RBSOG_FP64), ("mixed", R.RBSOG_MIXED)):
+            res = run_workload(R, w, st, sog, prec, args.steps, args.warmup, dev, skin=args.skin)
+            E = res["ehist"].sum(axis=1)
+            res["drift"] = {"all": energy_drift(E, w.dt, w.N * w.kT),
+                            "second_half": energy_drift(E[args.steps // 2:], w.dt, w.N * w.kT)}
+            info = res["info"]
+            res["lists"] = {"skin": info.skin, "nf": info.nf, "near_capacity": info.near_capacity}
+            t_tot[name] += res["elapsed_s"]
+            log(f"[bench] {w.name} {name}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.3f} ms/step; "
+                f"kernels " + ", ".join(f"{k} {v['ms_per_step'] * 1e3:.0f} us" for k, v in res["kernels"].items()))
+            rr[name] = res
+        ps_tot += w.N * args.steps
+        if not args.no_force_check:
+            rr["force_rel_rms"] = force_check(R, oracle, w, st, o, rr["fp64"]["x"], rr["fp64"]["step"] + 1, dev)
+            log(f"[bench] {w.name} force error vs oracle: {rr['force_rel_rms']}")
+        if g == gammas[0]:
+            headline_kernels = (w, rr["fp64"]["kernels"], rr["fp64"]["x"].cpu().numpy(), sog.n)
+            if not args.no_cpu_baseline:
+                # the oracle on this machine's host cores: a bounded number of
+                # velocity-Verlet steps of the same workload from the same state
+                ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
+                xo, vo = st.x.copy(), st.v.copy()
+                t0 = time.perf_counter()
+                fo, _, _ = ref.force(xo, 0)
+                t_f = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                ref.run(xo, vo, fo, 0, args.cpu_steps, w.dt)
+                tk = time.perf_counter() - t0
+                hi = host_info()
+                cpu = {"value": w.N * args.cpu_steps / tk, "unit": "particle-steps/s",
+                       "cores": oracle.num_threads(), "kind": "oracle",
+                       "sample": f"{args.cpu_steps} FP64 velocity-Verlet steps of {w.name} from the seeded state "
+                                 f"(OpenMP; one force evaluation {t_f:.1f} s)",
+                       "nproc": hi["nproc"], "cpu_model": hi["cpu_model"], "seconds": tk}
+                log(f"[bench] oracle: {cpu['value']:.4g} particle-steps/s on {cpu['cores']} threads "
+                    f"({hi['cpu_model']}, nproc {hi['nproc']}; {tk:.1f} s)")
+        runs[f"gamma_{g:g}"] = {"N": w.N, "kT": w.kT, "seed": w.seed,
+                                "fp64": strip(rr["fp64"]), "mixed": strip(rr["mixed"]),
+                                "force_rel_rms": rr.get("force_rel_rms")}
+        for name in ("fp64", "mixed"):
+            rr[name].pop("system", None)
+        del rr
+        torch.cuda.empty_cache()
 
-    r64 = results["fp64"]
+    # ---- roofline of the dominant kernel (FP64, first coupling) ----
+    roofline, kroof = None, {}
+    if headline_kernels is not None:
+        w, kern, xh, M = headline_kernels
+        npairs = count_pairs(xh, w.L, w.r_c)
+        near_slots = npairs * slots_pair(M, prices)
+        rho_slots = w.N * w.P * slots_rho(prices)
+        fused_rho = kern.get("rho_partial") is None
+        work = {
+            "near": near_slots + (rho_slots if fused_rho else 0.0),
+            "far": w.N * w.P * slots_far(prices),
+            "nlist": canonical_candidates(w.N, w.L, w.r_c) * SLOTS_CANDIDATE,
+        }
+        if not fused_rho:
+            work["rho_partial"] = rho_slots
+        kroof = rooflines(kern, work)
+        dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+        if dom in kroof:
+            roofline = dict(kroof[dom], kernel=dom + ("+rho_partial" if dom == "near" and fused_rho else ""),
+                            bound="alu", traffic=measured_traffic(dom))
+            vc = measured_valu(dom)
+            if vc is not None:
+                roofline["valu_counters"] = vc
+        log(f"[bench] near pairs {npairs} ({npairs / w.N:.1f} per particle); dominant kernel {dom}")
+
+    n_runs = len(gammas)
     out = {
         "metric": METRIC,
-        "value": r64["value"],
+        "value": ps_tot / t_tot["fp64"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r64["ms_per_step"],
+        "ms_per_step": 1e3 * t_tot["fp64"] / (n_runs * args.steps),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "N": w.N, "kappa": w.kappa, "gamma": w.gamma, "r_c": w.r_c, "P": w.P,
-                   "eps": w.eps, "dt": w.dt, "n_gauss": sog.n, "preequilibration_steps": args.preeq,
-                   "force_rel_rms": errs["fp64"]},
-        "mixed": {"value": results["mixed"]["value"], "ms_per_step": results["mixed"]["ms_per_step"],
-                  "dtype": "f32 pair/phase arithmetic, f64 accumulation", "force_rel_rms": errs["mixed"]},
-        "kernels_ms": {k: v["ms_per_launch"] for k, v in r64.get("kernels", {}).items()},
+        "config": {"workload": f"ocp_n1000000_k0.1_rc5_p500_" + "+".join(f"g{g:g}" for g in gammas),
+                   "N": base.N, "kappa": base.kappa, "gamma": gammas, "r_c": base.r_c, "P": base.P,
+                   "eps": base.eps, "dt": base.dt, "nve_steps_per_run": args.steps,
+                   "force_rel_rms": {k: (v["force_rel_rms"] or {}).get("fp64") for k, v in runs.items()}},
+        "mixed": {"value": ps_tot / t_tot["mixed"],
+                  "ms_per_step": 1e3 * t_tot["mixed"] / (n_runs * args.steps),
+                  "speedup_vs_fp64": t_tot["fp64"] / t_tot["mixed"],
+                  "dtype": "f32 pair/phase arithmetic, f64 positions, reduction, accumulation and integration",
+                  "force_rel_rms": {k: (v["force_rel_rms"] or {}).get("mixed") for k, v in runs.items()}},
+        "runs": runs,
         "roofline": roofline,
-        # every priced kernel against the FP64 vector peak (algorithmic flops per launch / its mean event time)
-        "kernel_rooflines": {k: {"achieved": v, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                                 "frac": v / PEAK_FP64_TFLOPS}
-                             for k, v in r64.get("algorithmic_tflops", {}).items()},
+        "kernel_rooflines": kroof,
+        "elementary_prices_fma_slots": prices,
         "cpu_baseline": cpu,
     }
-    out["force_only"] = {"fp64": results["fp64"]["force_only"], "mixed": results["mixed"]["force_only"],
-                         "unit": "particle-evaluations/s"}
-    if "drift" in results["fp64"]:
-        out["energy_drift"] = {"fp64": results["fp64"]["drift"], "mixed": results["mixed"]["drift"],
-                               "unit": "N k_B T per unit time"}
-    if not args.no_serve:
-        out["served"] = serve(args, dev, log)
-    if "kernels" in results["mixed"]:
-        out["mixed"]["kernels_ms"] = {k: v["ms_per_launch"] for k, v in results["mixed"]["kernels"].items()}
+
+    # ---- the other workloads of the suite ----
+    if not args.no_extra:
+        extra = {}
+        # N = 1000, kappa = 1, Gamma = 1, r_c = 3, P = 100, FP64, 100 steps
+        w = workloads.OCP_1K
+        st = workloads.make_state(w)
+        o = oracle.sog_auto(w.lam, w.r_c, w.eps)
+        sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+        res = run_workload(R, w, st, sog, R.RBSOG_FP64, w.steps, 20, dev, kernel_pass=False)
+        res["drift"] = energy_drift(res["ehist"].sum(axis=1), w.dt, w.N * w.kT)
+        ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
+        xo, vo = st.x.copy(), st.v.copy()
+        fo, _, _ = ref.force(xo, 0)
+        ref.run(xo, vo, fo, 0, w.steps, w.dt)
+        d = res["x"].cpu().numpy() - xo
+        d -= w.L * np.round(d / w.L)
+        res["trajectory_max_dx_vs_oracle"] = float(np.abs(d).max())
+        if not args.no_force_check:
+            res["force_rel_rms"] = force_check(R, oracle, w, st, o, res["x"], res["step"] + 1, dev)
+        extra[w.name] = strip(res)
+        log(f"[bench] {w.name}: {res['value']:.4g} particle-steps/s, trajectory |dx| {d.__abs__().max():.2e}")
+        del res
+
+        # N = 1e5, kappa = 0.5, Gamma = 10: 200 pre-equilibration steps, then FP64 and mixed
+        w = workloads.OCP_100K
+        st = workloads.make_state(w)
+        o = oracle.sog_auto(w.lam, w.r_c, w.eps)
+        sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+        s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, device=dev)
+        x = torch.tensor(st.x, device=dev)
+        v = torch.tensor(st.v, device=dev)
+        f = torch.empty_like(x)
+        R.rbsog_compute_forces(s.h, 0, x, f)
+        eh = torch.zeros((1, 6), dtype=torch.float64, device=dev)
+        ke_target = 0.5 * (3 * w.N - 3) * w.kT
+        for k in range(200):
+            R.rbsog_step(s.h, x, v, f, k, 1, w.dt, eh)
+            v.mul_(torch.sqrt(ke_target / eh[0, 5]))
+        R.rbsog_check(s.h)
+        xe, ve = x.cpu().numpy(), v.cpu().numpy()
+        del s
+        c2 = {"preequilibration_steps": 200}
+        for name, prec in (("fp64", R.RBSOG_FP64), ("mixed", R.RBSOG_MIXED)):
+            res = run_workload(R, w, st, sog, prec, w.steps, 20, dev, x0=xe, v0=ve, step0=200)
+            res["drift"] = energy_drift(res["ehist"].sum(axis=1), w.dt, w.N * w.kT)
+            c2[name] = strip(res)
+            log(f"[bench] {w.name} {name}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.4f} ms/step")
+            if name == "fp64":
+                xf, sf = res["x"], res["step"] + 1
+        if not args.no_force_check:
+            c2["force_rel_rms"] = force_check(R, oracle, w, st, o, xf, sf, dev)
+        extra[w.name] = c2
+
+        # binary mixture N = 2e5, mixed precision (and FP64 beside it), 500 steps
+        w = workloads.MIXTURE_200K
+        st = workloads.make_state(w)
+        o = oracle.sog_auto(w.lam, w.r_c, w.eps)
+        sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+        c5 = {}
+        for name, prec in (("mixed", R.RBSOG_MIXED), ("fp64", R.RBSOG_FP64)):
+            res = run_workload(R, w, st, sog, prec, w.steps, 20, dev, kernel_pass=False)
+            res["drift"] = energy_drift(res["ehist"].sum(axis=1), w.dt, w.N * w.kT)
+            c5[name] = strip(res)
+            if name == "mixed":
+                xf, sf = res["x"], res["step"] + 1
+            log(f"[bench] {w.name} {name}: {res['value']:.4g} particle-steps/s")
+        if not args.no_force_check:
+            c5["force_rel_rms"] = force_check(R, oracle, w, st, o, xf, sf, dev)
+        extra[w.name] = c5
+        if not args.no_serve:
+            extra["served"] = serve(args, dev)
+        out["extra"] = extra
     print(json.dumps(out), flush=True)
 
 

@@ -139,11 +139,19 @@ typedef struct rbsog_params {
                            and rbsog_step rebuilds them only when some particle
                            has moved more than skin/2 since the last build; < 0 =
                            default 0.125 r_c; capped so that L >= 3 (r_c + skin);
-                           0 = rebuild every step.  Results do not depend on it.
+                           0 = rebuild every step.  Results do not depend on it
+                           beyond rounding (sums taken in another order).
                            Hot systems, whose fastest particles cross skin/2 in a
                            step or two, run fastest with 0 (lists of r_c only):
-                           the default drops to 0 at the first rbsog_step when
-                           sqrt(2 ln(3N + 1) kT / m_min) dt > skin/4. */
+                           the default drops to 0 -- at an rbsog_step whose dt
+                           exceeds every earlier one, or at a served replica's
+                           admission -- when sqrt(2 ln(3N + 1) kT / m_min) dt >
+                           skin/4, and at an rbsog_step after earlier calls
+                           rebuilt the lists at more than half of at least ten
+                           steps (systems hotter than kT, such as a random
+                           start relaxing); the fine grid and list capacity are
+                           then re-derived for lists of r_c (rbsog_get_info
+                           reports the new skin, nf and near_capacity). */
     int full_k;         /* 0: random batch of P sampled modes (the method);
                            1: deterministic far field over the whole lattice,
                            coefficient Fhat(k)/V per mode (eqs. 3.5, UF without
@@ -153,7 +161,8 @@ typedef struct rbsog_params {
 
 typedef struct rbsog_handle rbsog_handle;
 
-/* Derived sizes of a created system (host copy). */
+/* Derived sizes of a created system (host copy).  skin, nf and near_capacity
+ * can change at an rbsog_step when a default skin drops to 0 (see skin). */
 typedef struct rbsog_info {
     int64_t N;
     int nc;             /* cells per axis, floor(L / r_c)                          */

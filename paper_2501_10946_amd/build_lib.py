@@ -1,6 +1,8 @@
 """Builds librbsog.so in-tree: host C++ with g++ (-ffp-contract=off, the
 sampling tables are fixed IEEE expression sequences), HIP sources with hipcc for
-gfx950 only, linked into one shared library next to this file."""
+gfx950 only, linked into one shared library next to this file.  Also builds
+libprice.so, the benchmark's measurement of FP64 elementary-function issue
+costs (not part of the force path)."""
 from __future__ import annotations
 
 import os
@@ -12,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "librbsog.so")
+PRICE_OUT = os.path.join(HERE, "libprice.so")
 BUILD = os.path.join(HERE, "_build")
 
 HOST_SRCS = ["host_sog.cpp", "host_tables.cpp", "host_near.cpp"]
@@ -47,6 +50,9 @@ def build(verbose: bool = False) -> str:
     tmp = OUT + ".tmp"
     subprocess.run([hipcc, "-shared", "--offload-arch=gfx950", "-o", tmp, *objs], check=True)
     os.replace(tmp, OUT)
+    tmp = PRICE_OUT + ".tmp"
+    subprocess.run([hipcc, *HIP_FLAGS, "-shared", os.path.join(CSRC, "price.hip"), "-o", tmp], check=True)
+    os.replace(tmp, PRICE_OUT)
     return OUT
 
 

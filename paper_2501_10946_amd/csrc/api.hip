@@ -56,6 +56,9 @@ int near_capacity(int64_t N, double L, double rl, int nf)
     return std::min(4096, std::max(8, (int)std::ceil(1.5 * expected + 16.0)));
 }
 
+// Cells per axis of the fine grid for lists of radius rl: width >= rl / 2, at least 6.
+static int fine_cells(double L, double rl) { return std::max(6, (int)std::floor(2.0 * L / rl)); }
+
 Derived derive(const rbsog_params *p, const rbsog_sog *s)
 {
     Derived d{};
@@ -64,7 +67,8 @@ Derived derive(const rbsog_params *p, const rbsog_sog *s)
     double skin = p->skin < 0.0 ? 0.125 * s->r_c : p->skin;
     skin = std::max(0.0, std::min(skin, p->L / 3.0 - s->r_c));
     d.nc = (int)std::floor(p->L / s->r_c);
-    d.nf = std::max(6, (int)std::floor(2.0 * p->L / (s->r_c + skin)));
+    d.nf = fine_cells(p->L, s->r_c + skin);
+    d.nf_tight = fine_cells(p->L, s->r_c);
     // the 5-cell stencil reaches 2 w = 2 L / nf: keep the list radius within it
     d.rl = std::min(s->r_c + skin, 2.0 * p->L / (double)d.nf);
     d.skin = std::max(0.0, d.rl - s->r_c);
@@ -80,7 +84,8 @@ Derived derive(const rbsog_params *p, const rbsog_sog *s)
 
 Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
 {
-    int ncell = std::max(d.nf * d.nf * d.nf, d.nc * d.nc * d.nc);  // either grid
+    // any grid: the coarse one, the fine one, and the fine one of a dropped skin
+    int ncell = std::max(std::max(d.nf * d.nf * d.nf, d.nf_tight * d.nf_tight * d.nf_tight), d.nc * d.nc * d.nc);
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -108,6 +113,7 @@ Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
     L.vs_old = take(sizeof(double) * 3 * (size_t)N);
     L.fs = take(sizeof(double) * 3 * (size_t)N);
     L.ms = take(sizeof(double) * (size_t)N);
+    L.ms_old = take(sizeof(double) * (size_t)N);
     const size_t nm = (size_t)d.nmodes;
     L.samp = take(sizeof(double) * 4 * (d.full_k ? nm : (size_t)P * (size_t)d.sbatch));
     L.part = take(d.full_k ? 0 : sizeof(double) * 2 * (size_t)nchunks(N, P) * (size_t)P);
@@ -117,7 +123,7 @@ Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
     L.fnear = take(sizeof(double) * 3 * kNearLanes * (size_t)N);
     L.epart = take(sizeof(double) * (size_t)near_blocks((int)N));
     L.kepart = take(sizeof(double) * (size_t)far_blocks((int)N));
-    L.flag = take(sizeof(int32_t) * 4);
+    L.flag = take(sizeof(int32_t) * 8);
     L.energy = take(sizeof(double) * 8);
     L.nbr = take(sizeof(int32_t) * (size_t)d.kp * 5 * (size_t)list_padded(N));
     L.nbr_cnt = take(sizeof(int32_t) * (size_t)N);
@@ -200,8 +206,8 @@ CellArgs cell_args(rbsog_handle *h, const CellGeom &g, const int32_t *gate, bool
     a.xs_old = h->xs_old;
     a.order_old = h->order_old;
     a.vs_old = h->vs_old;
-    a.m = h->m;
     a.ms = h->ms;
+    a.ms_old = h->ms_old;
     a.xb = h->xb;
     a.cell_id = h->cell_id;
     a.count = h->count;
@@ -390,6 +396,7 @@ int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bo
     if (!h->d.full_k) HIPCHECK(timed(h, kRhoReduce, [&] { return launch_rho_reduce(ra, h->st); }));
     FarArgs fa = far_args(h, samp, f, f_near, kick, dt);
     fa.gate_clear = gate_clear;
+    fa.rebuilds = gate_clear ? h->rebuilds : nullptr;
     if (kick && gate_raise) {
         fa.drift = 1;
         fa.dt = dt;
@@ -423,7 +430,21 @@ extern "C" int rbsog_workspace_size(const rbsog_params *p, const rbsog_sog *s, s
 extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const double *q_dev, const double *m_dev,
                             void *ws_dev, size_t ws_bytes, void *hip_stream, rbsog_handle **out)
 {
-    return create_system(p, s, q_dev, m_dev, ws_dev, ws_bytes, (hipStream_t)hip_stream, nullptr, out);
+    int rc = create_system(p, s, q_dev, m_dev, ws_dev, ws_bytes, (hipStream_t)hip_stream, nullptr, out);
+    if (rc) return rc;
+    // a system stepped by rbsog_step reads its rebuild count back (pinned host
+    // word, an event) to decide whether a default skin pays
+    rbsog_handle *h = *out;
+    if (h->skin_default) {
+        hipError_t e = hipHostMalloc((void **)&h->rb_host, sizeof(int32_t), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->rb_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            rbsog_destroy(h);
+            *out = nullptr;
+            return fail(RBSOG_EHIP, "rebuild counter: %s", hipGetErrorString(e));
+        }
+    }
+    return RBSOG_OK;
 }
 
 namespace rbsog {
@@ -473,7 +494,12 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
         return fail(RBSOG_EHIP, "reading m: %s", hipGetErrorString(e));
     }
     h->m_min = *std::min_element(qh.begin(), qh.end());
-    h->skin_checked = p->skin >= 0.0;   // only the default skin adapts
+    h->skin_default = p->skin < 0.0;   // only the default skin adapts
+    h->dt_checked = 0.0;
+    h->rb_host = nullptr;
+    h->rb_ev = nullptr;
+    h->rb_pending = false;
+    h->rb_steps = h->steps_done = 0;
     h->Q1 = q1;
     h->Q2 = q2;
     if (!(q2 > 0.0)) {
@@ -507,6 +533,7 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     h->vs_old = (double *)(w + L.vs_old);
     h->fs = (double *)(w + L.fs);
     h->ms = (double *)(w + L.ms);
+    h->ms_old = (double *)(w + L.ms_old);
     h->samp = (double4 *)(w + L.samp);
     h->part = (double2 *)(w + L.part);
     h->rho = (double2 *)(w + L.rho);
@@ -518,6 +545,7 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     h->flag = (int32_t *)(w + L.flag);
     h->gate = h->flag + 1;
     h->ticket = h->flag + 3;
+    h->rebuilds = h->flag + 4;
     h->phase = 0;
     h->samp_n = 0;
     h->energy = (double *)(w + L.energy);
@@ -555,7 +583,7 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
         }
         e = hipMemcpyAsync(h->samp, full.data(), sizeof(double) * full.size(), hipMemcpyHostToDevice, h->st);
     }
-    if (e == hipSuccess) e = hipMemsetAsync(h->flag, 0, sizeof(int32_t) * 4, h->st);
+    if (e == hipSuccess) e = hipMemsetAsync(h->flag, 0, sizeof(int32_t) * 8, h->st);
     if (e == hipSuccess) e = hipMemsetAsync(h->count, 0, L.cell_start - L.count, h->st);
     if (e == hipSuccess) e = launch_iota(h->order, (int)p->N, h->st);   // a cell order before the first build
     if (e == hipSuccess) e = hipStreamSynchronize(h->st);
@@ -669,6 +697,54 @@ extern "C" int rbsog_compute_forces(rbsog_handle *h, uint64_t step, const double
     return evaluate(h, samp, f_dev, f_near_dev, false, 0.0, energy_dev);
 }
 
+namespace rbsog {
+
+// The default skin pays off only when lists outlive several steps.  Once dt is
+// known the fastest of the 3N Maxwell velocity components, ~sqrt(2 ln 3N kT /
+// m_min), is compared with the skin: when it would cross skin/2 within two
+// steps, lists of r_c alone rebuilt every step are cheaper.  The fine grid is
+// then re-derived for the list radius r_c (more, smaller cells: the workspace
+// is sized for that grid from the start) with a list capacity for r_c, and the
+// next step rebuilds.  Results do not depend on the skin beyond the rounding
+// of sums taken in another order.
+static void drop_skin(rbsog_handle *h)
+{
+    h->d.skin = 0.0;
+    h->d.rl = h->sog.r_c;
+    h->d.nf = h->d.nf_tight;
+    h->d.kp = std::min(h->d.kp, near_capacity(h->p.N, h->p.L, h->d.rl, h->d.nf));
+    h->gf = make_geom(h->p.L, h->d.nf);
+    h->lists_valid = false;
+}
+
+bool adapt_skin(rbsog_handle *h, double dt)
+{
+    if (!h->skin_default || h->d.skin == 0.0 || !(dt > h->dt_checked) || !(h->m_min > 0.0)) return false;
+    h->dt_checked = dt;
+    const double vmax = std::sqrt(2.0 * std::log(3.0 * (double)h->p.N + 1.0) * h->p.kT / h->m_min);
+    if (!(0.5 * h->d.skin < 2.0 * vmax * dt)) return false;
+    drop_skin(h);
+    return true;
+}
+
+// The thermal estimate misses systems that run hotter than their kT (a
+// random start relaxing into a strongly coupled state heats far above it):
+// there the count of rebuilt steps decides.  After each rbsog_step the device
+// count is copied to a pinned host word behind an event; the next call reads
+// it if the copy has completed (never waiting) and drops the skin when more
+// than half of at least ten steps rebuilt their lists.
+bool adapt_skin_rebuilds(rbsog_handle *h)
+{
+    if (!h->rb_pending || !h->skin_default || h->d.skin == 0.0) return false;
+    if (hipEventQuery(h->rb_ev) != hipSuccess) return false;   // not arrived yet (or an error: keep the skin)
+    h->rb_pending = false;
+    if (h->rb_steps < 10 || 2 * (int64_t)*h->rb_host <= h->rb_steps) return false;
+    drop_skin(h);
+    return true;
+}
+
+}  // namespace rbsog
+
 extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double *f_dev, uint64_t step0, int nsteps,
                           double dt, double *energy_hist_dev)
 {
@@ -676,20 +752,8 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
     if (nsteps < 0) return fail(RBSOG_EINVAL, "nsteps must be >= 0");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RBSOG_EINVAL, "dt must be positive and finite");
     if (nsteps == 0) return RBSOG_OK;
-    // The default skin pays off only when lists outlive several steps.  At the
-    // first step (dt now known) the fastest of the 3N Maxwell velocity
-    // components, ~sqrt(2 ln 3N kT / m_min), is compared with the skin: when it
-    // would cross skin/2 within two steps, lists of r_c alone rebuilt every
-    // step are cheaper.  A smaller radius keeps the current lists valid (they
-    // cover more) and only tightens the rebuild test; results do not change.
-    if (!h->skin_checked) {
-        h->skin_checked = true;
-        const double vmax = std::sqrt(2.0 * std::log(3.0 * (double)h->p.N + 1.0) * h->p.kT / h->m_min);
-        if (h->m_min > 0.0 && 0.5 * h->d.skin < 2.0 * vmax * dt) {
-            h->d.skin = 0.0;
-            h->d.rl = h->sog.r_c;
-        }
-    }
+    adapt_skin_rebuilds(h);
+    adapt_skin(h, dt);
     // the state moves into cell order (the order of the last build) for the
     // steps and back into the caller's order at the end
     PermArgs io = perm_args(h, x_dev, v_dev, f_dev);
@@ -732,6 +796,13 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         h->phase = 1 - h->phase;
     }
     HIPCHECK(timed(h, kKickDrift, [&] { return launch_state_out(io, h->st); }));
+    h->steps_done += nsteps;
+    if (h->rb_host && h->skin_default && h->d.skin > 0.0) {
+        HIPCHECK(hipMemcpyAsync(h->rb_host, h->rebuilds, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+        HIPCHECK(hipEventRecord(h->rb_ev, h->st));
+        h->rb_pending = true;
+        h->rb_steps = h->steps_done;
+    }
     return RBSOG_OK;
 }
 
@@ -783,5 +854,10 @@ extern "C" void rbsog_destroy(rbsog_handle *h)
     if (!h) return;
     if (!h->records.empty()) (void)hipStreamSynchronize(h->st);
     for (auto &e : h->events) (void)hipEventDestroy(e);
+    if (h->rb_ev) {
+        (void)hipEventSynchronize(h->rb_ev);
+        (void)hipEventDestroy(h->rb_ev);
+    }
+    if (h->rb_host) (void)hipHostFree(h->rb_host);
     delete h;
 }

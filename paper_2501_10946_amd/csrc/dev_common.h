@@ -17,6 +17,16 @@ __device__ inline int cell_coord(double x, double inv_cell, int nc)
     return (int)f;
 }
 
+// Raises *flag when cond holds in any active lane of the wave: one atomic per
+// wave (the lowest such lane), not one per lane.  Every lane of a step may
+// raise the same rebuild gate (a hot system with no skin), and same-address
+// atomics from every lane serialise in the L2.
+__device__ inline void raise_any(int32_t *flag, bool cond)
+{
+    const uint64_t m = __ballot(cond);
+    if (m != 0 && (int)(threadIdx.x & 63) == __ffsll((unsigned long long)m) - 1) atomicOr(flag, 1);
+}
+
 // Fixed-order sum over a 256-thread block; valid in thread 0.
 __device__ inline double block_sum_256(double v, double *red)
 {

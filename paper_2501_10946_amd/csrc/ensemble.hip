@@ -468,6 +468,16 @@ extern "C" int rbsog_ens_admit(rbsog_ens *s, const rbsog_params *p, const rbsog_
         drop_replica(s, slot);
         return rc;
     }
+    // the default skin meets the time step here, as at a system's first
+    // rbsog_step: a hot replica drops it (and so rebuilds at its first step,
+    // like the system stepped alone), so that both take the same steps
+    if (adapt_skin(R.h, dt)) {
+        hipError_t le = launch_set_int(R.h->gate, 1, s->st);
+        if (le != hipSuccess) {
+            drop_replica(s, slot);
+            return ens_fail_hip(le, "raising the replica's rebuild gate");
+        }
+    }
     R.h->samp_n = 0;
     if (!R.mixed && R.h->sd.poly) R.ng = 9;
     R.e_adm = s->E;

@@ -41,6 +41,7 @@ __device__ inline void cell_ids_body(const CellArgs &a, int b)
     // it writes the new one in place
     a.xs_old[p] = r;
     a.order_old[p] = a.order[p];
+    a.ms_old[p] = a.ms[p];
     if (a.vs)
         for (int d = 0; d < 3; ++d) a.vs_old[d * a.N + p] = a.vs[d * a.N + p];
     int nc = a.g.nc;
@@ -165,7 +166,7 @@ __device__ inline void rank_body(const CellArgs &a, int b)
     const double4 row = a.xs_old[p];
     a.xs[pn] = row;
     a.order[pn] = key;
-    a.ms[pn] = a.m[key];
+    a.ms[pn] = a.ms_old[p];
     a.xb[pn] = row.x;
     a.xb[a.N + pn] = row.y;
     a.xb[2 * a.N + pn] = row.z;
@@ -181,8 +182,8 @@ RBSOG_KERNELS(rank, CellArgs, kBlock)
 
 static bool cell_args_ok(const CellArgs &a)
 {
-    return a.N >= 1 && a.g.nc >= 1 && a.xs && a.order && a.xs_old && a.order_old && (!a.vs || a.vs_old) && a.m &&
-           a.ms && a.xb && a.cell_id && a.count && a.cell_start && a.fill && a.tmp && a.tile_sum && a.ticket;
+    return a.N >= 1 && a.g.nc >= 1 && a.xs && a.order && a.xs_old && a.order_old && (!a.vs || a.vs_old) &&
+           a.ms && a.ms_old && a.xb && a.cell_id && a.count && a.cell_start && a.fill && a.tmp && a.tile_sum && a.ticket;
 }
 
 hipError_t launch_cell_build(const CellArgs &a, hipStream_t st)
@@ -231,8 +232,8 @@ __device__ inline void kick_drift_body(const KickDriftArgs &a, int b)
     double d2 = kick_drift_row(x, v, f, hm, a.dt, a.L, a.inv_L, a.xb, a.N, p, &bad);
     for (int d = 0; d < 3; ++d) a.vs[d * a.N + p] = v[d];
     a.xs[p] = make_double4(x[0], x[1], x[2], r.w);
-    if (bad) atomicOr(a.flag, 1);
-    if (!(d2 <= a.half_skin2)) atomicOr(a.gate, 1);
+    raise_any(a.flag, bad);
+    raise_any(a.gate, !(d2 <= a.half_skin2));
 }
 
 RBSOG_KERNELS(kick_drift, KickDriftArgs, kBlock)

@@ -52,7 +52,10 @@ __device__ inline void far_body(const FarArgs &a, int b)
     const int t = threadIdx.x;
     const int g = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;   // g is uniform per wave
     const int p = b * 64 + lane;
-    if (a.gate_clear && b == 0 && t == 0) *a.gate_clear = 0;
+    if (a.gate_clear && b == 0 && t == 0) {
+        if (a.rebuilds && *a.gate_clear) *a.rebuilds += 1;
+        *a.gate_clear = 0;
+    }
     const bool live = p < a.N;
     double4 pi = live ? a.xs[p] : make_double4(0.0, 0.0, 0.0, 0.0);
     // phases in revolutions (mixed) or 1/128 revolutions (FP64 table path)
@@ -133,7 +136,7 @@ __device__ inline void far_body(const FarArgs &a, int b)
                 a.f_near_out[2 * a.N + i] = fnz;
             }
         }
-        if (!isfinite(fx + fy + fz)) atomicOr(a.flag, 1);
+        raise_any(a.flag, !isfinite(fx + fy + fz));
         if (a.vs) {
             double mi = a.ms[p];
             double hm = a.half_dt / mi;
@@ -148,8 +151,8 @@ __device__ inline void far_body(const FarArgs &a, int b)
                 vy = v[1];
                 vz = v[2];
                 a.xs_next[p] = make_double4(x[0], x[1], x[2], pi.w);
-                if (bad) atomicOr(a.flag, 1);
-                if (!(d2 <= a.half_skin2)) atomicOr(a.gate_raise, 1);
+                raise_any(a.flag, bad);
+                raise_any(a.gate_raise, !(d2 <= a.half_skin2));
             }
             a.vs[p] = vx;
             a.vs[a.N + p] = vy;

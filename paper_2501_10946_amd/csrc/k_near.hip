@@ -277,35 +277,33 @@ __device__ inline double readlane_f64(double v, int l)
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// One wave lists the neighbours of the particles of two x-adjacent cells (the
-// "pair"; the last cell of a row of odd length alone).  Its candidates are the
-// particles of the pair's window: 25 rows (dz, dy = -2..2) of the cells x0 - 2
-// .. x1 + 2, each row one contiguous range of the cell order or two where it
-// wraps.  Lanes take 64 consecutive candidates at a time (a row piece found by
-// a binary search of the pieces' prefix sums, loads coalesced along the rows);
-// for each home particle in turn every lane tests its candidate, and the
-// accepted ones are appended in lane order (ballot / mbcnt) to that particle's
-// list.  So a particle's list holds the candidates within the list radius in
-// window order — planes, rows, wrap pieces, cell order — the same list, entry
-// for entry, as a walk of the particle's own 5 x 5 x 5 cells: the pair window's
-// extra cells lie at least 2 w >= r_c + skin away from the other cell's
-// particles.  A particle with more than 5 kp neighbours gets the count
-// 5 kp + 1 (its lanes then walk the cells in the evaluation).
-__device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
+// The window of cell pair q: two x-adjacent cells of the fine grid (the last
+// cell of a row of odd length alone) hold the home particles [h_beg, h_end);
+// their candidates are the particles of 25 rows (dz, dy = -2..2) of the cells
+// x0 - 2 .. x1 + 2, each row one contiguous range of the cell order or two
+// where it wraps, 50 pieces at most.  Lane l < 50 describes piece l; the
+// pieces' starts, exclusive prefix sums of their lengths and image-shift codes
+// (0/1/2 for -L/0/+L per axis) go to the wave's rows of pstart/ppref/pcode.
+// Returns false, uniformly over the wave, when q is past the last pair or the
+// pair has no home particle.  A window holds each particle at most once: it is
+// at most 6 cells wide in x and 5 in y and z, and the grid has at least 6.
+struct PairWindow {
+    int h_beg, h_end, total;
+};
+
+__device__ inline bool pair_window(const NearArgs &a, int q, int32_t *pstart, int32_t *ppref, int32_t *pcode,
+                                   PairWindow &win)
 {
-    __shared__ int32_t pstart[kListWaves][64], ppref[kListWaves][64], pcode[kListWaves][64];
     const int lane = threadIdx.x & 63;
     const int nf = a.g.nc, half = (nf + 1) >> 1;
-    if (q >= nf * nf * half) return;   // uniform per wave; no workgroup barrier below
+    if (q >= nf * nf * half) return false;
     const int row = q / half, ix = q - row * half;
     const int cz = row / nf, cy = row - cz * nf;
     const int x0 = 2 * ix, x1 = min(x0 + 1, nf - 1);
     const int cbase = (cz * nf + cy) * nf;
-    const int h_beg = a.cell_start[cbase + x0], h_end = a.cell_start[cbase + x1 + 1];
-    if (h_beg >= h_end) return;
-    // piece `lane` (< 50) of the window: row r = lane / 2 (dz = r / 5 - 2,
-    // dy = r mod 5 - 2), piece lane mod 2 of its x-cells x0 - 2 .. x1 + 2 (the
-    // part left of the wrap first); image shift codes 0/1/2 for -L/0/+L
+    win.h_beg = a.cell_start[cbase + x0];
+    win.h_end = a.cell_start[cbase + x1 + 1];
+    if (win.h_beg >= win.h_end) return false;
     int ps = 0, plen = 0, pc = 0;
     if (lane < 2 * 25) {
         const int r = lane >> 1, k = lane & 1;
@@ -336,13 +334,55 @@ __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
         int u = __shfl_up(incl, off);
         if (lane >= off) incl += u;
     }
-    const int total = __shfl(incl, 63);
-    pstart[wv][lane] = ps;
-    ppref[wv][lane] = incl - plen;
-    pcode[wv][lane] = pc;
+    win.total = __shfl(incl, 63);
+    pstart[lane] = ps;
+    ppref[lane] = incl - plen;
+    pcode[lane] = pc;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return true;
+}
+
+// Candidate c (< the window's total) of a window: its particle index j and the
+// image shift (sx, sy, sz) its piece is seen under.
+__device__ inline int window_candidate(const int32_t *pstart, const int32_t *ppref, const int32_t *pcode, int c,
+                                       double L, double &sx, double &sy, double &sz)
+{
+    // the last piece whose prefix is <= c (an empty piece shares the prefix
+    // of the next, so it is never the one found)
+    int lo = 0, n = 64;
+    while (n > 0) {
+        int h2 = n >> 1;
+        if (ppref[lo + h2] <= c) { lo += h2 + 1; n -= h2 + 1; }
+        else n = h2;
+    }
+    const int l = lo - 1;
+    const int code = pcode[l];
+    sx = shift_of(code & 3, L);
+    sy = shift_of((code >> 2) & 3, L);
+    sz = shift_of(code >> 4, L);
+    return pstart[l] + (c - ppref[l]);
+}
+
+// One wave lists the neighbours of the home particles of cell pair q.  Lanes
+// take 64 consecutive candidates of the window at a time (loads coalesced
+// along the rows); for each home particle in turn every lane tests its
+// candidate, and the accepted ones are appended in lane order (ballot /
+// mbcnt) to that particle's list.  So a particle's list holds the candidates
+// within the list radius in window order — planes, rows, wrap pieces, cell
+// order — the same list, entry for entry, as a walk of the particle's own
+// 5 x 5 x 5 cells: the pair window's extra cells lie at least 2 w >= r_c +
+// skin away from the other cell's particles.  A particle with more than 5 kp
+// neighbours gets the count 5 kp + 1 (its lanes then walk the cells in the
+// evaluation).
+__device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
+{
+    __shared__ int32_t pstart[kListWaves][64], ppref[kListWaves][64], pcode[kListWaves][64];
+    const int lane = threadIdx.x & 63;
+    PairWindow win;
+    if (!pair_window(a, q, pstart[wv], ppref[wv], pcode[wv], win)) return;   // uniform per wave
+    const int h_beg = win.h_beg, h_end = win.h_end, total = win.total;
     const int rows = kNearPlanes * a.kp;
     const double L = a.g.L;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));   // lanes under this one
@@ -359,20 +399,7 @@ __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
             double sx = 0.0, sy = 0.0, sz = 0.0;
             double4 qj = make_double4(0.0, 0.0, 0.0, 0.0);
             if (live) {
-                // the last piece whose prefix is <= c (an empty piece shares the
-                // prefix of the next, so it is never the one found)
-                int lo = 0, n = 64;
-                while (n > 0) {
-                    int h2 = n >> 1;
-                    if (ppref[wv][lo + h2] <= c) { lo += h2 + 1; n -= h2 + 1; }
-                    else n = h2;
-                }
-                const int l = lo - 1;
-                j = pstart[wv][l] + (c - ppref[wv][l]);
-                const int code = pcode[wv][l];
-                sx = shift_of(code & 3, L);
-                sy = shift_of((code >> 2) & 3, L);
-                sz = shift_of(code >> 4, L);
+                j = window_candidate(pstart[wv], ppref[wv], pcode[wv], c, L, sx, sy, sz);
                 qj = a.xs[j];
             }
             for (int h = hb; h < he; ++h) {

@@ -73,8 +73,8 @@ struct CellArgs {
     double4 *xs_old;       // [N] snapshot of xs (id pass -> rank pass)
     int32_t *order_old;    // [N] snapshot of order
     double *vs_old;        // SoA [3][N] snapshot of vs (when vs)
-    const double *m;       // [N] caller-order masses
-    double *ms;            // [N] masses in the new cell order
+    double *ms;            // [N] masses in cell order (valid in the old order on entry), rewritten
+    double *ms_old;        // [N] snapshot of ms
     double *xb;            // SoA [3][N] positions at the build, new cell order
     int32_t *cell_id;      // [N] by current cell position
     int32_t *count;        // [ncell]
@@ -268,6 +268,7 @@ struct FarArgs {
     const double2 *tab;        // [kPhaseTab] (sin, cos)(2 pi j / kPhaseTab) (FP64 path)
     SinCosShort ss;
     int32_t *gate_clear;       // null, or a rebuild gate to clear (nothing later in the step reads it)
+    int32_t *rebuilds;         // null, or a count of the steps whose gate was raised (with gate_clear)
     // With drift != 0 the kernel also applies the next step's first half-kick
     // and drift to the cell-order rows (the drift kernel's arithmetic, fused;
     // single systems only, the ensemble's far kernel ignores it):

@@ -26,7 +26,7 @@ constexpr size_t kAlign = 256;
 // Offsets of every buffer inside the workspace.
 struct Layout {
     size_t lattice, cdf, coef, first, size;
-    size_t cell_id, count, cell_start, fill, tmp, order, order_old, xs, xs_old, tile_sum, xb, vs, vs_old, fs, ms;
+    size_t cell_id, count, cell_start, fill, tmp, order, order_old, xs, xs_old, tile_sum, xb, vs, vs_old, fs, ms, ms_old;
     size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_cnt, tab;
     size_t total;
 };
@@ -38,6 +38,7 @@ struct Layout {
 struct Derived {
     double skin, rl;   // neighbour-list skin and radius r_c + skin
     int nc, nf;        // coarse and fine cells per axis
+    int nf_tight;      // fine cells per axis of lists of radius r_c alone (the grid a dropped skin uses; >= nf)
     int mmax;
     int64_t nlat;
     int kp;            // neighbour-list capacity per (particle, chunk)
@@ -76,7 +77,7 @@ struct rbsog_handle {
     // views into the workspace
     int32_t *lattice, *first, *size, *cell_id, *count, *cell_start, *fill, *tmp, *order, *order_old, *flag, *tile_sum;
     double *cdf, *coef, *eF, *fnear, *epart, *kepart, *energy, *xb;
-    double *vs, *vs_old, *fs, *ms;   // the stepped state in cell order (with xs)
+    double *vs, *vs_old, *fs, *ms, *ms_old;   // the stepped state in cell order (with xs)
     double4 *xs, *xs_old, *samp;
     double2 *part, *rho, *gk, *tab;
     int32_t *nbr, *nbr_cnt;
@@ -86,7 +87,13 @@ struct rbsog_handle {
     int phase;           // which gate word the next step uses
     bool lists_valid;    // cell order and lists in the workspace belong to the fine grid
     double m_min;        // lightest mass (host copy, for the default skin's thermal check)
-    bool skin_checked;   // the default skin has been checked against the first step's dt
+    bool skin_default;   // the skin is the library's default (only a default skin adapts)
+    double dt_checked;   // largest time step the default skin has been checked against
+    int32_t *rebuilds;   // device: steps of rbsog_step whose lists were rebuilt (since creation)
+    int32_t *rb_host;    // pinned host copy of it, read back after each rbsog_step
+    hipEvent_t rb_ev;    // completes when rb_host holds the count of rb_steps steps
+    bool rb_pending;
+    int64_t rb_steps, steps_done;
     uint64_t samp_step;  // first step of the modes in samp, with samp_n steps drawn
     int samp_n;
     // per-kernel event timing (rbsog_timing_enable)
@@ -137,6 +144,16 @@ FarArgs far_args(rbsog_handle *h, const double4 *samp, double *f, double *f_near
 EnergyArgs energy_args(rbsog_handle *h, double *out, bool kick);
 // cell order + lists of the fine grid from the rows in xs (gated or not)
 int prepare(rbsog_handle *h, const int32_t *gate, bool carry_v);
+// The default skin against the time step dt: when the fastest thermal velocity
+// component would carry a particle across skin/2 within two steps, the skin
+// drops to 0 and the fine grid and list capacity are re-derived for lists of
+// r_c alone (inside the same workspace; the next build is forced).  Checked
+// again whenever dt exceeds every earlier dt; returns true when it dropped.
+bool adapt_skin(rbsog_handle *h, double dt);
+// The same drop when the lists of the last rbsog_step calls were rebuilt at
+// more than half their steps (read back without waiting; checked when the
+// count of a previous call has arrived).
+bool adapt_skin_rebuilds(rbsog_handle *h);
 // rbsog_create; with lattice_dev (the packed lattice up to at least the
 // system's m_max, owned by the caller) the workspace holds no lattice copy
 int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev, const double *m_dev, void *ws_dev,

@@ -67,6 +67,13 @@ def mixed_set():
         Req(W("e_b", N=2600, kappa=0.5, gamma=10.0, r_c=4.0, P=200, seed=32), 1, R.RBSOG_MIXED, 20),
         Req(W("e_c", N=1500, kappa=2.0, gamma=0.5, r_c=4.0, P=37, seed=33), 2, R.RBSOG_FP64, 7),
         Req(W("e_d", N=900, kappa=0.2, gamma=3.0, r_c=4.0, P=300, seed=34), 3, R.RBSOG_MIXED, 15),
+        # hot (k_B T = 20): the default skin drops to 0 at admission, as at the
+        # first step of the system stepped alone
+        Req(W("e_hot", N=1500, kappa=1.0, gamma=0.05, r_c=4.0, P=200, seed=35), 4, R.RBSOG_MIXED, 10),
+        # long screening length: seven Gaussians, mixed precision
+        Req(W("e_k01", N=4000, kappa=0.1, gamma=1.0, r_c=4.0, P=200, seed=36), 5, R.RBSOG_MIXED, 8),
+        # the largest request size of the served workload
+        Req(W("e_big", N=40000, kappa=0.5, gamma=10.0, r_c=4.0, P=200, seed=37), 6, R.RBSOG_FP64, 6),
     ]
 
 
@@ -105,9 +112,10 @@ def run_ensemble(reqs, late, budget=1 << 30, max_slots=8):
 
 def test_ensemble_equals_alone(dev):
     reqs = mixed_set()
-    print("\n[ensemble] 4 replicas, one admitted late", flush=True)
-    out = run_ensemble(reqs, late={2})
-    assert sorted(out) == [0, 1, 2, 3]
+    assert reqs[5].sog.n == 7
+    print(f"\n[ensemble] {len(reqs)} replicas, two admitted late", flush=True)
+    out = run_ensemble(reqs, late={2, 4})
+    assert sorted(out) == list(range(len(reqs)))
     for i, r in enumerate(reqs):
         x, v, e = out[i]
         xa, va, ea = r.alone(dev)

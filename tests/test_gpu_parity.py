@@ -23,6 +23,26 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
+PER_ITEM = 10.0   # no single particle (or mode) may be off by more than 10x the RMS tolerance
+
+
+def assert_close(a, b, tol, what="", per=PER_ITEM):
+    """Relative RMS of a - b over all components within tol, and the largest
+    per-item error (a particle of a [3, N] force array, a mode of a [P, 2]
+    structure-factor array) within per * tol of the RMS item magnitude of b.
+    Comparisons after a run of steps take a larger `per`: the two states then
+    differ by the trajectory's rounding, which the steep pair force of a close
+    pair magnifies for that particle alone."""
+    a, b = np.asarray(a), np.asarray(b)
+    r = rel(a, b)
+    assert r <= tol, f"{what}: relative RMS {r:.3e} > {tol:.1e}"
+    axis = 0 if (a.ndim == 2 and a.shape[0] == 3) else -1
+    d = np.linalg.norm(a - b, axis=axis)
+    scale = float(np.sqrt(np.mean(np.linalg.norm(b, axis=axis) ** 2)))
+    worst = float(d.max()) / scale
+    assert worst <= per * tol, f"{what}: largest item error {worst:.3e} of the RMS magnitude"
+
+
 @pytest.fixture(scope="module")
 def dev():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
@@ -34,14 +54,14 @@ class Case:
     """One system on both sides: the oracle's SOG parameters expanded by the
     library (so both use the same coefficients bit for bit)."""
 
-    def __init__(self, dev, w: workloads.Workload, precision=0, density=0, state=None, mmax=0):
-        print(f"\n[case] {w.name} N={w.N} P={w.P} prec={precision} dens={density}", flush=True)
+    def __init__(self, dev, w: workloads.Workload, precision=0, density=0, state=None, mmax=0, skin=-1.0):
+        print(f"\n[case] {w.name} N={w.N} P={w.P} prec={precision} dens={density} skin={skin}", flush=True)
         self.w = w
         self.st = state or workloads.make_state(w)
         self.o = oracle.sog_auto(w.lam, w.r_c, w.eps)
         self.sog = R.sog_from_parameters(self.o.lam, self.o.rc, self.o.h, self.o.t0, self.o.w, self.o.M1, self.o.M2)
         self.sys = R.System(self.st.q, self.st.m, w.L, self.sog, w.kT, w.P, seed=w.seed, precision=precision,
-                            density=density, mmax=mmax, device=dev)
+                            density=density, mmax=mmax, skin=skin, device=dev)
         self.ref = oracle.System(self.st.q, self.st.m, w.L, self.o, w.kT, w.P, seed=w.seed, density=density,
                                  mmax=mmax)
         self.dev = dev
@@ -114,22 +134,27 @@ def test_rho(dev, w, precision):
         n3, coef = c.ref.draw(step)
         ro = oracle.rho(c.st.x, c.st.q, w.L, n3)
         tol = FP64_TOL if precision == 0 else MIXED_TOL
-        assert rel(rho.cpu().numpy(), ro) <= tol
+        assert_close(rho.cpu().numpy(), ro, tol, "rho")
+
+
+# the default skin, and no skin (lists of r_c, rebuilt at every step: how hot systems run)
+SKINS = [-1.0, 0.0]
 
 
 @pytest.mark.parametrize("w", SMALL, ids=lambda w: w.name)
 @pytest.mark.parametrize("precision", [0, 1])
-def test_forces_and_energy(dev, w, precision):
-    c = Case(dev, w, precision=precision)
+@pytest.mark.parametrize("skin", SKINS, ids=["skin", "noskin"])
+def test_forces_and_energy(dev, w, precision, skin):
+    c = Case(dev, w, precision=precision, skin=skin)
     tol = FP64_TOL if precision == 0 else MIXED_TOL
     for step in (0, 3):
         f, fn, e = c.forces(step)
         fo, fno, eo = c.ref.force(c.st.x, step)
         if w.N > 1:
-            assert rel(f, fo) <= tol
+            assert_close(f, fo, tol, "total")
             if np.linalg.norm(fno) > 0:
-                assert rel(fn, fno) <= tol
-            assert rel(f - fn, fo - fno) <= tol
+                assert_close(fn, fno, tol, "near")
+            assert_close(f - fn, fo - fno, tol, "far")
         else:
             assert np.abs(f - fo).max() <= 1e-12 and np.abs(fn).max() == 0.0
         for k in (0, 1):
@@ -172,20 +197,21 @@ def test_trajectory_small_ocp(dev, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_clustered_cells(dev, precision):
+@pytest.mark.parametrize("skin", SKINS, ids=["skin", "noskin"])
+def test_clustered_cells(dev, precision, skin):
     """A third of the particles packed into a cube of edge 2.5 around the box
     corner: cells there hold ~100 particles (several 64-particle home chunks
     per cell pair in the list build), the cluster wraps around every face, and
     lists are long.  Forces and energies as for the uniform cases."""
     w = workloads.Workload("cluster_n3000", N=3000, kappa=1.0, gamma=1.0, r_c=3.0, P=64, seed=77)
     st = workloads.clustered_state(w, frac=1.0 / 3.0, side=2.5)
-    c = Case(dev, w, precision=precision, state=st)
+    c = Case(dev, w, precision=precision, state=st, skin=skin)
     f, fn, e = c.forces(3)
     fo, fno, eo = c.ref.force(st.x, 3)
     tol = FP64_TOL if precision == 0 else MIXED_TOL
-    assert rel(f, fo) <= tol
-    assert rel(fn, fno) <= tol
-    assert rel(f - fn, fo - fno) <= tol
+    assert_close(f, fo, tol, "total")
+    assert_close(fn, fno, tol, "near")
+    assert_close(f - fn, fo - fno, tol, "far")
     assert abs(e[0] - eo[0]) <= tol * abs(eo[0])
 
 
@@ -227,27 +253,58 @@ def _sampled_reference(c, step, idx):
     return fn + ff, fn, rho
 
 
-@pytest.mark.parametrize("w", [workloads.OCP_100K, workloads.MIXTURE_200K, workloads.OCP_1M_STRONG],
-                         ids=lambda w: w.name)
+@pytest.mark.parametrize("w,skin", [(workloads.OCP_100K, -1.0), (workloads.MIXTURE_200K, -1.0),
+                                    (workloads.OCP_1M_WEAK, 0.0), (workloads.OCP_1M_WEAK, -1.0),
+                                    (workloads.OCP_1M_STRONG, 0.0), (workloads.OCP_1M_STRONG, -1.0)],
+                         ids=lambda v: v.name if hasattr(v, "name") else ("noskin" if v == 0 else "skin"))
 @pytest.mark.parametrize("precision", [0, 1])
-def test_full_size_sampled(dev, w, precision):
-    """At the full workload sizes, in the launch configuration the benchmark
-    times: forces on 256 sampled particles (and all structure factors) against
-    the oracle computed for those particles alone."""
-    c = Case(dev, w, precision=precision)
+def test_full_size_sampled(dev, w, skin, precision):
+    """At the full workload sizes, in the launch configurations the benchmark
+    times (the N = 1e6 plasmas step with no skin, on the finer grid of lists
+    of r_c): forces on 256 sampled particles (and all structure factors)
+    against the oracle computed for those particles alone."""
+    c = Case(dev, w, precision=precision, skin=skin)
     step = 11
     f, fn, e = c.forces(step)
     rng = np.random.default_rng(w.seed)
     idx = np.sort(rng.choice(w.N, 256, replace=False))
     fo, fno, rho_o = _sampled_reference(c, step, idx)
     tol = FP64_TOL if precision == 0 else MIXED_TOL
-    assert rel(f[:, idx], fo) <= tol
-    assert rel(fn[:, idx], fno) <= tol
-    assert rel(f[:, idx] - fn[:, idx], fo - fno) <= tol
+    assert_close(f[:, idx], fo, tol, "total")
+    assert_close(fn[:, idx], fno, tol, "near")
+    assert_close(f[:, idx] - fn[:, idx], fo - fno, tol, "far")
     rho = torch.zeros((w.P, 2), dtype=torch.float64, device=dev)
     R.rbsog_compute_rho(c.sys.h, step, c.x, rho)
     torch.cuda.synchronize()
-    assert rel(rho.cpu().numpy(), rho_o) <= tol
+    assert_close(rho.cpu().numpy(), rho_o, tol, "rho")
+
+
+def test_full_size_steps_hot(dev):
+    """The N = 1e6 weak-coupling plasma (k_B T = 10, fast particles: the default
+    skin drops to 0 at the first step and lists of r_c are rebuilt every step
+    on the finer grid) for two velocity-Verlet steps in FP64: all positions
+    agree with the oracle's steps to 1e-10, and so do the velocities (1e-9)."""
+    w = workloads.OCP_1M_WEAK
+    c = Case(dev, w)
+    assert R.rbsog_get_info(c.sys.h).skin > 0
+    x = c.x.clone()
+    v = torch.tensor(c.st.v, device=dev)
+    f = torch.empty_like(x)
+    R.rbsog_compute_forces(c.sys.h, 0, x, f)
+    nsteps = 2
+    R.rbsog_step(c.sys.h, x, v, f, 0, nsteps, w.dt)
+    R.rbsog_check(c.sys.h)
+    info = R.rbsog_get_info(c.sys.h)
+    assert info.skin == 0.0 and info.nf == int(math.floor(2 * w.L / w.r_c))
+    print("[case] oracle steps at N = 1e6", flush=True)
+    xo, vo = c.st.x.copy(), c.st.v.copy()
+    fo, _, _ = c.ref.force(xo, 0)
+    c.ref.run(xo, vo, fo, 0, nsteps, w.dt)
+    d = x.cpu().numpy() - xo
+    d -= w.L * np.round(d / w.L)
+    assert np.abs(d).max() <= 1e-10
+    assert np.abs(v.cpu().numpy() - vo).max() <= 1e-9
+    assert_close(f.cpu().numpy(), fo, FP64_TOL, "force after the steps", per=1000.0)
 
 
 def test_invalid_arguments(dev):
@@ -284,17 +341,37 @@ def test_nonfinite_flag(dev):
 
 
 @pytest.mark.parametrize("cap", [1, 3])
-def test_neighbour_list_overflow(dev, cap, monkeypatch):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_neighbour_list_overflow(dev, cap, precision, monkeypatch):
     """With the neighbour-list capacity forced tiny, every lane overflows and
-    finishes its pairs by the second walk: forces and energies unchanged."""
+    finishes its pairs by walking the cells: forces and energies unchanged,
+    right after a build (rbsog_compute_forces) and after particles have
+    drifted since the last build (steps with a skin, lists kept between
+    rebuilds)."""
     monkeypatch.setenv("RBSOG_NEAR_CAPACITY", str(cap))
     w = workloads.Workload("ragged_n2000_cap", N=2000, kappa=0.5, gamma=2.0, r_c=4.0, P=50, seed=21)
-    c = Case(dev, w)
-    for prec in (0,):
-        f, fn, e = c.forces(4)
-        fo, fno, eo = c.ref.force(c.st.x, 4)
-        assert rel(fn, fno) <= FP64_TOL and rel(f, fo) <= FP64_TOL
-        assert abs(e[0] - eo[0]) <= FP64_TOL * abs(eo[0])
+    c = Case(dev, w, precision=precision)
+    tol = FP64_TOL if precision == 0 else MIXED_TOL
+    f, fn, e = c.forces(4)
+    fo, fno, eo = c.ref.force(c.st.x, 4)
+    assert_close(fn, fno, tol, "near")
+    assert_close(f, fo, tol, "total")
+    assert abs(e[0] - eo[0]) <= tol * abs(eo[0])
+    # steps: the default skin stays (a cold plasma), so lists outlive the steps between rebuilds
+    assert R.rbsog_get_info(c.sys.h).near_capacity == cap
+    x = c.x.clone()
+    v = torch.tensor(c.st.v, device=dev)
+    ft = torch.tensor(fo, device=dev)
+    nsteps = 12
+    R.rbsog_step(c.sys.h, x, v, ft, 0, nsteps, w.dt)
+    R.rbsog_check(c.sys.h)
+    assert R.rbsog_get_info(c.sys.h).skin > 0
+    xo, vo, ffo = c.st.x.copy(), c.st.v.copy(), fo.copy()
+    c.ref.run(xo, vo, ffo, 0, nsteps, w.dt)
+    d = x.cpu().numpy() - xo
+    d -= w.L * np.round(d / w.L)
+    assert np.abs(d).max() <= (1e-10 if precision == 0 else 1e-5)
+    assert_close(ft.cpu().numpy(), ffo, tol if precision == 0 else 1e-4, "force after the steps", per=1000.0)
 
 
 @pytest.mark.parametrize("skin", [0.0, 0.3, 1.5])
@@ -388,8 +465,8 @@ def test_full_k_forces_and_energy(dev, w, precision):
     f, fn, e = outs[0]
     fo, fno, eo = ref.force(st.x, 3)
     tol = FP64_TOL if precision == 0 else MIXED_TOL
-    assert rel(f, fo) < tol
-    assert rel(f - fn, fo - fno) < tol
+    assert_close(f, fo, tol, "total")
+    assert_close(f - fn, fo - fno, tol, "far")
     assert abs(e[1] - eo[1]) <= tol * abs(eo[1])
     assert np.allclose(e[[0, 2, 3, 4]], eo[[0, 2, 3, 4]], rtol=tol, atol=0)
 
