@@ -361,6 +361,31 @@ int rbsog_ens_step_time(rbsog_ens *e, uint64_t ens_step, double *ms);
 /* Waits for the stream and frees the pool and every resident replica. */
 void rbsog_ens_destroy(rbsog_ens *e);
 
+/* ------------------------------------------------------------------------
+ * Without allocation
+ * ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * structure factors rho(k_l) = sum_j q_j exp(i k_l . r_j), k_l = 2 pi n_l / L,
+ * of P given lattice modes n_dev[P][3] (int32, device), over N particles at
+ * x_dev (SoA [3][N], caller order, device) with charges q_dev[N] (device),
+ * written to rho_dev[P][2] = (re, im) (device) -- the sums rbsog_compute_rho
+ * forms for the modes it draws, by the same kernels and group size, so the two
+ * agree for the same modes.  No handle and no workspace: the modes as the
+ * kernels read them, the rotation table, the partial sums and the reduction's
+ * outputs live in one static 64 MiB device array that each GPU the library
+ * runs on holds until the process ends; N and P whose partial sums would not
+ * fit (about ceil(N / 256) * P * 16 bytes for large N) are refused with
+ * RBSOG_EINVAL.  Calls no hipMalloc or hipFree.  The first call on a device
+ * sets up (resolves the array's address on that device and copies the 2 KB
+ * rotation table into it, synchronously) and must not be captured; later calls
+ * only enqueue kernels on hip_stream.  Every call on one GPU shares its array
+ * and overwrites what the last call left: calls that overlap on one GPU (other
+ * streams, other host threads) race.  precision: RBSOG_FP64 or RBSOG_MIXED.
+ * Errors: RBSOG_EINVAL, RBSOG_EHIP. */
+int rbsog_rho_noalloc(int64_t N, double L, const double *x_dev, const double *q_dev, int P, const int32_t *n_dev,
+                      int precision, void *hip_stream, double *rho_dev);
+
 /* Thread-local message describing the last failing call. */
 const char *rbsog_last_error(void);
 

@@ -100,6 +100,7 @@ def lib() -> C.CDLL:
                                            C.POINTER(C.c_size_t)]),
             "rbsog_ens_step_time": (C.c_int, [_p, C.c_uint64, C.POINTER(C.c_double)]),
             "rbsog_ens_destroy": (None, [_p]),
+            "rbsog_rho_noalloc": (C.c_int, [C.c_int64, C.c_double, _p, _p, C.c_int, _p, C.c_int, _p, _p]),
             "rbsog_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -239,6 +240,17 @@ def rbsog_step(h, x, v, f, step0: int, nsteps: int, dt: float, energy_hist=None)
     _check(lib().rbsog_step(h, _dptr(x, torch.float64, 3 * N), _dptr(v, torch.float64, 3 * N),
                             _dptr(f, torch.float64, 3 * N), step0, nsteps, dt,
                             _dptr(energy_hist, torch.float64, 6 * nsteps)))
+
+
+def rbsog_rho_noalloc(x, q, L: float, n, rho, precision: int = RBSOG_FP64, stream=None) -> None:
+    """Structure factors of the modes n [P, 3] (int32) into rho [P, 2], with no
+    allocation (the library's static scratch array)."""
+    import torch
+    N = q.numel()
+    P = n.shape[0]
+    _check(lib().rbsog_rho_noalloc(N, L, _dptr(x, torch.float64, 3 * N), _dptr(q, torch.float64, N), P,
+                                   _dptr(n, torch.int32, 3 * P), precision, stream or _stream(x.device),
+                                   _dptr(rho, torch.float64, 2 * P)))
 
 
 def rbsog_check(h) -> None:
