@@ -39,7 +39,8 @@ CellGeom make_geom(double L, int nc)
 }
 
 
-// kp, a fifth of a particle's list capacity (the list holds 5 kp entries):
+// kp, a fifth of a particle's list capacity (the list holds list_rows(kp), 5 kp
+// rounded up to whole blocks):
 // 1.5x the expected number of neighbours within the list radius divided by
 // five, plus 16; a particle with more neighbours walks its cells directly
 // instead, so this only sizes the fast path.  RBSOG_NEAR_CAPACITY overrides it
@@ -125,7 +126,7 @@ Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
     L.kepart = take(sizeof(double) * (size_t)far_blocks((int)N));
     L.flag = take(sizeof(int32_t) * 8);
     L.energy = take(sizeof(double) * 8);
-    L.nbr = take(sizeof(int32_t) * (size_t)d.kp * 5 * (size_t)list_padded(N));
+    L.nbr = take(sizeof(int32_t) * (size_t)list_rows(d.kp) * (size_t)list_padded(N));
     L.nbr_cnt = take(sizeof(int32_t) * (size_t)N);
     L.tab = take(sizeof(double) * 2 * kPhaseTable);
     L.total = off;

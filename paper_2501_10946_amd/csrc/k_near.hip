@@ -148,32 +148,6 @@ __device__ inline int row_ranges(const NearArgs &a, const Lane &l, int row, doub
     return n;
 }
 
-// Walk position within one range.
-struct Cursor {
-    int j, jend;
-    double bx, by, bz;      // particle position minus the image shift of the range
-};
-
-__device__ inline Cursor open_range(const Range &g, const double4 &pi, double L)
-{
-    Cursor c;
-    c.j = g.start_code & (int32_t)kIndexMask;
-    c.jend = g.end;
-    uint32_t code = (uint32_t)g.start_code >> 27;
-    c.bx = pi.x - shift_of((int)(code % 3u), L);
-    c.by = pi.y - shift_of((int)((code / 3u) % 3u), L);
-    c.bz = pi.z - shift_of((int)(code / 9u), L);
-    return c;
-}
-
-// The acceptance test of a candidate within radius sqrt(R2).
-__device__ inline bool accept(const Cursor &c, const double4 &q, int j, int p, double R2)
-{
-    double dx = c.bx - q.x, dy = c.by - q.y, dz = c.bz - q.z;
-    double r2 = dx * dx + dy * dy + dz * dz;
-    return r2 < R2 && j != p;
-}
-
 // FP64 1/sqrt(x) for x > 0: hardware estimate refined by two Newton steps.
 __device__ inline double rsqrt_f64(double x)
 {
@@ -365,61 +339,92 @@ __device__ inline int window_candidate(const int32_t *pstart, const int32_t *ppr
     return pstart[l] + (c - ppref[l]);
 }
 
-// One wave lists the neighbours of the home particles of cell pair q.  Lanes
-// take 64 consecutive candidates of the window at a time (loads coalesced
-// along the rows); for each home particle in turn every lane tests its
-// candidate, and the accepted ones are appended in lane order (ballot /
-// mbcnt) to that particle's list.  So a particle's list holds the candidates
-// within the list radius in window order — planes, rows, wrap pieces, cell
-// order — the same list, entry for entry, as a walk of the particle's own
-// 5 x 5 x 5 cells: the pair window's extra cells lie at least 2 w >= r_c +
-// skin away from the other cell's particles.  A particle with more than 5 kp
-// neighbours gets the count 5 kp + 1 (its lanes then walk the cells in the
-// evaluation).
+// One wave lists the neighbours of the home particles of cell pair q,
+// kListHomes of them per pass over the window.  Lanes take 64 consecutive
+// candidates of the window at a time (loads coalesced along the rows); each
+// home particle of the pass, its position read from LDS by every lane (a
+// broadcast), is tested against all 64, and the accepted ones are appended
+// in lane order (ballot / mbcnt) to that particle's list, the pass's running
+// counts staying wave-uniform (scalar registers).  So a particle's list holds
+// the candidates within the list radius in window order — planes, rows, wrap
+// pieces, cell order — the same list, entry for entry, as a walk of the
+// particle's own 5 x 5 x 5 cells: the pair window's extra cells lie at least
+// 2 w >= r_c + skin away from the other cell's particles.  A particle with
+// more than list_rows(kp) neighbours gets the count list_rows(kp) + 1 (its
+// lanes then walk the cells in the evaluation).
+constexpr int kListHomes = 16;
+static_assert(kListBlock == 8, "a list block is read as two int4");
+
 __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
 {
     __shared__ int32_t pstart[kListWaves][64], ppref[kListWaves][64], pcode[kListWaves][64];
+    __shared__ double hpos[kListWaves][3][kListHomes];
     const int lane = threadIdx.x & 63;
     PairWindow win;
     if (!pair_window(a, q, pstart[wv], ppref[wv], pcode[wv], win)) return;   // uniform per wave
-    const int h_beg = win.h_beg, h_end = win.h_end, total = win.total;
-    const int rows = kNearPlanes * a.kp;
+    const int total = win.total;
+    const int rows = list_rows(a.kp);
     const double L = a.g.L;
+    // the list radius with a relative margin of 1e-12: a candidate is tested
+    // as home - (its position + image shift), the evaluation forms the same
+    // difference in another order, and a pair on the radius must not be lost
+    // to the rounding (extra pairs beyond r_c are skipped by the evaluation)
+    const double R2 = a.rl2 * (1.0 + 1e-12);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));   // lanes under this one
-    // home particles 64 at a time; lane l keeps the position and the count of
-    // home particle hb + l (positions read once, then broadcast from lane h - hb)
-    for (int hb = h_beg; hb < h_end; hb += 64) {
-        const int he = min(h_end, hb + 64);
-        int cnt = 0;
-        const double4 mine = hb + lane < he ? a.xs[hb + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int hb = win.h_beg; hb < win.h_end; hb += kListHomes) {
+        const int nh = min(kListHomes, win.h_end - hb);
+        if (lane < nh) {
+            const double4 r = a.xs[hb + lane];
+            hpos[wv][0][lane] = r.x;
+            hpos[wv][1][lane] = r.y;
+            hpos[wv][2][lane] = r.z;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        int cnt[kListHomes];
+#pragma unroll
+        for (int hh = 0; hh < kListHomes; ++hh) cnt[hh] = 0;
         for (int c0 = 0; c0 < total; c0 += 64) {
             const int c = c0 + lane;
             const bool live = c < total;
-            int j = 0;
-            double sx = 0.0, sy = 0.0, sz = 0.0;
-            double4 qj = make_double4(0.0, 0.0, 0.0, 0.0);
+            int j = -1;
+            double px = 0.0, py = 0.0, pz = 0.0;   // the candidate, image-shifted
             if (live) {
+                double sx, sy, sz;
                 j = window_candidate(pstart[wv], ppref[wv], pcode[wv], c, L, sx, sy, sz);
-                qj = a.xs[j];
+                const double4 qj = a.xs[j];
+                px = qj.x + sx;
+                py = qj.y + sy;
+                pz = qj.z + sz;
             }
-            for (int h = hb; h < he; ++h) {
-                const int src = h - hb;
-                const double hx = readlane_f64(mine.x, src), hy = readlane_f64(mine.y, src),
-                             hz = readlane_f64(mine.z, src);
-                const Cursor cu{0, 0, hx - sx, hy - sy, hz - sz};
-                const bool ok = live && accept(cu, qj, j, h, a.rl2);
-                const uint64_t m = __ballot(ok);
-                if (m) {
-                    const int base = __builtin_amdgcn_readlane(cnt, h - hb);
+#pragma unroll
+            for (int hh = 0; hh < kListHomes; ++hh) {
+                if (hh < nh) {   // uniform
+                    const int h = __builtin_amdgcn_readfirstlane(hb + hh);
+                    // the home's position is read from LDS at each test (a
+                    // broadcast), not held in registers for every home
+                    __asm__ volatile("" ::: "memory");
+                    const double dx = hpos[wv][0][hh] - px, dy = hpos[wv][1][hh] - py, dz = hpos[wv][2][hh] - pz;
+                    const bool ok = live && dx * dx + dy * dy + dz * dz < R2 && j != h;
+                    const uint64_t m = __ballot(ok);
                     if (ok) {
-                        const int k = base + __popcll(m & below);
+                        const int k = cnt[hh] + __popcll(m & below);
                         if (k < rows) a.nbr[list_at(h, k, rows)] = j;
                     }
-                    if (lane == h - hb) cnt = base + __popcll(m);
+                    cnt[hh] += __popcll(m);
                 }
             }
         }
-        if (lane < he - hb) a.nbr_cnt[hb + lane] = cnt > rows ? rows + 1 : cnt;
+        int mine = 0;
+#pragma unroll
+        for (int hh = 0; hh < kListHomes; ++hh)
+            if (lane == hh) mine = cnt[hh];
+        if (lane < nh) a.nbr_cnt[hb + lane] = mine > rows ? rows + 1 : mine;
+        // the positions of the next pass overwrite these
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -443,7 +448,6 @@ __device__ inline void near_body(const NearArgs &a, int lb)
     const int grp = lb / kNearLanes;
     const int s = lb - grp * kNearLanes;   // this lane of the particle
     const int p = grp * kEvalThreads + t;
-    const size_t stride = (size_t)kNearLanes * 64;   // a lane's entries are kNearLanes rows apart
     double4 pi = make_double4(0.0, 0.0, 0.0, 0.0);
     int total = 0;
     if (p < a.N) {
@@ -451,30 +455,46 @@ __device__ inline void near_body(const NearArgs &a, int lb)
         total = a.nbr_cnt[p];
     }
     double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0;
-    if (total <= kNearPlanes * a.kp) {
-        // lane s takes entries s, s + kNearLanes, ... of the particle's list,
-        // two per pass: entries k, k + 1 are evaluated while the positions of
-        // k + 2, k + 3 and the indices of k + 4, k + 5 are loading (an index
-        // past the lane's count is not read: the particle itself, or the last
-        // one for the lanes past N, stands in for it and is never evaluated)
-        const int cnt = total > s ? (total - s + kNearLanes - 1) / kNearLanes : 0;
-        const int32_t *in = a.nbr + list_at(p, s, kNearPlanes * a.kp);
-        const int self = p < a.N ? p : a.N - 1;   // stands in for entries not read
-        int ja = cnt > 0 ? in[0] : self;
-        int jb = cnt > 1 ? in[stride] : self;
-        double4 qa = a.xs[ja], qb = a.xs[jb];
-        in += 2 * stride;
-        int jc = cnt > 2 ? in[0] : self;
-        int jd = cnt > 3 ? in[stride] : self;
-        for (int k = 0; k < cnt; k += 2) {
-            const double4 ca = qa, cb = qb;
-            qa = a.xs[jc];
-            qb = a.xs[jd];
-            in += 2 * stride;
-            jc = k + 4 < cnt ? in[0] : self;
-            jd = k + 5 < cnt ? in[stride] : self;
-            pair_force<MIXED, ENERGY, NG>(a, pi, ca, fx, fy, fz, en);
-            if (k + 1 < cnt) pair_force<MIXED, ENERGY, NG>(a, pi, cb, fx, fy, fz, en);
+    const int rows = list_rows(a.kp);
+    if (total <= rows) {
+        // lane s takes blocks s, s + kNearLanes, ... of the particle's list
+        // (kListBlock consecutive entries each): a block's indices arrive as
+        // two 16-byte loads while the block before is evaluated, and within a
+        // block the positions of two entries are loading while the two before
+        // are evaluated.  Entries past the count are not used: the particle
+        // itself (or the last one, for lanes past N) stands in for them and is
+        // never evaluated.
+        const int nblk = (total + kListBlock - 1) / kListBlock;
+        const int self = p < a.N ? p : a.N - 1;
+        const int32_t *blk = a.nbr + list_at(p, 0, rows);   // block b at blk + b * bstride
+        const size_t bstride = (size_t)kListBlock;
+        int4 n0 = make_int4(self, self, self, self), n1 = n0;
+        if (s < nblk) {
+            n0 = *(const int4 *)(blk + (size_t)s * bstride);
+            n1 = *(const int4 *)(blk + (size_t)s * bstride + 4);
+        }
+        for (int b = s; b < nblk; b += kNearLanes) {
+            const int ne = min(kListBlock, total - b * kListBlock);
+            int jj[kListBlock] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+            const int bn = b + kNearLanes;
+            if (bn < nblk) {
+                n0 = *(const int4 *)(blk + (size_t)bn * bstride);
+                n1 = *(const int4 *)(blk + (size_t)bn * bstride + 4);
+            }
+#pragma unroll
+            for (int e = 0; e < kListBlock; ++e)
+                if (e >= ne) jj[e] = self;
+            double4 qa = a.xs[jj[0]], qb = a.xs[jj[1]];
+#pragma unroll
+            for (int e = 0; e < kListBlock; e += 2) {
+                const double4 ca = qa, cb = qb;
+                if (e + 2 < kListBlock) {
+                    qa = a.xs[jj[e + 2]];
+                    qb = a.xs[jj[e + 3]];
+                }
+                if (e < ne) pair_force<MIXED, ENERGY, NG>(a, pi, ca, fx, fy, fz, en);
+                if (e + 1 < ne) pair_force<MIXED, ENERGY, NG>(a, pi, cb, fx, fy, fz, en);
+            }
         }
     } else {
         // the particle's list overflowed at the build: its lanes walk the

@@ -200,9 +200,9 @@ struct NearArgs {
     double margin;             // slack of the per-particle cell culling
     double inv_L;
     Exp2Poly e2;
-    int32_t *nbr;              // 5 kp entries per particle (tile-major, list_at): listed j in candidate order
-    int32_t *nbr_cnt;          // [N] listed count per particle; 5 kp + 1 when a plane overflowed
-    int kp;                    // list capacity per (particle, chunk); 5 kp per particle
+    int32_t *nbr;              // list_rows(kp) entries per particle (blocks, list_at): listed j in candidate order
+    int32_t *nbr_cnt;          // [N] listed count per particle; list_rows(kp) + 1 when the list overflowed
+    int kp;                    // list capacity: list_rows(kp) (about 5 kp) entries per particle
     double rl2;                // squared list radius (r_c + skin)^2; the fine grid has cells >= (r_c + skin)/2
     const int32_t *gate;       // list build: null = always, else only when *gate != 0
     // evaluation of one system: with nrho > 0 the first nrho workgroups (a
@@ -219,15 +219,19 @@ hipError_t launch_nlist(const NearArgs &a, hipStream_t st);
 // list build: one pair of x-adjacent cells per wave, kListWaves waves per workgroup
 constexpr int kListWaves = 4;
 __host__ __device__ inline int nlist_blocks(int nf) { return (nf * nf * ((nf + 1) / 2) + kListWaves - 1) / kListWaves; }
-// Neighbour lists are tile-major: entry k of particle p of an array with
-// `rows` entries per particle is at list_at(p, k, rows) — 64 consecutive
-// particles side by side in each row (a wave's row is one 256-byte segment)
-// and a tile's rows contiguous (a list build's stores stay within a few tens of
-// KB per tile).  Arrays hold list_padded(N) particles.
-__host__ __device__ inline size_t list_at(int p, int k, int rows)
-{
-    return ((size_t)(p >> 6) * (size_t)rows + (size_t)k) * 64 + (size_t)(p & 63);
-}
+// Neighbour lists are particle-major: the `rows` entries of particle p are
+// contiguous at list_at(p, 0, rows) (rows a multiple of kListBlock,
+// list_rows), so a list build's append of a run of accepted candidates of one
+// particle fills consecutive words and the lines of a list are written by the
+// one wave that builds it; the evaluation reads a particle's entries in blocks
+// of kListBlock (32 bytes, two 16-byte loads).  Measured at the N = 1e6 plasma
+// against a layout with the 64 particles of a tile side by side per entry (or
+// per block): the build's scattered one-word stores into 64-particle rows cost
+// more than the evaluation gains from reading rows of 64 lanes.  Arrays hold
+// list_padded(N) particles.
+constexpr int kListBlock = 8;
+__host__ __device__ inline int list_rows(int kp) { return (5 * kp + kListBlock - 1) / kListBlock * kListBlock; }
+__host__ __device__ inline size_t list_at(int p, int k, int rows) { return (size_t)p * (size_t)rows + (size_t)k; }
 __host__ __device__ inline int64_t list_padded(int64_t N) { return (N + 63) / 64 * 64; }
 // evaluation: a particle's list is dealt round-robin to kNearLanes lanes (3
 // measured fastest of 1..5 on the N = 1e5 plasma: longer runs per lane than 5,

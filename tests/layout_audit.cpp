@@ -69,13 +69,18 @@ static void audit(int64_t N, double L, double lambda, double rc, int P, double s
     CHECK(d.rl <= 2.0 * L / d.nf * (1 + 1e-15), "%s: list radius %g beyond the stencil of %d cells", tag, d.rl, d.nf);
     CHECK(rc <= 2.0 * L / d.nf_tight * (1 + 1e-15), "%s: r_c beyond the stencil of the tight grid", tag);
     CHECK(d.nf_tight >= d.nf, "%s: the tight grid is coarser", tag);
-    // neighbour lists: 5 kp rows per particle of the padded tile layout, for
+    // neighbour lists: list_rows(kp) entries per particle of the padded tiles, for
     // both list radii (the capacity only shrinks when the skin drops)
     const int kp_tight = near_capacity(N, L, rc, d.nf_tight);
     const int kp = d.kp > kp_tight ? d.kp : kp_tight;
-    CHECK(span(w.nbr, w.nbr_cnt) >= 4 * (size_t)kp * 5 * (size_t)list_padded(N), "%s: list rows", tag);
-    CHECK(list_at((int)list_padded(N) - 1, 5 * d.kp - 1, 5 * d.kp) < (size_t)d.kp * 5 * (size_t)list_padded(N),
+    const int rows = list_rows(kp);
+    CHECK(rows % kListBlock == 0 && rows >= 5 * kp, "%s: list rows of whole blocks", tag);
+    CHECK(span(w.nbr, w.nbr_cnt) >= 4 * (size_t)rows * (size_t)list_padded(N), "%s: list rows", tag);
+    CHECK(list_at((int)list_padded(N) - 1, rows - 1, rows) < (size_t)rows * (size_t)list_padded(N),
           "%s: last list entry", tag);
+    // the evaluation reads a particle's block b as two int4 at list_at(p, 8 b, rows): 16-byte aligned
+    CHECK(list_at(63, kListBlock, rows) - list_at(63, 0, rows) == (size_t)kListBlock &&
+          list_at(1, 0, rows) % 4 == 0, "%s: block stride", tag);
     // structure-factor partials: groups of the standalone launch and of the
     // shared launch (both precisions) within the buffer
     const size_t part_cap = span(w.part, w.rho) / 16;
