@@ -4,7 +4,14 @@
 // coarse grid of rbsog_build_cells, the fine grid of the force evaluation, and
 // the finer grid a hot system's default skin drops to), and the fine grids'
 // 5 x 5 x 5 stencil covers the list radius.  Prints one line per failure and
-// exits non-zero if any.
+// exits non-zero if any.  A second part checks that every launcher refuses
+// arguments that would send a kernel outside its buffers (a missing buffer, a
+// grid too coarse for the 5 x 5 x 5 stencil, a structure-factor group beyond
+// the staging area) on the host, before anything is launched; it runs only
+// where no GPU is visible, so that a missing check cannot launch a kernel on
+// the placeholder pointers it passes.
+#include <hip/hip_runtime.h>
+
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -102,6 +109,177 @@ static void audit(int64_t N, double L, double lambda, double rc, int P, double s
     CHECK(w.total >= w.tab + 16 * kPhaseTable, "%s: total", tag);
 }
 
+// every call below carries one argument a kernel cannot run on, and must be
+// refused with hipErrorInvalidValue
+static void guards()
+{
+    static double4 d4[4];
+    static double d[16];
+    static double2 d2[4];
+    static int32_t i32[16];
+    static int32_t *const ip = i32;
+    auto refused = [](hipError_t e, const char *what) {
+        CHECK(e == hipErrorInvalidValue, "launch not refused: %s (returned %d)", what, (int)e);
+    };
+    // cells: every buffer present but one
+    CellArgs c{};
+    c.N = 10;
+    c.g.nc = 3;
+    c.g.ncell = 27;
+    c.xs = d4;
+    c.order = ip;
+    c.xs_old = d4;
+    c.order_old = ip;
+    c.ms = d;
+    c.ms_old = d;
+    c.xb = d;
+    c.cell_id = ip;
+    c.count = ip;
+    c.cell_start = ip;
+    c.fill = ip;
+    c.tmp = ip;
+    c.tile_sum = ip;
+    c.ticket = nullptr;
+    refused(launch_cell_build(c, nullptr), "cell build without the scan ticket");
+    c.ticket = ip;
+    c.N = 0;
+    refused(launch_cell_build(c, nullptr), "cell build of no particles");
+    c.N = 10;
+    c.vs = d;   // velocities to move but no snapshot of them
+    refused(launch_cell_build(c, nullptr), "cell build moving velocities without their snapshot");
+    // near field
+    NearArgs n{};
+    n.N = 10;
+    n.g.nc = 6;
+    n.g.ncell = 216;
+    n.rc2 = 1.0;
+    n.rl2 = 1.2;
+    n.w = 1.0;
+    n.kp = 4;
+    n.xs = d4;
+    n.cell_start = ip;
+    n.nbr = ip;
+    n.nbr_cnt = ip;
+    n.fnear = d;
+    n.sog.n = 2;
+    NearArgs b = n;
+    b.g.nc = 5;
+    refused(launch_nlist(b, nullptr), "list build on a grid of 5 cells (the stencil would wrap onto itself)");
+    refused(launch_near(b, nullptr), "evaluation on a grid of 5 cells");
+    b = n;
+    b.rl2 = 0.9;
+    refused(launch_nlist(b, nullptr), "list radius below r_c");
+    b = n;
+    b.kp = 0;
+    refused(launch_nlist(b, nullptr), "list of no capacity");
+    b = n;
+    b.nbr = nullptr;
+    refused(launch_near(b, nullptr), "evaluation without lists");
+    b = n;
+    b.energy = 1;
+    refused(launch_near(b, nullptr), "energies without their partials");
+    b = n;
+    b.sog.n = 0;
+    refused(launch_near(b, nullptr), "no Gaussians");
+    b.sog.n = kMaxGauss + 1;
+    refused(launch_near(b, nullptr), "more Gaussians than the argument block holds");
+    b = n;
+    b.nrho = 4;
+    refused(launch_near(b, nullptr), "structure-factor workgroups not a multiple of 8");
+    // structure factors
+    RhoArgs r{};
+    r.N = 1000;
+    r.P = 200;
+    r.chunk = 64;
+    r.nchunk = 16;
+    r.xs = d4;
+    r.samp = d4;
+    r.part = d2;
+    r.rho = d2;
+    r.gk = d2;
+    r.eF = d;
+    r.tab = d2;
+    b = n;
+    b.nrho = 8;
+    b.red = r;
+    b.red.mixed = 1;
+    refused(launch_near(b, nullptr), "structure-factor partials of another precision than the near field");
+    b.red = r;
+    refused(launch_near(b, nullptr), "fewer structure-factor workgroups than the partials need");
+    RhoArgs q = r;
+    q.chunk = 512;
+    q.nchunk = 2;
+    refused(launch_rho_partial(q, nullptr), "groups larger than the largest group");
+    q = r;
+    q.P = 1;
+    q.chunk = 256;
+    q.nchunk = 4;
+    refused(launch_rho_partial(q, nullptr), "staged groups beyond the staging area");
+    q = r;
+    q.nchunk = 15;
+    refused(launch_rho_partial(q, nullptr), "groups that do not cover every particle");
+    q = r;
+    q.tab = nullptr;
+    refused(launch_rho_partial(q, nullptr), "FP64 phases without the rotation table");
+    q = r;
+    q.samp = nullptr;
+    refused(launch_rho_reduce(q, nullptr), "reduction without modes");
+    // far field, drift, sampling, state copies, energies
+    FarArgs f{};
+    f.N = 10;
+    f.P = 8;
+    f.xs = d4;
+    f.order = ip;
+    f.samp = d4;
+    f.gk = d2;
+    f.fnear = d;
+    f.f = d;
+    f.flag = ip;
+    f.tab = d2;
+    f.drift = 1;
+    refused(launch_far(f, nullptr), "fused drift without its buffers");
+    f.drift = 0;
+    f.vs = d;
+    refused(launch_far(f, nullptr), "second half-kick without masses");
+    KickDriftArgs k{};
+    k.N = 10;
+    k.xs = d4;
+    k.vs = d;
+    k.fs = d;
+    k.ms = d;
+    k.xb = d;
+    k.flag = ip;
+    refused(launch_kick_drift(k, nullptr), "drift without the rebuild gate");
+    SampleArgs sa{};
+    sa.P = 8;
+    sa.nstep = 2;
+    sa.nshell = 3;
+    sa.cdf = d;
+    sa.coef = d;
+    sa.first = ip;
+    sa.size = ip;
+    sa.lattice = ip;
+    sa.samp = d4;
+    sa.n_out = ip;
+    refused(launch_sample(sa, nullptr), "mode output of more than one step");
+    PermArgs pa{};
+    pa.N = 10;
+    pa.x = d;
+    pa.q = d;
+    pa.m = d;
+    pa.xs = d4;
+    pa.ms = d;
+    refused(launch_state_in(pa, nullptr), "state copy without the cell order");
+    pa.order = ip;
+    pa.v = d;
+    refused(launch_state_in(pa, nullptr), "velocities to copy without their cell-order rows");
+    EnergyArgs ea{};
+    ea.epart = d;
+    ea.eF = d;
+    refused(launch_energy(ea, nullptr), "energies without an output row");
+    refused(launch_iota(nullptr, 10, nullptr), "cell order without its array");
+}
+
 int main()
 {
     const double n = 3.0 / (4.0 * 3.141592653589793);   // number density of the workloads
@@ -124,6 +302,14 @@ int main()
                     audit(y.N, L, y.lambda, y.rc, P, sk);
                     ++cases;
                 }
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) ndev = 0;
+    if (ndev == 0) {
+        guards();
+        std::printf("launch guards checked\n");
+    } else {
+        std::printf("launch guards not checked: a GPU is visible\n");
     }
     std::printf("audited %d parameter sets, %d failures\n", cases, failures);
     return failures ? 1 : 0;

@@ -4,7 +4,12 @@ of particle counts, boxes (down to three cells), mode counts and skins, that
 each buffer the kernels index holds the largest index their launch shapes
 reach on every cell grid a system can use -- including the finer grid that a
 hot system's default skin drops to at its first step -- and that each fine
-grid's 5 x 5 x 5 stencil covers its list radius."""
+grid's 5 x 5 x 5 stencil covers its list radius.  Where no GPU is visible it
+also checks that every launcher refuses, on the host and before any launch,
+arguments a kernel cannot run on (a missing buffer, a grid of fewer than six
+cells, a structure-factor group beyond the staging area, ...): without a device
+an unrefused launch returns hipErrorNoDevice, not hipErrorInvalidValue, so a
+missing check fails the audit."""
 import os
 import shutil
 import subprocess
@@ -36,3 +41,4 @@ def test_workspace_plan_covers_every_launch(audit_exe):
     print(r.stdout[-2000:])
     assert r.returncode == 0, r.stdout[-4000:]
     assert "0 failures" in r.stdout
+    assert "launch guards checked" in r.stdout or "a GPU is visible" in r.stdout
