@@ -63,45 +63,61 @@ def slots_far(pr: dict) -> float:
     return 10 + pr["sincos"]
 
 
-# HBM bytes per launch of a kernel, from one FETCH_SIZE and one WRITE_SIZE counter
-# run (KiB per dispatch), each scaled by what the same counter reads for an FP64
-# copy of known size.  A figure holds only for the kernel sources it was taken
-# on: it is reported when the SHA-256 over the library sources still matches.
+# Sources each profiled kernel is built from: a stored counter figure holds
+# only while the SHA-256 over these files is the one it was taken on.
+KERNEL_SOURCES = {
+    "near": ["k_near.hip", "k_rho.hip", "dev_common.h", "dev_math.h", "launch.h"],
+    "far": ["k_far.hip", "dev_common.h", "dev_math.h", "launch.h"],
+    "nlist": ["k_near.hip", "dev_common.h", "launch.h"],
+}
+
+# HBM bytes per launch at the N = 1e6, Gamma = 0.1 plasma (FP64), from one
+# FETCH_SIZE and one WRITE_SIZE counter run (KiB per dispatch, mean over the
+# profiled dispatches), each scaled by what the same counter reads for an FP64
+# copy y = 2x of 256 MiB (FETCH_SIZE 131086 KiB for 262144 KiB read: x2.000;
+# WRITE_SIZE 262150 KiB for 262144 KiB written: x1.000).
 MEASURED_TRAFFIC = {
     # kernel: (sources sha256, FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale)
+    "near": ("aaabd9821eb4bfe1dbf9c7e8f7ec3ba1d858b051404e31c93b683c92004524a7", 475018.0, 100836.0, 2.0, 1.0),
+    "far": ("0768fb73ffe51155c1e662e5530626cf4ef2fe559ab0ed3e5021531bcf375a3f", 78268.0, 79102.0, 2.0, 1.0),
+    "nlist": ("79fd93e1b0f3efcbc8bde7318a91202147a9fe5d00891a8f051f574ef91db5de", 84184.0, 527295.0, 2.0, 1.0),
 }
 
-# VALU counters of a kernel at the headline workload (rocprofv3 --pmc, one pass
-# each): SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, SQ_BUSY_CU_CYCLES (or GRBM), and
-# VALUUtilization; keyed like MEASURED_TRAFFIC.
+# VALU issue at the same workload (FP64): VALU busy = SQ_ACTIVE_INST_VALU x 4
+# cycles / 1024 SIMDs / (GRBM_GUI_ACTIVE / 8 XCDs), lane utilisation =
+# SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU); their product is the
+# fraction of the VALU's lane-cycles that issued work.
 MEASURED_VALU = {
+    # kernel: (sources sha256, VALU busy, lane utilisation)
+    "near": ("aaabd9821eb4bfe1dbf9c7e8f7ec3ba1d858b051404e31c93b683c92004524a7", 0.67, 0.93),
+    "far": ("0768fb73ffe51155c1e662e5530626cf4ef2fe559ab0ed3e5021531bcf375a3f", 0.93, 1.00),
+    "nlist": ("79fd93e1b0f3efcbc8bde7318a91202147a9fe5d00891a8f051f574ef91db5de", 0.81, 0.76),
 }
 
 
-def sources_sha256() -> str:
+def sources_sha256(kernel: str) -> str:
     import hashlib
     d = os.path.join(ROOT, "paper_2501_10946_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            h.update(name.encode())
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(f.read())
+    for name in KERNEL_SOURCES[kernel]:
+        h.update(name.encode())
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()
 
 
 def measured_traffic(kernel: str):
     t = MEASURED_TRAFFIC.get(kernel)
-    if t is None or t[0] != sources_sha256():
+    if t is None or t[0] != sources_sha256(kernel):
         return None
     return (t[1] * t[3] + t[2] * t[4]) * 1024.0
 
 
 def measured_valu(kernel: str):
     t = MEASURED_VALU.get(kernel)
-    if t is None or t[0] != sources_sha256():
+    if t is None or t[0] != sources_sha256(kernel):
         return None
-    return t[1]
+    return {"valu_busy": t[1], "lane_utilisation": t[2], "busy_x_utilisation": t[1] * t[2]}
 
 
 def log(*a):
@@ -316,6 +332,97 @@ def rooflines(kern: dict, work: dict) -> dict:
 # the served ensemble
 # ---------------------------------------------------------------------------
 
+def preequilibrate(R, w, st, sog, dev, steps):
+    """`steps` FP64 steps from the seeded state with the velocities rescaled to
+    the target kinetic energy after each (untimed); returns (x, v) on the host."""
+    import torch
+    s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, device=dev)
+    x = torch.tensor(st.x, device=dev)
+    v = torch.tensor(st.v, device=dev)
+    f = torch.empty_like(x)
+    R.rbsog_compute_forces(s.h, 0, x, f)
+    eh = torch.zeros((1, 6), dtype=torch.float64, device=dev)
+    ke_target = 0.5 * (3 * w.N - 3) * w.kT
+    for k in range(steps):
+        R.rbsog_step(s.h, x, v, f, k, 1, w.dt, eh)
+        v.mul_(torch.sqrt(ke_target / eh[0, 5]))
+    R.rbsog_check(s.h)
+    xe, ve = x.cpu().numpy(), v.cpu().numpy()
+    del s
+    return xe, ve
+
+
+def variance_experiment(R, dev, draws=400, snapshots=20, equil_steps=20000, gap=100):
+    """The fluctuation comparison of the sampling densities (Section 5.3,
+    Fig. 8) through the library: the 1000-particle plasma with P = 20 at
+    effective couplings 1e-3 .. 100, equilibrated by the library's own dynamics
+    (velocities rescaled to the target temperature each step), then along an
+    NVE run `snapshots` states `gap` steps apart, each evaluated with `draws`
+    random batches per density against the full-lattice far field of the same
+    library: E_fluc = <(E* - E)^2>, F_fluc = <(1/N) sum_i |F*_i - F_i|^2>.
+    "adaptive_tinst" is the adaptive density at the snapshot's instantaneous
+    temperature (rbsog_set_kT, Section 4.3)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    names = {R.RBSOG_ADAPTIVE: "adaptive", R.RBSOG_FLAT: "flat", R.RBSOG_K2: "k2", R.RBSOG_DH4PI: "dh4pi"}
+    out = {"recipe": {"N": 1000, "P": 20, "kappa": workloads.VARIANCE_KAPPA, "r_c": 5.0 / workloads.VARIANCE_KAPPA,
+                      "draws_per_snapshot": draws, "snapshots": snapshots, "equilibration_steps": equil_steps,
+                      "snapshot_gap_steps": gap}, "gamma_star": {}}
+    for gs in workloads.VARIANCE_GAMMA_STAR:
+        w = workloads.variance_workload(gs)
+        st = workloads.make_state(w)
+        sog = R.rbsog_sog_init(w.lam, w.r_c, w.eps)
+        dyn = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, device=dev)
+        full = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, full_k=True, device=dev)
+        rb = {d: R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed + 1, density=d, device=dev) for d in names}
+        tinst = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed + 1, density=R.RBSOG_ADAPTIVE, device=dev)
+        x = torch.tensor(st.x, device=dev)
+        v = torch.tensor(st.v, device=dev)
+        f = torch.empty_like(x)
+        R.rbsog_compute_forces(dyn.h, 0, x, f)
+        eh = torch.zeros((1, 6), dtype=torch.float64, device=dev)
+        ke_target = 0.5 * (3 * w.N - 3) * w.kT
+        for k in range(equil_steps):
+            R.rbsog_step(dyn.h, x, v, f, k, 1, w.dt, eh)
+            v.mul_(torch.sqrt(ke_target / eh[0, 5]))
+        step = equil_steps
+        acc = {n: [0.0, 0.0] for n in list(names.values()) + ["adaptive_tinst"]}
+        F = torch.empty((draws, 3, w.N), dtype=torch.float64, device=dev)
+        E = torch.zeros((draws, 6), dtype=torch.float64, device=dev)
+        ff = torch.empty_like(x)
+        ef = torch.zeros(6, dtype=torch.float64, device=dev)
+        ehist = torch.zeros((gap, 6), dtype=torch.float64, device=dev)
+        t_inst = []
+        for snap in range(snapshots):
+            R.rbsog_step(dyn.h, x, v, f, step, gap, w.dt, ehist)
+            step += gap
+            kT_now = 2.0 * float(ehist[-1, 5]) / (3 * w.N - 3)
+            t_inst.append(kT_now)
+            R.rbsog_set_kT(tinst.h, kT_now)
+            R.rbsog_compute_forces(full.h, 0, x, ff, None, ef)
+            for name, sysm in [(names[d], rb[d]) for d in names] + [("adaptive_tinst", tinst)]:
+                for s in range(draws):
+                    R.rbsog_compute_forces(sysm.h, snap * draws + s, x, F[s], None, E[s])
+                acc[name][0] += float(((E[:, 1] - ef[1]) ** 2).mean())
+                acc[name][1] += float((((F - ff[None]) ** 2).sum(dim=(1, 2)) / w.N).mean())
+        for sysm in [dyn, full, tinst] + list(rb.values()):
+            R.rbsog_check(sysm.h)
+        res = {n: {"E_fluc": a[0] / snapshots, "F_fluc": a[1] / snapshots} for n, a in acc.items()}
+        emin = min(res[n]["E_fluc"] for n in names.values())
+        fmin = min(res[n]["F_fluc"] for n in names.values())
+        for n in res:
+            res[n]["E_rel"] = res[n]["E_fluc"] / emin
+            res[n]["F_rel"] = res[n]["F_fluc"] / fmin
+        out["gamma_star"][f"{gs:g}"] = {"gamma": w.gamma, "kT": w.kT, "dt": w.dt,
+                                         "kT_inst_mean": float(np.mean(t_inst)), "densities": res}
+        log(f"[bench] variance Gamma* {gs:g}: " + ", ".join(
+            f"{n} E {r['E_rel']:.2f} F {r['F_rel']:.2f}" for n, r in res.items()))
+        del dyn, full, rb, tinst
+    return out
+
+
 def serve(args, dev):
     """The served ensemble: seeded requests (N log-uniform in [500, 5e4], Gamma
     log-uniform in [0.1, 100], kappa uniform in [0.1, 2], r_c 4, P 200, 100
@@ -429,6 +536,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-ensemble measurement")
+    ap.add_argument("--no-variance", action="store_true", help="skip the sampling-density fluctuation comparison")
     ap.add_argument("--no-force-check", action="store_true")
     ap.add_argument("--skin", type=float, default=-1.0, help="neighbour-list skin (negative: the library default)")
     ap.add_argument("--gammas", default="0.1,100", help="couplings of the headline runs")
@@ -545,6 +653,11 @@ def main():
         if not fused_rho:
             work["rho_partial"] = rho_slots
         kroof = rooflines(kern, work)
+        for k in kroof:
+            kroof[k]["traffic"] = measured_traffic(k) if k in KERNEL_SOURCES else None
+            vc = measured_valu(k) if k in KERNEL_SOURCES else None
+            if vc is not None:
+                kroof[k]["valu_counters"] = vc
         dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
         if dom in kroof:
             roofline = dict(kroof[dom], kernel=dom + ("+rho_partial" if dom == "near" and fused_rho else ""),
@@ -612,19 +725,7 @@ def main():
         st = workloads.make_state(w)
         o = oracle.sog_auto(w.lam, w.r_c, w.eps)
         sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
-        s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, device=dev)
-        x = torch.tensor(st.x, device=dev)
-        v = torch.tensor(st.v, device=dev)
-        f = torch.empty_like(x)
-        R.rbsog_compute_forces(s.h, 0, x, f)
-        eh = torch.zeros((1, 6), dtype=torch.float64, device=dev)
-        ke_target = 0.5 * (3 * w.N - 3) * w.kT
-        for k in range(200):
-            R.rbsog_step(s.h, x, v, f, k, 1, w.dt, eh)
-            v.mul_(torch.sqrt(ke_target / eh[0, 5]))
-        R.rbsog_check(s.h)
-        xe, ve = x.cpu().numpy(), v.cpu().numpy()
-        del s
+        xe, ve = preequilibrate(R, w, st, sog, dev, 200)
         c2 = {"preequilibration_steps": 200}
         for name, prec in (("fp64", R.RBSOG_FP64), ("mixed", R.RBSOG_MIXED)):
             res = run_workload(R, w, st, sog, prec, w.steps, 20, dev, x0=xe, v0=ve, step0=200)
@@ -637,14 +738,15 @@ def main():
             c2["force_rel_rms"] = force_check(R, oracle, w, st, o, xf, sf, dev)
         extra[w.name] = c2
 
-        # binary mixture N = 2e5, mixed precision (and FP64 beside it), 500 steps
+        # binary mixture N = 2e5: 200 pre-equilibration steps, then mixed precision (and FP64 beside it), 500 steps
         w = workloads.MIXTURE_200K
         st = workloads.make_state(w)
         o = oracle.sog_auto(w.lam, w.r_c, w.eps)
         sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
-        c5 = {}
+        xe, ve = preequilibrate(R, w, st, sog, dev, 200)
+        c5 = {"preequilibration_steps": 200}
         for name, prec in (("mixed", R.RBSOG_MIXED), ("fp64", R.RBSOG_FP64)):
-            res = run_workload(R, w, st, sog, prec, w.steps, 20, dev, kernel_pass=False)
+            res = run_workload(R, w, st, sog, prec, w.steps, 20, dev, kernel_pass=False, x0=xe, v0=ve, step0=200)
             res["drift"] = energy_drift(res["ehist"].sum(axis=1), w.dt, w.N * w.kT)
             c5[name] = strip(res)
             if name == "mixed":
@@ -653,6 +755,8 @@ def main():
         if not args.no_force_check:
             c5["force_rel_rms"] = force_check(R, oracle, w, st, o, xf, sf, dev)
         extra[w.name] = c5
+        if not args.no_variance:
+            extra["variance_ocp_n1000_p20"] = variance_experiment(R, dev)
         if not args.no_serve:
             extra["served"] = serve(args, dev)
         out["extra"] = extra

@@ -261,6 +261,25 @@ int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double *f_dev, uin
                double dt, double *energy_hist_dev);
 
 /*
+ * Instantaneous temperature in the sampling measure (Section 4.3: in NVT runs
+ * the k_B T of the adaptive density, eq. 3.22, is the instantaneous one,
+ * computed on the fly, while the other terms stay precomputed).  Re-derives
+ * the shell CDF and the weights coef = S / (P V F(k)) of eq. 3.124 with kT in
+ * place of the configured k_B T, on the host in the order rbsog_create uses,
+ * and uploads them on the handle's stream: evaluations and steps enqueued
+ * after this call draw from the new measure (modes drawn ahead are discarded),
+ * those enqueued before it from the old one.  kT is typically 2 KE / (3N - 3)
+ * from the last energy row.  The densities FLAT and K2 do not depend on kT
+ * (their tables come out unchanged); with full_k only the stored kT changes.
+ * Host work ~ one pass over the shells (<= 1e4); no stream synchronisation
+ * except that a call waits for the previous call's upload to leave its pinned
+ * staging buffer.  A higher kT re-runs the default skin's thermal check at the
+ * next rbsog_step.  Errors: RBSOG_EINVAL (kT not positive and finite),
+ * RBSOG_EHIP.
+ */
+int rbsog_set_kT(rbsog_handle *h, double kT);
+
+/*
  * Synchronises the stream and reports the device flag: RBSOG_OK, or
  * RBSOG_ENONFINITE if any evaluation since the last check produced a
  * non-finite force or an over-long step (the flag is then cleared).

@@ -85,6 +85,7 @@ def lib() -> C.CDLL:
             "rbsog_compute_forces": (C.c_int, [_p, C.c_uint64, _p, _p, _p, _p]),
             "rbsog_step": (C.c_int, [_p, _p, _p, _p, C.c_uint64, C.c_int, C.c_double, _p]),
             "rbsog_check": (C.c_int, [_p]),
+            "rbsog_set_kT": (C.c_int, [_p, C.c_double]),
             "rbsog_timing_enable": (C.c_int, [_p, C.c_int]),
             "rbsog_timing_read": (C.c_int, [_p, C.POINTER(rbsog_timing)]),
             "rbsog_destroy": (None, [_p]),
@@ -255,6 +256,12 @@ def rbsog_rho_noalloc(x, q, L: float, n, rho, precision: int = RBSOG_FP64, strea
 
 def rbsog_check(h) -> None:
     _check(lib().rbsog_check(h))
+
+
+def rbsog_set_kT(h, kT: float) -> None:
+    """Re-derives the sampling measure with temperature kT (the instantaneous
+    temperature of an NVT run); later evaluations draw from it."""
+    _check(lib().rbsog_set_kT(h, kT))
 
 
 def rbsog_timing_enable(h, enable: bool = True) -> None:

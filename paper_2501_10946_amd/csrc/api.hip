@@ -850,10 +850,52 @@ extern "C" int rbsog_timing_read(rbsog_handle *h, rbsog_timing *out)
     return RBSOG_OK;
 }
 
+extern "C" int rbsog_set_kT(rbsog_handle *h, double kT)
+{
+    if (!h) return fail(RBSOG_EINVAL, "null handle");
+    if (!(kT > 0.0) || !std::isfinite(kT)) return fail(RBSOG_EINVAL, "kT must be positive and finite");
+    if (h->d.full_k) {   // no sampling: the full lattice does not depend on kT
+        h->p.kT = kT;
+        return RBSOG_OK;
+    }
+    rbsog_params p = h->p;
+    p.kT = kT;
+    Tables t;
+    build_tables(h->sog, p, h->Q2, h->d.mmax, &t, false);
+    if (t.nshell != h->nshell) return fail(RBSOG_EINVAL, "shell count changed with kT");
+    hipError_t e = hipSuccess;
+    if (!h->kt_host) {
+        e = hipHostMalloc((void **)&h->kt_host, sizeof(double) * 2 * (size_t)h->nshell, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&h->kt_ev, hipEventDisableTiming);
+        if (e != hipSuccess) return fail(RBSOG_EHIP, "rbsog_set_kT staging: %s", hipGetErrorString(e));
+    } else {
+        e = hipEventSynchronize(h->kt_ev);   // the previous upload has left the staging buffer
+        if (e != hipSuccess) return fail(RBSOG_EHIP, "rbsog_set_kT: %s", hipGetErrorString(e));
+    }
+    std::copy(t.cdf.begin(), t.cdf.end(), h->kt_host);
+    std::copy(t.coef.begin(), t.coef.end(), h->kt_host + h->nshell);
+    // stream order puts the new tables after every draw enqueued before this call
+    e = hipMemcpyAsync(h->cdf, h->kt_host, sizeof(double) * h->nshell, hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->coef, h->kt_host + h->nshell, sizeof(double) * h->nshell, hipMemcpyHostToDevice, h->st);
+    if (e == hipSuccess) e = hipEventRecord(h->kt_ev, h->st);
+    if (e != hipSuccess) return fail(RBSOG_EHIP, "rbsog_set_kT upload: %s", hipGetErrorString(e));
+    if (kT > h->p.kT) h->dt_checked = 0.0;   // a hotter system: the default skin's thermal check runs again
+    h->p.kT = kT;
+    h->S = t.S;
+    h->samp_n = 0;   // modes drawn ahead with the old measure are drawn again
+    return RBSOG_OK;
+}
+
 extern "C" void rbsog_destroy(rbsog_handle *h)
 {
     if (!h) return;
     if (!h->records.empty()) (void)hipStreamSynchronize(h->st);
+    if (h->kt_ev) {
+        (void)hipEventSynchronize(h->kt_ev);
+        (void)hipEventDestroy(h->kt_ev);
+    }
+    if (h->kt_host) (void)hipHostFree(h->kt_host);
     for (auto &e : h->events) (void)hipEventDestroy(e);
     if (h->rb_ev) {
         (void)hipEventSynchronize(h->rb_ev);

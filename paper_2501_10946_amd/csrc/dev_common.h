@@ -27,6 +27,17 @@ __device__ inline void raise_any(int32_t *flag, bool cond)
     if (m != 0 && (int)(threadIdx.x & 63) == __ffsll((unsigned long long)m) - 1) atomicOr(flag, 1);
 }
 
+// Raises a rebuild gate when some particle of the wave has moved more than half
+// the skin since the last build (d2: its squared displacement).  With no skin
+// any motion leaves the lists stale, so the gate is raised by the system's
+// first particle alone: one atomic per launch instead of one per wave (at 1e6
+// particles the 15 625 same-address atomics of the waves serialise for
+// ~0.15 ms).
+__device__ inline void raise_gate(int32_t *gate, double d2, double half_skin2, int p)
+{
+    raise_any(gate, half_skin2 > 0.0 ? !(d2 <= half_skin2) : p == 0);
+}
+
 // Fixed-order sum over a 256-thread block; valid in thread 0.
 __device__ inline double block_sum_256(double v, double *red)
 {

@@ -233,7 +233,7 @@ __device__ inline void kick_drift_body(const KickDriftArgs &a, int b)
     for (int d = 0; d < 3; ++d) a.vs[d * a.N + p] = v[d];
     a.xs[p] = make_double4(x[0], x[1], x[2], r.w);
     raise_any(a.flag, bad);
-    raise_any(a.gate, !(d2 <= a.half_skin2));
+    raise_gate(a.gate, d2, a.half_skin2, p);
 }
 
 RBSOG_KERNELS(kick_drift, KickDriftArgs, kBlock)

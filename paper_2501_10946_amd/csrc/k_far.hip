@@ -152,7 +152,7 @@ __device__ inline void far_body(const FarArgs &a, int b)
                 vz = v[2];
                 a.xs_next[p] = make_double4(x[0], x[1], x[2], pi.w);
                 raise_any(a.flag, bad);
-                raise_any(a.gate_raise, !(d2 <= a.half_skin2));
+                raise_gate(a.gate_raise, d2, a.half_skin2, p);
             }
             a.vs[p] = vx;
             a.vs[a.N + p] = vy;

@@ -96,6 +96,10 @@ struct rbsog_handle {
     int64_t rb_steps, steps_done;
     uint64_t samp_step;  // first step of the modes in samp, with samp_n steps drawn
     int samp_n;
+    // rbsog_set_kT: pinned staging of the re-derived cdf and coef ([2][nshell]),
+    // free again once kt_ev has completed
+    double *kt_host = nullptr;
+    hipEvent_t kt_ev = nullptr;
     // per-kernel event timing (rbsog_timing_enable)
     bool timing = false;
     std::vector<hipEvent_t> events;

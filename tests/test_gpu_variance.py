@@ -1,0 +1,191 @@
+"""The random-batch fluctuations through the library, against the exact
+variances of the lemma on unbiasedness (eqs. 3.22 and 3.24) evaluated by the
+oracle over the whole lattice, for the four sampling densities at weak,
+moderate and strong effective coupling (the comparison of Section 5.3 on the
+1000-particle plasma with P = 20); and the instantaneous-temperature measure
+(rbsog_set_kT, Section 4.3) against the oracle's tables built at that
+temperature.
+
+The configurations come from the oracle's own velocity-Verlet run (with the
+velocities rescaled to the target temperature after each step), so no input of
+the oracle comes from the library."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_2501_10946_amd")
+
+DENSITIES = {0: "adaptive", 1: "flat", 2: "k2", 3: "dh4pi"}
+DRAWS = 2000
+Z_MAX = 5.0
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    R.lib()
+    return torch.device("cuda:0")
+
+
+_configs = {}
+
+
+def equilibrated(gamma_star: float, steps: int = 300):
+    """(workload, state, oracle SOG) with positions after `steps` oracle steps
+    at the workload's temperature (velocities rescaled after each step)."""
+    if gamma_star in _configs:
+        return _configs[gamma_star]
+    w = workloads.variance_workload(gamma_star)
+    st = workloads.make_state(w)
+    o = oracle.sog_auto(w.lam, w.r_c, w.eps)
+    ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
+    x, v = st.x.copy(), st.v.copy()
+    f, _, _ = ref.force(x, 0)
+    target = 0.5 * (3 * w.N - 3) * w.kT
+    for k in range(steps):
+        eh = ref.run(x, v, f, k, 1, w.dt)
+        v *= math.sqrt(target / eh[0, 5])
+    st = workloads.State(x=np.ascontiguousarray(x), v=np.ascontiguousarray(v), q=st.q, m=st.m)
+    _configs[gamma_star] = (w, st, o)
+    return _configs[gamma_star]
+
+
+def exact_variances(w, st, o, density):
+    """E|Xi_U|^2 (eq. 3.22) and (1/N) sum_i E|Xi_F,i|^2 (eq. 3.24) at the
+    state's positions, with the far energy and forces of the full lattice."""
+    ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed, density=density)
+    n3, _ = ref.lattice()
+    V = w.L ** 3
+    k = (2 * math.pi / w.L) * n3.astype(np.float64)
+    k2 = (k * k).sum(1)
+    rho = oracle.rho(st.x, st.q, w.L, n3)
+    fh = o.Fhat(k2)
+    _, cdf, _ = ref.tables()
+    S = cdf[-1]
+    Q2 = float((st.q ** 2).sum())
+    Fk = np.array([oracle.density(density, w.kT, V, Q2, o.lam, v) for v in k2])
+    f_full, U_full = oracle.far_full(st.x, st.q, w.L, o, ref.mmax)
+    r2 = (rho ** 2).sum(1)
+    varU = (S / (4 * V ** 2) * (fh * r2 ** 2 / Fk).sum() - U_full ** 2) / w.P
+    th = st.x.T @ k.T
+    im = rho[None, :, 1] * np.cos(th) - rho[None, :, 0] * np.sin(th)
+    second = (st.q ** 2 * S / V ** 2) * ((k2 * fh / Fk)[None, :] * im ** 2).sum(1)
+    varF = (second.sum() - (f_full ** 2).sum()) / (w.P * w.N)
+    return varU, varF
+
+
+def gpu_fluctuations(dev, w, st, o, density, draws=DRAWS):
+    """(E* - E)^2 and (1/N) sum_i |F*_i - F_i|^2 over `draws` force
+    evaluations (Philox step indices 0 .. draws - 1) of the random-batch
+    system, E and F from the same library with the full lattice."""
+    sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+    rb = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, density=density, device=dev)
+    full = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, full_k=True, device=dev)
+    x = torch.tensor(st.x, device=dev)
+    ff = torch.empty_like(x)
+    ef = torch.zeros(6, dtype=torch.float64, device=dev)
+    R.rbsog_compute_forces(full.h, 0, x, ff, None, ef)
+    F = torch.empty((draws, 3, w.N), dtype=torch.float64, device=dev)
+    E = torch.zeros((draws, 6), dtype=torch.float64, device=dev)
+    for s in range(draws):
+        R.rbsog_compute_forces(rb.h, s, x, F[s], None, E[s])
+    dE2 = (E[:, 1] - ef[1]) ** 2
+    dF2 = ((F - ff[None]) ** 2).sum(dim=(1, 2)) / w.N
+    torch.cuda.synchronize()
+    R.rbsog_check(rb.h)
+    return dE2.cpu().numpy(), dF2.cpu().numpy()
+
+
+@pytest.mark.parametrize("gamma_star", [0.01, 1.0, 100.0])
+@pytest.mark.parametrize("density", sorted(DENSITIES))
+def test_fluctuations_match_exact_variances(dev, gamma_star, density):
+    """The mean squared deviation of the library's random-batch far energy and
+    force from the full-lattice ones, over 2000 draws, agrees with the exact
+    variances within five standard errors of the sample mean."""
+    w, st, o = equilibrated(gamma_star)
+    print(f"\n[case] variance {w.name} density {DENSITIES[density]} draws {DRAWS}", flush=True)
+    dE2, dF2 = gpu_fluctuations(dev, w, st, o, density)
+    varU, varF = exact_variances(w, st, o, density)
+    assert varU > 0 and varF > 0
+    for name, sample, exact in (("energy", dE2, varU), ("force", dF2, varF)):
+        se = sample.std(ddof=1) / math.sqrt(sample.size)
+        z = (sample.mean() - exact) / se
+        print(f"  {name}: sample {sample.mean():.4e} exact {exact:.4e} z {z:+.2f}", flush=True)
+        assert abs(z) <= Z_MAX, f"{name} fluctuation {sample.mean():.4e} vs exact {exact:.4e} (z = {z:.2f})"
+
+
+@pytest.mark.parametrize("density", [0, 1, 3])
+def test_set_kT_samples_bit_exact(dev, density):
+    """After rbsog_set_kT the draws are those of a system created at the new
+    temperature (the oracle's tables at that kT), bit for bit; FLAT does not
+    depend on kT."""
+    w = workloads.OCP_1K
+    st = workloads.make_state(w)
+    o = oracle.sog_auto(w.lam, w.r_c, w.eps)
+    sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+    s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, density=density, device=dev)
+    n = torch.zeros((w.P, 3), dtype=torch.int32, device=dev)
+    coef = torch.zeros(w.P, dtype=torch.float64, device=dev)
+    for kT in (0.37 * w.kT, 5.0 * w.kT, w.kT):
+        R.rbsog_set_kT(s.h, kT)
+        ref = oracle.System(st.q, st.m, w.L, o, kT, w.P, seed=w.seed, density=density)
+        for step in (0, 5, 1000):
+            R.rbsog_sample_k(s.h, step, n, coef)
+            torch.cuda.synchronize()
+            no, co = ref.draw(step)
+            assert np.array_equal(n.cpu().numpy(), no)
+            assert np.array_equal(coef.cpu().numpy().view(np.uint64), co.view(np.uint64))
+
+
+def test_set_kT_mid_trajectory(dev):
+    """Ten steps at k_B T, then ten with the measure re-derived at a new
+    temperature: the trajectory follows the oracle's (a system at k_B T for the
+    first ten, one at the new temperature for the rest) to 1e-10, so modes drawn
+    ahead with the old measure are not used after the change."""
+    w = workloads.OCP_1K
+    st = workloads.make_state(w)
+    o = oracle.sog_auto(w.lam, w.r_c, w.eps)
+    sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+    kT2 = 3.0 * w.kT
+    s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, device=dev)
+    x = torch.tensor(st.x, device=dev)
+    v = torch.tensor(st.v, device=dev)
+    f = torch.empty_like(x)
+    R.rbsog_compute_forces(s.h, 0, x, f)
+    R.rbsog_step(s.h, x, v, f, 0, 10, w.dt)
+    R.rbsog_set_kT(s.h, kT2)
+    R.rbsog_step(s.h, x, v, f, 10, 10, w.dt)
+    torch.cuda.synchronize()
+    R.rbsog_check(s.h)
+    r1 = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
+    r2 = oracle.System(st.q, st.m, w.L, o, kT2, w.P, seed=w.seed)
+    xo, vo = st.x.copy(), st.v.copy()
+    fo, _, _ = r1.force(xo, 0)
+    r1.run(xo, vo, fo, 0, 10, w.dt)
+    r2.run(xo, vo, fo, 10, 10, w.dt)
+    dx = np.abs(x.cpu().numpy() - xo)
+    dx = np.minimum(dx, w.L - dx)
+    assert dx.max() <= 1e-10, f"positions differ by {dx.max():.3e}"
+    # and the measure really changed: the run at k_B T alone ends elsewhere
+    r3 = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
+    xs, vs = st.x.copy(), st.v.copy()
+    fs, _, _ = r3.force(xs, 0)
+    r3.run(xs, vs, fs, 0, 20, w.dt)
+    assert np.abs(xs - xo).max() > 1e-8
+
+
+def test_set_kT_refuses_bad_temperature(dev):
+    w = workloads.OCP_1K
+    st = workloads.make_state(w)
+    sog = R.rbsog_sog_init(w.lam, w.r_c, w.eps)
+    s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, device=dev)
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(R.RbsogError):
+            R.rbsog_set_kT(s.h, bad)

@@ -77,6 +77,28 @@ MIXTURE_200K = Workload("mix_n200000_k0.5_g5", N=200_000, kappa=0.5, gamma=5.0, 
 
 ALL = [OCP_1K, OCP_100K, OCP_1M_WEAK, OCP_1M_STRONG, MIXTURE_200K]
 
+# The fluctuation comparison of the sampling densities (Section 5.3, Fig. 8):
+# a one-component plasma of 1000 particles with P = 20 modes per step over
+# effective couplings Gamma* = Gamma (1 + kappa + kappa^2) exp(-kappa) from
+# 1e-3 to 100.  The paper gives lambda and r_c in Angstrom (r_c = 5 lambda) but
+# not the density of this run; r_c = 5 lambda is kept, and kappa = 1 (lambda =
+# a) so that the box of 1000 particles at the reduced density holds three cells
+# of width r_c.
+VARIANCE_GAMMA_STAR = (1e-3, 1e-2, 1e-1, 1.0, 10.0, 100.0)
+VARIANCE_KAPPA = 1.0
+
+
+def gamma_from_effective(gamma_star: float, kappa: float) -> float:
+    """The coupling Gamma whose effective coupling (Section 5.1) is gamma_star."""
+    return gamma_star / ((1.0 + kappa + kappa * kappa) * math.exp(-kappa))
+
+
+def variance_workload(gamma_star: float, seed: int = 301) -> Workload:
+    kappa = VARIANCE_KAPPA
+    return Workload(f"ocp_n1000_k1_gstar{gamma_star:g}", N=1000, kappa=kappa,
+                    gamma=gamma_from_effective(gamma_star, kappa), r_c=5.0 / kappa, P=20, steps=0, seed=seed,
+                    dt=0.01 * min(1.0, math.sqrt(gamma_from_effective(gamma_star, kappa))))
+
 
 def rng(seed: int, stream: int = 0) -> np.random.Generator:
     """numpy Generator on a Philox bit stream keyed by (seed, stream)."""
