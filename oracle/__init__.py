@@ -59,6 +59,7 @@ def lib():
             "orc_sog_expand": (None, [_d, _d, _d, _d, _i, _i, _p, _p, _p, _p]),
             "orc_F": (_d, [_i, _p, _p, _d]),
             "orc_Fhat": (_d, [_i, _p, _p, _d]),
+            "orc_Fhat_slope": (_d, [_i, _p, _p, _d]),
             "orc_density": (_d, [_i, _d, _d, _d, _d, _d]),
             "orc_mmax_default": (_i, [_i, _p, _p, _d]),
             "orc_lattice_count": (_i64, [_i]),
@@ -66,12 +67,13 @@ def lib():
             "orc_shell_table": (_i, [_i, _p, _i, _p, _p, _d, _i, _d, _d, _d, _i, _p, _p, _p]),
             "orc_philox4x64_10": (None, [_p, _p, _p]),
             "orc_cells": (_i, [_i64, _p, _d, _d, _p, _p]),
-            "orc_near": (None, [_i64, _p, _p, _d, _d, _d, _i, _p, _p, _p, _p]),
+            "orc_near": (None, [_i64, _p, _p, _d, _d, _d, _i, _p, _p, _p, _p, _p]),
             "orc_near_subset": (_i, [_i64, _p, _p, _d, _d, _d, _i, _p, _p, _i64, _p, _p]),
             "orc_rho": (None, [_i64, _p, _p, _d, _i, _p, _p]),
             "orc_far_rb": (None, [_i64, _p, _p, _d, _i, _p, _p, _p, _p]),
             "orc_far_rb_energy": (_d, [_i, _p, _p]),
-            "orc_far_full": (_d, [_i64, _p, _p, _d, _i, _p, _p, _i, _p]),
+            "orc_far_rb_virial": (_d, [_i, _p, _p, _p, _d, _i, _p, _p]),
+            "orc_far_full": (_d, [_i64, _p, _p, _d, _i, _p, _p, _i, _p, _p]),
             "orc_sys_create": (_p, [_i64, _d, _d, _d, _d, _i, _i, _u64, _u32, _i, _i, _i, _p, _p, _p, _p, _p, _p]),
             "orc_sys_destroy": (None, [_p]),
             "orc_sys_mmax": (_i, [_p]),
@@ -145,6 +147,12 @@ class SOG:
     def Fhat(self, k2) -> np.ndarray:
         k2 = np.asarray(k2, dtype=np.float64)
         return np.array([lib().orc_Fhat(self.n, _ptr(self.A), _ptr(self.B), float(x)) for x in k2.ravel()]).reshape(k2.shape)
+
+    def Fhat_slope(self, k2) -> np.ndarray:
+        """-dFhat/d(k^2)."""
+        k2 = np.asarray(k2, dtype=np.float64)
+        return np.array([lib().orc_Fhat_slope(self.n, _ptr(self.A), _ptr(self.B), float(x))
+                         for x in k2.ravel()]).reshape(k2.shape)
 
 
 def h_star(eps: float, delta: float) -> float:
@@ -228,13 +236,15 @@ def cells(x: np.ndarray, L: float, rc: float):
     return cs, order
 
 
-def near(x, q, L, s: SOG):
+def near(x, q, L, s: SOG, virial: bool = False):
+    """Near-field forces [3, N] and energy U_N; with virial, also W_N."""
     x, q = _f64(x), _f64(q)
     N = x.shape[1]
     f = np.zeros((3, N))
-    U = C.c_double()
-    lib().orc_near(N, _ptr(x), _ptr(q), L, s.lam, s.rc, s.n, _ptr(s.c), _ptr(s.s), _ptr(f), C.byref(U))
-    return f, U.value
+    U, W = C.c_double(), C.c_double()
+    lib().orc_near(N, _ptr(x), _ptr(q), L, s.lam, s.rc, s.n, _ptr(s.c), _ptr(s.s), _ptr(f), C.byref(U),
+                   C.byref(W))
+    return (f, U.value, W.value) if virial else (f, U.value)
 
 
 def near_subset(x, q, L, s: SOG, idx):
@@ -267,11 +277,21 @@ def far_rb(x, q, L, n3, coef, rho_):
     return f
 
 
-def far_full(x, q, L, s: SOG, mmax: int):
+def far_full(x, q, L, s: SOG, mmax: int, virial: bool = False):
+    """Full-lattice far forces [3, N] and energy U_F; with virial, also W_F."""
     x, q = _f64(x), _f64(q)
     f = np.zeros_like(x)
-    U = lib().orc_far_full(x.shape[1], _ptr(x), _ptr(q), L, s.n, _ptr(s.A), _ptr(s.B), mmax, _ptr(f))
-    return f, U
+    W = C.c_double()
+    U = lib().orc_far_full(x.shape[1], _ptr(x), _ptr(q), L, s.n, _ptr(s.A), _ptr(s.B), mmax, _ptr(f),
+                           C.byref(W))
+    return (f, U, W.value) if virial else (f, U)
+
+
+def far_rb_virial(n3, coef, rho_, L, s: SOG) -> float:
+    """The random-batch estimator of the far-field virial for the modes n3."""
+    n3 = np.ascontiguousarray(n3, dtype=np.int32)
+    coef, rho_ = _f64(coef), _f64(rho_)
+    return lib().orc_far_rb_virial(n3.shape[0], _ptr(n3), _ptr(coef), _ptr(rho_), L, s.n, _ptr(s.A), _ptr(s.B))
 
 
 # ---------------------------------------------------------------------------
@@ -324,17 +344,17 @@ class System:
         return n, coef
 
     def force(self, x, step: int):
-        """Returns (f, f_near, energy[6])."""
+        """Returns (f, f_near, energy[8]): U_N, U_F, U_k0, U_self, U_bg, 0, W_N, W_F."""
         x = _f64(x)
         f = np.zeros_like(x)
         fn = np.zeros_like(x)
-        e = np.zeros(6)
+        e = np.zeros(8)
         lib().orc_sys_force(self._h, step, _ptr(x), _ptr(f), _ptr(fn), _ptr(e))
         return f, fn, e
 
     def run(self, x, v, f, step0: int, nsteps: int, dt: float):
-        """Advances (x, v, f) in place; returns the [nsteps, 6] energy history."""
-        eh = np.zeros((nsteps, 6))
+        """Advances (x, v, f) in place; returns the [nsteps, 8] energy history (KE in column 5)."""
+        eh = np.zeros((nsteps, 8))
         r = lib().orc_sys_run(self._h, _ptr(x), _ptr(v), _ptr(f), step0, nsteps, dt, _ptr(eh))
         if r != 0:
             raise RuntimeError("a particle moved a full box length in one step")

@@ -273,6 +273,15 @@ double orc_Fhat(int nG, const double *A, const double *B, double k2)
     return acc;
 }
 
+/* -dFhat/d(k^2) = sum_j A_j B_j exp(-B_j k^2): how the far-field kernel
+ * changes when a scaling of the box moves every k = 2 pi n / L. */
+double orc_Fhat_slope(int nG, const double *A, const double *B, double k2)
+{
+    double acc = 0.0;
+    for (int j = 0; j < nG; ++j) acc += A[j] * B[j] * exp(-B[j] * k2);
+    return acc;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Section 4.3: the adaptive importance-sampling density                      */
 /* ------------------------------------------------------------------------- */
@@ -533,14 +542,20 @@ static void near_pair(double r2, double lambda, int nG, const double *c, const d
 }
 
 /* Near-field forces (written to f, SoA) and energy U_N = 1/2 sum over ordered
- * pairs and images of q_i q_j N(|d|) with 0 < |d| < rc.  With L >= 3 rc and
+ * pairs and images of q_i q_j N(|d|) with 0 < |d| < rc, and (W_out, nullable)
+ * its virial W_N = 1/2 sum over the same ordered pairs of d . F_ij: when the
+ * configuration and the box are scaled together (d -> s d, V = L^3), a pair
+ * potential gives -3V dU/dV = sum over pairs of d . F_ij, since N(r) and N'(r)
+ * vanish at r_c (the C0 and C1 conditions of the SOG), so no pair crossing the
+ * cutoff contributes.  With L >= 3 rc and
  * N > 2000 the pairs are found through the cell list; otherwise every image
  * shift that can reach within rc is looped over directly (tiny boxes). */
 void orc_near(int64_t N, const double *x, const double *q, double L, double lambda, double rc, int nG,
-              const double *c, const double *s, double *f, double *U_out)
+              const double *c, const double *s, double *f, double *U_out, double *W_out)
 {
     double rc2 = rc * rc;
     double *ei = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
+    double *wi = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
     int nc = (int)floor(L / rc);
     if (nc >= 3 && N > 2000) {
         int32_t *cs = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nc * nc * nc + 1));
@@ -558,7 +573,7 @@ void orc_near(int64_t N, const double *x, const double *q, double L, double lamb
                 if (cc > nc - 1) cc = nc - 1;
                 ci[d] = cc;
             }
-            double fx = 0, fy = 0, fz = 0, e = 0;
+            double fx = 0, fy = 0, fz = 0, e = 0, w = 0;
             for (int dz = -1; dz <= 1; ++dz)
                 for (int dy = -1; dy <= 1; ++dy)
                     for (int dx = -1; dx <= 1; ++dx) {
@@ -579,10 +594,12 @@ void orc_near(int64_t N, const double *x, const double *q, double L, double lamb
                             double qq = q[i] * q[j];
                             fx += qq * fac * dx_; fy += qq * fac * dy_; fz += qq * fac * dz_;
                             e += 0.5 * qq * en;
+                            w += 0.5 * qq * fac * r2;
                         }
                     }
             f[i] = fx; f[N + i] = fy; f[2 * N + i] = fz;
             ei[i] = e;
+            wi[i] = w;
         }
         free(cs);
         free(ord);
@@ -590,7 +607,7 @@ void orc_near(int64_t N, const double *x, const double *q, double L, double lamb
         int nimg = (int)ceil(rc / L);
 #pragma omp parallel for schedule(dynamic, 16)
         for (int64_t i = 0; i < N; ++i) {
-            double fx = 0, fy = 0, fz = 0, e = 0;
+            double fx = 0, fy = 0, fz = 0, e = 0, w = 0;
             for (int64_t j = 0; j < N; ++j) {
                 for (int a = -nimg; a <= nimg; ++a)
                     for (int b = -nimg; b <= nimg; ++b)
@@ -606,16 +623,23 @@ void orc_near(int64_t N, const double *x, const double *q, double L, double lamb
                             double qq = q[i] * q[j];
                             fx += qq * fac * dx_; fy += qq * fac * dy_; fz += qq * fac * dz_;
                             e += 0.5 * qq * en;
+                            w += 0.5 * qq * fac * r2;
                         }
             }
             f[i] = fx; f[N + i] = fy; f[2 * N + i] = fz;
             ei[i] = e;
+            wi[i] = w;
         }
     }
-    double U = 0.0;
-    for (int64_t i = 0; i < N; ++i) U += ei[i];
+    double U = 0.0, W = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        U += ei[i];
+        W += wi[i];
+    }
     *U_out = U;
+    if (W_out) *W_out = W;
     free(ei);
+    free(wi);
 }
 
 /* Near-field force on a subset of particles idx[0..nsub) (for checks at sizes
@@ -756,13 +780,35 @@ double orc_far_rb_energy(int P, const double *coef, const double *rho)
     return 0.5 * U;
 }
 
+/* Virial of the far field, W_F = -3V dU_F/dV with the configuration scaled
+ * with the box: U_F = (1/2V) sum_k Fhat(k^2) |rho(k)|^2 has rho unchanged
+ * (k . r is invariant) while 1/V and k^2 = (2 pi / L)^2 |n|^2 (prop. to V^(-2/3))
+ * change, so W_F = 3 U_F - (1/V) sum_k k^2 G(k^2) |rho(k)|^2 with
+ * G = -dFhat/d(k^2).  Its random-batch estimator over the modes of eq. (UF)
+ * (the same importance weights as the energy, coef_l = S / (P V F(k_l))):
+ *   W*_F = sum_l coef_l |rho_l|^2 (3/2 - k_l^2 G(k_l^2) / Fhat(k_l^2)). */
+double orc_far_rb_virial(int P, const int32_t *n3, const double *coef, const double *rho, double L, int nG,
+                         const double *A, const double *B)
+{
+    double t = (2.0 * ORC_PI) / L, W = 0.0;
+    for (int l = 0; l < P; ++l) {
+        double m = (double)n3[3 * l] * n3[3 * l] + (double)n3[3 * l + 1] * n3[3 * l + 1] +
+                   (double)n3[3 * l + 2] * n3[3 * l + 2];
+        double k2 = t * t * m;
+        double r2 = rho[2 * l] * rho[2 * l] + rho[2 * l + 1] * rho[2 * l + 1];
+        W += coef[l] * r2 * (1.5 - k2 * orc_Fhat_slope(nG, A, B, k2) / orc_Fhat(nG, A, B, k2));
+    }
+    return W;
+}
+
 /* Deterministic far field summed over every lattice mode 1 <= |n|^2 <= mmax
  * (eqs. 3.5 and 3.8, k = 0 excluded; its energy is added separately):
  *   U_F = (1/2V) sum_k Fhat(k) |rho(k)|^2,
- *   F_i += -(q_i/V) sum_k k Fhat(k) Im(e^{-ik.r_i} rho(k)).
- * Adds into f; returns U_F. */
+ *   F_i += -(q_i/V) sum_k k Fhat(k) Im(e^{-ik.r_i} rho(k)),
+ * and (W_out, nullable) the virial W_F = 3 U_F - (1/V) sum_k k^2 G(k^2) |rho|^2
+ * (see orc_far_rb_virial).  Adds into f; returns U_F. */
 double orc_far_full(int64_t N, const double *x, const double *q, double L, int nG, const double *A,
-                    const double *B, int mmax, double *f)
+                    const double *B, int mmax, double *f, double *W_out)
 {
     int64_t cnt = orc_lattice_count(mmax);
     int32_t *n3 = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)cnt);
@@ -788,9 +834,16 @@ double orc_far_full(int64_t N, const double *x, const double *q, double L, int n
         rho[2 * p] = re;
         rho[2 * p + 1] = im;
     }
-    double U = 0.0;
-    for (int64_t p = 0; p < cnt; ++p) U += fh[p] * (rho[2 * p] * rho[2 * p] + rho[2 * p + 1] * rho[2 * p + 1]);
+    double U = 0.0, Wk = 0.0;
+    for (int64_t p = 0; p < cnt; ++p) {
+        double m = (double)n3[3 * p] * n3[3 * p] + (double)n3[3 * p + 1] * n3[3 * p + 1] +
+                   (double)n3[3 * p + 2] * n3[3 * p + 2];
+        double r2 = rho[2 * p] * rho[2 * p] + rho[2 * p + 1] * rho[2 * p + 1];
+        U += fh[p] * r2;
+        Wk += t * t * m * orc_Fhat_slope(nG, A, B, t * t * m) * r2;
+    }
     U = U / (2.0 * V);
+    if (W_out) *W_out = 3.0 * U - Wk / V;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         double fx = 0, fy = 0, fz = 0;
@@ -891,21 +944,25 @@ void orc_sys_draw(const orc_sys *S, uint64_t step, int32_t *n_out, double *coef_
 
 /* One force evaluation at force-evaluation index `step` (the force step of
  * Algorithm 2).  f (SoA) receives near + far forces; f_near (nullable) the near part
- * alone.  energy[6] (nullable) = { U_N, U_F (estimator, or the full sum in
- * full-k mode), U_k0, U_self, U_bg, 0 }, where
+ * alone.  energy[8] (nullable) = { U_N, U_F (estimator, or the full sum in
+ * full-k mode), U_k0, U_self, U_bg, 0, W_N, W_F (estimator, or the full
+ * sum) }, where
  *   U_k0   = Fhat(0) (sum q)^2 / (2V)  -- the k = 0 mode of eq. (3.5), excluded
  *            from sampling and added deterministically;
  *   U_self = -1/2 sum q_i^2 F(0)       -- Section 4.1;
  *   U_bg   = -(sum q)^2 4 pi lambda^2 / (2V) -- the uniform neutralising
- *            background's interaction energy (constant, no force). */
+ *            background's interaction energy (constant, no force);
+ *   W_N, W_F = the virials -3V dU/dV of the near and far parts (orc_near,
+ *            orc_far_rb_virial); U_k0 and U_bg scale as 1/V, so their
+ *            virials are 3 U_k0 and 3 U_bg, and U_self has none. */
 void orc_sys_force(const orc_sys *S, uint64_t step, const double *x, double *f, double *f_near, double *energy)
 {
     int64_t N = S->N;
-    double UN = 0.0, UF = 0.0;
-    orc_near(N, x, S->q, S->L, S->lambda, S->rc, S->nG, S->c, S->s, f, &UN);
+    double UN = 0.0, UF = 0.0, WN = 0.0, WF = 0.0;
+    orc_near(N, x, S->q, S->L, S->lambda, S->rc, S->nG, S->c, S->s, f, &UN, &WN);
     if (f_near) memcpy(f_near, f, sizeof(double) * 3 * (size_t)N);
     if (S->full_k) {
-        UF = orc_far_full(N, x, S->q, S->L, S->nG, S->A, S->B, S->mmax, f);
+        UF = orc_far_full(N, x, S->q, S->L, S->nG, S->A, S->B, S->mmax, f, &WF);
     } else {
         int32_t *n = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)S->P);
         double *coef = (double *)malloc(sizeof(double) * (size_t)S->P);
@@ -914,6 +971,7 @@ void orc_sys_force(const orc_sys *S, uint64_t step, const double *x, double *f, 
         orc_rho(N, x, S->q, S->L, S->P, n, rho);
         orc_far_rb(N, x, S->q, S->L, S->P, n, coef, rho, f);
         UF = orc_far_rb_energy(S->P, coef, rho);
+        WF = orc_far_rb_virial(S->P, n, coef, rho, S->L, S->nG, S->A, S->B);
         free(n); free(coef); free(rho);
     }
     if (energy) {
@@ -923,6 +981,8 @@ void orc_sys_force(const orc_sys *S, uint64_t step, const double *x, double *f, 
         energy[3] = -0.5 * S->Q2 * S->F0;
         energy[4] = -(S->Q1 * S->Q1) * (4.0 * ORC_PI * S->lambda * S->lambda) / (2.0 * S->V);
         energy[5] = 0.0;
+        energy[6] = WN;
+        energy[7] = WF;
     }
 }
 
@@ -939,8 +999,8 @@ static double kinetic(const orc_sys *S, const double *v)
  * on entry.  For each of nsteps steps n = 0..nsteps-1:
  *   v += (dt/2) f / m;   x += dt v;   wrap x into [0, L);
  *   f = F(x, step0 + n + 1);   v += (dt/2) f / m.
- * ehist (nullable) receives [nsteps][6] energies of the new state, with
- * KE in slot 5.  Returns 0, or -1 if a particle moved a full box length. */
+ * ehist (nullable) receives [nsteps][8] energy rows of the new state
+ * (orc_sys_force's, with KE in slot 5).  Returns 0, or -1 if a particle moved a full box length. */
 int orc_sys_run(const orc_sys *S, double *x, double *v, double *f, uint64_t step0, int nsteps, double dt,
                 double *ehist)
 {
@@ -962,7 +1022,7 @@ int orc_sys_run(const orc_sys *S, double *x, double *v, double *f, uint64_t step
                 x[d * N + i] = xx;
             }
         }
-        double e[6];
+        double e[8];
         orc_sys_force(S, step0 + (uint64_t)n + 1, x, f, NULL, e);
         for (int64_t i = 0; i < N; ++i) {
             double hm = (0.5 * dt) / S->m[i];
@@ -970,7 +1030,7 @@ int orc_sys_run(const orc_sys *S, double *x, double *v, double *f, uint64_t step
         }
         if (ehist) {
             e[5] = kinetic(S, v);
-            memcpy(ehist + 6 * (size_t)n, e, sizeof(e));
+            memcpy(ehist + 8 * (size_t)n, e, sizeof(e));
         }
     }
     return bad ? -1 : 0;
