@@ -85,6 +85,8 @@ def lib():
             "orc_sys_force": (None, [_p, _u64, _p, _p, _p, _p]),
             "orc_sys_run": (_i, [_p, _p, _p, _p, _u64, _i, _d, _p]),
             "orc_num_threads": (_i, []),
+            "orc_ssf": (None, [_i64, _p, _p, _d, _i, _p]),
+            "orc_rdf": (None, [_i64, _p, _d, _d, _i, _p, _p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -359,6 +361,24 @@ class System:
         if r != 0:
             raise RuntimeError("a particle moved a full box length in one step")
         return eh
+
+
+def ssf(x, w, L: float, mmax: int) -> np.ndarray:
+    """Shell means of |sum_j w_j exp(i k.r_j)|^2 for |n|^2 = 0..mmax (0 where a
+    shell is empty); S(k) = ssf / N with unit weights."""
+    x, w = _f64(x), _f64(w)
+    out = np.zeros(mmax + 1)
+    lib().orc_ssf(x.shape[1], _ptr(x), _ptr(w), L, mmax, _ptr(out))
+    return out
+
+
+def rdf(x, L: float, r_max: float, nbins: int):
+    """(counts, ambiguous) of ordered pairs by minimum-image distance bin."""
+    x = _f64(x)
+    counts = np.zeros(nbins, dtype=np.int64)
+    amb = np.zeros(nbins, dtype=np.int64)
+    lib().orc_rdf(x.shape[1], _ptr(x), L, r_max, nbins, _ptr(counts), _ptr(amb))
+    return counts, amb
 
 
 def num_threads() -> int:

@@ -1036,6 +1036,75 @@ int orc_sys_run(const orc_sys *S, double *x, double *v, double *f, uint64_t step
     return bad ? -1 : 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Observables of Section 5.1: static structure factor and pair distribution  */
+/* ------------------------------------------------------------------------- */
+
+/* Shell means of the weighted structure factor over every lattice mode with
+ * 1 <= |n|^2 <= mmax:  s_out[m] = (1/cnt_m) sum_{|n|^2 = m} |sum_j w_j e^{ik.r_j}|^2,
+ * k = 2 pi n / L, cnt_m the modes of shell m (s_out[m] = 0 where there are
+ * none, and for m = 0).  With unit weights S(k) = s_out / N, the static
+ * structure factor <rho(k) rho(-k)> / N. */
+void orc_ssf(int64_t N, const double *x, const double *w, double L, int mmax, double *s_out)
+{
+    int64_t cnt = orc_lattice_count(mmax);
+    int32_t *n3 = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)(cnt > 0 ? cnt : 1));
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * ((size_t)mmax + 2));
+    orc_lattice_build(mmax, n3, start);
+    double t = (2.0 * ORC_PI) / L;
+    double *r2 = (double *)malloc(sizeof(double) * (size_t)(cnt > 0 ? cnt : 1));
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < cnt; ++p) {
+        double kx = t * n3[3 * p], ky = t * n3[3 * p + 1], kz = t * n3[3 * p + 2];
+        double re = 0.0, im = 0.0;
+        for (int64_t j = 0; j < N; ++j) {
+            double th = kx * x[j] + ky * x[N + j] + kz * x[2 * N + j];
+            re += w[j] * cos(th);
+            im += w[j] * sin(th);
+        }
+        r2[p] = re * re + im * im;
+    }
+    for (int m = 0; m <= mmax; ++m) {
+        double acc = 0.0;
+        for (int64_t p = start[m]; p < start[m + 1]; ++p) acc += r2[p];
+        s_out[m] = start[m + 1] > start[m] ? acc / (double)(start[m + 1] - start[m]) : 0.0;
+    }
+    free(n3); free(start); free(r2);
+}
+
+/* Histogram of ordered pairs (i, j), i != j, by minimum-image distance r <
+ * r_max (r_max <= L/2, so at most one image counts): bin floor(r / dr), dr =
+ * r_max / nbins, added into counts[nbins].  g(r) of bin b is counts[b] /
+ * (N (N/V) 4/3 pi ((b+1)^3 - b^3) dr^3).  A pair whose r / dr lies within
+ * 1e-9 of a bin edge could fall on either side under another rounding of the
+ * same arithmetic: it is also counted into amb[] of both adjacent bins. */
+void orc_rdf(int64_t N, const double *x, double L, double r_max, int nbins, int64_t *counts, int64_t *amb)
+{
+    double dr = r_max / nbins;
+    for (int64_t i = 0; i < N; ++i)
+        for (int64_t j = 0; j < N; ++j) {
+            if (j == i) continue;
+            double r2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                double u = x[d * N + i] - x[d * N + j];
+                u -= L * floor(u / L + 0.5);
+                r2 += u * u;
+            }
+            double r = sqrt(r2);
+            if (!(r < r_max)) continue;
+            double y = r / dr;
+            int b = (int)floor(y);
+            if (b >= nbins) b = nbins - 1;
+            counts[b] += 1;
+            double e = floor(y + 0.5);
+            if (fabs(y - e) < 1e-9) {
+                int hi = (int)e;
+                if (hi - 1 >= 0 && hi - 1 < nbins) amb[hi - 1] += 1;
+                if (hi >= 0 && hi < nbins) amb[hi] += 1;
+            }
+        }
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
