@@ -271,7 +271,7 @@ def run_workload(R, w, st, sog, prec, steps, warmup, dev, skin=-1.0, x0=None, v0
         R.rbsog_check(s.h)
     # the energy history of the same trajectory (untimed)
     x, v, f = xs.clone(), vs.clone(), torch.empty_like(xs)
-    eh = torch.zeros((steps, 6), dtype=torch.float64, device=dev)
+    eh = torch.zeros((steps, R.ENERGY_COLS), dtype=torch.float64, device=dev)
     R.rbsog_compute_forces(s.h, step0, x, f)
     t0 = time.perf_counter()
     R.rbsog_step(s.h, x, v, f, step0, steps, w.dt, eh)
@@ -341,7 +341,7 @@ def preequilibrate(R, w, st, sog, dev, steps):
     v = torch.tensor(st.v, device=dev)
     f = torch.empty_like(x)
     R.rbsog_compute_forces(s.h, 0, x, f)
-    eh = torch.zeros((1, 6), dtype=torch.float64, device=dev)
+    eh = torch.zeros((1, R.ENERGY_COLS), dtype=torch.float64, device=dev)
     ke_target = 0.5 * (3 * w.N - 3) * w.kT
     for k in range(steps):
         R.rbsog_step(s.h, x, v, f, k, 1, w.dt, eh)
@@ -382,7 +382,7 @@ def variance_experiment(R, dev, draws=400, snapshots=20, equil_steps=20000, gap=
         v = torch.tensor(st.v, device=dev)
         f = torch.empty_like(x)
         R.rbsog_compute_forces(dyn.h, 0, x, f)
-        eh = torch.zeros((1, 6), dtype=torch.float64, device=dev)
+        eh = torch.zeros((1, R.ENERGY_COLS), dtype=torch.float64, device=dev)
         ke_target = 0.5 * (3 * w.N - 3) * w.kT
         for k in range(equil_steps):
             R.rbsog_step(dyn.h, x, v, f, k, 1, w.dt, eh)
@@ -390,10 +390,10 @@ def variance_experiment(R, dev, draws=400, snapshots=20, equil_steps=20000, gap=
         step = equil_steps
         acc = {n: [0.0, 0.0] for n in list(names.values()) + ["adaptive_tinst"]}
         F = torch.empty((draws, 3, w.N), dtype=torch.float64, device=dev)
-        E = torch.zeros((draws, 6), dtype=torch.float64, device=dev)
+        E = torch.zeros((draws, R.ENERGY_COLS), dtype=torch.float64, device=dev)
         ff = torch.empty_like(x)
-        ef = torch.zeros(6, dtype=torch.float64, device=dev)
-        ehist = torch.zeros((gap, 6), dtype=torch.float64, device=dev)
+        ef = torch.zeros(R.ENERGY_COLS, dtype=torch.float64, device=dev)
+        ehist = torch.zeros((gap, R.ENERGY_COLS), dtype=torch.float64, device=dev)
         t_inst = []
         for snap in range(snapshots):
             R.rbsog_step(dyn.h, x, v, f, step, gap, w.dt, ehist)
@@ -595,9 +595,13 @@ def main():
         rr = {}
         for name, prec in (("fp64", R.RBSOG_FP64), ("mixed", R.RBSOG_MIXED)):
             res = run_workload(R, w, st, sog, prec, args.steps, args.warmup, dev, skin=args.skin)
-            E = res["ehist"].sum(axis=1)
+            E = res["ehist"][:, :6].sum(axis=1)
             res["drift"] = {"all": energy_drift(E, w.dt, w.N * w.kT),
                             "second_half": energy_drift(E[args.steps // 2:], w.dt, w.N * w.kT)}
+            eh = res["ehist"]
+            pv = (2 * eh[:, 5] + eh[:, 6] + eh[:, 7] + 3 * (eh[:, 2] + eh[:, 4])) / (3 * w.V)
+            res["pressure"] = {"mean": float(pv.mean()), "std": float(pv.std()), "ideal": w.N * w.kT / w.V,
+                               "from": "(2 KE + W_N + W*_F + 3 U_k0 + 3 U_bg) / (3V) per step"}
             info = res["info"]
             res["lists"] = {"skin": info.skin, "nf": info.nf, "near_capacity": info.near_capacity}
             t_tot[name] += res["elapsed_s"]
@@ -706,7 +710,7 @@ def main():
         o = oracle.sog_auto(w.lam, w.r_c, w.eps)
         sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
         res = run_workload(R, w, st, sog, R.RBSOG_FP64, w.steps, 20, dev, kernel_pass=False)
-        res["drift"] = energy_drift(res["ehist"].sum(axis=1), w.dt, w.N * w.kT)
+        res["drift"] = energy_drift(res["ehist"][:, :6].sum(axis=1), w.dt, w.N * w.kT)
         ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
         xo, vo = st.x.copy(), st.v.copy()
         fo, _, _ = ref.force(xo, 0)
@@ -729,7 +733,7 @@ def main():
         c2 = {"preequilibration_steps": 200}
         for name, prec in (("fp64", R.RBSOG_FP64), ("mixed", R.RBSOG_MIXED)):
             res = run_workload(R, w, st, sog, prec, w.steps, 20, dev, x0=xe, v0=ve, step0=200)
-            res["drift"] = energy_drift(res["ehist"].sum(axis=1), w.dt, w.N * w.kT)
+            res["drift"] = energy_drift(res["ehist"][:, :6].sum(axis=1), w.dt, w.N * w.kT)
             c2[name] = strip(res)
             log(f"[bench] {w.name} {name}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.4f} ms/step")
             if name == "fp64":
@@ -747,7 +751,7 @@ def main():
         c5 = {"preequilibration_steps": 200}
         for name, prec in (("mixed", R.RBSOG_MIXED), ("fp64", R.RBSOG_FP64)):
             res = run_workload(R, w, st, sog, prec, w.steps, 20, dev, kernel_pass=False, x0=xe, v0=ve, step0=200)
-            res["drift"] = energy_drift(res["ehist"].sum(axis=1), w.dt, w.N * w.kT)
+            res["drift"] = energy_drift(res["ehist"][:, :6].sum(axis=1), w.dt, w.N * w.kT)
             c5[name] = strip(res)
             if name == "mixed":
                 xf, sf = res["x"], res["step"] + 1

@@ -63,6 +63,8 @@ extern "C" {
 
 #define RBSOG_AUTO (-999)   /* M1 = M2 = RBSOG_AUTO: choose the numbers of Gaussians */
 #define RBSOG_MAX_GAUSS 32
+/* Doubles in one energy row (rbsog_compute_forces, rbsog_step, rbsog_ens_retire). */
+#define RBSOG_ENERGY_COLS 8
 
 /*
  * SOG decomposition Y(r) = N(r) + F(r) of the Yukawa kernel
@@ -238,10 +240,19 @@ int rbsog_compute_rho(rbsog_handle *h, uint64_t step, const double *x_dev, doubl
  *   f_i = sum_{j: |d| < r_c} q_i q_j [F_N1 + F_N2](|d|) d            (near, d = r_i - r_j, minimum image)
  *       - q_i sum_l coef_l k_l Im(exp(-i k_l . r_i) rho(k_l))          (far, random batch)
  * writes f_dev[3*N] (original particle order), f_near_dev[3*N] (nullable) the
- * near part alone, and energy_dev[6] (nullable, device) =
+ * near part alone, and energy_dev[RBSOG_ENERGY_COLS] (nullable, device) =
  *   { U_N, U*_F, U_k0 = Fhat(0)(sum q)^2/(2V), U_self = -F(0) sum q^2 / 2,
- *     U_bg = -(sum q)^2 4 pi lambda^2/(2V), 0 }.
- * Errors: RBSOG_EINVAL, RBSOG_EHIP.
+ *     U_bg = -(sum q)^2 4 pi lambda^2/(2V), 0, W_N, W*_F }
+ * with the virials W = -3V dU/dV of the near and far parts (configuration
+ * scaled with the box, d -> s d, V = L^3):
+ *   W_N  = sum over pairs of d . F_ij (N and N' vanish at r_c, the SOG's C0 and
+ *          C1 conditions, so pairs at the cutoff add nothing);
+ *   W*_F = sum_l coef_l |rho_l|^2 (3/2 - k_l^2 G(k_l^2) / Fhat(k_l^2)),
+ *          G = -dFhat/d(k^2) = sum_j A_j B_j exp(-B_j k^2): the random-batch
+ *          estimator (the weights of eq. UF) of 3 U_F - (1/V) sum_k k^2 G |rho|^2.
+ * U_k0 and U_bg scale as 1/V (virial 3 U_k0 and 3 U_bg), U_self not at all, so
+ * the pressure is P = (2 KE + W_N + W*_F + 3 U_k0 + 3 U_bg) / (3V).  All sums
+ * in FP64 in both precisions.  Errors: RBSOG_EINVAL, RBSOG_EHIP.
  */
 int rbsog_compute_forces(rbsog_handle *h, uint64_t step, const double *x_dev, double *f_dev,
                          double *f_near_dev, double *energy_dev);
@@ -251,8 +262,9 @@ int rbsog_compute_forces(rbsog_handle *h, uint64_t step, const double *x_dev, do
  *   v += (dt/2) f / m;  x += dt v;  wrap into [0, L);  f = F(x, step0 + n + 1);
  *   v += (dt/2) f / m.
  * f_dev must hold F(x, step0) on entry (e.g. from rbsog_compute_forces).
- * energy_hist_dev (nullable, device) receives [nsteps][6] energies of the new
- * state, as in rbsog_compute_forces with KE = sum m v^2 / 2 in slot 5.
+ * energy_hist_dev (nullable, device) receives [nsteps][RBSOG_ENERGY_COLS]
+ * energy rows of the new state, as in rbsog_compute_forces with
+ * KE = sum m v^2 / 2 in slot 5.
  * A particle moving a box length or more in one step, or a non-finite force,
  * raises a device flag reported by rbsog_check.
  * Errors: RBSOG_EINVAL, RBSOG_EHIP.
@@ -361,7 +373,7 @@ int rbsog_ens_step(rbsog_ens *e);
 int rbsog_ens_poll(rbsog_ens *e, int *done_slots, int *n_done);
 
 /* Copies a finished replica out (any of x_host, v_host [3][N] and
- * energy_hist_host [nsteps][6], rows as rbsog_compute_forces' energy_out of
+ * energy_hist_host [nsteps][RBSOG_ENERGY_COLS], rows as rbsog_compute_forces' energy_out of
  * steps 1..nsteps, may be null) and frees its slot and pool range.
  * Synchronises.  Errors: RBSOG_EINVAL (no such slot, or steps left),
  * RBSOG_ENONFINITE (the replica produced a non-finite force or an over-long

@@ -20,6 +20,8 @@ RBSOG_OK = 0
 RBSOG_EINVAL, RBSOG_ENOROOT, RBSOG_EWORKSPACE, RBSOG_EAGAIN, RBSOG_ENONFINITE, RBSOG_EHIP, RBSOG_ENOMEM = range(-1, -8, -1)
 RBSOG_FP64, RBSOG_MIXED = 0, 1
 RBSOG_ADAPTIVE, RBSOG_FLAT, RBSOG_K2, RBSOG_DH4PI = 0, 1, 2, 3
+# doubles per energy row: U_N, U*_F, U_k0, U_self, U_bg, KE, W_N, W*_F
+ENERGY_COLS = 8
 RBSOG_AUTO = -999
 RBSOG_MAX_GAUSS = 32
 
@@ -232,7 +234,7 @@ def rbsog_compute_forces(h, step: int, x, f, f_near=None, energy=None):
     import torch
     N, P, _ = _n(h)
     _check(lib().rbsog_compute_forces(h, step, _dptr(x, torch.float64, 3 * N), _dptr(f, torch.float64, 3 * N),
-                                      _dptr(f_near, torch.float64, 3 * N), _dptr(energy, torch.float64, 6)))
+                                      _dptr(f_near, torch.float64, 3 * N), _dptr(energy, torch.float64, ENERGY_COLS)))
 
 
 def rbsog_step(h, x, v, f, step0: int, nsteps: int, dt: float, energy_hist=None):
@@ -240,7 +242,7 @@ def rbsog_step(h, x, v, f, step0: int, nsteps: int, dt: float, energy_hist=None)
     N, P, _ = _n(h)
     _check(lib().rbsog_step(h, _dptr(x, torch.float64, 3 * N), _dptr(v, torch.float64, 3 * N),
                             _dptr(f, torch.float64, 3 * N), step0, nsteps, dt,
-                            _dptr(energy_hist, torch.float64, 6 * nsteps)))
+                            _dptr(energy_hist, torch.float64, ENERGY_COLS * nsteps)))
 
 
 def rbsog_rho_noalloc(x, q, L: float, n, rho, precision: int = RBSOG_FP64, stream=None) -> None:

@@ -121,8 +121,10 @@ Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
     L.rho = take(sizeof(double) * 2 * nm);
     L.gk = take(sizeof(double) * 2 * nm);
     L.eF = take(sizeof(double) * nm);
+    L.eW = take(sizeof(double) * nm);
+    L.vm = take(sizeof(double) * ((size_t)d.mmax + 1));
     L.fnear = take(sizeof(double) * 3 * kNearLanes * (size_t)N);
-    L.epart = take(sizeof(double) * (size_t)near_blocks((int)N));
+    L.epart = take(sizeof(double) * 2 * (size_t)near_blocks((int)N));
     L.kepart = take(sizeof(double) * (size_t)far_blocks((int)N));
     L.flag = take(sizeof(int32_t) * 8);
     L.energy = take(sizeof(double) * 8);
@@ -299,6 +301,8 @@ RhoArgs rho_args(rbsog_handle *h, const double4 *samp)
     a.rho = h->rho;
     a.gk = h->gk;
     a.eF = h->eF;
+    a.eW = h->eW;
+    a.vm = h->vm;
     a.mixed = h->p.precision == RBSOG_MIXED;
     a.tab = h->tab;
     a.ss = make_sincos_short();
@@ -372,6 +376,7 @@ EnergyArgs energy_args(rbsog_handle *h, double *out, bool kick)
     ea.epart = h->epart;
     ea.kepart = kick ? h->kepart : nullptr;
     ea.eF = h->eF;
+    ea.eW = h->eW;
     ea.Uk0 = h->Uk0;
     ea.Uself = h->Uself;
     ea.Ubg = h->Ubg;
@@ -540,6 +545,8 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     h->rho = (double2 *)(w + L.rho);
     h->gk = (double2 *)(w + L.gk);
     h->eF = (double *)(w + L.eF);
+    h->eW = (double *)(w + L.eW);
+    h->vm = (double *)(w + L.vm);
     h->fnear = (double *)(w + L.fnear);
     h->epart = (double *)(w + L.epart);
     h->kepart = (double *)(w + L.kepart);
@@ -567,6 +574,10 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->size, t.shell_size.data(), sizeof(int32_t) * t.nshell, hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess) e = hipMemcpyAsync(h->tab, tabh, sizeof(tabh), hipMemcpyHostToDevice, h->st);
+    std::vector<double> vmh((size_t)h->d.mmax + 1);
+    virial_table(*s, p->L, h->d.mmax, vmh.data());
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->vm, vmh.data(), sizeof(double) * vmh.size(), hipMemcpyHostToDevice, h->st);
     // full lattice: every n with its coefficient Fhat(k^2)/V, k = 2 pi n / L
     std::vector<double> full;
     if (e == hipSuccess && h->d.full_k) {
@@ -791,7 +802,7 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         uint64_t step = step0 + (uint64_t)n + 1;
         rc = modes(h, step, nsteps - n, &samp);
         if (rc) return rc;
-        double *e = energy_hist_dev ? energy_hist_dev + 6 * (size_t)n : nullptr;
+        double *e = energy_hist_dev ? energy_hist_dev + kEnergyCols * (size_t)n : nullptr;
         rc = evaluate(h, samp, nullptr, nullptr, true, dt, e, n + 1 < nsteps ? gate_next : nullptr, gate);
         if (rc) return rc;
         h->phase = 1 - h->phase;

@@ -202,6 +202,11 @@ __device__ inline void rho_reduce_body(const RhoArgs &a, int b)
         a.rho[l] = make_double2(re, im);
         a.gk[l] = make_double2(cf * re, cf * im);
         a.eF[l] = 0.5 * cf * (re * re + im * im);
+        if (a.eW) {   // |n|^2 from the mode's integer components (exact in FP64)
+            const double4 sl = a.samp[l];
+            const int m = (int)(sl.x * sl.x + sl.y * sl.y + sl.z * sl.z);
+            a.eW[l] = cf * (re * re + im * im) * (1.5 - a.vm[m]);
+        }
         if (a.rho_out) {
             a.rho_out[2 * l] = re;
             a.rho_out[2 * l + 1] = im;

@@ -253,7 +253,7 @@ size_t replica_bytes(const rbsog_params *p, const rbsog_sog *sog, int nsteps)
     const size_t N = (size_t)p->N;
     const size_t ws = make_layout(p->N, derive(p, sog), p->P, true).total;
     return align_up(ws) + align_up(sizeof(double) * 3 * N) * 3 + align_up(sizeof(double) * N) * 2 +
-           align_up(sizeof(double) * 6 * (size_t)nsteps);
+           align_up(sizeof(double) * kEnergyCols * (size_t)nsteps);
 }
 
 // Argument blocks of slot r (the replica was admitted with e_adm steps launched).
@@ -437,7 +437,7 @@ extern "C" int rbsog_ens_admit(rbsog_ens *s, const rbsog_params *p, const rbsog_
     R.f = take(sizeof(double) * 3 * N);
     R.q = take(sizeof(double) * N);
     R.m = take(sizeof(double) * N);
-    R.ehist = take(sizeof(double) * 6 * (size_t)nsteps);
+    R.ehist = take(sizeof(double) * kEnergyCols * (size_t)nsteps);
     R.N = p->N;
     R.P = p->P;
     R.ng = sog->n <= 8 ? sog->n : 0;
@@ -607,7 +607,7 @@ extern "C" int rbsog_ens_retire(rbsog_ens *s, int slot, double *x_host, double *
     if (e == hipSuccess && v_host)
         e = hipMemcpyAsync(v_host, R.v, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, s->st);
     if (e == hipSuccess && energy_hist_host)
-        e = hipMemcpyAsync(energy_hist_host, R.ehist, sizeof(double) * 6 * (size_t)R.nsteps, hipMemcpyDeviceToHost,
+        e = hipMemcpyAsync(energy_hist_host, R.ehist, sizeof(double) * kEnergyCols * (size_t)R.nsteps, hipMemcpyDeviceToHost,
                            s->st);
     if (e == hipSuccess) e = hipStreamSynchronize(s->st);
     if (e != hipSuccess) return ens_fail_hip(e, "reading the replica back");

@@ -24,6 +24,26 @@ double fhat(const rbsog_sog &s, double k2)
     return acc;
 }
 
+// The virial -3V dU/dV of the far part scales the configuration with the box:
+// rho(k) is unchanged, 1/V gives 3 U_F, and each k^2 = (2 pi / L)^2 m moves as
+// V^(-2/3), which adds -(1/V) sum_k k^2 G(k^2) |rho|^2 with G = -dFhat/d(k^2)
+// = sum_j A_j B_j exp(-B_j k^2).  A mode's term is therefore its energy term
+// times 2 (3/2 - vm), vm = k^2 G / Fhat; vm depends on |n|^2 = m only.
+void virial_table(const rbsog_sog &s, double L, int mmax, double *vm)
+{
+    const double t = (2.0 * kPi) / L;
+    for (int m = 0; m <= mmax; ++m) {
+        const double k2 = t * t * (double)m;
+        double F = 0.0, G = 0.0;
+        for (int j = 0; j < s.n; ++j) {
+            const double e = std::exp(-s.B[j] * k2);
+            F += s.A[j] * e;
+            G += s.A[j] * s.B[j] * e;
+        }
+        vm[m] = F > 0.0 ? k2 * G / F : 0.0;
+    }
+}
+
 // Correction factor of the measure.  ADAPTIVE is the leading Debye-Hueckel
 // term of eq. (3.22) as printed, with eps(k)^{-1}/k^2 = lambda^2/(1 + lambda^2 k^2)
 // for the Yukawa dielectric eps(k) = 1 + (lambda k)^{-2}.

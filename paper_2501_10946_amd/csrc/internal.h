@@ -53,6 +53,10 @@ void lattice_copy(int mmax, int32_t *out);
 double density(int kind, double kT, double V, double Q2, double lambda, double k2);
 // Fhat(k^2) = sum_m A_m exp(-B_m k^2) in ascending m
 double fhat(const rbsog_sog &s, double k2);
+// vm[m] = k^2 G(k^2) / Fhat(k^2) at k^2 = (2 pi / L)^2 m, m = 0 .. mmax, with
+// G = -dFhat/d(k^2): the factor a mode's term of the far-field virial carries
+// beside 3/2 of its energy term
+void virial_table(const rbsog_sog &s, double L, int mmax, double *vm);
 // shell CDF, coefficients and shell ranges; the packed lattice too when asked
 void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax, Tables *t, bool with_lattice);
 // (sin, cos)(2 pi j / kPhaseTable), j = 0 .. kPhaseTable - 1, interleaved, from

@@ -217,9 +217,15 @@ hipError_t launch_far(const FarArgs &a, hipStream_t st)
 __device__ inline void energy_body(const EnergyArgs &a, uint64_t shift)
 {
     __shared__ double red[kBlock];
-    double un = 0.0, ke = 0.0, uf = 0.0;
-    for (int b = threadIdx.x; b < a.nnear; b += kBlock) un += a.epart[b];
-    for (int l = threadIdx.x; l < a.P; l += kBlock) uf += a.eF[l];
+    double un = 0.0, ke = 0.0, uf = 0.0, wn = 0.0, wf = 0.0;
+    for (int b = threadIdx.x; b < a.nnear; b += kBlock) {
+        un += a.epart[b];
+        wn += a.epart[a.nnear + b];
+    }
+    for (int l = threadIdx.x; l < a.P; l += kBlock) {
+        uf += a.eF[l];
+        wf += a.eW[l];
+    }
     if (a.kepart)
         for (int b = threadIdx.x; b < a.nfar; b += kBlock) ke += a.kepart[b];
     un = block_sum_256(un, red);
@@ -227,14 +233,20 @@ __device__ inline void energy_body(const EnergyArgs &a, uint64_t shift)
     uf = block_sum_256(uf, red);
     __syncthreads();
     ke = block_sum_256(ke, red);
+    __syncthreads();
+    wn = block_sum_256(wn, red);
+    __syncthreads();
+    wf = block_sum_256(wf, red);
     if (threadIdx.x == 0) {
-        double *o = a.out + 6 * (shift + a.row0);
+        double *o = a.out + kEnergyCols * (shift + a.row0);
         o[0] = un;
         o[1] = uf;
         o[2] = a.Uk0;
         o[3] = a.Uself;
         o[4] = a.Ubg;
         o[5] = ke;
+        o[6] = wn;
+        o[7] = wf;
     }
 }
 
@@ -256,7 +268,7 @@ hipError_t launch_energy_batch(const EnergyArgs *tab, const EnsItem *items, int 
 
 hipError_t launch_energy(const EnergyArgs &a, hipStream_t st)
 {
-    if (!a.epart || !a.eF || !a.out) return hipErrorInvalidValue;
+    if (!a.epart || !a.eF || !a.eW || !a.out) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_energy, dim3(1), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }

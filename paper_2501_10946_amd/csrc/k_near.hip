@@ -177,7 +177,7 @@ __device__ inline double near_poly_eval(const double *c, double y)
 
 template <bool MIXED, bool ENERGY, int NG>
 __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const double4 &pj, double &fx, double &fy,
-                                  double &fz, double &en)
+                                  double &fz, double &en, double &vir)
 {
     const double L = a.g.L;
     // d by the minimum image (|d| < r_c <= L/3)
@@ -205,7 +205,10 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
         fx = fma(fac, dx, fx);
         fy = fma(fac, dy, fy);
         fz = fma(fac, dz, fz);
-        if (ENERGY) en = fma(qq, (double)(ey * irf - fs), en);
+        if (ENERGY) {
+            en = fma(qq, (double)(ey * irf - fs), en);
+            vir = fma(fac, r2, vir);   // d . F of the pair
+        }
     } else if constexpr (NG == kPolyNG) {
         // H(r) / r^3 and K(r) / r with H, K the polynomials in y = 2 r / r_c - 1
         double ir = rsqrt_f64(r2);
@@ -215,7 +218,10 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
         fx = fma(fac, dx, fx);
         fy = fma(fac, dy, fy);
         fz = fma(fac, dz, fz);
-        if (ENERGY) en = fma(qq, near_poly_eval(a.sog.kpoly, y) * ir, en);
+        if (ENERGY) {
+            en = fma(qq, near_poly_eval(a.sog.kpoly, y) * ir, en);
+            vir = fma(fac, r2, vir);   // d . F of the pair
+        }
     } else {
         double ir = rsqrt_f64(r2);
         double r = r2 * ir;
@@ -234,7 +240,10 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
         fx = fma(fac, dx, fx);
         fy = fma(fac, dy, fy);
         fz = fma(fac, dz, fz);
-        if (ENERGY) en = fma(qq, ey * ir - fs, en);
+        if (ENERGY) {
+            en = fma(qq, ey * ir - fs, en);
+            vir = fma(fac, r2, vir);   // d . F of the pair
+        }
     }
 }
 
@@ -443,7 +452,7 @@ __device__ inline void nlist_body(const NearArgs &a, int lb)
 template <bool MIXED, bool ENERGY, int NG>
 __device__ inline void near_body(const NearArgs &a, int lb)
 {
-    __shared__ double red[kEvalThreads];
+    __shared__ double2 red[kEvalThreads];
     const int t = threadIdx.x;
     const int grp = lb / kNearLanes;
     const int s = lb - grp * kNearLanes;   // this lane of the particle
@@ -454,7 +463,7 @@ __device__ inline void near_body(const NearArgs &a, int lb)
         pi = a.xs[p];
         total = a.nbr_cnt[p];
     }
-    double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0;
+    double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0, vir = 0.0;
     const int rows = list_rows(a.kp);
     if (total <= rows) {
         // lane s takes blocks s, s + kNearLanes, ... of the particle's list
@@ -492,8 +501,8 @@ __device__ inline void near_body(const NearArgs &a, int lb)
                     qa = a.xs[jj[e + 2]];
                     qb = a.xs[jj[e + 3]];
                 }
-                if (e < ne) pair_force<MIXED, ENERGY, NG>(a, pi, ca, fx, fy, fz, en);
-                if (e + 1 < ne) pair_force<MIXED, ENERGY, NG>(a, pi, cb, fx, fy, fz, en);
+                if (e < ne) pair_force<MIXED, ENERGY, NG>(a, pi, ca, fx, fy, fz, en, vir);
+                if (e + 1 < ne) pair_force<MIXED, ENERGY, NG>(a, pi, cb, fx, fy, fz, en, vir);
             }
         }
     } else {
@@ -515,7 +524,7 @@ __device__ inline void near_body(const NearArgs &a, int lb)
                         if (k >= n) break;
                         const int j0 = g[k].start_code & (int32_t)kIndexMask;
                         for (int j = j0; j < g[k].end; ++j)
-                            if (j != p) pair_force<MIXED, ENERGY, NG>(a, pi, a.xs[j], fx, fy, fz, en);
+                            if (j != p) pair_force<MIXED, ENERGY, NG>(a, pi, a.xs[j], fx, fy, fz, en, vir);
                     }
                 }
             }
@@ -527,14 +536,17 @@ __device__ inline void near_body(const NearArgs &a, int lb)
         o[a.N] = fy;
         o[2 * (size_t)a.N] = fz;
     }
-    if (ENERGY) {
-        red[t] = 0.5 * en;
+    if (ENERGY) {   // each pair is seen from both ends: half of its energy and virial from each
+        red[t] = make_double2(0.5 * en, 0.5 * vir);
         __syncthreads();
         for (int off = kEvalThreads / 2; off > 0; off >>= 1) {
-            if (t < off) red[t] += red[t + off];
+            if (t < off) red[t] = make_double2(red[t].x + red[t + off].x, red[t].y + red[t + off].y);
             __syncthreads();
         }
-        if (t == 0) a.epart[lb] = red[0];
+        if (t == 0) {
+            a.epart[lb] = red[0].x;
+            a.epart[near_blocks(a.N) + lb] = red[0].y;
+        }
     }
 }
 

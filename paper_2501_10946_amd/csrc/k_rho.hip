@@ -84,7 +84,7 @@ hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st)
 
 hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st)
 {
-    if (!a.part || !a.rho || !a.gk || !a.eF || !a.samp) return hipErrorInvalidValue;
+    if (!a.part || !a.rho || !a.gk || !a.eF || !a.samp || (a.eW && !a.vm)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_rho_reduce, dim3(rho_reduce_blocks(a.P)), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
@@ -130,6 +130,10 @@ __global__ __launch_bounds__(kBlock) void k_rho_full(RhoArgs a)
         a.rho[l] = make_double2(re, im);
         a.gk[l] = make_double2(cf * re, cf * im);
         a.eF[l] = 0.5 * cf * (re * re + im * im);
+        if (a.eW) {
+            const int m = (int)(k.x * k.x + k.y * k.y + k.z * k.z);
+            a.eW[l] = cf * (re * re + im * im) * (1.5 - a.vm[m]);
+        }
         if (a.rho_out) {
             a.rho_out[2 * l] = re;
             a.rho_out[2 * l + 1] = im;
@@ -139,7 +143,8 @@ __global__ __launch_bounds__(kBlock) void k_rho_full(RhoArgs a)
 
 hipError_t launch_rho_full(const RhoArgs &a, hipStream_t st)
 {
-    if (a.N < 1 || a.P < 1 || !a.xs || !a.samp || !a.rho || !a.gk || !a.eF || (!a.mixed && !a.tab))
+    if (a.N < 1 || a.P < 1 || !a.xs || !a.samp || !a.rho || !a.gk || !a.eF || (!a.mixed && !a.tab) ||
+        (a.eW && !a.vm))
         return hipErrorInvalidValue;
     dim3 grid((unsigned)((a.P + kBlock - 1) / kBlock));
     if (a.mixed) hipLaunchKernelGGL(k_rho_full<true>, grid, dim3(kBlock), 0, st, a);

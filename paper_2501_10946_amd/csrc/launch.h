@@ -163,6 +163,8 @@ struct RhoArgs {
     double2 *rho;              // [P]
     double2 *gk;               // [P] coef * rho
     double *eF;                // [P] coef |rho|^2 / 2
+    double *eW;                // null, or [P] coef |rho|^2 (3/2 - vm[|n|^2]): the modes' far-field virial terms
+    const double *vm;          // [m_max + 1] k^2 G / Fhat by |n|^2 (when eW)
     double *rho_out;           // [P][2] or null
     int mixed;
     const double2 *tab;        // [kPhaseTab] (sin, cos)(2 pi j / kPhaseTab) (FP64 path)
@@ -193,7 +195,7 @@ struct NearArgs {
     const double4 *xs;         // cell order
     const int32_t *cell_start;
     double *fnear;             // [kNearLanes][3][N] partial forces of the lanes of each particle, cell order
-    double *epart;             // [near_blocks(N)] energy partials (when energy)
+    double *epart;             // [2][near_blocks(N)] energy, then virial partials (when energy)
     int mixed;
     int energy;
     double w;                  // cell width L / nc (g is the fine grid, nc = floor(2L / r_c))
@@ -289,13 +291,16 @@ hipError_t launch_far(const FarArgs &a, hipStream_t st);
 hipError_t launch_far_batch(const FarArgs *tab, const EnsItem *items, int n, bool mixed, hipStream_t st);
 
 // --- energies ---------------------------------------------------------------
+// An energy row: U_N, U*_F, U_k0, U_self, U_bg, KE, W_N, W*_F.
+constexpr int kEnergyCols = 8;
 struct EnergyArgs {
     int nnear, nfar, P;
-    const double *epart;       // [nnear]
+    const double *epart;       // [2][nnear]: energy, then virial partials
     const double *kepart;      // [nfar] or null
     const double *eF;          // [P]
+    const double *eW;          // [P]
     double Uk0, Uself, Ubg;
-    double *out;               // [rows][6]; one system writes row row0
+    double *out;               // [rows][kEnergyCols]; one system writes row row0
     uint64_t row0;
 };
 hipError_t launch_energy(const EnergyArgs &a, hipStream_t st);

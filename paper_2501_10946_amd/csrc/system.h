@@ -27,7 +27,7 @@ constexpr size_t kAlign = 256;
 struct Layout {
     size_t lattice, cdf, coef, first, size;
     size_t cell_id, count, cell_start, fill, tmp, order, order_old, xs, xs_old, tile_sum, xb, vs, vs_old, fs, ms, ms_old;
-    size_t samp, part, rho, gk, eF, fnear, epart, kepart, flag, energy, nbr, nbr_cnt, tab;
+    size_t samp, part, rho, gk, eF, eW, vm, fnear, epart, kepart, flag, energy, nbr, nbr_cnt, tab;
     size_t total;
 };
 
@@ -76,7 +76,7 @@ struct rbsog_handle {
     SogDev sd;
     // views into the workspace
     int32_t *lattice, *first, *size, *cell_id, *count, *cell_start, *fill, *tmp, *order, *order_old, *flag, *tile_sum;
-    double *cdf, *coef, *eF, *fnear, *epart, *kepart, *energy, *xb;
+    double *cdf, *coef, *eF, *eW, *vm, *fnear, *epart, *kepart, *energy, *xb;
     double *vs, *vs_old, *fs, *ms, *ms_old;   // the stepped state in cell order (with xs)
     double4 *xs, *xs_old, *samp;
     double2 *part, *rho, *gk, *tab;

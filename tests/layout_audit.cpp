@@ -103,7 +103,10 @@ static void audit(int64_t N, double L, double lambda, double rc, int P, double s
     }
     CHECK(span(w.samp, w.part) >= 32 * (size_t)P * (size_t)d.sbatch, "%s: sampled modes", tag);
     CHECK(span(w.fnear, w.epart) >= 8 * 3 * (size_t)kNearLanes * (size_t)N, "%s: near partial forces", tag);
-    CHECK(span(w.epart, w.kepart) >= 8 * (size_t)near_blocks((int)N), "%s: near energy partials", tag);
+    CHECK(span(w.epart, w.kepart) >= 16 * (size_t)near_blocks((int)N), "%s: near energy and virial partials", tag);
+    CHECK(span(w.eW, w.vm) >= 8 * (size_t)d.nmodes, "%s: virial terms of the modes", tag);
+    // the reduction indexes vm by |n|^2 of a sampled mode, at most m_max
+    CHECK(span(w.vm, w.fnear) >= 8 * ((size_t)d.mmax + 1), "%s: virial factors by |n|^2", tag);
     CHECK(span(w.kepart, w.flag) >= 8 * (size_t)far_blocks((int)N), "%s: kinetic partials", tag);
     CHECK(span(w.xs, w.xs_old) >= 32 * (size_t)N && span(w.ms, w.ms_old) >= 8 * (size_t)N, "%s: rows", tag);
     CHECK(w.total >= w.tab + 16 * kPhaseTable, "%s: total", tag);

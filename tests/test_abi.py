@@ -89,7 +89,7 @@ def test_ensemble_sizing(R):
     p = R.make_params(1000, 16.1199, 1.0, 100, 1)
     b100 = R.rbsog_ens_bytes(p, sog, 100)
     b200 = R.rbsog_ens_bytes(p, sog, 200)
-    assert b100 % 256 == 0 and b200 >= b100 + 100 * 6 * 8
+    assert b100 % 256 == 0 and b200 >= b100 + 100 * 8 * 8
     assert b100 >= 11 * 8 * 1000
     big = R.make_params(8000, 2 * 16.1199, 1.0, 100, 1)
     assert R.rbsog_ens_bytes(big, sog, 100) > b100

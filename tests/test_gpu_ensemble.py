@@ -52,7 +52,7 @@ class Req:
         x = torch.tensor(self.st.x, device=dev)
         v = torch.tensor(self.st.v, device=dev)
         f = torch.empty_like(x)
-        e = torch.zeros((self.nsteps, 6), dtype=torch.float64, device=dev)
+        e = torch.zeros((self.nsteps, R.ENERGY_COLS), dtype=torch.float64, device=dev)
         R.rbsog_compute_forces(s.h, 0, x, f)
         R.rbsog_step(s.h, x, v, f, 0, self.nsteps, DT, e)
         torch.cuda.synchronize()
@@ -99,9 +99,9 @@ def run_ensemble(reqs, late, budget=1 << 30, max_slots=8):
                 r = reqs[inv[s]]
                 x = np.empty(3 * r.w.N)
                 v = np.empty(3 * r.w.N)
-                e = np.empty(6 * r.nsteps)
+                e = np.empty(R.ENERGY_COLS * r.nsteps)
                 R.rbsog_ens_retire(ens, s, x, v, e)
-                out[inv[s]] = (x.reshape(3, -1), v.reshape(3, -1), e.reshape(-1, 6))
+                out[inv[s]] = (x.reshape(3, -1), v.reshape(3, -1), e.reshape(-1, R.ENERGY_COLS))
             if len(out) == len(reqs):
                 break
         assert R.rbsog_ens_status(ens)["resident"] == 0
@@ -147,7 +147,7 @@ def test_ensemble_admission_and_timeline(dev):
     big = Req(W("e_big", N=3000, kappa=0.5, gamma=10.0, r_c=4.0, P=200, seed=51), 0, R.RBSOG_MIXED, 4)
     small = Req(W("e_small", N=800, kappa=1.0, gamma=1.0, r_c=3.0, P=50, seed=52), 1, R.RBSOG_FP64, 3)
     need = R.rbsog_ens_bytes(big.params, big.sog, big.nsteps)
-    assert need < R.rbsog_workspace_size(big.params, big.sog) + 11 * 8 * 3000 + 6 * 8 * 4 + 4096
+    assert need < R.rbsog_workspace_size(big.params, big.sog) + 11 * 8 * 3000 + R.ENERGY_COLS * 8 * 4 + 4096
     ens = R.rbsog_ens_create(need, 4)
     try:
         slot = big.admit(ens)

@@ -71,7 +71,7 @@ class Case:
         x = self.x if x is None else x
         f = torch.empty_like(x)
         fn = torch.empty_like(x)
-        e = torch.zeros(6, dtype=torch.float64, device=self.dev)
+        e = torch.zeros(R.ENERGY_COLS, dtype=torch.float64, device=self.dev)
         R.rbsog_compute_forces(self.sys.h, step, x, f, fn, e)
         torch.cuda.synchronize()
         return f.cpu().numpy(), fn.cpu().numpy(), e.cpu().numpy()
@@ -160,6 +160,14 @@ def test_forces_and_energy(dev, w, precision, skin):
         for k in (0, 1):
             assert abs(e[k] - eo[k]) <= tol * max(abs(eo[k]), 1e-300) + (1e-300 if eo[k] == 0 else 0)
         assert np.allclose(e[2:5], eo[2:5], rtol=1e-13, atol=0)
+        assert_virials(e, eo, tol)
+
+
+def assert_virials(e, eo, tol):
+    """Near and far virials of an energy row against the oracle's, relative to
+    the size of their terms (the far virial's mode terms change sign)."""
+    assert abs(e[6] - eo[6]) <= tol * (abs(eo[6]) + abs(eo[0])), f"W_N {e[6]} vs {eo[6]}"
+    assert abs(e[7] - eo[7]) <= tol * (abs(eo[7]) + 3 * abs(eo[1])), f"W_F {e[7]} vs {eo[7]}"
 
 
 def test_forces_repeatable(dev):
@@ -182,7 +190,7 @@ def test_trajectory_small_ocp(dev, precision):
     v = torch.tensor(c.st.v, device=dev)
     f, _, _ = c.forces(0)
     ft = torch.tensor(f, device=dev)
-    eh = torch.zeros((w.steps, 6), dtype=torch.float64, device=dev)
+    eh = torch.zeros((w.steps, R.ENERGY_COLS), dtype=torch.float64, device=dev)
     R.rbsog_step(c.sys.h, x, v, ft, 0, w.steps, w.dt, eh)
     R.rbsog_check(c.sys.h)
     xo, vo = c.st.x.copy(), c.st.v.copy()
@@ -192,8 +200,11 @@ def test_trajectory_small_ocp(dev, precision):
     d -= w.L * np.round(d / w.L)
     tol = 1e-10 if precision == 0 else 1e-4
     assert np.abs(d).max() <= tol
-    E, Eo = eh.cpu().numpy().sum(1), eho.sum(1)
+    ehn = eh.cpu().numpy()
+    E, Eo = ehn[:, :6].sum(1), eho[:, :6].sum(1)
     assert np.abs(E - Eo).max() <= (1e-9 if precision == 0 else 1e-3) * np.abs(Eo).max()
+    Wv, Wo = ehn[:, 6:].sum(1), eho[:, 6:].sum(1)
+    assert np.abs(Wv - Wo).max() <= (1e-9 if precision == 0 else 1e-3) * np.abs(Wo).max()
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -230,7 +241,7 @@ def test_split_calls_bit_exact(dev, precision):
         v = torch.tensor(c.st.v, device=dev)
         f, _, _ = c.forces(0)
         ft = torch.tensor(f, device=dev)
-        eh = torch.zeros((30, 6), dtype=torch.float64, device=dev)
+        eh = torch.zeros((30, R.ENERGY_COLS), dtype=torch.float64, device=dev)
         s0 = 0
         for n in split:
             R.rbsog_step(c.sys.h, x, v, ft, s0, n, w.dt, eh[s0:])
@@ -457,7 +468,7 @@ def test_full_k_forces_and_energy(dev, w, precision):
     for step in (3, 11):
         f = torch.empty_like(x)
         fn = torch.empty_like(x)
-        e = torch.zeros(6, dtype=torch.float64, device=dev)
+        e = torch.zeros(R.ENERGY_COLS, dtype=torch.float64, device=dev)
         R.rbsog_compute_forces(s.h, step, x, f, fn, e)
         torch.cuda.synchronize()
         outs.append((f.cpu().numpy(), fn.cpu().numpy(), e.cpu().numpy()))
@@ -469,6 +480,7 @@ def test_full_k_forces_and_energy(dev, w, precision):
     assert_close(f - fn, fo - fno, tol, "far")
     assert abs(e[1] - eo[1]) <= tol * abs(eo[1])
     assert np.allclose(e[[0, 2, 3, 4]], eo[[0, 2, 3, 4]], rtol=tol, atol=0)
+    assert_virials(e, eo, tol)
 
 
 def test_full_k_refuses_sampling_calls(dev):

@@ -90,10 +90,10 @@ def gpu_fluctuations(dev, w, st, o, density, draws=DRAWS):
     full = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, full_k=True, device=dev)
     x = torch.tensor(st.x, device=dev)
     ff = torch.empty_like(x)
-    ef = torch.zeros(6, dtype=torch.float64, device=dev)
+    ef = torch.zeros(R.ENERGY_COLS, dtype=torch.float64, device=dev)
     R.rbsog_compute_forces(full.h, 0, x, ff, None, ef)
     F = torch.empty((draws, 3, w.N), dtype=torch.float64, device=dev)
-    E = torch.zeros((draws, 6), dtype=torch.float64, device=dev)
+    E = torch.zeros((draws, R.ENERGY_COLS), dtype=torch.float64, device=dev)
     for s in range(draws):
         R.rbsog_compute_forces(rb.h, s, x, F[s], None, E[s])
     dE2 = (E[:, 1] - ef[1]) ** 2
