@@ -86,6 +86,8 @@ def lib():
             "orc_sys_run": (_i, [_p, _p, _p, _p, _u64, _i, _d, _p]),
             "orc_num_threads": (_i, []),
             "orc_ssf": (None, [_i64, _p, _p, _d, _i, _p]),
+            "orc_langevin_normals": (None, [_u64, _u64, _u64, _u32, _p]),
+            "orc_sys_set_langevin": (None, [_p, _d, _d]),
             "orc_rdf": (None, [_i64, _p, _d, _d, _i, _p, _p]),
         }
         for name, (res, args) in sig.items():
@@ -354,6 +356,10 @@ class System:
         lib().orc_sys_force(self._h, step, _ptr(x), _ptr(f), _ptr(fn), _ptr(e))
         return f, fn, e
 
+    def set_langevin(self, friction: float, bath_kT: float):
+        """Langevin thermostat for run() (friction 0: plain velocity-Verlet)."""
+        lib().orc_sys_set_langevin(self._h, friction, bath_kT)
+
     def run(self, x, v, f, step0: int, nsteps: int, dt: float):
         """Advances (x, v, f) in place; returns the [nsteps, 8] energy history (KE in column 5)."""
         eh = np.zeros((nsteps, 8))
@@ -361,6 +367,12 @@ class System:
         if r != 0:
             raise RuntimeError("a particle moved a full box length in one step")
         return eh
+
+
+def langevin_normals(i: int, step: int, seed: int, replica: int = 0) -> np.ndarray:
+    z = np.zeros(3)
+    lib().orc_langevin_normals(i, step, seed, replica, _ptr(z))
+    return z
 
 
 def ssf(x, w, L: float, mmax: int) -> np.ndarray:

@@ -870,6 +870,7 @@ typedef struct {
     int64_t N;
     double L, V, lambda, rc, kT, Q1, Q2;
     int P, mmax, density, full_k, nG;
+    double friction, bath_kT; /* Langevin thermostat (friction 0: plain velocity-Verlet) */
     uint64_t seed;
     uint32_t replica;
     double c[64], s[64], A[64], B[64];
@@ -999,20 +1000,64 @@ static double kinetic(const orc_sys *S, const double *v)
  * on entry.  For each of nsteps steps n = 0..nsteps-1:
  *   v += (dt/2) f / m;   x += dt v;   wrap x into [0, L);
  *   f = F(x, step0 + n + 1);   v += (dt/2) f / m.
+ * With a Langevin thermostat (friction g > 0, bath k_B T) the drift becomes the
+ * BAOAB splitting's A-O-A: x += (dt/2) v;  v = c v + sqrt((1 - c^2) k_B T / m) z
+ * with c = exp(-g dt) and z the particle's normals for force index
+ * step0 + n + 1 (orc_langevin_normals);  x += (dt/2) v. 
  * ehist (nullable) receives [nsteps][8] energy rows of the new state
  * (orc_sys_force's, with KE in slot 5).  Returns 0, or -1 if a particle moved a full box length. */
+/* The three normal deviates of particle i (caller index) for the thermostat
+ * step into force index `step`: Philox4x64-10(counter = (i, step, 1, 0), key
+ * = (seed, replica)) gives four uniforms u_k = ((w_k >> 11) + 1) 2^-53 in
+ * (0, 1], and the Box-Muller transform z0 + i z1 = sqrt(-2 ln u0) e^{2 pi i u1},
+ * z2 = sqrt(-2 ln u2) cos(2 pi u3) (counter word 2 = 1 keeps these apart from
+ * the mode draws, whose word 2 is 0). */
+void orc_langevin_normals(uint64_t i, uint64_t step, uint64_t seed, uint32_t replica, double z[3])
+{
+    uint64_t ctr[4] = {i, step, 1, 0}, key[2] = {seed, (uint64_t)replica}, w[4];
+    orc_philox4x64_10(ctr, key, w);
+    double u[4];
+    for (int k = 0; k < 4; ++k) u[k] = (double)((w[k] >> 11) + 1) * 0x1p-53;
+    double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+    z[0] = r0 * cos(2.0 * ORC_PI * u[1]);
+    z[1] = r0 * sin(2.0 * ORC_PI * u[1]);
+    z[2] = r1 * cos(2.0 * ORC_PI * u[3]);
+}
+
+/* Langevin thermostat for Algorithm 2's time loop: friction (per unit time)
+ * and bath temperature; friction 0 turns it off. */
+void orc_sys_set_langevin(orc_sys *S, double friction, double bath_kT)
+{
+    S->friction = friction;
+    S->bath_kT = bath_kT;
+}
+
 int orc_sys_run(const orc_sys *S, double *x, double *v, double *f, uint64_t step0, int nsteps, double dt,
                 double *ehist)
 {
     int64_t N = S->N;
     double L = S->L;
     int bad = 0;
+    const double c1 = exp(-S->friction * dt);
     for (int n = 0; n < nsteps; ++n) {
         for (int64_t i = 0; i < N; ++i) {
             double hm = (0.5 * dt) / S->m[i];
+            double z[3] = {0.0, 0.0, 0.0}, sig = 0.0;
+            if (S->friction > 0.0) {
+                orc_langevin_normals((uint64_t)i, step0 + (uint64_t)n + 1, S->seed, S->replica, z);
+                sig = sqrt((1.0 - c1 * c1) * S->bath_kT / S->m[i]);
+            }
             for (int d = 0; d < 3; ++d) {
                 double vv = v[d * N + i] + hm * f[d * N + i];
-                double dx = dt * vv;
+                double dx;
+                if (S->friction > 0.0) {
+                    /* BAOAB: half drift, Ornstein-Uhlenbeck velocity update, half drift */
+                    double v2 = c1 * vv + sig * z[d];
+                    dx = 0.5 * dt * vv + 0.5 * dt * v2;
+                    vv = v2;
+                } else {
+                    dx = dt * vv;
+                }
                 if (fabs(dx) >= L) bad = 1;
                 double xx = x[d * N + i] + dx;
                 if (xx >= L) xx -= L;
