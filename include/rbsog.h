@@ -292,6 +292,25 @@ int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double *f_dev, uin
 int rbsog_set_kT(rbsog_handle *h, double kT);
 
 /*
+ * Thermostat of rbsog_step (Algorithm 2 leaves the integration scheme and
+ * thermostat open; Section 5.1 runs NVT dynamics): a Langevin bath of
+ * friction `friction` (per unit time) at temperature kT, as the BAOAB
+ * splitting of the velocity-Verlet step -- the drift of each step becomes
+ *   x += (dt/2) v;  v = c v + sqrt((1 - c^2) kT / m) z;  x += (dt/2) v,
+ *   c = exp(-friction dt),
+ * with z three standard normals per particle and step: Philox4x64-10(counter =
+ * (caller index, force index the drift leads to, 1, 0), key = (seed,
+ * replica)) as four uniforms ((w >> 11) + 1) 2^-53, through the Box-Muller
+ * transform sqrt(-2 ln u0) (cos, sin)(2 pi u1), sqrt(-2 ln u2) cos(2 pi u3).
+ * Reproducible and independent of the cell order.  friction = 0 (the
+ * default) is plain velocity-Verlet (NVE).  The sampling measure keeps its
+ * own temperature (rbsog_set_kT).  Single systems only (the served ensemble
+ * runs NVE).  Errors: RBSOG_EINVAL (negative or non-finite friction, or kT not
+ * positive and finite with friction > 0).
+ */
+int rbsog_set_thermostat(rbsog_handle *h, double friction, double kT);
+
+/*
  * Synchronises the stream and reports the device flag: RBSOG_OK, or
  * RBSOG_ENONFINITE if any evaluation since the last check produced a
  * non-finite force or an over-long step (the flag is then cleared).
@@ -383,6 +402,48 @@ int rbsog_ens_retire(rbsog_ens *e, int slot, double *x_host, double *v_host, dou
 /* Resident replicas (active or finished, not yet retired), active replicas,
  * ensemble steps launched so far, free pool bytes (any may be null). */
 int rbsog_ens_status(const rbsog_ens *e, int *resident, int *active, uint64_t *ens_steps, size_t *pool_free);
+
+/* ------------------------------------------------------------------------
+ * Observables (Section 5.1)
+ * ------------------------------------------------------------------------ */
+
+/* Scratch bytes rbsog_ssf needs for N particles and shells 1..m_s (host
+ * only).  Errors: RBSOG_EINVAL. */
+int rbsog_ssf_scratch_size(int64_t N, int m_s, size_t *bytes);
+
+/*
+ * Static structure factor by lattice shell (Section 5.1: S(k) = <rho(k) rho(-k)> / N
+ * with rho the Fourier transform of the particle distribution), from the
+ * structure-factor kernels of the far field over every lattice mode with
+ * 1 <= |n|^2 <= m_s (k = 2 pi n / L, cubic box):
+ *   s_dev[m] = (1/cnt_m) sum_{|n|^2 = m} |sum_j w_j exp(i k . r_j)|^2,
+ * cnt_m the modes of shell m; s_dev[m] = 0 for m = 0 and for empty shells.
+ * With unit weights w_dev, S(|k|) = s_dev / N; with the charges, the charge
+ * structure factor.  x_dev [3][N] and w_dev [N] (device, caller order),
+ * s_dev [m_s + 1] (device).  FP64 (sums in a fixed order, bitwise
+ * reproducible).  scratch_dev: device memory of rbsog_ssf_scratch_size bytes,
+ * 256-byte aligned, owned by the caller.  Work ~ N * (4/3) pi m_s^(3/2)
+ * (particle, mode) terms.  Enqueued on hip_stream and synchronised before
+ * returning (the host-side tables of the modes are released then).
+ * Errors: RBSOG_EINVAL, RBSOG_EWORKSPACE, RBSOG_EHIP.
+ */
+int rbsog_ssf(int64_t N, double L, const double *x_dev, const double *w_dev, int m_s, void *scratch_dev,
+              size_t scratch_bytes, void *hip_stream, double *s_dev);
+
+/*
+ * Pair-distance histogram behind the radial distribution function (Section
+ * 5.1): for every ordered pair (i, j), i != j, with minimum-image distance
+ * r < r_max, adds 1 to hist_dev[floor(r / dr)], dr = r_max / nbins (uint64,
+ * device; the caller zeroes it, so that calls over many configurations
+ * accumulate).  g(r) of bin b = hist[b] / (snapshots N (N / V) (4/3) pi
+ * ((b + 1)^3 - b^3) dr^3).  x_dev [3][N] in [0, L) (device, caller order).
+ * 0 < r_max <= r_c of the system, 1 <= nbins <= 4096.  Uses the system's fine
+ * cell grid (its workspace rows are reordered; the next force evaluation
+ * rebuilds its lists).  Integer counts, independent of the order of the
+ * additions; a pair within rounding of a bin edge may fall on either side.
+ * Asynchronous on the handle's stream.  Errors: RBSOG_EINVAL, RBSOG_EHIP.
+ */
+int rbsog_rdf(rbsog_handle *h, const double *x_dev, double r_max, int nbins, unsigned long long *hist_dev);
 
 /* Milliseconds from rbsog_ens_create to the device completion of ensemble
  * step ens_step (1-based, one of the last 8192 launched); waits for it.

@@ -88,6 +88,7 @@ def lib() -> C.CDLL:
             "rbsog_step": (C.c_int, [_p, _p, _p, _p, C.c_uint64, C.c_int, C.c_double, _p]),
             "rbsog_check": (C.c_int, [_p]),
             "rbsog_set_kT": (C.c_int, [_p, C.c_double]),
+            "rbsog_set_thermostat": (C.c_int, [_p, C.c_double, C.c_double]),
             "rbsog_timing_enable": (C.c_int, [_p, C.c_int]),
             "rbsog_timing_read": (C.c_int, [_p, C.POINTER(rbsog_timing)]),
             "rbsog_destroy": (None, [_p]),
@@ -104,6 +105,9 @@ def lib() -> C.CDLL:
             "rbsog_ens_step_time": (C.c_int, [_p, C.c_uint64, C.POINTER(C.c_double)]),
             "rbsog_ens_destroy": (None, [_p]),
             "rbsog_rho_noalloc": (C.c_int, [C.c_int64, C.c_double, _p, _p, C.c_int, _p, C.c_int, _p, _p]),
+            "rbsog_ssf_scratch_size": (C.c_int, [C.c_int64, C.c_int, C.POINTER(C.c_size_t)]),
+            "rbsog_ssf": (C.c_int, [C.c_int64, C.c_double, _p, _p, C.c_int, _p, C.c_size_t, _p, _p]),
+            "rbsog_rdf": (C.c_int, [_p, _p, C.c_double, C.c_int, _p]),
             "rbsog_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -254,6 +258,34 @@ def rbsog_rho_noalloc(x, q, L: float, n, rho, precision: int = RBSOG_FP64, strea
     _check(lib().rbsog_rho_noalloc(N, L, _dptr(x, torch.float64, 3 * N), _dptr(q, torch.float64, N), P,
                                    _dptr(n, torch.int32, 3 * P), precision, stream or _stream(x.device),
                                    _dptr(rho, torch.float64, 2 * P)))
+
+
+def rbsog_set_thermostat(h, friction: float, kT: float) -> None:
+    """Langevin bath (BAOAB) for rbsog_step; friction 0 turns it off."""
+    _check(lib().rbsog_set_thermostat(h, friction, kT))
+
+
+def rbsog_ssf_scratch_size(N: int, m_s: int) -> int:
+    b = C.c_size_t(0)
+    _check(lib().rbsog_ssf_scratch_size(N, m_s, C.byref(b)))
+    return b.value
+
+
+def rbsog_ssf(x, w, L: float, m_s: int, scratch, s, stream=None) -> None:
+    """Shell means of |sum_j w_j exp(i k.r_j)|^2 for |n|^2 = 0..m_s into s
+    [m_s + 1] (S(k) = s / N with unit weights)."""
+    import torch
+    N = w.numel()
+    _check(lib().rbsog_ssf(N, L, _dptr(x, torch.float64, 3 * N), _dptr(w, torch.float64, N), m_s,
+                           _dptr(scratch), scratch.numel() * scratch.element_size(), stream or _stream(x.device),
+                           _dptr(s, torch.float64, m_s + 1)))
+
+
+def rbsog_rdf(h, x, r_max: float, nbins: int, hist) -> None:
+    """Adds the ordered-pair counts by distance bin into hist [nbins] (int64)."""
+    import torch
+    N, P, _ = _n(h)
+    _check(lib().rbsog_rdf(h, _dptr(x, torch.float64, 3 * N), r_max, nbins, _dptr(hist, torch.int64, nbins)))
 
 
 def rbsog_check(h) -> None:

@@ -386,8 +386,22 @@ EnergyArgs energy_args(rbsog_handle *h, double *out, bool kick)
 
 // Structure factors, near field, far field (+ optional kick) and the energy
 // sums of one evaluation whose cell order, lists and modes are prepared.
+Thermo thermo(const rbsog_handle *h, double dt, uint64_t step)
+{
+    Thermo t{};
+    if (h->friction > 0.0) {
+        t.on = 1;
+        t.c1 = std::exp(-h->friction * dt);
+        t.c2kT = (1.0 - t.c1 * t.c1) * h->bath_kT;
+        t.seed = h->p.seed;
+        t.replica = h->p.replica;
+        t.step = step;
+    }
+    return t;
+}
+
 int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bool kick, double dt, double *energy,
-             int32_t *gate_raise, int32_t *gate_clear)
+             int32_t *gate_raise, int32_t *gate_clear, uint64_t next_step)
 {
     RhoArgs ra = rho_args(h, samp);
     NearArgs na = near_args(h, nullptr, energy != nullptr);
@@ -411,6 +425,7 @@ int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bo
         fa.xb = h->xb;
         fa.xs_next = h->xs;
         fa.gate_raise = gate_raise;
+        fa.th = thermo(h, dt, next_step);
     }
     HIPCHECK(timed(h, kFar, [&] { return launch_far(fa, h->st); }));
     if (energy) {
@@ -733,7 +748,8 @@ bool adapt_skin(rbsog_handle *h, double dt)
 {
     if (!h->skin_default || h->d.skin == 0.0 || !(dt > h->dt_checked) || !(h->m_min > 0.0)) return false;
     h->dt_checked = dt;
-    const double vmax = std::sqrt(2.0 * std::log(3.0 * (double)h->p.N + 1.0) * h->p.kT / h->m_min);
+    const double kT = std::max(h->p.kT, h->bath_kT);   // a thermostat may hold the system hotter
+    const double vmax = std::sqrt(2.0 * std::log(3.0 * (double)h->p.N + 1.0) * kT / h->m_min);
     if (!(0.5 * h->d.skin < 2.0 * vmax * dt)) return false;
     drop_skin(h);
     return true;
@@ -792,6 +808,8 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         k.gate = gate;
         k.gate_next = gate_next;
         k.flag = h->flag;
+        k.th = thermo(h, dt, step0 + 1);
+        k.order = h->order;
         HIPCHECK(timed(h, kKickDrift, [&] { return launch_kick_drift(k, h->st); }));
     }
     for (int n = 0; n < nsteps; ++n) {
@@ -803,7 +821,7 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         rc = modes(h, step, nsteps - n, &samp);
         if (rc) return rc;
         double *e = energy_hist_dev ? energy_hist_dev + kEnergyCols * (size_t)n : nullptr;
-        rc = evaluate(h, samp, nullptr, nullptr, true, dt, e, n + 1 < nsteps ? gate_next : nullptr, gate);
+        rc = evaluate(h, samp, nullptr, nullptr, true, dt, e, n + 1 < nsteps ? gate_next : nullptr, gate, step + 1);
         if (rc) return rc;
         h->phase = 1 - h->phase;
     }
@@ -895,6 +913,18 @@ extern "C" int rbsog_set_kT(rbsog_handle *h, double kT)
     h->p.kT = kT;
     h->S = t.S;
     h->samp_n = 0;   // modes drawn ahead with the old measure are drawn again
+    return RBSOG_OK;
+}
+
+extern "C" int rbsog_set_thermostat(rbsog_handle *h, double friction, double kT)
+{
+    if (!h) return fail(RBSOG_EINVAL, "null handle");
+    if (!(friction >= 0.0) || !std::isfinite(friction)) return fail(RBSOG_EINVAL, "friction must be >= 0 and finite");
+    if (friction > 0.0 && (!(kT > 0.0) || !std::isfinite(kT)))
+        return fail(RBSOG_EINVAL, "the bath temperature must be positive and finite");
+    if (friction > 0.0 && kT > h->bath_kT) h->dt_checked = 0.0;   // the default skin's thermal check runs again
+    h->friction = friction;
+    h->bath_kT = friction > 0.0 ? kT : 0.0;
     return RBSOG_OK;
 }
 

@@ -52,19 +52,51 @@ __device__ inline double block_sum_256(double v, double *red)
     return red[0];
 }
 
+// The thermostat's three normal deviates of particle i (caller index) for the
+// drift into force index `step`: four uniforms ((w >> 11) + 1) 2^-53 in (0, 1]
+// from Philox4x64-10(counter (i, step, 1, 0), key (seed, replica)) -- word 2 =
+// 1 keeps them apart from the mode draws -- through the Box-Muller transform.
+__device__ inline void langevin_normals(uint64_t i, const Thermo &th, double z[3])
+{
+    uint64_t w[4];
+    philox4x64_10(i, th.step, 1, 0, th.seed, (uint64_t)th.replica, w);
+    double u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) u[k] = (double)((w[k] >> 11) + 1) * 0x1p-53;
+    const double twopi = 6.283185307179586;
+    const double r0 = sqrt(-2.0 * log(u[0])), r1 = sqrt(-2.0 * log(u[2]));
+    z[0] = r0 * cos(twopi * u[1]);
+    z[1] = r0 * sin(twopi * u[1]);
+    z[2] = r1 * cos(twopi * u[3]);
+}
+
 // First half-kick and drift of one particle (cell position p): v += hm f,
 // x += dt v, wrapped into [0, L); returns the squared minimum-image distance
 // from the build position xb and sets *bad on a step of a box length or more.
 // The drift kernel and the far kernel's fused form both run this, so that
-// their trajectories agree bit for bit.
+// their trajectories agree bit for bit.  hm = dt / (2 m); with a thermostat
+// on, ci is the particle's caller index and m its mass.
 __device__ inline double kick_drift_row(double x[3], double v[3], const double f[3], double hm, double dt, double L,
-                                        double inv_L, const double *xb, int N, int p, bool *bad)
+                                        double inv_L, const double *xb, int N, int p, bool *bad,
+                                        const Thermo &th, uint64_t ci, double m)
 {
     double d2 = 0.0;
+    double z[3] = {0.0, 0.0, 0.0}, sig = 0.0;
+    if (th.on) {
+        langevin_normals(ci, th, z);
+        sig = sqrt(th.c2kT / m);
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         double vv = v[d] + hm * f[d];
-        double dx = dt * vv;
+        double dx;
+        if (th.on) {   // half drift, Ornstein-Uhlenbeck update, half drift
+            const double v2 = th.c1 * vv + sig * z[d];
+            dx = 0.5 * dt * vv + 0.5 * dt * v2;
+            vv = v2;
+        } else {
+            dx = dt * vv;
+        }
         *bad |= !(fabs(dx) < L);
         double xx = x[d] + dx;
         if (xx >= L) xx -= L;

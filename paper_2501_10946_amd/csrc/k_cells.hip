@@ -229,7 +229,8 @@ __device__ inline void kick_drift_body(const KickDriftArgs &a, int b)
     double v[3] = {a.vs[p], a.vs[a.N + p], a.vs[2 * a.N + p]};
     const double f[3] = {a.fs[p], a.fs[a.N + p], a.fs[2 * a.N + p]};
     bool bad = false;
-    double d2 = kick_drift_row(x, v, f, hm, a.dt, a.L, a.inv_L, a.xb, a.N, p, &bad);
+    double d2 = kick_drift_row(x, v, f, hm, a.dt, a.L, a.inv_L, a.xb, a.N, p, &bad, a.th,
+                               a.th.on ? (uint64_t)a.order[p] : 0, a.ms[p]);
     for (int d = 0; d < 3; ++d) a.vs[d * a.N + p] = v[d];
     a.xs[p] = make_double4(x[0], x[1], x[2], r.w);
     raise_any(a.flag, bad);
@@ -240,7 +241,8 @@ RBSOG_KERNELS(kick_drift, KickDriftArgs, kBlock)
 
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t st)
 {
-    if (a.N < 1 || !a.xs || !a.vs || !a.fs || !a.ms || !a.xb || !a.gate || !a.flag) return hipErrorInvalidValue;
+    if (a.N < 1 || !a.xs || !a.vs || !a.fs || !a.ms || !a.xb || !a.gate || !a.flag || (a.th.on && !a.order))
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_kick_drift, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }

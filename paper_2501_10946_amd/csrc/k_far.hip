@@ -146,7 +146,8 @@ __device__ inline void far_body(const FarArgs &a, int b)
                 double x[3] = {pi.x, pi.y, pi.z}, v[3] = {vx, vy, vz};
                 const double f[3] = {fx, fy, fz};
                 bool bad = false;
-                double d2 = kick_drift_row(x, v, f, hm, a.dt, a.L, a.inv_L, a.xb, a.N, p, &bad);
+                double d2 = kick_drift_row(x, v, f, hm, a.dt, a.L, a.inv_L, a.xb, a.N, p, &bad, a.th,
+                                           a.th.on ? (uint64_t)a.order[p] : 0, mi);
                 vx = v[0];
                 vy = v[1];
                 vz = v[2];

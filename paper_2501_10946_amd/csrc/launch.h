@@ -112,6 +112,18 @@ hipError_t launch_state_in(const PermArgs &a, hipStream_t st);
 hipError_t launch_state_out(const PermArgs &a, hipStream_t st);
 
 // --- integration ------------------------------------------------------------
+// Langevin thermostat in the drift (on != 0): the drift becomes the A-O-A of
+// the BAOAB splitting, x += (dt/2) v;  v = c1 v + sqrt(c2kT / m) z;  x += (dt/2) v,
+// z the particle's normals for force index `step` (langevin_normals).
+struct Thermo {
+    int on;
+    double c1;                 // exp(-friction dt)
+    double c2kT;               // (1 - c1^2) k_B T of the bath
+    uint64_t seed;
+    uint32_t replica;
+    uint64_t step;             // force index the drift leads to
+};
+
 // First half-kick and drift in cell order.
 struct KickDriftArgs {
     int N;
@@ -125,6 +137,8 @@ struct KickDriftArgs {
     int32_t *gate;         // raised when a particle moved more than skin / 2 since the build
     int32_t *gate_next;    // null, or the next step's gate, cleared
     int *flag;             // set to 1 on a step of a box length or more
+    Thermo th;
+    const int32_t *order;  // caller index of each row (the thermostat's noise counter; when th.on)
 };
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t st);
 hipError_t launch_kick_drift_batch(const KickDriftArgs *tab, const EnsItem *per256, int n, hipStream_t st);
@@ -285,6 +299,7 @@ struct FarArgs {
     const double *xb;          // SoA [3][N] positions at the last build, cell order
     double4 *xs_next;
     int32_t *gate_raise;
+    Thermo th;                 // the drift's thermostat (single systems)
 };
 hipError_t launch_far(const FarArgs &a, hipStream_t st);
 // ensemble: far_blocks items per replica

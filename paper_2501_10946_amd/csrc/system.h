@@ -100,6 +100,8 @@ struct rbsog_handle {
     // free again once kt_ev has completed
     double *kt_host = nullptr;
     hipEvent_t kt_ev = nullptr;
+    // Langevin thermostat of rbsog_step (rbsog_set_thermostat; friction 0: off)
+    double friction = 0.0, bath_kT = 0.0;
     // per-kernel event timing (rbsog_timing_enable)
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -164,7 +166,10 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
                   size_t ws_bytes, hipStream_t stream, const int32_t *lattice_dev, rbsog_handle **out);
 // gate_raise non-null (with kick): the far kernel also applies the next
 // step's first half-kick and drift, raising gate_raise; gate_clear is cleared
+// the thermostat of a step's drift into force index `step` (off without friction)
+Thermo thermo(const rbsog_handle *h, double dt, uint64_t step);
+// with gate_raise the far kernel also drifts into force index next_step
 int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bool kick, double dt, double *energy,
-             int32_t *gate_raise = nullptr, int32_t *gate_clear = nullptr);
+             int32_t *gate_raise = nullptr, int32_t *gate_clear = nullptr, uint64_t next_step = 0);
 
 }  // namespace rbsog
