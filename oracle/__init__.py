@@ -57,6 +57,13 @@ def lib():
             "orc_sog_maxerr": (_d, [_d, _d, _d, _d, _d, _i, _i]),
             "orc_sog_auto": (_i, [_d, _d, _d, _p, _p, _p, _p, _p, _p]),
             "orc_sog_expand": (None, [_d, _d, _d, _d, _i, _i, _p, _p, _p, _p]),
+            "orc_sog_expand_s": (None, [_d, _d, _d, _d, _d, _i, _i, _p, _p, _p, _p]),
+            "orc_yukawa_dr2": (_d, [_d, _d]),
+            "orc_sog_far2": (_d, [_d, _d, _d, _d, _d, _i, _i, _d]),
+            "orc_sog_c2_residual": (_d, [_d, _d, _d, _d, _i, _i]),
+            "orc_sog_c2_root": (_i, [_d, _d, _d, _i, _i, _p, _p, _p]),
+            "orc_sog_maxerr2": (_d, [_d, _d, _d, _d, _d, _d, _i, _i]),
+            "orc_sog_auto2": (_i, [_d, _d, _d, _p, _p, _p, _p, _p, _p, _p]),
             "orc_F": (_d, [_i, _p, _p, _d]),
             "orc_Fhat": (_d, [_i, _p, _p, _d]),
             "orc_Fhat_slope": (_d, [_i, _p, _p, _d]),
@@ -124,6 +131,8 @@ class SOG:
     A: np.ndarray = None
     B: np.ndarray = None
     err: float = float("nan")
+    sigma: float = 1.0    # bandwidth factor of the narrowest Gaussian (Appendix C; 1 for C1)
+    smooth: int = 1
 
     @property
     def n(self) -> int:
@@ -140,8 +149,8 @@ class SOG:
     def expand(self) -> "SOG":
         n = self.n
         self.c, self.s, self.A, self.B = (np.zeros(n) for _ in range(4))
-        lib().orc_sog_expand(self.lam, self.h, self.t0, self.w, self.M1, self.M2, _ptr(self.c), _ptr(self.s),
-                             _ptr(self.A), _ptr(self.B))
+        lib().orc_sog_expand_s(self.lam, self.h, self.t0, self.w, self.sigma, self.M1, self.M2, _ptr(self.c),
+                               _ptr(self.s), _ptr(self.A), _ptr(self.B))
         return self
 
     def F(self, r) -> np.ndarray:
@@ -180,6 +189,30 @@ def sog_auto(lam: float, rc: float, eps: float) -> SOG:
     s = SOG(lam, rc, h.value, t0.value, w.value, M1.value, M2.value).expand()
     s.err = err.value
     return s
+
+
+def sog_c2(lam: float, rc: float, h: float, M1: int, M2: int) -> SOG:
+    """The C2-continuous decomposition of Appendix C for given M1, M2."""
+    t0, w, sg = C.c_double(), C.c_double(), C.c_double()
+    if lib().orc_sog_c2_root(lam, rc, h, M1, M2, C.byref(t0), C.byref(w), C.byref(sg)) != 0:
+        raise ValueError("no C2 root with positive weight and bandwidth")
+    return SOG(lam, rc, h, t0.value, w.value, M1, M2, sigma=sg.value, smooth=2).expand()
+
+
+def sog_auto2(lam: float, rc: float, eps: float) -> SOG:
+    M1, M2 = C.c_int(), C.c_int()
+    h, t0, w, sg, err = (C.c_double() for _ in range(5))
+    r = lib().orc_sog_auto2(lam, rc, eps, C.byref(M1), C.byref(M2), C.byref(h), C.byref(t0), C.byref(w),
+                            C.byref(sg), C.byref(err))
+    if r != 0:
+        raise ValueError("no C2 SOG found")
+    s = SOG(lam, rc, h.value, t0.value, w.value, M1.value, M2.value, sigma=sg.value, smooth=2).expand()
+    s.err = err.value
+    return s
+
+
+def sog_far2(s: SOG, r) -> float:
+    return lib().orc_sog_far2(s.lam, s.h, s.t0, s.w, s.sigma, s.M1, s.M2, r)
 
 
 def sog_w(lam, rc, h, t0, M1, M2) -> float:

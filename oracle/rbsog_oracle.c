@@ -230,6 +230,139 @@ int orc_sog_auto(double lambda, double rc, double eps, int *M1_out, int *M2_out,
     return -1;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Appendix C: the C2-continuous decomposition                                */
+/* ------------------------------------------------------------------------- */
+
+/* Narrowest Gaussian of eq. (c2), its bandwidth scaled by sigma:
+ * g(r) = pi^{-1/2} exp(-r^2 e^{t} sigma - e^{-t}/(4 lambda^2) + t/2), t = t_M2. */
+static double orc_g2(double t, double sigma, double r, double lambda)
+{
+    return exp(-r * r * exp(t) * sigma - exp(-t) / (4.0 * lambda * lambda) + 0.5 * t) / sqrt(ORC_PI);
+}
+
+/* d^2 Y / dr^2 = exp(-r/lambda) (1/(lambda^2 r) + 2/(lambda r^2) + 2/r^3). */
+double orc_yukawa_dr2(double r, double lambda)
+{
+    return exp(-r / lambda) * (1.0 / (lambda * lambda * r) + 2.0 / (lambda * r * r) + 2.0 / (r * r * r));
+}
+
+/* F(r) of eq. (c2): h [ w g(r) + sum_{m=-M1}^{M2-1} f(t_m, r) ]. */
+double orc_sog_far2(double lambda, double h, double t0, double w, double sigma, int M1, int M2, double r)
+{
+    double acc = 0.0;
+    for (int m = -M1; m <= M2 - 1; ++m) acc += orc_f(t0 + m * h, r, lambda);
+    return h * (w * orc_g2(t0 + M2 * h, sigma, r, lambda) + acc);
+}
+
+typedef struct { double lambda, rc, h; int M1, M2; } c2_ctx;
+
+/* For a given t0 the potential and force conditions at rc fix the narrowest
+ * Gaussian: with S the fixed-weight sum, P0 = Y(rc)/h - S(rc) = w g(rc) and
+ * P1 = Y'(rc)/h - S'(rc) = w g'(rc), and g'/g = -2 r e^{t_M2} sigma, so
+ * b := e^{t_M2} sigma = -P1 / (2 rc P0) and w = P0 / g(rc).  Returns the
+ * curvature residual Y''(rc)/h - S''(rc) - w g''(rc), g'' = (4 r^2 b^2 - 2 b) g,
+ * and (through the pointers, when given) sigma and w; NaN where b or P0 is
+ * not positive. */
+static double c2_solve(double t0, const c2_ctx *c, double *sigma_out, double *w_out)
+{
+    double S0 = 0.0, S1 = 0.0, S2 = 0.0, r = c->rc;
+    for (int m = -c->M1; m <= c->M2 - 1; ++m) {
+        double t = t0 + m * c->h, a = exp(t), fv = orc_f(t, r, c->lambda);
+        S0 += fv;
+        S1 += -2.0 * r * a * fv;
+        S2 += (4.0 * r * r * a * a - 2.0 * a) * fv;
+    }
+    double P0 = orc_yukawa(r, c->lambda) / c->h - S0;
+    double P1 = orc_yukawa_dr(r, c->lambda) / c->h - S1;
+    double b = -P1 / (2.0 * r * P0);
+    if (!(P0 > 0.0) || !(b > 0.0) || !isfinite(b)) return NAN;
+    double tm = t0 + c->M2 * c->h;
+    double sigma = b / exp(tm);
+    double g = orc_g2(tm, sigma, r, c->lambda);
+    if (!(g >= DBL_MIN / DBL_EPSILON)) return NAN;
+    if (sigma_out) *sigma_out = sigma;
+    if (w_out) *w_out = P0 / g;
+    return orc_yukawa_dr2(r, c->lambda) / c->h - S2 - P0 * (4.0 * r * r * b * b - 2.0 * b);
+}
+
+static double c2_residual(double t0, void *vctx) { return c2_solve(t0, (const c2_ctx *)vctx, NULL, NULL); }
+
+double orc_sog_c2_residual(double lambda, double rc, double h, double t0, int M1, int M2)
+{
+    c2_ctx c = {lambda, rc, h, M1, M2};
+    return c2_residual(t0, &c);
+}
+
+/* Smallest t0 in [0, h) where C0, C1 and C2 hold together with w > 0 and
+ * sigma > e^{-h} -- the adjusted Gaussian stays the narrowest, its exponent
+ * e^{t_M2} sigma above its neighbour's e^{t_M2 - h}: the interval scanned in
+ * 400 pieces, each sign change of the curvature residual refined by Brent's
+ * method. */
+int orc_sog_c2_root(double lambda, double rc, double h, int M1, int M2, double *t0_out, double *w_out,
+                    double *sigma_out)
+{
+    c2_ctx c = {lambda, rc, h, M1, M2};
+    const int nscan = 400;
+    double a = 0.0, fa = c2_residual(a, &c);
+    for (int k = 0; k < nscan; ++k) {
+        double b = (double)(k + 1) * h / (double)nscan;
+        double fb = c2_residual(b, &c);
+        double root = NAN;
+        if (fa == 0.0) root = a;
+        else if ((fa < 0.0 && fb > 0.0) || (fa > 0.0 && fb < 0.0)) root = brent(c2_residual, &c, a, b, fa, fb, 1e-15);
+        if (!isnan(root) && !(fabs(c2_residual(root, &c)) <= 1e-8 * fabs(orc_yukawa_dr2(rc, lambda) / h))) root = NAN;
+        if (!isnan(root) && root < h) {
+            double sg, w;
+            c2_solve(root, &c, &sg, &w);
+            if (w > 0.0 && isfinite(w) && sg > exp(-h) && isfinite(sg)) {
+                *t0_out = root;
+                *w_out = w;
+                *sigma_out = sg;
+                return 0;
+            }
+        }
+        a = b; fa = fb;
+    }
+    return -1;
+}
+
+/* max |Y - F| of eq. (c2) on the grid of orc_sog_maxerr. */
+double orc_sog_maxerr2(double lambda, double rc, double h, double t0, double w, double sigma, int M1, int M2)
+{
+    double R = 33.0 * lambda, emax = 0.0;
+    for (int j = 0; j <= 1600; ++j) {
+        double u = (double)j / 1600.0;
+        double r = rc + (R - rc) * u * u;
+        double e = fabs(orc_yukawa(r, lambda) - orc_sog_far2(lambda, h, t0, w, sigma, M1, M2, r));
+        if (e > emax) emax = e;
+    }
+    return emax;
+}
+
+/* Automatic numbers of Gaussians for the C2 decomposition, by the rule of
+ * orc_sog_auto (smallest M_tot, M2 from -12 up, first set meeting eps). */
+int orc_sog_auto2(double lambda, double rc, double eps, int *M1_out, int *M2_out, double *h_out, double *t0_out,
+                  double *w_out, double *sigma_out, double *err_out)
+{
+    double h = orc_h_star(eps, rc);
+    for (int Mtot = 1; Mtot <= 48; ++Mtot) {
+        for (int M2 = -12; M2 <= Mtot - 1; ++M2) {
+            int M1 = Mtot - 1 - M2;
+            if (M1 < 0) continue;
+            double t0, w, sg;
+            if (orc_sog_c2_root(lambda, rc, h, M1, M2, &t0, &w, &sg) != 0) continue;
+            double err = orc_sog_maxerr2(lambda, rc, h, t0, w, sg, M1, M2);
+            if (err <= eps) {
+                *M1_out = M1; *M2_out = M2; *h_out = h; *t0_out = t0; *w_out = w; *sigma_out = sg;
+                *err_out = err;
+                return 0;
+            }
+        }
+    }
+    return -1;
+}
+
 /* Expansion of the SOG (eq. 2.41) into Gaussian coefficients, index
  * j = m + M1 for m = -M1..M2 (ascending m), and of its 3-D Fourier transform
  * (Section 4.1, the transform of F):
@@ -239,8 +372,19 @@ int orc_sog_auto(double lambda, double rc, double eps, int *M1_out, int *M2_out,
  * so that F(r) = sum_j c_j exp(-s_j r^2) and Fhat(k) = sum_j A_j exp(-B_j k^2).
  * The evaluation order of every expression is part of the contract with the
  * sampler (the shell weights must be reproducible bit for bit). */
+void orc_sog_expand_s(double lambda, double h, double t0, double w, double sigma, int M1, int M2, double *c,
+                      double *s, double *A, double *B);
+
 void orc_sog_expand(double lambda, double h, double t0, double w, int M1, int M2, double *c, double *s,
                     double *A, double *B)
+{
+    orc_sog_expand_s(lambda, h, t0, w, 1.0, M1, M2, c, s, A, B);
+}
+
+/* The same with the narrowest Gaussian's bandwidth scaled by sigma (the C2
+ * form of Appendix C: s_j = e^{t_M2} sigma at m = M2; sigma = 1 is the C1 form). */
+void orc_sog_expand_s(double lambda, double h, double t0, double w, double sigma, int M1, int M2, double *c,
+                      double *s, double *A, double *B)
 {
     const double pi = ORC_PI;
     const double pi32 = pi * sqrt(pi);
@@ -250,7 +394,10 @@ void orc_sog_expand(double lambda, double h, double t0, double w, int M1, int M2
         double t = t0 + (double)m * h;
         double sj = exp(t);
         double cj = (h / sqrt(pi)) * exp(0.5 * t - exp(-t) * inv4l2);
-        if (m == M2) cj = cj * w;
+        if (m == M2) {
+            cj = cj * w;
+            sj = sj * sigma;
+        }
         c[j] = cj;
         s[j] = sj;
         A[j] = pi32 * cj / (sj * sqrt(sj));
