@@ -69,7 +69,8 @@ extern "C" {
 /*
  * SOG decomposition Y(r) = N(r) + F(r) of the Yukawa kernel
  * Y(r) = exp(-r/lambda)/r (Section 3, Algorithm 1, C1-continuous form):
- *   F(r)    = h [ w f(t_{M2}, r) + sum_{m=-M1}^{M2-1} f(t_m, r) ]  (eq. 2.41)
+ *   F(r)    = h [ w f(t_{M2}, r) + sum_{m=-M1}^{M2-1} f(t_m, r) ]  (eq. 2.41;
+ *             with smooth = 2 the m = M2 term has exponent e^{t_M2} sigma r^2, eq. c2)
  *           = sum_j c[j] exp(-s[j] r^2),     j = m + M1, m = -M1..M2,
  *   Fhat(k) = sum_j A[j] exp(-B[j] k^2)      (its 3-D Fourier transform, Section 4.1),
  * with f(t,r) = pi^{-1/2} exp(-r^2 e^t - e^{-t}/(4 lambda^2) + t/2) (eq. ftr),
@@ -84,19 +85,28 @@ typedef struct rbsog_sog {
     double F0;               /* F(0) = sum c                                         */
     double Fhat0;            /* Fhat(0) = sum A                                      */
     double max_err;          /* max |Y - F| on [r_c, 33 lambda] (sampled densely)    */
+    int smooth;              /* 2: the C2 form of Appendix C (sigma used); else C1   */
+    double sigma;            /* C2: the narrowest Gaussian's exponent is e^{t_M2} sigma */
 } rbsog_sog;
 
 /*
- * Algorithm 1 (Section 3.2): h from eq. (2.30) with delta = r_c, then the
- * smallest starting point t0 in [0, h) that makes the decomposition C1 at r_c
- * (eq. 1.25) with w from the C0 condition (eq. 2.42) and w > 0.  With
- * M1 = M2 = RBSOG_AUTO the smallest total M1 + M2 + 1 whose error on
+ * Algorithm 1 (Section 3.2): h from eq. (2.30) with delta = r_c, then
+ * smooth = 1: the smallest starting point t0 in [0, h) that makes the
+ *   decomposition C1 at r_c (eq. 1.25) with w from the C0 condition
+ *   (eq. 2.42) and w > 0;
+ * smooth = 2 (Appendix C, eq. c2): the narrowest Gaussian also gets a
+ *   bandwidth factor sigma, and (t0, w, sigma) make Y - F vanish at r_c with
+ *   its first and second derivatives: for each t0 the first two conditions
+ *   give sigma and w in closed form and the curvature condition is solved in
+ *   t0 (smallest root in [0, h) with w > 0 and sigma > e^{-h}, so that the
+ *   adjusted Gaussian stays the narrowest).
+ * With M1 = M2 = RBSOG_AUTO the smallest total M1 + M2 + 1 whose error on
  * [r_c, 33 lambda] is <= eps is chosen (for each total, M2 = -12 upward);
  * otherwise the given M1 >= 0, M2 are used.  Host only, no GPU needed.
  * Errors: RBSOG_EINVAL (lambda, r_c or eps not positive and finite,
- * r_c >= 33 lambda, eps >= 1, bad M1/M2), RBSOG_ENOROOT.
+ * r_c >= 33 lambda, eps >= 1, smooth not 1 or 2, bad M1/M2), RBSOG_ENOROOT.
  */
-int rbsog_sog_init(double lambda, double r_c, double eps, int M1, int M2, rbsog_sog *out);
+int rbsog_sog_init(double lambda, double r_c, double eps, int smooth, int M1, int M2, rbsog_sog *out);
 
 /*
  * Recomputes c, s, A, B, F0, Fhat0 and max_err of *sog from its lambda, r_c,

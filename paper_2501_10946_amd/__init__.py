@@ -38,7 +38,8 @@ class rbsog_sog(C.Structure):
                 ("M1", C.c_int), ("M2", C.c_int), ("n", C.c_int),
                 ("c", C.c_double * RBSOG_MAX_GAUSS), ("s", C.c_double * RBSOG_MAX_GAUSS),
                 ("A", C.c_double * RBSOG_MAX_GAUSS), ("B", C.c_double * RBSOG_MAX_GAUSS),
-                ("F0", C.c_double), ("Fhat0", C.c_double), ("max_err", C.c_double)]
+                ("F0", C.c_double), ("Fhat0", C.c_double), ("max_err", C.c_double),
+                ("smooth", C.c_int), ("sigma", C.c_double)]
 
 
 class rbsog_params(C.Structure):
@@ -74,7 +75,8 @@ def lib() -> C.CDLL:
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
         L = C.CDLL(LIB_PATH)
         sig = {
-            "rbsog_sog_init": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.POINTER(rbsog_sog)]),
+            "rbsog_sog_init": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
+                                         C.POINTER(rbsog_sog)]),
             "rbsog_sog_expand": (C.c_int, [C.POINTER(rbsog_sog)]),
             "rbsog_sog_near_poly": (C.c_int, [C.POINTER(rbsog_sog), _p, _p]),
             "rbsog_workspace_size": (C.c_int, [C.POINTER(rbsog_params), C.POINTER(rbsog_sog), C.POINTER(C.c_size_t)]),
@@ -147,9 +149,10 @@ def _stream(device=None) -> C.c_void_p:
 
 # --- host functions ---------------------------------------------------------------
 
-def rbsog_sog_init(lambda_: float, r_c: float, eps: float, M1: int = RBSOG_AUTO, M2: int = RBSOG_AUTO) -> rbsog_sog:
+def rbsog_sog_init(lambda_: float, r_c: float, eps: float, M1: int = RBSOG_AUTO, M2: int = RBSOG_AUTO,
+                   smooth: int = 1) -> rbsog_sog:
     out = rbsog_sog()
-    _check(lib().rbsog_sog_init(lambda_, r_c, eps, M1, M2, C.byref(out)))
+    _check(lib().rbsog_sog_init(lambda_, r_c, eps, smooth, M1, M2, C.byref(out)))
     return out
 
 
@@ -171,11 +174,13 @@ def rbsog_sog_near_poly(sog: rbsog_sog):
 
 
 def sog_from_parameters(lambda_: float, r_c: float, h: float, t0: float, w: float, M1: int, M2: int,
-                        eps: float = 0.0) -> rbsog_sog:
-    """A decomposition given by its parameters (h, t0, w, M1, M2), expanded by the library."""
+                        eps: float = 0.0, sigma: float = None) -> rbsog_sog:
+    """A decomposition given by its parameters (h, t0, w, M1, M2, and sigma for
+    the C2 form), expanded by the library."""
     s = rbsog_sog()
     s.lambda_, s.r_c, s.eps, s.h, s.t0, s.w, s.M1, s.M2 = lambda_, r_c, eps, h, t0, w, M1, M2
     s.n = M1 + M2 + 1
+    s.smooth, s.sigma = (1, 1.0) if sigma is None else (2, sigma)
     return rbsog_sog_expand(s)
 
 

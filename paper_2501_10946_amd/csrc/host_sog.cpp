@@ -1,5 +1,5 @@
 // Host side of Algorithm 1 (Section 3.2): the C1-continuous sum-of-Gaussians
-// decomposition of the Yukawa kernel.  Built with -ffp-contract=off so that
+// decomposition of the Yukawa kernel, and its C2-continuous form (Appendix C).  Built with -ffp-contract=off so that
 // the coefficient expansion is a fixed sequence of IEEE FP64 operations.
 #include <cfloat>
 #include <cmath>
@@ -60,6 +60,43 @@ struct C1Problem {
     }
 };
 
+// The C2 form (Appendix C, eq. c2): the narrowest Gaussian m = M2 has the
+// exponent e^{t} sigma r^2, g(r) = pi^{-1/2} exp(-r^2 e^t sigma - e^{-t}/(4 lambda^2) + t/2).
+// With S the fixed-weight sum (and S', S'' its r-derivatives), the value and
+// slope conditions at r_c read w g = Y/h - S =: P0 and w g' = Y'/h - S' =: P1;
+// since g'/g = -2 r e^t sigma they give b = e^t sigma = -P1 / (2 r_c P0) and
+// w = P0 / g, and leave the curvature condition, with g'' = (4 r^2 b^2 - 2 b) g,
+//   R(t0) = Y''/h - S'' - P0 (4 r_c^2 b^2 - 2 b) = 0.
+struct C2Problem {
+    double lambda, rc, h;
+    int M1, M2;
+    double y, yp, ypp;  // Y, Y', Y'' at rc
+
+    // residual of the curvature condition; sigma and w through the pointers;
+    // NaN where P0 or b is not positive or g underflows
+    double solve(double t0, double *sigma, double *w) const
+    {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int m = -M1; m < M2; ++m) {
+            const double t = t0 + m * h, a = std::exp(t), f = integrand(t, rc, lambda);
+            s0 += f;
+            s1 += -2.0 * rc * a * f;
+            s2 += (4.0 * rc * rc * a * a - 2.0 * a) * f;
+        }
+        const double p0 = y / h - s0, p1 = yp / h - s1;
+        const double b = -p1 / (2.0 * rc * p0);
+        if (!(p0 > 0.0) || !(b > 0.0) || !std::isfinite(b)) return NAN;
+        const double tm = t0 + M2 * h;
+        const double sg = b / std::exp(tm);
+        const double g = std::exp(-rc * rc * std::exp(tm) * sg - std::exp(-tm) / (4.0 * lambda * lambda) + 0.5 * tm) /
+                         std::sqrt(kPi);
+        if (!(g >= DBL_MIN / DBL_EPSILON)) return NAN;
+        if (sigma) *sigma = sg;
+        if (w) *w = p0 / g;
+        return ypp / h - s2 - p0 * (4.0 * rc * rc * b * b - 2.0 * b);
+    }
+};
+
 }  // namespace
 
 double step_size(double eps, double delta)
@@ -111,6 +148,51 @@ int c1_start(double lambda, double rc, double h, int M1, int M2, double *t0_out,
     return -1;
 }
 
+// Smallest t0 in [0, h) where the C2 conditions hold with w > 0 and sigma >
+// e^{-h} (the adjusted Gaussian stays narrower than its neighbour m = M2 - 1):
+// 400 equal pieces, each sign change bisected to the resolution of FP64.
+int c2_start(double lambda, double rc, double h, int M1, int M2, double *t0_out, double *w_out, double *sigma_out)
+{
+    const double e = std::exp(-rc / lambda);
+    C2Problem pb{lambda, rc, h, M1, M2, e / rc, -e * (1.0 / (lambda * rc) + 1.0 / (rc * rc)),
+                 e * (1.0 / (lambda * lambda * rc) + 2.0 / (lambda * rc * rc) + 2.0 / (rc * rc * rc))};
+    const int pieces = 400;
+    double a = 0.0, ra = pb.solve(a, nullptr, nullptr);
+    for (int k = 1; k <= pieces; ++k) {
+        double b = (double)k * h / (double)pieces;
+        double rb = pb.solve(b, nullptr, nullptr);
+        double root = NAN;
+        if (ra == 0.0) {
+            root = a;
+        } else if ((ra < 0.0 && rb > 0.0) || (ra > 0.0 && rb < 0.0)) {
+            double lo = a, hi = b, rlo = ra;
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                double rm = pb.solve(mid, nullptr, nullptr);
+                if (std::isnan(rm)) break;
+                if (rm == 0.0) { lo = hi = mid; break; }
+                if ((rm < 0.0) == (rlo < 0.0)) { lo = mid; rlo = rm; } else { hi = mid; }
+            }
+            root = 0.5 * (lo + hi);
+            if (!(std::fabs(pb.solve(root, nullptr, nullptr)) <= 1e-8 * std::fabs(pb.ypp / h))) root = NAN;
+        }
+        if (!std::isnan(root) && root < h) {
+            double sg = NAN, w = NAN;
+            pb.solve(root, &sg, &w);
+            if (w > 0.0 && std::isfinite(w) && sg > std::exp(-h) && std::isfinite(sg)) {
+                *t0_out = root;
+                *w_out = w;
+                *sigma_out = sg;
+                return 0;
+            }
+        }
+        a = b;
+        ra = rb;
+    }
+    return -1;
+}
+
 void expand(rbsog_sog *s)
 {
     const double pi = kPi;
@@ -123,7 +205,10 @@ void expand(rbsog_sog *s)
         double t = s->t0 + (double)m * s->h;
         double sj = std::exp(t);
         double cj = (s->h / std::sqrt(pi)) * std::exp(0.5 * t - std::exp(-t) * inv4l2);
-        if (m == s->M2) cj = cj * s->w;
+        if (m == s->M2) {
+            cj = cj * s->w;
+            if (s->smooth == 2) sj = sj * s->sigma;
+        }
         s->c[j] = cj;
         s->s[j] = sj;
         s->A[j] = pi32 * cj / (sj * std::sqrt(sj));
@@ -155,13 +240,14 @@ double sog_max_error(const rbsog_sog &s)
 
 using namespace rbsog;
 
-extern "C" int rbsog_sog_init(double lambda, double r_c, double eps, int M1, int M2, rbsog_sog *out)
+extern "C" int rbsog_sog_init(double lambda, double r_c, double eps, int smooth, int M1, int M2, rbsog_sog *out)
 {
     if (!out) return fail(RBSOG_EINVAL, "rbsog_sog_init: out is null");
     if (!(lambda > 0.0) || !std::isfinite(lambda) || !(r_c > 0.0) || !std::isfinite(r_c))
         return fail(RBSOG_EINVAL, "rbsog_sog_init: lambda and r_c must be positive and finite");
     if (!(eps > 0.0 && eps < 1.0)) return fail(RBSOG_EINVAL, "rbsog_sog_init: eps must lie in (0, 1)");
     if (!(r_c < 33.0 * lambda)) return fail(RBSOG_EINVAL, "rbsog_sog_init: r_c must be below 33 lambda");
+    if (smooth != 1 && smooth != 2) return fail(RBSOG_EINVAL, "rbsog_sog_init: smooth must be 1 or 2");
     bool autom = (M1 == RBSOG_AUTO && M2 == RBSOG_AUTO);
     if (!autom && (M1 < 0 || M1 + M2 + 1 < 1 || M1 + M2 + 1 > RBSOG_MAX_GAUSS))
         return fail(RBSOG_EINVAL, "rbsog_sog_init: need M1 >= 0 and 1 <= M1+M2+1 <= %d", RBSOG_MAX_GAUSS);
@@ -170,11 +256,18 @@ extern "C" int rbsog_sog_init(double lambda, double r_c, double eps, int M1, int
     s.r_c = r_c;
     s.eps = eps;
     s.h = step_size(eps, r_c);
+    s.smooth = smooth;
+    s.sigma = 1.0;
+    auto start = [&](int m1, int m2) {
+        return smooth == 2 ? c2_start(lambda, r_c, s.h, m1, m2, &s.t0, &s.w, &s.sigma)
+                           : c1_start(lambda, r_c, s.h, m1, m2, &s.t0, &s.w);
+    };
     if (!autom) {
         s.M1 = M1;
         s.M2 = M2;
-        if (c1_start(lambda, r_c, s.h, M1, M2, &s.t0, &s.w) != 0)
-            return fail(RBSOG_ENOROOT, "rbsog_sog_init: no C1 starting point with w > 0 for M1=%d M2=%d", M1, M2);
+        if (start(M1, M2) != 0)
+            return fail(RBSOG_ENOROOT, "rbsog_sog_init: no C%d starting point with w > 0 for M1=%d M2=%d", smooth, M1,
+                        M2);
         expand(&s);
         s.max_err = sog_max_error(s);
         *out = s;
@@ -184,12 +277,9 @@ extern "C" int rbsog_sog_init(double lambda, double r_c, double eps, int M1, int
         for (int m2 = -12; m2 <= total - 1; ++m2) {
             int m1 = total - 1 - m2;
             if (m1 < 0) continue;
-            double t0, w;
-            if (c1_start(lambda, r_c, s.h, m1, m2, &t0, &w) != 0) continue;
+            if (start(m1, m2) != 0) continue;
             s.M1 = m1;
             s.M2 = m2;
-            s.t0 = t0;
-            s.w = w;
             expand(&s);
             s.max_err = sog_max_error(s);
             if (s.max_err <= eps) {
@@ -210,6 +300,8 @@ extern "C" int rbsog_sog_expand(rbsog_sog *sog)
     if (!(sog->lambda > 0.0) || !(sog->h > 0.0) || !(sog->r_c > 0.0) || !std::isfinite(sog->t0) ||
         !std::isfinite(sog->w))
         return fail(RBSOG_EINVAL, "rbsog_sog_expand: lambda, h, r_c must be positive and t0, w finite");
+    if (sog->smooth == 2 && !(sog->sigma > 0.0 && std::isfinite(sog->sigma)))
+        return fail(RBSOG_EINVAL, "rbsog_sog_expand: the C2 form needs a positive, finite sigma");
     expand(sog);
     sog->max_err = sog_max_error(*sog);
     return RBSOG_OK;

@@ -41,7 +41,7 @@ static size_t span(size_t a, size_t b) { return b - a; }   // bytes between two 
 static void audit(int64_t N, double L, double lambda, double rc, int P, double skin)
 {
     rbsog_sog s{};
-    if (rbsog_sog_init(lambda, rc, 1e-4, RBSOG_AUTO, RBSOG_AUTO, &s) != RBSOG_OK) {
+    if (rbsog_sog_init(lambda, rc, 1e-4, 1, RBSOG_AUTO, RBSOG_AUTO, &s) != RBSOG_OK) {
         std::printf("skip: no SOG for lambda %g r_c %g\n", lambda, rc);
         return;
     }

@@ -56,12 +56,41 @@ def test_sog_init_matches_oracle(R, lam, rc, eps):
     assert abs(s.max_err - o.err) <= 1e-3 * eps
 
 
+@pytest.mark.parametrize("lam,rc,eps", [(0.5773, 2.8865, 1e-3), (0.5773, 2.8865, 1e-5), (1.0, 3.0, 1e-4),
+                                        (10.0, 5.0, 1e-4), (0.5773, 2.8865, 1e-9), (0.5773, 2.8865, 1e-13)])
+def test_sog_init_c2_matches_oracle(R, lam, rc, eps):
+    """The C2 form (Appendix C) by the library's own solver: the oracle's
+    numbers of Gaussians, the step bit for bit, (t0, w, sigma) within 1e-13 at
+    eps >= 1e-5 (the curvature root is well conditioned there) and, at any
+    eps, the same decomposition to within a thousandth of eps on the grid."""
+    s = R.rbsog_sog_init(lam, rc, eps, smooth=2)
+    o = oracle.sog_auto2(lam, rc, eps)
+    assert s.smooth == 2 and (s.M1, s.M2) == (o.M1, o.M2) and s.h == o.h
+    if eps >= 1e-5:
+        assert abs(s.t0 - o.t0) <= 1e-13 * o.h
+        assert abs(s.w - o.w) <= 1e-13 and abs(s.sigma - o.sigma) <= 1e-13
+    assert s.max_err <= eps
+    R_ = 33 * lam
+    r = rc + (R_ - rc) * (np.arange(1601) / 1600.0) ** 2
+    Fl = (np.array(s.c[: s.n])[None, :] * np.exp(-np.array(s.s[: s.n])[None, :] * r[:, None] ** 2)).sum(1)
+    assert np.abs(Fl - o.F(r)).max() <= 1e-3 * eps
+
+
+def test_sog_init_refuses_bad_smoothness(R):
+    with pytest.raises(R.RbsogError):
+        R.rbsog_sog_init(1.0, 3.0, 1e-4, smooth=3)
+
+
 def test_expansion_is_bitwise(R):
     """Given the same parameters, library and oracle expand to the same bits."""
     o = oracle.sog_auto(2.0, 4.0, 1e-4)
     s = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
     for a, b in ((s.c, o.c), (s.s, o.s), (s.A, o.A), (s.B, o.B)):
         assert np.array_equal(np.array(a[: o.n]).view(np.uint64), np.asarray(b).view(np.uint64))
+    o2 = oracle.sog_auto2(2.0, 4.0, 1e-5)   # and the C2 form with its sigma
+    s2 = R.sog_from_parameters(o2.lam, o2.rc, o2.h, o2.t0, o2.w, o2.M1, o2.M2, sigma=o2.sigma)
+    for a, b in ((s2.c, o2.c), (s2.s, o2.s), (s2.A, o2.A), (s2.B, o2.B)):
+        assert np.array_equal(np.array(a[: o2.n]).view(np.uint64), np.asarray(b).view(np.uint64))
 
 
 def test_host_errors(R):
