@@ -543,6 +543,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rates", default="0.5,0.8,1.2",
                     help="Poisson arrival rates as fractions of the measured saturated capacity")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the served-ensemble measurement, printed as its own JSON line (for profiling)")
     ap.add_argument("--copy-calibration", type=float, default=0.0,
                     help="MiB of an elementwise FP64 copy (y = 2x) to run first, as a known-traffic reference "
                          "for hardware byte counters")
@@ -558,6 +560,10 @@ def main():
     import oracle
     import paper_2501_10946_amd as R
     import workloads
+
+    if args.serve_only:
+        print(json.dumps({"served": serve(args, torch.device("cuda:0"))}), flush=True)
+        return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")

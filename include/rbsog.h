@@ -187,7 +187,7 @@ typedef struct rbsog_info {
     double skin;        /* neighbour-list skin in use                              */
     int nf;             /* cells per axis of the force evaluation's fine grid      */
     int near_capacity;  /* kp: a particle's neighbour list holds up to 5 kp entries */
-    int near_poly;      /* 1: the FP64 pair kernel uses the polynomial H, K        */
+    int near_poly;      /* 1: the FP64 pair kernel uses the polynomial H, K (0 in mixed precision) */
 } rbsog_info;
 
 /*

@@ -17,6 +17,7 @@
 namespace rbsog {
 
 static_assert(kPhaseTable == kPhaseTab, "host and device rotation tables differ in size");
+static_assert(kFarTable == kFarTab, "host and device far-field tables differ in size");
 
 namespace {
 thread_local std::string g_error;
@@ -131,6 +132,7 @@ Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
     L.nbr = take(sizeof(int32_t) * (size_t)list_rows(d.kp) * (size_t)list_padded(N));
     L.nbr_cnt = take(sizeof(int32_t) * (size_t)N);
     L.tab = take(sizeof(double) * 2 * kPhaseTable);
+    L.tab_far = take(sizeof(double) * 2 * kFarTable);
     L.total = off;
     return L;
 }
@@ -362,8 +364,8 @@ FarArgs far_args(rbsog_handle *h, const double4 *samp, double *f, double *f_near
     fa.kepart = kick ? h->kepart : nullptr;
     fa.flag = h->flag;
     fa.mixed = h->p.precision == RBSOG_MIXED;
-    fa.tab = h->tab;
-    fa.ss = make_sincos_short();
+    fa.tab = h->tab_far;
+    fa.ss = make_sincos_far();
     return fa;
 }
 
@@ -411,6 +413,16 @@ int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bo
         // the partial sums run in the near kernel's first workgroups
         na.red = ra;
         na.nrho = (int)((rho_blocks(ra.nchunk, ra.P) + 7) / 8 * 8);
+        // Spread through a launch of several rounds of workgroups, the partial
+        // sums fill the issue slots the near field's gathers leave (near launches
+        // of the plasmas: N = 2e5, 4 178 workgroups, 115 -> 108 us; N = 6e5,
+        // 536 -> 450 us; N = 1e6, 19 350 workgroups, 0.91 -> 0.74 ms).  A launch
+        // the chip holds at once gains nothing from that and runs best with the
+        // longer partial-sum workgroups dispatched first (N = 1e5: 1 789
+        // workgroups, 49.5 us first, 53.6 us spread).
+        na.interleave = (int64_t)na.nrho + near_blocks((int)h->p.N) >= kInterleaveBlocks;
+        if (const char *e = std::getenv("RBSOG_NEAR_INTERLEAVE"))   // 0 / 1: a tuning knob
+            na.interleave = std::atoi(e) != 0;
     }
     HIPCHECK(timed(h, kNear, [&] { return launch_near(na, h->st); }));
     if (!h->d.full_k) HIPCHECK(timed(h, kRhoReduce, [&] { return launch_rho_reduce(ra, h->st); }));
@@ -471,7 +483,8 @@ extern "C" int rbsog_create(const rbsog_params *p, const rbsog_sog *s, const dou
 namespace rbsog {
 
 int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev, const double *m_dev, void *ws_dev,
-                  size_t ws_bytes, hipStream_t stream, const int32_t *lattice_dev, rbsog_handle **out)
+                  size_t ws_bytes, hipStream_t stream, const int32_t *lattice_dev, rbsog_handle **out,
+                  const double *q_host, const double *m_host, bool sync)
 {
     int rc = check_params(p, s);
     if (rc) return rc;
@@ -498,23 +511,30 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
         delete h;
         return fail(RBSOG_EWORKSPACE, "workspace of %zu bytes is below the %zu needed", ws_bytes, need);
     }
-    // sum q and sum q^2 in particle order (they enter the measure, eq. 3.22)
-    std::vector<double> qh((size_t)p->N);
-    hipError_t e = hipMemcpyAsync(qh.data(), q_dev, sizeof(double) * (size_t)p->N, hipMemcpyDeviceToHost, h->st);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
-    if (e != hipSuccess) {
-        delete h;
-        return fail(RBSOG_EHIP, "reading q: %s", hipGetErrorString(e));
+    // sum q and sum q^2 in particle order (they enter the measure, eq. 3.22),
+    // from the caller's host copies when given, else read back from the device
+    std::vector<double> qh;
+    hipError_t e = hipSuccess;
+    if (!q_host || !m_host) {
+        qh.resize((size_t)p->N);
+        e = hipMemcpyAsync(qh.data(), q_dev, sizeof(double) * (size_t)p->N, hipMemcpyDeviceToHost, h->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(RBSOG_EHIP, "reading q: %s", hipGetErrorString(e));
+        }
     }
     double q1 = 0.0, q2 = 0.0;
-    charge_sums(qh.data(), p->N, &q1, &q2);
-    e = hipMemcpyAsync(qh.data(), m_dev, sizeof(double) * (size_t)p->N, hipMemcpyDeviceToHost, h->st);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
-    if (e != hipSuccess) {
-        delete h;
-        return fail(RBSOG_EHIP, "reading m: %s", hipGetErrorString(e));
+    charge_sums(q_host ? q_host : qh.data(), p->N, &q1, &q2);
+    if (!q_host || !m_host) {
+        e = hipMemcpyAsync(qh.data(), m_dev, sizeof(double) * (size_t)p->N, hipMemcpyDeviceToHost, h->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(RBSOG_EHIP, "reading m: %s", hipGetErrorString(e));
+        }
     }
-    h->m_min = *std::min_element(qh.begin(), qh.end());
+    h->m_min = (q_host && m_host) ? *std::min_element(m_host, m_host + p->N) : *std::min_element(qh.begin(), qh.end());
     h->skin_default = p->skin < 0.0;   // only the default skin adapts
     h->dt_checked = 0.0;
     h->rb_host = nullptr;
@@ -575,6 +595,7 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     h->nbr = (int32_t *)(w + L.nbr);
     h->nbr_cnt = (int32_t *)(w + L.nbr_cnt);
     h->tab = (double2 *)(w + L.tab);
+    h->tab_far = (double2 *)(w + L.tab_far);
     double tabh[2 * kPhaseTable];
     phase_table(tabh);
     h->lists_valid = false;
@@ -589,6 +610,10 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->size, t.shell_size.data(), sizeof(int32_t) * t.nshell, hipMemcpyHostToDevice, h->st);
     if (e == hipSuccess) e = hipMemcpyAsync(h->tab, tabh, sizeof(tabh), hipMemcpyHostToDevice, h->st);
+    std::vector<double> tabf(2 * (size_t)kFarTable);
+    far_table(tabf.data());
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->tab_far, tabf.data(), sizeof(double) * tabf.size(), hipMemcpyHostToDevice, h->st);
     std::vector<double> vmh((size_t)h->d.mmax + 1);
     virial_table(*s, p->L, h->d.mmax, vmh.data());
     if (e == hipSuccess)
@@ -613,7 +638,10 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     if (e == hipSuccess) e = hipMemsetAsync(h->flag, 0, sizeof(int32_t) * 8, h->st);
     if (e == hipSuccess) e = hipMemsetAsync(h->count, 0, L.cell_start - L.count, h->st);
     if (e == hipSuccess) e = launch_iota(h->order, (int)p->N, h->st);   // a cell order before the first build
-    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    // the uploads above are from host memory this function releases: pageable
+    // copies are staged by the runtime before the calls return, so only the
+    // single-system path's documented synchronisation remains
+    if (e == hipSuccess && sync) e = hipStreamSynchronize(h->st);
     if (e != hipSuccess) {
         delete h;
         return fail(RBSOG_EHIP, "uploading tables: %s", hipGetErrorString(e));
@@ -629,7 +657,9 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
         h->sd.cs2[j] = 2.0 * s->c[j] * s->s[j];
     }
     static_assert(kNearPolyDeg + 1 == sizeof(h->sd.hpoly) / sizeof(double), "near polynomial size");
-    h->sd.poly = near_poly(*s, s->r_c, h->sd.hpoly, h->sd.kpoly) ? 1 : 0;
+    // the polynomial pair function serves the FP64 kernels only (mixed precision
+    // evaluates the exponentials in FP32), so a mixed system skips the fit
+    h->sd.poly = (p->precision == RBSOG_FP64 && near_poly(*s, s->r_c, h->sd.hpoly, h->sd.kpoly)) ? 1 : 0;
     h->sd.y_scale = 2.0 / s->r_c;
     if (const char *e = std::getenv("RBSOG_NEAR_POLY"))   // 0: evaluate the Gaussians one by one
         if (std::atoi(e) == 0) h->sd.poly = 0;

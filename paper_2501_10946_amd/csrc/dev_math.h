@@ -166,6 +166,41 @@ __device__ inline void sincos_rev_tab(double w, const double2 *tab, const SinCos
     *c = fma(t.y, cp, -(t.x * sp));
 }
 
+// The far field's finer table: 1024 entries (16 KB of LDS, which only the far
+// kernel carries), so that the remainder |f| <= 1/2 in 1/1024 revolutions is
+// at most pi/1024 rad and degree-5/4 series suffice (first omitted terms below
+// 6e-22 relative to sin and 2e-18 absolute for cos): two FMA fewer per
+// (particle, mode) than the 128-entry form.
+constexpr int kFarTab = 1024;
+struct SinCosFar {
+    double s[3];
+    double c[3];
+};
+constexpr SinCosFar make_sincos_far()
+{
+    SinCosFar p{};
+    for (int k = 0; k < 3; ++k) {
+        double sg = (k % 2) ? -1.0 : 1.0;
+        p.s[k] = sg * taylor_coef(kTwoPi / kFarTab, 2 * k + 1);
+        p.c[k] = sg * taylor_coef(kTwoPi / kFarTab, 2 * k);
+    }
+    return p;
+}
+
+// sin and cos of 2 pi w / 1024 for a phase w in 1/1024 revolutions, as
+// sincos_rev_tab with the far field's table
+__device__ inline void sincos_rev_far(double w, const double2 *tab, const SinCosFar &P, double *s, double *c)
+{
+    double jr = rint(w);
+    double f = w - jr;
+    double2 t = tab[(int)jr & (kFarTab - 1)];
+    double f2 = f * f;
+    double sp = fma(fma(P.s[2], f2, P.s[1]), f2, P.s[0]) * f;
+    double cp = fma(fma(P.c[2], f2, P.c[1]), f2, P.c[0]);
+    *s = fma(t.x, cp, t.y * sp);
+    *c = fma(t.y, cp, -(t.x * sp));
+}
+
 // The same in FP32 after the exact FP64 reduction to [-1/2, 1/2] revolutions:
 // the hardware sine and cosine take their argument in revolutions.
 __device__ inline void sincos_rev_f32(double u, float *s, float *c)

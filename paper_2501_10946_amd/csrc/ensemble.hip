@@ -157,6 +157,9 @@ struct rbsog_ens {
     // the step as a HIP graph, captured once per resident set and replayed
     bool use_graph = true;
     hipStream_t cap = nullptr;
+    // admissions upload on a stream of their own (default priority) and wait
+    // for those copies alone, not for the steps in flight on st
+    hipStream_t up = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     // the packed Fourier lattice shared by every replica (a prefix serves any
@@ -276,25 +279,25 @@ int write_tables(rbsog_ens *s, int r, double dt)
     k.gate = h->gate;
     k.gate_next = nullptr;
     k.flag = h->flag;
-    if ((e = put(s->t_kick, r, k, s->st)) != hipSuccess) return ens_fail_hip(e, "kick table");
+    if ((e = put(s->t_kick, r, k, s->up)) != hipSuccess) return ens_fail_hip(e, "kick table");
     CellArgs c = cell_args(h, h->gf, h->gate, true);
-    if ((e = put(s->t_cell, r, c, s->st)) != hipSuccess) return ens_fail_hip(e, "cell table");
+    if ((e = put(s->t_cell, r, c, s->up)) != hipSuccess) return ens_fail_hip(e, "cell table");
     NearArgs nl = near_args(h, h->gate, false);
-    if ((e = put(s->t_nlist, r, nl, s->st)) != hipSuccess) return ens_fail_hip(e, "list table");
+    if ((e = put(s->t_nlist, r, nl, s->up)) != hipSuccess) return ens_fail_hip(e, "list table");
     // modes of force index E + 1 - e_adm at ensemble step E (unsigned wrap)
     SampleArgs sa = sample_args(h, (uint64_t)1 - R.e_adm, 1);
-    if ((e = put(s->t_samp, r, sa, s->st)) != hipSuccess) return ens_fail_hip(e, "sample table");
+    if ((e = put(s->t_samp, r, sa, s->up)) != hipSuccess) return ens_fail_hip(e, "sample table");
     RhoArgs ra = rho_args(h, h->samp);
-    if ((e = put(s->t_rho, r, ra, s->st)) != hipSuccess) return ens_fail_hip(e, "rho table");
+    if ((e = put(s->t_rho, r, ra, s->up)) != hipSuccess) return ens_fail_hip(e, "rho table");
     NearArgs na = near_args(h, nullptr, true);
-    if ((e = put(s->t_near, r, na, s->st)) != hipSuccess) return ens_fail_hip(e, "near table");
+    if ((e = put(s->t_near, r, na, s->up)) != hipSuccess) return ens_fail_hip(e, "near table");
     FarArgs fa = far_args(h, h->samp, nullptr, nullptr, true, dt);
     fa.gate_clear = h->gate;
-    if ((e = put(s->t_far, r, fa, s->st)) != hipSuccess) return ens_fail_hip(e, "far table");
+    if ((e = put(s->t_far, r, fa, s->up)) != hipSuccess) return ens_fail_hip(e, "far table");
     // energies of step E - e_adm go to row E - e_adm
     EnergyArgs ea = energy_args(h, R.ehist, true);
     ea.row0 = (uint64_t)0 - R.e_adm;
-    if ((e = put(s->t_energy, r, ea, s->st)) != hipSuccess) return ens_fail_hip(e, "energy table");
+    if ((e = put(s->t_energy, r, ea, s->up)) != hipSuccess) return ens_fail_hip(e, "energy table");
     return RBSOG_OK;
 }
 
@@ -320,7 +323,7 @@ int ensure_lattice(rbsog_ens *s, int mmax)
         if (!R.used || !R.h) continue;
         R.h->lattice = dev;
         SampleArgs sa = sample_args(R.h, (uint64_t)1 - R.e_adm, 1);
-        if ((e = put(s->t_samp, r, sa, s->st)) != hipSuccess) {
+        if ((e = put(s->t_samp, r, sa, s->up)) != hipSuccess) {
             (void)hipFree(dev);
             return ens_fail_hip(e, "sample table");
         }
@@ -365,6 +368,7 @@ extern "C" int rbsog_ens_create(size_t hbm_budget, int max_slots, void *hip_stre
     if (e == hipSuccess) e = hipMalloc((void **)&s->E_dev, sizeof(uint64_t));
     if (e == hipSuccess) e = hipMemsetAsync(s->E_dev, 0, sizeof(uint64_t), s->st);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->up, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&s->ev0);
     if (e == hipSuccess) {
         s->ev.resize(kEnsEvents, nullptr);
@@ -443,19 +447,22 @@ extern "C" int rbsog_ens_admit(rbsog_ens *s, const rbsog_params *p, const rbsog_
     R.ng = sog->n <= 8 ? sog->n : 0;
     R.mixed = p->precision == RBSOG_MIXED;
     R.nsteps = nsteps;
-    hipError_t e = hipMemcpyAsync(R.x, x_host, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s->st);
-    if (e == hipSuccess) e = hipMemcpyAsync(R.v, v_host, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s->st);
-    if (e == hipSuccess) e = hipMemcpyAsync(R.q, q_host, sizeof(double) * N, hipMemcpyHostToDevice, s->st);
-    if (e == hipSuccess) e = hipMemcpyAsync(R.m, m_host, sizeof(double) * N, hipMemcpyHostToDevice, s->st);
+    // the state and the system's tables go up on the upload stream, which is
+    // then waited for (the copies only); the replica's kernels follow on st
+    hipError_t e = hipMemcpyAsync(R.x, x_host, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s->up);
+    if (e == hipSuccess) e = hipMemcpyAsync(R.v, v_host, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s->up);
+    if (e == hipSuccess) e = hipMemcpyAsync(R.q, q_host, sizeof(double) * N, hipMemcpyHostToDevice, s->up);
+    if (e == hipSuccess) e = hipMemcpyAsync(R.m, m_host, sizeof(double) * N, hipMemcpyHostToDevice, s->up);
     if (e != hipSuccess) {
         drop_replica(s, slot);
         return ens_fail_hip(e, "uploading the replica");
     }
-    rc = create_system(p, sog, R.q, R.m, wsp, align_up(ws), s->st, s->lat, &R.h);
+    rc = create_system(p, sog, R.q, R.m, wsp, align_up(ws), s->up, s->lat, &R.h, q_host, m_host, true);
     if (rc) {
         drop_replica(s, slot);
         return rc;
     }
+    R.h->st = s->st;
     // the force of the initial state, evaluation index 0, then the state in
     // cell order, where the steps keep it until retirement
     rc = rbsog_compute_forces(R.h, 0, R.x, R.f, nullptr, nullptr);
@@ -654,6 +661,7 @@ extern "C" void rbsog_ens_destroy(rbsog_ens *s)
         if (s->rep[r].h) rbsog_destroy(s->rep[r].h);
     drop_graph(s);
     if (s->cap) (void)hipStreamDestroy(s->cap);
+    if (s->up) (void)hipStreamDestroy(s->up);
     s->items.release();
     if (s->lat) (void)hipFree(s->lat);
     if (s->E_dev) (void)hipFree(s->E_dev);

@@ -173,21 +173,25 @@ void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax
     for (int i = 0; i < t->nshell; ++i) t->coef.push_back(t->S / ((double)p.P * V * Fk_of[i]));
 }
 
-void phase_table(double out[2 * kPhaseTable])
+// (sin, cos)(2 pi j / n), j < n: 2 pi j / n is within an ulp of the exact
+// angle; the quarter turns are set exactly so that they carry no rounding
+static void rotation_table(double *out, int n)
 {
     const double two_pi = 6.283185307179586;
-    for (int j = 0; j < kPhaseTable; ++j) {
-        // 2 pi j / 128 is within an ulp of the exact angle; j = 32, 64, 96 are
-        // set exactly so that the quarter turns carry no rounding
-        double a = two_pi * (double)j / (double)kPhaseTable;
+    for (int j = 0; j < n; ++j) {
+        double a = two_pi * (double)j / (double)n;
         double s = std::sin(a), c = std::cos(a);
-        if (j == kPhaseTable / 4) { s = 1.0; c = 0.0; }
-        if (j == kPhaseTable / 2) { s = 0.0; c = -1.0; }
-        if (j == 3 * kPhaseTable / 4) { s = -1.0; c = 0.0; }
+        if (j == n / 4) { s = 1.0; c = 0.0; }
+        if (j == n / 2) { s = 0.0; c = -1.0; }
+        if (j == 3 * n / 4) { s = -1.0; c = 0.0; }
         out[2 * j] = s;
         out[2 * j + 1] = c;
     }
 }
+
+void phase_table(double out[2 * kPhaseTable]) { rotation_table(out, kPhaseTable); }
+
+void far_table(double out[2 * kFarTable]) { rotation_table(out, kFarTable); }
 
 void charge_sums(const double *q, int64_t N, double *q1, double *q2)
 {

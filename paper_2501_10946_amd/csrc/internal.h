@@ -63,6 +63,9 @@ void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax
 // the host's libm: the rotation table of the FP64 phase kernels
 constexpr int kPhaseTable = 128;
 void phase_table(double out[2 * kPhaseTable]);
+// the far field's finer table, (sin, cos)(2 pi j / 1024)
+constexpr int kFarTable = 1024;
+void far_table(double out[2 * kFarTable]);
 // sum q and sum q^2 in particle order (plain FP64 additions, no contraction)
 void charge_sums(const double *q, int64_t N, double *q1, double *q2);
 

@@ -22,7 +22,7 @@ constexpr int kFarThreads = 64 * kFarGroups;
 constexpr int kFarTile = 256;
 
 // Im(exp(-i k.r) coef rho) of one mode (kv: n, gv: coef rho); (sx, sy, sz) is
-// r/L (mixed) or 128 r/L (FP64), so that n.s is the phase in the unit that the
+// r/L (mixed) or 1024 r/L (FP64), so that n.s is the phase in the unit that the
 // precision's sine and cosine take.
 template <bool MIXED>
 __device__ inline double far_term(const FarArgs &a, const double2 *tab, const double4 &kv, const double2 &gv,
@@ -35,7 +35,7 @@ __device__ inline double far_term(const FarArgs &a, const double2 *tab, const do
         return gv.y * (double)cs - gv.x * (double)sn;
     } else {
         double sn, cs;
-        sincos_rev_tab(u, tab, a.ss, &sn, &cs);
+        sincos_rev_far(u, tab, a.ss, &sn, &cs);
         return gv.y * cs - gv.x * sn;
     }
 }
@@ -45,7 +45,7 @@ __device__ inline void far_body(const FarArgs &a, int b)
 {
     __shared__ double4 sk[kFarTile];
     __shared__ double2 sg[kFarTile];
-    __shared__ double2 tab[kPhaseTab];
+    __shared__ double2 tab[kFarTab];
     __shared__ double red[64];
     static_assert(sizeof(sk) >= 3 * kFarThreads * sizeof(double), "partials reuse the sample tile");
     double(*part)[kFarThreads] = (double(*)[kFarThreads])sk;
@@ -58,12 +58,12 @@ __device__ inline void far_body(const FarArgs &a, int b)
     }
     const bool live = p < a.N;
     double4 pi = live ? a.xs[p] : make_double4(0.0, 0.0, 0.0, 0.0);
-    // phases in revolutions (mixed) or 1/128 revolutions (FP64 table path)
-    const double ph = MIXED ? a.inv_L : a.inv_L * kPhaseTab;
+    // phases in revolutions (mixed) or 1/1024 revolutions (FP64 table path)
+    const double ph = MIXED ? a.inv_L : a.inv_L * kFarTab;
     double sx = pi.x * ph, sy = pi.y * ph, sz = pi.z * ph;
     double ax = 0.0, ay = 0.0, az = 0.0;
     if (!MIXED)
-        for (int k = t; k < kPhaseTab; k += kFarThreads) tab[k] = a.tab[k];
+        for (int k = t; k < kFarTab; k += kFarThreads) tab[k] = a.tab[k];
     for (int l0 = 0; l0 < a.P; l0 += kFarTile) {
         __syncthreads();
         if (l0 + t < a.P) {

@@ -327,20 +327,25 @@ __device__ inline bool pair_window(const NearArgs &a, int q, int32_t *pstart, in
     return true;
 }
 
-// Candidate c (< the window's total) of a window: its particle index j and the
-// image shift (sx, sy, sz) its piece is seen under.
-__device__ inline int window_candidate(const int32_t *pstart, const int32_t *ppref, const int32_t *pcode, int c,
-                                       double L, double &sx, double &sy, double &sz)
+// The piece of candidate c (< the window's total): the last piece whose prefix
+// is <= c (an empty piece shares the prefix of the next, so it is never the
+// one found), by binary search over the 64 prefixes.
+__device__ inline int window_piece(const int32_t *ppref, int c)
 {
-    // the last piece whose prefix is <= c (an empty piece shares the prefix
-    // of the next, so it is never the one found)
     int lo = 0, n = 64;
     while (n > 0) {
         int h2 = n >> 1;
         if (ppref[lo + h2] <= c) { lo += h2 + 1; n -= h2 + 1; }
         else n = h2;
     }
-    const int l = lo - 1;
+    return lo - 1;
+}
+
+// Candidate c of piece l of a window: its particle index j and the image shift
+// (sx, sy, sz) the piece is seen under.
+__device__ inline int window_candidate(const int32_t *pstart, const int32_t *ppref, const int32_t *pcode, int c,
+                                       int l, double L, double &sx, double &sy, double &sz)
+{
     const int code = pcode[l];
     sx = shift_of(code & 3, L);
     sy = shift_of((code >> 2) & 3, L);
@@ -362,16 +367,30 @@ __device__ inline int window_candidate(const int32_t *pstart, const int32_t *ppr
 // more than list_rows(kp) neighbours gets the count list_rows(kp) + 1 (its
 // lanes then walk the cells in the evaluation).
 constexpr int kListHomes = 16;
+// windows of up to this many candidates get a table of each candidate's piece
+// (one byte each, in LDS), written once per window: a lookup per candidate in
+// place of a binary search per chunk of candidates, which the few home
+// particles of a cell pair (~8 at the N = 1e6 plasma) would otherwise share
+constexpr int kPieceTab = 2048;
 static_assert(kListBlock == 8, "a list block is read as two int4");
 
 __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
 {
     __shared__ int32_t pstart[kListWaves][64], ppref[kListWaves][64], pcode[kListWaves][64];
     __shared__ double hpos[kListWaves][3][kListHomes];
+    __shared__ uint8_t pidx[kListWaves][kPieceTab];
     const int lane = threadIdx.x & 63;
     PairWindow win;
     if (!pair_window(a, q, pstart[wv], ppref[wv], pcode[wv], win)) return;   // uniform per wave
     const int total = win.total;
+    const bool tabled = total <= kPieceTab;   // uniform
+    if (tabled) {   // lane l writes its piece's index over the piece's candidates
+        const int b0 = ppref[wv][lane], b1 = lane < 63 ? ppref[wv][lane + 1] : total;
+        for (int t = b0; t < b1; ++t) pidx[wv][t] = (uint8_t)lane;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     const int rows = list_rows(a.kp);
     const double L = a.g.L;
     // the list radius with a relative margin of 1e-12: a candidate is tested
@@ -379,7 +398,6 @@ __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
     // difference in another order, and a pair on the radius must not be lost
     // to the rounding (extra pairs beyond r_c are skipped by the evaluation)
     const double R2 = a.rl2 * (1.0 + 1e-12);
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));   // lanes under this one
     for (int hb = win.h_beg; hb < win.h_end; hb += kListHomes) {
         const int nh = min(kListHomes, win.h_end - hb);
         if (lane < nh) {
@@ -401,7 +419,8 @@ __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
             double px = 0.0, py = 0.0, pz = 0.0;   // the candidate, image-shifted
             if (live) {
                 double sx, sy, sz;
-                j = window_candidate(pstart[wv], ppref[wv], pcode[wv], c, L, sx, sy, sz);
+                const int l = tabled ? (int)pidx[wv][c] : window_piece(ppref[wv], c);
+                j = window_candidate(pstart[wv], ppref[wv], pcode[wv], c, l, L, sx, sy, sz);
                 const double4 qj = a.xs[j];
                 px = qj.x + sx;
                 py = qj.y + sy;
@@ -415,11 +434,17 @@ __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
                     // broadcast), not held in registers for every home
                     __asm__ volatile("" ::: "memory");
                     const double dx = hpos[wv][0][hh] - px, dy = hpos[wv][1][hh] - py, dz = hpos[wv][2][hh] - pz;
-                    const bool ok = live && dx * dx + dy * dy + dz * dz < R2 && j != h;
-                    const uint64_t m = __ballot(ok);
+                    // one predicate, no short-circuit branches; the append
+                    // position by mbcnt; the home's row base wave-uniform, the
+                    // entry a 32-bit offset into it
+                    const bool ok = (dx * dx + dy * dy + dz * dz < R2) & live & (j != h);
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(ok);
                     if (ok) {
-                        const int k = cnt[hh] + __popcll(m & below);
-                        if (k < rows) a.nbr[list_at(h, k, rows)] = j;
+                        const uint32_t k = (uint32_t)cnt[hh] +
+                                           __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        int32_t *row = a.nbr + list_at(h, 0, rows);
+                        if (k < (uint32_t)rows) row[k] = j;
                     }
                     cnt[hh] += __popcll(m);
                 }
@@ -561,11 +586,29 @@ __global__ __launch_bounds__(kEvalThreads) void k_near(NearArgs a)
 {
     static_assert(kEvalThreads == kBlock, "the structure-factor workgroups have kBlock threads");
     const int b = (int)blockIdx.x;
-    if (b < a.nrho) {   // uniform per workgroup
-        if (b < rho_blocks(a.red.nchunk, a.red.P)) rho_partial_body<true, MIXED>(a.red, b);
+    if (a.nrho == 0 || !a.interleave) {
+        if (b < a.nrho) {   // uniform per workgroup
+            if (b < rho_blocks(a.red.nchunk, a.red.P)) rho_partial_body<true, MIXED>(a.red, b);
+            return;
+        }
+        near_body<MIXED, ENERGY, NG>(a, xcd_block(b - a.nrho, (int)gridDim.x - a.nrho));
         return;
     }
-    near_body<MIXED, ENERGY, NG>(a, xcd_block(b - a.nrho, (int)gridDim.x - a.nrho));
+    // The structure-factor workgroups are spread evenly through the launch in
+    // whole groups of 8 (one per XCD), so that every compute unit holds
+    // arithmetic-bound partial sums beside the near field's gather-bound
+    // waves; the near groups keep their dispatch order, and with it the XCD
+    // mapping, and the partial last group is a near group.
+    const int64_t gr = a.nrho / 8, gn = (gridDim.x - a.nrho + 7) / 8, G = gr + gn;
+    const int64_t g = b / 8;
+    const int64_t before = (g * gr + G - 1) / G;          // structure-factor groups before group g
+    const int64_t upto = ((g + 1) * gr + G - 1) / G;
+    if (upto > before) {   // uniform per workgroup
+        const int rb = (int)(before * 8 + (b & 7));
+        if (rb < rho_blocks(a.red.nchunk, a.red.P)) rho_partial_body<true, MIXED>(a.red, rb);
+        return;
+    }
+    near_body<MIXED, ENERGY, NG>(a, xcd_block((int)((g - before) * 8 + (b & 7)), (int)gridDim.x - a.nrho));
 }
 
 __global__ __launch_bounds__(kListThreads) void k_nlist_batch(const NearArgs *__restrict__ tab,

@@ -221,14 +221,19 @@ struct NearArgs {
     int kp;                    // list capacity: list_rows(kp) (about 5 kp) entries per particle
     double rl2;                // squared list radius (r_c + skin)^2; the fine grid has cells >= (r_c + skin)/2
     const int32_t *gate;       // list build: null = always, else only when *gate != 0
-    // evaluation of one system: with nrho > 0 the first nrho workgroups (a
-    // multiple of 8, so the XCD mapping of the rest is unchanged) compute the
-    // structure-factor partial sums of `red` instead (the launch carries their
-    // dynamic LDS), so that they run alongside the near field, whose gathers
-    // leave the arithmetic units idle much of the time
+    // evaluation of one system: with nrho > 0, nrho workgroups (a multiple of
+    // 8) compute the structure-factor partial sums of `red` instead (the launch
+    // carries their dynamic LDS), so that they run alongside the near field,
+    // whose gathers leave the arithmetic units idle much of the time: the
+    // first nrho, or, with interleave, groups of 8 spread evenly through the
+    // launch (either way the near workgroups keep their XCD mapping)
     int nrho;
+    int interleave;
     RhoArgs red;
 };
+// near launches of at least this many workgroups (several rounds of the chip's
+// resident workgroups) spread their structure-factor workgroups (interleave)
+constexpr int64_t kInterleaveBlocks = 3072;
 hipError_t launch_nlist(const NearArgs &a, hipStream_t st);
 // workgroups per system: list build (cell pairs of the fine grid of nf cells per axis), evaluation
 // (256 particles x one of 5 lanes), far field (64 particles)
@@ -285,8 +290,8 @@ struct FarArgs {
     double *kepart;            // [far_blocks(N)] kinetic-energy partials (when vs)
     int *flag;                 // set to 1 on a non-finite force
     int mixed;
-    const double2 *tab;        // [kPhaseTab] (sin, cos)(2 pi j / kPhaseTab) (FP64 path)
-    SinCosShort ss;
+    const double2 *tab;        // [kFarTab] (sin, cos)(2 pi j / kFarTab) (FP64 path)
+    SinCosFar ss;
     int32_t *gate_clear;       // null, or a rebuild gate to clear (nothing later in the step reads it)
     int32_t *rebuilds;         // null, or a count of the steps whose gate was raised (with gate_clear)
     // With drift != 0 the kernel also applies the next step's first half-kick

@@ -27,7 +27,7 @@ constexpr size_t kAlign = 256;
 struct Layout {
     size_t lattice, cdf, coef, first, size;
     size_t cell_id, count, cell_start, fill, tmp, order, order_old, xs, xs_old, tile_sum, xb, vs, vs_old, fs, ms, ms_old;
-    size_t samp, part, rho, gk, eF, eW, vm, fnear, epart, kepart, flag, energy, nbr, nbr_cnt, tab;
+    size_t samp, part, rho, gk, eF, eW, vm, fnear, epart, kepart, flag, energy, nbr, nbr_cnt, tab, tab_far;
     size_t total;
 };
 
@@ -79,7 +79,7 @@ struct rbsog_handle {
     double *cdf, *coef, *eF, *eW, *vm, *fnear, *epart, *kepart, *energy, *xb;
     double *vs, *vs_old, *fs, *ms, *ms_old;   // the stepped state in cell order (with xs)
     double4 *xs, *xs_old, *samp;
-    double2 *part, *rho, *gk, *tab;
+    double2 *part, *rho, *gk, *tab, *tab_far;
     int32_t *nbr, *nbr_cnt;
     int32_t *gate;       // device, two words: rebuild the cell order and lists in this step
                          // (steps alternate between them; each step clears the other)
@@ -162,8 +162,12 @@ bool adapt_skin(rbsog_handle *h, double dt);
 bool adapt_skin_rebuilds(rbsog_handle *h);
 // rbsog_create; with lattice_dev (the packed lattice up to at least the
 // system's m_max, owned by the caller) the workspace holds no lattice copy
+// q_host, m_host (nullable): host copies of the charges and masses, which
+// spare the read-back of q_dev and m_dev; with sync false nothing waits on the
+// stream (the table uploads complete in stream order).
 int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev, const double *m_dev, void *ws_dev,
-                  size_t ws_bytes, hipStream_t stream, const int32_t *lattice_dev, rbsog_handle **out);
+                  size_t ws_bytes, hipStream_t stream, const int32_t *lattice_dev, rbsog_handle **out,
+                  const double *q_host = nullptr, const double *m_host = nullptr, bool sync = true);
 // gate_raise non-null (with kick): the far kernel also applies the next
 // step's first half-kick and drift, raising gate_raise; gate_clear is cleared
 // the thermostat of a step's drift into force index `step` (off without friction)

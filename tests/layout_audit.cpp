@@ -109,7 +109,8 @@ static void audit(int64_t N, double L, double lambda, double rc, int P, double s
     CHECK(span(w.vm, w.fnear) >= 8 * ((size_t)d.mmax + 1), "%s: virial factors by |n|^2", tag);
     CHECK(span(w.kepart, w.flag) >= 8 * (size_t)far_blocks((int)N), "%s: kinetic partials", tag);
     CHECK(span(w.xs, w.xs_old) >= 32 * (size_t)N && span(w.ms, w.ms_old) >= 8 * (size_t)N, "%s: rows", tag);
-    CHECK(w.total >= w.tab + 16 * kPhaseTable, "%s: total", tag);
+    CHECK(span(w.tab, w.tab_far) >= 16 * (size_t)kPhaseTable, "%s: rotation table", tag);
+    CHECK(w.total >= w.tab_far + 16 * (size_t)kFarTable, "%s: total", tag);
 }
 
 // every call below carries one argument a kernel cannot run on, and must be
