@@ -96,6 +96,8 @@ def lib():
             "orc_langevin_normals": (None, [_u64, _u64, _u64, _u32, _p]),
             "orc_sys_set_langevin": (None, [_p, _d, _d]),
             "orc_rdf": (None, [_i64, _p, _d, _d, _i, _p, _p]),
+            "orc_track": (None, [_i64, _d, _p, _p, _p]),
+            "orc_msd_vacf": (None, [_i64, _p, _p, _p, _p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -424,6 +426,20 @@ def rdf(x, L: float, r_max: float, nbins: int):
     amb = np.zeros(nbins, dtype=np.int64)
     lib().orc_rdf(x.shape[1], _ptr(x), L, r_max, nbins, _ptr(counts), _ptr(amb))
     return counts, amb
+
+
+def track(x, L: float, x_last, disp) -> None:
+    """disp += minimum-image (x - x_last); x_last = x (in place)."""
+    x = _f64(x)
+    assert x_last.flags.c_contiguous and disp.flags.c_contiguous
+    lib().orc_track(x.shape[1], L, _ptr(x), _ptr(x_last), _ptr(disp))
+
+
+def msd_vacf(disp, v0, v):
+    out = np.zeros(2)
+    disp, v0, v = _f64(disp), _f64(v0), _f64(v)
+    lib().orc_msd_vacf(disp.shape[1], _ptr(disp), _ptr(v0), _ptr(v), _ptr(out))
+    return float(out[0]), float(out[1])
 
 
 def num_threads() -> int:

@@ -1297,6 +1297,34 @@ void orc_rdf(int64_t N, const double *x, double L, double r_max, int nbins, int6
         }
 }
 
+/* Unwrapped displacement between two snapshots of the wrapped positions:
+ * disp += (x - x_last) - L rint((x - x_last)/L), the minimum image (each
+ * particle must have moved less than L/2 in between), then x_last = x. */
+void orc_track(int64_t N, double L, const double *x, double *x_last, double *disp)
+{
+    for (int64_t k = 0; k < 3 * N; ++k) {
+        double d = x[k] - x_last[k];
+        d = d - L * rint(d / L);
+        disp[k] += d;
+        x_last[k] = x[k];
+    }
+}
+
+/* Mean squared displacement (1/N) sum_i |disp_i|^2 and velocity
+ * autocorrelation (1/N) sum_i v0_i . v_i (Section 5.1's MSD and VACF at one
+ * time lag), in particle order. */
+void orc_msd_vacf(int64_t N, const double *disp, const double *v0, const double *v, double out[2])
+{
+    double msd = 0.0, vacf = 0.0;
+    for (int64_t i = 0; i < N; ++i)
+        for (int d = 0; d < 3; ++d) {
+            msd += disp[d * N + i] * disp[d * N + i];
+            vacf += v0[d * N + i] * v[d * N + i];
+        }
+    out[0] = msd / (double)N;
+    out[1] = vacf / (double)N;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
