@@ -81,6 +81,14 @@ def lib():
             "orc_far_rb_energy": (_d, [_i, _p, _p]),
             "orc_far_rb_virial": (_d, [_i, _p, _p, _p, _d, _i, _p, _p]),
             "orc_far_full": (_d, [_i64, _p, _p, _d, _i, _p, _p, _i, _p, _p]),
+            "orc_kernel_Y": (_d, [_i, _p, _p, _d]),
+            "orc_egs_split": (_i, [_d, _d, _p, _p]),
+            "orc_kernel_maxerr": (_d, [_i, _p, _p, _d, _d, _i, _p, _p]),
+            "orc_density_k": (_d, [_i, _d, _d, _d, _i, _p, _p, _d]),
+            "orc_near_k": (_i, [_i64, _p, _p, _d, _i, _p, _p, _d, _i, _p, _p, _p, _p, _p]),
+            "orc_near_subset_k": (_i, [_i64, _p, _p, _d, _i, _p, _p, _d, _i, _p, _p, _i64, _p, _p]),
+            "orc_sys_create_k": (_p, [_i64, _d, _i, _p, _p, _d, _d, _i, _i, _u64, _u32, _i, _i, _i, _p, _p, _p, _p,
+                                      _p, _p]),
             "orc_sys_create": (_p, [_i64, _d, _d, _d, _d, _i, _i, _u64, _u32, _i, _i, _i, _p, _p, _p, _p, _p, _p]),
             "orc_sys_destroy": (None, [_p]),
             "orc_sys_mmax": (_i, [_p]),
@@ -135,10 +143,24 @@ class SOG:
     err: float = float("nan")
     sigma: float = 1.0    # bandwidth factor of the narrowest Gaussian (Appendix C; 1 for C1)
     smooth: int = 1
+    ya: Optional[np.ndarray] = None   # the kernel's Yukawa terms, sum_j ya_j e^{-r/yl_j}/r
+    yl: Optional[np.ndarray] = None   # (None: the Yukawa kernel at lam)
+    nu: float = 0.0                   # EGS gradient-correction strength (0: Yukawa)
 
     @property
     def n(self) -> int:
+        if self.c is not None:
+            return len(self.c)
         return self.M1 + self.M2 + 1
+
+    @property
+    def terms(self):
+        """(count, a, l) of the kernel sum_j a_j e^{-r/l_j}/r."""
+        if self.yl is None:
+            return 1, np.array([1.0]), np.array([float(self.lam)])
+        a = np.ascontiguousarray(self.ya, dtype=np.float64)
+        l = np.ascontiguousarray(self.yl, dtype=np.float64)
+        return len(l), a, l
 
     @property
     def F0(self) -> float:
@@ -149,7 +171,7 @@ class SOG:
         return float(sum(self.A))
 
     def expand(self) -> "SOG":
-        n = self.n
+        n = self.M1 + self.M2 + 1
         self.c, self.s, self.A, self.B = (np.zeros(n) for _ in range(4))
         lib().orc_sog_expand_s(self.lam, self.h, self.t0, self.w, self.sigma, self.M1, self.M2, _ptr(self.c),
                                _ptr(self.s), _ptr(self.A), _ptr(self.B))
@@ -211,6 +233,53 @@ def sog_auto2(lam: float, rc: float, eps: float) -> SOG:
     s = SOG(lam, rc, h.value, t0.value, w.value, M1.value, M2.value, sigma=sg.value, smooth=2).expand()
     s.err = err.value
     return s
+
+
+def egs_split(lam: float, nu: float):
+    """(a, l): the EGS kernel of Section 1 as sum_j a_j e^{-r/l_j}/r."""
+    a, l = np.zeros(2), np.zeros(2)
+    if lib().orc_egs_split(lam, nu, _ptr(a), _ptr(l)) != 0:
+        raise ValueError("EGS needs lambda > 0 and 0 < nu < 1")
+    return a, l
+
+
+def kernel_Y(s: SOG, r) -> np.ndarray:
+    nY, ya, yl = s.terms
+    r = np.asarray(r, dtype=np.float64)
+    return np.array([lib().orc_kernel_Y(nY, _ptr(ya), _ptr(yl), float(x)) for x in r.ravel()]).reshape(r.shape)
+
+
+def kernel_maxerr(s: SOG, R: float) -> float:
+    nY, ya, yl = s.terms
+    return lib().orc_kernel_maxerr(nY, _ptr(ya), _ptr(yl), s.rc, R, s.n, _ptr(s.c), _ptr(s.s))
+
+
+EGS_RANGE = 33.0   # the approximation range [r_c, 33 l] of Algorithm 1, per Yukawa term
+
+
+def sog_egs(lam: float, nu: float, rc: float, eps: float, smooth: int = 1) -> SOG:
+    """The EGS kernel (Section 1) decomposed term by term: each Yukawa term
+    a_j e^{-r/l_j}/r gets the decomposition of Algorithm 1 (smooth = 1) or of
+    Appendix C (smooth = 2) at length l_j and tolerance eps / (|a_1| + |a_2|),
+    and F is the sum of a_j times each term's Gaussians, so that |Y - F| <=
+    eps on [r_c, 33 l_1] and N = Y - F inherits each term's continuity at r_c.
+    A term with r_c >= 33 l_j has no Gaussians: it lies wholly in the near
+    field, cut at r_c where it is below e^{-33}/r_c."""
+    a, l = egs_split(lam, nu)
+    eps_j = eps / float(np.abs(a).sum())
+    cs, ss, As, Bs = [], [], [], []
+    for aj, lj in zip(a, l):
+        if rc >= EGS_RANGE * lj:
+            continue
+        t = sog_auto(lj, rc, eps_j) if smooth == 1 else sog_auto2(lj, rc, eps_j)
+        cs.append(aj * t.c)
+        ss.append(t.s)
+        As.append(aj * t.A)
+        Bs.append(t.B)
+    out = SOG(lam, rc, float("nan"), float("nan"), float("nan"), 0, 0, smooth=smooth, ya=a, yl=l, nu=nu)
+    out.c, out.s, out.A, out.B = (np.ascontiguousarray(np.concatenate(v)) for v in (cs, ss, As, Bs))
+    out.err = kernel_maxerr(out, EGS_RANGE * float(l[0]))
+    return out
 
 
 def sog_far2(s: SOG, r) -> float:
@@ -281,8 +350,10 @@ def near(x, q, L, s: SOG, virial: bool = False):
     N = x.shape[1]
     f = np.zeros((3, N))
     U, W = C.c_double(), C.c_double()
-    lib().orc_near(N, _ptr(x), _ptr(q), L, s.lam, s.rc, s.n, _ptr(s.c), _ptr(s.s), _ptr(f), C.byref(U),
-                   C.byref(W))
+    nY, ya, yl = s.terms
+    if lib().orc_near_k(N, _ptr(x), _ptr(q), L, nY, _ptr(ya), _ptr(yl), s.rc, s.n, _ptr(s.c), _ptr(s.s), _ptr(f),
+                        C.byref(U), C.byref(W)) != 0:
+        raise ValueError("near: bad kernel")
     return (f, U.value, W.value) if virial else (f, U.value)
 
 
@@ -291,10 +362,11 @@ def near_subset(x, q, L, s: SOG, idx):
     x, q = _f64(x), _f64(q)
     idx = np.ascontiguousarray(idx, dtype=np.int64)
     f = np.zeros((3, len(idx)))
-    rc = lib().orc_near_subset(x.shape[1], _ptr(x), _ptr(q), L, s.lam, s.rc, s.n, _ptr(s.c), _ptr(s.s), len(idx),
-                               _ptr(idx), _ptr(f))
+    nY, ya, yl = s.terms
+    rc = lib().orc_near_subset_k(x.shape[1], _ptr(x), _ptr(q), L, nY, _ptr(ya), _ptr(yl), s.rc, s.n, _ptr(s.c),
+                                 _ptr(s.s), len(idx), _ptr(idx), _ptr(f))
     if rc != 0:
-        raise ValueError("near_subset: particle index out of range")
+        raise ValueError("near_subset: particle index out of range or bad kernel")
     return f
 
 
@@ -347,9 +419,10 @@ class System:
         self.N = self.q.shape[0]
         self.L, self.sog, self.kT, self.P = L, s, kT, P
         self.V = L ** 3
-        self._h = lib().orc_sys_create(self.N, L, s.lam, s.rc, kT, P, mmax, seed, replica, density, int(full_k),
-                                       s.n, _ptr(s.c), _ptr(s.s), _ptr(s.A), _ptr(s.B), _ptr(self.q),
-                                       _ptr(self.m))
+        nY, self._ya, self._yl = s.terms
+        self._h = lib().orc_sys_create_k(self.N, L, nY, _ptr(self._ya), _ptr(self._yl), s.rc, kT, P, mmax, seed,
+                                         replica, density, int(full_k), s.n, _ptr(s.c), _ptr(s.s), _ptr(s.A),
+                                         _ptr(s.B), _ptr(self.q), _ptr(self.m))
         if not self._h:
             raise ValueError("oracle system creation failed")
         self.mmax = lib().orc_sys_mmax(self._h)

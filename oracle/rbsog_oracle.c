@@ -42,6 +42,97 @@ double orc_yukawa_dr(double r, double lambda)
     return -exp(-r / lambda) * (1.0 / (lambda * r) + 1.0 / (r * r));
 }
 
+/* The screened kernels, as sums of Yukawa terms Y(r) = sum_j a_j e^{-r/l_j}/r
+ * (1 <= n <= 2): the Yukawa kernel of eq. (epsilon) is n = 1, a = 1,
+ * l = lambda; the exact gradient-corrected screening (EGS) kernel of Section 1
+ * is the two-term partial-fraction form of orc_egs_split.  Fourier transform:
+ * Yhat(k) = sum_j a_j 4 pi l_j^2 / (1 + l_j^2 k^2). */
+typedef struct { int n; double a[2], l[2]; } orc_kern;
+
+static orc_kern kern_yukawa(double lambda)
+{
+    orc_kern K = {1, {1.0, 0.0}, {lambda, 1.0}};
+    return K;
+}
+
+/* 0 if n is 1 or 2 and every l_j is positive and finite. */
+static int kern_make(int n, const double *a, const double *l, orc_kern *K)
+{
+    if (n < 1 || n > 2) return -1;
+    K->n = n;
+    K->a[1] = 0.0;
+    K->l[1] = 1.0;
+    for (int j = 0; j < n; ++j) {
+        if (!(l[j] > 0.0) || !isfinite(l[j]) || !isfinite(a[j])) return -1;
+        K->a[j] = a[j];
+        K->l[j] = l[j];
+    }
+    return 0;
+}
+
+/* sum_j a_j l_j^2: the kernel's integral over space is 4 pi times this
+ * (Yhat(0)/(4 pi)); lambda^2 for both the Yukawa and the EGS kernel. */
+static double kern_l2(const orc_kern *K)
+{
+    double acc = 0.0;
+    for (int j = 0; j < K->n; ++j) acc += K->a[j] * K->l[j] * K->l[j];
+    return acc;
+}
+
+/* Y(r) of a kernel given by its terms. */
+double orc_kernel_Y(int n, const double *a, const double *l, double r)
+{
+    orc_kern K;
+    if (kern_make(n, a, l, &K) != 0) return NAN;
+    double acc = 0.0;
+    for (int j = 0; j < K.n; ++j) acc += K.a[j] * exp(-r / K.l[j]) / r;
+    return acc;
+}
+
+/* The EGS dielectric of Section 1, eps(k) = 1 + (lambda k)^{-2} (1 + nu
+ * lambda^2 k^2 / 4)^{-1}, gives the potential 4 pi / (k^2 eps(k)) =
+ * 4 pi (1 + b k^2) / (b k^4 + k^2 + lambda^{-2}) with b = nu lambda^2 / 4.  The
+ * denominator is b (k^2 + alpha_1)(k^2 + alpha_2) with
+ *   alpha_1 = 2 / (lambda^2 (1 + sqrt(1 - nu))),
+ *   alpha_2 = 2 (1 + sqrt(1 - nu)) / (nu lambda^2)
+ * (alpha_1 written without the cancellation of (1 - sqrt(1 - nu))), and partial
+ * fractions give 4 pi / (k^2 eps) = sum_j a_j 4 pi / (k^2 + alpha_j) with
+ * a_1 = alpha_2 / (alpha_2 - alpha_1), a_2 = -alpha_1 / (alpha_2 - alpha_1):
+ * the difference of two Yukawa kernels of lengths l_j = alpha_j^{-1/2}.
+ * a_1 + a_2 = 1 (Coulomb at short range) and a_1 l_1^2 + a_2 l_2^2 = lambda^2.
+ * Needs 0 < nu < 1 (nu = 1 is a double root, nu > 1 complex lengths).
+ * Returns 0, or -1 outside that range. */
+int orc_egs_split(double lambda, double nu, double *a_out, double *l_out)
+{
+    if (!(lambda > 0.0) || !isfinite(lambda) || !(nu > 0.0) || !(nu < 1.0)) return -1;
+    double sq = sqrt(1.0 - nu);
+    double al1 = 2.0 / (lambda * lambda * (1.0 + sq));
+    double al2 = 2.0 * (1.0 + sq) / (nu * lambda * lambda);
+    a_out[0] = al2 / (al2 - al1);
+    a_out[1] = -al1 / (al2 - al1);
+    l_out[0] = 1.0 / sqrt(al1);
+    l_out[1] = 1.0 / sqrt(al2);
+    return 0;
+}
+
+/* max_{r in G} |Y(r) - F(r)| for a kernel given by its terms and any Gaussian
+ * list, on G = { rc + (R - rc) u^2 : u = j/1600, j = 0..1600 } (the grid of
+ * orc_sog_maxerr). */
+double orc_kernel_maxerr(int n, const double *a, const double *l, double rc, double R, int nG, const double *c,
+                         const double *s)
+{
+    double emax = 0.0;
+    for (int j = 0; j <= 1600; ++j) {
+        double u = j / 1600.0;
+        double r = rc + (R - rc) * u * u;
+        double F = 0.0;
+        for (int g = 0; g < nG; ++g) F += c[g] * exp(-s[g] * r * r);
+        double e = fabs(orc_kernel_Y(n, a, l, r) - F);
+        if (e > emax) emax = e;
+    }
+    return emax;
+}
+
 /* Integrand of the integral representation Y(r) = int f(t,r) dt (eq. ftr):
  * f(t,r) = pi^{-1/2} exp(-r^2 e^t - e^{-t}/(4 lambda^2) + t/2). */
 double orc_f(double t, double r, double lambda)
@@ -442,15 +533,36 @@ enum { ORC_ADAPTIVE = 0, ORC_FLAT = 1, ORC_K2 = 2, ORC_DH4PI = 3 };
  * as printed.  FLAT (F = 1) and K2 (F = k^2) are the two earlier densities the
  * paper compares against in Section 4.2; DH4PI keeps the 4 pi that the
  * potential's own Fourier transform carries (4 pi lambda^2/(1 + lambda^2 k^2)). */
-double orc_density(int kind, double kT, double V, double Q2, double lambda, double k2)
+static double density_k(int kind, double kT, double V, double Q2, const orc_kern *K, double k2)
 {
-    double l2 = lambda * lambda;
+    /* eps(k)^{-1}/k^2 = Yhat(k)/(4 pi) = sum_j a_j l_j^2/(1 + l_j^2 k^2) */
+    double g = 0.0;
+    for (int j = 0; j < K->n; ++j) {
+        double l2 = K->l[j] * K->l[j];
+        g += K->a[j] * l2 / (1.0 + l2 * k2);
+    }
     switch (kind) {
     case ORC_FLAT: return 1.0;
     case ORC_K2: return k2;
-    case ORC_DH4PI: return (kT * V) / ((kT * V) / Q2 + (4.0 * ORC_PI * l2) / (1.0 + l2 * k2));
-    default: return (kT * V) / ((kT * V) / Q2 + l2 / (1.0 + l2 * k2));
+    case ORC_DH4PI: return (kT * V) / ((kT * V) / Q2 + 4.0 * ORC_PI * g);
+    default: return (kT * V) / ((kT * V) / Q2 + g);
     }
+}
+
+double orc_density(int kind, double kT, double V, double Q2, double lambda, double k2)
+{
+    orc_kern K = kern_yukawa(lambda);
+    return density_k(kind, kT, V, Q2, &K, k2);
+}
+
+/* The same for a kernel given by its terms (the first term of eq. (3.22) is
+ * written for any dielectric eps(k): eps^{-1}/k^2 is the kernel's
+ * Yhat(k)/(4 pi)).  NAN for a bad kernel. */
+double orc_density_k(int kind, double kT, double V, double Q2, int n, const double *a, const double *l, double k2)
+{
+    orc_kern K;
+    if (kern_make(n, a, l, &K) != 0) return NAN;
+    return density_k(kind, kT, V, Q2, &K, k2);
 }
 
 /* Default lattice truncation: the largest m >= 1 with Fhat(tk2 m) >= 1e-16 Fhat(0),
@@ -524,9 +636,21 @@ void orc_lattice_build(int mmax, int32_t *n3, int64_t *start)
  * r3(m) > 0 in ascending m: cdf_i = cdf_{i-1} + r3(m_i) W(m_i), S = cdf_last.
  * Also returns per shell the coefficient coef = S / (P V F(k^2)) of the
  * estimators of eq. (UF).  Returns the number of shells. */
+static int shell_table_k(int mmax, const int64_t *start, int nG, const double *A, const double *B, double L,
+                         int kind, double kT, double Q2, const orc_kern *K, int P, int32_t *shell_m, double *cdf,
+                         double *coef);
+
 int orc_shell_table(int mmax, const int64_t *start, int nG, const double *A, const double *B, double L,
                     int kind, double kT, double Q2, double lambda, int P, int32_t *shell_m, double *cdf,
                     double *coef)
+{
+    orc_kern K = kern_yukawa(lambda);
+    return shell_table_k(mmax, start, nG, A, B, L, kind, kT, Q2, &K, P, shell_m, cdf, coef);
+}
+
+static int shell_table_k(int mmax, const int64_t *start, int nG, const double *A, const double *B, double L,
+                         int kind, double kT, double Q2, const orc_kern *K, int P, int32_t *shell_m, double *cdf,
+                         double *coef)
 {
     double t = (2.0 * ORC_PI) / L;
     double tk2 = t * t;
@@ -537,7 +661,7 @@ int orc_shell_table(int mmax, const int64_t *start, int nG, const double *A, con
         int64_t r3 = start[m + 1] - start[m];
         if (r3 <= 0) continue;
         double k2 = tk2 * (double)m;
-        double Fk = orc_density(kind, kT, V, Q2, lambda, k2);
+        double Fk = density_k(kind, kT, V, Q2, K, k2);
         double W = Fk * orc_Fhat(nG, A, B, k2);
         run = run + (double)r3 * W;
         shell_m[ns] = m;
@@ -547,7 +671,7 @@ int orc_shell_table(int mmax, const int64_t *start, int nG, const double *A, con
     double S = run;
     for (int i = 0; i < ns; ++i) {
         double k2 = tk2 * (double)shell_m[i];
-        double Fk = orc_density(kind, kT, V, Q2, lambda, k2);
+        double Fk = density_k(kind, kT, V, Q2, K, k2);
         coef[i] = S / ((double)P * V * Fk);
     }
     return ns;
@@ -668,16 +792,21 @@ int orc_cells(int64_t N, const double *x, double L, double rc, int32_t *cell_sta
 /* ------------------------------------------------------------------------- */
 
 /* Pair force factor and energy of the near part N(r) = Y(r) - F(r), r < rc
- * (eq. short):  F_N1(r) = e^{-r/lambda}(1 + r/lambda)/r^3,
+ * (eq. short):  F_N1(r) = e^{-r/lambda}(1 + r/lambda)/r^3 (summed over the
+ * kernel's Yukawa terms, each weighted by a_j, for a two-term kernel),
  * F_N2(r) = -2 sum_j c_j s_j e^{-s_j r^2};  the force on i from j is
  * q_i q_j (F_N1 + F_N2) d with d = r_i - r_j (minimum image; eq. 3.8 is
  * written with r_ij, whose sign is read so that like charges repel). */
-static void near_pair(double r2, double lambda, int nG, const double *c, const double *s, double *fac,
+static void near_pair(double r2, const orc_kern *K, int nG, const double *c, const double *s, double *fac,
                       double *en)
 {
     double r = sqrt(r2);
-    double ey = exp(-r / lambda);
-    double f1 = ey * (1.0 + r / lambda) / (r2 * r);
+    double f1 = 0.0, y = 0.0;
+    for (int j = 0; j < K->n; ++j) {
+        double ey = exp(-r / K->l[j]);
+        f1 += K->a[j] * ey * (1.0 + r / K->l[j]) / (r2 * r);
+        y += K->a[j] * ey / r;
+    }
     double f2 = 0.0, fr = 0.0;
     for (int j = 0; j < nG; ++j) {
         double g = exp(-s[j] * r2);
@@ -685,7 +814,7 @@ static void near_pair(double r2, double lambda, int nG, const double *c, const d
         fr += c[j] * g;
     }
     *fac = f1 - 2.0 * f2;
-    *en = ey / r - fr;
+    *en = y - fr;
 }
 
 /* Near-field forces (written to f, SoA) and energy U_N = 1/2 sum over ordered
@@ -697,8 +826,27 @@ static void near_pair(double r2, double lambda, int nG, const double *c, const d
  * cutoff contributes.  With L >= 3 rc and
  * N > 2000 the pairs are found through the cell list; otherwise every image
  * shift that can reach within rc is looped over directly (tiny boxes). */
+static void near_k(int64_t N, const double *x, const double *q, double L, orc_kern K, double rc, int nG,
+                   const double *c, const double *s, double *f, double *U_out, double *W_out);
+
 void orc_near(int64_t N, const double *x, const double *q, double L, double lambda, double rc, int nG,
               const double *c, const double *s, double *f, double *U_out, double *W_out)
+{
+    near_k(N, x, q, L, kern_yukawa(lambda), rc, nG, c, s, f, U_out, W_out);
+}
+
+/* orc_near for a kernel given by its terms.  Returns 0, or -1 for a bad kernel. */
+int orc_near_k(int64_t N, const double *x, const double *q, double L, int nY, const double *ya, const double *yl,
+               double rc, int nG, const double *c, const double *s, double *f, double *U_out, double *W_out)
+{
+    orc_kern K;
+    if (kern_make(nY, ya, yl, &K) != 0) return -1;
+    near_k(N, x, q, L, K, rc, nG, c, s, f, U_out, W_out);
+    return 0;
+}
+
+static void near_k(int64_t N, const double *x, const double *q, double L, orc_kern K, double rc, int nG,
+                   const double *c, const double *s, double *f, double *U_out, double *W_out)
 {
     double rc2 = rc * rc;
     double *ei = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
@@ -737,7 +885,7 @@ void orc_near(int64_t N, const double *x, const double *q, double L, double lamb
                             double r2 = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
                             if (r2 >= rc2) continue;
                             double fac, en;
-                            near_pair(r2, lambda, nG, c, s, &fac, &en);
+                            near_pair(r2, &K, nG, c, s, &fac, &en);
                             double qq = q[i] * q[j];
                             fx += qq * fac * dx_; fy += qq * fac * dy_; fz += qq * fac * dz_;
                             e += 0.5 * qq * en;
@@ -766,7 +914,7 @@ void orc_near(int64_t N, const double *x, const double *q, double L, double lamb
                             double r2 = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
                             if (r2 >= rc2 || r2 == 0.0) continue;
                             double fac, en;
-                            near_pair(r2, lambda, nG, c, s, &fac, &en);
+                            near_pair(r2, &K, nG, c, s, &fac, &en);
                             double qq = q[i] * q[j];
                             fx += qq * fac * dx_; fy += qq * fac * dy_; fz += qq * fac * dz_;
                             e += 0.5 * qq * en;
@@ -795,8 +943,27 @@ void orc_near(int64_t N, const double *x, const double *q, double L, double lamb
  * list when L >= 3 rc and by looping over every image shift that can reach
  * within rc otherwise (boxes smaller than three cutoffs).  f_out is
  * [3][nsub].  Returns 0, or -1 for an index outside [0, N). */
+static int near_subset_k(int64_t N, const double *x, const double *q, double L, orc_kern K, double rc, int nG,
+                         const double *c, const double *s, int64_t nsub, const int64_t *idx, double *f_out);
+
 int orc_near_subset(int64_t N, const double *x, const double *q, double L, double lambda, double rc, int nG,
                     const double *c, const double *s, int64_t nsub, const int64_t *idx, double *f_out)
+{
+    return near_subset_k(N, x, q, L, kern_yukawa(lambda), rc, nG, c, s, nsub, idx, f_out);
+}
+
+/* orc_near_subset for a kernel given by its terms (-1 also for a bad kernel). */
+int orc_near_subset_k(int64_t N, const double *x, const double *q, double L, int nY, const double *ya,
+                      const double *yl, double rc, int nG, const double *c, const double *s, int64_t nsub,
+                      const int64_t *idx, double *f_out)
+{
+    orc_kern K;
+    if (kern_make(nY, ya, yl, &K) != 0) return -1;
+    return near_subset_k(N, x, q, L, K, rc, nG, c, s, nsub, idx, f_out);
+}
+
+static int near_subset_k(int64_t N, const double *x, const double *q, double L, orc_kern K, double rc, int nG,
+                         const double *c, const double *s, int64_t nsub, const int64_t *idx, double *f_out)
 {
     double rc2 = rc * rc;
     int nc = (int)floor(L / rc);
@@ -819,7 +986,7 @@ int orc_near_subset(int64_t N, const double *x, const double *q, double L, doubl
                             double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
                             if (r2 >= rc2 || r2 == 0.0) continue;
                             double fac, en;
-                            near_pair(r2, lambda, nG, c, s, &fac, &en);
+                            near_pair(r2, &K, nG, c, s, &fac, &en);
                             double qq = q[i] * q[j];
                             fx += qq * fac * ddx; fy += qq * fac * ddy; fz += qq * fac * ddz;
                         }
@@ -859,7 +1026,7 @@ int orc_near_subset(int64_t N, const double *x, const double *q, double L, doubl
                         double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
                         if (r2 >= rc2) continue;
                         double fac, en;
-                        near_pair(r2, lambda, nG, c, s, &fac, &en);
+                        near_pair(r2, &K, nG, c, s, &fac, &en);
                         double qq = q[i] * q[j];
                         fx += qq * fac * ddx; fy += qq * fac * ddy; fz += qq * fac * ddz;
                     }
@@ -1016,6 +1183,7 @@ double orc_far_full(int64_t N, const double *x, const double *q, double L, int n
 typedef struct {
     int64_t N;
     double L, V, lambda, rc, kT, Q1, Q2;
+    orc_kern kern; /* the kernel's Yukawa terms */
     int P, mmax, density, full_k, nG;
     double friction, bath_kT; /* Langevin thermostat (friction 0: plain velocity-Verlet) */
     uint64_t seed;
@@ -1033,13 +1201,30 @@ typedef struct {
 } orc_sys;
 
 /* Builds the sampling tables of a system.  q and m must outlive the system. */
+orc_sys *orc_sys_create_k(int64_t N, double L, int nY, const double *ya, const double *yl, double rc, double kT,
+                          int P, int mmax, uint64_t seed, uint32_t replica, int density, int full_k, int nG,
+                          const double *c, const double *s, const double *A, const double *B, const double *q,
+                          const double *m);
+
 orc_sys *orc_sys_create(int64_t N, double L, double lambda, double rc, double kT, int P, int mmax,
                         uint64_t seed, uint32_t replica, int density, int full_k, int nG, const double *c,
                         const double *s, const double *A, const double *B, const double *q, const double *m)
 {
-    if (nG < 1 || nG > 64) return NULL;
+    double one = 1.0;
+    return orc_sys_create_k(N, L, 1, &one, &lambda, rc, kT, P, mmax, seed, replica, density, full_k, nG, c, s, A,
+                            B, q, m);
+}
+
+/* orc_sys_create for a kernel given by its Yukawa terms (ya, yl; nY <= 2). */
+orc_sys *orc_sys_create_k(int64_t N, double L, int nY, const double *ya, const double *yl, double rc, double kT,
+                          int P, int mmax, uint64_t seed, uint32_t replica, int density, int full_k, int nG,
+                          const double *c, const double *s, const double *A, const double *B, const double *q,
+                          const double *m)
+{
+    orc_kern K;
+    if (nG < 1 || nG > 64 || kern_make(nY, ya, yl, &K) != 0) return NULL;
     orc_sys *S = (orc_sys *)calloc(1, sizeof(orc_sys));
-    S->N = N; S->L = L; S->V = L * L * L; S->lambda = lambda; S->rc = rc; S->kT = kT;
+    S->N = N; S->L = L; S->V = L * L * L; S->lambda = yl[0]; S->kern = K; S->rc = rc; S->kT = kT;
     S->P = P; S->density = density; S->full_k = full_k; S->nG = nG;
     S->seed = seed; S->replica = replica; S->q = q; S->m = m;
     memcpy(S->c, c, sizeof(double) * nG); memcpy(S->s, s, sizeof(double) * nG);
@@ -1057,8 +1242,8 @@ orc_sys *orc_sys_create(int64_t N, double L, double lambda, double rc, double kT
     S->shell_m = (int32_t *)malloc(sizeof(int32_t) * ((size_t)S->mmax + 1));
     S->cdf = (double *)malloc(sizeof(double) * ((size_t)S->mmax + 1));
     S->shell_coef = (double *)malloc(sizeof(double) * ((size_t)S->mmax + 1));
-    S->nshell = orc_shell_table(S->mmax, S->start, nG, A, B, L, density, kT, q2, lambda, P, S->shell_m,
-                                S->cdf, S->shell_coef);
+    S->nshell = shell_table_k(S->mmax, S->start, nG, A, B, L, density, kT, q2, &S->kern, P, S->shell_m,
+                              S->cdf, S->shell_coef);
     return S;
 }
 
@@ -1099,7 +1284,9 @@ void orc_sys_draw(const orc_sys *S, uint64_t step, int32_t *n_out, double *coef_
  *            from sampling and added deterministically;
  *   U_self = -1/2 sum q_i^2 F(0)       -- Section 4.1;
  *   U_bg   = -(sum q)^2 4 pi lambda^2 / (2V) -- the uniform neutralising
- *            background's interaction energy (constant, no force);
+ *            background's interaction energy (constant, no force; 4 pi
+ *            lambda^2 is the kernel's integral over space, the same for the
+ *            Yukawa and the EGS kernel);
  *   W_N, W_F = the virials -3V dU/dV of the near and far parts (orc_near,
  *            orc_far_rb_virial); U_k0 and U_bg scale as 1/V, so their
  *            virials are 3 U_k0 and 3 U_bg, and U_self has none. */
@@ -1107,7 +1294,7 @@ void orc_sys_force(const orc_sys *S, uint64_t step, const double *x, double *f, 
 {
     int64_t N = S->N;
     double UN = 0.0, UF = 0.0, WN = 0.0, WF = 0.0;
-    orc_near(N, x, S->q, S->L, S->lambda, S->rc, S->nG, S->c, S->s, f, &UN, &WN);
+    near_k(N, x, S->q, S->L, S->kern, S->rc, S->nG, S->c, S->s, f, &UN, &WN);
     if (f_near) memcpy(f_near, f, sizeof(double) * 3 * (size_t)N);
     if (S->full_k) {
         UF = orc_far_full(N, x, S->q, S->L, S->nG, S->A, S->B, S->mmax, f, &WF);
@@ -1127,7 +1314,7 @@ void orc_sys_force(const orc_sys *S, uint64_t step, const double *x, double *f, 
         energy[1] = UF;
         energy[2] = S->Fhat0 * S->Q1 * S->Q1 / (2.0 * S->V);
         energy[3] = -0.5 * S->Q2 * S->F0;
-        energy[4] = -(S->Q1 * S->Q1) * (4.0 * ORC_PI * S->lambda * S->lambda) / (2.0 * S->V);
+        energy[4] = -(S->Q1 * S->Q1) * (4.0 * ORC_PI * kern_l2(&S->kern)) / (2.0 * S->V);
         energy[5] = 0.0;
         energy[6] = WN;
         energy[7] = WF;
