@@ -1,7 +1,9 @@
 // Observables of Section 5.1 on the device: the static structure factor by
 // lattice shell (computed with the structure-factor kernels of the far field
-// over every mode of the shells) and the pair-distance histogram behind the
-// radial distribution function (over the fine cell grid of a system).
+// over every mode of the shells), the pair-distance histogram behind the
+// radial distribution function (over the fine cell grid of a system), and the
+// unwrapped displacements behind the mean squared displacement with the
+// velocity autocorrelation.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -131,10 +133,104 @@ __global__ __launch_bounds__(kBlock) void k_rdf(RdfArgs a)
         if (h[b]) atomicAdd(&a.hist[b], (unsigned long long)h[b]);
 }
 
+// ---------------------------------------------------------------------------
+// displacement tracking, MSD and VACF
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_track(int64_t n3, double L, double inv_L, const double *__restrict__ x,
+                                                  double *__restrict__ x_last, double *__restrict__ disp)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n3) return;
+    const double xn = x[k];
+    double d = xn - x_last[k];
+    d = d - L * rint(d * inv_L);
+    disp[k] += d;
+    x_last[k] = xn;
+}
+
+constexpr int kMsdBlocks = 1024;   // fixed grid: partials summed in one order whatever N is
+
+// per-block partial sums of |disp|^2 and v0 . v over a fixed grid-stride
+// assignment of particles, then one block adds the partials in block order
+__global__ __launch_bounds__(kBlock) void k_msd_part(int64_t N, const double *__restrict__ disp,
+                                                     const double *__restrict__ v0, const double *__restrict__ v,
+                                                     double2 *__restrict__ part)
+{
+    __shared__ double red[kBlock];
+    double m = 0.0, c = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (int64_t)kMsdBlocks * kBlock)
+        for (int d = 0; d < 3; ++d) {
+            const double u = disp[d * N + i];
+            m = fma(u, u, m);
+            c = fma(v0[d * N + i], v[d * N + i], c);
+        }
+    m = block_sum_256(m, red);
+    __syncthreads();
+    c = block_sum_256(c, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(m, c);
+}
+
+__global__ __launch_bounds__(kBlock) void k_msd_final(int64_t N, const double2 *__restrict__ part,
+                                                      double *__restrict__ out)
+{
+    __shared__ double red[kBlock];
+    double m = 0.0, c = 0.0;
+    for (int b = threadIdx.x; b < kMsdBlocks; b += kBlock) {
+        m += part[b].x;
+        c += part[b].y;
+    }
+    m = block_sum_256(m, red);
+    __syncthreads();
+    c = block_sum_256(c, red);
+    if (threadIdx.x == 0) {
+        out[0] = m / (double)N;
+        out[1] = c / (double)N;
+    }
+}
+
 }  // namespace
 }  // namespace rbsog
 
 using namespace rbsog;
+
+extern "C" int rbsog_track(int64_t N, double L, const double *x_dev, double *x_last_dev, double *disp_dev,
+                           void *hip_stream)
+{
+    if (N < 1 || N > ((int64_t)1 << 27) - 1) return fail(RBSOG_EINVAL, "N must lie in [1, 2^27 - 1]");
+    if (!(L > 0.0) || !std::isfinite(L)) return fail(RBSOG_EINVAL, "L must be positive and finite");
+    if (!x_dev || !x_last_dev || !disp_dev) return fail(RBSOG_EINVAL, "null x, x_last or disp");
+    const int64_t n3 = 3 * N;
+    hipLaunchKernelGGL(k_track, dim3((unsigned)((n3 + kBlock - 1) / kBlock)), dim3(kBlock), 0, (hipStream_t)hip_stream,
+                       n3, L, 1.0 / L, x_dev, x_last_dev, disp_dev);
+    HIPCHECK(hipGetLastError());
+    return RBSOG_OK;
+}
+
+extern "C" int rbsog_msd_scratch_size(size_t *bytes)
+{
+    if (!bytes) return fail(RBSOG_EINVAL, "null bytes");
+    *bytes = sizeof(double2) * kMsdBlocks;
+    return RBSOG_OK;
+}
+
+extern "C" int rbsog_msd_vacf(int64_t N, const double *disp_dev, const double *v0_dev, const double *v_dev,
+                              void *scratch_dev, size_t scratch_bytes, void *hip_stream, double *out_dev)
+{
+    if (N < 1 || N > ((int64_t)1 << 27) - 1) return fail(RBSOG_EINVAL, "N must lie in [1, 2^27 - 1]");
+    if (!disp_dev || !v0_dev || !v_dev || !scratch_dev || !out_dev)
+        return fail(RBSOG_EINVAL, "null disp, v0, v, scratch or out");
+    if (scratch_bytes < sizeof(double2) * kMsdBlocks)
+        return fail(RBSOG_EWORKSPACE, "scratch of %zu bytes is below the %zu needed", scratch_bytes,
+                    sizeof(double2) * kMsdBlocks);
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_msd_part, dim3(kMsdBlocks), dim3(kBlock), 0, st, N, disp_dev, v0_dev, v_dev,
+                       (double2 *)scratch_dev);
+    HIPCHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_msd_final, dim3(1), dim3(kBlock), 0, st, N, (const double2 *)scratch_dev, out_dev);
+    HIPCHECK(hipGetLastError());
+    return RBSOG_OK;
+}
 
 extern "C" int rbsog_ssf_scratch_size(int64_t N, int m_s, size_t *bytes)
 {
