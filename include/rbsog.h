@@ -87,6 +87,14 @@ typedef struct rbsog_sog {
     double max_err;          /* max |Y - F| on [r_c, 33 lambda] (sampled densely)    */
     int smooth;              /* 2: the C2 form of Appendix C (sigma used); else C1   */
     double sigma;            /* C2: the narrowest Gaussian's exponent is e^{t_M2} sigma */
+    /* The kernel (zero-initialised: the Yukawa kernel above).  nyuk = 2: the
+     * exact gradient-corrected screening kernel of Section 1,
+     * Y(r) = ya[0] e^{-r/yl[0]}/r + ya[1] e^{-r/yl[1]}/r (rbsog_sog_init_egs);
+     * then c, s, A, B hold both terms' Gaussians (n of them), and h, t0, w,
+     * M1, M2, sigma are those of the first term's decomposition.            */
+    int nyuk;                /* 0 or 1: Yukawa; 2: the EGS kernel               */
+    double nu;               /* EGS gradient-correction strength, 0 < nu < 1     */
+    double ya[2], yl[2];     /* nyuk = 2: weights and lengths of the two terms   */
 } rbsog_sog;
 
 /*
@@ -109,6 +117,28 @@ typedef struct rbsog_sog {
 int rbsog_sog_init(double lambda, double r_c, double eps, int smooth, int M1, int M2, rbsog_sog *out);
 
 /*
+ * The exact gradient-corrected screening (EGS) kernel of Section 1, whose
+ * dielectric is eps(k) = 1 + (lambda k)^{-2} (1 + nu lambda^2 k^2 / 4)^{-1},
+ * as the difference of two Yukawa kernels (partial fractions of
+ * 4 pi / (k^2 eps(k))): ya[j] e^{-r/yl[j]}/r with yl[j] = alpha_j^{-1/2},
+ * alpha_1 = 2 / (lambda^2 (1 + sqrt(1 - nu))), alpha_2 = 2 (1 + sqrt(1 - nu)) /
+ * (nu lambda^2), ya[0] = alpha_2 / (alpha_2 - alpha_1) = 1 - ya[1].  Each term
+ * gets the decomposition of rbsog_sog_init (numbers of Gaussians chosen
+ * automatically, C1 or C2 as smooth says) at length yl[j] and tolerance
+ * eps / (|ya[0]| + |ya[1]|); F is the sum of ya[j] times each term's
+ * Gaussians, so |Y - F| <= eps on [r_c, 33 yl[0]] (max_err) and N = Y - F is
+ * as smooth at r_c as each term.  A term with r_c >= 33 yl[j] has no Gaussians
+ * and lies wholly inside the near field (it is below e^{-33}/r_c at r_c).
+ * Systems built on the result use the kernel everywhere: the pair function,
+ * the adaptive density of eq. (3.22) (with eps(k)^{-1}/k^2 of this
+ * dielectric) and the energy constants.  Host only.
+ * Errors: RBSOG_EINVAL (lambda, r_c or eps as rbsog_sog_init, nu outside
+ * (0, 1), r_c >= 33 yl[0], more than RBSOG_MAX_GAUSS Gaussians in all),
+ * RBSOG_ENOROOT.
+ */
+int rbsog_sog_init_egs(double lambda, double nu, double r_c, double eps, int smooth, rbsog_sog *out);
+
+/*
  * Recomputes c, s, A, B, F0, Fhat0 and max_err of *sog from its lambda, r_c,
  * h, t0, w, M1, M2 (for a decomposition given by its parameters, e.g. a row of
  * the paper's Table 1).  The expansion is evaluated in a fixed IEEE FP64
@@ -116,7 +146,8 @@ int rbsog_sog_init(double lambda, double r_c, double eps, int smooth, int M1, in
  * c = (h/sqrt(pi)) exp(t/2 - exp(-t)/(4 lambda^2)) [* w at m = M2];
  * A = pi sqrt(pi) c / (s sqrt(s)); B = 1/(4 s)), so identical parameters give
  * identical coefficients on any conforming host.  Host only.
- * Errors: RBSOG_EINVAL.
+ * Errors: RBSOG_EINVAL (also for a two-term kernel, nyuk = 2, whose Gaussians
+ * come from rbsog_sog_init_egs or the caller).
  */
 int rbsog_sog_expand(rbsog_sog *sog);
 
@@ -169,7 +200,22 @@ typedef struct rbsog_params {
                            coefficient Fhat(k)/V per mode (eqs. 3.5, UF without
                            sampling) -- a test reference, N x nlat work per force;
                            P is then unused and rbsog_compute_rho is refused   */
+    int sampler;        /* RBSOG_SAMPLER_IID (0): P i.i.d. modes per step by the
+                           inverse CDF of the shell weights;
+                           RBSOG_SAMPLER_MH (1): the Metropolis-Hastings chain
+                           Section 4.1 names for drawing P(k): an independence
+                           chain whose proposals are drawn exactly from the
+                           measure with F = 1 (P_q proportional to Fhat) and
+                           accepted with probability min(1, F(k')/F(k)); the
+                           P modes of a step are the chain's next P states.
+                           The chain advances over the modes as the library
+                           draws them (ahead, in consecutive steps), so its
+                           draws depend on the history of calls as well as on
+                           the key; single systems only (not the ensemble)   */
 } rbsog_params;
+
+#define RBSOG_SAMPLER_IID 0
+#define RBSOG_SAMPLER_MH 1
 
 typedef struct rbsog_handle rbsog_handle;
 
@@ -454,6 +500,30 @@ int rbsog_ssf(int64_t N, double L, const double *x_dev, const double *w_dev, int
  * Asynchronous on the handle's stream.  Errors: RBSOG_EINVAL, RBSOG_EHIP.
  */
 int rbsog_rdf(rbsog_handle *h, const double *x_dev, double r_max, int nbins, unsigned long long *hist_dev);
+
+/*
+ * Unwrapped displacements (for the mean squared displacement of Section 5.1):
+ * disp_dev += d - L rint(d / L), d = x_dev - x_last_dev, then x_last_dev =
+ * x_dev (all [3][N], device, caller order).  rbsog_step returns positions
+ * wrapped into the box; calling this after each call (or often enough that no
+ * particle moves L/2 or more in between) accumulates each particle's true
+ * displacement.  Asynchronous on hip_stream.  Errors: RBSOG_EINVAL.
+ */
+int rbsog_track(int64_t N, double L, const double *x_dev, double *x_last_dev, double *disp_dev, void *hip_stream);
+
+/* Scratch bytes of rbsog_msd_vacf (host only).  Errors: RBSOG_EINVAL. */
+int rbsog_msd_scratch_size(size_t *bytes);
+
+/*
+ * Mean squared displacement and velocity autocorrelation at one time lag
+ * (Section 5.1): out_dev[0] = (1/N) sum_i |disp_i|^2, out_dev[1] = (1/N)
+ * sum_i v0_i . v_i (disp, v0, v [3][N], device; out [2], device), FP64 sums in
+ * a fixed order (bitwise reproducible).  scratch_dev: rbsog_msd_scratch_size
+ * bytes of device memory.  Asynchronous on hip_stream.
+ * Errors: RBSOG_EINVAL, RBSOG_EWORKSPACE.
+ */
+int rbsog_msd_vacf(int64_t N, const double *disp_dev, const double *v0_dev, const double *v_dev, void *scratch_dev,
+                   size_t scratch_bytes, void *hip_stream, double *out_dev);
 
 /* Milliseconds from rbsog_ens_create to the device completion of ensemble
  * step ens_step (1-based, one of the last 8192 launched); waits for it.

@@ -103,6 +103,8 @@ def lib():
             "orc_ssf": (None, [_i64, _p, _p, _d, _i, _p]),
             "orc_langevin_normals": (None, [_u64, _u64, _u64, _u32, _p]),
             "orc_sys_set_langevin": (None, [_p, _d, _d]),
+            "orc_sys_set_sampler": (_i, [_p, _i]),
+            "orc_mh_draw": (None, [_i, _u64, _u64, _u32, _i, _p, _p, _p, _p, _p, _p, _p, _p]),
             "orc_rdf": (None, [_i64, _p, _d, _d, _i, _p, _p]),
             "orc_track": (None, [_i64, _d, _p, _p, _p]),
             "orc_msd_vacf": (None, [_i64, _p, _p, _p, _p]),
@@ -413,7 +415,7 @@ class System:
     """Sampling tables plus force evaluation and velocity-Verlet stepping."""
 
     def __init__(self, q, m, L: float, s: SOG, kT: float, P: int, seed: int, replica: int = 0, mmax: int = 0,
-                 density: int = ADAPTIVE, full_k: bool = False):
+                 density: int = ADAPTIVE, full_k: bool = False, sampler: int = 0):
         self.q = _f64(q)
         self.m = _f64(m)
         self.N = self.q.shape[0]
@@ -427,6 +429,8 @@ class System:
             raise ValueError("oracle system creation failed")
         self.mmax = lib().orc_sys_mmax(self._h)
         self.nshell = lib().orc_sys_nshell(self._h)
+        if sampler:
+            self.set_sampler(sampler)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -463,6 +467,11 @@ class System:
         e = np.zeros(8)
         lib().orc_sys_force(self._h, step, _ptr(x), _ptr(f), _ptr(fn), _ptr(e))
         return f, fn, e
+
+    def set_sampler(self, sampler: int):
+        """0: i.i.d. inverse-CDF draws; 1: the Metropolis-Hastings chain (emptied)."""
+        if lib().orc_sys_set_sampler(self._h, sampler) != 0:
+            raise ValueError("sampler must be 0 or 1")
 
     def set_langevin(self, friction: float, bath_kT: float):
         """Langevin thermostat for run() (friction 0: plain velocity-Verlet)."""

@@ -716,31 +716,78 @@ void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
  *   i = first shell with cdf_i > target (the last shell if none);
  *   j = floor(w1 r3(m_i) / 2^64)  (high word of the 64x64 product);
  *   n_l = lattice[start[m_i] + j],  coef_l = coef of shell i. */
+/* One draw from a shell CDF with two Philox words: the shell from w0, the
+ * point within it from w1 (as above).  Sets the shell index and returns the
+ * lattice index. */
+static int64_t draw_point(uint64_t w0, uint64_t w1, int nshell, const int32_t *shell_m, const double *cdf,
+                          const int64_t *start, int *shell_out)
+{
+    double S = cdf[nshell - 1];
+    double u = (double)(w0 >> 11) * (1.0 / 9007199254740992.0);
+    double target = u * S;
+    int lo = 0, hi = nshell; /* first index with cdf > target */
+    while (lo < hi) {
+        int mid = lo + (hi - lo) / 2;
+        if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+    }
+    int i = lo < nshell ? lo : nshell - 1;
+    int m = shell_m[i];
+    uint64_t r3 = (uint64_t)(start[m + 1] - start[m]);
+    uint64_t jhi, jlo;
+    mulhilo64(w1, r3, &jhi, &jlo);
+    *shell_out = i;
+    return start[m] + (int64_t)jhi;
+}
+
 void orc_draw(int P, uint64_t step, uint64_t seed, uint32_t replica, int nshell, const int32_t *shell_m,
               const double *cdf, const double *shell_coef, const int64_t *start, const int32_t *n3,
               int32_t *n_out, double *coef_out)
 {
-    double S = cdf[nshell - 1];
     for (int l = 0; l < P; ++l) {
         uint64_t ctr[4] = {(uint64_t)l, step, 0, 0}, key[2] = {seed, (uint64_t)replica}, w[4];
         orc_philox4x64_10(ctr, key, w);
-        double u = (double)(w[0] >> 11) * (1.0 / 9007199254740992.0);
-        double target = u * S;
-        int lo = 0, hi = nshell; /* first index with cdf > target */
-        while (lo < hi) {
-            int mid = lo + (hi - lo) / 2;
-            if (cdf[mid] > target) hi = mid; else lo = mid + 1;
-        }
-        int i = lo < nshell ? lo : nshell - 1;
-        int m = shell_m[i];
-        uint64_t r3 = (uint64_t)(start[m + 1] - start[m]);
-        uint64_t jhi, jlo;
-        mulhilo64(w[1], r3, &jhi, &jlo);
-        int64_t p = start[m] + (int64_t)jhi;
+        int i;
+        int64_t p = draw_point(w[0], w[1], nshell, shell_m, cdf, start, &i);
         n_out[3 * l + 0] = n3[3 * p + 0];
         n_out[3 * l + 1] = n3[3 * p + 1];
         n_out[3 * l + 2] = n3[3 * p + 2];
         coef_out[l] = shell_coef[i];
+    }
+}
+
+/* The Metropolis-Hastings variant of the draws (Section 4.1 names the method
+ * for sampling P(k) and gives no chain; the reading taken): an independence
+ * chain on the lattice whose proposals come from the measure with F = 1,
+ * P_q(k) proportional to Fhat(k), drawn exactly as above from its own shell
+ * CDF cdf_q.  Against the target P(k) proportional to F(k) Fhat(k) the
+ * Metropolis-Hastings ratio P(k') P_q(k) / (P(k) P_q(k')) is F(k') / F(k) =
+ * coef(k) / coef(k'), the estimator coefficient S / (P V F) being inversely
+ * proportional to F.  Step l at force-evaluation index `step`:
+ *   (w0, w1, w2, w3) = Philox4x64-10(counter = (l, step, 2, 0), key = (seed, replica));
+ *   proposal k' (shell i') from w0, w1 on cdf_q;  a = (w2 >> 11) 2^-53;
+ *   the chain moves to k' iff it is empty or a coef(i') < coef(i);
+ *   sample l = the chain's state after that decision.
+ * state[2] = (lattice index, shell index) of the chain, shell index -1 for
+ * an empty chain; it carries over from call to call. */
+void orc_mh_draw(int P, uint64_t step, uint64_t seed, uint32_t replica, int nshell, const int32_t *shell_m,
+                 const double *cdf_q, const double *shell_coef, const int64_t *start, const int32_t *n3,
+                 int64_t *state, int32_t *n_out, double *coef_out)
+{
+    for (int l = 0; l < P; ++l) {
+        uint64_t ctr[4] = {(uint64_t)l, step, 2, 0}, key[2] = {seed, (uint64_t)replica}, w[4];
+        orc_philox4x64_10(ctr, key, w);
+        int ip;
+        int64_t pp = draw_point(w[0], w[1], nshell, shell_m, cdf_q, start, &ip);
+        double a = (double)(w[2] >> 11) * (1.0 / 9007199254740992.0);
+        if (state[1] < 0 || a * shell_coef[ip] < shell_coef[state[1]]) {
+            state[0] = pp;
+            state[1] = ip;
+        }
+        int64_t p = state[0];
+        n_out[3 * l + 0] = n3[3 * p + 0];
+        n_out[3 * l + 1] = n3[3 * p + 1];
+        n_out[3 * l + 2] = n3[3 * p + 2];
+        coef_out[l] = shell_coef[state[1]];
     }
 }
 
@@ -1198,6 +1245,10 @@ typedef struct {
     int nshell;
     int32_t *shell_m;
     double *cdf, *shell_coef;
+    /* Metropolis-Hastings draws (sampler 1): the proposal CDF and the chain */
+    int sampler;
+    double *cdf_q;
+    int64_t mh_state[2];
 } orc_sys;
 
 /* Builds the sampling tables of a system.  q and m must outlive the system. */
@@ -1250,7 +1301,7 @@ orc_sys *orc_sys_create_k(int64_t N, double L, int nY, const double *ya, const d
 void orc_sys_destroy(orc_sys *S)
 {
     if (!S) return;
-    free(S->n3); free(S->start); free(S->shell_m); free(S->cdf); free(S->shell_coef);
+    free(S->n3); free(S->start); free(S->shell_m); free(S->cdf); free(S->shell_coef); free(S->cdf_q);
     free(S);
 }
 
@@ -1269,10 +1320,37 @@ void orc_sys_lattice(const orc_sys *S, int32_t *n3, int64_t *start)
     memcpy(start, S->start, sizeof(int64_t) * ((size_t)S->mmax + 2));
 }
 
-void orc_sys_draw(const orc_sys *S, uint64_t step, int32_t *n_out, double *coef_out)
+/* The draws of force-evaluation index `step`: i.i.d. (sampler 0) or the next P
+ * states of the Metropolis-Hastings chain (sampler 1, which advances it). */
+void orc_sys_draw(orc_sys *S, uint64_t step, int32_t *n_out, double *coef_out)
 {
-    orc_draw(S->P, step, S->seed, S->replica, S->nshell, S->shell_m, S->cdf, S->shell_coef, S->start, S->n3,
-             n_out, coef_out);
+    if (S->sampler == 1)
+        orc_mh_draw(S->P, step, S->seed, S->replica, S->nshell, S->shell_m, S->cdf_q, S->shell_coef, S->start,
+                    S->n3, S->mh_state, n_out, coef_out);
+    else
+        orc_draw(S->P, step, S->seed, S->replica, S->nshell, S->shell_m, S->cdf, S->shell_coef, S->start, S->n3,
+                 n_out, coef_out);
+}
+
+/* Selects the sampler: 0 i.i.d. inverse-CDF draws, 1 the Metropolis-Hastings
+ * chain of orc_mh_draw (its proposal table is built here and the chain
+ * emptied).  Returns 0, or -1 for another value. */
+int orc_sys_set_sampler(orc_sys *S, int sampler)
+{
+    if (sampler != 0 && sampler != 1) return -1;
+    S->sampler = sampler;
+    S->mh_state[0] = 0;
+    S->mh_state[1] = -1;
+    if (sampler == 1 && !S->cdf_q) {
+        S->cdf_q = (double *)malloc(sizeof(double) * ((size_t)S->mmax + 1));
+        int32_t *m_tmp = (int32_t *)malloc(sizeof(int32_t) * ((size_t)S->mmax + 1));
+        double *c_tmp = (double *)malloc(sizeof(double) * ((size_t)S->mmax + 1));
+        shell_table_k(S->mmax, S->start, S->nG, S->A, S->B, S->L, ORC_FLAT, S->kT, S->Q2, &S->kern, S->P, m_tmp,
+                      S->cdf_q, c_tmp);
+        free(m_tmp);
+        free(c_tmp);
+    }
+    return 0;
 }
 
 /* One force evaluation at force-evaluation index `step` (the force step of
@@ -1290,7 +1368,7 @@ void orc_sys_draw(const orc_sys *S, uint64_t step, int32_t *n_out, double *coef_
  *   W_N, W_F = the virials -3V dU/dV of the near and far parts (orc_near,
  *            orc_far_rb_virial); U_k0 and U_bg scale as 1/V, so their
  *            virials are 3 U_k0 and 3 U_bg, and U_self has none. */
-void orc_sys_force(const orc_sys *S, uint64_t step, const double *x, double *f, double *f_near, double *energy)
+void orc_sys_force(orc_sys *S, uint64_t step, const double *x, double *f, double *f_near, double *energy)
 {
     int64_t N = S->N;
     double UN = 0.0, UF = 0.0, WN = 0.0, WF = 0.0;
@@ -1366,7 +1444,7 @@ void orc_sys_set_langevin(orc_sys *S, double friction, double bath_kT)
     S->bath_kT = bath_kT;
 }
 
-int orc_sys_run(const orc_sys *S, double *x, double *v, double *f, uint64_t step0, int nsteps, double dt,
+int orc_sys_run(orc_sys *S, double *x, double *v, double *f, uint64_t step0, int nsteps, double dt,
                 double *ehist)
 {
     int64_t N = S->N;

@@ -22,6 +22,7 @@ RBSOG_FP64, RBSOG_MIXED = 0, 1
 RBSOG_ADAPTIVE, RBSOG_FLAT, RBSOG_K2, RBSOG_DH4PI = 0, 1, 2, 3
 # doubles per energy row: U_N, U*_F, U_k0, U_self, U_bg, KE, W_N, W*_F
 ENERGY_COLS = 8
+RBSOG_SAMPLER_IID, RBSOG_SAMPLER_MH = 0, 1
 RBSOG_AUTO = -999
 RBSOG_MAX_GAUSS = 32
 
@@ -39,13 +40,14 @@ class rbsog_sog(C.Structure):
                 ("c", C.c_double * RBSOG_MAX_GAUSS), ("s", C.c_double * RBSOG_MAX_GAUSS),
                 ("A", C.c_double * RBSOG_MAX_GAUSS), ("B", C.c_double * RBSOG_MAX_GAUSS),
                 ("F0", C.c_double), ("Fhat0", C.c_double), ("max_err", C.c_double),
-                ("smooth", C.c_int), ("sigma", C.c_double)]
+                ("smooth", C.c_int), ("sigma", C.c_double),
+                ("nyuk", C.c_int), ("nu", C.c_double), ("ya", C.c_double * 2), ("yl", C.c_double * 2)]
 
 
 class rbsog_params(C.Structure):
     _fields_ = [("N", C.c_int64), ("L", C.c_double), ("kT", C.c_double), ("P", C.c_int), ("mmax", C.c_int),
                 ("seed", C.c_uint64), ("replica", C.c_uint32), ("precision", C.c_int), ("density", C.c_int),
-                ("skin", C.c_double), ("full_k", C.c_int)]
+                ("skin", C.c_double), ("full_k", C.c_int), ("sampler", C.c_int)]
 
 
 RBSOG_NUM_KERNEL_CLASSES = 9
@@ -75,6 +77,8 @@ def lib() -> C.CDLL:
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
         L = C.CDLL(LIB_PATH)
         sig = {
+            "rbsog_sog_init_egs": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int,
+                                             C.POINTER(rbsog_sog)]),
             "rbsog_sog_init": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, C.c_int,
                                          C.POINTER(rbsog_sog)]),
             "rbsog_sog_expand": (C.c_int, [C.POINTER(rbsog_sog)]),
@@ -110,6 +114,9 @@ def lib() -> C.CDLL:
             "rbsog_ssf_scratch_size": (C.c_int, [C.c_int64, C.c_int, C.POINTER(C.c_size_t)]),
             "rbsog_ssf": (C.c_int, [C.c_int64, C.c_double, _p, _p, C.c_int, _p, C.c_size_t, _p, _p]),
             "rbsog_rdf": (C.c_int, [_p, _p, C.c_double, C.c_int, _p]),
+            "rbsog_track": (C.c_int, [C.c_int64, C.c_double, _p, _p, _p, _p]),
+            "rbsog_msd_scratch_size": (C.c_int, [C.POINTER(C.c_size_t)]),
+            "rbsog_msd_vacf": (C.c_int, [C.c_int64, _p, _p, _p, _p, C.c_size_t, _p, _p]),
             "rbsog_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -156,6 +163,12 @@ def rbsog_sog_init(lambda_: float, r_c: float, eps: float, M1: int = RBSOG_AUTO,
     return out
 
 
+def rbsog_sog_init_egs(lambda_: float, nu: float, r_c: float, eps: float, smooth: int = 1) -> rbsog_sog:
+    out = rbsog_sog()
+    _check(lib().rbsog_sog_init_egs(lambda_, nu, r_c, eps, smooth, C.byref(out)))
+    return out
+
+
 def rbsog_sog_expand(sog: rbsog_sog) -> rbsog_sog:
     _check(lib().rbsog_sog_expand(C.byref(sog)))
     return sog
@@ -184,11 +197,34 @@ def sog_from_parameters(lambda_: float, r_c: float, h: float, t0: float, w: floa
     return rbsog_sog_expand(s)
 
 
+def sog_from_gaussians(lambda_: float, r_c: float, c, s, A, B, ya=None, yl=None, nu: float = 0.0,
+                       eps: float = 0.0, smooth: int = 1) -> rbsog_sog:
+    """A decomposition given by its Gaussians (F = sum c exp(-s r^2), Fhat =
+    sum A exp(-B k^2)) and, for the EGS kernel, its two Yukawa terms (weights
+    ya, lengths yl).  F(0) and Fhat(0) are summed in list order."""
+    n = len(c)
+    if not 1 <= n <= RBSOG_MAX_GAUSS or not len(s) == len(A) == len(B) == n:
+        raise ValueError(f"need 1..{RBSOG_MAX_GAUSS} Gaussians with matching c, s, A, B")
+    out = rbsog_sog()
+    out.lambda_, out.r_c, out.eps, out.smooth = lambda_, r_c, eps, smooth
+    out.M1, out.M2, out.n = n - 1, 0, n
+    out.sigma = 1.0
+    for j in range(n):
+        out.c[j], out.s[j], out.A[j], out.B[j] = float(c[j]), float(s[j]), float(A[j]), float(B[j])
+    out.F0 = sum(float(v) for v in c)
+    out.Fhat0 = sum(float(v) for v in A)
+    if yl is not None:
+        out.nyuk, out.nu = 2, nu
+        out.ya[0], out.ya[1] = float(ya[0]), float(ya[1])
+        out.yl[0], out.yl[1] = float(yl[0]), float(yl[1])
+    return out
+
+
 def make_params(N: int, L: float, kT: float, P: int, seed: int, replica: int = 0, mmax: int = 0,
                 precision: int = RBSOG_FP64, density: int = RBSOG_ADAPTIVE, skin: float = -1.0,
-                full_k: bool = False) -> rbsog_params:
+                full_k: bool = False, sampler: int = 0) -> rbsog_params:
     return rbsog_params(N=N, L=L, kT=kT, P=P, mmax=mmax, seed=seed, replica=replica, precision=precision,
-                        density=density, skin=skin, full_k=1 if full_k else 0)
+                        density=density, skin=skin, full_k=1 if full_k else 0, sampler=sampler)
 
 
 def rbsog_workspace_size(params: rbsog_params, sog: rbsog_sog) -> int:
@@ -293,6 +329,30 @@ def rbsog_rdf(h, x, r_max: float, nbins: int, hist) -> None:
     _check(lib().rbsog_rdf(h, _dptr(x, torch.float64, 3 * N), r_max, nbins, _dptr(hist, torch.int64, nbins)))
 
 
+def rbsog_track(x, L: float, x_last, disp, stream=None) -> None:
+    """disp += minimum-image (x - x_last); x_last = x (device tensors [3, N])."""
+    import torch
+    N = x.shape[1]
+    _check(lib().rbsog_track(N, L, _dptr(x, torch.float64, 3 * N), _dptr(x_last, torch.float64, 3 * N),
+                             _dptr(disp, torch.float64, 3 * N), stream or _stream(x.device)))
+
+
+def rbsog_msd_scratch_size() -> int:
+    b = C.c_size_t(0)
+    _check(lib().rbsog_msd_scratch_size(C.byref(b)))
+    return b.value
+
+
+def rbsog_msd_vacf(disp, v0, v, scratch, out, stream=None) -> None:
+    """out[0] = mean |disp|^2, out[1] = mean v0 . v (device tensors)."""
+    import torch
+    N = disp.shape[1]
+    _check(lib().rbsog_msd_vacf(N, _dptr(disp, torch.float64, 3 * N), _dptr(v0, torch.float64, 3 * N),
+                                _dptr(v, torch.float64, 3 * N), _dptr(scratch),
+                                scratch.numel() * scratch.element_size(), stream or _stream(disp.device),
+                                _dptr(out, torch.float64, 2)))
+
+
 def rbsog_check(h) -> None:
     _check(lib().rbsog_check(h))
 
@@ -390,13 +450,13 @@ class System:
 
     def __init__(self, q, m, L: float, sog: rbsog_sog, kT: float, P: int, seed: int, replica: int = 0,
                  mmax: int = 0, precision: int = RBSOG_FP64, density: int = RBSOG_ADAPTIVE, skin: float = -1.0,
-                 full_k: bool = False, device="cuda"):
+                 full_k: bool = False, device="cuda", sampler: int = 0):
         import torch
         self.q = torch.as_tensor(q, dtype=torch.float64, device=device).contiguous()
         self.m = torch.as_tensor(m, dtype=torch.float64, device=device).contiguous()
         self.N = self.q.numel()
         self.sog = sog
-        self.params = make_params(self.N, L, kT, P, seed, replica, mmax, precision, density, skin, full_k)
+        self.params = make_params(self.N, L, kT, P, seed, replica, mmax, precision, density, skin, full_k, sampler)
         nbytes = rbsog_workspace_size(self.params, sog)
         self.ws = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device=device)
         self.h = rbsog_create(self.params, sog, self.q, self.m, self.ws)

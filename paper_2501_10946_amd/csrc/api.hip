@@ -133,6 +133,8 @@ Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
     L.nbr_cnt = take(sizeof(int32_t) * (size_t)N);
     L.tab = take(sizeof(double) * 2 * kPhaseTable);
     L.tab_far = take(sizeof(double) * 2 * kFarTable);
+    L.cdf_q = take(sizeof(double) * (size_t)d.mmax);
+    L.mh = take(sizeof(int32_t) * 2);
     L.total = off;
     return L;
 }
@@ -145,13 +147,20 @@ int check_params(const rbsog_params *p, const rbsog_sog *s)
     if (!(p->kT > 0.0) || !std::isfinite(p->kT)) return fail(RBSOG_EINVAL, "kT must be positive and finite");
     if (p->P < 1 || p->P > 4096) return fail(RBSOG_EINVAL, "P must lie in [1, 4096]");
     if (p->full_k != 0 && p->full_k != 1) return fail(RBSOG_EINVAL, "full_k must be 0 or 1");
+    if (p->sampler != RBSOG_SAMPLER_IID && p->sampler != RBSOG_SAMPLER_MH)
+        return fail(RBSOG_EINVAL, "sampler must be RBSOG_SAMPLER_IID or RBSOG_SAMPLER_MH");
     if (p->precision != RBSOG_FP64 && p->precision != RBSOG_MIXED) return fail(RBSOG_EINVAL, "unknown precision");
     if (p->density < RBSOG_ADAPTIVE || p->density > RBSOG_DH4PI) return fail(RBSOG_EINVAL, "unknown density");
     if (p->mmax < 0 || p->mmax > kMaxLatticeM) return fail(RBSOG_EINVAL, "mmax must lie in [0, %d]", kMaxLatticeM);
     if (!std::isfinite(p->skin)) return fail(RBSOG_EINVAL, "skin must be finite");
-    if (s->n < 1 || s->n > RBSOG_MAX_GAUSS || s->n != s->M1 + s->M2 + 1)
+    if (s->nyuk < 0 || s->nyuk > 2) return fail(RBSOG_EINVAL, "sog: nyuk must be 0, 1 or 2");
+    if (s->n < 1 || s->n > RBSOG_MAX_GAUSS || (s->nyuk != 2 && s->n != s->M1 + s->M2 + 1))
         return fail(RBSOG_EINVAL, "sog: inconsistent number of Gaussians");
     if (!(s->r_c > 0.0) || !(s->lambda > 0.0)) return fail(RBSOG_EINVAL, "sog: lambda and r_c must be positive");
+    if (s->nyuk == 2)
+        for (int t = 0; t < 2; ++t)
+            if (!(s->yl[t] > 0.0) || !std::isfinite(s->yl[t]) || !std::isfinite(s->ya[t]))
+                return fail(RBSOG_EINVAL, "sog: the kernel's terms need positive, finite lengths and finite weights");
     double nc = std::floor(p->L / s->r_c);
     if (nc < 3.0) return fail(RBSOG_EINVAL, "box too small: floor(L / r_c) = %g < 3", nc);
     double nf = std::floor(2.0 * p->L / s->r_c);
@@ -283,6 +292,11 @@ SampleArgs sample_args(rbsog_handle *h, uint64_t step, int nstep)
     a.size = h->size;
     a.lattice = h->lattice;
     a.samp = h->samp;
+    if (h->p.sampler == RBSOG_SAMPLER_MH) {
+        a.cdf_q = h->cdf_q;
+        a.Sq = h->Sq;
+        a.mh = h->mh;
+    }
     return a;
 }
 
@@ -596,6 +610,8 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     h->nbr_cnt = (int32_t *)(w + L.nbr_cnt);
     h->tab = (double2 *)(w + L.tab);
     h->tab_far = (double2 *)(w + L.tab_far);
+    h->cdf_q = (double *)(w + L.cdf_q);
+    h->mh = (int32_t *)(w + L.mh);
     double tabh[2 * kPhaseTable];
     phase_table(tabh);
     h->lists_valid = false;
@@ -614,6 +630,22 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     far_table(tabf.data());
     if (e == hipSuccess)
         e = hipMemcpyAsync(h->tab_far, tabf.data(), sizeof(double) * tabf.size(), hipMemcpyHostToDevice, h->st);
+    // Metropolis-Hastings draws: the proposal measure's CDF (F = 1) over the
+    // same shells, and an empty chain
+    std::vector<double> cdfq;
+    const int32_t mh0[2] = {0, -1};
+    if (e == hipSuccess && p->sampler == RBSOG_SAMPLER_MH && !h->d.full_k) {
+        rbsog_params pq = *p;
+        pq.density = RBSOG_FLAT;
+        Tables tq;
+        build_tables(*s, pq, q2, h->d.mmax, &tq, false);
+        if (tq.nshell != t.nshell) e = hipErrorInvalidValue;   // both list the shells with r3(m) > 0
+        cdfq = tq.cdf;
+        h->Sq = tq.S;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->cdf_q, cdfq.data(), sizeof(double) * cdfq.size(), hipMemcpyHostToDevice, h->st);
+        if (e == hipSuccess) e = hipMemcpyAsync(h->mh, mh0, sizeof(mh0), hipMemcpyHostToDevice, h->st);
+    }
     std::vector<double> vmh((size_t)h->d.mmax + 1);
     virial_table(*s, p->L, h->d.mmax, vmh.data());
     if (e == hipSuccess)
@@ -648,9 +680,15 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     }
     // kernel-side SOG and the constant energies (Section 4.1)
     const double log2e = 1.4426950408889634;
+    const KernelTerms kt = kernel_terms(*s);
     h->sd.n = s->n;
-    h->sd.inv_lambda = 1.0 / s->lambda;
-    h->sd.inv_lambda_log2e = log2e / s->lambda;
+    h->sd.inv_lambda = 1.0 / kt.l[0];
+    h->sd.inv_lambda_log2e = log2e / kt.l[0];
+    h->sd.two = kt.n == 2 ? 1 : 0;
+    h->sd.ya1 = kt.a[0];
+    h->sd.ya2 = kt.a[1];
+    h->sd.inv_lambda2 = 1.0 / kt.l[1];
+    h->sd.inv_lambda2_log2e = log2e / kt.l[1];
     for (int j = 0; j < s->n; ++j) {
         h->sd.c[j] = s->c[j];
         h->sd.s_log2e[j] = s->s[j] * log2e;
@@ -665,7 +703,11 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
         if (std::atoi(e) == 0) h->sd.poly = 0;
     h->Uk0 = s->Fhat0 * q1 * q1 / (2.0 * h->V);
     h->Uself = -0.5 * q2 * s->F0;
-    h->Ubg = -(q1 * q1) * (4.0 * kPi * s->lambda * s->lambda) / (2.0 * h->V);
+    // the kernel's integral over space, 4 pi sum_t a_t l_t^2 (4 pi lambda^2 for
+    // both kernels; summed so that either is taken as given)
+    double l2 = 0.0;
+    for (int t = 0; t < kt.n; ++t) l2 += kt.a[t] * kt.l[t] * kt.l[t];
+    h->Ubg = -(q1 * q1) * (4.0 * kPi * l2) / (2.0 * h->V);
     *out = h;
     return RBSOG_OK;
 }

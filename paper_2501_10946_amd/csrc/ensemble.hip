@@ -408,6 +408,8 @@ extern "C" int rbsog_ens_admit(rbsog_ens *s, const rbsog_params *p, const rbsog_
     int rc = check_params(p, sog);
     if (rc) return rc;
     if (p->full_k) return fail(RBSOG_EINVAL, "the ensemble serves random-batch replicas only (full_k = 0)");
+    if (p->sampler != RBSOG_SAMPLER_IID)
+        return fail(RBSOG_EINVAL, "the ensemble draws i.i.d. modes only (sampler = RBSOG_SAMPLER_IID)");
     int slot = -1;
     for (int r = 0; r < s->max_slots; ++r)
         if (!s->rep[r].used) {

@@ -6,6 +6,8 @@
 // F(r) = sum_g c_g exp(-s_g r^2).  Multiplying out the singular factors leaves
 //   H(r) = r^3 [F_N1 + F_N2] = exp(-r/lambda)(1 + r/lambda) - r^3 G(r^2),
 //   K(r) = r (Y - F)         = exp(-r/lambda) - r F(r^2),
+// (for a two-term kernel, the terms' a_t exp(-r/l_t)(1 + r/l_t) and
+// a_t exp(-r/l_t) summed in place of the first parts),
 // both entire in r with H(0) = K(0) = 1 and derivatives governed by
 // r_c/lambda and s_max r_c^2 (a few units for the SOG of Algorithm 1 at eps =
 // 1e-4).  On [0, r_c] each is matched by a single polynomial of degree
@@ -46,14 +48,20 @@ const CosTable &cos_table()
 // H(r) (force) or K(r) (energy) in extended precision.
 long double hk(const rbsog_sog &s, long double r, bool force)
 {
-    const long double r2 = r * r, rl = r / (long double)s.lambda;
+    const long double r2 = r * r;
     long double acc = 0.0L;
     for (int g = 0; g < s.n; ++g) {
         long double e = std::exp(-(long double)s.s[g] * r2);
         acc += force ? 2.0L * (long double)s.c[g] * (long double)s.s[g] * e : (long double)s.c[g] * e;
     }
-    long double ey = std::exp(-rl);
-    return force ? ey * (1.0L + rl) - r2 * r * acc : ey - r * acc;
+    const KernelTerms K = kernel_terms(s);
+    long double y = 0.0L;
+    for (int t = 0; t < K.n; ++t) {
+        const long double rl = r / (long double)K.l[t];
+        const long double ey = std::exp(-rl);
+        y += (long double)K.a[t] * (force ? ey * (1.0L + rl) : ey);
+    }
+    return force ? y - r2 * r * acc : y - r * acc;
 }
 
 // Chebyshev interpolant of degree < kNodes of H or K over r = (y + 1) r_c / 2,

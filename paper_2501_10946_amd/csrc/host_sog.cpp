@@ -221,16 +221,20 @@ void expand(rbsog_sog *s)
     s->Fhat0 = Fh0;
 }
 
-// max |Y - F| over r = r_c + (33 lambda - r_c) u^2, u = j/1600, j = 0..1600.
+// max |Y - F| over r = r_c + (33 l - r_c) u^2, u = j/1600, j = 0..1600, with l
+// the kernel's longest length (lambda for the Yukawa kernel).
 double sog_max_error(const rbsog_sog &s)
 {
-    double R = 33.0 * s.lambda, worst = 0.0;
+    const KernelTerms K = kernel_terms(s);
+    double R = 33.0 * K.l[0], worst = 0.0;
     for (int j = 0; j <= 1600; ++j) {
         double u = (double)j / 1600.0;
         double r = s.r_c + (R - s.r_c) * u * u;
         double F = 0.0;
         for (int g = 0; g < s.n; ++g) F += s.c[g] * std::exp(-s.s[g] * r * r);
-        double e = std::fabs(std::exp(-r / s.lambda) / r - F);
+        double Y = 0.0;
+        for (int t = 0; t < K.n; ++t) Y += K.a[t] * std::exp(-r / K.l[t]) / r;
+        double e = std::fabs(Y - F);
         if (e > worst) worst = e;
     }
     return worst;
@@ -291,9 +295,79 @@ extern "C" int rbsog_sog_init(double lambda, double r_c, double eps, int smooth,
     return fail(RBSOG_ENOROOT, "rbsog_sog_init: no decomposition with at most %d Gaussians meets eps", RBSOG_MAX_GAUSS);
 }
 
+// Two-term kernel: the partial fractions of 4 pi / (k^2 eps_EGS(k)).  With
+// b = nu lambda^2 / 4 the potential is 4 pi (1 + b k^2) / (b k^4 + k^2 +
+// lambda^{-2}); the denominator's roots in k^2 are -alpha_{1,2} =
+// -(1 -+ sqrt(1 - nu)) / (2 b), the smaller written as 2 / (lambda^2 (1 +
+// sqrt(1 - nu))) to avoid the cancellation, and the residues give the weights.
+extern "C" int rbsog_sog_init_egs(double lambda, double nu, double r_c, double eps, int smooth, rbsog_sog *out)
+{
+    if (!out) return fail(RBSOG_EINVAL, "rbsog_sog_init_egs: out is null");
+    if (!(lambda > 0.0) || !std::isfinite(lambda) || !(r_c > 0.0) || !std::isfinite(r_c))
+        return fail(RBSOG_EINVAL, "rbsog_sog_init_egs: lambda and r_c must be positive and finite");
+    if (!(nu > 0.0 && nu < 1.0)) return fail(RBSOG_EINVAL, "rbsog_sog_init_egs: nu must lie in (0, 1)");
+    if (!(eps > 0.0 && eps < 1.0)) return fail(RBSOG_EINVAL, "rbsog_sog_init_egs: eps must lie in (0, 1)");
+    if (smooth != 1 && smooth != 2) return fail(RBSOG_EINVAL, "rbsog_sog_init_egs: smooth must be 1 or 2");
+    const double root = std::sqrt(1.0 - nu);
+    const double alpha[2] = {2.0 / (lambda * lambda * (1.0 + root)), 2.0 * (1.0 + root) / (nu * lambda * lambda)};
+    const double gap = alpha[1] - alpha[0];
+    rbsog_sog s{};
+    s.nyuk = 2;
+    s.nu = nu;
+    s.ya[0] = alpha[1] / gap;
+    s.ya[1] = -alpha[0] / gap;
+    s.yl[0] = 1.0 / std::sqrt(alpha[0]);
+    s.yl[1] = 1.0 / std::sqrt(alpha[1]);
+    if (!(r_c < 33.0 * s.yl[0]))
+        return fail(RBSOG_EINVAL, "rbsog_sog_init_egs: r_c must be below 33 times the longer length %g", s.yl[0]);
+    const double eps_term = eps / (std::fabs(s.ya[0]) + std::fabs(s.ya[1]));
+    int n = 0;
+    for (int j = 0; j < 2; ++j) {
+        if (!(r_c < 33.0 * s.yl[j])) continue;   // wholly near: no Gaussians
+        rbsog_sog t{};
+        const int rc = rbsog_sog_init(s.yl[j], r_c, eps_term, smooth, RBSOG_AUTO, RBSOG_AUTO, &t);
+        if (rc != RBSOG_OK) return rc;
+        if (n + t.n > RBSOG_MAX_GAUSS)
+            return fail(RBSOG_EINVAL, "rbsog_sog_init_egs: the two terms need %d Gaussians, more than %d", n + t.n,
+                        RBSOG_MAX_GAUSS);
+        if (j == 0) {
+            s.h = t.h;
+            s.t0 = t.t0;
+            s.w = t.w;
+            s.M1 = t.M1;
+            s.M2 = t.M2;
+            s.sigma = t.sigma;
+        }
+        for (int g = 0; g < t.n; ++g, ++n) {
+            s.c[n] = s.ya[j] * t.c[g];
+            s.s[n] = t.s[g];
+            s.A[n] = s.ya[j] * t.A[g];
+            s.B[n] = t.B[g];
+        }
+    }
+    s.n = n;
+    s.lambda = lambda;
+    s.r_c = r_c;
+    s.eps = eps;
+    s.smooth = smooth;
+    s.F0 = 0.0;
+    s.Fhat0 = 0.0;
+    for (int g = 0; g < n; ++g) {
+        s.F0 += s.c[g];
+        s.Fhat0 += s.A[g];
+    }
+    s.max_err = sog_max_error(s);
+    if (!(s.max_err <= eps))
+        return fail(RBSOG_ENOROOT, "rbsog_sog_init_egs: the combined error %g exceeds eps", s.max_err);
+    *out = s;
+    return RBSOG_OK;
+}
+
 extern "C" int rbsog_sog_expand(rbsog_sog *sog)
 {
     if (!sog) return fail(RBSOG_EINVAL, "rbsog_sog_expand: null");
+    if (sog->nyuk == 2)
+        return fail(RBSOG_EINVAL, "rbsog_sog_expand: a two-term kernel is built by rbsog_sog_init_egs only");
     int n = sog->M1 + sog->M2 + 1;
     if (sog->M1 < 0 || n < 1 || n > RBSOG_MAX_GAUSS)
         return fail(RBSOG_EINVAL, "rbsog_sog_expand: need M1 >= 0 and 1 <= M1+M2+1 <= %d", RBSOG_MAX_GAUSS);

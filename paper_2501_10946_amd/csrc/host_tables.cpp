@@ -45,15 +45,20 @@ void virial_table(const rbsog_sog &s, double L, int mmax, double *vm)
 }
 
 // Correction factor of the measure.  ADAPTIVE is the leading Debye-Hueckel
-// term of eq. (3.22) as printed, with eps(k)^{-1}/k^2 = lambda^2/(1 + lambda^2 k^2)
-// for the Yukawa dielectric eps(k) = 1 + (lambda k)^{-2}.
-double density(int kind, double kT, double V, double Q2, double lambda, double k2)
+// term of eq. (3.22) as printed, with eps(k)^{-1}/k^2 the kernel's Yhat(k) /
+// (4 pi): lambda^2/(1 + lambda^2 k^2) for the Yukawa dielectric eps(k) = 1 +
+// (lambda k)^{-2}, the sum of its two terms' for the EGS dielectric.
+double density(int kind, double kT, double V, double Q2, const KernelTerms &K, double k2)
 {
-    double l2 = lambda * lambda;
     if (kind == RBSOG_FLAT) return 1.0;
     if (kind == RBSOG_K2) return k2;
-    if (kind == RBSOG_DH4PI) return (kT * V) / ((kT * V) / Q2 + (4.0 * kPi * l2) / (1.0 + l2 * k2));
-    return (kT * V) / ((kT * V) / Q2 + l2 / (1.0 + l2 * k2));
+    double g = 0.0;
+    for (int t = 0; t < K.n; ++t) {
+        const double l2 = K.l[t] * K.l[t];
+        g += K.a[t] * l2 / (1.0 + l2 * k2);
+    }
+    if (kind == RBSOG_DH4PI) return (kT * V) / ((kT * V) / Q2 + 4.0 * kPi * g);
+    return (kT * V) / ((kT * V) / Q2 + g);
 }
 
 // Largest m >= 1 with Fhat((2 pi/L)^2 m) >= 1e-16 Fhat(0).
@@ -160,7 +165,7 @@ void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax
     for (int m = 1; m <= mmax; ++m) {
         if (size[m] == 0) continue;
         double k2 = tk2 * (double)m;
-        double Fk = density(p.density, p.kT, V, Q2, s.lambda, k2);
+        double Fk = density(p.density, p.kT, V, Q2, kernel_terms(s), k2);
         double W = Fk * fhat(s, k2);
         acc = acc + (double)size[m] * W;
         t->cdf.push_back(acc);

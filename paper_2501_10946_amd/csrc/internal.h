@@ -14,6 +14,19 @@ namespace rbsog {
 // thread-local error message behind rbsog_last_error()
 int fail(int code, const char *fmt, ...);
 
+// ---- host: the kernel's Yukawa terms ----------------------------------------
+// Y(r) = sum_{t < n} a[t] e^{-r/l[t]}/r: the Yukawa kernel (n = 1, a = 1,
+// l = lambda) or the two terms of the EGS kernel (nyuk = 2), longest first.
+struct KernelTerms {
+    int n;
+    double a[2], l[2];
+};
+inline KernelTerms kernel_terms(const rbsog_sog &s)
+{
+    if (s.nyuk == 2) return KernelTerms{2, {s.ya[0], s.ya[1]}, {s.yl[0], s.yl[1]}};
+    return KernelTerms{1, {1.0, 0.0}, {s.lambda, 1.0}};
+}
+
 // ---- host: Algorithm 1 (host_sog.cpp) --------------------------------------
 double step_size(double eps, double delta);
 int c1_start(double lambda, double rc, double h, int M1, int M2, double *t0, double *w);
@@ -50,7 +63,10 @@ int default_mmax(const rbsog_sog &s, double L);
 // a process-wide cache that grows to the largest m_max asked for)
 int64_t lattice_points(int mmax);
 void lattice_copy(int mmax, int32_t *out);
-double density(int kind, double kT, double V, double Q2, double lambda, double k2);
+// the correction factor of the sampling measure (eq. 3.124) for the kernel's
+// terms (the first term of eq. 3.22 with eps(k)^{-1}/k^2 = sum_t a_t l_t^2 /
+// (1 + l_t^2 k^2))
+double density(int kind, double kT, double V, double Q2, const KernelTerms &K, double k2);
 // Fhat(k^2) = sum_m A_m exp(-B_m k^2) in ascending m
 double fhat(const rbsog_sog &s, double k2);
 // vm[m] = k^2 G(k^2) / Fhat(k^2) at k^2 = (2 pi / L)^2 m, m = 0 .. mmax, with

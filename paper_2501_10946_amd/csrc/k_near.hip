@@ -1,6 +1,7 @@
 // gfx950 kernel of librbsog: the near field of eq. (3.8),
 //   f_i = sum_{j : |d| < r_c} q_i q_j [F_N1(r) + F_N2(r)] d,   d = r_i - r_j (minimum image),
 //   F_N1 = exp(-r/lambda)(1 + r/lambda)/r^3,  F_N2 = -2 sum_g c_g s_g exp(-s_g r^2),
+//   (F_N1 summed over the terms a_t exp(-r/l_t)(1 + r/l_t)/r^3 of a two-term kernel),
 // and the near energy U_N = 1/2 sum q_i q_j (Y(r) - F(r)).
 //
 // The cell grid is the fine one, cells of width w = L / floor(2L / (r_c + skin))
@@ -193,7 +194,13 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
         float irf = __builtin_amdgcn_rsqf(r2f);
         float rf = r2f * irf;
         float ey = __builtin_amdgcn_exp2f(-rf * (float)a.sog.inv_lambda_log2e);
-        float f1 = ey * (1.0f + rf * (float)a.sog.inv_lambda) * (irf * irf * irf);
+        float f1 = ey * (1.0f + rf * (float)a.sog.inv_lambda);
+        if (a.sog.two) {   // the second Yukawa term of a two-term kernel
+            const float ez = __builtin_amdgcn_exp2f(-rf * (float)a.sog.inv_lambda2_log2e);
+            f1 = fmaf((float)a.sog.ya2, ez * (1.0f + rf * (float)a.sog.inv_lambda2), (float)a.sog.ya1 * f1);
+            ey = fmaf((float)a.sog.ya2, ez, (float)a.sog.ya1 * ey);
+        }
+        f1 = f1 * (irf * irf * irf);
         float gs = 0.0f, fs = 0.0f;
 #pragma unroll
         for (int g = 0; g < (NG == kPolyNG ? 0 : gauss_count<NG>(a)); ++g) {
@@ -226,7 +233,13 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
         double ir = rsqrt_f64(r2);
         double r = r2 * ir;
         double ey = exp2_nonpos(-r * a.sog.inv_lambda_log2e, a.e2);
-        double f1 = ey * fma(r, a.sog.inv_lambda, 1.0) * (ir * ir * ir);
+        double f1 = ey * fma(r, a.sog.inv_lambda, 1.0);
+        if (a.sog.two) {   // the second Yukawa term of a two-term kernel
+            const double ez = exp2_nonpos(-r * a.sog.inv_lambda2_log2e, a.e2);
+            f1 = fma(a.sog.ya2, ez * fma(r, a.sog.inv_lambda2, 1.0), a.sog.ya1 * f1);
+            ey = fma(a.sog.ya2, ez, a.sog.ya1 * ey);
+        }
+        f1 = f1 * (ir * ir * ir);
         double gs = 0.0, fs = 0.0;
         {
 #pragma unroll

@@ -41,6 +41,11 @@ struct SogDev {
     int n;                      // Gaussians
     double inv_lambda;          // 1/lambda
     double inv_lambda_log2e;    // log2(e)/lambda: exp(-r/lambda) = 2^(-r log2(e)/lambda)
+    // a second Yukawa term (the EGS kernel): Y = ya1 e^{-r/l1}/r + ya2 e^{-r/l2}/r
+    // with l1 in inv_lambda above; two == 0 for the Yukawa kernel (ya1 = 1)
+    int two;
+    double ya1, ya2;
+    double inv_lambda2, inv_lambda2_log2e;
     double c[kMaxGauss];        // F(r) = sum c exp(-s r^2)
     double s_log2e[kMaxGauss];  // s log2(e): exp(-s r^2) = 2^(-s log2(e) r^2)
     double cs2[kMaxGauss];      // 2 c s (force factor of the Gaussians)
@@ -159,7 +164,13 @@ struct SampleArgs {
     double4 *samp;             // [nstep][P] (nx, ny, nz, coef)
     int32_t *n_out;            // [P][3] or null (nstep == 1)
     double *coef_out;          // [P] or null (nstep == 1)
+    // Metropolis-Hastings draws when mh is set: proposals from cdf_q (total
+    // Sq), chain state mh[2] = (lattice index, shell index; -1 empty)
+    const double *cdf_q;       // [nshell]
+    double Sq;
+    int32_t *mh;
 };
+// i.i.d. draws, or (a.mh set) the Metropolis-Hastings chain in one workgroup
 hipError_t launch_sample(const SampleArgs &a, hipStream_t st);
 // ensemble: items of 64 draws, ceil(P/64) per replica, nstep = 1
 // (shift: device word holding the ensemble step counter)

@@ -28,6 +28,7 @@ struct Layout {
     size_t lattice, cdf, coef, first, size;
     size_t cell_id, count, cell_start, fill, tmp, order, order_old, xs, xs_old, tile_sum, xb, vs, vs_old, fs, ms, ms_old;
     size_t samp, part, rho, gk, eF, eW, vm, fnear, epart, kepart, flag, energy, nbr, nbr_cnt, tab, tab_far;
+    size_t cdf_q, mh;   // Metropolis-Hastings draws: proposal CDF, chain state
     size_t total;
 };
 
@@ -96,6 +97,11 @@ struct rbsog_handle {
     int64_t rb_steps, steps_done;
     uint64_t samp_step;  // first step of the modes in samp, with samp_n steps drawn
     int samp_n;
+    // Metropolis-Hastings draws (p.sampler == 1): the proposal CDF (F = 1) and
+    // its total, and the chain state (lattice index, shell index; -1 empty)
+    double *cdf_q = nullptr;
+    double Sq = 0.0;
+    int32_t *mh = nullptr;
     // rbsog_set_kT: pinned staging of the re-derived cdf and coef ([2][nshell]),
     // free again once kt_ev has completed
     double *kt_host = nullptr;

@@ -110,7 +110,9 @@ static void audit(int64_t N, double L, double lambda, double rc, int P, double s
     CHECK(span(w.kepart, w.flag) >= 8 * (size_t)far_blocks((int)N), "%s: kinetic partials", tag);
     CHECK(span(w.xs, w.xs_old) >= 32 * (size_t)N && span(w.ms, w.ms_old) >= 8 * (size_t)N, "%s: rows", tag);
     CHECK(span(w.tab, w.tab_far) >= 16 * (size_t)kPhaseTable, "%s: rotation table", tag);
-    CHECK(w.total >= w.tab_far + 16 * (size_t)kFarTable, "%s: total", tag);
+    CHECK(span(w.tab_far, w.cdf_q) >= 16 * (size_t)kFarTable, "%s: far rotation table", tag);
+    CHECK(span(w.cdf_q, w.mh) >= 8 * (size_t)d.mmax, "%s: proposal CDF of the chain", tag);
+    CHECK(w.total >= w.mh + 8, "%s: total", tag);
 }
 
 // every call below carries one argument a kernel cannot run on, and must be

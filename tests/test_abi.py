@@ -76,6 +76,36 @@ def test_sog_init_c2_matches_oracle(R, lam, rc, eps):
     assert np.abs(Fl - o.F(r)).max() <= 1e-3 * eps
 
 
+@pytest.mark.parametrize("lam,nu,rc,eps,smooth", [(1.0, 0.3, 3.0, 1e-4, 1), (0.5773, 0.8, 2.8865, 1e-6, 1),
+                                                  (1.0, 0.01, 3.0, 1e-4, 1), (1.0, 0.5, 2.5, 1e-5, 2)])
+def test_sog_init_egs_matches_oracle(R, lam, nu, rc, eps, smooth):
+    """The EGS kernel (Section 1) by the library's own partial fractions and
+    per-term decompositions: the oracle's two terms to rounding, the same
+    number of Gaussians with each term's numbers chosen the oracle's way, the
+    same Gaussians to 1e-12, and the combined bound met."""
+    s = R.rbsog_sog_init_egs(lam, nu, rc, eps, smooth)
+    o = oracle.sog_egs(lam, nu, rc, eps, smooth)
+    _, a, l = o.terms
+    assert s.nyuk == 2 and s.nu == nu and s.smooth == smooth
+    assert np.allclose(list(s.ya), a, rtol=1e-14, atol=0) and np.allclose(list(s.yl), l, rtol=1e-14, atol=0)
+    assert s.n == o.n
+    for mine, ref in ((s.c, o.c), (s.s, o.s), (s.A, o.A), (s.B, o.B)):
+        got = np.array(mine[:s.n])
+        assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    assert s.max_err <= eps and abs(s.max_err - o.err) <= 1e-3 * eps
+    assert abs(s.F0 - o.F0) <= 1e-12 * abs(o.F0) and abs(s.Fhat0 - o.Fhat0) <= 1e-12 * abs(o.Fhat0)
+
+
+def test_sog_init_egs_refuses(R):
+    for nu in (0.0, 1.0, -0.2, 1.7, float("nan")):
+        with pytest.raises(R.RbsogError):
+            R.rbsog_sog_init_egs(1.0, nu, 3.0, 1e-4)
+    with pytest.raises(R.RbsogError):   # r_c beyond the range of the longer term
+        R.rbsog_sog_init_egs(0.1, 0.5, 4.0, 1e-4)
+    with pytest.raises(R.RbsogError):
+        R.rbsog_sog_init_egs(1.0, 0.5, 3.0, 1e-4, smooth=3)
+
+
 def test_sog_init_refuses_bad_smoothness(R):
     with pytest.raises(R.RbsogError):
         R.rbsog_sog_init(1.0, 3.0, 1e-4, smooth=3)
@@ -91,6 +121,19 @@ def test_expansion_is_bitwise(R):
     s2 = R.sog_from_parameters(o2.lam, o2.rc, o2.h, o2.t0, o2.w, o2.M1, o2.M2, sigma=o2.sigma)
     for a, b in ((s2.c, o2.c), (s2.s, o2.s), (s2.A, o2.A), (s2.B, o2.B)):
         assert np.array_equal(np.array(a[: o2.n]).view(np.uint64), np.asarray(b).view(np.uint64))
+
+
+def test_sampler_parameter(R):
+    """Both samplers size the same workspace (the chain's table and state are
+    always reserved); other values are refused."""
+    o = oracle.sog_auto(1.0, 3.0, 1e-4)
+    sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+    a = R.rbsog_workspace_size(R.make_params(1000, 16.0, 1.0, 100, 1), sog)
+    b = R.rbsog_workspace_size(R.make_params(1000, 16.0, 1.0, 100, 1, sampler=R.RBSOG_SAMPLER_MH), sog)
+    assert a == b > 0
+    with pytest.raises(R.RbsogError) as e:
+        R.rbsog_workspace_size(R.make_params(1000, 16.0, 1.0, 100, 1, sampler=2), sog)
+    assert e.value.code == R.RBSOG_EINVAL
 
 
 def test_host_errors(R):
@@ -152,6 +195,29 @@ def test_near_poly_matches_pair_function(R, lam, rc):
     assert np.max(np.abs(pk - (ey - r * F))) < 2e-15
     rr = r[1:]
     assert np.allclose(pk[1:] / rr, np.exp(-rr / lam) / rr - o.F(rr), rtol=0, atol=2e-15 / rr.min())
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.9])
+def test_near_poly_matches_egs_pair_function(R, nu):
+    """The same for the two-term EGS kernel: H and K against the pair function
+    written out from the oracle's split and Gaussians (to 4e-15 times the
+    terms' weight, |a_1| + |a_2|)."""
+    lam, rc = 1.0, 3.0
+    s = R.rbsog_sog_init_egs(lam, nu, rc, 1e-4)
+    o = oracle.sog_egs(lam, nu, rc, 1e-4)
+    _, a, l = o.terms
+    ok, h, k = R.rbsog_sog_near_poly(s)
+    assert ok
+    r = np.linspace(0.0, rc, 2001)
+    y = 2.0 * r / rc - 1.0
+    c, sg = np.asarray(o.c), np.asarray(o.s)
+    G = (2.0 * c * sg * np.exp(-np.outer(r * r, sg))).sum(axis=1)
+    F = (c * np.exp(-np.outer(r * r, sg))).sum(axis=1)
+    H = sum(aj * np.exp(-r / lj) * (1.0 + r / lj) for aj, lj in zip(a, l)) - r ** 3 * G
+    K = sum(aj * np.exp(-r / lj) for aj, lj in zip(a, l)) - r * F
+    tol = 4e-15 * np.abs(a).sum()   # the terms cancel: the numpy reference rounds at their scale
+    assert np.max(np.abs(np.polynomial.polynomial.polyval(y, h) - H)) < tol
+    assert np.max(np.abs(np.polynomial.polynomial.polyval(y, k) - K)) < tol
 
 
 def test_near_poly_declines_when_inaccurate(R):

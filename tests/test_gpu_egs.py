@@ -1,0 +1,171 @@
+"""Systems on the exact gradient-corrected screening (EGS) kernel of Section 1
+(two Yukawa terms) through the library against the oracle: the oracle's
+Gaussians and terms handed to the library unchanged (so both sides draw the
+same modes from the same tables), forces, energies and virials within 1e-12
+(FP64) / 1e-5 (mixed) on the polynomial (where its fit holds) and the
+per-Gaussian FP64 pair paths,
+a 40-step trajectory to 1e-10, a kernel whose short term lies wholly in the
+near field, the library's own EGS decomposition against the oracle's, and an
+EGS replica in the served ensemble equal bit for bit to the system stepped
+alone."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_2501_10946_amd")
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-5
+DT = 0.01
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    R.lib()
+    return torch.device("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def lib_sog(o):
+    _, a, l = o.terms
+    return R.sog_from_gaussians(o.lam, o.rc, o.c, o.s, o.A, o.B, ya=a, yl=l, nu=o.nu, smooth=o.smooth)
+
+
+W = workloads.Workload
+CASES = [(W("egs_n1000_k1", N=1000, kappa=1.0, gamma=1.0, r_c=3.0, P=100, seed=301, eps=1e-5), 0.3),
+         (W("egs_n5000_k0.5", N=5000, kappa=0.5, gamma=5.0, r_c=4.0, P=64, seed=302, eps=1e-7), 0.8),
+         # the short term (length 0.05) lies wholly inside r_c = 3: no Gaussians of its own
+         (W("egs_n2000_nearonly", N=2000, kappa=1.0, gamma=2.0, r_c=3.0, P=50, seed=303, eps=1e-6), 0.01)]
+
+
+@pytest.mark.parametrize("w,nu", CASES, ids=lambda c: getattr(c, "name", str(c)))
+@pytest.mark.parametrize("path", ["fp64", "fp64_gauss", "mixed"])
+def test_egs_forces_energies(dev, w, nu, path, monkeypatch):
+    o = oracle.sog_egs(w.lam, nu, w.r_c, w.eps)
+    precision = 1 if path == "mixed" else 0
+    if path == "fp64_gauss":
+        monkeypatch.setenv("RBSOG_NEAR_POLY", "0")
+    st = workloads.make_state(w)
+    print(f"\n[case] EGS {w.name} nu={nu} {path} n={o.n} terms={o.terms[2]}", flush=True)
+    sog = lib_sog(o)
+    s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, precision=precision, device=dev)
+    if path == "fp64":   # the polynomial pair function wherever the fit holds (the first case)
+        assert R.rbsog_get_info(s.h).near_poly == int(R.rbsog_sog_near_poly(sog)[0])
+        assert R.rbsog_get_info(s.h).near_poly == 1 or w.name != "egs_n1000_k1"
+    if path == "fp64_gauss":
+        assert R.rbsog_get_info(s.h).near_poly == 0
+    ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
+    x = torch.tensor(st.x, device=dev)
+    f = torch.empty_like(x)
+    fn = torch.empty_like(x)
+    e = torch.zeros(R.ENERGY_COLS, dtype=torch.float64, device=dev)
+    R.rbsog_compute_forces(s.h, 5, x, f, fn, e)
+    torch.cuda.synchronize()
+    fo, fno, eo = ref.force(st.x, 5)
+    tol = FP64_TOL if precision == 0 else MIXED_TOL
+    f, fn, e = f.cpu().numpy(), fn.cpu().numpy(), e.cpu().numpy()
+    assert _rel(f, fo) <= tol and _rel(fn, fno) <= tol and _rel(f - fn, fo - fno) <= tol
+    for k in (0, 1):
+        assert abs(e[k] - eo[k]) <= tol * abs(eo[k])
+    for k in (2, 3, 4):   # constants: the same formulas in FP64 on both sides
+        assert abs(e[k] - eo[k]) <= 1e-13 * max(1.0, abs(eo[k]))
+    assert abs(e[6] - eo[6]) <= tol * (abs(eo[6]) + abs(eo[0]))
+    assert abs(e[7] - eo[7]) <= tol * (abs(eo[7]) + 3 * abs(eo[1]))
+
+
+def test_egs_trajectory(dev):
+    w, nu = CASES[0]
+    o = oracle.sog_egs(w.lam, nu, w.r_c, w.eps)
+    st = workloads.make_state(w)
+    s = R.System(st.q, st.m, w.L, lib_sog(o), w.kT, w.P, seed=w.seed, device=dev)
+    ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
+    x = torch.tensor(st.x, device=dev)
+    v = torch.tensor(st.v, device=dev)
+    f = torch.empty_like(x)
+    R.rbsog_compute_forces(s.h, 0, x, f)
+    R.rbsog_step(s.h, x, v, f, 0, 40, w.dt)
+    torch.cuda.synchronize()
+    R.rbsog_check(s.h)
+    xo, vo = st.x.copy(), st.v.copy()
+    fo, _, _ = ref.force(xo, 0)
+    ref.run(xo, vo, fo, 0, 40, w.dt)
+    d = x.cpu().numpy() - xo
+    d -= w.L * np.round(d / w.L)
+    assert np.abs(d).max() <= 1e-10
+
+
+def test_library_egs_decomposition(dev):
+    """A system on the library's own EGS decomposition: forces within the
+    decomposition tolerance of the oracle's full-lattice EGS forces."""
+    w, nu = CASES[0]
+    sog = R.rbsog_sog_init_egs(w.lam, nu, w.r_c, 1e-10)
+    o = oracle.sog_egs(w.lam, nu, w.r_c, 1e-10)
+    st = workloads.make_state(w)
+    s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, full_k=True, device=dev)
+    ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed, full_k=True)
+    x = torch.tensor(st.x, device=dev)
+    f = torch.empty_like(x)
+    R.rbsog_compute_forces(s.h, 0, x, f)
+    torch.cuda.synchronize()
+    fo, _, _ = ref.force(st.x, 0)
+    assert _rel(f.cpu().numpy(), fo) <= 1e-9
+
+
+def test_egs_replica_in_ensemble(dev):
+    """An EGS replica and a Yukawa replica stepped together in the served
+    ensemble end exactly where each ends stepped alone."""
+    out = {}
+    reqs = []
+    for i, (w, nu) in enumerate([CASES[0], (W("y_n800", N=800, kappa=1.0, gamma=1.0, r_c=3.0, P=80, seed=304),
+                                            None)]):
+        st = workloads.make_state(w)
+        if nu is None:
+            o = oracle.sog_auto(w.lam, w.r_c, w.eps)
+            sog = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+        else:
+            sog = lib_sog(oracle.sog_egs(w.lam, nu, w.r_c, w.eps))
+        prec = R.RBSOG_FP64 if i == 0 else R.RBSOG_MIXED
+        reqs.append((w, st, sog, R.make_params(w.N, w.L, w.kT, w.P, 104, i, 0, prec), prec, 9))
+    ens = R.rbsog_ens_create(1 << 30, 4)
+    try:
+        slots = {}
+        for i, (w, st, sog, p, prec, n) in enumerate(reqs):
+            slots[R.rbsog_ens_admit(ens, p, sog, np.ascontiguousarray(st.x), np.ascontiguousarray(st.v),
+                                    np.ascontiguousarray(st.q), np.ascontiguousarray(st.m), n, DT)] = i
+        for _ in range(50):
+            R.rbsog_ens_step(ens)
+            torch.cuda.synchronize()
+            for sl in R.rbsog_ens_poll(ens, 4):
+                i = slots[sl]
+                w, st, sog, p, prec, n = reqs[i]
+                x, v, e = np.empty(3 * w.N), np.empty(3 * w.N), np.empty(R.ENERGY_COLS * n)
+                R.rbsog_ens_retire(ens, sl, x, v, e)
+                out[i] = (x.reshape(3, -1), v.reshape(3, -1), e.reshape(-1, R.ENERGY_COLS))
+            if len(out) == len(reqs):
+                break
+    finally:
+        R.rbsog_ens_destroy(ens)
+    assert sorted(out) == [0, 1]
+    for i, (w, st, sog, p, prec, n) in enumerate(reqs):
+        s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=104, replica=i, precision=prec, device=dev)
+        x = torch.tensor(st.x, device=dev)
+        v = torch.tensor(st.v, device=dev)
+        f = torch.empty_like(x)
+        eh = torch.zeros((n, R.ENERGY_COLS), dtype=torch.float64, device=dev)
+        R.rbsog_compute_forces(s.h, 0, x, f)
+        R.rbsog_step(s.h, x, v, f, 0, n, DT, eh)
+        torch.cuda.synchronize()
+        assert np.array_equal(out[i][0], x.cpu().numpy()), f"replica {i}: positions"
+        assert np.array_equal(out[i][1], v.cpu().numpy()), f"replica {i}: velocities"
+        assert np.array_equal(out[i][2], eh.cpu().numpy()), f"replica {i}: energies"
