@@ -104,6 +104,8 @@ def lib():
             "orc_langevin_normals": (None, [_u64, _u64, _u64, _u32, _p]),
             "orc_sys_set_langevin": (None, [_p, _d, _d]),
             "orc_sys_set_sampler": (_i, [_p, _i]),
+            "orc_sys_set_bath": (_i, [_p, _i, _d, _d]),
+            "orc_sys_bath_state": (None, [_p, _p]),
             "orc_mh_draw": (None, [_i, _u64, _u64, _u32, _i, _p, _p, _p, _p, _p, _p, _p, _p]),
             "orc_rdf": (None, [_i64, _p, _d, _d, _i, _p, _p]),
             "orc_track": (None, [_i64, _d, _p, _p, _p]),
@@ -472,6 +474,17 @@ class System:
         """0: i.i.d. inverse-CDF draws; 1: the Metropolis-Hastings chain (emptied)."""
         if lib().orc_sys_set_sampler(self._h, sampler) != 0:
             raise ValueError("sampler must be 0 or 1")
+
+    def set_bath(self, kind: int, rate: float, bath_kT: float):
+        """Global bath for run(): 2 Nose-Hoover, 3 Berendsen (rate = 1/tau), 0 off."""
+        if lib().orc_sys_set_bath(self._h, kind, rate, bath_kT) != 0:
+            raise ValueError("bad bath")
+
+    def bath_state(self):
+        """(xi, eta) of the Nose-Hoover bath."""
+        out = np.zeros(2)
+        lib().orc_sys_bath_state(self._h, _ptr(out))
+        return float(out[0]), float(out[1])
 
     def set_langevin(self, friction: float, bath_kT: float):
         """Langevin thermostat for run() (friction 0: plain velocity-Verlet)."""

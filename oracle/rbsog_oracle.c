@@ -1233,6 +1233,9 @@ typedef struct {
     orc_kern kern; /* the kernel's Yukawa terms */
     int P, mmax, density, full_k, nG;
     double friction, bath_kT; /* Langevin thermostat (friction 0: plain velocity-Verlet) */
+    int bath;                 /* 0 none / Langevin (friction), 2 Nose-Hoover, 3 Berendsen */
+    double bath_rate;         /* 1/tau of the global baths                                */
+    double xi, eta;           /* Nose-Hoover friction variable and its time integral      */
     uint64_t seed;
     uint32_t replica;
     double c[64], s[64], A[64], B[64];
@@ -1437,11 +1440,75 @@ void orc_langevin_normals(uint64_t i, uint64_t step, uint64_t seed, uint32_t rep
 }
 
 /* Langevin thermostat for Algorithm 2's time loop: friction (per unit time)
- * and bath temperature; friction 0 turns it off. */
+ * and bath temperature; friction 0 turns it off (and any global bath). */
 void orc_sys_set_langevin(orc_sys *S, double friction, double bath_kT)
 {
     S->friction = friction;
     S->bath_kT = bath_kT;
+    S->bath = 0;
+}
+
+/* The global baths of the time loop (Section 5.1 equilibrates in the NVT
+ * ensemble with Nose-Hoover dynamics; Berendsen's weak coupling is the other
+ * global scheme), each applied as a half-step operator T(dt/2) before and
+ * after every velocity-Verlet step (a symmetric Trotter splitting of the
+ * thermostatted equations), with g = 3N degrees of freedom and tau = 1/rate:
+ *   Nose-Hoover (one thermostat, mass Q = g kT tau^2):
+ *     xi += (dt/4)(2K - g kT)/Q;  v *= e^{-xi dt/2} (K *= e^{-xi dt});
+ *     eta += (dt/2) xi;  xi += (dt/4)(2K - g kT)/Q;
+ *     the extended energy K + U + Q xi^2/2 + g kT eta is conserved;
+ *   Berendsen: lambda^2 = 1 + (dt/(2 tau))(g kT/(2K) - 1), v *= lambda
+ *     (K *= lambda^2; lambda = 1 when K = 0), relaxing K to g kT/2 at rate
+ *     1/tau.
+ * K is the kinetic energy.  kind 2 or 3 (0 switches every bath off); rate and
+ * bath_kT positive.  xi and eta restart at 0.  Returns 0, or -1. */
+int orc_sys_set_bath(orc_sys *S, int kind, double rate, double bath_kT)
+{
+    if (kind == 0) {
+        S->bath = 0;
+        S->friction = 0.0;
+        return 0;
+    }
+    if ((kind != 2 && kind != 3) || !(rate > 0.0) || !(bath_kT > 0.0)) return -1;
+    S->bath = kind;
+    S->bath_rate = rate;
+    S->bath_kT = bath_kT;
+    S->friction = 0.0;
+    S->xi = 0.0;
+    S->eta = 0.0;
+    return 0;
+}
+
+void orc_sys_bath_state(const orc_sys *S, double out[2])
+{
+    out[0] = S->xi;
+    out[1] = S->eta;
+}
+
+/* One half-step operator T(dt/2) of a global bath on kinetic energy *K;
+ * returns the factor the velocities are scaled by and updates *K. */
+static double bath_half(orc_sys *S, double dt, double *K)
+{
+    double g = 3.0 * (double)S->N, gkT = g * S->bath_kT;
+    if (S->bath == 2) {
+        double tau = 1.0 / S->bath_rate, Q = gkT * tau * tau;
+        S->xi += 0.25 * dt * (2.0 * *K - gkT) / Q;
+        double sc = exp(-0.5 * dt * S->xi);
+        *K = *K * (sc * sc);
+        S->eta += 0.5 * dt * S->xi;
+        S->xi += 0.25 * dt * (2.0 * *K - gkT) / Q;
+        return sc;
+    }
+    if (!(*K > 0.0)) return 1.0;
+    double lam2 = 1.0 + 0.5 * dt * S->bath_rate * (gkT / (2.0 * *K) - 1.0);
+    if (lam2 < 0.0) lam2 = 0.0;
+    *K = *K * lam2;
+    return sqrt(lam2);
+}
+
+static void scale_v(const orc_sys *S, double *v, double sc)
+{
+    for (int64_t k = 0; k < 3 * S->N; ++k) v[k] *= sc;
 }
 
 int orc_sys_run(orc_sys *S, double *x, double *v, double *f, uint64_t step0, int nsteps, double dt,
@@ -1451,6 +1518,12 @@ int orc_sys_run(orc_sys *S, double *x, double *v, double *f, uint64_t step0, int
     double L = S->L;
     int bad = 0;
     const double c1 = exp(-S->friction * dt);
+    const int global = S->bath == 2 || S->bath == 3;
+    double K = 0.0;
+    if (global && nsteps > 0) { /* the first step's opening half-step */
+        K = kinetic(S, v);
+        scale_v(S, v, bath_half(S, dt, &K));
+    }
     for (int n = 0; n < nsteps; ++n) {
         for (int64_t i = 0; i < N; ++i) {
             double hm = (0.5 * dt) / S->m[i];
@@ -1485,10 +1558,15 @@ int orc_sys_run(orc_sys *S, double *x, double *v, double *f, uint64_t step0, int
             double hm = (0.5 * dt) / S->m[i];
             for (int d = 0; d < 3; ++d) v[d * N + i] = v[d * N + i] + hm * f[d * N + i];
         }
-        if (ehist) {
+        if (global) { /* closing half-step, then the next step's opening one */
+            K = kinetic(S, v);
+            scale_v(S, v, bath_half(S, dt, &K));
+            if (ehist) e[5] = K;
+            if (n + 1 < nsteps) scale_v(S, v, bath_half(S, dt, &K));
+        } else if (ehist) {
             e[5] = kinetic(S, v);
-            memcpy(ehist + 8 * (size_t)n, e, sizeof(e));
         }
+        if (ehist) memcpy(ehist + 8 * (size_t)n, e, sizeof(e));
     }
     return bad ? -1 : 0;
 }
