@@ -366,6 +366,39 @@ int rbsog_set_kT(rbsog_handle *h, double kT);
  */
 int rbsog_set_thermostat(rbsog_handle *h, double friction, double kT);
 
+#define RBSOG_BATH_NONE 0
+#define RBSOG_BATH_LANGEVIN 1
+#define RBSOG_BATH_NOSE_HOOVER 2
+#define RBSOG_BATH_BERENDSEN 3
+
+/*
+ * Bath of rbsog_step, one at a time (replaces the previous one):
+ *   RBSOG_BATH_NONE: plain velocity-Verlet (rate, kT ignored);
+ *   RBSOG_BATH_LANGEVIN: as rbsog_set_thermostat(h, rate, kT);
+ *   RBSOG_BATH_NOSE_HOOVER: the NVT dynamics Section 5.1 equilibrates with,
+ *     one thermostat variable xi of mass Q = g kT tau^2 (g = 3N, tau = 1/rate);
+ *   RBSOG_BATH_BERENDSEN: weak coupling, the kinetic energy relaxing to
+ *     g kT/2 at rate 1/tau.
+ * The global baths act as a half-step operator before and after each
+ * velocity-Verlet step (with K the kinetic energy):
+ *   Nose-Hoover: xi += (dt/4)(2K - g kT)/Q; v *= e^{-xi dt/2};
+ *     eta += (dt/2) xi; xi += (dt/4)(2K - g kT)/Q (K after the scaling);
+ *     K + U + Q xi^2/2 + g kT eta is conserved;
+ *   Berendsen: v *= lambda, lambda^2 = 1 + (dt/(2 tau))(g kT/(2K) - 1).
+ * The kinetic energy needs the whole system, so under a global bath each
+ * step's next half-kick and drift run as a kernel of their own rather than in
+ * the far kernel (one more launch and a single-workgroup reduction per step).
+ * The energy rows report K after the step's closing half-step.  xi and eta
+ * restart at 0 on every call that selects a global bath; they carry over
+ * between rbsog_step calls.  Errors: RBSOG_EINVAL (unknown kind; rate or kT
+ * not positive and finite for a bath other than NONE), RBSOG_EHIP.
+ */
+int rbsog_set_bath(rbsog_handle *h, int kind, double rate, double kT);
+
+/* (xi, eta) of a Nose-Hoover bath into out[2] (host); synchronises the
+ * stream.  Errors: RBSOG_EINVAL, RBSOG_EHIP. */
+int rbsog_bath_state(rbsog_handle *h, double *out);
+
 /*
  * Synchronises the stream and reports the device flag: RBSOG_OK, or
  * RBSOG_ENONFINITE if any evaluation since the last check produced a

@@ -23,6 +23,7 @@ RBSOG_ADAPTIVE, RBSOG_FLAT, RBSOG_K2, RBSOG_DH4PI = 0, 1, 2, 3
 # doubles per energy row: U_N, U*_F, U_k0, U_self, U_bg, KE, W_N, W*_F
 ENERGY_COLS = 8
 RBSOG_SAMPLER_IID, RBSOG_SAMPLER_MH = 0, 1
+RBSOG_BATH_NONE, RBSOG_BATH_LANGEVIN, RBSOG_BATH_NOSE_HOOVER, RBSOG_BATH_BERENDSEN = 0, 1, 2, 3
 RBSOG_AUTO = -999
 RBSOG_MAX_GAUSS = 32
 
@@ -114,6 +115,8 @@ def lib() -> C.CDLL:
             "rbsog_ssf_scratch_size": (C.c_int, [C.c_int64, C.c_int, C.POINTER(C.c_size_t)]),
             "rbsog_ssf": (C.c_int, [C.c_int64, C.c_double, _p, _p, C.c_int, _p, C.c_size_t, _p, _p]),
             "rbsog_rdf": (C.c_int, [_p, _p, C.c_double, C.c_int, _p]),
+            "rbsog_set_bath": (C.c_int, [_p, C.c_int, C.c_double, C.c_double]),
+            "rbsog_bath_state": (C.c_int, [_p, C.POINTER(C.c_double)]),
             "rbsog_track": (C.c_int, [C.c_int64, C.c_double, _p, _p, _p, _p]),
             "rbsog_msd_scratch_size": (C.c_int, [C.POINTER(C.c_size_t)]),
             "rbsog_msd_vacf": (C.c_int, [C.c_int64, _p, _p, _p, _p, C.c_size_t, _p, _p]),
@@ -327,6 +330,17 @@ def rbsog_rdf(h, x, r_max: float, nbins: int, hist) -> None:
     import torch
     N, P, _ = _n(h)
     _check(lib().rbsog_rdf(h, _dptr(x, torch.float64, 3 * N), r_max, nbins, _dptr(hist, torch.int64, nbins)))
+
+
+def rbsog_set_bath(h, kind: int, rate: float, kT: float) -> None:
+    _check(lib().rbsog_set_bath(h, kind, rate, kT))
+
+
+def rbsog_bath_state(h):
+    """(xi, eta) of a Nose-Hoover bath."""
+    out = (C.c_double * 2)()
+    _check(lib().rbsog_bath_state(h, out))
+    return out[0], out[1]
 
 
 def rbsog_track(x, L: float, x_last, disp, stream=None) -> None:

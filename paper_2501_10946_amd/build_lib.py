@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 
 HOST_SRCS = ["host_sog.cpp", "host_tables.cpp", "host_near.cpp"]
 HIP_SRCS = ["k_cells.hip", "k_sample.hip", "k_rho.hip", "k_near.hip", "k_far.hip", "api.hip", "ensemble.hip",
-            "noalloc.hip", "observe.hip"]
+            "noalloc.hip", "observe.hip", "k_bath.hip"]
 
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall", f"-I{INCLUDE}"]
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",

@@ -135,6 +135,7 @@ Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
     L.tab_far = take(sizeof(double) * 2 * kFarTable);
     L.cdf_q = take(sizeof(double) * (size_t)d.mmax);
     L.mh = take(sizeof(int32_t) * 2);
+    L.bath = take(sizeof(double) * kBathWords);
     L.total = off;
     return L;
 }
@@ -416,8 +417,23 @@ Thermo thermo(const rbsog_handle *h, double dt, uint64_t step)
     return t;
 }
 
+BathArgs bath_args(const rbsog_handle *h, double dt, int mode)
+{
+    BathArgs b{};
+    b.kind = h->bath_kind;
+    b.mode = mode;
+    b.dt = dt;
+    b.gkT = 3.0 * (double)h->p.N * h->bath_kT;
+    b.rate = h->bath_rate;
+    b.Q = b.gkT / (h->bath_rate * h->bath_rate);
+    b.nfar = far_blocks((int)h->p.N);
+    b.kepart = h->kepart;
+    b.bath = h->bath;
+    return b;
+}
+
 int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bool kick, double dt, double *energy,
-             int32_t *gate_raise, int32_t *gate_clear, uint64_t next_step)
+             int32_t *gate_raise, int32_t *gate_clear, uint64_t next_step, int bath_mode)
 {
     RhoArgs ra = rho_args(h, samp);
     NearArgs na = near_args(h, nullptr, energy != nullptr);
@@ -454,8 +470,12 @@ int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bo
         fa.th = thermo(h, dt, next_step);
     }
     HIPCHECK(timed(h, kFar, [&] { return launch_far(fa, h->st); }));
+    // a global bath: the step's closing half-step (and the next one's opening)
+    // on the kinetic energy the far kernel's half-kick left
+    if (kick && bath_mode) HIPCHECK(timed(h, kKickDrift, [&] { return launch_bath(bath_args(h, dt, bath_mode), h->st); }));
     if (energy) {
         EnergyArgs ea = energy_args(h, energy, kick);
+        if (kick && bath_mode) ea.ke_set = h->bath + 3;
         HIPCHECK(timed(h, kEnergy, [&] { return launch_energy(ea, h->st); }));
     }
     return RBSOG_OK;
@@ -612,6 +632,7 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     h->tab_far = (double2 *)(w + L.tab_far);
     h->cdf_q = (double *)(w + L.cdf_q);
     h->mh = (int32_t *)(w + L.mh);
+    h->bath = (double *)(w + L.bath);
     double tabh[2 * kPhaseTable];
     phase_table(tabh);
     h->lists_valid = false;
@@ -646,6 +667,8 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
             e = hipMemcpyAsync(h->cdf_q, cdfq.data(), sizeof(double) * cdfq.size(), hipMemcpyHostToDevice, h->st);
         if (e == hipSuccess) e = hipMemcpyAsync(h->mh, mh0, sizeof(mh0), hipMemcpyHostToDevice, h->st);
     }
+    static const double bath0[kBathWords] = {};
+    if (e == hipSuccess) e = hipMemcpyAsync(h->bath, bath0, sizeof(bath0), hipMemcpyHostToDevice, h->st);
     std::vector<double> vmh((size_t)h->d.mmax + 1);
     virial_table(*s, p->L, h->d.mmax, vmh.data());
     if (e == hipSuccess)
@@ -858,6 +881,7 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
     // steps and back into the caller's order at the end
     PermArgs io = perm_args(h, x_dev, v_dev, f_dev);
     HIPCHECK(timed(h, kKickDrift, [&] { return launch_state_in(io, h->st); }));
+    const bool global = h->bath_kind == kBathNoseHoover || h->bath_kind == kBathBerendsen;
     // The first step's half-kick and drift run as their own kernel; those of
     // the later steps are fused into the far kernel of the step before.  Steps
     // alternate between two rebuild gates: the drift into step n raises gate n,
@@ -882,6 +906,11 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         k.flag = h->flag;
         k.th = thermo(h, dt, step0 + 1);
         k.order = h->order;
+        if (global) {   // the first step's opening half-step of the bath
+            HIPCHECK(timed(h, kKickDrift, [&] { return launch_ke_partials(k.N, h->vs, h->ms, h->kepart, h->st); }));
+            HIPCHECK(timed(h, kKickDrift, [&] { return launch_bath(bath_args(h, dt, 1), h->st); }));
+            k.vscale = h->bath + 2;
+        }
         HIPCHECK(timed(h, kKickDrift, [&] { return launch_kick_drift(k, h->st); }));
     }
     for (int n = 0; n < nsteps; ++n) {
@@ -893,10 +922,33 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         rc = modes(h, step, nsteps - n, &samp);
         if (rc) return rc;
         double *e = energy_hist_dev ? energy_hist_dev + kEnergyCols * (size_t)n : nullptr;
-        rc = evaluate(h, samp, nullptr, nullptr, true, dt, e, n + 1 < nsteps ? gate_next : nullptr, gate, step + 1);
+        const bool last = n + 1 == nsteps;
+        // a global bath keeps the next step's half-kick and drift out of the far
+        // kernel: its velocity factor needs the whole system's kinetic energy
+        rc = evaluate(h, samp, nullptr, nullptr, true, dt, e, (last || global) ? nullptr : gate_next, gate, step + 1,
+                      global ? (last ? 2 : 3) : 0);
         if (rc) return rc;
+        if (global && !last) {
+            KickDriftArgs k{};
+            k.N = (int)h->p.N;
+            k.L = h->p.L;
+            k.inv_L = 1.0 / h->p.L;
+            k.dt = dt;
+            k.xs = h->xs;
+            k.vs = h->vs;
+            k.fs = h->fs;
+            k.ms = h->ms;
+            k.xb = h->xb;
+            k.half_skin2 = 0.25 * h->d.skin * h->d.skin;
+            k.gate = gate_next;
+            k.flag = h->flag;
+            k.vscale = h->bath + 2;
+            HIPCHECK(timed(h, kKickDrift, [&] { return launch_kick_drift(k, h->st); }));
+        }
         h->phase = 1 - h->phase;
     }
+    if (global)   // the last step's closing half-step
+        HIPCHECK(timed(h, kKickDrift, [&] { return launch_scale_v((int)h->p.N, h->vs, h->bath + 2, h->st); }));
     HIPCHECK(timed(h, kKickDrift, [&] { return launch_state_out(io, h->st); }));
     h->steps_done += nsteps;
     if (h->rb_host && h->skin_default && h->d.skin > 0.0) {
@@ -988,15 +1040,42 @@ extern "C" int rbsog_set_kT(rbsog_handle *h, double kT)
     return RBSOG_OK;
 }
 
+extern "C" int rbsog_set_bath(rbsog_handle *h, int kind, double rate, double kT)
+{
+    if (!h) return fail(RBSOG_EINVAL, "null handle");
+    if (kind < RBSOG_BATH_NONE || kind > RBSOG_BATH_BERENDSEN) return fail(RBSOG_EINVAL, "unknown bath kind");
+    if (kind != RBSOG_BATH_NONE) {
+        if (!(rate > 0.0) || !std::isfinite(rate)) return fail(RBSOG_EINVAL, "the bath rate must be positive and finite");
+        if (!(kT > 0.0) || !std::isfinite(kT))
+            return fail(RBSOG_EINVAL, "the bath temperature must be positive and finite");
+    }
+    if (kind != RBSOG_BATH_NONE && kT > h->bath_kT) h->dt_checked = 0.0;   // the default skin's thermal check runs again
+    h->bath_kind = kind;
+    h->friction = kind == RBSOG_BATH_LANGEVIN ? rate : 0.0;
+    h->bath_rate = kind == RBSOG_BATH_NONE ? 0.0 : rate;
+    h->bath_kT = kind == RBSOG_BATH_NONE ? 0.0 : kT;
+    if (kind == RBSOG_BATH_NOSE_HOOVER || kind == RBSOG_BATH_BERENDSEN) {   // xi and eta restart at 0
+        static const double zero[kBathWords] = {};
+        HIPCHECK(hipMemcpyAsync(h->bath, zero, sizeof(zero), hipMemcpyHostToDevice, h->st));
+    }
+    return RBSOG_OK;
+}
+
 extern "C" int rbsog_set_thermostat(rbsog_handle *h, double friction, double kT)
 {
     if (!h) return fail(RBSOG_EINVAL, "null handle");
     if (!(friction >= 0.0) || !std::isfinite(friction)) return fail(RBSOG_EINVAL, "friction must be >= 0 and finite");
-    if (friction > 0.0 && (!(kT > 0.0) || !std::isfinite(kT)))
-        return fail(RBSOG_EINVAL, "the bath temperature must be positive and finite");
-    if (friction > 0.0 && kT > h->bath_kT) h->dt_checked = 0.0;   // the default skin's thermal check runs again
-    h->friction = friction;
-    h->bath_kT = friction > 0.0 ? kT : 0.0;
+    return rbsog_set_bath(h, friction > 0.0 ? RBSOG_BATH_LANGEVIN : RBSOG_BATH_NONE, friction, kT);
+}
+
+extern "C" int rbsog_bath_state(rbsog_handle *h, double *out)
+{
+    if (!h || !out) return fail(RBSOG_EINVAL, "null handle or out");
+    double b[kBathWords];
+    HIPCHECK(hipMemcpyAsync(b, h->bath, sizeof(b), hipMemcpyDeviceToHost, h->st));
+    HIPCHECK(hipStreamSynchronize(h->st));
+    out[0] = b[0];
+    out[1] = b[1];
     return RBSOG_OK;
 }
 

@@ -227,6 +227,12 @@ __device__ inline void kick_drift_body(const KickDriftArgs &a, int b)
     const double4 r = a.xs[p];
     double x[3] = {r.x, r.y, r.z};
     double v[3] = {a.vs[p], a.vs[a.N + p], a.vs[2 * a.N + p]};
+    if (a.vscale) {   // a global bath's half-steps since the last kick
+        const double sc = *a.vscale;
+        v[0] = v[0] * sc;
+        v[1] = v[1] * sc;
+        v[2] = v[2] * sc;
+    }
     const double f[3] = {a.fs[p], a.fs[a.N + p], a.fs[2 * a.N + p]};
     bool bad = false;
     double d2 = kick_drift_row(x, v, f, hm, a.dt, a.L, a.inv_L, a.xb, a.N, p, &bad, a.th,

@@ -245,7 +245,7 @@ __device__ inline void energy_body(const EnergyArgs &a, uint64_t shift)
         o[2] = a.Uk0;
         o[3] = a.Uself;
         o[4] = a.Ubg;
-        o[5] = ke;
+        o[5] = a.ke_set ? *a.ke_set : ke;
         o[6] = wn;
         o[7] = wf;
     }

@@ -144,6 +144,7 @@ struct KickDriftArgs {
     int *flag;             // set to 1 on a step of a box length or more
     Thermo th;
     const int32_t *order;  // caller index of each row (the thermostat's noise counter; when th.on)
+    const double *vscale;  // null, or a device factor the velocities take before the half-kick
 };
 hipError_t launch_kick_drift(const KickDriftArgs &a, hipStream_t st);
 hipError_t launch_kick_drift_batch(const KickDriftArgs *tab, const EnsItem *per256, int n, hipStream_t st);
@@ -333,11 +334,33 @@ struct EnergyArgs {
     double Uk0, Uself, Ubg;
     double *out;               // [rows][kEnergyCols]; one system writes row row0
     uint64_t row0;
+    const double *ke_set;      // null, or the kinetic energy to report (a global bath's, after its half-step)
 };
 hipError_t launch_energy(const EnergyArgs &a, hipStream_t st);
 // ensemble: one item per replica; each writes row *shift + row0 of its out
 hipError_t launch_energy_batch(const EnergyArgs *tab, const EnsItem *items, int n, const uint64_t *shift,
                                hipStream_t st);
+
+
+// --- global baths (Nose-Hoover, Berendsen) ------------------------------------
+// The bath state lives on the device: kBathWords doubles, [0] xi, [1] eta (the
+// Nose-Hoover friction and its time integral), [2] the factor the velocities
+// take next, [3] the kinetic energy after the last closing half-step.
+constexpr int kBathWords = 8;
+constexpr int kBathNoseHoover = 2, kBathBerendsen = 3;
+struct BathArgs {
+    int kind;                  // kBathNoseHoover or kBathBerendsen
+    int mode;                  // 1: opening half-step; 2: closing; 3: closing then opening
+    double dt, gkT, Q, rate;   // g k_B T with g = 3N; Nose-Hoover mass g kT tau^2; 1/tau
+    int nfar;
+    const double *kepart;      // [nfar] kinetic-energy partials of the current velocities
+    double *bath;              // [kBathWords]
+};
+hipError_t launch_bath(const BathArgs &a, hipStream_t st);
+// kinetic-energy partials of vs (cell order) in the far kernel's blocks
+hipError_t launch_ke_partials(int N, const double *vs, const double *ms, double *kepart, hipStream_t st);
+// vs *= *scale
+hipError_t launch_scale_v(int N, double *vs, const double *scale, hipStream_t st);
 
 
 }  // namespace rbsog

@@ -29,6 +29,7 @@ struct Layout {
     size_t cell_id, count, cell_start, fill, tmp, order, order_old, xs, xs_old, tile_sum, xb, vs, vs_old, fs, ms, ms_old;
     size_t samp, part, rho, gk, eF, eW, vm, fnear, epart, kepart, flag, energy, nbr, nbr_cnt, tab, tab_far;
     size_t cdf_q, mh;   // Metropolis-Hastings draws: proposal CDF, chain state
+    size_t bath;        // global bath state (kBathWords doubles)
     size_t total;
 };
 
@@ -108,6 +109,11 @@ struct rbsog_handle {
     hipEvent_t kt_ev = nullptr;
     // Langevin thermostat of rbsog_step (rbsog_set_thermostat; friction 0: off)
     double friction = 0.0, bath_kT = 0.0;
+    // global bath of rbsog_step (rbsog_set_bath: Nose-Hoover or Berendsen;
+    // 0: none), its rate 1/tau and device state
+    int bath_kind = 0;
+    double bath_rate = 0.0;
+    double *bath = nullptr;
     // per-kernel event timing (rbsog_timing_enable)
     bool timing = false;
     std::vector<hipEvent_t> events;
@@ -180,6 +186,7 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
 Thermo thermo(const rbsog_handle *h, double dt, uint64_t step);
 // with gate_raise the far kernel also drifts into force index next_step
 int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bool kick, double dt, double *energy,
-             int32_t *gate_raise = nullptr, int32_t *gate_clear = nullptr, uint64_t next_step = 0);
+             int32_t *gate_raise = nullptr, int32_t *gate_clear = nullptr, uint64_t next_step = 0,
+             int bath_mode = 0);
 
 }  // namespace rbsog

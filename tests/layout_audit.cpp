@@ -112,7 +112,8 @@ static void audit(int64_t N, double L, double lambda, double rc, int P, double s
     CHECK(span(w.tab, w.tab_far) >= 16 * (size_t)kPhaseTable, "%s: rotation table", tag);
     CHECK(span(w.tab_far, w.cdf_q) >= 16 * (size_t)kFarTable, "%s: far rotation table", tag);
     CHECK(span(w.cdf_q, w.mh) >= 8 * (size_t)d.mmax, "%s: proposal CDF of the chain", tag);
-    CHECK(w.total >= w.mh + 8, "%s: total", tag);
+    CHECK(span(w.mh, w.bath) >= 8, "%s: chain state", tag);
+    CHECK(w.total >= w.bath + 8 * (size_t)kBathWords, "%s: total", tag);
 }
 
 // every call below carries one argument a kernel cannot run on, and must be
@@ -153,6 +154,31 @@ static void guards()
     c.N = 10;
     c.vs = d;   // velocities to move but no snapshot of them
     refused(launch_cell_build(c, nullptr), "cell build moving velocities without their snapshot");
+    // global baths
+    BathArgs ba{};
+    ba.kind = kBathNoseHoover;
+    ba.mode = 3;
+    ba.dt = 0.01;
+    ba.gkT = 30.0;
+    ba.Q = 1.0;
+    ba.rate = 1.0;
+    ba.nfar = 1;
+    ba.kepart = d;
+    ba.bath = d;
+    BathArgs bb = ba;
+    bb.mode = 0;
+    refused(launch_bath(bb, nullptr), "bath step of no half-step");
+    bb = ba;
+    bb.kind = 1;
+    refused(launch_bath(bb, nullptr), "bath kernel for a local (Langevin) bath");
+    bb = ba;
+    bb.Q = 0.0;
+    refused(launch_bath(bb, nullptr), "Nose-Hoover of no mass");
+    bb = ba;
+    bb.kepart = nullptr;
+    refused(launch_bath(bb, nullptr), "bath without kinetic partials");
+    refused(launch_ke_partials(0, d, d, d, nullptr), "kinetic partials of no particles");
+    refused(launch_scale_v(4, d, nullptr, nullptr), "velocity scaling without its factor");
     // near field
     NearArgs n{};
     n.N = 10;
