@@ -78,9 +78,9 @@ KERNEL_SOURCES = {
 # WRITE_SIZE 262150 KiB for 262144 KiB written: x1.000).
 MEASURED_TRAFFIC = {
     # kernel: (sources sha256, FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale)
-    "near": ("cb5a8445e8db941953d4cdb5040480630e8dcdac1b05e0daf63bc0ad4786350b", 446129.0, 100836.0, 2.0, 1.0),
-    "far": ("588a3c800a7387fd521e28549d55d14f3a7d53b62e450a6bb1d034d3b82c572c", 78334.0, 78613.0, 2.0, 1.0),
-    "nlist": ("37be81c709958307290ced9782fe720a393df3645ab90f387636741a12468be1", 84019.0, 523248.0, 2.0, 1.0),
+    "near": ("1daa80a40affc7c07b42801c5af763a5a0ecd0fcea18a323e0697bd37ae38133", 446270.0, 100836.0, 2.0, 1.0),
+    "far": ("c041e700b542d55eb61e478ffa06fc1bce98a2cbebf5a009e76e816abb1d10a0", 78334.0, 78613.0, 2.0, 1.0),
+    "nlist": ("85afbbb2331887b4c272203addcf417e21c115a9895568513adf8907a6f07213", 84024.0, 523322.0, 2.0, 1.0),
 }
 
 # VALU issue at the same workload (FP64): VALU busy = SQ_ACTIVE_INST_VALU x 4
@@ -89,9 +89,9 @@ MEASURED_TRAFFIC = {
 # fraction of the VALU's lane-cycles that issued work.
 MEASURED_VALU = {
     # kernel: (sources sha256, VALU busy, lane utilisation)
-    "near": ("cb5a8445e8db941953d4cdb5040480630e8dcdac1b05e0daf63bc0ad4786350b", 0.87, 0.90),
-    "far": ("588a3c800a7387fd521e28549d55d14f3a7d53b62e450a6bb1d034d3b82c572c", 0.88, 1.00),
-    "nlist": ("37be81c709958307290ced9782fe720a393df3645ab90f387636741a12468be1", 0.77, 0.78),
+    "near": ("1daa80a40affc7c07b42801c5af763a5a0ecd0fcea18a323e0697bd37ae38133", 0.87, 0.90),
+    "far": ("c041e700b542d55eb61e478ffa06fc1bce98a2cbebf5a009e76e816abb1d10a0", 0.88, 1.00),
+    "nlist": ("85afbbb2331887b4c272203addcf417e21c115a9895568513adf8907a6f07213", 0.77, 0.78),
 }
 
 
