@@ -89,6 +89,17 @@ def lib():
             "orc_near_subset_k": (_i, [_i64, _p, _p, _d, _i, _p, _p, _d, _i, _p, _p, _i64, _p, _p]),
             "orc_sys_create_k": (_p, [_i64, _d, _i, _p, _p, _d, _d, _i, _i, _u64, _u32, _i, _i, _i, _p, _p, _p, _p,
                                       _p, _p]),
+            "orc_cells_box": (None, [_i64, _p, _p, _d, _p, _p, _p]),
+            "orc_near_box": (_i, [_i64, _p, _p, _p, _i, _p, _p, _d, _i, _p, _p, _p, _p, _p]),
+            "orc_near_subset_box": (_i, [_i64, _p, _p, _p, _i, _p, _p, _d, _i, _p, _p, _i64, _p, _p]),
+            "orc_rho_box": (None, [_i64, _p, _p, _p, _i, _p, _p]),
+            "orc_far_rb_box": (None, [_i64, _p, _p, _p, _i, _p, _p, _p, _p]),
+            "orc_far_rb_virial_box": (_d, [_i, _p, _p, _p, _p, _i, _p, _p]),
+            "orc_far_full_box": (_d, [_i64, _p, _p, _p, _i, _p, _p, _p, _p]),
+            "orc_box_lattice": (_i64, [_p, _i, _p, _p, _p, _p]),
+            "orc_box_draw": (None, [_i, _u64, _u64, _u32, _i64, _p, _p, _p, _p, _p]),
+            "orc_sys_create_box": (_p, [_i64, _p, _i, _p, _p, _d, _d, _i, _i, _u64, _u32, _i, _i, _i, _p, _p, _p, _p,
+                                        _p, _p]),
             "orc_sys_create": (_p, [_i64, _d, _d, _d, _d, _i, _i, _u64, _u32, _i, _i, _i, _p, _p, _p, _p, _p, _p]),
             "orc_sys_destroy": (None, [_p]),
             "orc_sys_mmax": (_i, [_p]),
@@ -348,15 +359,33 @@ def cells(x: np.ndarray, L: float, rc: float):
     return cs, order
 
 
+def box(L) -> np.ndarray:
+    """Edges (L_x, L_y, L_z) of a box given as one edge or three."""
+    b = np.ascontiguousarray(np.broadcast_to(np.asarray(L, dtype=np.float64), (3,)))
+    return b.copy()
+
+
+def is_cube(L) -> bool:
+    b = box(L)
+    return bool(b[0] == b[1] == b[2])
+
+
 def near(x, q, L, s: SOG, virial: bool = False):
-    """Near-field forces [3, N] and energy U_N; with virial, also W_N."""
+    """Near-field forces [3, N] and energy U_N; with virial, also W_N.  L: one
+    edge or the three edges of a cuboid."""
     x, q = _f64(x), _f64(q)
     N = x.shape[1]
     f = np.zeros((3, N))
     U, W = C.c_double(), C.c_double()
     nY, ya, yl = s.terms
-    if lib().orc_near_k(N, _ptr(x), _ptr(q), L, nY, _ptr(ya), _ptr(yl), s.rc, s.n, _ptr(s.c), _ptr(s.s), _ptr(f),
-                        C.byref(U), C.byref(W)) != 0:
+    if np.ndim(L) == 0:
+        r = lib().orc_near_k(N, _ptr(x), _ptr(q), L, nY, _ptr(ya), _ptr(yl), s.rc, s.n, _ptr(s.c), _ptr(s.s),
+                             _ptr(f), C.byref(U), C.byref(W))
+    else:
+        Lb = box(L)
+        r = lib().orc_near_box(N, _ptr(x), _ptr(q), _ptr(Lb), nY, _ptr(ya), _ptr(yl), s.rc, s.n, _ptr(s.c),
+                               _ptr(s.s), _ptr(f), C.byref(U), C.byref(W))
+    if r != 0:
         raise ValueError("near: bad kernel")
     return (f, U.value, W.value) if virial else (f, U.value)
 
@@ -367,8 +396,13 @@ def near_subset(x, q, L, s: SOG, idx):
     idx = np.ascontiguousarray(idx, dtype=np.int64)
     f = np.zeros((3, len(idx)))
     nY, ya, yl = s.terms
-    rc = lib().orc_near_subset_k(x.shape[1], _ptr(x), _ptr(q), L, nY, _ptr(ya), _ptr(yl), s.rc, s.n, _ptr(s.c),
-                                 _ptr(s.s), len(idx), _ptr(idx), _ptr(f))
+    if np.ndim(L) == 0:
+        rc = lib().orc_near_subset_k(x.shape[1], _ptr(x), _ptr(q), L, nY, _ptr(ya), _ptr(yl), s.rc, s.n,
+                                     _ptr(s.c), _ptr(s.s), len(idx), _ptr(idx), _ptr(f))
+    else:
+        Lb = box(L)
+        rc = lib().orc_near_subset_box(x.shape[1], _ptr(x), _ptr(q), _ptr(Lb), nY, _ptr(ya), _ptr(yl), s.rc, s.n,
+                                       _ptr(s.c), _ptr(s.s), len(idx), _ptr(idx), _ptr(f))
     if rc != 0:
         raise ValueError("near_subset: particle index out of range or bad kernel")
     return f
@@ -379,7 +413,10 @@ def rho(x, q, L, n3) -> np.ndarray:
     n3 = np.ascontiguousarray(n3, dtype=np.int32)
     P = n3.shape[0]
     out = np.zeros((P, 2))
-    lib().orc_rho(x.shape[1], _ptr(x), _ptr(q), L, P, _ptr(n3), _ptr(out))
+    if np.ndim(L) == 0:
+        lib().orc_rho(x.shape[1], _ptr(x), _ptr(q), L, P, _ptr(n3), _ptr(out))
+    else:
+        lib().orc_rho_box(x.shape[1], _ptr(x), _ptr(q), _ptr(box(L)), P, _ptr(n3), _ptr(out))
     return out
 
 
@@ -388,7 +425,11 @@ def far_rb(x, q, L, n3, coef, rho_):
     n3 = np.ascontiguousarray(n3, dtype=np.int32)
     coef, rho_ = _f64(coef), _f64(rho_)
     f = np.zeros_like(x)
-    lib().orc_far_rb(x.shape[1], _ptr(x), _ptr(q), L, n3.shape[0], _ptr(n3), _ptr(coef), _ptr(rho_), _ptr(f))
+    if np.ndim(L) == 0:
+        lib().orc_far_rb(x.shape[1], _ptr(x), _ptr(q), L, n3.shape[0], _ptr(n3), _ptr(coef), _ptr(rho_), _ptr(f))
+    else:
+        lib().orc_far_rb_box(x.shape[1], _ptr(x), _ptr(q), _ptr(box(L)), n3.shape[0], _ptr(n3), _ptr(coef),
+                             _ptr(rho_), _ptr(f))
     return f
 
 
@@ -406,7 +447,32 @@ def far_rb_virial(n3, coef, rho_, L, s: SOG) -> float:
     """The random-batch estimator of the far-field virial for the modes n3."""
     n3 = np.ascontiguousarray(n3, dtype=np.int32)
     coef, rho_ = _f64(coef), _f64(rho_)
-    return lib().orc_far_rb_virial(n3.shape[0], _ptr(n3), _ptr(coef), _ptr(rho_), L, s.n, _ptr(s.A), _ptr(s.B))
+    if np.ndim(L) == 0:
+        return lib().orc_far_rb_virial(n3.shape[0], _ptr(n3), _ptr(coef), _ptr(rho_), L, s.n, _ptr(s.A), _ptr(s.B))
+    return lib().orc_far_rb_virial_box(n3.shape[0], _ptr(n3), _ptr(coef), _ptr(rho_), _ptr(box(L)), s.n,
+                                       _ptr(s.A), _ptr(s.B))
+
+
+def box_lattice(L, s: SOG):
+    """(n3 [count, 3], k2 [count]): the Fourier lattice of a box, sorted by k^2."""
+    Lb = box(L)
+    cnt = lib().orc_box_lattice(_ptr(Lb), s.n, _ptr(s.A), _ptr(s.B), None, None)
+    if cnt < 0:
+        raise ValueError("lattice beyond |n_d| = 511")
+    n3 = np.zeros((cnt, 3), dtype=np.int32)
+    k2 = np.zeros(cnt)
+    lib().orc_box_lattice(_ptr(Lb), s.n, _ptr(s.A), _ptr(s.B), _ptr(n3), _ptr(k2))
+    return n3, k2
+
+
+def far_full_box(x, q, L, s: SOG, virial: bool = False):
+    """Full-lattice far forces and energy of a box over box_lattice's modes."""
+    x, q = _f64(x), _f64(q)
+    f = np.zeros_like(x)
+    W = C.c_double()
+    U = lib().orc_far_full_box(x.shape[1], _ptr(x), _ptr(q), _ptr(box(L)), s.n, _ptr(s.A), _ptr(s.B), _ptr(f),
+                               C.byref(W))
+    return (f, U, W.value) if virial else (f, U)
 
 
 # ---------------------------------------------------------------------------
@@ -422,11 +488,17 @@ class System:
         self.m = _f64(m)
         self.N = self.q.shape[0]
         self.L, self.sog, self.kT, self.P = L, s, kT, P
-        self.V = L ** 3
+        self.V = float(np.prod(box(L)))
         nY, self._ya, self._yl = s.terms
-        self._h = lib().orc_sys_create_k(self.N, L, nY, _ptr(self._ya), _ptr(self._yl), s.rc, kT, P, mmax, seed,
-                                         replica, density, int(full_k), s.n, _ptr(s.c), _ptr(s.s), _ptr(s.A),
-                                         _ptr(s.B), _ptr(self.q), _ptr(self.m))
+        if np.ndim(L) == 0:
+            self._h = lib().orc_sys_create_k(self.N, L, nY, _ptr(self._ya), _ptr(self._yl), s.rc, kT, P, mmax, seed,
+                                             replica, density, int(full_k), s.n, _ptr(s.c), _ptr(s.s), _ptr(s.A),
+                                             _ptr(s.B), _ptr(self.q), _ptr(self.m))
+        else:
+            self._Lb = box(L)
+            self._h = lib().orc_sys_create_box(self.N, _ptr(self._Lb), nY, _ptr(self._ya), _ptr(self._yl), s.rc, kT,
+                                               P, mmax, seed, replica, density, int(full_k), s.n, _ptr(s.c),
+                                               _ptr(s.s), _ptr(s.A), _ptr(s.B), _ptr(self.q), _ptr(self.m))
         if not self._h:
             raise ValueError("oracle system creation failed")
         self.mmax = lib().orc_sys_mmax(self._h)
@@ -548,13 +620,14 @@ def num_threads() -> int:
 def yukawa_image_sum(x, q, L, lam, r_max: float):
     """Energy and forces of the periodic Yukawa system by direct summation over
     every image with |r_ij + n L| < r_max (the plain definition the method
-    approximates; Section 2).  Pure numpy, for a handful of particles."""
+    approximates; Section 2; L one edge or the three of a cuboid).  Pure
+    numpy, for a handful of particles."""
     x = _f64(x)
     q = _f64(q)
     N = x.shape[1]
-    nimg = int(math.ceil(r_max / L)) + 1
-    rng = np.arange(-nimg, nimg + 1)
-    sh = np.stack(np.meshgrid(rng, rng, rng, indexing="ij"), -1).reshape(-1, 3) * L
+    Lb = box(L)
+    ax = [np.arange(-(int(math.ceil(r_max / Lb[d])) + 1), int(math.ceil(r_max / Lb[d])) + 2) for d in range(3)]
+    sh = np.stack(np.meshgrid(*ax, indexing="ij"), -1).reshape(-1, 3) * Lb[None, :]
     U = 0.0
     f = np.zeros((3, N))
     pos = x.T

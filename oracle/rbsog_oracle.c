@@ -795,27 +795,34 @@ void orc_mh_draw(int P, uint64_t step, uint64_t seed, uint32_t replica, int nshe
 /* Cell list (the neighbour set of eq. 3.8, built as cells of width >= rc)    */
 /* ------------------------------------------------------------------------- */
 
-/* nc = floor(L/rc) cells per axis, inv = nc/L, c_d = clamp(floor(x_d inv), 0, nc-1),
- * id = (c_z nc + c_y) nc + c_x.  cell_start[nc^3+1] and order[N] list the
- * particles sorted by id, ties in ascending particle index (a stable sort of
- * the original order).  Returns nc. */
-int orc_cells(int64_t N, const double *x, double L, double rc, int32_t *cell_start, int32_t *order)
+/* Cells of a box with edges Lb[3]: nc_d = floor(L_d/rc) cells along axis d,
+ * inv_d = nc_d/L_d, c_d = clamp(floor(x_d inv_d), 0, nc_d-1),
+ * id = (c_z nc_y + c_y) nc_x + c_x.  cell_start[nc_x nc_y nc_z + 1] and
+ * order[N] list the particles sorted by id, ties in ascending particle index
+ * (a stable sort of the original order).  Writes nc_d to nc_out. */
+void orc_cells_box(int64_t N, const double *x, const double *Lb, double rc, int32_t *cell_start, int32_t *order,
+                   int *nc_out)
 {
-    int nc = (int)floor(L / rc);
-    double inv = (double)nc / L;
-    int64_t ncell = (int64_t)nc * nc * nc;
+    int nc[3];
+    double inv[3];
+    for (int d = 0; d < 3; ++d) {
+        nc[d] = (int)floor(Lb[d] / rc);
+        inv[d] = (double)nc[d] / Lb[d];
+        nc_out[d] = nc[d];
+    }
+    int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
     int32_t *id = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));
     int64_t *cnt = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
     for (int64_t i = 0; i < N; ++i) {
         int cd[3];
         for (int d = 0; d < 3; ++d) {
-            double f = floor(x[d * N + i] * inv);
+            double f = floor(x[d * N + i] * inv[d]);
             int c = (int)f;
             if (f < 0.0) c = 0;
-            if (c > nc - 1) c = nc - 1;
+            if (c > nc[d] - 1) c = nc[d] - 1;
             cd[d] = c;
         }
-        id[i] = (cd[2] * nc + cd[1]) * nc + cd[0];
+        id[i] = (cd[2] * nc[1] + cd[1]) * nc[0] + cd[0];
         cnt[id[i]]++;
     }
     int64_t run = 0;
@@ -831,7 +838,15 @@ int orc_cells(int64_t N, const double *x, double L, double rc, int32_t *cell_sta
     }
     free(cnt);
     free(id);
-    return nc;
+}
+
+/* The cubic box: nc = floor(L/rc) per axis.  Returns nc. */
+int orc_cells(int64_t N, const double *x, double L, double rc, int32_t *cell_start, int32_t *order)
+{
+    const double Lb[3] = {L, L, L};
+    int nc[3];
+    orc_cells_box(N, x, Lb, rc, cell_start, order, nc);
+    return nc[0];
 }
 
 /* ------------------------------------------------------------------------- */
@@ -873,46 +888,63 @@ static void near_pair(double r2, const orc_kern *K, int nG, const double *c, con
  * cutoff contributes.  With L >= 3 rc and
  * N > 2000 the pairs are found through the cell list; otherwise every image
  * shift that can reach within rc is looped over directly (tiny boxes). */
-static void near_k(int64_t N, const double *x, const double *q, double L, orc_kern K, double rc, int nG,
-                   const double *c, const double *s, double *f, double *U_out, double *W_out);
+static void near_box(int64_t N, const double *x, const double *q, const double *Lb, orc_kern K, double rc,
+                     int nG, const double *c, const double *s, double *f, double *U_out, double *W_out);
 
 void orc_near(int64_t N, const double *x, const double *q, double L, double lambda, double rc, int nG,
               const double *c, const double *s, double *f, double *U_out, double *W_out)
 {
-    near_k(N, x, q, L, kern_yukawa(lambda), rc, nG, c, s, f, U_out, W_out);
+    const double Lb[3] = {L, L, L};
+    near_box(N, x, q, Lb, kern_yukawa(lambda), rc, nG, c, s, f, U_out, W_out);
 }
 
 /* orc_near for a kernel given by its terms.  Returns 0, or -1 for a bad kernel. */
 int orc_near_k(int64_t N, const double *x, const double *q, double L, int nY, const double *ya, const double *yl,
                double rc, int nG, const double *c, const double *s, double *f, double *U_out, double *W_out)
 {
+    const double Lb[3] = {L, L, L};
     orc_kern K;
     if (kern_make(nY, ya, yl, &K) != 0) return -1;
-    near_k(N, x, q, L, K, rc, nG, c, s, f, U_out, W_out);
+    near_box(N, x, q, Lb, K, rc, nG, c, s, f, U_out, W_out);
     return 0;
 }
 
-static void near_k(int64_t N, const double *x, const double *q, double L, orc_kern K, double rc, int nG,
-                   const double *c, const double *s, double *f, double *U_out, double *W_out)
+/* orc_near_k in a box of edges Lb[3] (a cuboid; every pair within rc, over
+ * all images). */
+int orc_near_box(int64_t N, const double *x, const double *q, const double *Lb, int nY, const double *ya,
+                 const double *yl, double rc, int nG, const double *c, const double *s, double *f, double *U_out,
+                 double *W_out)
+{
+    orc_kern K;
+    if (kern_make(nY, ya, yl, &K) != 0) return -1;
+    near_box(N, x, q, Lb, K, rc, nG, c, s, f, U_out, W_out);
+    return 0;
+}
+
+static void near_box(int64_t N, const double *x, const double *q, const double *Lb, orc_kern K, double rc,
+                     int nG, const double *c, const double *s, double *f, double *U_out, double *W_out)
 {
     double rc2 = rc * rc;
     double *ei = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
     double *wi = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
-    int nc = (int)floor(L / rc);
-    if (nc >= 3 && N > 2000) {
-        int32_t *cs = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nc * nc * nc + 1));
+    int nc[3];
+    for (int d = 0; d < 3; ++d) nc[d] = (int)floor(Lb[d] / rc);
+    if (nc[0] >= 3 && nc[1] >= 3 && nc[2] >= 3 && N > 2000) {
+        int32_t *cs = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nc[0] * nc[1] * nc[2] + 1));
         int32_t *ord = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
-        orc_cells(N, x, L, rc, cs, ord);
-        double inv = (double)nc / L;
+        int ncb[3];
+        orc_cells_box(N, x, Lb, rc, cs, ord, ncb);
+        double inv[3];
+        for (int d = 0; d < 3; ++d) inv[d] = (double)nc[d] / Lb[d];
 #pragma omp parallel for schedule(dynamic, 256)
         for (int64_t i = 0; i < N; ++i) {
             double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
             int ci[3];
             for (int d = 0; d < 3; ++d) {
-                double fl = floor(x[d * N + i] * inv);
+                double fl = floor(x[d * N + i] * inv[d]);
                 int cc = (int)fl;
                 if (fl < 0.0) cc = 0;
-                if (cc > nc - 1) cc = nc - 1;
+                if (cc > nc[d] - 1) cc = nc[d] - 1;
                 ci[d] = cc;
             }
             double fx = 0, fy = 0, fz = 0, e = 0, w = 0;
@@ -921,10 +953,10 @@ static void near_k(int64_t N, const double *x, const double *q, double L, orc_ke
                     for (int dx = -1; dx <= 1; ++dx) {
                         int cx = ci[0] + dx, cy = ci[1] + dy, cz = ci[2] + dz;
                         double sx = 0, sy = 0, sz = 0; /* image shift of the neighbour cell */
-                        if (cx < 0) { cx += nc; sx = -L; } else if (cx >= nc) { cx -= nc; sx = L; }
-                        if (cy < 0) { cy += nc; sy = -L; } else if (cy >= nc) { cy -= nc; sy = L; }
-                        if (cz < 0) { cz += nc; sz = -L; } else if (cz >= nc) { cz -= nc; sz = L; }
-                        int cell = (cz * nc + cy) * nc + cx;
+                        if (cx < 0) { cx += nc[0]; sx = -Lb[0]; } else if (cx >= nc[0]) { cx -= nc[0]; sx = Lb[0]; }
+                        if (cy < 0) { cy += nc[1]; sy = -Lb[1]; } else if (cy >= nc[1]) { cy -= nc[1]; sy = Lb[1]; }
+                        if (cz < 0) { cz += nc[2]; sz = -Lb[2]; } else if (cz >= nc[2]) { cz -= nc[2]; sz = Lb[2]; }
+                        int cell = (cz * nc[1] + cy) * nc[0] + cx;
                         for (int32_t p = cs[cell]; p < cs[cell + 1]; ++p) {
                             int64_t j = ord[p];
                             if (j == i) continue;
@@ -946,18 +978,19 @@ static void near_k(int64_t N, const double *x, const double *q, double L, orc_ke
         free(cs);
         free(ord);
     } else {
-        int nimg = (int)ceil(rc / L);
+        int ni[3];
+        for (int d = 0; d < 3; ++d) ni[d] = (int)ceil(rc / Lb[d]);
 #pragma omp parallel for schedule(dynamic, 16)
         for (int64_t i = 0; i < N; ++i) {
             double fx = 0, fy = 0, fz = 0, e = 0, w = 0;
             for (int64_t j = 0; j < N; ++j) {
-                for (int a = -nimg; a <= nimg; ++a)
-                    for (int b = -nimg; b <= nimg; ++b)
-                        for (int cc = -nimg; cc <= nimg; ++cc) {
+                for (int a = -ni[0]; a <= ni[0]; ++a)
+                    for (int b = -ni[1]; b <= ni[1]; ++b)
+                        for (int cc = -ni[2]; cc <= ni[2]; ++cc) {
                             if (j == i && a == 0 && b == 0 && cc == 0) continue;
-                            double dx_ = x[i] - x[j] - a * L;
-                            double dy_ = x[N + i] - x[N + j] - b * L;
-                            double dz_ = x[2 * N + i] - x[2 * N + j] - cc * L;
+                            double dx_ = x[i] - x[j] - a * Lb[0];
+                            double dy_ = x[N + i] - x[N + j] - b * Lb[1];
+                            double dz_ = x[2 * N + i] - x[2 * N + j] - cc * Lb[2];
                             double r2 = dx_ * dx_ + dy_ * dy_ + dz_ * dz_;
                             if (r2 >= rc2 || r2 == 0.0) continue;
                             double fac, en;
@@ -990,13 +1023,15 @@ static void near_k(int64_t N, const double *x, const double *q, double L, orc_ke
  * list when L >= 3 rc and by looping over every image shift that can reach
  * within rc otherwise (boxes smaller than three cutoffs).  f_out is
  * [3][nsub].  Returns 0, or -1 for an index outside [0, N). */
-static int near_subset_k(int64_t N, const double *x, const double *q, double L, orc_kern K, double rc, int nG,
-                         const double *c, const double *s, int64_t nsub, const int64_t *idx, double *f_out);
+static int near_subset_box(int64_t N, const double *x, const double *q, const double *Lb, orc_kern K, double rc,
+                           int nG, const double *c, const double *s, int64_t nsub, const int64_t *idx,
+                           double *f_out);
 
 int orc_near_subset(int64_t N, const double *x, const double *q, double L, double lambda, double rc, int nG,
                     const double *c, const double *s, int64_t nsub, const int64_t *idx, double *f_out)
 {
-    return near_subset_k(N, x, q, L, kern_yukawa(lambda), rc, nG, c, s, nsub, idx, f_out);
+    const double Lb[3] = {L, L, L};
+    return near_subset_box(N, x, q, Lb, kern_yukawa(lambda), rc, nG, c, s, nsub, idx, f_out);
 }
 
 /* orc_near_subset for a kernel given by its terms (-1 also for a bad kernel). */
@@ -1004,32 +1039,46 @@ int orc_near_subset_k(int64_t N, const double *x, const double *q, double L, int
                       const double *yl, double rc, int nG, const double *c, const double *s, int64_t nsub,
                       const int64_t *idx, double *f_out)
 {
+    const double Lb[3] = {L, L, L};
     orc_kern K;
     if (kern_make(nY, ya, yl, &K) != 0) return -1;
-    return near_subset_k(N, x, q, L, K, rc, nG, c, s, nsub, idx, f_out);
+    return near_subset_box(N, x, q, Lb, K, rc, nG, c, s, nsub, idx, f_out);
 }
 
-static int near_subset_k(int64_t N, const double *x, const double *q, double L, orc_kern K, double rc, int nG,
-                         const double *c, const double *s, int64_t nsub, const int64_t *idx, double *f_out)
+/* orc_near_subset_k in a box of edges Lb[3]. */
+int orc_near_subset_box(int64_t N, const double *x, const double *q, const double *Lb, int nY, const double *ya,
+                        const double *yl, double rc, int nG, const double *c, const double *s, int64_t nsub,
+                        const int64_t *idx, double *f_out)
+{
+    orc_kern K;
+    if (kern_make(nY, ya, yl, &K) != 0) return -1;
+    return near_subset_box(N, x, q, Lb, K, rc, nG, c, s, nsub, idx, f_out);
+}
+
+static int near_subset_box(int64_t N, const double *x, const double *q, const double *Lb, orc_kern K, double rc,
+                           int nG, const double *c, const double *s, int64_t nsub, const int64_t *idx,
+                           double *f_out)
 {
     double rc2 = rc * rc;
-    int nc = (int)floor(L / rc);
+    int nc[3];
+    for (int d = 0; d < 3; ++d) nc[d] = (int)floor(Lb[d] / rc);
     for (int64_t k = 0; k < nsub; ++k)
         if (idx[k] < 0 || idx[k] >= N) return -1;
-    if (nc < 3) {
-        int nimg = (int)ceil(rc / L);
+    if (nc[0] < 3 || nc[1] < 3 || nc[2] < 3) {
+        int ni[3];
+        for (int d = 0; d < 3; ++d) ni[d] = (int)ceil(rc / Lb[d]);
 #pragma omp parallel for schedule(dynamic, 4)
         for (int64_t k = 0; k < nsub; ++k) {
             int64_t i = idx[k];
             double fx = 0, fy = 0, fz = 0;
             for (int64_t j = 0; j < N; ++j)
-                for (int a = -nimg; a <= nimg; ++a)
-                    for (int b = -nimg; b <= nimg; ++b)
-                        for (int cc = -nimg; cc <= nimg; ++cc) {
+                for (int a = -ni[0]; a <= ni[0]; ++a)
+                    for (int b = -ni[1]; b <= ni[1]; ++b)
+                        for (int cc = -ni[2]; cc <= ni[2]; ++cc) {
                             if (j == i && a == 0 && b == 0 && cc == 0) continue;
-                            double ddx = x[i] - x[j] - a * L;
-                            double ddy = x[N + i] - x[N + j] - b * L;
-                            double ddz = x[2 * N + i] - x[2 * N + j] - cc * L;
+                            double ddx = x[i] - x[j] - a * Lb[0];
+                            double ddy = x[N + i] - x[N + j] - b * Lb[1];
+                            double ddz = x[2 * N + i] - x[2 * N + j] - cc * Lb[2];
                             double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
                             if (r2 >= rc2 || r2 == 0.0) continue;
                             double fac, en;
@@ -1041,19 +1090,21 @@ static int near_subset_k(int64_t N, const double *x, const double *q, double L, 
         }
         return 0;
     }
-    int32_t *cs = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nc * nc * nc + 1));
+    int32_t *cs = (int32_t *)malloc(sizeof(int32_t) * ((size_t)nc[0] * nc[1] * nc[2] + 1));
     int32_t *ord = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
-    orc_cells(N, x, L, rc, cs, ord);
-    double inv = (double)nc / L;
+    int ncb[3];
+    orc_cells_box(N, x, Lb, rc, cs, ord, ncb);
+    double inv[3];
+    for (int d = 0; d < 3; ++d) inv[d] = (double)nc[d] / Lb[d];
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t k = 0; k < nsub; ++k) {
         int64_t i = idx[k];
         int ci[3];
         for (int d = 0; d < 3; ++d) {
-            double fl = floor(x[d * N + i] * inv);
+            double fl = floor(x[d * N + i] * inv[d]);
             int cc = (int)fl;
             if (fl < 0.0) cc = 0;
-            if (cc > nc - 1) cc = nc - 1;
+            if (cc > nc[d] - 1) cc = nc[d] - 1;
             ci[d] = cc;
         }
         double fx = 0, fy = 0, fz = 0;
@@ -1062,10 +1113,10 @@ static int near_subset_k(int64_t N, const double *x, const double *q, double L, 
                 for (int dx = -1; dx <= 1; ++dx) {
                     int cx = ci[0] + dx, cy = ci[1] + dy, cz = ci[2] + dz;
                     double sx = 0, sy = 0, sz = 0;
-                    if (cx < 0) { cx += nc; sx = -L; } else if (cx >= nc) { cx -= nc; sx = L; }
-                    if (cy < 0) { cy += nc; sy = -L; } else if (cy >= nc) { cy -= nc; sy = L; }
-                    if (cz < 0) { cz += nc; sz = -L; } else if (cz >= nc) { cz -= nc; sz = L; }
-                    int cell = (cz * nc + cy) * nc + cx;
+                    if (cx < 0) { cx += nc[0]; sx = -Lb[0]; } else if (cx >= nc[0]) { cx -= nc[0]; sx = Lb[0]; }
+                    if (cy < 0) { cy += nc[1]; sy = -Lb[1]; } else if (cy >= nc[1]) { cy -= nc[1]; sy = Lb[1]; }
+                    if (cz < 0) { cz += nc[2]; sz = -Lb[2]; } else if (cz >= nc[2]) { cz -= nc[2]; sz = Lb[2]; }
+                    int cell = (cz * nc[1] + cy) * nc[0] + cx;
                     for (int32_t p = cs[cell]; p < cs[cell + 1]; ++p) {
                         int64_t j = ord[p];
                         if (j == i) continue;
@@ -1089,14 +1140,16 @@ static int near_subset_k(int64_t N, const double *x, const double *q, double L, 
 /* Section 2 and 4.1: structure factors and the far field                     */
 /* ------------------------------------------------------------------------- */
 
-/* rho(k_l) = sum_j q_j e^{i k_l . r_j} with k_l = (2 pi/L) n_l (Section 2).
- * rho is [P][2] = (re, im).  The phase is formed literally as k . r. */
-void orc_rho(int64_t N, const double *x, const double *q, double L, int P, const int32_t *n3, double *rho)
+/* rho(k_l) = sum_j q_j e^{i k_l . r_j} with k_l = 2 pi (n_x/L_x, n_y/L_y, n_z/L_z)
+ * (Section 2; a box of edges Lb[3]).  rho is [P][2] = (re, im).  The phase
+ * is formed literally as k . r. */
+void orc_rho_box(int64_t N, const double *x, const double *q, const double *Lb, int P, const int32_t *n3,
+                 double *rho)
 {
-    double t = (2.0 * ORC_PI) / L;
+    double tx = (2.0 * ORC_PI) / Lb[0], ty = (2.0 * ORC_PI) / Lb[1], tz = (2.0 * ORC_PI) / Lb[2];
 #pragma omp parallel for schedule(static)
     for (int l = 0; l < P; ++l) {
-        double kx = t * n3[3 * l], ky = t * n3[3 * l + 1], kz = t * n3[3 * l + 2];
+        double kx = tx * n3[3 * l], ky = ty * n3[3 * l + 1], kz = tz * n3[3 * l + 2];
         double re = 0.0, im = 0.0;
         for (int64_t j = 0; j < N; ++j) {
             double th = kx * x[j] + ky * x[N + j] + kz * x[2 * N + j];
@@ -1108,19 +1161,26 @@ void orc_rho(int64_t N, const double *x, const double *q, double L, int P, const
     }
 }
 
+/* The cubic box: k = (2 pi / L) n. */
+void orc_rho(int64_t N, const double *x, const double *q, double L, int P, const int32_t *n3, double *rho)
+{
+    const double Lb[3] = {L, L, L};
+    orc_rho_box(N, x, q, Lb, P, n3, rho);
+}
+
 /* Random-batch far force, eq. (UF):  F*_i = -(S/(2PV)) sum_l grad_i |rho_l|^2 / F(k_l)
  * with grad_i |rho|^2 = 2 q_i k Im(e^{-i k.r_i} rho), i.e.
  * F*_i = -q_i sum_l coef_l k_l (rho_im cos th - rho_re sin th),  coef = S/(P V F(k)).
  * Adds into f (SoA). */
-void orc_far_rb(int64_t N, const double *x, const double *q, double L, int P, const int32_t *n3,
-                const double *coef, const double *rho, double *f)
+void orc_far_rb_box(int64_t N, const double *x, const double *q, const double *Lb, int P, const int32_t *n3,
+                    const double *coef, const double *rho, double *f)
 {
-    double t = (2.0 * ORC_PI) / L;
+    double tx = (2.0 * ORC_PI) / Lb[0], ty = (2.0 * ORC_PI) / Lb[1], tz = (2.0 * ORC_PI) / Lb[2];
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
         double fx = 0, fy = 0, fz = 0;
         for (int l = 0; l < P; ++l) {
-            double kx = t * n3[3 * l], ky = t * n3[3 * l + 1], kz = t * n3[3 * l + 2];
+            double kx = tx * n3[3 * l], ky = ty * n3[3 * l + 1], kz = tz * n3[3 * l + 2];
             double th = kx * x[i] + ky * x[N + i] + kz * x[2 * N + i];
             double im = rho[2 * l + 1] * cos(th) - rho[2 * l] * sin(th);
             double g = coef[l] * im;
@@ -1130,6 +1190,13 @@ void orc_far_rb(int64_t N, const double *x, const double *q, double L, int P, co
         f[N + i] -= q[i] * fy;
         f[2 * N + i] -= q[i] * fz;
     }
+}
+
+void orc_far_rb(int64_t N, const double *x, const double *q, double L, int P, const int32_t *n3,
+                const double *coef, const double *rho, double *f)
+{
+    const double Lb[3] = {L, L, L};
+    orc_far_rb_box(N, x, q, Lb, P, n3, coef, rho, f);
 }
 
 /* Estimator of the far energy, eq. (UF): U*_F = S/(2PV) sum_l |rho_l|^2 / F(k_l)
@@ -1142,50 +1209,61 @@ double orc_far_rb_energy(int P, const double *coef, const double *rho)
 }
 
 /* Virial of the far field, W_F = -3V dU_F/dV with the configuration scaled
- * with the box: U_F = (1/2V) sum_k Fhat(k^2) |rho(k)|^2 has rho unchanged
- * (k . r is invariant) while 1/V and k^2 = (2 pi / L)^2 |n|^2 (prop. to V^(-2/3))
+ * with the box (all edges by one factor): U_F = (1/2V) sum_k Fhat(k^2) |rho(k)|^2
+ * has rho unchanged (k . r is invariant) while 1/V and k^2 (each k_d = 2 pi
+ * n_d / L_d, so k^2 is prop. to V^(-2/3))
  * change, so W_F = 3 U_F - (1/V) sum_k k^2 G(k^2) |rho(k)|^2 with
  * G = -dFhat/d(k^2).  Its random-batch estimator over the modes of eq. (UF)
  * (the same importance weights as the energy, coef_l = S / (P V F(k_l))):
  *   W*_F = sum_l coef_l |rho_l|^2 (3/2 - k_l^2 G(k_l^2) / Fhat(k_l^2)). */
-double orc_far_rb_virial(int P, const int32_t *n3, const double *coef, const double *rho, double L, int nG,
-                         const double *A, const double *B)
+static double box_k2(const double *Lb, const int32_t *n)
 {
-    double t = (2.0 * ORC_PI) / L, W = 0.0;
+    if (Lb[0] == Lb[1] && Lb[1] == Lb[2]) { /* cubic: (2 pi/L)^2 |n|^2, as the shell tables form it */
+        double t = (2.0 * ORC_PI) / Lb[0];
+        double m = (double)n[0] * n[0] + (double)n[1] * n[1] + (double)n[2] * n[2];
+        return t * t * m;
+    }
+    double kx = (2.0 * ORC_PI) * n[0] / Lb[0], ky = (2.0 * ORC_PI) * n[1] / Lb[1], kz = (2.0 * ORC_PI) * n[2] / Lb[2];
+    return kx * kx + ky * ky + kz * kz;
+}
+
+double orc_far_rb_virial_box(int P, const int32_t *n3, const double *coef, const double *rho, const double *Lb,
+                             int nG, const double *A, const double *B)
+{
+    double W = 0.0;
     for (int l = 0; l < P; ++l) {
-        double m = (double)n3[3 * l] * n3[3 * l] + (double)n3[3 * l + 1] * n3[3 * l + 1] +
-                   (double)n3[3 * l + 2] * n3[3 * l + 2];
-        double k2 = t * t * m;
+        double k2 = box_k2(Lb, n3 + 3 * l);
         double r2 = rho[2 * l] * rho[2 * l] + rho[2 * l + 1] * rho[2 * l + 1];
         W += coef[l] * r2 * (1.5 - k2 * orc_Fhat_slope(nG, A, B, k2) / orc_Fhat(nG, A, B, k2));
     }
     return W;
 }
 
-/* Deterministic far field summed over every lattice mode 1 <= |n|^2 <= mmax
- * (eqs. 3.5 and 3.8, k = 0 excluded; its energy is added separately):
+double orc_far_rb_virial(int P, const int32_t *n3, const double *coef, const double *rho, double L, int nG,
+                         const double *A, const double *B)
+{
+    const double Lb[3] = {L, L, L};
+    return orc_far_rb_virial_box(P, n3, coef, rho, Lb, nG, A, B);
+}
+
+/* Deterministic far field summed over the lattice modes n3[0..cnt) of a box
+ * of edges Lb[3] (eqs. 3.5 and 3.8, k = 0 excluded; its energy is added
+ * separately):
  *   U_F = (1/2V) sum_k Fhat(k) |rho(k)|^2,
  *   F_i += -(q_i/V) sum_k k Fhat(k) Im(e^{-ik.r_i} rho(k)),
  * and (W_out, nullable) the virial W_F = 3 U_F - (1/V) sum_k k^2 G(k^2) |rho|^2
  * (see orc_far_rb_virial).  Adds into f; returns U_F. */
-double orc_far_full(int64_t N, const double *x, const double *q, double L, int nG, const double *A,
-                    const double *B, int mmax, double *f, double *W_out)
+static double far_full_list(int64_t N, const double *x, const double *q, const double *Lb, int nG, const double *A,
+                            const double *B, int64_t cnt, const int32_t *n3, double *f, double *W_out)
 {
-    int64_t cnt = orc_lattice_count(mmax);
-    int32_t *n3 = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)cnt);
-    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * ((size_t)mmax + 2));
-    orc_lattice_build(mmax, n3, start);
-    double t = (2.0 * ORC_PI) / L, V = L * L * L;
-    double *rho = (double *)malloc(sizeof(double) * 2 * (size_t)cnt);
-    double *fh = (double *)malloc(sizeof(double) * (size_t)cnt);
-    for (int64_t p = 0; p < cnt; ++p) {
-        double m = (double)n3[3 * p] * n3[3 * p] + (double)n3[3 * p + 1] * n3[3 * p + 1] +
-                   (double)n3[3 * p + 2] * n3[3 * p + 2];
-        fh[p] = orc_Fhat(nG, A, B, t * t * m);
-    }
+    double tx = (2.0 * ORC_PI) / Lb[0], ty = (2.0 * ORC_PI) / Lb[1], tz = (2.0 * ORC_PI) / Lb[2];
+    double V = Lb[0] * Lb[1] * Lb[2];
+    double *rho = (double *)malloc(sizeof(double) * 2 * (size_t)(cnt > 0 ? cnt : 1));
+    double *fh = (double *)malloc(sizeof(double) * (size_t)(cnt > 0 ? cnt : 1));
+    for (int64_t p = 0; p < cnt; ++p) fh[p] = orc_Fhat(nG, A, B, box_k2(Lb, n3 + 3 * p));
 #pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < cnt; ++p) {
-        double kx = t * n3[3 * p], ky = t * n3[3 * p + 1], kz = t * n3[3 * p + 2];
+        double kx = tx * n3[3 * p], ky = ty * n3[3 * p + 1], kz = tz * n3[3 * p + 2];
         double re = 0.0, im = 0.0;
         for (int64_t j = 0; j < N; ++j) {
             double th = kx * x[j] + ky * x[N + j] + kz * x[2 * N + j];
@@ -1197,11 +1275,10 @@ double orc_far_full(int64_t N, const double *x, const double *q, double L, int n
     }
     double U = 0.0, Wk = 0.0;
     for (int64_t p = 0; p < cnt; ++p) {
-        double m = (double)n3[3 * p] * n3[3 * p] + (double)n3[3 * p + 1] * n3[3 * p + 1] +
-                   (double)n3[3 * p + 2] * n3[3 * p + 2];
+        double k2 = box_k2(Lb, n3 + 3 * p);
         double r2 = rho[2 * p] * rho[2 * p] + rho[2 * p + 1] * rho[2 * p + 1];
         U += fh[p] * r2;
-        Wk += t * t * m * orc_Fhat_slope(nG, A, B, t * t * m) * r2;
+        Wk += k2 * orc_Fhat_slope(nG, A, B, k2) * r2;
     }
     U = U / (2.0 * V);
     if (W_out) *W_out = 3.0 * U - Wk / V;
@@ -1209,7 +1286,7 @@ double orc_far_full(int64_t N, const double *x, const double *q, double L, int n
     for (int64_t i = 0; i < N; ++i) {
         double fx = 0, fy = 0, fz = 0;
         for (int64_t p = 0; p < cnt; ++p) {
-            double kx = t * n3[3 * p], ky = t * n3[3 * p + 1], kz = t * n3[3 * p + 2];
+            double kx = tx * n3[3 * p], ky = ty * n3[3 * p + 1], kz = tz * n3[3 * p + 2];
             double th = kx * x[i] + ky * x[N + i] + kz * x[2 * N + i];
             double im = rho[2 * p + 1] * cos(th) - rho[2 * p] * sin(th);
             double g = fh[p] * im;
@@ -1219,8 +1296,136 @@ double orc_far_full(int64_t N, const double *x, const double *q, double L, int n
         f[N + i] -= q[i] * fy / V;
         f[2 * N + i] -= q[i] * fz / V;
     }
-    free(n3); free(start); free(rho); free(fh);
+    free(rho); free(fh);
     return U;
+}
+
+/* The cubic box over every mode 1 <= |n|^2 <= mmax. */
+double orc_far_full(int64_t N, const double *x, const double *q, double L, int nG, const double *A,
+                    const double *B, int mmax, double *f, double *W_out)
+{
+    int64_t cnt = orc_lattice_count(mmax);
+    int32_t *n3 = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)cnt);
+    int64_t *start = (int64_t *)malloc(sizeof(int64_t) * ((size_t)mmax + 2));
+    orc_lattice_build(mmax, n3, start);
+    const double Lb[3] = {L, L, L};
+    double U = far_full_list(N, x, q, Lb, nG, A, B, cnt, n3, f, W_out);
+    free(n3); free(start);
+    return U;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cuboid boxes: the lattice and the sampling measure point by point         */
+/* ------------------------------------------------------------------------- */
+
+typedef struct { double k2; int32_t n[3]; } box_point;
+
+static int box_point_cmp(const void *a, const void *b)
+{
+    const box_point *p = (const box_point *)a, *r = (const box_point *)b;
+    if (p->k2 < r->k2) return -1;
+    if (p->k2 > r->k2) return 1;
+    for (int d = 0; d < 3; ++d) {
+        if (p->n[d] < r->n[d]) return -1;
+        if (p->n[d] > r->n[d]) return 1;
+    }
+    return 0;
+}
+
+/* The Fourier lattice of a box of edges Lb[3] (k = 2 pi (n_x/L_x, n_y/L_y,
+ * n_z/L_z)): every n != 0 with Fhat(k^2) >= 1e-16 Fhat(0) (the truncation of
+ * the cubic default, Fhat decreasing in k^2), sorted by (k^2, n_x, n_y, n_z).
+ * In a cubic box this is the lattice 1 <= |n|^2 <= m_max of the default
+ * m_max.  Writes n3_out[count][3] and k2_out[count] when not null; returns the
+ * count, or -1 when some |n_d| would exceed 511. */
+int64_t orc_box_lattice(const double *Lb, int nG, const double *A, const double *B, int32_t *n3_out,
+                        double *k2_out)
+{
+    double thr = 1e-16 * orc_Fhat(nG, A, B, 0.0);
+    double lo = 0.0, hi = 1.0;
+    while (orc_Fhat(nG, A, B, hi) >= thr) hi *= 2.0;
+    for (int it = 0; it < 200; ++it) { /* the k^2 where Fhat crosses thr */
+        double mid = 0.5 * (lo + hi);
+        if (orc_Fhat(nG, A, B, mid) >= thr) lo = mid; else hi = mid;
+    }
+    int nm[3];
+    for (int d = 0; d < 3; ++d) {
+        nm[d] = (int)floor(Lb[d] * sqrt(hi) / (2.0 * ORC_PI)) + 1;
+        if (nm[d] > 511) return -1;
+    }
+    int64_t cap = (int64_t)(2 * nm[0] + 1) * (2 * nm[1] + 1) * (2 * nm[2] + 1);
+    box_point *pts = (box_point *)malloc(sizeof(box_point) * (size_t)cap);
+    int64_t cnt = 0;
+    for (int a = -nm[0]; a <= nm[0]; ++a)
+        for (int b = -nm[1]; b <= nm[1]; ++b)
+            for (int c = -nm[2]; c <= nm[2]; ++c) {
+                if (a == 0 && b == 0 && c == 0) continue;
+                int32_t n[3] = {a, b, c};
+                double k2 = box_k2(Lb, n);
+                if (!(orc_Fhat(nG, A, B, k2) >= thr)) continue;
+                pts[cnt].k2 = k2;
+                pts[cnt].n[0] = a; pts[cnt].n[1] = b; pts[cnt].n[2] = c;
+                cnt++;
+            }
+    qsort(pts, (size_t)cnt, sizeof(box_point), box_point_cmp);
+    for (int64_t i = 0; i < cnt; ++i) {
+        if (n3_out) for (int d = 0; d < 3; ++d) n3_out[3 * i + d] = pts[i].n[d];
+        if (k2_out) k2_out[i] = pts[i].k2;
+    }
+    free(pts);
+    return cnt;
+}
+
+/* The far field of orc_far_full over the lattice of orc_box_lattice. */
+double orc_far_full_box(int64_t N, const double *x, const double *q, const double *Lb, int nG, const double *A,
+                        const double *B, double *f, double *W_out)
+{
+    int64_t cnt = orc_box_lattice(Lb, nG, A, B, NULL, NULL);
+    if (cnt < 0) return NAN;
+    int32_t *n3 = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)(cnt > 0 ? cnt : 1));
+    orc_box_lattice(Lb, nG, A, B, n3, NULL);
+    double U = far_full_list(N, x, q, Lb, nG, A, B, cnt, n3, f, W_out);
+    free(n3);
+    return U;
+}
+
+/* Point-by-point measure of a cuboid box, eq. (3.124) without the shell
+ * grouping (the measure depends on k^2, which no longer groups by |n|^2):
+ * cdf_i = cdf_{i-1} + F(k_i^2) Fhat(k_i^2) over the lattice in its order,
+ * S = cdf_last, coef_i = S / (P V F(k_i^2)). */
+static void box_tables(int64_t cnt, const double *k2, int nG, const double *A, const double *B, double V, int kind,
+                       double kT, double Q2, const orc_kern *K, int P, double *cdf, double *coef)
+{
+    double run = 0.0;
+    for (int64_t i = 0; i < cnt; ++i) {
+        double Fk = density_k(kind, kT, V, Q2, K, k2[i]);
+        run = run + Fk * orc_Fhat(nG, A, B, k2[i]);
+        cdf[i] = run;
+    }
+    for (int64_t i = 0; i < cnt; ++i) coef[i] = run / ((double)P * V * density_k(kind, kT, V, Q2, K, k2[i]));
+}
+
+/* Draws of a cuboid box: sample l at force-evaluation index `step` takes
+ * (w0, ...) = Philox4x64-10(counter = (l, step, 0, 0), key = (seed, replica)),
+ * u = (w0 >> 11) 2^-53, and the first point with cdf_i > u S (the last if
+ * none). */
+void orc_box_draw(int P, uint64_t step, uint64_t seed, uint32_t replica, int64_t cnt, const double *cdf,
+                  const double *coef, const int32_t *n3, int32_t *n_out, double *coef_out)
+{
+    double S = cdf[cnt - 1];
+    for (int l = 0; l < P; ++l) {
+        uint64_t ctr[4] = {(uint64_t)l, step, 0, 0}, key[2] = {seed, (uint64_t)replica}, w[4];
+        orc_philox4x64_10(ctr, key, w);
+        double target = (double)(w[0] >> 11) * (1.0 / 9007199254740992.0) * S;
+        int64_t lo = 0, hi = cnt;
+        while (lo < hi) {
+            int64_t mid = lo + (hi - lo) / 2;
+            if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        int64_t i = lo < cnt ? lo : cnt - 1;
+        for (int d = 0; d < 3; ++d) n_out[3 * l + d] = n3[3 * i + d];
+        coef_out[l] = coef[i];
+    }
 }
 
 /* ------------------------------------------------------------------------- */
@@ -1230,6 +1435,8 @@ double orc_far_full(int64_t N, const double *x, const double *q, double L, int n
 typedef struct {
     int64_t N;
     double L, V, lambda, rc, kT, Q1, Q2;
+    double Lb[3];  /* edges; a cuboid (cuboid = 1) samples point by point */
+    int cuboid;
     orc_kern kern; /* the kernel's Yukawa terms */
     int P, mmax, density, full_k, nG;
     double friction, bath_kT; /* Langevin thermostat (friction 0: plain velocity-Verlet) */
@@ -1279,6 +1486,7 @@ orc_sys *orc_sys_create_k(int64_t N, double L, int nY, const double *ya, const d
     if (nG < 1 || nG > 64 || kern_make(nY, ya, yl, &K) != 0) return NULL;
     orc_sys *S = (orc_sys *)calloc(1, sizeof(orc_sys));
     S->N = N; S->L = L; S->V = L * L * L; S->lambda = yl[0]; S->kern = K; S->rc = rc; S->kT = kT;
+    S->Lb[0] = S->Lb[1] = S->Lb[2] = L;
     S->P = P; S->density = density; S->full_k = full_k; S->nG = nG;
     S->seed = seed; S->replica = replica; S->q = q; S->m = m;
     memcpy(S->c, c, sizeof(double) * nG); memcpy(S->s, s, sizeof(double) * nG);
@@ -1301,6 +1509,50 @@ orc_sys *orc_sys_create_k(int64_t N, double L, int nY, const double *ya, const d
     return S;
 }
 
+/* A system in a box of edges Lb[3].  Equal edges give orc_sys_create_k's
+ * system; a cuboid samples point by point (orc_box_lattice, the point
+ * tables, orc_box_draw) and requires mmax = 0 (the default truncation).
+ * NULL for bad arguments or a lattice beyond |n_d| = 511. */
+orc_sys *orc_sys_create_box(int64_t N, const double *Lb, int nY, const double *ya, const double *yl, double rc,
+                            double kT, int P, int mmax, uint64_t seed, uint32_t replica, int density, int full_k,
+                            int nG, const double *c, const double *s, const double *A, const double *B,
+                            const double *q, const double *m)
+{
+    if (Lb[0] == Lb[1] && Lb[1] == Lb[2])
+        return orc_sys_create_k(N, Lb[0], nY, ya, yl, rc, kT, P, mmax, seed, replica, density, full_k, nG, c, s, A,
+                                B, q, m);
+    orc_kern K;
+    if (nG < 1 || nG > 64 || mmax != 0 || kern_make(nY, ya, yl, &K) != 0) return NULL;
+    for (int d = 0; d < 3; ++d)
+        if (!(Lb[d] > 0.0)) return NULL;
+    int64_t cnt = orc_box_lattice(Lb, nG, A, B, NULL, NULL);
+    if (cnt < 1) return NULL;
+    orc_sys *S = (orc_sys *)calloc(1, sizeof(orc_sys));
+    S->N = N; S->L = Lb[0]; S->V = Lb[0] * Lb[1] * Lb[2]; S->lambda = yl[0]; S->kern = K; S->rc = rc; S->kT = kT;
+    S->Lb[0] = Lb[0]; S->Lb[1] = Lb[1]; S->Lb[2] = Lb[2];
+    S->cuboid = 1;
+    S->P = P; S->density = density; S->full_k = full_k; S->nG = nG;
+    S->seed = seed; S->replica = replica; S->q = q; S->m = m;
+    memcpy(S->c, c, sizeof(double) * nG); memcpy(S->s, s, sizeof(double) * nG);
+    memcpy(S->A, A, sizeof(double) * nG); memcpy(S->B, B, sizeof(double) * nG);
+    double q1 = 0.0, q2 = 0.0;
+    for (int64_t i = 0; i < N; ++i) { q1 += q[i]; q2 += q[i] * q[i]; }
+    S->Q1 = q1; S->Q2 = q2;
+    S->F0 = 0.0; for (int j = 0; j < nG; ++j) S->F0 += c[j];
+    S->Fhat0 = orc_Fhat(nG, A, B, 0.0);
+    S->mmax = 0;
+    S->nlat = cnt;
+    S->nshell = (int)cnt;
+    S->n3 = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)cnt);
+    double *k2 = (double *)malloc(sizeof(double) * (size_t)cnt);
+    orc_box_lattice(Lb, nG, A, B, S->n3, k2);
+    S->cdf = (double *)malloc(sizeof(double) * (size_t)cnt);
+    S->shell_coef = (double *)malloc(sizeof(double) * (size_t)cnt);
+    box_tables(cnt, k2, nG, A, B, S->V, density, kT, q2, &K, P, S->cdf, S->shell_coef);
+    free(k2);
+    return S;
+}
+
 void orc_sys_destroy(orc_sys *S)
 {
     if (!S) return;
@@ -1313,21 +1565,24 @@ int orc_sys_nshell(const orc_sys *S) { return S->nshell; }
 int64_t orc_sys_nlat(const orc_sys *S) { return S->nlat; }
 void orc_sys_tables(const orc_sys *S, int32_t *shell_m, double *cdf, double *coef)
 {
-    memcpy(shell_m, S->shell_m, sizeof(int32_t) * S->nshell);
+    if (S->shell_m) memcpy(shell_m, S->shell_m, sizeof(int32_t) * S->nshell);
+    else memset(shell_m, 0, sizeof(int32_t) * S->nshell); /* a cuboid: one entry per lattice point */
     memcpy(cdf, S->cdf, sizeof(double) * S->nshell);
     memcpy(coef, S->shell_coef, sizeof(double) * S->nshell);
 }
 void orc_sys_lattice(const orc_sys *S, int32_t *n3, int64_t *start)
 {
     memcpy(n3, S->n3, sizeof(int32_t) * 3 * (size_t)S->nlat);
-    memcpy(start, S->start, sizeof(int64_t) * ((size_t)S->mmax + 2));
+    if (S->start) memcpy(start, S->start, sizeof(int64_t) * ((size_t)S->mmax + 2));
 }
 
 /* The draws of force-evaluation index `step`: i.i.d. (sampler 0) or the next P
  * states of the Metropolis-Hastings chain (sampler 1, which advances it). */
 void orc_sys_draw(orc_sys *S, uint64_t step, int32_t *n_out, double *coef_out)
 {
-    if (S->sampler == 1)
+    if (S->cuboid)
+        orc_box_draw(S->P, step, S->seed, S->replica, S->nlat, S->cdf, S->shell_coef, S->n3, n_out, coef_out);
+    else if (S->sampler == 1)
         orc_mh_draw(S->P, step, S->seed, S->replica, S->nshell, S->shell_m, S->cdf_q, S->shell_coef, S->start,
                     S->n3, S->mh_state, n_out, coef_out);
     else
@@ -1341,6 +1596,7 @@ void orc_sys_draw(orc_sys *S, uint64_t step, int32_t *n_out, double *coef_out)
 int orc_sys_set_sampler(orc_sys *S, int sampler)
 {
     if (sampler != 0 && sampler != 1) return -1;
+    if (sampler == 1 && S->cuboid) return -1; /* the chain's proposals are drawn by shell */
     S->sampler = sampler;
     S->mh_state[0] = 0;
     S->mh_state[1] = -1;
@@ -1375,19 +1631,20 @@ void orc_sys_force(orc_sys *S, uint64_t step, const double *x, double *f, double
 {
     int64_t N = S->N;
     double UN = 0.0, UF = 0.0, WN = 0.0, WF = 0.0;
-    near_k(N, x, S->q, S->L, S->kern, S->rc, S->nG, S->c, S->s, f, &UN, &WN);
+    near_box(N, x, S->q, S->Lb, S->kern, S->rc, S->nG, S->c, S->s, f, &UN, &WN);
     if (f_near) memcpy(f_near, f, sizeof(double) * 3 * (size_t)N);
     if (S->full_k) {
-        UF = orc_far_full(N, x, S->q, S->L, S->nG, S->A, S->B, S->mmax, f, &WF);
+        if (S->cuboid) UF = orc_far_full_box(N, x, S->q, S->Lb, S->nG, S->A, S->B, f, &WF);
+        else UF = orc_far_full(N, x, S->q, S->L, S->nG, S->A, S->B, S->mmax, f, &WF);
     } else {
         int32_t *n = (int32_t *)malloc(sizeof(int32_t) * 3 * (size_t)S->P);
         double *coef = (double *)malloc(sizeof(double) * (size_t)S->P);
         double *rho = (double *)malloc(sizeof(double) * 2 * (size_t)S->P);
         orc_sys_draw(S, step, n, coef);
-        orc_rho(N, x, S->q, S->L, S->P, n, rho);
-        orc_far_rb(N, x, S->q, S->L, S->P, n, coef, rho, f);
+        orc_rho_box(N, x, S->q, S->Lb, S->P, n, rho);
+        orc_far_rb_box(N, x, S->q, S->Lb, S->P, n, coef, rho, f);
         UF = orc_far_rb_energy(S->P, coef, rho);
-        WF = orc_far_rb_virial(S->P, n, coef, rho, S->L, S->nG, S->A, S->B);
+        WF = orc_far_rb_virial_box(S->P, n, coef, rho, S->Lb, S->nG, S->A, S->B);
         free(n); free(coef); free(rho);
     }
     if (energy) {
@@ -1515,7 +1772,6 @@ int orc_sys_run(orc_sys *S, double *x, double *v, double *f, uint64_t step0, int
                 double *ehist)
 {
     int64_t N = S->N;
-    double L = S->L;
     int bad = 0;
     const double c1 = exp(-S->friction * dt);
     const int global = S->bath == 2 || S->bath == 3;
@@ -1543,11 +1799,12 @@ int orc_sys_run(orc_sys *S, double *x, double *v, double *f, uint64_t step0, int
                 } else {
                     dx = dt * vv;
                 }
-                if (fabs(dx) >= L) bad = 1;
+                const double Ld = S->Lb[d];
+                if (fabs(dx) >= Ld) bad = 1;
                 double xx = x[d * N + i] + dx;
-                if (xx >= L) xx -= L;
-                if (xx < 0.0) xx += L;
-                if (xx >= L) xx = 0.0;
+                if (xx >= Ld) xx -= Ld;
+                if (xx < 0.0) xx += Ld;
+                if (xx >= Ld) xx = 0.0;
                 v[d * N + i] = vv;
                 x[d * N + i] = xx;
             }
