@@ -169,7 +169,8 @@ int rbsog_sog_near_poly(const rbsog_sog *sog, double *h, double *k);
 /* One periodic system. */
 typedef struct rbsog_params {
     int64_t N;          /* particles, 1 .. 2^27 - 1                                */
-    double L;           /* cubic box edge; requires floor(L / r_c) >= 3            */
+    double L;           /* box edge (the x edge of a cuboid, see Ly, Lz);
+                           requires floor(L / r_c) >= 3                       */
     double kT;          /* k_B T entering the adaptive density (eq. 3.22), > 0     */
     int P;              /* random-batch size, 1..4096                              */
     int mmax;           /* Fourier lattice 1 <= |n|^2 <= mmax, k = 2 pi n / L;
@@ -212,6 +213,18 @@ typedef struct rbsog_params {
                            draws them (ahead, in consecutive steps), so its
                            draws depend on the history of calls as well as on
                            the key; single systems only (not the ensemble)   */
+    double Ly, Lz;      /* edges of a cuboid box along y and z (Section 2 and
+                           Algorithm 2 take the box as (L_x, L_y, L_z)); 0 =
+                           equal to L (a cube).  L is then the x edge; every
+                           edge needs floor(L_d / r_c) >= 3.  A cuboid's modes
+                           are k = 2 pi (n_x/L_x, n_y/L_y, n_z/L_z) over every
+                           n != 0 with Fhat(k^2) >= 1e-16 Fhat(0), ordered by
+                           (k^2, n_x, n_y, n_z); its measure (eq. 3.124) is
+                           tabled point by point (k^2 no longer groups by
+                           |n|^2) and a draw takes the point from one Philox
+                           word.  A cuboid requires mmax = 0 and the i.i.d.
+                           sampler; the served ensemble, rbsog_ssf and
+                           rbsog_rho_noalloc take cubes only.                 */
 } rbsog_params;
 
 #define RBSOG_SAMPLER_IID 0
@@ -223,7 +236,7 @@ typedef struct rbsog_handle rbsog_handle;
  * can change at an rbsog_step when a default skin drops to 0 (see skin). */
 typedef struct rbsog_info {
     int64_t N;
-    int nc;             /* cells per axis, floor(L / r_c)                          */
+    int nc;             /* cells along x, floor(L / r_c)                           */
     int mmax;           /* lattice truncation in use                               */
     int nshell;         /* non-empty shells |n|^2 = m in the lattice               */
     int64_t nlat;       /* lattice points                                          */
@@ -234,6 +247,9 @@ typedef struct rbsog_info {
     int nf;             /* cells per axis of the force evaluation's fine grid      */
     int near_capacity;  /* kp: a particle's neighbour list holds up to 5 kp entries */
     int near_poly;      /* 1: the FP64 pair kernel uses the polynomial H, K (0 in mixed precision) */
+    int nc_y, nc_z;     /* cells along y and z (equal to nc in a cube); the
+                           cell list of rbsog_build_cells has nc nc_y nc_z cells,
+                           and nshell = nlat in a cuboid (one entry per point) */
 } rbsog_info;
 
 /*

@@ -98,6 +98,7 @@ def lib():
             "orc_far_full_box": (_d, [_i64, _p, _p, _p, _i, _p, _p, _p, _p]),
             "orc_box_lattice": (_i64, [_p, _i, _p, _p, _p, _p]),
             "orc_box_draw": (None, [_i, _u64, _u64, _u32, _i64, _p, _p, _p, _p, _p]),
+            "orc_rdf_box": (None, [_i64, _p, _p, _d, _i, _p, _p]),
             "orc_sys_create_box": (_p, [_i64, _p, _i, _p, _p, _d, _d, _i, _i, _u64, _u32, _i, _i, _i, _p, _p, _p, _p,
                                         _p, _p]),
             "orc_sys_create": (_p, [_i64, _d, _d, _d, _d, _i, _i, _u64, _u32, _i, _i, _i, _p, _p, _p, _p, _p, _p]),
@@ -370,6 +371,19 @@ def is_cube(L) -> bool:
     return bool(b[0] == b[1] == b[2])
 
 
+def cells_box(x: np.ndarray, L, rc: float):
+    """The cell list of a box of edges L (three values): (cell_start, order, nc[3])."""
+    x = _f64(x)
+    N = x.shape[1]
+    Lb = box(L)
+    nc = np.floor(Lb / rc).astype(np.int64)
+    cs = np.zeros(int(nc.prod()) + 1, dtype=np.int32)
+    order = np.zeros(N, dtype=np.int32)
+    nco = np.zeros(3, dtype=np.int32)
+    lib().orc_cells_box(N, _ptr(x), _ptr(Lb), rc, _ptr(cs), _ptr(order), _ptr(nco))
+    return cs, order, nco
+
+
 def near(x, q, L, s: SOG, virial: bool = False):
     """Near-field forces [3, N] and energy U_N; with virial, also W_N.  L: one
     edge or the three edges of a cuboid."""
@@ -586,12 +600,16 @@ def ssf(x, w, L: float, mmax: int) -> np.ndarray:
     return out
 
 
-def rdf(x, L: float, r_max: float, nbins: int):
-    """(counts, ambiguous) of ordered pairs by minimum-image distance bin."""
+def rdf(x, L, r_max: float, nbins: int):
+    """(counts, ambiguous) of ordered pairs by minimum-image distance bin (L one
+    edge or a cuboid's three)."""
     x = _f64(x)
     counts = np.zeros(nbins, dtype=np.int64)
     amb = np.zeros(nbins, dtype=np.int64)
-    lib().orc_rdf(x.shape[1], _ptr(x), L, r_max, nbins, _ptr(counts), _ptr(amb))
+    if np.ndim(L) == 0:
+        lib().orc_rdf(x.shape[1], _ptr(x), L, r_max, nbins, _ptr(counts), _ptr(amb))
+    else:
+        lib().orc_rdf_box(x.shape[1], _ptr(x), _ptr(box(L)), r_max, nbins, _ptr(counts), _ptr(amb))
     return counts, amb
 
 

@@ -1870,7 +1870,18 @@ void orc_ssf(int64_t N, const double *x, const double *w, double L, int mmax, do
  * (N (N/V) 4/3 pi ((b+1)^3 - b^3) dr^3).  A pair whose r / dr lies within
  * 1e-9 of a bin edge could fall on either side under another rounding of the
  * same arithmetic: it is also counted into amb[] of both adjacent bins. */
+void orc_rdf_box(int64_t N, const double *x, const double *Lb, double r_max, int nbins, int64_t *counts,
+                 int64_t *amb);
+
 void orc_rdf(int64_t N, const double *x, double L, double r_max, int nbins, int64_t *counts, int64_t *amb)
+{
+    const double Lb[3] = {L, L, L};
+    orc_rdf_box(N, x, Lb, r_max, nbins, counts, amb);
+}
+
+/* orc_rdf in a box of edges Lb[3] (r_max <= L_d/2 on every axis). */
+void orc_rdf_box(int64_t N, const double *x, const double *Lb, double r_max, int nbins, int64_t *counts,
+                 int64_t *amb)
 {
     double dr = r_max / nbins;
     for (int64_t i = 0; i < N; ++i)
@@ -1879,7 +1890,7 @@ void orc_rdf(int64_t N, const double *x, double L, double r_max, int nbins, int6
             double r2 = 0.0;
             for (int d = 0; d < 3; ++d) {
                 double u = x[d * N + i] - x[d * N + j];
-                u -= L * floor(u / L + 0.5);
+                u -= Lb[d] * floor(u / Lb[d] + 0.5);
                 r2 += u * u;
             }
             double r = sqrt(r2);

@@ -48,7 +48,8 @@ class rbsog_sog(C.Structure):
 class rbsog_params(C.Structure):
     _fields_ = [("N", C.c_int64), ("L", C.c_double), ("kT", C.c_double), ("P", C.c_int), ("mmax", C.c_int),
                 ("seed", C.c_uint64), ("replica", C.c_uint32), ("precision", C.c_int), ("density", C.c_int),
-                ("skin", C.c_double), ("full_k", C.c_int), ("sampler", C.c_int)]
+                ("skin", C.c_double), ("full_k", C.c_int), ("sampler", C.c_int), ("Ly", C.c_double),
+                ("Lz", C.c_double)]
 
 
 RBSOG_NUM_KERNEL_CLASSES = 9
@@ -62,7 +63,8 @@ class rbsog_timing(C.Structure):
 class rbsog_info(C.Structure):
     _fields_ = [("N", C.c_int64), ("nc", C.c_int), ("mmax", C.c_int), ("nshell", C.c_int), ("nlat", C.c_int64),
                 ("S", C.c_double), ("Q1", C.c_double), ("Q2", C.c_double), ("ws_bytes", C.c_size_t),
-                ("skin", C.c_double), ("nf", C.c_int), ("near_capacity", C.c_int), ("near_poly", C.c_int)]
+                ("skin", C.c_double), ("nf", C.c_int), ("near_capacity", C.c_int), ("near_poly", C.c_int),
+                ("nc_y", C.c_int), ("nc_z", C.c_int)]
 
 
 _lib = None
@@ -223,11 +225,16 @@ def sog_from_gaussians(lambda_: float, r_c: float, c, s, A, B, ya=None, yl=None,
     return out
 
 
-def make_params(N: int, L: float, kT: float, P: int, seed: int, replica: int = 0, mmax: int = 0,
+def make_params(N: int, L, kT: float, P: int, seed: int, replica: int = 0, mmax: int = 0,
                 precision: int = RBSOG_FP64, density: int = RBSOG_ADAPTIVE, skin: float = -1.0,
                 full_k: bool = False, sampler: int = 0) -> rbsog_params:
-    return rbsog_params(N=N, L=L, kT=kT, P=P, mmax=mmax, seed=seed, replica=replica, precision=precision,
-                        density=density, skin=skin, full_k=1 if full_k else 0, sampler=sampler)
+    """L: one edge (a cube) or the three edges (L_x, L_y, L_z) of a cuboid."""
+    if isinstance(L, (tuple, list)):
+        Lx, Ly, Lz = (float(v) for v in L)
+    else:
+        Lx, Ly, Lz = float(L), 0.0, 0.0
+    return rbsog_params(N=N, L=Lx, kT=kT, P=P, mmax=mmax, seed=seed, replica=replica, precision=precision,
+                        density=density, skin=skin, full_k=1 if full_k else 0, sampler=sampler, Ly=Ly, Lz=Lz)
 
 
 def rbsog_workspace_size(params: rbsog_params, sog: rbsog_sog) -> int:
@@ -245,7 +252,7 @@ def rbsog_create(params: rbsog_params, sog: rbsog_sog, q, m, ws, stream=None) ->
     _check(lib().rbsog_create(C.byref(params), C.byref(sog), _dptr(q, torch.float64, N), _dptr(m, torch.float64, N),
                               _dptr(ws), ws.numel() * ws.element_size(), stream or _stream(q.device), C.byref(h)))
     info = rbsog_get_info(h)
-    _sizes[h.value] = (info.N, params.P, info.nc ** 3)
+    _sizes[h.value] = (info.N, params.P, info.nc * info.nc_y * info.nc_z)
     return h
 
 
@@ -462,7 +469,7 @@ class System:
     """Holds one system's device buffers (charges, masses, workspace) and
     handle; all work goes through the C-ABI on the current torch stream."""
 
-    def __init__(self, q, m, L: float, sog: rbsog_sog, kT: float, P: int, seed: int, replica: int = 0,
+    def __init__(self, q, m, L, sog: rbsog_sog, kT: float, P: int, seed: int, replica: int = 0,
                  mmax: int = 0, precision: int = RBSOG_FP64, density: int = RBSOG_ADAPTIVE, skin: float = -1.0,
                  full_k: bool = False, device="cuda", sampler: int = 0):
         import torch

@@ -29,14 +29,23 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // groups of the structure-factor partial buffer: an upper bound on those of any launch (rho_chunk <= rho_chunk_shared)
 int nchunks(int64_t N, int P) { return (int)((N + rho_chunk((int)N, P) - 1) / rho_chunk((int)N, P)); }
 
-CellGeom make_geom(double L, int nc)
+CellGeom make_geom(const double Lb[3], const int nc[3])
 {
     CellGeom g{};
-    g.nc = nc;
-    g.ncell = nc * nc * nc;
-    g.L = L;
-    g.inv_cell = (double)nc / L;
+    for (int d = 0; d < 3; ++d) {
+        g.nc[d] = nc[d];
+        g.L[d] = Lb[d];
+        g.inv_cell[d] = (double)nc[d] / Lb[d];
+    }
+    g.ncell = nc[0] * nc[1] * nc[2];
     return g;
+}
+
+void box_edges(const rbsog_params *p, double Lb[3])
+{
+    Lb[0] = p->L;
+    Lb[1] = p->Ly > 0.0 ? p->Ly : p->L;
+    Lb[2] = p->Lz > 0.0 ? p->Lz : p->L;
 }
 
 
@@ -46,14 +55,13 @@ CellGeom make_geom(double L, int nc)
 // five, plus 16; a particle with more neighbours walks its cells directly
 // instead, so this only sizes the fast path.  RBSOG_NEAR_CAPACITY overrides it
 // (a tuning knob).
-int near_capacity(int64_t N, double L, double rl, int nf)
+int near_capacity(int64_t N, double V, double rl)
 {
-    (void)nf;
     if (const char *e = std::getenv("RBSOG_NEAR_CAPACITY")) {
         int v = std::atoi(e);
         if (v >= 1 && v <= 4096) return v;
     }
-    double n = (double)N / (L * L * L);
+    double n = (double)N / V;
     double expected = n * (4.0 / 3.0) * kPi * rl * rl * rl / 5.0;
     return std::min(4096, std::max(8, (int)std::ceil(1.5 * expected + 16.0)));
 }
@@ -66,17 +74,30 @@ Derived derive(const rbsog_params *p, const rbsog_sog *s)
     Derived d{};
     // default skin 0.125 r_c (the fastest of 0.05..0.33 r_c on the N = 1e5 plasma);
     // never so large that the fine grid drops below 6 cells
+    box_edges(p, d.Lb);
+    d.cuboid = !(d.Lb[0] == d.Lb[1] && d.Lb[1] == d.Lb[2]);
+    const double Lmin = std::min(d.Lb[0], std::min(d.Lb[1], d.Lb[2]));
     double skin = p->skin < 0.0 ? 0.125 * s->r_c : p->skin;
-    skin = std::max(0.0, std::min(skin, p->L / 3.0 - s->r_c));
-    d.nc = (int)std::floor(p->L / s->r_c);
-    d.nf = fine_cells(p->L, s->r_c + skin);
-    d.nf_tight = fine_cells(p->L, s->r_c);
-    // the 5-cell stencil reaches 2 w = 2 L / nf: keep the list radius within it
-    d.rl = std::min(s->r_c + skin, 2.0 * p->L / (double)d.nf);
+    skin = std::max(0.0, std::min(skin, Lmin / 3.0 - s->r_c));
+    d.rl = s->r_c + skin;
+    for (int a = 0; a < 3; ++a) {
+        d.nc[a] = (int)std::floor(d.Lb[a] / s->r_c);
+        d.nf[a] = fine_cells(d.Lb[a], s->r_c + skin);
+        d.nf_tight[a] = fine_cells(d.Lb[a], s->r_c);
+        // the 5-cell stencil reaches 2 w = 2 L / nf: keep the list radius within it
+        d.rl = std::min(d.rl, 2.0 * d.Lb[a] / (double)d.nf[a]);
+    }
     d.skin = std::max(0.0, d.rl - s->r_c);
-    d.mmax = p->mmax > 0 ? p->mmax : default_mmax(*s, p->L);
-    d.nlat = lattice_points(d.mmax);
-    d.kp = near_capacity(p->N, p->L, d.rl, d.nf);
+    if (d.cuboid) {
+        d.mmax = 0;
+        d.nlat = box_lattice_points(*s, d.Lb);
+        d.nshells = d.nlat;
+    } else {
+        d.mmax = p->mmax > 0 ? p->mmax : default_mmax(*s, p->L);
+        d.nlat = lattice_points(d.mmax);
+        d.nshells = d.mmax;
+    }
+    d.kp = near_capacity(p->N, d.Lb[0] * d.Lb[1] * d.Lb[2], d.rl);
     d.sbatch = std::max(1, std::min(64, 16384 / std::max(1, p->P)));
     d.full_k = p->full_k ? 1 : 0;
     d.nmodes = d.full_k ? d.nlat : (int64_t)p->P;
@@ -87,7 +108,8 @@ Derived derive(const rbsog_params *p, const rbsog_sog *s)
 Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
 {
     // any grid: the coarse one, the fine one, and the fine one of a dropped skin
-    int ncell = std::max(std::max(d.nf * d.nf * d.nf, d.nf_tight * d.nf_tight * d.nf_tight), d.nc * d.nc * d.nc);
+    int ncell = std::max(std::max(d.nf[0] * d.nf[1] * d.nf[2], d.nf_tight[0] * d.nf_tight[1] * d.nf_tight[2]),
+                         d.nc[0] * d.nc[1] * d.nc[2]);
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -96,10 +118,10 @@ Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
         return o;
     };
     L.lattice = take(shared_lattice ? 0 : sizeof(int32_t) * (size_t)d.nlat);
-    L.cdf = take(sizeof(double) * (size_t)d.mmax);
-    L.coef = take(sizeof(double) * (size_t)d.mmax);
-    L.first = take(sizeof(int32_t) * (size_t)d.mmax);
-    L.size = take(sizeof(int32_t) * (size_t)d.mmax);
+    L.cdf = take(sizeof(double) * (size_t)d.nshells);
+    L.coef = take(sizeof(double) * (size_t)d.nshells);
+    L.first = take(sizeof(int32_t) * (size_t)d.nshells);
+    L.size = take(sizeof(int32_t) * (size_t)d.nshells);
     L.cell_id = take(sizeof(int32_t) * (size_t)N);
     L.count = take(sizeof(int32_t) * (size_t)ncell);
     L.cell_start = take(sizeof(int32_t) * ((size_t)ncell + 1));
@@ -133,9 +155,10 @@ Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice)
     L.nbr_cnt = take(sizeof(int32_t) * (size_t)N);
     L.tab = take(sizeof(double) * 2 * kPhaseTable);
     L.tab_far = take(sizeof(double) * 2 * kFarTable);
-    L.cdf_q = take(sizeof(double) * (size_t)d.mmax);
+    L.cdf_q = take(sizeof(double) * (size_t)d.nshells);
     L.mh = take(sizeof(int32_t) * 2);
     L.bath = take(sizeof(double) * kBathWords);
+    L.fab = take(sizeof(double) * 2 * kMaxGauss);
     L.total = off;
     return L;
 }
@@ -162,10 +185,24 @@ int check_params(const rbsog_params *p, const rbsog_sog *s)
         for (int t = 0; t < 2; ++t)
             if (!(s->yl[t] > 0.0) || !std::isfinite(s->yl[t]) || !std::isfinite(s->ya[t]))
                 return fail(RBSOG_EINVAL, "sog: the kernel's terms need positive, finite lengths and finite weights");
-    double nc = std::floor(p->L / s->r_c);
-    if (nc < 3.0) return fail(RBSOG_EINVAL, "box too small: floor(L / r_c) = %g < 3", nc);
-    double nf = std::floor(2.0 * p->L / s->r_c);
-    if (nf * nf * nf > (double)(1 << 26)) return fail(RBSOG_EINVAL, "too many cells (L / r_c too large)");
+    if (!(p->Ly >= 0.0) || !std::isfinite(p->Ly) || !(p->Lz >= 0.0) || !std::isfinite(p->Lz))
+        return fail(RBSOG_EINVAL, "Ly and Lz must be finite and >= 0 (0: equal to L)");
+    double Lb[3];
+    box_edges(p, Lb);
+    double nfp = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        double nc = std::floor(Lb[a] / s->r_c);
+        if (nc < 3.0) return fail(RBSOG_EINVAL, "box too small: floor(L_%c / r_c) = %g < 3", "xyz"[a], nc);
+        nfp *= std::floor(2.0 * Lb[a] / s->r_c);
+    }
+    if (nfp > (double)(1 << 26)) return fail(RBSOG_EINVAL, "too many cells (L / r_c too large)");
+    const bool cuboid = !(Lb[0] == Lb[1] && Lb[1] == Lb[2]);
+    if (cuboid) {
+        if (p->mmax != 0) return fail(RBSOG_EINVAL, "a cuboid box takes the default lattice (mmax = 0)");
+        if (p->sampler != RBSOG_SAMPLER_IID) return fail(RBSOG_EINVAL, "a cuboid box draws i.i.d. modes only");
+        if (box_lattice_points(*s, Lb) < 1)
+            return fail(RBSOG_EINVAL, "the cuboid's lattice is empty or exceeds |n_d| = 511");
+    }
     return RBSOG_OK;
 }
 
@@ -257,9 +294,11 @@ NearArgs near_args(rbsog_handle *h, const int32_t *gate, bool energy)
     NearArgs na{};
     na.N = (int)h->p.N;
     na.g = h->gf;
-    na.w = h->p.L / (double)h->gf.nc;
-    na.margin = 1e-9 * h->p.L;
-    na.inv_L = 1.0 / h->p.L;
+    for (int d = 0; d < 3; ++d) {
+        na.w[d] = h->d.Lb[d] / (double)h->gf.nc[d];
+        na.inv_L[d] = 1.0 / h->d.Lb[d];
+    }
+    na.margin = 1e-9 * std::max(h->d.Lb[0], std::max(h->d.Lb[1], h->d.Lb[2]));
     na.e2 = make_exp2_poly();
     na.nbr = h->nbr;
     na.nbr_cnt = h->nbr_cnt;
@@ -311,7 +350,7 @@ RhoArgs rho_args(rbsog_handle *h, const double4 *samp)
     // the same order as the system alone.  nchunks() (the buffer) bounds it.
     a.chunk = rho_chunk_shared((int)h->p.N, h->p.P, h->p.precision == RBSOG_MIXED);
     a.nchunk = (int)((h->p.N + a.chunk - 1) / a.chunk);
-    a.inv_L = 1.0 / h->p.L;
+    for (int d = 0; d < 3; ++d) a.inv_L[d] = 1.0 / h->d.Lb[d];
     a.xs = h->xs;
     a.samp = samp;
     a.part = h->part;
@@ -319,7 +358,14 @@ RhoArgs rho_args(rbsog_handle *h, const double4 *samp)
     a.gk = h->gk;
     a.eF = h->eF;
     a.eW = h->eW;
-    a.vm = h->vm;
+    if (h->d.cuboid) {   // virial factors from the Fourier coefficients, mode by mode
+        a.vm = nullptr;
+        a.nG = h->sog.n;
+        a.fa = h->fab;
+        a.fb = h->fab + kMaxGauss;
+    } else {
+        a.vm = h->vm;
+    }
     a.mixed = h->p.precision == RBSOG_MIXED;
     a.tab = h->tab;
     a.ss = make_sincos_short();
@@ -363,8 +409,10 @@ FarArgs far_args(rbsog_handle *h, const double4 *samp, double *f, double *f_near
     FarArgs fa{};
     fa.N = (int)h->p.N;
     fa.P = (int)h->d.nmodes;
-    fa.two_pi_over_L = (2.0 * kPi) / h->p.L;
-    fa.inv_L = 1.0 / h->p.L;
+    for (int d = 0; d < 3; ++d) {
+        fa.two_pi_over_L[d] = (2.0 * kPi) / h->d.Lb[d];
+        fa.inv_L[d] = 1.0 / h->d.Lb[d];
+    }
     fa.xs = h->xs;
     fa.order = h->order;
     fa.samp = samp;
@@ -462,7 +510,7 @@ int evaluate(rbsog_handle *h, const double4 *samp, double *f, double *f_near, bo
     if (kick && gate_raise) {
         fa.drift = 1;
         fa.dt = dt;
-        fa.L = h->p.L;
+        for (int d = 0; d < 3; ++d) fa.L[d] = h->d.Lb[d];
         fa.half_skin2 = 0.25 * h->d.skin * h->d.skin;
         fa.xb = h->xb;
         fa.xs_next = h->xs;
@@ -532,9 +580,9 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     h->m = m_dev;
     h->st = stream;
     h->d = derive(p, s);
-    h->g = make_geom(p->L, h->d.nc);
-    h->gf = make_geom(p->L, h->d.nf);
-    h->V = p->L * p->L * p->L;
+    h->g = make_geom(h->d.Lb, h->d.nc);
+    h->gf = make_geom(h->d.Lb, h->d.nf);
+    h->V = h->d.Lb[0] * h->d.Lb[1] * h->d.Lb[2];
     if (h->d.full_k && (lattice_dev || h->d.nlat > 0x7fffffff)) {
         delete h;
         return fail(RBSOG_EINVAL, "full_k needs a lattice of fewer than 2^31 points in the system's own workspace");
@@ -630,6 +678,7 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     h->nbr_cnt = (int32_t *)(w + L.nbr_cnt);
     h->tab = (double2 *)(w + L.tab);
     h->tab_far = (double2 *)(w + L.tab_far);
+    h->fab = (double *)(w + L.fab);
     h->cdf_q = (double *)(w + L.cdf_q);
     h->mh = (int32_t *)(w + L.mh);
     h->bath = (double *)(w + L.bath);
@@ -669,6 +718,12 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     }
     static const double bath0[kBathWords] = {};
     if (e == hipSuccess) e = hipMemcpyAsync(h->bath, bath0, sizeof(bath0), hipMemcpyHostToDevice, h->st);
+    double fabh[2 * kMaxGauss] = {};
+    for (int g = 0; g < s->n; ++g) {
+        fabh[g] = s->A[g];
+        fabh[kMaxGauss + g] = s->B[g];
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(h->fab, fabh, sizeof(fabh), hipMemcpyHostToDevice, h->st);
     std::vector<double> vmh((size_t)h->d.mmax + 1);
     virial_table(*s, p->L, h->d.mmax, vmh.data());
     if (e == hipSuccess)
@@ -676,17 +731,16 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     // full lattice: every n with its coefficient Fhat(k^2)/V, k = 2 pi n / L
     std::vector<double> full;
     if (e == hipSuccess && h->d.full_k) {
-        const double tt = (2.0 * kPi) / p->L, V = p->L * p->L * p->L;
+        const double V = h->V;
         full.resize(4 * (size_t)t.nlat);
         for (int64_t i = 0; i < t.nlat; ++i) {
             uint32_t pk = (uint32_t)t.packed[(size_t)i];
             int nx = (int)(pk & 1023u) - kLatticeBias, ny = (int)((pk >> 10) & 1023u) - kLatticeBias;
             int nz = (int)((pk >> 20) & 1023u) - kLatticeBias;
-            double m = (double)nx * nx + (double)ny * ny + (double)nz * nz;
             full[4 * i] = nx;
             full[4 * i + 1] = ny;
             full[4 * i + 2] = nz;
-            full[4 * i + 3] = fhat(*s, tt * tt * m) / V;
+            full[4 * i + 3] = fhat(*s, box_k2(h->d.Lb, nx, ny, nz)) / V;
         }
         e = hipMemcpyAsync(h->samp, full.data(), sizeof(double) * full.size(), hipMemcpyHostToDevice, h->st);
     }
@@ -741,7 +795,7 @@ extern "C" int rbsog_get_info(const rbsog_handle *h, rbsog_info *out)
 {
     if (!h || !out) return fail(RBSOG_EINVAL, "null handle or out");
     out->N = h->p.N;
-    out->nc = h->g.nc;
+    out->nc = h->g.nc[0];
     out->mmax = h->d.mmax;
     out->nshell = h->nshell;
     out->nlat = h->d.nlat;
@@ -750,9 +804,11 @@ extern "C" int rbsog_get_info(const rbsog_handle *h, rbsog_info *out)
     out->Q2 = h->Q2;
     out->ws_bytes = h->lay.total;
     out->skin = h->d.skin;
-    out->nf = h->gf.nc;
+    out->nf = h->gf.nc[0];
     out->near_capacity = h->d.kp;
     out->near_poly = h->sd.poly;
+    out->nc_y = h->g.nc[1];
+    out->nc_z = h->g.nc[2];
     return RBSOG_OK;
 }
 
@@ -833,9 +889,9 @@ static void drop_skin(rbsog_handle *h)
 {
     h->d.skin = 0.0;
     h->d.rl = h->sog.r_c;
-    h->d.nf = h->d.nf_tight;
-    h->d.kp = std::min(h->d.kp, near_capacity(h->p.N, h->p.L, h->d.rl, h->d.nf));
-    h->gf = make_geom(h->p.L, h->d.nf);
+    for (int d = 0; d < 3; ++d) h->d.nf[d] = h->d.nf_tight[d];
+    h->d.kp = std::min(h->d.kp, near_capacity(h->p.N, h->V, h->d.rl));
+    h->gf = make_geom(h->d.Lb, h->d.nf);
     h->lists_valid = false;
 }
 
@@ -892,8 +948,10 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         if (!h->lists_valid) HIPCHECK(launch_set_int(gate, 1, h->st));
         KickDriftArgs k{};
         k.N = (int)h->p.N;
-        k.L = h->p.L;
-        k.inv_L = 1.0 / h->p.L;
+        for (int d = 0; d < 3; ++d) {
+            k.L[d] = h->d.Lb[d];
+            k.inv_L[d] = 1.0 / h->d.Lb[d];
+        }
         k.dt = dt;
         k.xs = h->xs;
         k.vs = h->vs;
@@ -931,8 +989,10 @@ extern "C" int rbsog_step(rbsog_handle *h, double *x_dev, double *v_dev, double 
         if (global && !last) {
             KickDriftArgs k{};
             k.N = (int)h->p.N;
-            k.L = h->p.L;
-            k.inv_L = 1.0 / h->p.L;
+            for (int d = 0; d < 3; ++d) {
+                k.L[d] = h->d.Lb[d];
+                k.inv_L[d] = 1.0 / h->d.Lb[d];
+            }
             k.dt = dt;
             k.xs = h->xs;
             k.vs = h->vs;

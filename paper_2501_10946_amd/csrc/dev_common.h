@@ -76,9 +76,9 @@ __device__ inline void langevin_normals(uint64_t i, const Thermo &th, double z[3
 // The drift kernel and the far kernel's fused form both run this, so that
 // their trajectories agree bit for bit.  hm = dt / (2 m); with a thermostat
 // on, ci is the particle's caller index and m its mass.
-__device__ inline double kick_drift_row(double x[3], double v[3], const double f[3], double hm, double dt, double L,
-                                        double inv_L, const double *xb, int N, int p, bool *bad,
-                                        const Thermo &th, uint64_t ci, double m)
+__device__ inline double kick_drift_row(double x[3], double v[3], const double f[3], double hm, double dt,
+                                        const double Lb[3], const double inv_Lb[3], const double *xb, int N, int p,
+                                        bool *bad, const Thermo &th, uint64_t ci, double m)
 {
     double d2 = 0.0;
     double z[3] = {0.0, 0.0, 0.0}, sig = 0.0;
@@ -97,6 +97,7 @@ __device__ inline double kick_drift_row(double x[3], double v[3], const double f
         } else {
             dx = dt * vv;
         }
+        const double L = Lb[d];
         *bad |= !(fabs(dx) < L);
         double xx = x[d] + dx;
         if (xx >= L) xx -= L;
@@ -105,7 +106,7 @@ __device__ inline double kick_drift_row(double x[3], double v[3], const double f
         v[d] = vv;
         x[d] = xx;
         double s = xx - xb[d * N + p];
-        s = fma(-L, rint(s * inv_L), s);
+        s = fma(-L, rint(s * inv_Lb[d]), s);
         d2 = fma(s, s, d2);
     }
     return d2;
@@ -154,13 +155,16 @@ __device__ inline void rho_partial_body(const RhoArgs &a, int b)
     const int s_hi = (int)min((int64_t)a.nchunk - 1, (g0 + kBlock - 1) / a.P);
     const int j_lo = s_lo * a.chunk;
     const int j_hi = min(a.N, (s_hi + 1) * a.chunk);
-    const double ph = MIXED ? a.inv_L : a.inv_L * kPhaseTab;   // phase unit of the precision
+    // phase units of the precision, per axis
+    const double phx = MIXED ? a.inv_L[0] : a.inv_L[0] * kPhaseTab;
+    const double phy = MIXED ? a.inv_L[1] : a.inv_L[1] * kPhaseTab;
+    const double phz = MIXED ? a.inv_L[2] : a.inv_L[2] * kPhaseTab;
     for (int k = t; k < j_hi - j_lo; k += kBlock) {
         int j = j_lo + k;
         double4 v;
         if (CELL) v = a.xs[j];
         else v = make_double4(a.x[j], a.x[a.N + j], a.x[2 * a.N + j], a.q[j]);
-        sp[k] = make_double4(v.x * ph, v.y * ph, v.z * ph, v.w);
+        sp[k] = make_double4(v.x * phx, v.y * phy, v.z * phz, v.w);
     }
     if (!MIXED)
         for (int k = t; k < kPhaseTab; k += kBlock) tab[k] = a.tab[k];
@@ -178,6 +182,26 @@ __device__ inline void rho_partial_body(const RhoArgs &a, int b)
     }
     if (i < e) rho_term<CELL, MIXED>(a, tab, k, sp[i], re0, im0);
     a.part[g] = make_double2(re0 + re1, im0 + im1);
+}
+
+// k^2 G / Fhat of a mode (G = -dFhat/d(k^2)): from the table by |n|^2 in a
+// cube, from the Fourier coefficients in a cuboid.
+__device__ inline double mode_vm(const RhoArgs &a, const double4 &sl)
+{
+    if (a.vm) {   // |n|^2 from the mode's integer components (exact in FP64)
+        const int m = (int)(sl.x * sl.x + sl.y * sl.y + sl.z * sl.z);
+        return a.vm[m];
+    }
+    const double tp = 6.283185307179586;
+    const double kx = tp * sl.x * a.inv_L[0], ky = tp * sl.y * a.inv_L[1], kz = tp * sl.z * a.inv_L[2];
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    double F = 0.0, G = 0.0;
+    for (int g = 0; g < a.nG; ++g) {
+        const double e = exp(-a.fb[g] * k2);
+        F += a.fa[g] * e;
+        G += a.fa[g] * a.fb[g] * e;
+    }
+    return F > 0.0 ? k2 * G / F : 0.0;
 }
 
 // Fixed-order sum of the chunk partials, one workgroup per kRedModes adjacent
@@ -234,11 +258,7 @@ __device__ inline void rho_reduce_body(const RhoArgs &a, int b)
         a.rho[l] = make_double2(re, im);
         a.gk[l] = make_double2(cf * re, cf * im);
         a.eF[l] = 0.5 * cf * (re * re + im * im);
-        if (a.eW) {   // |n|^2 from the mode's integer components (exact in FP64)
-            const double4 sl = a.samp[l];
-            const int m = (int)(sl.x * sl.x + sl.y * sl.y + sl.z * sl.z);
-            a.eW[l] = cf * (re * re + im * im) * (1.5 - a.vm[m]);
-        }
+        if (a.eW) a.eW[l] = cf * (re * re + im * im) * (1.5 - mode_vm(a, a.samp[l]));
         if (a.rho_out) {
             a.rho_out[2 * l] = re;
             a.rho_out[2 * l + 1] = im;

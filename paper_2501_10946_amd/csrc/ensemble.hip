@@ -267,8 +267,10 @@ int write_tables(rbsog_ens *s, int r, double dt)
     hipError_t e;
     KickDriftArgs k{};
     k.N = (int)R.N;
-    k.L = h->p.L;
-    k.inv_L = 1.0 / h->p.L;
+    for (int d = 0; d < 3; ++d) {
+        k.L[d] = h->d.Lb[d];
+        k.inv_L[d] = 1.0 / h->d.Lb[d];
+    }
     k.dt = dt;
     k.xs = h->xs;
     k.vs = h->vs;
@@ -410,6 +412,8 @@ extern "C" int rbsog_ens_admit(rbsog_ens *s, const rbsog_params *p, const rbsog_
     if (p->full_k) return fail(RBSOG_EINVAL, "the ensemble serves random-batch replicas only (full_k = 0)");
     if (p->sampler != RBSOG_SAMPLER_IID)
         return fail(RBSOG_EINVAL, "the ensemble draws i.i.d. modes only (sampler = RBSOG_SAMPLER_IID)");
+    if ((p->Ly > 0.0 && p->Ly != p->L) || (p->Lz > 0.0 && p->Lz != p->L))
+        return fail(RBSOG_EINVAL, "the ensemble serves cubic boxes only (Ly, Lz of 0 or equal to L)");
     int slot = -1;
     for (int r = 0; r < s->max_slots; ++r)
         if (!s->rep[r].used) {

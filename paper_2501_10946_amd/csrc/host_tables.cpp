@@ -139,8 +139,106 @@ void lattice_copy(int mmax, int32_t *out)
     std::copy(g_lat.packed.begin(), g_lat.packed.begin() + n, out);
 }
 
+// k^2 of lattice point n in a box of edges Lb: (2 pi / L)^2 |n|^2 in a cube (as
+// the shell tables form it), else the sum over the axes of (2 pi n_d / L_d)^2.
+double box_k2(const double Lb[3], int nx, int ny, int nz)
+{
+    if (Lb[0] == Lb[1] && Lb[1] == Lb[2]) {
+        const double t = (2.0 * kPi) / Lb[0];
+        const double m = (double)nx * nx + (double)ny * ny + (double)nz * nz;
+        return t * t * m;
+    }
+    const double kx = (2.0 * kPi) * nx / Lb[0], ky = (2.0 * kPi) * ny / Lb[1], kz = (2.0 * kPi) * nz / Lb[2];
+    return kx * kx + ky * ky + kz * kz;
+}
+
+namespace {
+
+struct BoxPoint {
+    double k2;
+    int n[3];
+};
+
+// The lattice of a cuboid: every n != 0 with Fhat(k^2) >= 1e-16 Fhat(0), sorted
+// by (k^2, nx, ny, nz).  False when some |n_d| would exceed 511 (the packing).
+bool box_points(const rbsog_sog &s, const double Lb[3], std::vector<BoxPoint> *out)
+{
+    const double thr = 1e-16 * fhat(s, 0.0);
+    double lo = 0.0, hi = 1.0;
+    while (fhat(s, hi) >= thr) hi *= 2.0;
+    for (int it = 0; it < 200; ++it) {   // the k^2 where Fhat crosses the threshold
+        const double mid = 0.5 * (lo + hi);
+        if (fhat(s, mid) >= thr) lo = mid; else hi = mid;
+    }
+    int nm[3];
+    for (int d = 0; d < 3; ++d) {
+        nm[d] = (int)std::floor(Lb[d] * std::sqrt(hi) / (2.0 * kPi)) + 1;
+        if (nm[d] > 511) return false;
+    }
+    out->clear();
+    for (int a = -nm[0]; a <= nm[0]; ++a)
+        for (int b = -nm[1]; b <= nm[1]; ++b)
+            for (int c = -nm[2]; c <= nm[2]; ++c) {
+                if (a == 0 && b == 0 && c == 0) continue;
+                const double k2 = box_k2(Lb, a, b, c);
+                if (!(fhat(s, k2) >= thr)) continue;
+                out->push_back(BoxPoint{k2, {a, b, c}});
+            }
+    std::sort(out->begin(), out->end(), [](const BoxPoint &x, const BoxPoint &y) {
+        if (x.k2 != y.k2) return x.k2 < y.k2;
+        if (x.n[0] != y.n[0]) return x.n[0] < y.n[0];
+        if (x.n[1] != y.n[1]) return x.n[1] < y.n[1];
+        return x.n[2] < y.n[2];
+    });
+    return true;
+}
+
+}  // namespace
+
+int64_t box_lattice_points(const rbsog_sog &s, const double Lb[3])
+{
+    std::vector<BoxPoint> pts;
+    if (!box_points(s, Lb, &pts)) return -1;
+    return (int64_t)pts.size();
+}
+
 void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax, Tables *t, bool with_lattice)
 {
+    double Lb[3];
+    box_edges(&p, Lb);
+    if (!(Lb[0] == Lb[1] && Lb[1] == Lb[2])) {
+        // a cuboid: every lattice point its own shell (the measure depends on
+        // k^2, which no longer groups by |n|^2)
+        std::vector<BoxPoint> pts;
+        box_points(s, Lb, &pts);
+        const double V = Lb[0] * Lb[1] * Lb[2];
+        t->mmax = 0;
+        t->nlat = (int64_t)pts.size();
+        t->packed.clear();
+        t->cdf.clear();
+        t->coef.clear();
+        t->shell_first.clear();
+        t->shell_size.clear();
+        std::vector<double> Fk_of;
+        double acc = 0.0;
+        for (size_t i = 0; i < pts.size(); ++i) {
+            const BoxPoint &q = pts[i];
+            if (with_lattice)
+                t->packed.push_back((int32_t)((uint32_t)(q.n[0] + kLatticeBias) |
+                                              ((uint32_t)(q.n[1] + kLatticeBias) << 10) |
+                                              ((uint32_t)(q.n[2] + kLatticeBias) << 20)));
+            const double Fk = density(p.density, p.kT, V, Q2, kernel_terms(s), q.k2);
+            acc = acc + Fk * fhat(s, q.k2);
+            t->cdf.push_back(acc);
+            t->shell_first.push_back((int32_t)i);
+            t->shell_size.push_back(1);
+            Fk_of.push_back(Fk);
+        }
+        t->nshell = (int)t->cdf.size();
+        t->S = acc;
+        for (int i = 0; i < t->nshell; ++i) t->coef.push_back(t->S / ((double)p.P * V * Fk_of[i]));
+        return;
+    }
     t->mmax = mmax;
     std::vector<int64_t> size, first;
     {

@@ -74,7 +74,14 @@ double fhat(const rbsog_sog &s, double k2);
 // beside 3/2 of its energy term
 void virial_table(const rbsog_sog &s, double L, int mmax, double *vm);
 // shell CDF, coefficients and shell ranges; the packed lattice too when asked
+// (a cuboid box, see box_edges, gets one entry per lattice point and ignores mmax)
 void build_tables(const rbsog_sog &s, const rbsog_params &p, double Q2, int mmax, Tables *t, bool with_lattice);
+// k^2 of lattice point n in a box of edges Lb
+double box_k2(const double Lb[3], int nx, int ny, int nz);
+// points of a cuboid's lattice (every n != 0 with Fhat(k^2) >= 1e-16 Fhat(0)), or -1 beyond |n_d| = 511
+int64_t box_lattice_points(const rbsog_sog &s, const double Lb[3]);
+// the box edges of the parameters (Ly, Lz of 0 take L)
+void box_edges(const rbsog_params *p, double Lb[3]);
 // (sin, cos)(2 pi j / kPhaseTable), j = 0 .. kPhaseTable - 1, interleaved, from
 // the host's libm: the rotation table of the FP64 phase kernels
 constexpr int kPhaseTable = 128;

@@ -44,11 +44,10 @@ __device__ inline void cell_ids_body(const CellArgs &a, int b)
     a.ms_old[p] = a.ms[p];
     if (a.vs)
         for (int d = 0; d < 3; ++d) a.vs_old[d * a.N + p] = a.vs[d * a.N + p];
-    int nc = a.g.nc;
-    int cx = cell_coord(r.x, a.g.inv_cell, nc);
-    int cy = cell_coord(r.y, a.g.inv_cell, nc);
-    int cz = cell_coord(r.z, a.g.inv_cell, nc);
-    int id = (cz * nc + cy) * nc + cx;
+    int cx = cell_coord(r.x, a.g.inv_cell[0], a.g.nc[0]);
+    int cy = cell_coord(r.y, a.g.inv_cell[1], a.g.nc[1]);
+    int cz = cell_coord(r.z, a.g.inv_cell[2], a.g.nc[2]);
+    int id = (cz * a.g.nc[1] + cy) * a.g.nc[0] + cx;
     a.cell_id[p] = id;
     atomicAdd(&a.count[id], 1);
 }
@@ -182,7 +181,7 @@ RBSOG_KERNELS(rank, CellArgs, kBlock)
 
 static bool cell_args_ok(const CellArgs &a)
 {
-    return a.N >= 1 && a.g.nc >= 1 && a.xs && a.order && a.xs_old && a.order_old && (!a.vs || a.vs_old) &&
+    return a.N >= 1 && a.g.nc[0] >= 1 && a.g.nc[1] >= 1 && a.g.nc[2] >= 1 && a.xs && a.order && a.xs_old && a.order_old && (!a.vs || a.vs_old) &&
            a.ms && a.ms_old && a.xb && a.cell_id && a.count && a.cell_start && a.fill && a.tmp && a.tile_sum && a.ticket;
 }
 

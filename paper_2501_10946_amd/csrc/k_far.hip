@@ -59,8 +59,10 @@ __device__ inline void far_body(const FarArgs &a, int b)
     const bool live = p < a.N;
     double4 pi = live ? a.xs[p] : make_double4(0.0, 0.0, 0.0, 0.0);
     // phases in revolutions (mixed) or 1/1024 revolutions (FP64 table path)
-    const double ph = MIXED ? a.inv_L : a.inv_L * kFarTab;
-    double sx = pi.x * ph, sy = pi.y * ph, sz = pi.z * ph;
+    const double phx = MIXED ? a.inv_L[0] : a.inv_L[0] * kFarTab;
+    const double phy = MIXED ? a.inv_L[1] : a.inv_L[1] * kFarTab;
+    const double phz = MIXED ? a.inv_L[2] : a.inv_L[2] * kFarTab;
+    double sx = pi.x * phx, sy = pi.y * phy, sz = pi.z * phz;
     double ax = 0.0, ay = 0.0, az = 0.0;
     if (!MIXED)
         for (int k = t; k < kFarTab; k += kFarThreads) tab[k] = a.tab[k];
@@ -107,7 +109,8 @@ __device__ inline void far_body(const FarArgs &a, int b)
             by += part[1][k * 64 + t];
             bz += part[2][k * 64 + t];
         }
-        double sc = -pi.w * a.two_pi_over_L;
+        const double scx = -pi.w * a.two_pi_over_L[0], scy = -pi.w * a.two_pi_over_L[1];
+        const double scz = -pi.w * a.two_pi_over_L[2];
         // near field: the lane partials, added in lane order
         double fnx = 0.0, fny = 0.0, fnz = 0.0;
 #pragma unroll
@@ -117,7 +120,7 @@ __device__ inline void far_body(const FarArgs &a, int b)
             fny += pl[a.N];
             fnz += pl[2 * (size_t)a.N];
         }
-        double fx = fnx + sc * bx, fy = fny + sc * by, fz = fnz + sc * bz;
+        double fx = fnx + scx * bx, fy = fny + scy * by, fz = fnz + scz * bz;
         if (a.fs) {
             a.fs[p] = fx;
             a.fs[a.N + p] = fy;

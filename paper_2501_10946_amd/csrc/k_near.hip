@@ -90,14 +90,14 @@ __device__ inline Lane make_lane(const NearArgs &a, int p, int plane)
     l.zc = 1;
     l.gz = 1e300;
     if (p < a.N) {
-        const int nf = a.g.nc;
+        const int nfz = a.g.nc[2];
         l.pi = a.xs[p];
-        l.cx = cell_coord(l.pi.x, a.g.inv_cell, nf);
-        l.cy = cell_coord(l.pi.y, a.g.inv_cell, nf);
-        int czu = cell_coord(l.pi.z, a.g.inv_cell, nf) + plane - 2;
-        l.gz = slab_gap(l.pi.z, czu, a.w, a.margin);
+        l.cx = cell_coord(l.pi.x, a.g.inv_cell[0], a.g.nc[0]);
+        l.cy = cell_coord(l.pi.y, a.g.inv_cell[1], a.g.nc[1]);
+        int czu = cell_coord(l.pi.z, a.g.inv_cell[2], nfz) + plane - 2;
+        l.gz = slab_gap(l.pi.z, czu, a.w[2], a.margin);
         l.cz = czu;
-        if (czu < 0) { l.cz += nf; l.zc = 0; } else if (czu >= nf) { l.cz -= nf; l.zc = 2; }
+        if (czu < 0) { l.cz += nfz; l.zc = 0; } else if (czu >= nfz) { l.cz -= nfz; l.zc = 2; }
     }
     return l;
 }
@@ -107,23 +107,23 @@ __device__ inline Lane make_lane(const NearArgs &a, int p, int plane)
 // 0, 1 or 2 ranges.
 __device__ inline int row_ranges(const NearArgs &a, const Lane &l, int row, double R2, Range out[2])
 {
-    const int nf = a.g.nc;
-    const double w = a.w, m = a.margin;
+    const int nf = a.g.nc[0], nfy = a.g.nc[1];
+    const double m = a.margin;
     int cyu = l.cy + row - 2;
-    double gy = slab_gap(l.pi.y, cyu, w, m);
+    double gy = slab_gap(l.pi.y, cyu, a.w[1], m);
     double rem = R2 - gy * gy - l.gz * l.gz;
     if (!(rem > 0.0)) return 0;
     int dxlo = -2, dxhi = 2;
     for (int k = 0; k < 2; ++k) {   // at most two x-cells per side can be culled
-        double gl = slab_gap(l.pi.x, l.cx + dxlo, w, m);
+        double gl = slab_gap(l.pi.x, l.cx + dxlo, a.w[0], m);
         if (dxlo < 0 && !(gl * gl < rem)) ++dxlo;
-        double gh = slab_gap(l.pi.x, l.cx + dxhi, w, m);
+        double gh = slab_gap(l.pi.x, l.cx + dxhi, a.w[0], m);
         if (dxhi > 0 && !(gh * gh < rem)) --dxhi;
     }
     int xa = l.cx + dxlo, xb = l.cx + dxhi;   // unwrapped; xb - xa <= 4 < nf
     int cyw = cyu, yc = 1;
-    if (cyw < 0) { cyw += nf; yc = 0; } else if (cyw >= nf) { cyw -= nf; yc = 2; }
-    int base = (l.cz * nf + cyw) * nf;
+    if (cyw < 0) { cyw += nfy; yc = 0; } else if (cyw >= nfy) { cyw -= nfy; yc = 2; }
+    int base = (l.cz * nfy + cyw) * nf;
     int code = 3 * yc + 9 * l.zc;
     int n = 0;
     // piece left of the wrap (or the whole row), then the piece past it
@@ -180,12 +180,11 @@ template <bool MIXED, bool ENERGY, int NG>
 __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const double4 &pj, double &fx, double &fy,
                                   double &fz, double &en, double &vir)
 {
-    const double L = a.g.L;
-    // d by the minimum image (|d| < r_c <= L/3)
+    // d by the minimum image (|d| < r_c <= L_d/3)
     double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-    dx = fma(-L, rint(dx * a.inv_L), dx);
-    dy = fma(-L, rint(dy * a.inv_L), dy);
-    dz = fma(-L, rint(dz * a.inv_L), dz);
+    dx = fma(-a.g.L[0], rint(dx * a.inv_L[0]), dx);
+    dy = fma(-a.g.L[1], rint(dy * a.inv_L[1]), dy);
+    dz = fma(-a.g.L[2], rint(dz * a.inv_L[2]), dz);
     double r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 < a.rc2)) return;   // listed within r_c + skin, beyond r_c now
     double qq = pi.w * pj.w;
@@ -291,12 +290,12 @@ __device__ inline bool pair_window(const NearArgs &a, int q, int32_t *pstart, in
                                    PairWindow &win)
 {
     const int lane = threadIdx.x & 63;
-    const int nf = a.g.nc, half = (nf + 1) >> 1;
-    if (q >= nf * nf * half) return false;
+    const int nf = a.g.nc[0], nfy = a.g.nc[1], nfz = a.g.nc[2], half = (nf + 1) >> 1;
+    if (q >= nfz * nfy * half) return false;
     const int row = q / half, ix = q - row * half;
-    const int cz = row / nf, cy = row - cz * nf;
+    const int cz = row / nfy, cy = row - cz * nfy;
     const int x0 = 2 * ix, x1 = min(x0 + 1, nf - 1);
-    const int cbase = (cz * nf + cy) * nf;
+    const int cbase = (cz * nfy + cy) * nf;
     win.h_beg = a.cell_start[cbase + x0];
     win.h_end = a.cell_start[cbase + x1 + 1];
     if (win.h_beg >= win.h_end) return false;
@@ -304,10 +303,10 @@ __device__ inline bool pair_window(const NearArgs &a, int q, int32_t *pstart, in
     if (lane < 2 * 25) {
         const int r = lane >> 1, k = lane & 1;
         int czw = cz + r / 5 - 2, zc = 1;
-        if (czw < 0) { czw += nf; zc = 0; } else if (czw >= nf) { czw -= nf; zc = 2; }
+        if (czw < 0) { czw += nfz; zc = 0; } else if (czw >= nfz) { czw -= nfz; zc = 2; }
         int cyw = cy + r % 5 - 2, yc = 1;
-        if (cyw < 0) { cyw += nf; yc = 0; } else if (cyw >= nf) { cyw -= nf; yc = 2; }
-        const int rb = (czw * nf + cyw) * nf;
+        if (cyw < 0) { cyw += nfy; yc = 0; } else if (cyw >= nfy) { cyw -= nfy; yc = 2; }
+        const int rb = (czw * nfy + cyw) * nf;
         const int xa = x0 - 2, xb = x1 + 2;   // at most 6 cells <= nf: one side wraps at most
         int lo = xa, hi = xb, xc = 1;
         bool has = k == 0;
@@ -357,12 +356,12 @@ __device__ inline int window_piece(const int32_t *ppref, int c)
 // Candidate c of piece l of a window: its particle index j and the image shift
 // (sx, sy, sz) the piece is seen under.
 __device__ inline int window_candidate(const int32_t *pstart, const int32_t *ppref, const int32_t *pcode, int c,
-                                       int l, double L, double &sx, double &sy, double &sz)
+                                       int l, const double Lb[3], double &sx, double &sy, double &sz)
 {
     const int code = pcode[l];
-    sx = shift_of(code & 3, L);
-    sy = shift_of((code >> 2) & 3, L);
-    sz = shift_of(code >> 4, L);
+    sx = shift_of(code & 3, Lb[0]);
+    sy = shift_of((code >> 2) & 3, Lb[1]);
+    sz = shift_of(code >> 4, Lb[2]);
     return pstart[l] + (c - ppref[l]);
 }
 
@@ -405,7 +404,6 @@ __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     const int rows = list_rows(a.kp);
-    const double L = a.g.L;
     // the list radius with a relative margin of 1e-12: a candidate is tested
     // as home - (its position + image shift), the evaluation forms the same
     // difference in another order, and a pair on the radius must not be lost
@@ -433,7 +431,7 @@ __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
             if (live) {
                 double sx, sy, sz;
                 const int l = tabled ? (int)pidx[wv][c] : window_piece(ppref[wv], c);
-                j = window_candidate(pstart[wv], ppref[wv], pcode[wv], c, l, L, sx, sy, sz);
+                j = window_candidate(pstart[wv], ppref[wv], pcode[wv], c, l, a.g.L, sx, sy, sz);
                 const double4 qj = a.xs[j];
                 px = qj.x + sx;
                 py = qj.y + sy;
@@ -649,8 +647,8 @@ __global__ __launch_bounds__(kEvalThreads) void k_near_batch(const NearArgs *__r
 static bool near_args_ok(const NearArgs &a)
 {
     return a.N >= 1 && a.xs && a.cell_start && a.nbr && a.nbr_cnt && a.fnear && a.kp >= 1 &&
-           a.g.nc >= 6 &&
-           a.rc2 > 0.0 && a.rl2 >= a.rc2 && a.w > 0.0 && (!a.energy || a.epart) && a.nrho >= 0 && a.nrho % 8 == 0 &&
+           a.g.nc[0] >= 6 && a.g.nc[1] >= 6 && a.g.nc[2] >= 6 &&
+           a.rc2 > 0.0 && a.rl2 >= a.rc2 && a.w[0] > 0.0 && a.w[1] > 0.0 && a.w[2] > 0.0 && (!a.energy || a.epart) && a.nrho >= 0 && a.nrho % 8 == 0 &&
            (a.nrho == 0 || (a.red.xs && rho_partial_ok(a.red) && a.red.mixed == a.mixed &&
                             a.nrho >= rho_blocks(a.red.nchunk, a.red.P)));
 }

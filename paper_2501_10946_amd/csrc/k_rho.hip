@@ -8,6 +8,10 @@
 
 namespace rbsog {
 
+// the virial factors of eW: by |n|^2 from vm (a cube), or mode by mode from
+// the Fourier coefficients (a cuboid)
+static bool vm_ok(const RhoArgs &a) { return a.vm || (a.nG >= 1 && a.nG <= kMaxGauss && a.fa && a.fb); }
+
 // Partial sums per (group, sample): rho_partial_body (shared with the near
 // kernel, which can run it in its first workgroups) is in dev_common.h.
 
@@ -84,7 +88,7 @@ hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st)
 
 hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st)
 {
-    if (!a.part || !a.rho || !a.gk || !a.eF || !a.samp || (a.eW && !a.vm)) return hipErrorInvalidValue;
+    if (!a.part || !a.rho || !a.gk || !a.eF || !a.samp || (a.eW && !vm_ok(a))) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_rho_reduce, dim3(rho_reduce_blocks(a.P)), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
@@ -107,14 +111,17 @@ __global__ __launch_bounds__(kBlock) void k_rho_full(RhoArgs a)
         for (int k = t; k < kPhaseTab; k += kBlock) tab[k] = a.tab[k];
     const int l = blockIdx.x * kBlock + t;
     const bool live = l < a.P;
-    const double ph = MIXED ? a.inv_L : a.inv_L * kPhaseTab;   // phase unit of the precision
+    // phase units of the precision, per axis
+    const double phx = MIXED ? a.inv_L[0] : a.inv_L[0] * kPhaseTab;
+    const double phy = MIXED ? a.inv_L[1] : a.inv_L[1] * kPhaseTab;
+    const double phz = MIXED ? a.inv_L[2] : a.inv_L[2] * kPhaseTab;
     const double4 k = live ? a.samp[l] : make_double4(0.0, 0.0, 0.0, 0.0);
     double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
     for (int j0 = 0; j0 < a.N; j0 += kBlock) {
         __syncthreads();
         if (j0 + t < a.N) {
             double4 v = a.xs[j0 + t];
-            sp[t] = make_double4(v.x * ph, v.y * ph, v.z * ph, v.w);
+            sp[t] = make_double4(v.x * phx, v.y * phy, v.z * phz, v.w);
         }
         __syncthreads();
         const int nj = min(kBlock, a.N - j0);
@@ -130,10 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_rho_full(RhoArgs a)
         a.rho[l] = make_double2(re, im);
         a.gk[l] = make_double2(cf * re, cf * im);
         a.eF[l] = 0.5 * cf * (re * re + im * im);
-        if (a.eW) {
-            const int m = (int)(k.x * k.x + k.y * k.y + k.z * k.z);
-            a.eW[l] = cf * (re * re + im * im) * (1.5 - a.vm[m]);
-        }
+        if (a.eW) a.eW[l] = cf * (re * re + im * im) * (1.5 - mode_vm(a, k));
         if (a.rho_out) {
             a.rho_out[2 * l] = re;
             a.rho_out[2 * l + 1] = im;
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void k_rho_full(RhoArgs a)
 hipError_t launch_rho_full(const RhoArgs &a, hipStream_t st)
 {
     if (a.N < 1 || a.P < 1 || !a.xs || !a.samp || !a.rho || !a.gk || !a.eF || (!a.mixed && !a.tab) ||
-        (a.eW && !a.vm))
+        (a.eW && !vm_ok(a)))
         return hipErrorInvalidValue;
     dim3 grid((unsigned)((a.P + kBlock - 1) / kBlock));
     if (a.mixed) hipLaunchKernelGGL(k_rho_full<true>, grid, dim3(kBlock), 0, st, a);

@@ -56,11 +56,12 @@ struct SogDev {
     double kpoly[29];           // r (Y - F)
 };
 
-// Geometry of the cell list.
+// Geometry of the cell list (a cube has equal entries on the three axes).
 struct CellGeom {
-    int nc;                // cells per axis
-    int ncell;             // nc^3
-    double L, inv_cell;    // box edge, nc / L
+    int nc[3];             // cells along x, y, z
+    int ncell;             // nc[0] nc[1] nc[2]
+    double L[3];           // box edges
+    double inv_cell[3];    // nc[d] / L[d]
 };
 
 // --- cells -----------------------------------------------------------------
@@ -132,7 +133,7 @@ struct Thermo {
 // First half-kick and drift in cell order.
 struct KickDriftArgs {
     int N;
-    double L, inv_L, dt;
+    double L[3], inv_L[3], dt;
     double4 *xs;           // [N] (x, y, z, q), positions updated in place
     double *vs;            // SoA [3][N], updated in place
     const double *fs;      // SoA [3][N]
@@ -181,7 +182,7 @@ hipError_t launch_sample_batch(const SampleArgs *tab, const EnsItem *items, int 
 // --- structure factors -----------------------------------------------------------
 struct RhoArgs {
     int N, P, nchunk, chunk;   // chunk = particles per group (a power of two, rho_chunk)
-    double inv_L;
+    double inv_L[3];           // 1 / L_d: k . r = 2 pi sum_d n_d x_d / L_d
     const double4 *xs;         // cell-ordered (x, y, z, q), or null to read x/q
     const double *x, *q;       // original-order SoA positions and charges
     const double4 *samp;       // [P]
@@ -189,8 +190,12 @@ struct RhoArgs {
     double2 *rho;              // [P]
     double2 *gk;               // [P] coef * rho
     double *eF;                // [P] coef |rho|^2 / 2
-    double *eW;                // null, or [P] coef |rho|^2 (3/2 - vm[|n|^2]): the modes' far-field virial terms
-    const double *vm;          // [m_max + 1] k^2 G / Fhat by |n|^2 (when eW)
+    double *eW;                // null, or [P] coef |rho|^2 (3/2 - vm): the modes' far-field virial terms
+    const double *vm;          // [m_max + 1] vm = k^2 G / Fhat by |n|^2 (a cube, when eW)
+    // a cuboid (vm null, eW set): vm from k^2 = sum_d (2 pi n_d / L_d)^2 and the
+    // decomposition's Fourier coefficients, Fhat = sum_g fa[g] exp(-fb[g] k^2)
+    int nG;
+    const double *fa, *fb;     // [nG] each
     double *rho_out;           // [P][2] or null
     int mixed;
     const double2 *tab;        // [kPhaseTab] (sin, cos)(2 pi j / kPhaseTab) (FP64 path)
@@ -224,9 +229,9 @@ struct NearArgs {
     double *epart;             // [2][near_blocks(N)] energy, then virial partials (when energy)
     int mixed;
     int energy;
-    double w;                  // cell width L / nc (g is the fine grid, nc = floor(2L / r_c))
+    double w[3];               // cell widths L_d / nc_d (g is the fine grid, nc_d = floor(2 L_d / (r_c + skin)))
     double margin;             // slack of the per-particle cell culling
-    double inv_L;
+    double inv_L[3];
     Exp2Poly e2;
     int32_t *nbr;              // list_rows(kp) entries per particle (blocks, list_at): listed j in candidate order
     int32_t *nbr_cnt;          // [N] listed count per particle; list_rows(kp) + 1 when the list overflowed
@@ -251,7 +256,10 @@ hipError_t launch_nlist(const NearArgs &a, hipStream_t st);
 // (256 particles x one of 5 lanes), far field (64 particles)
 // list build: one pair of x-adjacent cells per wave, kListWaves waves per workgroup
 constexpr int kListWaves = 4;
-__host__ __device__ inline int nlist_blocks(int nf) { return (nf * nf * ((nf + 1) / 2) + kListWaves - 1) / kListWaves; }
+__host__ __device__ inline int nlist_blocks(const int nf[3])
+{
+    return (nf[2] * nf[1] * ((nf[0] + 1) / 2) + kListWaves - 1) / kListWaves;
+}
 // Neighbour lists are particle-major: the `rows` entries of particle p are
 // contiguous at list_at(p, 0, rows) (rows a multiple of kListBlock,
 // list_rows), so a list build's append of a run of accepted candidates of one
@@ -287,7 +295,7 @@ hipError_t launch_near(const NearArgs &a, hipStream_t st);
 // --- far field + assembly + second half-kick ---------------------------------------
 struct FarArgs {
     int N, P;
-    double two_pi_over_L, inv_L;
+    double two_pi_over_L[3], inv_L[3];
     const double4 *xs;         // cell order
     const int32_t *order;
     const double4 *samp;       // [P] (nx, ny, nz, coef)
@@ -312,7 +320,7 @@ struct FarArgs {
     // xs_next = xs (written back), gate_raise raised when a particle has moved
     // more than half the skin since the build.
     int drift;
-    double dt, L, half_skin2;
+    double dt, L[3], half_skin2;
     const double *xb;          // SoA [3][N] positions at the last build, cell order
     double4 *xs_next;
     int32_t *gate_raise;

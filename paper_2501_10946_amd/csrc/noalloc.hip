@@ -94,7 +94,7 @@ extern "C" int rbsog_rho_noalloc(int64_t N, double L, const double *x_dev, const
     a.P = P;
     a.chunk = chunk;
     a.nchunk = nchunk;
-    a.inv_L = 1.0 / L;
+    a.inv_L[0] = a.inv_L[1] = a.inv_L[2] = 1.0 / L;
     a.xs = nullptr;
     a.x = x_dev;
     a.q = q_dev;

@@ -97,22 +97,22 @@ __global__ __launch_bounds__(kBlock) void k_rdf(RdfArgs a)
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p < a.N) {
         const double4 r = a.xs[p];
-        const int nc = a.g.nc;
-        const int cx = cell_coord(r.x, a.g.inv_cell, nc), cy = cell_coord(r.y, a.g.inv_cell, nc),
-                  cz = cell_coord(r.z, a.g.inv_cell, nc);
+        const int ncx = a.g.nc[0], ncy = a.g.nc[1], ncz = a.g.nc[2];
+        const int cx = cell_coord(r.x, a.g.inv_cell[0], ncx), cy = cell_coord(r.y, a.g.inv_cell[1], ncy),
+                  cz = cell_coord(r.z, a.g.inv_cell[2], ncz);
         for (int dz = -2; dz <= 2; ++dz) {
             int z = cz + dz;
             double sz = 0.0;
-            if (z < 0) { z += nc; sz = -a.g.L; } else if (z >= nc) { z -= nc; sz = a.g.L; }
+            if (z < 0) { z += ncz; sz = -a.g.L[2]; } else if (z >= ncz) { z -= ncz; sz = a.g.L[2]; }
             for (int dy = -2; dy <= 2; ++dy) {
                 int y = cy + dy;
                 double sy = 0.0;
-                if (y < 0) { y += nc; sy = -a.g.L; } else if (y >= nc) { y -= nc; sy = a.g.L; }
+                if (y < 0) { y += ncy; sy = -a.g.L[1]; } else if (y >= ncy) { y -= ncy; sy = a.g.L[1]; }
                 for (int dx = -2; dx <= 2; ++dx) {
                     int x = cx + dx;
                     double sx = 0.0;
-                    if (x < 0) { x += nc; sx = -a.g.L; } else if (x >= nc) { x -= nc; sx = a.g.L; }
-                    const int c = (z * nc + y) * nc + x;
+                    if (x < 0) { x += ncx; sx = -a.g.L[0]; } else if (x >= ncx) { x -= ncx; sx = a.g.L[0]; }
+                    const int c = (z * ncy + y) * ncx + x;
                     for (int j = a.cell_start[c]; j < a.cell_start[c + 1]; ++j) {
                         if (j == p) continue;
                         const double4 q = a.xs[j];
@@ -285,7 +285,7 @@ extern "C" int rbsog_ssf(int64_t N, double L, const double *x_dev, const double 
         a.P = (int)std::min<int64_t>(pl.P, pl.K - c0);
         a.chunk = rho_chunk((int)N, a.P);
         a.nchunk = (int)((N + a.chunk - 1) / a.chunk);
-        a.inv_L = 1.0 / L;
+        a.inv_L[0] = a.inv_L[1] = a.inv_L[2] = 1.0 / L;
         a.x = x_dev;
         a.q = w_dev;
         a.samp = dm + c0;
@@ -326,7 +326,8 @@ extern "C" int rbsog_rdf(rbsog_handle *h, const double *x_dev, double r_max, int
     a.rmax2 = r_max * r_max;
     a.dr = r_max / nbins;
     a.hist = hist_dev;
-    if (a.g.nc < 5) return fail(RBSOG_EINVAL, "fine grid of %d cells is below the 5-cell stencil", a.g.nc);
+    for (int d = 0; d < 3; ++d)
+        if (a.g.nc[d] < 5) return fail(RBSOG_EINVAL, "fine grid of %d cells is below the 5-cell stencil", a.g.nc[d]);
     hipLaunchKernelGGL(k_rdf, dim3((a.N + kBlock - 1) / kBlock), dim3(kBlock), 0, h->st, a);
     HIPCHECK(hipGetLastError());
     return RBSOG_OK;

@@ -30,6 +30,7 @@ struct Layout {
     size_t samp, part, rho, gk, eF, eW, vm, fnear, epart, kepart, flag, energy, nbr, nbr_cnt, tab, tab_far;
     size_t cdf_q, mh;   // Metropolis-Hastings draws: proposal CDF, chain state
     size_t bath;        // global bath state (kBathWords doubles)
+    size_t fab;         // the decomposition's Fourier coefficients A, B (cuboid virial factors)
     size_t total;
 };
 
@@ -39,10 +40,13 @@ struct Layout {
 // (cells >= (r_c + skin)/2, a 5 x 5 x 5 stencil).
 struct Derived {
     double skin, rl;   // neighbour-list skin and radius r_c + skin
-    int nc, nf;        // coarse and fine cells per axis
-    int nf_tight;      // fine cells per axis of lists of radius r_c alone (the grid a dropped skin uses; >= nf)
-    int mmax;
+    double Lb[3];      // box edges (equal in a cube)
+    int cuboid;        // edges differ: the measure point by point (each lattice point its own shell)
+    int nc[3], nf[3];  // coarse and fine cells per axis
+    int nf_tight[3];   // fine cells per axis of lists of radius r_c alone (the grid a dropped skin uses; >= nf)
+    int mmax;          // cube: lattice 1 <= |n|^2 <= mmax; cuboid: 0
     int64_t nlat;
+    int64_t nshells;   // capacity of the per-shell tables: mmax (cube) or nlat (cuboid)
     int kp;            // neighbour-list capacity per (particle, chunk)
     int sbatch;        // steps whose modes one sampling launch draws
     int full_k;        // deterministic far field over the whole lattice
@@ -51,7 +55,11 @@ struct Derived {
 
 size_t align_up(size_t v);
 int nchunks(int64_t N, int P);
-CellGeom make_geom(double L, int nc);
+CellGeom make_geom(const double Lb[3], const int nc[3]);
+// the box edges of the parameters (Ly, Lz of 0 take L)
+void box_edges(const rbsog_params *p, double Lb[3]);
+// kp of a system of N particles in volume V for lists of radius rl
+int near_capacity(int64_t N, double V, double rl);
 Derived derive(const rbsog_params *p, const rbsog_sog *s);
 // shared_lattice: the packed lattice lives outside the workspace
 Layout make_layout(int64_t N, const Derived &d, int P, bool shared_lattice);
@@ -100,6 +108,7 @@ struct rbsog_handle {
     int samp_n;
     // Metropolis-Hastings draws (p.sampler == 1): the proposal CDF (F = 1) and
     // its total, and the chain state (lattice index, shell index; -1 empty)
+    double *fab = nullptr;   // [2][kMaxGauss] A then B
     double *cdf_q = nullptr;
     double Sq = 0.0;
     int32_t *mh = nullptr;

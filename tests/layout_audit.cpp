@@ -20,9 +20,6 @@
 
 using namespace rbsog;
 
-namespace rbsog {
-int near_capacity(int64_t N, double L, double rl, int nf);
-}
 
 static int failures = 0;
 
@@ -38,8 +35,9 @@ static int failures = 0;
 
 static size_t span(size_t a, size_t b) { return b - a; }   // bytes between two consecutive offsets
 
-static void audit(int64_t N, double L, double lambda, double rc, int P, double skin)
+static void audit(int64_t N, const double Lb[3], double lambda, double rc, int P, double skin)
 {
+    const double L = Lb[0];
     rbsog_sog s{};
     if (rbsog_sog_init(lambda, rc, 1e-4, 1, RBSOG_AUTO, RBSOG_AUTO, &s) != RBSOG_OK) {
         std::printf("skip: no SOG for lambda %g r_c %g\n", lambda, rc);
@@ -56,29 +54,38 @@ static void audit(int64_t N, double L, double lambda, double rc, int P, double s
     p.density = RBSOG_ADAPTIVE;
     p.skin = skin;
     p.full_k = 0;
+    p.Ly = Lb[1];
+    p.Lz = Lb[2];
     if (check_params(&p, &s) != RBSOG_OK) return;   // refused before any launch
     const Derived d = derive(&p, &s);
     const Layout w = make_layout(N, d, P, false);
     char tag[160];
-    std::snprintf(tag, sizeof tag, "N %lld L %.4g lambda %g r_c %g P %d skin %g", (long long)N, L, lambda, rc, P,
-                  skin);
+    std::snprintf(tag, sizeof tag, "N %lld L %.4g x %.4g x %.4g lambda %g r_c %g P %d skin %g", (long long)N, Lb[0],
+                  Lb[1], Lb[2], lambda, rc, P, skin);
     // cell grids the kernels can index: coarse, fine, fine of a dropped skin
-    const int grids[3] = {d.nc, d.nf, d.nf_tight};
-    for (int g : grids) {
-        const size_t ncell = (size_t)g * g * g;
-        CHECK(span(w.count, w.cell_start) >= 4 * ncell, "%s grid %d: counts", tag, g);
-        CHECK(span(w.cell_start, w.fill) >= 4 * (ncell + 1), "%s grid %d: cell starts", tag, g);
-        CHECK(span(w.fill, w.tmp) >= 4 * ncell, "%s grid %d: fill", tag, g);
-        CHECK(span(w.tile_sum, w.xb) >= 4 * (size_t)scan_tiles((int)ncell), "%s grid %d: scan tiles", tag, g);
+    const int *grids[3] = {d.nc, d.nf, d.nf_tight};
+    for (const int *g : grids) {
+        const size_t ncell = (size_t)g[0] * g[1] * g[2];
+        CHECK(span(w.count, w.cell_start) >= 4 * ncell, "%s grid %d: counts", tag, g[0]);
+        CHECK(span(w.cell_start, w.fill) >= 4 * (ncell + 1), "%s grid %d: cell starts", tag, g[0]);
+        CHECK(span(w.fill, w.tmp) >= 4 * ncell, "%s grid %d: fill", tag, g[0]);
+        CHECK(span(w.tile_sum, w.xb) >= 4 * (size_t)scan_tiles((int)ncell), "%s grid %d: scan tiles", tag, g[0]);
     }
-    // the 5-cell stencil of each fine grid reaches the list radius; at least 6 cells
-    CHECK(d.nf >= 6 && d.nf_tight >= 6, "%s: fine grid below 6 cells", tag);
-    CHECK(d.rl <= 2.0 * L / d.nf * (1 + 1e-15), "%s: list radius %g beyond the stencil of %d cells", tag, d.rl, d.nf);
-    CHECK(rc <= 2.0 * L / d.nf_tight * (1 + 1e-15), "%s: r_c beyond the stencil of the tight grid", tag);
-    CHECK(d.nf_tight >= d.nf, "%s: the tight grid is coarser", tag);
+    for (int a = 0; a < 3; ++a) {
+        // the 5-cell stencil of each fine grid reaches the list radius; at least 6 cells
+        CHECK(d.nf[a] >= 6 && d.nf_tight[a] >= 6, "%s: fine grid below 6 cells (axis %d)", tag, a);
+        CHECK(d.rl <= 2.0 * Lb[a] / d.nf[a] * (1 + 1e-15), "%s: list radius %g beyond the stencil of %d cells", tag,
+              d.rl, d.nf[a]);
+        CHECK(rc <= 2.0 * Lb[a] / d.nf_tight[a] * (1 + 1e-15), "%s: r_c beyond the stencil of the tight grid", tag);
+        CHECK(d.nf_tight[a] >= d.nf[a], "%s: the tight grid is coarser", tag);
+    }
+    // the sampling tables hold one entry per shell (cube) or per point (cuboid)
+    CHECK(span(w.cdf, w.coef) >= 8 * (size_t)d.nshells && span(w.cdf_q, w.mh) >= 8 * (size_t)d.nshells,
+          "%s: sampling tables", tag);
+    CHECK(d.cuboid ? d.nshells == d.nlat : d.nshells == d.mmax, "%s: table capacity", tag);
     // neighbour lists: list_rows(kp) entries per particle of the padded tiles, for
     // both list radii (the capacity only shrinks when the skin drops)
-    const int kp_tight = near_capacity(N, L, rc, d.nf_tight);
+    const int kp_tight = near_capacity(N, Lb[0] * Lb[1] * Lb[2], rc);
     const int kp = d.kp > kp_tight ? d.kp : kp_tight;
     const int rows = list_rows(kp);
     CHECK(rows % kListBlock == 0 && rows >= 5 * kp, "%s: list rows of whole blocks", tag);
@@ -111,9 +118,10 @@ static void audit(int64_t N, double L, double lambda, double rc, int P, double s
     CHECK(span(w.xs, w.xs_old) >= 32 * (size_t)N && span(w.ms, w.ms_old) >= 8 * (size_t)N, "%s: rows", tag);
     CHECK(span(w.tab, w.tab_far) >= 16 * (size_t)kPhaseTable, "%s: rotation table", tag);
     CHECK(span(w.tab_far, w.cdf_q) >= 16 * (size_t)kFarTable, "%s: far rotation table", tag);
-    CHECK(span(w.cdf_q, w.mh) >= 8 * (size_t)d.mmax, "%s: proposal CDF of the chain", tag);
+    CHECK(span(w.cdf_q, w.mh) >= 8 * (size_t)d.nshells, "%s: proposal CDF of the chain", tag);
     CHECK(span(w.mh, w.bath) >= 8, "%s: chain state", tag);
-    CHECK(w.total >= w.bath + 8 * (size_t)kBathWords, "%s: total", tag);
+    CHECK(span(w.bath, w.fab) >= 8 * (size_t)kBathWords, "%s: bath state", tag);
+    CHECK(w.total >= w.fab + 16 * (size_t)kMaxGauss, "%s: total", tag);
 }
 
 // every call below carries one argument a kernel cannot run on, and must be
@@ -131,7 +139,7 @@ static void guards()
     // cells: every buffer present but one
     CellArgs c{};
     c.N = 10;
-    c.g.nc = 3;
+    c.g.nc[0] = c.g.nc[1] = c.g.nc[2] = 3;
     c.g.ncell = 27;
     c.xs = d4;
     c.order = ip;
@@ -182,11 +190,11 @@ static void guards()
     // near field
     NearArgs n{};
     n.N = 10;
-    n.g.nc = 6;
+    n.g.nc[0] = n.g.nc[1] = n.g.nc[2] = 6;
     n.g.ncell = 216;
     n.rc2 = 1.0;
     n.rl2 = 1.2;
-    n.w = 1.0;
+    n.w[0] = n.w[1] = n.w[2] = 1.0;
     n.kp = 4;
     n.xs = d4;
     n.cell_start = ip;
@@ -195,7 +203,7 @@ static void guards()
     n.fnear = d;
     n.sog.n = 2;
     NearArgs b = n;
-    b.g.nc = 5;
+    b.g.nc[2] = 5;
     refused(launch_nlist(b, nullptr), "list build on a grid of 5 cells (the stencil would wrap onto itself)");
     refused(launch_near(b, nullptr), "evaluation on a grid of 5 cells");
     b = n;
@@ -327,11 +335,18 @@ int main()
     for (const Sys &y : sys) {
         const double L0 = std::cbrt((double)y.N / n);
         // the workload's box, and the smallest box the checks admit (three cells)
-        const double Ls[] = {L0, 3.0 * y.rc, 3.0 * y.rc * (1.0 + 1e-12)};
-        for (double L : Ls)
+        // and cuboids: elongated along one axis, and with one edge at three cells
+        const double Ls[][3] = {{L0, L0, L0},
+                                {3.0 * y.rc, 3.0 * y.rc, 3.0 * y.rc},
+                                {3.0 * y.rc * (1.0 + 1e-12), 3.0 * y.rc * (1.0 + 1e-12), 3.0 * y.rc * (1.0 + 1e-12)},
+                                {L0, 1.3 * L0, 0.8 * L0},
+                                {3.0 * y.rc, 2.0 * L0, L0}};
+        for (int k = 0; k < 5; ++k)
             for (int P : Ps)
                 for (double sk : skins) {
-                    audit(y.N, L, y.lambda, y.rc, P, sk);
+                    // a cuboid's lattice is enumerated point by point: fewer combinations
+                    if (k >= 3 && ((P != 7 && P != 500) || (sk != -1.0 && sk != 0.0))) continue;
+                    audit(y.N, Ls[k], y.lambda, y.rc, P, sk);
                     ++cases;
                 }
     }

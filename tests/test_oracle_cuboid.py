@@ -221,3 +221,16 @@ def test_equal_edges_reduce_to_the_cube(orc):
     fa, ua, wa = orc.far_full(st.x, st.q, L, s, mmax, virial=True)
     fb, ub, wb = orc.far_full_box(st.x, st.q, (L, L, L), s, virial=True)
     assert np.array_equal(fa, fb) and ua == ub and wa == wb
+
+
+def test_rdf_in_a_cuboid_against_kdtree(orc):
+    Lb = (9.0, 12.0, 10.5)
+    st = _state(600, Lb, 37)
+    counts, amb = orc.rdf(st.x, Lb, 3.0, 30)
+    pairs = cKDTree(st.x.T, boxsize=Lb).query_pairs(3.0, output_type="ndarray")
+    d = st.x.T[pairs[:, 0]] - st.x.T[pairs[:, 1]]
+    d -= np.asarray(Lb)[None, :] * np.round(d / np.asarray(Lb)[None, :])
+    r = np.sqrt((d * d).sum(1))
+    ref = 2 * np.bincount(np.minimum((r / 0.1).astype(int), 29), minlength=30)
+    assert np.abs(counts - ref).max() <= amb.max() + 0 and counts.sum() == ref.sum()
+    assert np.array_equal(orc.rdf(st.x, (9.0, 9.0, 9.0), 3.0, 30)[0], orc.rdf(st.x, 9.0, 3.0, 30)[0])
