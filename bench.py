@@ -78,9 +78,9 @@ KERNEL_SOURCES = {
 # WRITE_SIZE 262150 KiB for 262144 KiB written: x1.000).
 MEASURED_TRAFFIC = {
     # kernel: (sources sha256, FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale)
-    "near": ("1daa80a40affc7c07b42801c5af763a5a0ecd0fcea18a323e0697bd37ae38133", 446270.0, 100836.0, 2.0, 1.0),
-    "far": ("c041e700b542d55eb61e478ffa06fc1bce98a2cbebf5a009e76e816abb1d10a0", 78334.0, 78613.0, 2.0, 1.0),
-    "nlist": ("85afbbb2331887b4c272203addcf417e21c115a9895568513adf8907a6f07213", 84024.0, 523322.0, 2.0, 1.0),
+    "near": ("d8c9f6e42707f5b874408e2458aecb0d11c451e58c0f9aefb937b4941811bc81", 445102.0, 100836.0, 2.0, 1.0),
+    "far": ("2a2d8c4ed6f9770c395bafc5c93274e7890212a221fc82e9c790665929ea5ec1", 78336.0, 78613.0, 2.0, 1.0),
+    "nlist": ("cd7fab6f9cb30d6e2cc0f3f7d282234e971de26c020789d22c1c505136e1fe7d", 84018.0, 523160.0, 2.0, 1.0),
 }
 
 # VALU issue at the same workload (FP64): VALU busy = SQ_ACTIVE_INST_VALU x 4
@@ -89,9 +89,9 @@ MEASURED_TRAFFIC = {
 # fraction of the VALU's lane-cycles that issued work.
 MEASURED_VALU = {
     # kernel: (sources sha256, VALU busy, lane utilisation)
-    "near": ("1daa80a40affc7c07b42801c5af763a5a0ecd0fcea18a323e0697bd37ae38133", 0.87, 0.90),
-    "far": ("c041e700b542d55eb61e478ffa06fc1bce98a2cbebf5a009e76e816abb1d10a0", 0.88, 1.00),
-    "nlist": ("85afbbb2331887b4c272203addcf417e21c115a9895568513adf8907a6f07213", 0.77, 0.78),
+    "near": ("d8c9f6e42707f5b874408e2458aecb0d11c451e58c0f9aefb937b4941811bc81", 0.88, 0.88),
+    "far": ("2a2d8c4ed6f9770c395bafc5c93274e7890212a221fc82e9c790665929ea5ec1", 0.88, 1.00),
+    "nlist": ("cd7fab6f9cb30d6e2cc0f3f7d282234e971de26c020789d22c1c505136e1fe7d", 0.77, 0.78),
 }
 
 
