@@ -560,6 +560,11 @@ int rbsog_rdf(rbsog_handle *h, const double *x_dev, double r_max, int nbins, uns
  */
 int rbsog_track(int64_t N, double L, const double *x_dev, double *x_last_dev, double *disp_dev, void *hip_stream);
 
+/* rbsog_track in a cuboid box of edges (Lx, Ly, Lz): the minimum image per
+ * axis.  Errors: RBSOG_EINVAL. */
+int rbsog_track_box(int64_t N, double Lx, double Ly, double Lz, const double *x_dev, double *x_last_dev,
+                    double *disp_dev, void *hip_stream);
+
 /* Scratch bytes of rbsog_msd_vacf (host only).  Errors: RBSOG_EINVAL. */
 int rbsog_msd_scratch_size(size_t *bytes);
 

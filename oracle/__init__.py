@@ -121,6 +121,7 @@ def lib():
             "orc_mh_draw": (None, [_i, _u64, _u64, _u32, _i, _p, _p, _p, _p, _p, _p, _p, _p]),
             "orc_rdf": (None, [_i64, _p, _d, _d, _i, _p, _p]),
             "orc_track": (None, [_i64, _d, _p, _p, _p]),
+            "orc_track_box": (None, [_i64, _p, _p, _p, _p]),
             "orc_msd_vacf": (None, [_i64, _p, _p, _p, _p]),
         }
         for name, (res, args) in sig.items():
@@ -613,11 +614,15 @@ def rdf(x, L, r_max: float, nbins: int):
     return counts, amb
 
 
-def track(x, L: float, x_last, disp) -> None:
-    """disp += minimum-image (x - x_last); x_last = x (in place)."""
+def track(x, L, x_last, disp) -> None:
+    """disp += minimum-image (x - x_last); x_last = x (in place); L one edge
+    or the three edges of a cuboid."""
     x = _f64(x)
     assert x_last.flags.c_contiguous and disp.flags.c_contiguous
-    lib().orc_track(x.shape[1], L, _ptr(x), _ptr(x_last), _ptr(disp))
+    if is_cube(L):
+        lib().orc_track(x.shape[1], box(L)[0], _ptr(x), _ptr(x_last), _ptr(disp))
+    else:
+        lib().orc_track_box(x.shape[1], _ptr(box(L)), _ptr(x), _ptr(x_last), _ptr(disp))
 
 
 def msd_vacf(disp, v0, v):

@@ -1921,6 +1921,20 @@ void orc_track(int64_t N, double L, const double *x, double *x_last, double *dis
     }
 }
 
+/* orc_track in a cuboid box of edges Lb[3]: the minimum image along each
+ * axis with that axis's edge. */
+void orc_track_box(int64_t N, const double *Lb, const double *x, double *x_last, double *disp)
+{
+    for (int a = 0; a < 3; ++a)
+        for (int64_t i = 0; i < N; ++i) {
+            const int64_t k = a * N + i;
+            double d = x[k] - x_last[k];
+            d = d - Lb[a] * rint(d / Lb[a]);
+            disp[k] += d;
+            x_last[k] = x[k];
+        }
+}
+
 /* Mean squared displacement (1/N) sum_i |disp_i|^2 and velocity
  * autocorrelation (1/N) sum_i v0_i . v_i (Section 5.1's MSD and VACF at one
  * time lag), in particle order. */

@@ -120,6 +120,7 @@ def lib() -> C.CDLL:
             "rbsog_set_bath": (C.c_int, [_p, C.c_int, C.c_double, C.c_double]),
             "rbsog_bath_state": (C.c_int, [_p, C.POINTER(C.c_double)]),
             "rbsog_track": (C.c_int, [C.c_int64, C.c_double, _p, _p, _p, _p]),
+            "rbsog_track_box": (C.c_int, [C.c_int64, C.c_double, C.c_double, C.c_double, _p, _p, _p, _p]),
             "rbsog_msd_scratch_size": (C.c_int, [C.POINTER(C.c_size_t)]),
             "rbsog_msd_vacf": (C.c_int, [C.c_int64, _p, _p, _p, _p, C.c_size_t, _p, _p]),
             "rbsog_last_error": (C.c_char_p, []),
@@ -350,12 +351,17 @@ def rbsog_bath_state(h):
     return out[0], out[1]
 
 
-def rbsog_track(x, L: float, x_last, disp, stream=None) -> None:
-    """disp += minimum-image (x - x_last); x_last = x (device tensors [3, N])."""
+def rbsog_track(x, L, x_last, disp, stream=None) -> None:
+    """disp += minimum-image (x - x_last); x_last = x (device tensors [3, N]);
+    L one edge or the three edges of a cuboid."""
     import torch
     N = x.shape[1]
-    _check(lib().rbsog_track(N, L, _dptr(x, torch.float64, 3 * N), _dptr(x_last, torch.float64, 3 * N),
-                             _dptr(disp, torch.float64, 3 * N), stream or _stream(x.device)))
+    args = (_dptr(x, torch.float64, 3 * N), _dptr(x_last, torch.float64, 3 * N), _dptr(disp, torch.float64, 3 * N),
+            stream or _stream(x.device))
+    if isinstance(L, (tuple, list)):
+        _check(lib().rbsog_track_box(N, float(L[0]), float(L[1]), float(L[2]), *args))
+    else:
+        _check(lib().rbsog_track(N, L, *args))
 
 
 def rbsog_msd_scratch_size() -> int:

@@ -137,14 +137,19 @@ __global__ __launch_bounds__(kBlock) void k_rdf(RdfArgs a)
 // displacement tracking, MSD and VACF
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_track(int64_t n3, double L, double inv_L, const double *__restrict__ x,
+struct TrackBox {
+    double L[3], inv_L[3];
+};
+
+__global__ __launch_bounds__(kBlock) void k_track(int64_t N, TrackBox b, const double *__restrict__ x,
                                                   double *__restrict__ x_last, double *__restrict__ disp)
 {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= n3) return;
+    if (k >= 3 * N) return;
+    const int a = (int)(k / N);   // the axis of component k (SoA [3][N])
     const double xn = x[k];
     double d = xn - x_last[k];
-    d = d - L * rint(d * inv_L);
+    d = d - b.L[a] * rint(d * b.inv_L[a]);
     disp[k] += d;
     x_last[k] = xn;
 }
@@ -194,17 +199,30 @@ __global__ __launch_bounds__(kBlock) void k_msd_final(int64_t N, const double2 *
 
 using namespace rbsog;
 
-extern "C" int rbsog_track(int64_t N, double L, const double *x_dev, double *x_last_dev, double *disp_dev,
-                           void *hip_stream)
+extern "C" int rbsog_track_box(int64_t N, double Lx, double Ly, double Lz, const double *x_dev, double *x_last_dev,
+                               double *disp_dev, void *hip_stream)
 {
     if (N < 1 || N > ((int64_t)1 << 27) - 1) return fail(RBSOG_EINVAL, "N must lie in [1, 2^27 - 1]");
-    if (!(L > 0.0) || !std::isfinite(L)) return fail(RBSOG_EINVAL, "L must be positive and finite");
+    const double Lb[3] = {Lx, Ly, Lz};
+    TrackBox b{};
+    for (int a = 0; a < 3; ++a) {
+        if (!(Lb[a] > 0.0) || !std::isfinite(Lb[a])) return fail(RBSOG_EINVAL, "box edges must be positive and finite");
+        b.L[a] = Lb[a];
+        b.inv_L[a] = 1.0 / Lb[a];
+    }
     if (!x_dev || !x_last_dev || !disp_dev) return fail(RBSOG_EINVAL, "null x, x_last or disp");
     const int64_t n3 = 3 * N;
     hipLaunchKernelGGL(k_track, dim3((unsigned)((n3 + kBlock - 1) / kBlock)), dim3(kBlock), 0, (hipStream_t)hip_stream,
-                       n3, L, 1.0 / L, x_dev, x_last_dev, disp_dev);
+                       N, b, x_dev, x_last_dev, disp_dev);
     HIPCHECK(hipGetLastError());
     return RBSOG_OK;
+}
+
+extern "C" int rbsog_track(int64_t N, double L, const double *x_dev, double *x_last_dev, double *disp_dev,
+                           void *hip_stream)
+{
+    if (!(L > 0.0) || !std::isfinite(L)) return fail(RBSOG_EINVAL, "L must be positive and finite");
+    return rbsog_track_box(N, L, L, L, x_dev, x_last_dev, disp_dev, hip_stream);
 }
 
 extern "C" int rbsog_msd_scratch_size(size_t *bytes)

@@ -61,6 +61,32 @@ def test_track_and_averages_match_oracle(dev, N):
     assert np.array_equal(_msd(dev, dp_d, v0_d, v_d), got)
 
 
+# N = 777: the axis boundaries 777 and 1554 of the [3][N] rows fall inside workgroups
+@pytest.mark.parametrize("N", [1, 777, 262145])
+def test_track_cuboid_matches_oracle(dev, N):
+    """rbsog_track with three edges: each component folds by its own edge."""
+    print(f"\n[case] track cuboid N={N}", flush=True)
+    rng = np.random.default_rng(100 + N)
+    Lb = (6.0, 11.0, 8.5)
+    Lc = np.array(Lb)[:, None]
+    x0 = rng.random((3, N)) * Lc
+    v = rng.normal(0, 2.0, (3, N))
+    x_last = np.ascontiguousarray(x0.copy())
+    disp = np.zeros((3, N))
+    xl_d = torch.tensor(x0, device=dev)
+    dp_d = torch.zeros((3, N), dtype=torch.float64, device=dev)
+    x = x0
+    for n in range(25):
+        x = np.ascontiguousarray(np.mod(x + v * 0.1 + rng.normal(0, 0.5, (3, N)), Lc))
+        oracle.track(x, Lb, x_last, disp)
+        R.rbsog_track(torch.tensor(x, device=dev), Lb, xl_d, dp_d)
+    torch.cuda.synchronize()
+    assert np.array_equal(xl_d.cpu().numpy(), x_last)
+    assert np.abs(dp_d.cpu().numpy() - disp).max() <= 1e-12 * max(Lb)
+    with pytest.raises(R.RbsogError):
+        R.rbsog_track(xl_d, (6.0, 0.0, 8.5), xl_d.clone(), dp_d)
+
+
 def test_tracks_a_library_run(dev):
     w = workloads.OCP_1K
     st = workloads.make_state(w)

@@ -39,3 +39,19 @@ def test_tracking_independent_of_snapshot_spacing(orc):
             orc.track(x, L, x_last, disp)
         out.append(disp)
     assert np.allclose(out[0], out[1], rtol=0, atol=1e-12)
+
+
+def test_ballistic_unwrapping_cuboid(orc):
+    """The same unwrapping with a different edge per axis: each component
+    folds by its own edge (a shared edge would miscount the crossings)."""
+    rng = np.random.default_rng(6)
+    N, Lb, dt = 400, np.array([7.0, 4.5, 10.0]), 0.05
+    x0 = rng.random((3, N)) * Lb[:, None]
+    v = rng.normal(0, 3.0, (3, N))
+    x_last = np.ascontiguousarray(x0.copy())
+    disp = np.zeros((3, N))
+    steps = 400
+    for n in range(1, steps + 1):
+        x = np.mod(x0 + v * (n * dt), Lb[:, None])
+        orc.track(x, tuple(Lb), x_last, disp)
+    assert np.allclose(disp, v * (steps * dt), rtol=0, atol=1e-9)
