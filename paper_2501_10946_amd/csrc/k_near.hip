@@ -339,6 +339,16 @@ __device__ inline bool pair_window(const NearArgs &a, int q, int32_t *pstart, in
     return true;
 }
 
+// The piece of cell pair q's window that holds its home particles (see
+// pair_window): the central row's first piece, or its second when the row
+// wraps at the low x side.
+__device__ inline int pair_window_home_piece(const NearArgs &a, int q)
+{
+    const int half = (a.g.nc[0] + 1) >> 1;
+    const int ix = q - (q / half) * half;
+    return 2 * ix - 2 < 0 ? 25 : 24;
+}
+
 // The piece of candidate c (< the window's total): the last piece whose prefix
 // is <= c (an empty piece shares the prefix of the next, so it is never the
 // one found), by binary search over the 64 prefixes.
@@ -404,6 +414,13 @@ __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     const int rows = list_rows(a.kp);
+    // The home particles are consecutive candidates of the window's central
+    // row (dy = dz = 0, no image shift): piece 24 of that row, or piece 25
+    // when the row wraps at the low x side (its first piece is then the
+    // wrapped cells).  home_c is the candidate index of h_beg, so the lane
+    // that holds a home itself follows from the lane's candidate index.
+    const int lhome = pair_window_home_piece(a, q);
+    const int home_c = __builtin_amdgcn_readfirstlane(ppref[wv][lhome] + (win.h_beg - pstart[wv][lhome]));
     // the list radius with a relative margin of 1e-12: a candidate is tested
     // as home - (its position + image shift), the evaluation forms the same
     // difference in another order, and a pair on the radius must not be lost
@@ -420,12 +437,18 @@ __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        int cnt[kListHomes];
+        // the pass's homes' lists are consecutive rows from pass_row on; slot[hh]
+        // is the next entry of home hh counted from pass_row (hh rows + count)
+        int32_t *pass_row = a.nbr + list_at(hb, 0, rows);
+        uint32_t slot[kListHomes];
 #pragma unroll
-        for (int hh = 0; hh < kListHomes; ++hh) cnt[hh] = 0;
+        for (int hh = 0; hh < kListHomes; ++hh) slot[hh] = (uint32_t)(hh * rows);
+        const int hc = home_c + (hb - win.h_beg);   // candidate index of the pass's first home
         for (int c0 = 0; c0 < total; c0 += 64) {
             const int c = c0 + lane;
             const bool live = c < total;
+            const uint64_t live_m = __builtin_amdgcn_ballot_w64(live);
+            const int own = c - hc;   // the pass's home whose own lane this is (any other value: none)
             int j = -1;
             double px = 0.0, py = 0.0, pz = 0.0;   // the candidate, image-shifted
             if (live) {
@@ -440,31 +463,31 @@ __device__ inline void nlist_pair(const NearArgs &a, int q, int wv)
 #pragma unroll
             for (int hh = 0; hh < kListHomes; ++hh) {
                 if (hh < nh) {   // uniform
-                    const int h = __builtin_amdgcn_readfirstlane(hb + hh);
                     // the home's position is read from LDS at each test (a
                     // broadcast), not held in registers for every home
                     __asm__ volatile("" ::: "memory");
                     const double dx = hpos[wv][0][hh] - px, dy = hpos[wv][1][hh] - py, dz = hpos[wv][2][hh] - pz;
-                    // one predicate, no short-circuit branches; the append
-                    // position by mbcnt; the home's row base wave-uniform, the
-                    // entry a 32-bit offset into it
-                    const bool ok = (dx * dx + dy * dy + dz * dz < R2) & live & (j != h);
-                    const uint64_t m = __builtin_amdgcn_ballot_w64(ok);
-                    if (ok) {
-                        const uint32_t k = (uint32_t)cnt[hh] +
-                                           __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                        int32_t *row = a.nbr + list_at(h, 0, rows);
-                        if (k < (uint32_t)rows) row[k] = j;
+                    // the accepted lanes as one wave mask (the distance test,
+                    // the live lanes, not the home's own lane); the appends
+                    // run under it, at positions by mbcnt.  Appends past the
+                    // capacity all land on the row's last entry: the list is
+                    // then marked overflowed and never read.
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(dx * dx + dy * dy + dz * dz < R2) & live_m &
+                                       __builtin_amdgcn_ballot_w64(own != hh);
+                    if (__builtin_amdgcn_inverse_ballot_w64(m)) {
+                        const uint32_t k = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, slot[hh]));
+                        const uint32_t kk = min(k, (uint32_t)(hh * rows + rows - 1));
+                        *(int32_t *)((char *)pass_row + (kk << 2)) = j;
                     }
-                    cnt[hh] += __popcll(m);
+                    slot[hh] += (uint32_t)__popcll(m);
                 }
             }
         }
         int mine = 0;
 #pragma unroll
         for (int hh = 0; hh < kListHomes; ++hh)
-            if (lane == hh) mine = cnt[hh];
+            if (lane == hh) mine = (int)(slot[hh] - (uint32_t)(hh * rows));
         if (lane < nh) a.nbr_cnt[hb + lane] = mine > rows ? rows + 1 : mine;
         // the positions of the next pass overwrite these
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
