@@ -156,12 +156,13 @@ int rbsog_sog_expand(rbsog_sog *sog);
  * H(r) = r^3 [F_N1(r) + F_N2(r)] = exp(-r/lambda)(1 + r/lambda) - r^3 G(r^2)
  * with G(r^2) = sum_m 2 c_m s_m exp(-s_m r^2) (the pair force is
  * q_i q_j H(r)/r^3 d), and K(r) = r (Y(r) - F(r)) (the pair energy is
- * q_i q_j K(r)/r), on 0 <= r <= r_c as polynomials of degree 28 in
- * y = 2 r / r_c - 1, ascending powers written to h[29] and k[29] (Chebyshev
- * interpolation in extended precision, converted to powers of y).  Returns 1
- * when both are within 1e-15 (absolute; H(0) = K(0) = 1) over the whole
- * interval, with FP64 Horner evaluation (then the FP64 pair kernel uses them),
- * 0 when not (then it evaluates the exponentials one by one).  Host only.
+ * q_i q_j K(r)/r), on 0 <= r <= r_c as polynomials in y = 2 r / r_c - 1,
+ * ascending powers written to h[29] and k[29] (Chebyshev interpolation in
+ * extended precision, truncated, converted to powers of y; the powers above
+ * the degree are zero).  Returns the lowest degree of 24, 26 and 28 at which
+ * both are within 1e-15 (absolute; H(0) = K(0) = 1) over the whole interval
+ * with FP64 Horner evaluation (then the FP64 pair kernel uses them), 0 when
+ * none is (then it evaluates the exponentials one by one).  Host only.
  * Errors: RBSOG_EINVAL.
  */
 int rbsog_sog_near_poly(const rbsog_sog *sog, double *h, double *k);
@@ -246,7 +247,7 @@ typedef struct rbsog_info {
     double skin;        /* neighbour-list skin in use                              */
     int nf;             /* cells per axis of the force evaluation's fine grid      */
     int near_capacity;  /* kp: a particle's neighbour list holds up to 5 kp entries */
-    int near_poly;      /* 1: the FP64 pair kernel uses the polynomial H, K (0 in mixed precision) */
+    int near_poly;      /* degree of the polynomials H, K the FP64 pair kernel uses (0: none; 0 in mixed precision) */
     int nc_y, nc_z;     /* cells along y and z (equal to nc in a cube); the
                            cell list of rbsog_build_cells has nc nc_y nc_z cells,
                            and nshell = nlat in a cuboid (one entry per point) */

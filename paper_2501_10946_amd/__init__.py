@@ -181,15 +181,15 @@ def rbsog_sog_expand(sog: rbsog_sog) -> rbsog_sog:
 
 
 def rbsog_sog_near_poly(sog: rbsog_sog):
-    """(accepted, h[29], k[29]): the FP64 pair kernel's polynomials H(r) = r^3 (F_N1 + F_N2)
-    and K(r) = r (Y - F) in y = 2 r / r_c - 1."""
+    """(degree, h[29], k[29]): the FP64 pair kernel's polynomials H(r) = r^3 (F_N1 + F_N2)
+    and K(r) = r (Y - F) in y = 2 r / r_c - 1 (degree 0: declined)."""
     import numpy as np
     h = np.zeros(29)
     k = np.zeros(29)
     r = lib().rbsog_sog_near_poly(C.byref(sog), C.c_void_p(h.ctypes.data), C.c_void_p(k.ctypes.data))
     if r < 0:
         _check(r)
-    return bool(r), h, k
+    return int(r), h, k
 
 
 def sog_from_parameters(lambda_: float, r_c: float, h: float, t0: float, w: float, M1: int, M2: int,

@@ -774,7 +774,7 @@ int create_system(const rbsog_params *p, const rbsog_sog *s, const double *q_dev
     static_assert(kNearPolyDeg + 1 == sizeof(h->sd.hpoly) / sizeof(double), "near polynomial size");
     // the polynomial pair function serves the FP64 kernels only (mixed precision
     // evaluates the exponentials in FP32), so a mixed system skips the fit
-    h->sd.poly = (p->precision == RBSOG_FP64 && near_poly(*s, s->r_c, h->sd.hpoly, h->sd.kpoly)) ? 1 : 0;
+    h->sd.poly = p->precision == RBSOG_FP64 ? near_poly(*s, s->r_c, h->sd.hpoly, h->sd.kpoly) : 0;
     h->sd.y_scale = 2.0 / s->r_c;
     if (const char *e = std::getenv("RBSOG_NEAR_POLY"))   // 0: evaluate the Gaussians one by one
         if (std::atoi(e) == 0) h->sd.poly = 0;

@@ -35,11 +35,14 @@ double sog_max_error(const rbsog_sog &s);
 
 // ---- host: the near-field pair function as a polynomial (host_near.cpp) ----
 // H(r) = r^3 [F_N1 + F_N2](r) and K(r) = r (Y(r) - F(r)) on [0, r_c] as
-// polynomials of degree kNearPolyDeg in y = 2 r / r_c - 1 (ascending powers);
-// false when either misses kNearPolyTol (absolute; H(0) = K(0) = 1).
+// polynomials in y = 2 r / r_c - 1 (ascending powers, kNearPolyDeg + 1 of
+// them) of the lowest degree of kNearPolyDegs at which both are within
+// kNearPolyTol (absolute; H(0) = K(0) = 1), the powers above it zero; returns
+// that degree, 0 when none is accurate enough.
 constexpr int kNearPolyDeg = 28;
+constexpr int kNearPolyDegs[3] = {24, 26, 28};
 constexpr double kNearPolyTol = 1e-15;
-bool near_poly(const rbsog_sog &s, double rc, double h_out[kNearPolyDeg + 1], double k_out[kNearPolyDeg + 1]);
+int near_poly(const rbsog_sog &s, double rc, double h_out[kNearPolyDeg + 1], double k_out[kNearPolyDeg + 1]);
 
 // ---- host: Fourier lattice and sampling tables (host_tables.cpp) -----------
 // Lattice vectors are packed into one int32: (nx+512) | (ny+512)<<10 | (nz+512)<<20.

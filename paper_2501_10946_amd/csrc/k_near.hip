@@ -161,30 +161,38 @@ __device__ inline double rsqrt_f64(double x)
 }
 
 // Gaussians of the pair function: NG > 0 is a compile-time count, 0 the
-// run-time count of the argument block; kPolyNG: the whole pair function from
-// the polynomials of the argument block (FP64).
-constexpr int kPolyNG = -1;
+// run-time count of the argument block; NG < 0: the whole pair function from
+// the polynomials of the argument block, of degree -NG (FP64).  kPolyNG, the
+// full degree, also serves polynomials of a lower degree (their higher powers
+// are zero, and Horner's first steps then leave the leading coefficient
+// unchanged, so the result is the same bit for bit).
+constexpr int kPolyNG = -28;
 template <int NG>
 __device__ inline int gauss_count(const NearArgs &a) { return NG > 0 ? NG : a.sog.n; }
 
-// Horner in y of the degree-28 polynomial c (ascending powers).
+// Horner in y of the degree-D polynomial c (ascending powers).
+template <int D>
 __device__ inline double near_poly_eval(const double *c, double y)
 {
-    double p = c[28];
+    static_assert(D >= 1 && D <= 28, "the argument block holds 29 powers");
+    double p = c[D];
 #pragma unroll
-    for (int k = 27; k >= 0; --k) p = fma(p, y, c[k]);
+    for (int k = D - 1; k >= 0; --k) p = fma(p, y, c[k]);
     return p;
 }
 
-template <bool MIXED, bool ENERGY, int NG>
+// IMG: the axes (bit d for axis d) on which the minimum-image step is taken;
+// the callers leave an axis out only where the step provably changes nothing
+// (near_image_axes).
+template <bool MIXED, bool ENERGY, int NG, int IMG = 7>
 __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const double4 &pj, double &fx, double &fy,
                                   double &fz, double &en, double &vir)
 {
     // d by the minimum image (|d| < r_c <= L_d/3)
     double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-    dx = fma(-a.g.L[0], rint(dx * a.inv_L[0]), dx);
-    dy = fma(-a.g.L[1], rint(dy * a.inv_L[1]), dy);
-    dz = fma(-a.g.L[2], rint(dz * a.inv_L[2]), dz);
+    if (IMG & 1) dx = fma(-a.g.L[0], rint(dx * a.inv_L[0]), dx);
+    if (IMG & 2) dy = fma(-a.g.L[1], rint(dy * a.inv_L[1]), dy);
+    if (IMG & 4) dz = fma(-a.g.L[2], rint(dz * a.inv_L[2]), dz);
     double r2 = dx * dx + dy * dy + dz * dz;
     if (!(r2 < a.rc2)) return;   // listed within r_c + skin, beyond r_c now
     double qq = pi.w * pj.w;
@@ -202,7 +210,7 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
         f1 = f1 * (irf * irf * irf);
         float gs = 0.0f, fs = 0.0f;
 #pragma unroll
-        for (int g = 0; g < (NG == kPolyNG ? 0 : gauss_count<NG>(a)); ++g) {
+        for (int g = 0; g < (NG < 0 ? 0 : gauss_count<NG>(a)); ++g) {
             float eg = __builtin_amdgcn_exp2f(-(float)a.sog.s_log2e[g] * r2f);
             gs = fmaf((float)a.sog.cs2[g], eg, gs);
             if (ENERGY) fs = fmaf((float)a.sog.c[g], eg, fs);
@@ -215,17 +223,17 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
             en = fma(qq, (double)(ey * irf - fs), en);
             vir = fma(fac, r2, vir);   // d . F of the pair
         }
-    } else if constexpr (NG == kPolyNG) {
+    } else if constexpr (NG < 0) {
         // H(r) / r^3 and K(r) / r with H, K the polynomials in y = 2 r / r_c - 1
         double ir = rsqrt_f64(r2);
         double r = r2 * ir;
         const double y = fma(r, a.sog.y_scale, -1.0);
-        double fac = qq * (near_poly_eval(a.sog.hpoly, y) * (ir * ir * ir));
+        double fac = qq * (near_poly_eval<-NG>(a.sog.hpoly, y) * (ir * ir * ir));
         fx = fma(fac, dx, fx);
         fy = fma(fac, dy, fy);
         fz = fma(fac, dz, fz);
         if (ENERGY) {
-            en = fma(qq, near_poly_eval(a.sog.kpoly, y) * ir, en);
+            en = fma(qq, near_poly_eval<-NG>(a.sog.kpoly, y) * ir, en);
             vir = fma(fac, r2, vir);   // d . F of the pair
         }
     } else {
@@ -507,6 +515,79 @@ __device__ inline void nlist_body(const NearArgs &a, int lb)
 // evaluation
 // ---------------------------------------------------------------------------
 
+// The axes on which a pair of this wave may need the minimum image (bit d:
+// axis d), uniform over the wave: those along which some home particle lies
+// within r_c of a face (with a relative margin of 1e-6).  A home particle
+// farther from both faces of an axis sees every particle within r_c of it at
+// its own unwrapped coordinate on that axis, so the raw difference is the
+// displacement itself and the minimum-image step would return it unchanged
+// (rint of a ratio below 1/2 is 0); a farther particle shows a raw difference
+// at least as large as its true one and stays beyond r_c either way.  Lanes
+// past N count as interior.  1 for the x axis alone (a wave of cell-ordered
+// particles crosses the box along x), 7 whenever y or z is needed.
+__device__ inline int near_image_axes(const NearArgs &a, const double4 &pi, int p)
+{
+    const double m = sqrt(a.rc2) * (1.0 + 1e-6);
+    const bool live = p < a.N;
+    const bool ex = live && !(pi.x >= m && pi.x <= a.g.L[0] - m);
+    const bool eyz = live && !(pi.y >= m && pi.y <= a.g.L[1] - m && pi.z >= m && pi.z <= a.g.L[2] - m);
+    if (__builtin_amdgcn_ballot_w64(eyz)) return 7;
+    return __builtin_amdgcn_ballot_w64(ex) ? 1 : 0;
+}
+
+// Row j of the cell-ordered positions by a 32-bit byte offset from the
+// wave-uniform base (j < 2^27: the offset fits), one address operation
+// fewer per neighbour than a 64-bit index.
+__device__ inline double4 xs_row(const double4 *xs, int j)
+{
+    return *(const double4 *)((const char *)xs + ((uint32_t)j << 5));
+}
+
+// A lane's share of particle p's list (total <= rows entries): lane s takes
+// blocks s, s + kNearLanes, ... (kListBlock consecutive entries each).  A
+// block's indices arrive as two 16-byte loads while the block before is
+// evaluated, and within a block the positions of two entries are loading
+// while the two before are evaluated.  Entries past the count are not used:
+// the particle itself (or the last one, for lanes past N) stands in for them
+// and is never evaluated.
+template <bool MIXED, bool ENERGY, int NG, int IMG>
+__device__ inline void near_list(const NearArgs &a, const double4 &pi, int p, int s, int total, int rows, double &fx,
+                                 double &fy, double &fz, double &en, double &vir)
+{
+    const int nblk = (total + kListBlock - 1) / kListBlock;
+    const int self = p < a.N ? p : a.N - 1;
+    const int32_t *blk = a.nbr + list_at(p, 0, rows);   // block b at blk + b * bstride
+    const size_t bstride = (size_t)kListBlock;
+    int4 n0 = make_int4(self, self, self, self), n1 = n0;
+    if (s < nblk) {
+        n0 = *(const int4 *)(blk + (size_t)s * bstride);
+        n1 = *(const int4 *)(blk + (size_t)s * bstride + 4);
+    }
+    for (int b = s; b < nblk; b += kNearLanes) {
+        const int ne = min(kListBlock, total - b * kListBlock);
+        int jj[kListBlock] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
+        const int bn = b + kNearLanes;
+        if (bn < nblk) {
+            n0 = *(const int4 *)(blk + (size_t)bn * bstride);
+            n1 = *(const int4 *)(blk + (size_t)bn * bstride + 4);
+        }
+#pragma unroll
+        for (int e = 0; e < kListBlock; ++e)
+            if (e >= ne) jj[e] = self;
+        double4 qa = xs_row(a.xs, jj[0]), qb = xs_row(a.xs, jj[1]);
+#pragma unroll
+        for (int e = 0; e < kListBlock; e += 2) {
+            const double4 ca = qa, cb = qb;
+            if (e + 2 < kListBlock) {
+                qa = xs_row(a.xs, jj[e + 2]);
+                qb = xs_row(a.xs, jj[e + 3]);
+            }
+            if (e < ne) pair_force<MIXED, ENERGY, NG, IMG>(a, pi, ca, fx, fy, fz, en, vir);
+            if (e + 1 < ne) pair_force<MIXED, ENERGY, NG, IMG>(a, pi, cb, fx, fy, fz, en, vir);
+        }
+    }
+}
+
 // lb: the logical workgroup (256 particles, one of kNearLanes lanes each)
 template <bool MIXED, bool ENERGY, int NG>
 __device__ inline void near_body(const NearArgs &a, int lb)
@@ -525,45 +606,11 @@ __device__ inline void near_body(const NearArgs &a, int lb)
     double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0, vir = 0.0;
     const int rows = list_rows(a.kp);
     if (total <= rows) {
-        // lane s takes blocks s, s + kNearLanes, ... of the particle's list
-        // (kListBlock consecutive entries each): a block's indices arrive as
-        // two 16-byte loads while the block before is evaluated, and within a
-        // block the positions of two entries are loading while the two before
-        // are evaluated.  Entries past the count are not used: the particle
-        // itself (or the last one, for lanes past N) stands in for them and is
-        // never evaluated.
-        const int nblk = (total + kListBlock - 1) / kListBlock;
-        const int self = p < a.N ? p : a.N - 1;
-        const int32_t *blk = a.nbr + list_at(p, 0, rows);   // block b at blk + b * bstride
-        const size_t bstride = (size_t)kListBlock;
-        int4 n0 = make_int4(self, self, self, self), n1 = n0;
-        if (s < nblk) {
-            n0 = *(const int4 *)(blk + (size_t)s * bstride);
-            n1 = *(const int4 *)(blk + (size_t)s * bstride + 4);
-        }
-        for (int b = s; b < nblk; b += kNearLanes) {
-            const int ne = min(kListBlock, total - b * kListBlock);
-            int jj[kListBlock] = {n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, n1.z, n1.w};
-            const int bn = b + kNearLanes;
-            if (bn < nblk) {
-                n0 = *(const int4 *)(blk + (size_t)bn * bstride);
-                n1 = *(const int4 *)(blk + (size_t)bn * bstride + 4);
-            }
-#pragma unroll
-            for (int e = 0; e < kListBlock; ++e)
-                if (e >= ne) jj[e] = self;
-            double4 qa = a.xs[jj[0]], qb = a.xs[jj[1]];
-#pragma unroll
-            for (int e = 0; e < kListBlock; e += 2) {
-                const double4 ca = qa, cb = qb;
-                if (e + 2 < kListBlock) {
-                    qa = a.xs[jj[e + 2]];
-                    qb = a.xs[jj[e + 3]];
-                }
-                if (e < ne) pair_force<MIXED, ENERGY, NG>(a, pi, ca, fx, fy, fz, en, vir);
-                if (e + 1 < ne) pair_force<MIXED, ENERGY, NG>(a, pi, cb, fx, fy, fz, en, vir);
-            }
-        }
+        // the minimum-image axes: uniform over the lanes that take this branch
+        const int img = near_image_axes(a, pi, p);
+        if (img == 0) near_list<MIXED, ENERGY, NG, 0>(a, pi, p, s, total, rows, fx, fy, fz, en, vir);
+        else if (img == 1) near_list<MIXED, ENERGY, NG, 1>(a, pi, p, s, total, rows, fx, fy, fz, en, vir);
+        else near_list<MIXED, ENERGY, NG, 7>(a, pi, p, s, total, rows, fx, fy, fz, en, vir);
     } else {
         // the particle's list overflowed at the build: its lanes walk the
         // cells of the stencil planes dz = plane - 2 (lane s the planes s,
@@ -688,8 +735,10 @@ static void launch_near_ng(const NearArgs &a, dim3 grid, hipStream_t st)
 {
     dim3 block(kEvalThreads);
     const size_t lds = a.nrho > 0 ? rho_lds_bytes(a.red.P, a.red.chunk, MIXED) : 0;
-    if (!MIXED && a.sog.poly) {
-        hipLaunchKernelGGL((k_near<false, ENERGY, kPolyNG>), grid, block, lds, st, a);
+    if (!MIXED && a.sog.poly) {   // the polynomials' degree: 24, 26 or 28
+        if (a.sog.poly <= 24) hipLaunchKernelGGL((k_near<false, ENERGY, -24>), grid, block, lds, st, a);
+        else if (a.sog.poly <= 26) hipLaunchKernelGGL((k_near<false, ENERGY, -26>), grid, block, lds, st, a);
+        else hipLaunchKernelGGL((k_near<false, ENERGY, kPolyNG>), grid, block, lds, st, a);
         return;
     }
     switch (a.sog.n) {

@@ -49,7 +49,8 @@ struct SogDev {
     double c[kMaxGauss];        // F(r) = sum c exp(-s r^2)
     double s_log2e[kMaxGauss];  // s log2(e): exp(-s r^2) = 2^(-s log2(e) r^2)
     double cs2[kMaxGauss];      // 2 c s (force factor of the Gaussians)
-    // the pair function as polynomials of y = r y_scale - 1 (when poly != 0)
+    // the pair function as polynomials of y = r y_scale - 1 of degree poly
+    // (0: none; the powers above it are zero)
     int poly;
     double y_scale;             // 2 / r_c
     double hpoly[29];           // r^3 (F_N1 + F_N2), ascending powers of y

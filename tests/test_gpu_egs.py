@@ -62,7 +62,7 @@ def test_egs_forces_energies(dev, w, nu, path, monkeypatch):
     s = R.System(st.q, st.m, w.L, sog, w.kT, w.P, seed=w.seed, precision=precision, device=dev)
     if path == "fp64":   # the polynomial pair function wherever the fit holds (the first case)
         assert R.rbsog_get_info(s.h).near_poly == int(R.rbsog_sog_near_poly(sog)[0])
-        assert R.rbsog_get_info(s.h).near_poly == 1 or w.name != "egs_n1000_k1"
+        assert R.rbsog_get_info(s.h).near_poly > 0 or w.name != "egs_n1000_k1"
     if path == "fp64_gauss":
         assert R.rbsog_get_info(s.h).near_poly == 0
     ref = oracle.System(st.q, st.m, w.L, o, w.kT, w.P, seed=w.seed)
