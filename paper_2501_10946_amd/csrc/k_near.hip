@@ -27,7 +27,7 @@
 //            neighbour position already in flight, and stores its partial
 //            force; the far-field kernel adds the partials in lane order.  In FP64
 //            the pair function is, when its fit is accurate, one polynomial
-//            in r (r^3 times the force factor, 28 FMAs, no exponential),
+//            in r (r^3 times the force factor, 24 to 28 FMAs, no exponential),
 //            otherwise the number of Gaussians is a template parameter for
 //            the common counts; coefficients stay in scalar registers.  When a
 //            particle's list overflowed at the build, its lanes walk the

@@ -227,3 +227,47 @@ def test_near_poly_declines_when_inaccurate(R):
     s = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
     ok, _, _ = R.rbsog_sog_near_poly(s)
     assert not ok
+
+
+def _cheb_trunc_error(o, lam, rc, deg):
+    """Worst error of H and K truncated to degree deg in y = 2 r / r_c - 1
+    (numpy's Chebyshev interpolation at 64 nodes, independent of the
+    library's fit)."""
+    c, sg = np.asarray(o.c), np.asarray(o.s)
+
+    def H(r):
+        return np.exp(-r / lam) * (1 + r / lam) - r ** 3 * (2 * c * sg * np.exp(-np.outer(r * r, sg))).sum(axis=1)
+
+    def K(r):
+        return np.exp(-r / lam) - r * (c * np.exp(-np.outer(r * r, sg))).sum(axis=1)
+
+    y = np.linspace(-1.0, 1.0, 1025)
+    worst = 0.0
+    for f in (H, K):
+        full = np.polynomial.chebyshev.Chebyshev.interpolate(lambda t: f((t + 1) * rc / 2), 63)
+        worst = max(worst, np.abs(full.truncate(deg + 1)(y) - f((y + 1) * rc / 2)).max())
+    return worst
+
+
+@pytest.mark.parametrize("lam,rc,expect", [(10.0, 5.0, 24), (2.0, 4.0, 26)])
+def test_near_poly_lowest_degree(R, lam, rc, expect):
+    """The polynomials come at the lowest of the degrees 24, 26, 28 that meets
+    1e-15, the powers above it zero: at the degree below the returned one a
+    Chebyshev truncation (numpy, FP64: its own rounding floor is ~2e-15) misses
+    by several times that floor, while the returned polynomials follow the
+    pair function to within the floor."""
+    o = oracle.sog_auto(lam, rc, 1e-4)
+    s = R.sog_from_parameters(o.lam, o.rc, o.h, o.t0, o.w, o.M1, o.M2)
+    deg, h, k = R.rbsog_sog_near_poly(s)
+    assert deg == expect
+    assert not h[deg + 1:].any() and not k[deg + 1:].any() and h[deg] != 0.0
+    r = np.linspace(0.0, rc, 2001)
+    y = 2.0 * r / rc - 1.0
+    c, sg = np.asarray(o.c), np.asarray(o.s)
+    ey = np.exp(-r / lam)
+    Href = ey * (1.0 + r / lam) - r ** 3 * (2.0 * c * sg * np.exp(-np.outer(r * r, sg))).sum(axis=1)
+    Kref = ey - r * (c * np.exp(-np.outer(r * r, sg))).sum(axis=1)
+    assert np.abs(np.polynomial.polynomial.polyval(y, h) - Href).max() < 2e-15
+    assert np.abs(np.polynomial.polynomial.polyval(y, k) - Kref).max() < 2e-15
+    if deg > 24:
+        assert _cheb_trunc_error(o, lam, rc, deg - 2) > 6e-15
