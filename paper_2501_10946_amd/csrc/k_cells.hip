@@ -31,11 +31,36 @@ __device__ inline bool gate_open(const int32_t *gate) { return gate == nullptr |
 // the system's grid; the single-system kernels pass blockIdx.x, the ensemble
 // kernels the (replica, block) item of a work list.
 
-__device__ inline void cell_ids_body(const CellArgs &a, int b)
+// Wave-aggregated counting: the particles of a wave are consecutive rows of
+// the cell order, so runs of neighbouring lanes share a cell.  The first lane
+// of each run (live lanes form a prefix of the wave) adds the run's length
+// with one atomic, and with want_base its lanes get consecutive slots from
+// the value it read back: a quarter of the atomics of one per particle at
+// ~4 particles per cell.  The slots within a cell depend on the order the
+// atomics land in, as before; the rank pass makes the final order
+// independent of them.
+__device__ inline int add_runs(int32_t *cnt, int id, bool live, bool want_base)
 {
-    if (!gate_open(a.gate)) return;
-    int p = b * kBlock + threadIdx.x;
-    if (p >= a.N) return;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lv = __builtin_amdgcn_ballot_w64(live);
+    const int prev = __shfl_up(id, 1);
+    const bool head = live && (lane == 0 || prev != id);
+    const uint64_t H = __builtin_amdgcn_ballot_w64(head);
+    int base = 0;
+    if (head) {
+        const uint64_t above = H & ~((2ull << lane) - 1ull);   // (2 << 63) wraps to 0: no head above lane 63
+        const int end = above ? __ffsll((long long)above) - 1 : 64 - __clzll((long long)lv);
+        if (want_base) base = atomicAdd(&cnt[id], end - lane);
+        else atomicAdd(&cnt[id], end - lane);
+    }
+    if (!want_base) return 0;
+    const int start = 63 - __clzll((long long)(H & ((2ull << lane) - 1ull)));   // this lane's run head
+    return __shfl(base, start) + (lane - start);
+}
+
+// Snapshot of row p for the rank pass and its cell id (stored).
+__device__ inline int cell_id_of(const CellArgs &a, int p)
+{
     const double4 r = a.xs[p];
     // snapshot of the row: the rank pass reads the old order from here while
     // it writes the new one in place
@@ -49,7 +74,17 @@ __device__ inline void cell_ids_body(const CellArgs &a, int b)
     int cz = cell_coord(r.z, a.g.inv_cell[2], a.g.nc[2]);
     int id = (cz * a.g.nc[1] + cy) * a.g.nc[0] + cx;
     a.cell_id[p] = id;
-    atomicAdd(&a.count[id], 1);
+    return id;
+}
+
+__device__ inline void cell_ids_body(const CellArgs &a, int b)
+{
+    if (!gate_open(a.gate)) return;
+    int p = b * kBlock + threadIdx.x;
+    const bool live = p < a.N;
+    int id = -1;
+    if (live) id = cell_id_of(a, p);
+    add_runs(a.count, id, live, false);
 }
 
 // Exclusive scan of the cell counts in two passes.
@@ -140,10 +175,10 @@ __device__ inline void scatter_body(const CellArgs &a, int b)
 {
     if (!gate_open(a.gate)) return;
     int p = b * kBlock + threadIdx.x;
-    if (p >= a.N) return;
-    int c = a.cell_id[p];
-    int slot = atomicAdd(&a.fill[c], 1);
-    a.tmp[a.cell_start[c] + slot] = a.order_old[p];
+    const bool live = p < a.N;
+    const int c = live ? a.cell_id[p] : -1;
+    const int slot = add_runs(a.fill, c, live, true);
+    if (live) a.tmp[a.cell_start[c] + slot] = a.order_old[p];
 }
 
 // Stable position: a particle's rank within its cell is the number of cell
