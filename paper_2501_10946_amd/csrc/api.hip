@@ -369,6 +369,8 @@ RhoArgs rho_args(rbsog_handle *h, const double4 *samp)
     a.mixed = h->p.precision == RBSOG_MIXED;
     a.tab = h->tab;
     a.ss = make_sincos_short();
+    a.tab_fine = h->tab_far;
+    a.sf = make_sincos_far();
     return a;
 }
 

@@ -122,9 +122,10 @@ __device__ inline double kick_drift_row(double x[3], double v[3], const double f
 // ---------------------------------------------------------------------------
 
 // One particle's term q exp(i k.r) of a mode; p holds (r/L, q) (mixed) or
-// (128 r/L, q) (FP64), so that k.p is the phase in the unit that the
+// (T r/L, q) (FP64, T the entries of the rotation table: kPhaseTab, or
+// kFarTab with FINE), so that k.p is the phase in the unit that the
 // precision's sine and cosine take.
-template <bool CELL, bool MIXED>
+template <bool CELL, bool MIXED, bool FINE = false>
 __device__ inline void rho_term(const RhoArgs &a, const double2 *tab, const double4 &k, const double4 &p,
                                 double &re, double &im)
 {
@@ -136,19 +137,21 @@ __device__ inline void rho_term(const RhoArgs &a, const double2 *tab, const doub
         im = fma(p.w, (double)sn, im);
     } else {
         double sn, cs;
-        sincos_rev_tab(u, tab, a.ss, &sn, &cs);
+        if (FINE) sincos_rev_far(u, tab, a.sf, &sn, &cs);
+        else sincos_rev_tab(u, tab, a.ss, &sn, &cs);
         re = fma(p.w, cs, re);
         im = fma(p.w, sn, im);
     }
 }
 
-template <bool CELL, bool MIXED>
+template <bool CELL, bool MIXED, bool FINE>
 __device__ inline void rho_partial_body(const RhoArgs &a, int b)
 {
     // dynamic LDS: the rotation table (FP64), then the staged particles
+    constexpr int T = FINE ? kFarTab : kPhaseTab;
     extern __shared__ double4 lds[];
     double2 *tab = (double2 *)lds;
-    double4 *sp = lds + (MIXED ? 0 : kPhaseTab / 2);
+    double4 *sp = lds + (MIXED ? 0 : T / 2);
     const int t = threadIdx.x;
     const int64_t g0 = (int64_t)b * kBlock;
     const int s_lo = (int)(g0 / a.P);
@@ -156,9 +159,9 @@ __device__ inline void rho_partial_body(const RhoArgs &a, int b)
     const int j_lo = s_lo * a.chunk;
     const int j_hi = min(a.N, (s_hi + 1) * a.chunk);
     // phase units of the precision, per axis
-    const double phx = MIXED ? a.inv_L[0] : a.inv_L[0] * kPhaseTab;
-    const double phy = MIXED ? a.inv_L[1] : a.inv_L[1] * kPhaseTab;
-    const double phz = MIXED ? a.inv_L[2] : a.inv_L[2] * kPhaseTab;
+    const double phx = MIXED ? a.inv_L[0] : a.inv_L[0] * T;
+    const double phy = MIXED ? a.inv_L[1] : a.inv_L[1] * T;
+    const double phz = MIXED ? a.inv_L[2] : a.inv_L[2] * T;
     for (int k = t; k < j_hi - j_lo; k += kBlock) {
         int j = j_lo + k;
         double4 v;
@@ -166,8 +169,10 @@ __device__ inline void rho_partial_body(const RhoArgs &a, int b)
         else v = make_double4(a.x[j], a.x[a.N + j], a.x[2 * a.N + j], a.q[j]);
         sp[k] = make_double4(v.x * phx, v.y * phy, v.z * phz, v.w);
     }
-    if (!MIXED)
-        for (int k = t; k < kPhaseTab; k += kBlock) tab[k] = a.tab[k];
+    if (!MIXED) {
+        const double2 *src = FINE ? a.tab_fine : a.tab;
+        for (int k = t; k < T; k += kBlock) tab[k] = src[k];
+    }
     __syncthreads();
     const int64_t g = g0 + t;
     if (g >= (int64_t)a.nchunk * a.P) return;
@@ -177,10 +182,10 @@ __device__ inline void rho_partial_body(const RhoArgs &a, int b)
     double re0 = 0.0, im0 = 0.0, re1 = 0.0, im1 = 0.0;
     int i = ib;
     for (; i + 1 < e; i += 2) {
-        rho_term<CELL, MIXED>(a, tab, k, sp[i], re0, im0);
-        rho_term<CELL, MIXED>(a, tab, k, sp[i + 1], re1, im1);
+        rho_term<CELL, MIXED, FINE>(a, tab, k, sp[i], re0, im0);
+        rho_term<CELL, MIXED, FINE>(a, tab, k, sp[i + 1], re1, im1);
     }
-    if (i < e) rho_term<CELL, MIXED>(a, tab, k, sp[i], re0, im0);
+    if (i < e) rho_term<CELL, MIXED, FINE>(a, tab, k, sp[i], re0, im0);
     a.part[g] = make_double2(re0 + re1, im0 + im1);
 }
 

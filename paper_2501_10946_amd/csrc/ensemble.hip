@@ -215,7 +215,7 @@ int rebuild_lists(rbsog_ens *s)
         add(rbsog_ens::LRED0 + pr, rho_reduce_blocks(R.P));
         add(rbsog_ens::LFAR0 + pr, far_blocks(N));
         add((pr ? rbsog_ens::LNEAR1 : rbsog_ens::LNEAR0) + R.ng, near_blocks(N));
-        lds[pr] = std::max(lds[pr], rho_lds_bytes(R.P, chunk, pr == 1));
+        lds[pr] = std::max(lds[pr], rho_lds_bytes(R.P, chunk, pr == 1, true));
     }
     size_t total = 0;
     for (int k = 0; k < rbsog_ens::NLISTS; ++k) {

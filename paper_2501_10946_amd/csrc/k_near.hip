@@ -669,7 +669,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_near(NearArgs a)
     const int b = (int)blockIdx.x;
     if (a.nrho == 0 || !a.interleave) {
         if (b < a.nrho) {   // uniform per workgroup
-            if (b < rho_blocks(a.red.nchunk, a.red.P)) rho_partial_body<true, MIXED>(a.red, b);
+            if (b < rho_blocks(a.red.nchunk, a.red.P)) rho_partial_body<true, MIXED, true>(a.red, b);
             return;
         }
         near_body<MIXED, ENERGY, NG>(a, xcd_block(b - a.nrho, (int)gridDim.x - a.nrho));
@@ -686,7 +686,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_near(NearArgs a)
     const int64_t upto = ((g + 1) * gr + G - 1) / G;
     if (upto > before) {   // uniform per workgroup
         const int rb = (int)(before * 8 + (b & 7));
-        if (rb < rho_blocks(a.red.nchunk, a.red.P)) rho_partial_body<true, MIXED>(a.red, rb);
+        if (rb < rho_blocks(a.red.nchunk, a.red.P)) rho_partial_body<true, MIXED, true>(a.red, rb);
         return;
     }
     near_body<MIXED, ENERGY, NG>(a, xcd_block((int)((g - before) * 8 + (b & 7)), (int)gridDim.x - a.nrho));
@@ -719,7 +719,7 @@ static bool near_args_ok(const NearArgs &a)
     return a.N >= 1 && a.xs && a.cell_start && a.nbr && a.nbr_cnt && a.fnear && a.kp >= 1 &&
            a.g.nc[0] >= 6 && a.g.nc[1] >= 6 && a.g.nc[2] >= 6 &&
            a.rc2 > 0.0 && a.rl2 >= a.rc2 && a.w[0] > 0.0 && a.w[1] > 0.0 && a.w[2] > 0.0 && (!a.energy || a.epart) && a.nrho >= 0 && a.nrho % 8 == 0 &&
-           (a.nrho == 0 || (a.red.xs && rho_partial_ok(a.red) && a.red.mixed == a.mixed &&
+           (a.nrho == 0 || (a.red.xs && rho_partial_ok(a.red) && a.red.mixed == a.mixed && (a.mixed || a.red.tab_fine) &&
                             a.nrho >= rho_blocks(a.red.nchunk, a.red.P)));
 }
 
@@ -734,7 +734,7 @@ template <bool MIXED, bool ENERGY>
 static void launch_near_ng(const NearArgs &a, dim3 grid, hipStream_t st)
 {
     dim3 block(kEvalThreads);
-    const size_t lds = a.nrho > 0 ? rho_lds_bytes(a.red.P, a.red.chunk, MIXED) : 0;
+    const size_t lds = a.nrho > 0 ? rho_lds_bytes(a.red.P, a.red.chunk, MIXED, true) : 0;
     if (!MIXED && a.sog.poly) {   // the polynomials' degree: 24, 26 or 28
         if (a.sog.poly <= 24) hipLaunchKernelGGL((k_near<false, ENERGY, -24>), grid, block, lds, st, a);
         else if (a.sog.poly <= 26) hipLaunchKernelGGL((k_near<false, ENERGY, -26>), grid, block, lds, st, a);

@@ -18,7 +18,7 @@ static bool vm_ok(const RhoArgs &a) { return a.vm || (a.nG >= 1 && a.nG <= kMaxG
 template <bool CELL, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_rho_partial(RhoArgs a)
 {
-    rho_partial_body<CELL, MIXED>(a, (int)blockIdx.x);
+    rho_partial_body<CELL, MIXED, false>(a, (int)blockIdx.x);
 }
 
 template <bool MIXED>
@@ -26,7 +26,7 @@ __global__ __launch_bounds__(kBlock) void k_rho_partial_batch(const RhoArgs *__r
                                                               const EnsItem *__restrict__ items)
 {
     const EnsItem e = items[blockIdx.x];
-    rho_partial_body<true, MIXED>(tab[e.r], e.b);
+    rho_partial_body<true, MIXED, true>(tab[e.r], e.b);   // the finer table, as the single system's step
 }
 
 // rho_reduce_body is in dev_common.h.
@@ -65,7 +65,7 @@ int rho_chunk_shared(int N, int P, bool mixed)
     // carries it), never smaller than the group of the launch of their own, so
     // that the partials fit the same buffer
     int c = 1;
-    while (2 * c <= kRhoChunkMax && rho_lds_bytes(P, 2 * c, mixed) <= 16384 && (255 / P + 2) * 2 * c <= kRhoStage)
+    while (2 * c <= kRhoChunkMax && rho_lds_bytes(P, 2 * c, mixed, false) <= 16384 && (255 / P + 2) * 2 * c <= kRhoStage)
         c *= 2;
     return std::max(c, rho_chunk(N, P));
 }
@@ -75,7 +75,7 @@ hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st)
     if (!rho_partial_ok(a)) return hipErrorInvalidValue;
     const int64_t lanes = (int64_t)a.nchunk * a.P;
     dim3 grid((unsigned)((lanes + kBlock - 1) / kBlock));
-    size_t lds = rho_lds_bytes(a.P, a.chunk, a.mixed);
+    size_t lds = rho_lds_bytes(a.P, a.chunk, a.mixed, false);
     if (a.xs) {
         if (a.mixed) hipLaunchKernelGGL((k_rho_partial<true, true>), grid, dim3(kBlock), lds, st, a);
         else hipLaunchKernelGGL((k_rho_partial<true, false>), grid, dim3(kBlock), lds, st, a);
@@ -159,9 +159,9 @@ hipError_t launch_rho_full(const RhoArgs &a, hipStream_t st)
 // Ensemble: one launch over every replica's groups (items: rho_blocks per
 // replica) with the largest staging any of them needs, then the reduction
 // (items: P per replica).
-size_t rho_lds_bytes(int P, int chunk, bool mixed)
+size_t rho_lds_bytes(int P, int chunk, bool mixed, bool fine)
 {
-    return sizeof(double4) * ((mixed ? 0 : kPhaseTab / 2) + (size_t)(255 / P + 2) * chunk);
+    return sizeof(double4) * ((mixed ? 0 : (fine ? kFarTab : kPhaseTab) / 2) + (size_t)(255 / P + 2) * chunk);
 }
 
 hipError_t launch_rho_batch(const RhoArgs *tab, const EnsItem *part_items, int npart, size_t lds, bool mixed,

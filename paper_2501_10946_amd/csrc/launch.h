@@ -201,6 +201,11 @@ struct RhoArgs {
     int mixed;
     const double2 *tab;        // [kPhaseTab] (sin, cos)(2 pi j / kPhaseTab) (FP64 path)
     SinCosShort ss;
+    // the far field's finer table ([kFarTab] entries), used by the partial
+    // sums of a step (near launch, served ensemble): two FMA fewer per
+    // (particle, mode) than the kPhaseTab form, at 14 KB more LDS
+    const double2 *tab_fine;
+    SinCosFar sf;
 };
 hipError_t launch_rho_partial(const RhoArgs &a, hipStream_t st);
 bool rho_partial_ok(const RhoArgs &a);   // the partial launch's argument checks
@@ -209,7 +214,8 @@ hipError_t launch_rho_reduce(const RhoArgs &a, hipStream_t st);
 hipError_t launch_rho_full(const RhoArgs &a, hipStream_t st);
 // workgroups of the partial kernel and its dynamic LDS bytes
 __host__ __device__ inline int64_t rho_blocks(int nchunk, int P) { return ((int64_t)nchunk * P + kBlock - 1) / kBlock; }
-size_t rho_lds_bytes(int P, int chunk, bool mixed);
+// (fine: the kFarTab table of a step's partial sums)
+size_t rho_lds_bytes(int P, int chunk, bool mixed, bool fine);
 // the reduction: one workgroup per kRedModes adjacent samples
 constexpr int kRedModes = 4;
 __host__ __device__ inline int rho_reduce_blocks(int P) { return (P + kRedModes - 1) / kRedModes; }
