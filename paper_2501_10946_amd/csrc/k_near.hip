@@ -538,9 +538,9 @@ __device__ inline int near_image_axes(const NearArgs &a, const double4 &pi, int 
 // Row j of the cell-ordered positions by a 32-bit byte offset from the
 // wave-uniform base (j < 2^27: the offset fits), one address operation
 // fewer per neighbour than a 64-bit index.
-__device__ inline double4 xs_row(const double4 *xs, int j)
+__device__ inline double4 xs_row(const NearArgs &a, int j)
 {
-    return *(const double4 *)((const char *)xs + ((uint32_t)j << 5));
+    return *(const double4 *)((const char *)a.xs + ((uint32_t)j << 5));
 }
 
 // A lane's share of particle p's list (total <= rows entries): lane s takes
@@ -574,13 +574,13 @@ __device__ inline void near_list(const NearArgs &a, const double4 &pi, int p, in
 #pragma unroll
         for (int e = 0; e < kListBlock; ++e)
             if (e >= ne) jj[e] = self;
-        double4 qa = xs_row(a.xs, jj[0]), qb = xs_row(a.xs, jj[1]);
+        double4 qa = xs_row(a, jj[0]), qb = xs_row(a, jj[1]);
 #pragma unroll
         for (int e = 0; e < kListBlock; e += 2) {
             const double4 ca = qa, cb = qb;
             if (e + 2 < kListBlock) {
-                qa = xs_row(a.xs, jj[e + 2]);
-                qb = xs_row(a.xs, jj[e + 3]);
+                qa = xs_row(a, jj[e + 2]);
+                qb = xs_row(a, jj[e + 3]);
             }
             if (e < ne) pair_force<MIXED, ENERGY, NG, IMG>(a, pi, ca, fx, fy, fz, en, vir);
             if (e + 1 < ne) pair_force<MIXED, ENERGY, NG, IMG>(a, pi, cb, fx, fy, fz, en, vir);
@@ -662,8 +662,11 @@ __global__ __launch_bounds__(kListThreads) void k_nlist(NearArgs a)
     nlist_body(a, xcd_block((int)blockIdx.x, (int)gridDim.x));
 }
 
+// Mixed precision without energies: held to the registers of 5 waves per SIMD
+// (it needs a few more than 96 otherwise, and its gathers want the waves).
 template <bool MIXED, bool ENERGY, int NG>
-__global__ __launch_bounds__(kEvalThreads) void k_near(NearArgs a)
+__global__ __launch_bounds__(kEvalThreads) __attribute__((amdgpu_waves_per_eu(MIXED && !ENERGY ? 5 : 1))) void k_near(
+    NearArgs a)
 {
     static_assert(kEvalThreads == kBlock, "the structure-factor workgroups have kBlock threads");
     const int b = (int)blockIdx.x;
