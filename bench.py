@@ -75,12 +75,12 @@ KERNEL_SOURCES = {
 # FETCH_SIZE and one WRITE_SIZE counter run (KiB per dispatch, mean over the
 # profiled dispatches), each scaled by what the same counter reads for an FP64
 # copy y = 2x of 256 MiB (FETCH_SIZE 131086 KiB for 262144 KiB read: x2.000;
-# WRITE_SIZE 262150 KiB for 262144 KiB written: x1.000).
+# WRITE_SIZE 262147 KiB for 262144 KiB written: x1.000).
 MEASURED_TRAFFIC = {
     # kernel: (sources sha256, FETCH_SIZE KiB, WRITE_SIZE KiB, fetch scale, write scale)
-    "near": ("d8c9f6e42707f5b874408e2458aecb0d11c451e58c0f9aefb937b4941811bc81", 445102.0, 100836.0, 2.0, 1.0),
-    "far": ("2a2d8c4ed6f9770c395bafc5c93274e7890212a221fc82e9c790665929ea5ec1", 78336.0, 78613.0, 2.0, 1.0),
-    "nlist": ("cd7fab6f9cb30d6e2cc0f3f7d282234e971de26c020789d22c1c505136e1fe7d", 84018.0, 523160.0, 2.0, 1.0),
+    "near": ("2edc4d3d5daba9c89dc3bd03b92b66876eec853fe4d09cafb3ce0c42d98c9f5a", 419413.0, 100836.0, 2.0, 1.0),
+    "far": ("8a7c054038bc2072189517df0d36b38d52c239fcc80a1550dab3e5fc888b6711", 78336.0, 78613.0, 2.0, 1.0),
+    "nlist": ("adf973cba8197b26cebf41bd16d350515c2037a2819a967fb5d13af835ff96be", 83770.0, 517545.0, 2.0, 1.0),
 }
 
 # VALU issue at the same workload (FP64): VALU busy = SQ_ACTIVE_INST_VALU x 4
@@ -89,9 +89,9 @@ MEASURED_TRAFFIC = {
 # fraction of the VALU's lane-cycles that issued work.
 MEASURED_VALU = {
     # kernel: (sources sha256, VALU busy, lane utilisation)
-    "near": ("d8c9f6e42707f5b874408e2458aecb0d11c451e58c0f9aefb937b4941811bc81", 0.88, 0.88),
-    "far": ("2a2d8c4ed6f9770c395bafc5c93274e7890212a221fc82e9c790665929ea5ec1", 0.88, 1.00),
-    "nlist": ("cd7fab6f9cb30d6e2cc0f3f7d282234e971de26c020789d22c1c505136e1fe7d", 0.77, 0.78),
+    "near": ("2edc4d3d5daba9c89dc3bd03b92b66876eec853fe4d09cafb3ce0c42d98c9f5a", 0.79, 0.89),
+    "far": ("8a7c054038bc2072189517df0d36b38d52c239fcc80a1550dab3e5fc888b6711", 0.89, 1.00),
+    "nlist": ("adf973cba8197b26cebf41bd16d350515c2037a2819a967fb5d13af835ff96be", 0.83, 0.76),
 }
 
 

@@ -193,7 +193,10 @@ __device__ inline void pair_force(const NearArgs &a, const double4 &pi, const do
     if (IMG & 1) dx = fma(-a.g.L[0], rint(dx * a.inv_L[0]), dx);
     if (IMG & 2) dy = fma(-a.g.L[1], rint(dy * a.inv_L[1]), dy);
     if (IMG & 4) dz = fma(-a.g.L[2], rint(dz * a.inv_L[2]), dz);
-    double r2 = dx * dx + dy * dy + dz * dz;
+    // written out as FMAs: the compiler's own contraction of a sum of squares
+    // may pick another product to fuse depending on how d was formed, and the
+    // IMG variants must give the same bits
+    const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
     if (!(r2 < a.rc2)) return;   // listed within r_c + skin, beyond r_c now
     double qq = pi.w * pj.w;
     if (MIXED) {
@@ -588,8 +591,11 @@ __device__ inline void near_list(const NearArgs &a, const double4 &pi, int p, in
     }
 }
 
-// lb: the logical workgroup (256 particles, one of kNearLanes lanes each)
-template <bool MIXED, bool ENERGY, int NG>
+// lb: the logical workgroup (256 particles, one of kNearLanes lanes each).
+// SPLIT: choose the minimum-image axes per wave (near_image_axes); the served
+// ensemble's small replicas have nearly every wave at a face, so their batch
+// launch takes every axis and saves the code.
+template <bool MIXED, bool ENERGY, int NG, bool SPLIT = true>
 __device__ inline void near_body(const NearArgs &a, int lb)
 {
     __shared__ double2 red[kEvalThreads];
@@ -607,7 +613,7 @@ __device__ inline void near_body(const NearArgs &a, int lb)
     const int rows = list_rows(a.kp);
     if (total <= rows) {
         // the minimum-image axes: uniform over the lanes that take this branch
-        const int img = near_image_axes(a, pi, p);
+        const int img = SPLIT ? near_image_axes(a, pi, p) : 7;
         if (img == 0) near_list<MIXED, ENERGY, NG, 0>(a, pi, p, s, total, rows, fx, fy, fz, en, vir);
         else if (img == 1) near_list<MIXED, ENERGY, NG, 1>(a, pi, p, s, total, rows, fx, fy, fz, en, vir);
         else near_list<MIXED, ENERGY, NG, 7>(a, pi, p, s, total, rows, fx, fy, fz, en, vir);
@@ -708,11 +714,11 @@ __global__ __launch_bounds__(kEvalThreads) void k_near_batch(const NearArgs *__r
 {
     const EnsItem e = items[blockIdx.x];
     if constexpr (NG == 0) {
-        near_body<MIXED, ENERGY, NG>(tab[e.r], e.b);
+        near_body<MIXED, ENERGY, NG, false>(tab[e.r], e.b);
     } else {
         // read before any store, the copy's fields become scalar loads
         const NearArgs a = tab[e.r];
-        near_body<MIXED, ENERGY, NG>(a, e.b);
+        near_body<MIXED, ENERGY, NG, false>(a, e.b);
     }
 }
 
