@@ -25,7 +25,7 @@ constexpr int kFarTile = 256;
 // r/L (mixed) or 1024 r/L (FP64), so that n.s is the phase in the unit that the
 // precision's sine and cosine take.
 template <bool MIXED>
-__device__ inline double far_term(const SinCosFar &P, const double2 *tab, const double4 &kv, const double2 &gv,
+__device__ inline double far_term(const FarArgs &a, const double2 *tab, const double4 &kv, const double2 &gv,
                                   double sx, double sy, double sz)
 {
     double u = kv.x * sx + kv.y * sy + kv.z * sz;
@@ -35,18 +35,9 @@ __device__ inline double far_term(const SinCosFar &P, const double2 *tab, const 
         return gv.y * (double)cs - gv.x * (double)sn;
     } else {
         double sn, cs;
-        sincos_rev_far(u, tab, P, &sn, &cs);
+        sincos_rev_far(u, tab, a.ss, &sn, &cs);
         return gv.y * cs - gv.x * sn;
     }
-}
-
-// x in a vector register: the series' inner FMA (two coefficients, one
-// power) may take only one scalar operand, so with both coefficients in
-// scalar registers the compiler moves one across at every call.
-__device__ inline double in_vgpr(double x)
-{
-    __asm__("" : "+v"(x));
-    return x;
 }
 
 template <bool MIXED, bool DRIFT>
@@ -73,11 +64,6 @@ __device__ inline void far_body(const FarArgs &a, int b)
     const double phz = MIXED ? a.inv_L[2] : a.inv_L[2] * kFarTab;
     double sx = pi.x * phx, sy = pi.y * phy, sz = pi.z * phz;
     double ax = 0.0, ay = 0.0, az = 0.0;
-    SinCosFar P = a.ss;
-    if (!MIXED) {
-        P.s[1] = in_vgpr(P.s[1]);
-        P.c[1] = in_vgpr(P.c[1]);
-    }
     if (!MIXED)
         for (int k = t; k < kFarTab; k += kFarThreads) tab[k] = a.tab[k];
     for (int l0 = 0; l0 < a.P; l0 += kFarTile) {
@@ -92,8 +78,8 @@ __device__ inline void far_body(const FarArgs &a, int b)
         int k = g;
         for (; k + kFarGroups < nl; k += 2 * kFarGroups) {
             const double4 k0 = sk[k], k1 = sk[k + kFarGroups];
-            const double im0 = far_term<MIXED>(P, tab, k0, sg[k], sx, sy, sz);
-            const double im1 = far_term<MIXED>(P, tab, k1, sg[k + kFarGroups], sx, sy, sz);
+            const double im0 = far_term<MIXED>(a, tab, k0, sg[k], sx, sy, sz);
+            const double im1 = far_term<MIXED>(a, tab, k1, sg[k + kFarGroups], sx, sy, sz);
             ax += im0 * k0.x;
             ay += im0 * k0.y;
             az += im0 * k0.z;
@@ -103,7 +89,7 @@ __device__ inline void far_body(const FarArgs &a, int b)
         }
         if (k < nl) {
             const double4 k0 = sk[k];
-            const double im0 = far_term<MIXED>(P, tab, k0, sg[k], sx, sy, sz);
+            const double im0 = far_term<MIXED>(a, tab, k0, sg[k], sx, sy, sz);
             ax += im0 * k0.x;
             ay += im0 * k0.y;
             az += im0 * k0.z;
