@@ -561,8 +561,14 @@ int rbsog_rdf(rbsog_handle *h, const double *x_dev, double r_max, int nbins, uns
  */
 int rbsog_track(int64_t N, double L, const double *x_dev, double *x_last_dev, double *disp_dev, void *hip_stream);
 
-/* rbsog_track in a cuboid box of edges (Lx, Ly, Lz): the minimum image per
- * axis.  Errors: RBSOG_EINVAL. */
+/*
+ * rbsog_track in a cuboid box of edges (Lx, Ly, Lz) (Section 2's box
+ * L = (L_x, L_y, L_z)): component a of d folds by its own edge, d - L_a
+ * rint(d / L_a); arrays as rbsog_track ([3][N], device, caller order, owned
+ * by the caller; x_last_dev and disp_dev updated in place).  Asynchronous on
+ * hip_stream.  Errors: RBSOG_EINVAL (N outside [1, 2^27 - 1], an edge not
+ * positive and finite, a null array).
+ */
 int rbsog_track_box(int64_t N, double Lx, double Ly, double Lz, const double *x_dev, double *x_last_dev,
                     double *disp_dev, void *hip_stream);
 
