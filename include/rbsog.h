@@ -412,8 +412,13 @@ int rbsog_set_thermostat(rbsog_handle *h, double friction, double kT);
  */
 int rbsog_set_bath(rbsog_handle *h, int kind, double rate, double kT);
 
-/* (xi, eta) of a Nose-Hoover bath into out[2] (host); synchronises the
- * stream.  Errors: RBSOG_EINVAL, RBSOG_EHIP. */
+/*
+ * The Nose-Hoover bath's state (the NVT runs of Section 5.1): its friction
+ * xi and the integral eta of xi over time (which enters the conserved
+ * extended energy K + U + Q xi^2/2 + g k_B T eta) into out[2] (host memory,
+ * the caller's; meaningful for the Nose-Hoover bath only).  Synchronises the
+ * stream.  Errors: RBSOG_EINVAL, RBSOG_EHIP.
+ */
 int rbsog_bath_state(rbsog_handle *h, double *out);
 
 /*
